@@ -1,0 +1,272 @@
+"""The variational fit of C ~ A B (Sec. 2.3) with the randomized SVD of
+Sec. 3.1, in plain FP64 numpy.
+
+Conventions (shared with the GPU path as definitions, not as code):
+  * cores (left, out, in, right); C_l carries (c, s = A's out, u = B's in, c');
+  * environments L_l[c, a, b] and R_l[c, a, b] are indexed by the C, A and B
+    bonds at the open side (Sec. 2.3.3, Fig. envs); L_0 = R_{L+1} = [[[1]]];
+  * the two-site tensor of bond l (Sec. 2.3.4, Fig. derivatives (c)) is the
+    n x m matrix with rows (c, s1, u1) and columns (s2, u2, c'') row-major;
+  * the randomized range finder sketches from the right, M Omega (Sec. 3.1);
+  * r = min(chi_max, n, m, chi^A_l chi^B_l): chi_max is the bond cap of Alg. 3,
+    n, m bound any SVD of M, and chi^A_l chi^B_l bounds the rank of A B across
+    bond l, so no structurally zero singular value is kept; the sketch width
+    is k = min(chi_max + p, n, m, chi^A_l chi^B_l) and k = min(n, m) means the
+    plain SVD;
+  * singular vectors are sign-fixed (largest-magnitude entry of each U column
+    positive, Vt rows flipped along), Q of the sketch has R_jj >= 0;
+  * tau > 0 truncation keeps the smallest r with
+    (sum_{j>r} sigma_j^2)^(1/2) <= (tau / L) ||sigma||_2 (Sec. 2.3.4).
+
+Pins (tests/test_oracle_fit.py): L = 2 reduces to the truncated SVD of the
+dense product (Eckart-Young); the exact-rank regime reproduces A B; the error
+is bounded below by the dense bond-unfolding tails and never increases from one
+update to the next; forward updates leave left-orthogonal cores; the result is
+invariant under gauge transforms of A and B; RSVD equals SVD when the sketch
+spans the range; the batched inverse-gauge schedule keeps its gauge relations
+and reaches the exact product in the exact-rank regime.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import canon
+from .philox import gaussian_matrix
+
+GUARD = 1e-14
+
+
+def ext_left(Lprev, A, B):
+    """First two diagrams of Fig. envs: contract L_{l-1}[c, a, b] with A_l[a, s, t, a']
+    and then with B_l[b, t, u, b'] into XL[c, s, u, a', b']."""
+    T = np.tensordot(Lprev, A, axes=([1], [0]))           # [c, b, s, t, a']
+    X = np.tensordot(T, B, axes=([1, 3], [0, 1]))          # [c, s, a', u, b']
+    return X.transpose(0, 1, 3, 2, 4)
+
+
+def ext_right(A, B, Rnext):
+    """Mirror of ext_left: XR[a, b, s, u, c'] = sum A_l[a, s, t, a'] B_l[b, t, u, b']
+    R_{l+1}[c', a', b']."""
+    T = np.tensordot(A, Rnext, axes=([3], [1]))            # [a, s, t, c', b']
+    X = np.tensordot(T, B, axes=([2, 4], [1, 3]))          # [a, s, c', b, u]
+    return X.transpose(0, 3, 1, 4, 2)
+
+
+def env_left(Lprev, C, A, B):
+    """L_l[c', a', b'] = sum L_{l-1}[c, a, b] C_l[c, s, u, c'] A_l[a, s, t, a'] B_l[b, t, u, b']
+    (Fig. envs, site-canonical form: no Y tensors; third diagram closes with C)."""
+    return np.tensordot(C, ext_left(Lprev, A, B), axes=([0, 1, 2], [0, 1, 2]))
+
+
+def env_right(Rnext, C, A, B):
+    """R_l[c, a, b] = sum C_l[c, s, u, c'] A_l[a, s, t, a'] B_l[b, t, u, b'] R_{l+1}[c', a', b']."""
+    X = np.tensordot(ext_right(A, B, Rnext), C, axes=([2, 3, 4], [1, 2, 3]))  # [a, b, c]
+    return X.transpose(2, 0, 1)
+
+
+def two_site_matrix(Lm, A1, B1, A2, B2, Rp):
+    """The projected 6-leg tensor of Fig. derivatives (c)/(d):
+    Theta[c,s1,u1,s2,u2,c''] = sum L[c,a,b] A1[a,s1,t1,a'] B1[b,t1,u1,b']
+                                   A2[a',s2,t2,a''] B2[b',t2,u2,b''] R[c'',a'',b''],
+    reshaped to (c s1 u1) x (s2 u2 c'')."""
+    XL = ext_left(Lm, A1, B1)                              # [c, s1, u1, a', b']
+    XR = ext_right(A2, B2, Rp)                             # [a', b', s2, u2, c'']
+    T = np.tensordot(XL, XR, axes=([3, 4], [0, 1]))
+    c, s1, u1, s2, u2, cc = T.shape
+    return T.reshape(c * s1 * u1, s2 * u2 * cc)
+
+
+@dataclass
+class Factor:
+    U: np.ndarray
+    S: np.ndarray
+    Vt: np.ndarray
+    k: int
+    gap: float
+    n_guard: int
+    sigma_all: np.ndarray = field(repr=False, default=None)
+
+
+def truncation_rank(S, chi_max, cap, tau, L):
+    r = min(chi_max, cap, len(S))
+    if tau > 0.0:
+        tot = float(np.sum(S ** 2))
+        thr = (tau / L) ** 2 * tot
+        tail = np.concatenate([np.cumsum((S ** 2)[::-1])[::-1][1:], [0.0]])
+        ok = np.nonzero(tail <= thr)[0]
+        r = min(r, int(ok[0]) + 1 if len(ok) else len(S))
+    return max(r, 1)
+
+
+def factorize(M, chi_max, sketch_p, rank_cap, omega, tau=0.0, L=1):
+    """Truncated SVD of the two-site matrix (Alg. 3), optionally through the
+    randomized range finder of Sec. 3.1: M Omega = Q R, Q^T M = U_b S V^T,
+    U = Q U_b.  ``omega(m, k)`` returns the Gaussian test matrix."""
+    n, m = M.shape
+    kmax = min(n, m, rank_cap)
+    k = min(n, m) if sketch_p < 0 else min(chi_max + sketch_p, kmax)
+    if k >= min(n, m):
+        U, S, Vt = np.linalg.svd(M, full_matrices=False)
+        k = min(n, m)
+    else:
+        Om = omega(m, k)
+        Q, _ = canon.qr_pos(M @ Om)
+        Ub, S, Vt = np.linalg.svd(Q.T @ M, full_matrices=False)
+        U = Q @ Ub
+    r = truncation_rank(S, chi_max, kmax, tau, L)
+    gap = float((S[r - 1] - S[r]) / S[r - 1]) if len(S) > r else 1.0
+    U, Sr, Vt = U[:, :r], S[:r], Vt[:r]
+    s = canon.sign_fix_columns(U)
+    U, Vt = U * s[None, :], Vt * s[:, None]
+    n_guard = int(np.sum(Sr <= GUARD * Sr[0]))
+    return Factor(U, Sr, Vt, k, gap, n_guard, S)
+
+
+@dataclass
+class FitResult:
+    C: list
+    nu: float
+    bond_dims: list
+    min_gap: float
+    n_guard: int
+    ks: list
+    records: list = field(default_factory=list)
+
+
+def _preprocess(A, B):
+    A1, nuA = canon.left_orthogonalize(A)
+    B1, nuB = canon.left_orthogonalize(B)
+    caps = [A1[l].shape[3] * B1[l].shape[3] for l in range(len(A1) - 1)]
+    return A1, B1, nuA * nuB, caps
+
+
+def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
+               on_update=None, C_init=None):
+    """Alg. 5 with the site-canonical update of Alg. 3.
+
+    Preprocessing left-orthogonalizes A and B and splits off their norms; the
+    initial guess is (the preprocessed) A, right-orthogonalized; all right
+    environments are precomputed; sweeps alternate forward and backward, each a
+    pass of L-1 updates (the first backward update repeats the last forward
+    bond with a fresh Omega).  Omega of sweep i at bond l (1-based) is the
+    Philox stream (pair, i, l).  ``on_update(sweep, l, C_scaled)`` is called
+    after each update."""
+    L = len(A)
+    A1, B1, nu, caps = _preprocess(A, B)
+    C = canon.right_orthogonalize(A1 if C_init is None else C_init)
+    ones = np.ones((1, 1, 1))
+    Lenv = [None] * (L + 1)
+    Renv = [None] * (L + 2)
+    Lenv[0] = ones
+    Renv[L + 1] = ones
+    # environments use 1-based site labels: site l is index l-1 in the lists
+    for l in range(L, 2, -1):
+        Renv[l] = env_right(Renv[l + 1], C[l - 1], A1[l - 1], B1[l - 1])
+    min_gap, n_guard, ks = 1.0, 0, []
+    for sweep in range(n_sweeps):
+        fwd = sweep % 2 == 0
+        bonds = range(1, L) if fwd else range(L - 1, 0, -1)
+        for l in bonds:
+            if fwd and l >= 2:
+                Lenv[l - 1] = env_left(Lenv[l - 2], C[l - 2], A1[l - 2], B1[l - 2])
+            if not fwd and l <= L - 2:
+                Renv[l + 2] = env_right(Renv[l + 3], C[l + 1], A1[l + 1], B1[l + 1])
+            M = two_site_matrix(Lenv[l - 1], A1[l - 1], B1[l - 1], A1[l], B1[l], Renv[l + 2])
+            f = factorize(M, chi_max, sketch_p, caps[l - 1],
+                          lambda m, k, l=l, sweep=sweep: gaussian_matrix(m, k, seed, pair, sweep, l),
+                          tau, L)
+            cl = C[l - 1].shape[0]
+            cr = C[l].shape[3]
+            d1, d2 = A1[l - 1].shape[1], B1[l - 1].shape[2]
+            r = len(f.S)
+            if fwd:
+                C[l - 1] = f.U.reshape(cl, d1, d2, r)
+                C[l] = (f.S[:, None] * f.Vt).reshape(r, d1, d2, cr)
+            else:
+                C[l - 1] = (f.U * f.S[None, :]).reshape(cl, d1, d2, r)
+                C[l] = f.Vt.reshape(r, d1, d2, cr)
+            min_gap = min(min_gap, f.gap)
+            n_guard += f.n_guard
+            ks.append(f.k)
+            if on_update is not None:
+                Cs = [c.copy() for c in C]
+                Cs[0] = Cs[0] * nu
+                on_update(sweep, l, Cs)
+    out = [c.copy() for c in C]
+    out[0] = out[0] * nu
+    dims = [1] + [c.shape[3] for c in C]
+    return FitResult(out, nu, dims, min_gap, n_guard, ks)
+
+
+def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
+                 on_half_step=None):
+    """Single-device limit of the parallel fit in inverse canonical form
+    (Sec. 4, Alg. 4 and Alg. 6 with every sub-TT two sites long): half-step q
+    updates every bond l with l = 1 (mod 2) for q = 0 and l = 0 (mod 2) for
+    q = 1, each independently from the environments as they stood at the
+    half-step's start.  An update sets Psi_l = U S, Psi_{l+1} = S V^T,
+    Y_l = S^{-1} (Alg. 4) and rebuilds L_l from Psi_l Y_l = U and R_{l+1}
+    from Y_l Psi_{l+1} = V^T.  Omega of half-step q of sweep i at bond l is the
+    Philox stream (pair, 2 i + q, l).  The result is merged as C_l = Psi_l Y_l,
+    C_L = Psi_L (Sec. 4.7)."""
+    L = len(A)
+    A1, B1, nu, caps = _preprocess(A, B)
+    C0 = canon.right_orthogonalize(A1)
+    Psi, Y, n_guard = canon.inverse_canonical(C0, GUARD)
+    ones = np.ones((1, 1, 1))
+    Lenv = [None] * (L + 1)
+    Renv = [None] * (L + 2)
+    Lenv[0] = ones
+    Renv[L + 1] = ones
+    for l in range(1, L - 1):  # L_l from C_l = Psi_l Y_l
+        Cl = Psi[l - 1] * Y[l - 1][None, None, None, :]
+        Lenv[l] = env_left(Lenv[l - 1], Cl, A1[l - 1], B1[l - 1])
+    for l in range(L, 2, -1):  # R_l from Y_{l-1} Psi_l
+        Cl = Y[l - 2][:, None, None, None] * Psi[l - 1]
+        Renv[l] = env_right(Renv[l + 1], Cl, A1[l - 1], B1[l - 1])
+    min_gap, ks = 1.0, []
+    for sweep in range(n_sweeps):
+        for q in (0, 1):
+            bonds = [l for l in range(1, L) if (l % 2 == 1) == (q == 0)]
+            facs = {}
+            for l in bonds:
+                M = two_site_matrix(Lenv[l - 1], A1[l - 1], B1[l - 1], A1[l], B1[l], Renv[l + 2])
+                facs[l] = factorize(
+                    M, chi_max, sketch_p, caps[l - 1],
+                    lambda m, k, l=l, st=2 * sweep + q: gaussian_matrix(m, k, seed, pair, st, l),
+                    tau, L)
+            for l in bonds:
+                f = facs[l]
+                cl = Psi[l - 1].shape[0]
+                cr = Psi[l].shape[3]
+                d1, d2 = A1[l - 1].shape[1], B1[l - 1].shape[2]
+                r = len(f.S)
+                U4 = f.U.reshape(cl, d1, d2, r)
+                V4 = f.Vt.reshape(r, d1, d2, cr)
+                Psi[l - 1] = U4 * f.S[None, None, None, :]
+                Psi[l] = f.S[:, None, None, None] * V4
+                Y[l - 1] = 1.0 / f.S
+                n_guard += f.n_guard
+                min_gap = min(min_gap, f.gap)
+                ks.append(f.k)
+                if l <= L - 2:
+                    Lenv[l] = env_left(Lenv[l - 1], U4, A1[l - 1], B1[l - 1])
+                if l + 1 >= 3:
+                    Renv[l + 1] = env_right(Renv[l + 2], V4, A1[l], B1[l])
+            if on_half_step is not None:
+                Cm = canon.merge_inverse_canonical(Psi, Y)
+                Cm[0] = Cm[0] * nu
+                on_half_step(sweep, q, Cm)
+    C = canon.merge_inverse_canonical(Psi, Y)
+    C[0] = C[0] * nu
+    dims = [1] + [c.shape[3] for c in C]
+    return FitResult(C, nu, dims, min_gap, n_guard, ks)
+
+
+def fit_multi_pair(pairs, chi_maxes, n_sweeps, sketch_p=-1, seed=0):
+    """Independent even/odd fits of several pairs; pair i uses Philox pair
+    index i."""
+    return [fit_even_odd(A, B, cm, n_sweeps, sketch_p, seed, pair=i)
+            for i, ((A, B), cm) in enumerate(zip(pairs, chi_maxes))]
