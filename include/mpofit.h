@@ -1,0 +1,176 @@
+/*
+ * libmpofit: variational fit C ~ A.B of two matrix product operators on an
+ * AMD Instinct MI355X (gfx950), with the randomized two-site update.
+ *
+ * The problem statement follows Foderà, Ritter, Shinaoka, von Delft,
+ * "Parallelized contraction of tensor trains or matrix product operators":
+ *   - MPO cores A_l of shape (chi_{l-1}, d_out, d_in, chi_l), chi_0 = chi_L = 1
+ *     (Sec. 2, definition of an MPO);
+ *   - C = A B contracts the input leg of A with the output leg of B (Sec. 2,
+ *     Fig. mpo_mpo (a)); C's cores carry (left, A's out, B's in, right);
+ *   - the fit minimizes ||A B - C||_F (Sec. 2.3, Eq. fit_min) by two-site
+ *     updates (Sec. 2.3.2-2.3.4, Alg. 3), sweeping as in Alg. 5, optionally
+ *     with the randomized SVD of Sec. 3.1, or in the inverse canonical gauge
+ *     with all bonds of one parity updated together (Alg. 4 and Sec. 4).
+ *
+ * Conventions of every entry point:
+ *   - Device pointers live on the device current when the call is made and
+ *     all work is enqueued on `stream` (a hipStream_t passed as void*; NULL =
+ *     the default stream).  Calls return once the work is enqueued, except
+ *     where a call documents a host read-back.
+ *   - The library never allocates device memory: the caller provides one
+ *     workspace blob sized by mpo_fit_workspace_bytes and keeps it, and every
+ *     input pointer, alive until mpo_fit_destroy.  The context object itself
+ *     is host memory owned by the library.
+ *   - Every call returns an mpo_status; no exception or abort crosses the
+ *     boundary.  mpo_last_error() gives a message for the last non-OK status
+ *     of the calling thread.
+ *   - A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef MPOFIT_H
+#define MPOFIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPO_OK = 0,
+  MPO_ERR_INVALID_ARG = 1, /* null pointer, bad enum, bad option value        */
+  MPO_ERR_SHAPE = 2,       /* inconsistent bond or physical dimensions        */
+  MPO_ERR_WORKSPACE = 3,   /* workspace too small or misaligned (256 bytes)   */
+  MPO_ERR_DEVICE = 4,      /* a HIP runtime call failed                       */
+  MPO_ERR_NUMERIC = 5,     /* non-finite value, failed Cholesky, or a singular
+                              value at or below 1e-14 sigma_1 that the inverse
+                              gauge would invert                             */
+  MPO_ERR_UNSUPPORTED = 6  /* option combination this build does not run     */
+} mpo_status;
+
+/* Arithmetic of the contractions (environment extensions, two-site tensor,
+   environment updates).  The QR of the sketch, the truncated SVD and 1/S of
+   the inverse gauge are FP64 in every mode. */
+typedef enum {
+  MPO_FP64 = 0,
+  MPO_FP32 = 1,
+  MPO_BF16 = 2,  /* BF16 operands (power-of-two per-tensor scale, round to
+                    nearest even), FP32 accumulation and FP32 storage */
+  MPO_BF16X3 = 3 /* split BF16: each scaled FP32 operand x = hi + lo, hi and lo
+                    BF16; three BF16 products per term (lo*hi + hi*lo + hi*hi),
+                    FP32 accumulation and storage */
+} mpo_precision;
+
+typedef enum {
+  MPO_SCHED_SERIAL = 0,  /* Alg. 5: alternating forward/backward sweeps of the
+                            site-canonical update of Alg. 3                   */
+  MPO_SCHED_EVEN_ODD = 1 /* inverse canonical gauge (Alg. 4): every bond
+                            l = 1 (mod 2) together, then every l = 0 (mod 2),
+                            from the environments at the half-step's start;
+                            one sweep = both half-steps (Sec. 4)              */
+} mpo_schedule;
+
+/* One MPO: L cores, core l (0-based) is a device array of
+   chi[l] * d * d * chi[l+1] doubles, row-major (left, out, in, right). */
+typedef struct {
+  int32_t L;                 /* number of sites, >= 2                         */
+  int32_t d;                 /* physical dimension (d_out = d_in = d), >= 1   */
+  const int32_t* chi;        /* host array of L+1 bond dims, chi[0]=chi[L]=1  */
+  const double* const* cores;/* host array of L device pointers               */
+} mpo_tt;
+
+typedef struct {
+  mpo_tt A, B;               /* C ~ A B; A and B must share L and d           */
+} mpo_pair;
+
+typedef struct {
+  int32_t chi_max;    /* bond cap chi_C of C (Alg. 3 "maxbonddim"), >= 1      */
+  double tau;         /* truncation tolerance of Sec. 2.3.4; only 0 is run    */
+  int32_t precision;  /* mpo_precision                                         */
+  int32_t schedule;   /* mpo_schedule                                          */
+  int32_t sketch_p;   /* < 0: plain SVD of the two-site matrix; >= 0: RSVD with
+                         k = min(chi_max + p, n, m, chi^A_l chi^B_l) columns  */
+  uint64_t seed;      /* Philox key word 0 of the Gaussian test matrix        */
+  int32_t capture_graph; /* 1: replay each sweep as a captured hipGraph once
+                            the bond dimensions have settled                  */
+  int32_t reserved[3];
+} mpo_fit_opts;
+
+typedef struct mpo_fit_ctx mpo_fit_ctx;
+
+/* Bytes of device workspace mpo_fit_init needs for these pairs and options.
+   `bytes` is written on success. */
+mpo_status mpo_fit_workspace_bytes(const mpo_pair* pairs, int32_t n_pairs,
+                                   const mpo_fit_opts* opts, size_t* bytes);
+
+/* Prepares the fit of every pair (Alg. 5 preprocessing): copies the cores,
+   left-orthogonalizes A and B (norms split off), takes C = A right-
+   orthogonalized (serial) or in inverse canonical form (even/odd) as the
+   initial guess (Sec. 2.3.5), and precomputes the environments.  The inputs
+   may be released once the stream has passed this call.  `workspace` must be
+   256-byte aligned and at least mpo_fit_workspace_bytes long.  On success
+   *ctx receives a new context. */
+mpo_status mpo_fit_init(mpo_fit_ctx** ctx, const mpo_pair* pairs, int32_t n_pairs,
+                        const mpo_fit_opts* opts, void* workspace, size_t ws_bytes,
+                        void* stream);
+
+/* Runs n_sweeps sweeps of every pair.  Serial: a sweep is one directional
+   pass of L-1 updates, the direction alternating from forward (Alg. 5).
+   Even/odd: a sweep is two half-steps.  Synchronizes the stream at the end to
+   read the device status flags; returns MPO_ERR_NUMERIC if one was raised. */
+mpo_status mpo_fit_sweep(mpo_fit_ctx* ctx, int32_t n_sweeps);
+
+/* Current bond dimensions of C for one pair: chi_c receives L+1 ints (host). */
+mpo_status mpo_fit_bond_dims(const mpo_fit_ctx* ctx, int32_t pair, int32_t* chi_c);
+
+/* Copies C of one pair into caller-owned device arrays (FP64, same layout as
+   the inputs, bond dims from mpo_fit_bond_dims), C scaled back by the norms
+   split off A and B, so that C ~ A B.  Enqueued on the context's stream. */
+mpo_status mpo_fit_export_c(mpo_fit_ctx* ctx, int32_t pair, double* const* c_cores);
+
+/* Number of sweeps run so far. */
+mpo_status mpo_fit_sweeps_done(const mpo_fit_ctx* ctx, int32_t* n);
+
+/* Gradient of loss(A, B) = <W, P(A B)>_F with respect to every core of A and
+   B, where P is the orthogonal projector onto the MPOs that share C's
+   isometries after the last sweep (the frozen truncation bases) and have a
+   free bond matrix at the orthogonality centre; equivalently
+   loss = <P(W), A B>_F.  W is an MPO on the same sites (device FP64 cores).
+   gA and gB are caller-owned device arrays shaped like the cores of A and B
+   as passed to mpo_fit_init.  *loss (host) receives the loss; the call
+   synchronizes the stream.  Serial schedule only.  `recompute_env` = 1 keeps
+   only every ceil(sqrt(L))-th left environment and recomputes the rest. */
+mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_tt* W, double* const* gA,
+                        double* const* gB, double* loss, int32_t recompute_env);
+
+/* Fit error ||A B - C||_F / ||A B||_F in FP64 from transfer passes:
+   ||AB||^2 by a four-layer pass, <C, AB> by a three-layer pass and ||C||^2
+   by a two-layer pass, all on the device (the naive product of Alg. 1 is
+   never formed).  The difference of squares floors near 1e-8 (Sec. 5.2).
+   Needs `workspace` of mpo_contract_check_bytes bytes.  Synchronizes
+   `stream`; *rel_err and (if non-null) *ab_norm2 are host outputs. */
+mpo_status mpo_contract_check_bytes(const mpo_pair* pair, const mpo_tt* C, size_t* bytes);
+mpo_status mpo_contract_exact_check(const mpo_pair* pair, const mpo_tt* C, double* rel_err,
+                                    double* ab_norm2, void* workspace, size_t ws_bytes,
+                                    void* stream);
+
+/* Device time, in milliseconds, of the last mpo_fit_sweep call's kernels
+   between its first and last launch (HIP events on the context stream). */
+mpo_status mpo_fit_last_sweep_ms(const mpo_fit_ctx* ctx, double* ms);
+
+/* Per-kernel-class device time of the last mpo_fit_sweep call when the
+   context was created with profiling (opts.reserved[0] = 1): fills up to
+   `n` entries of ms[] and names[] (static strings) and writes the count. */
+mpo_status mpo_fit_profile(const mpo_fit_ctx* ctx, int32_t n, double* ms, const char** names,
+                           double* flops, int32_t* count);
+
+void mpo_fit_destroy(mpo_fit_ctx* ctx);
+
+const char* mpo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPOFIT_H */

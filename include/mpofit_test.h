@@ -1,0 +1,44 @@
+/*
+ * Test hooks of libmpofit: direct entry points to two of its kernels so the
+ * test suite can check them in isolation against NumPy.  Not part of the fit
+ * API.  Same conventions as mpofit.h (device pointers, caller-owned
+ * workspace of at least 64 MiB, 256-byte aligned, work on `stream`, the call
+ * synchronizes the stream before returning).
+ */
+#ifndef MPOFIT_TEST_H
+#define MPOFIT_TEST_H
+
+#include "mpofit.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C[M x N] = alpha * op(A) op(B) (+ C if beta), through the grouped MFMA GEMM.
+   mode: 0 FP64, 1 FP32, 2 BF16; ta/tb/tc: 0 FP64, 1 FP32 element types;
+   a_kcontig: A(m,k) at m*lda+k (1) or k*lda+m (0); b_kcontig: B(k,n) at
+   n*ldb+k (1) or k*ldb+n (0); C(m,n) at m*ldc+n; tile 0 (64x64) or 1
+   (128x128, FP32/BF16); splits >= 1 forces that many K chunks. */
+mpo_status mpo_test_gemm(int mode, int ta, int tb, int tc, int a_kcontig, int b_kcontig, int tile,
+                         int M, int N, int K, const void* A, int lda, const void* B, int ldb,
+                         void* Cm, int ldc, double alpha, int beta, int splits, void* workspace,
+                         size_t ws_bytes, void* stream);
+
+/* Top r eigenpairs of the symmetric k x k FP64 matrix H (row-major, lower
+   triangle read): evals descending, Z k x r row-major. */
+mpo_status mpo_test_eig(const double* H, int k, int r, double* evals, double* Z, void* workspace,
+                        size_t ws_bytes, void* stream);
+
+/* Q = CholeskyQR2 of the n x k FP64 matrix X (row-major, in place). */
+mpo_status mpo_test_cholqr(double* X, int n, int k, void* workspace, size_t ws_bytes, void* stream);
+
+/* Gaussian test matrix of one bond (same definition as the fit's): out is
+   m x k FP64 row-major with rows in (c'', su) order, m = chi * dd. */
+mpo_status mpo_test_omega(double* out, int chi, int dd, int k, int bond, int stream_idx, int pair,
+                          uint64_t seed, void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPOFIT_TEST_H */

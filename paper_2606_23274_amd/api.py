@@ -1,0 +1,149 @@
+"""Python front end of libmpofit: C ~ A B by the variational fit on one GPU.
+
+PyTorch provides device memory and the stream; every step of the fit runs in
+the library's HIP kernels.  Cores are (chi_left, d_out, d_in, chi_right)
+float64 arrays (numpy or torch); C = A B contracts A's input leg with B's
+output leg.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _dev_cores(cores, device):
+    out = []
+    for c in cores:
+        t = c if isinstance(c, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(c))
+        out.append(t.to(device=device, dtype=torch.float64).contiguous())
+    return out
+
+
+class _TT:
+    """Keeps the ctypes view of one MPO and the tensors it points to alive."""
+
+    def __init__(self, cores):
+        self.cores = cores
+        L = len(cores)
+        self.d = int(cores[0].shape[1])
+        chi = [int(cores[0].shape[0])] + [int(c.shape[3]) for c in cores]
+        self.chi = (C.c_int32 * (L + 1))(*chi)
+        self.ptrs = (C.c_void_p * L)(*[c.data_ptr() for c in cores])
+        self.tt = _lib.MpoTT(L, self.d, self.chi, self.ptrs)
+
+
+class FitContext:
+    """One fit of one or several independent MPO pairs.
+
+    precision: 'fp64' | 'fp32' | 'bf16'; schedule: 'serial' | 'even_odd';
+    sketch_p < 0 runs the plain SVD, >= 0 the randomized SVD with chi_max + p
+    sketch columns.
+    """
+
+    def __init__(self, pairs, chi_max, precision="fp32", schedule="serial", sketch_p=-1, seed=0,
+                 capture_graph=True, device="cuda:0", profile=False):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self._tts = []
+        arr = (_lib.MpoPair * len(pairs))()
+        for i, (A, B) in enumerate(pairs):
+            ta, tb = _TT(_dev_cores(A, self.device)), _TT(_dev_cores(B, self.device))
+            self._tts += [ta, tb]
+            arr[i] = _lib.MpoPair(ta.tt, tb.tt)
+        self._pairs = arr
+        self.n_pairs = len(pairs)
+        self.L = [len(A) for A, _ in pairs]
+        opts = _lib.MpoFitOpts()
+        opts.chi_max = int(chi_max)
+        opts.tau = 0.0
+        opts.precision = _lib.PRECISION[precision]
+        opts.schedule = _lib.SCHEDULE[schedule]
+        opts.sketch_p = int(sketch_p)
+        opts.seed = int(seed)
+        opts.capture_graph = 1 if capture_graph else 0
+        opts.reserved[0] = 1 if profile else 0
+        self._opts = opts
+        nbytes = C.c_size_t()
+        _lib.check(self.lib.mpo_fit_workspace_bytes(arr, len(pairs), C.byref(opts), C.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        # 256-byte alignment: over-allocate and offset
+        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        # a stream of our own (default priority): the legacy null stream
+        # cannot be captured into a graph
+        with torch.cuda.device(self.device):
+            torch.cuda.current_stream().synchronize()
+            self.stream = torch.cuda.Stream(device=self.device)
+        ctx = C.c_void_p()
+        _lib.check(self.lib.mpo_fit_init(C.byref(ctx), arr, len(pairs), C.byref(opts),
+                                         C.c_void_p(self._ws_ptr), nbytes.value,
+                                         C.c_void_p(self.stream.cuda_stream)))
+        self.ctx = ctx
+
+    def sweep(self, n=1):
+        _lib.check(self.lib.mpo_fit_sweep(self.ctx, int(n)))  # synchronizes our stream
+
+    def sweeps_done(self):
+        n = C.c_int32()
+        _lib.check(self.lib.mpo_fit_sweeps_done(self.ctx, C.byref(n)))
+        return n.value
+
+    def last_sweep_ms(self):
+        v = C.c_double()
+        _lib.check(self.lib.mpo_fit_last_sweep_ms(self.ctx, C.byref(v)))
+        return v.value
+
+    def bond_dims(self, pair=0):
+        L = self.L[pair]
+        out = (C.c_int32 * (L + 1))()
+        _lib.check(self.lib.mpo_fit_bond_dims(self.ctx, pair, out))
+        return list(out)
+
+    def export(self, pair=0):
+        """C of one pair (scaled so that C ~ A B) as float64 device tensors."""
+        dims = self.bond_dims(pair)
+        L = self.L[pair]
+        d = self._tts[2 * pair].d
+        cores = [torch.empty((dims[i], d, d, dims[i + 1]), dtype=torch.float64, device=self.device)
+                 for i in range(L)]
+        ptrs = (C.c_void_p * L)(*[c.data_ptr() for c in cores])
+        torch.cuda.current_stream(self.device).synchronize()  # allocations visible to our stream
+        _lib.check(self.lib.mpo_fit_export_c(self.ctx, pair, ptrs))  # synchronizes our stream
+        return cores
+
+    def export_numpy(self, pair=0):
+        return [c.cpu().numpy() for c in self.export(pair)]
+
+    def profile(self):
+        n = C.c_int32()
+        _lib.check(self.lib.mpo_fit_profile(self.ctx, 0, None, None, None, C.byref(n)))
+        ms = (C.c_double * n.value)()
+        names = (C.c_char_p * n.value)()
+        _lib.check(self.lib.mpo_fit_profile(self.ctx, n.value, ms, names, None, C.byref(n)))
+        return {names[i].decode(): ms[i] for i in range(n.value)}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.mpo_fit_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fit(A, B, chi_max, sweeps, **kw):
+    """Convenience: fit one pair and return C's cores as numpy arrays."""
+    ctx = FitContext([(A, B)], chi_max, **kw)
+    try:
+        ctx.sweep(sweeps)
+        return ctx.export_numpy(0)
+    finally:
+        ctx.close()

@@ -1,0 +1,453 @@
+// Grouped MFMA GEMM for gfx950 (see gemm.hpp).
+//
+// Workgroup = 256 threads = 4 wave64s in a 2x2 grid; each wave owns a
+// (BM/2) x (BN/2) block of the tile made of 16x16 MFMA blocks.
+//   FP64: v_mfma_f64_16x16x4f64,  BK = 16 (4 MFMA k-steps)
+//   FP32: v_mfma_f32_16x16x4f32,  BK = 16
+//   BF16: v_mfma_f32_16x16x32_bf16, BK = 32, FP32 accumulation
+//   BF16X3: each operand x = hi + lo with hi = bf16(x), lo = bf16(x - hi);
+//         three BF16 MFMAs per product (lo*hi + hi*lo + hi*hi), FP32 accumulation
+// Both operand tiles sit in LDS as [row][BK + pad] with K contiguous, so each
+// lane fetches its fragment with one wide LDS read.  Within a 16-wide K slab
+// lane group g = lane/16 feeds k = 4g + s to MFMA step s (a permutation of
+// the summation order that lets the 4 values be one vector read).  The LDS is
+// double-buffered: the global loads of slab t+1 are in flight while slab t is
+// multiplied.
+#include <tuple>
+
+#include "gemm.hpp"
+
+namespace mpofit {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <int TILE> struct TileShape;
+template <> struct TileShape<0> { static constexpr int BM = 64, BN = 64; };
+template <> struct TileShape<1> { static constexpr int BM = 128, BN = 128; };
+
+template <Mode M> struct ModeT;
+template <> struct ModeT<Mode::F64> {
+  using acc_t = double;
+  using lds_t = double;
+  using accv_t = doublex4;
+  static constexpr int BK = 16;
+  static constexpr int PAD = 2;
+};
+template <> struct ModeT<Mode::F32> {
+  using acc_t = float;
+  using lds_t = float;
+  using accv_t = floatx4;
+  static constexpr int BK = 16;
+  static constexpr int PAD = 4;
+};
+template <> struct ModeT<Mode::BF16> {
+  using acc_t = float;
+  using lds_t = unsigned short;
+  using accv_t = floatx4;
+  static constexpr int BK = 32;
+  static constexpr int PAD = 8;
+};
+template <> struct ModeT<Mode::BF16X3> : ModeT<Mode::BF16> {};
+
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+template <DType T> struct DT;
+template <> struct DT<DType::F64> { using type = double; };
+template <> struct DT<DType::F32> { using type = float; };
+
+// FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ unsigned short f2bf(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (unsigned short)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+// Exponent e with 2^e <= amax < 2^(e+1); 0 for amax == 0.
+__device__ __forceinline__ int scale_exp(const unsigned* amax) {
+  if (!amax) return 0;
+  float a = __uint_as_float(*amax);
+  if (!(a > 0.f)) return 0;
+  int e;
+  frexpf(a, &e);
+  return e - 1;
+}
+
+template <Mode MODE, typename T>
+__device__ __forceinline__ typename ModeT<MODE>::lds_t to_lds(T v, float inv_scale) {
+  if constexpr (MODE == Mode::F64) return (double)v;
+  else if constexpr (MODE == Mode::F32) return (float)v;
+  else return f2bf((float)v * inv_scale);
+}
+
+// low part of the BF16 split of a scaled value: bf16(x - hi)
+template <typename T>
+__device__ __forceinline__ unsigned short lo_part(T v, float inv_scale) {
+  const float x = (float)v * inv_scale;
+  return f2bf(x - bf2f(f2bf(x)));
+}
+
+// Loads a (ROWS x BK) operand tile into registers in the stored type; the
+// conversion to the LDS type (and the BF16 scale) happens at the LDS store.
+template <typename T, bool KCONTIG, int ROWS, int BK>
+struct TileLoader {
+  static constexpr int NV = ROWS * BK / 4 / kThreads;  // 4-wide loads per thread
+  static_assert(NV >= 1, "tile too small");
+  T v[NV][4];
+
+  __device__ __forceinline__ void load(const T* base, int ld, int rows_valid, int k0, int kend,
+                                       bool vec_ok) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      int idx = threadIdx.x + kThreads * i;
+      int r, k;
+      if constexpr (KCONTIG) {
+        r = idx / (BK / 4);
+        k = k0 + 4 * (idx % (BK / 4));
+      } else {
+        k = k0 + idx / (ROWS / 4);
+        r = 4 * (idx % (ROWS / 4));
+      }
+      if constexpr (KCONTIG) {
+        const T* p = base + (long long)r * ld + k;
+        if (vec_ok && r < rows_valid && k + 3 < kend) {
+          if constexpr (sizeof(T) == 4) {
+            float4 q = *reinterpret_cast<const float4*>(p);
+            v[i][0] = q.x; v[i][1] = q.y; v[i][2] = q.z; v[i][3] = q.w;
+          } else {
+            double2 q0 = *reinterpret_cast<const double2*>(p);
+            double2 q1 = *reinterpret_cast<const double2*>(p + 2);
+            v[i][0] = q0.x; v[i][1] = q0.y; v[i][2] = q1.x; v[i][3] = q1.y;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            v[i][j] = (r < rows_valid && k + j < kend) ? p[j] : T(0);
+        }
+      } else {
+        const T* p = base + (long long)k * ld + r;
+        if (vec_ok && r + 3 < rows_valid && k < kend) {
+          if constexpr (sizeof(T) == 4) {
+            float4 q = *reinterpret_cast<const float4*>(p);
+            v[i][0] = q.x; v[i][1] = q.y; v[i][2] = q.z; v[i][3] = q.w;
+          } else {
+            double2 q0 = *reinterpret_cast<const double2*>(p);
+            double2 q1 = *reinterpret_cast<const double2*>(p + 2);
+            v[i][0] = q0.x; v[i][1] = q0.y; v[i][2] = q1.x; v[i][3] = q1.y;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            v[i][j] = (r + j < rows_valid && k < kend) ? p[j] : T(0);
+        }
+      }
+    }
+  }
+
+  template <Mode MODE, typename L>
+  __device__ __forceinline__ void store(L* lds, L* lds_lo, int ldl, float inv_scale) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      int idx = threadIdx.x + kThreads * i;
+      if constexpr (KCONTIG) {
+        int r = idx / (BK / 4);
+        int k = 4 * (idx % (BK / 4));
+        L* q = lds + r * ldl + k;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q[j] = to_lds<MODE>(v[i][j], inv_scale);
+        if constexpr (MODE == Mode::BF16X3) {
+          L* ql = lds_lo + r * ldl + k;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) ql[j] = lo_part(v[i][j], inv_scale);
+        }
+      } else {
+        int k = idx / (ROWS / 4);
+        int r = 4 * (idx % (ROWS / 4));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lds[(r + j) * ldl + k] = to_lds<MODE>(v[i][j], inv_scale);
+        if constexpr (MODE == Mode::BF16X3) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) lds_lo[(r + j) * ldl + k] = lo_part(v[i][j], inv_scale);
+        }
+      }
+    }
+  }
+};
+
+template <Mode MODE, typename TA, typename TB, typename TC, bool AK, bool BKC, int TILE>
+__global__ void __launch_bounds__(kThreads)
+gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
+  using MT = ModeT<MODE>;
+  using acc_t = typename MT::acc_t;
+  using lds_t = typename MT::lds_t;
+  using accv_t = typename MT::accv_t;
+  constexpr int BM = TileShape<TILE>::BM, BN = TileShape<TILE>::BN;
+  constexpr int BK = MT::BK, LDL = BK + MT::PAD;
+  constexpr int WM = BM / 2, WN = BN / 2;       // wave tile
+  constexpr int FM = WM / 16, FN = WN / 16;     // MFMA blocks per wave
+
+  constexpr int NLO = MODE == Mode::BF16X3 ? 2 : 1;  // hi (and lo) tiles
+  __shared__ __align__(16) lds_t sA[NLO][2][BM * LDL];
+  __shared__ __align__(16) lds_t sB[NLO][2][BN * LDL];
+  __shared__ int s_last;
+
+  // locate this workgroup's problem
+  const int wg = blockIdx.x;
+  int lo = 0, hi = n_desc - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].wg_begin <= wg) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc& d = descs[lo];
+  int local = wg - d.wg_begin;
+  const int tn = local % d.tiles_n; local /= d.tiles_n;
+  const int tm = local % d.tiles_m; local /= d.tiles_m;
+  const int split = local % d.splits;
+  const int bidx = local / d.splits;
+  const int b2 = bidx % d.nb[2];
+  const int b1 = (bidx / d.nb[2]) % d.nb[1];
+  const int b0 = bidx / (d.nb[2] * d.nb[1]);
+
+  const TA* Ab = reinterpret_cast<const TA*>(d.A) + b0 * d.sA[0] + b1 * d.sA[1] + b2 * d.sA[2];
+  const TB* Bb = reinterpret_cast<const TB*>(d.B) + b0 * d.sB[0] + b1 * d.sB[1] + b2 * d.sB[2];
+  TC* Cb = reinterpret_cast<TC*>(d.C) + b0 * d.sC[0] + b1 * d.sC[1] + b2 * d.sC[2];
+
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int kbeg = split * d.kchunk;
+  const int kend = min(d.K, kbeg + d.kchunk);
+  // operand origins: A(m0, .), B(., n0)
+  const TA* Ap = AK ? Ab + (long long)m0 * d.lda : Ab + m0;
+  const TB* Bp = BKC ? Bb + (long long)n0 * d.ldb : Bb + n0;
+  const int rows_a = d.M - m0, rows_b = d.N - n0;
+
+  float inv_sa = 1.f, inv_sb = 1.f, out_scale = 1.f;
+  if constexpr (MODE == Mode::BF16 || MODE == Mode::BF16X3) {
+    int ea = scale_exp(d.amax_a), eb = scale_exp(d.amax_b);
+    inv_sa = ldexpf(1.f, -ea);
+    inv_sb = ldexpf(1.f, -eb);
+    out_scale = ldexpf(1.f, ea + eb);
+  }
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int lrow = lane & 15, lgrp = lane >> 4;
+
+  accv_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = accv_t{0, 0, 0, 0};
+
+  TileLoader<TA, AK, BM, BK> la;
+  TileLoader<TB, BKC, BN, BK> lb;
+  const int nslab = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+
+  if (nslab > 0) {
+    la.load(Ap, d.lda, rows_a, kbeg, kend, d.vec_a);
+    lb.load(Bp, d.ldb, rows_b, kbeg, kend, d.vec_b);
+    la.template store<MODE>(sA[0][0], sA[NLO - 1][0], LDL, inv_sa);
+    lb.template store<MODE>(sB[0][0], sB[NLO - 1][0], LDL, inv_sb);
+  }
+  __syncthreads();
+
+  for (int t = 0; t < nslab; ++t) {
+    const int cur = t & 1;
+    const bool more = t + 1 < nslab;
+    if (more) {
+      la.load(Ap, d.lda, rows_a, kbeg + (t + 1) * BK, kend, d.vec_a);
+      lb.load(Bp, d.ldb, rows_b, kbeg + (t + 1) * BK, kend, d.vec_b);
+    }
+    const lds_t* As = sA[0][cur];
+    const lds_t* Bs = sB[0][cur];
+    if constexpr (MODE == Mode::BF16X3) {
+      const lds_t* Al = sA[NLO - 1][cur];
+      const lds_t* Bl = sB[NLO - 1][cur];
+      bf16x8 af[FM], bfr[FN], afl[FM], bfl[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        af[i] = *reinterpret_cast<const bf16x8*>(As + (wm + 16 * i + lrow) * LDL + 8 * lgrp);
+        afl[i] = *reinterpret_cast<const bf16x8*>(Al + (wm + 16 * i + lrow) * LDL + 8 * lgrp);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        bfr[j] = *reinterpret_cast<const bf16x8*>(Bs + (wn + 16 * j + lrow) * LDL + 8 * lgrp);
+        bfl[j] = *reinterpret_cast<const bf16x8*>(Bl + (wn + 16 * j + lrow) * LDL + 8 * lgrp);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afl[i], bfr[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+    } else if constexpr (MODE == Mode::BF16) {
+      bf16x8 af[FM], bfr[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        af[i] = *reinterpret_cast<const bf16x8*>(As + (wm + 16 * i + lrow) * LDL + 8 * lgrp);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        bfr[j] = *reinterpret_cast<const bf16x8*>(Bs + (wn + 16 * j + lrow) * LDL + 8 * lgrp);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    } else {
+      lds_t af[FM][4], bfr[FN][4];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const lds_t* p = As + (wm + 16 * i + lrow) * LDL + 4 * lgrp;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) af[i][s] = p[s];
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const lds_t* p = Bs + (wn + 16 * j + lrow) * LDL + 4 * lgrp;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) bfr[j][s] = p[s];
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            if constexpr (MODE == Mode::F64)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bfr[j][s], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s], bfr[j][s], acc[i][j], 0, 0, 0);
+          }
+    }
+    if (more) {
+      la.template store<MODE>(sA[0][cur ^ 1], sA[NLO - 1][cur ^ 1], LDL, inv_sa);
+      lb.template store<MODE>(sB[0][cur ^ 1], sB[NLO - 1][cur ^ 1], LDL, inv_sb);
+    }
+    __syncthreads();
+  }
+
+  // split-K: every split stores its partial tile; the last to arrive sums
+  // them in split order (deterministic) and runs the epilogue.
+  if (d.splits > 1) {
+    const long long tile_id = ((long long)bidx * d.tiles_m + tm) * d.tiles_n + tn;
+    acc_t* part = reinterpret_cast<acc_t*>(d.partials) +
+                  (tile_id * d.splits) * (long long)(BM * BN);
+    acc_t* mine = part + (long long)split * (BM * BN);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          mine[(((wave * FM + i) * FN + j) * 4 + e) * 64 + lane] = acc[i][j][e];
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int prev = atomicAdd(d.counters + tile_id, 1);
+      s_last = (prev == d.splits - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc_t sum = 0;
+          for (int s = 0; s < d.splits; ++s)
+            sum += __builtin_nontemporal_load(
+                part + (long long)s * (BM * BN) + (((wave * FM + i) * FN + j) * 4 + e) * 64 + lane);
+          acc[i][j][e] = sum;
+        }
+    if (threadIdx.x == 0) d.counters[tile_id] = 0;
+  }
+
+  // epilogue: lane holds column lrow of each 16x16 block; result register e
+  // is row 4*lgrp + e for the FP32/BF16 instructions and row lgrp + 4*e for
+  // the FP64 one (four one-row groups per block)
+  const double alpha = d.alpha * (double)out_scale;
+  float amax = 0.f;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn + 16 * j + lrow;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = m0 + wm + 16 * i + (MODE == Mode::F64 ? lgrp + 4 * e : 4 * lgrp + e);
+        if (row < d.M && col < d.N) {
+          TC* p = Cb + (long long)row * d.ldc + col;
+          double v = alpha * (double)acc[i][j][e];
+          if (d.beta) v += (double)*p;
+          *p = (TC)v;
+          amax = fmaxf(amax, fabsf((float)v));
+        }
+      }
+    }
+  if (d.amax_c) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+    if (lane == 0) atomicMax(d.amax_c, __float_as_uint(amax));
+  }
+}
+
+template <Mode MODE, typename TA, typename TB, typename TC, bool AK, bool BKC>
+void launch_tile(int tile, const GemmDesc* d, int n, int wgs, hipStream_t s) {
+  if constexpr (MODE == Mode::F64) {
+    gemm_kernel<MODE, TA, TB, TC, AK, BKC, 0><<<wgs, kThreads, 0, s>>>(d, n);
+  } else {
+    if (tile == 1) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 1><<<wgs, kThreads, 0, s>>>(d, n);
+    else gemm_kernel<MODE, TA, TB, TC, AK, BKC, 0><<<wgs, kThreads, 0, s>>>(d, n);
+  }
+}
+
+template <Mode MODE, typename TA, typename TB, typename TC>
+void launch_layout(const GemmKind& k, const GemmDesc* d, int n, int wgs, hipStream_t s) {
+  if (k.a_kcontig && k.b_kcontig) launch_tile<MODE, TA, TB, TC, true, true>(k.tile, d, n, wgs, s);
+  else if (k.a_kcontig) launch_tile<MODE, TA, TB, TC, true, false>(k.tile, d, n, wgs, s);
+  else if (k.b_kcontig) launch_tile<MODE, TA, TB, TC, false, true>(k.tile, d, n, wgs, s);
+  else launch_tile<MODE, TA, TB, TC, false, false>(k.tile, d, n, wgs, s);
+}
+
+// Instantiated combinations: FP64 mode takes FP64 or FP32 operands and writes
+// FP64; FP32 and BF16 modes take an FP32 or FP64 first
+// operand, an FP32 second operand, and write FP32.
+template <Mode MODE>
+void launch_types(const GemmKind& k, const GemmDesc* d, int n, int wgs, hipStream_t s) {
+  if constexpr (MODE == Mode::F64) {
+    if (k.tc != DType::F64) throw Error{6, "FP64 GEMM writes FP64"};
+    if (k.ta == DType::F64 && k.tb == DType::F64) launch_layout<MODE, double, double, double>(k, d, n, wgs, s);
+    else if (k.ta == DType::F64) launch_layout<MODE, double, float, double>(k, d, n, wgs, s);
+    else if (k.tb == DType::F64) launch_layout<MODE, float, double, double>(k, d, n, wgs, s);
+    else launch_layout<MODE, float, float, double>(k, d, n, wgs, s);
+  } else {
+    if (k.tc != DType::F32 || k.tb != DType::F32) throw Error{6, "FP32/BF16 GEMM operand types"};
+    if (k.ta == DType::F64) launch_layout<MODE, double, float, float>(k, d, n, wgs, s);
+    else launch_layout<MODE, float, float, float>(k, d, n, wgs, s);
+  }
+}
+
+}  // namespace
+
+int gemm_bm(int tile) { return tile == 1 ? 128 : 64; }
+int gemm_bn(int tile) { return tile == 1 ? 128 : 64; }
+int gemm_bk(Mode mode) { return (mode == Mode::BF16 || mode == Mode::BF16X3) ? 32 : 16; }
+size_t gemm_acc_bytes(Mode mode) { return mode == Mode::F64 ? 8 : 4; }
+
+void launch_gemm(const GemmKind& kind, const GemmDesc* d_descs, int n_desc, int total_wgs,
+                 hipStream_t stream) {
+  if (total_wgs <= 0) return;
+  switch (kind.mode) {
+    case Mode::F64: launch_types<Mode::F64>(kind, d_descs, n_desc, total_wgs, stream); break;
+    case Mode::F32: launch_types<Mode::F32>(kind, d_descs, n_desc, total_wgs, stream); break;
+    case Mode::BF16: launch_types<Mode::BF16>(kind, d_descs, n_desc, total_wgs, stream); break;
+    case Mode::BF16X3: launch_types<Mode::BF16X3>(kind, d_descs, n_desc, total_wgs, stream); break;
+  }
+}
+
+}  // namespace mpofit

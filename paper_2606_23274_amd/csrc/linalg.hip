@@ -1,0 +1,770 @@
+// FP64 small dense linear algebra of the two-site update (see linalg.hpp).
+//
+// Cholesky:   one workgroup per matrix, right-looking, the working copy packed
+//             (lower triangle) in LDS when it fits, else in the output buffer.
+// TRSM:       one wave per row of X; the row lives in registers and the
+//             right-looking substitution needs one broadcast per column.
+// Eigenpairs: Householder tridiagonalization in one workgroup (packed in LDS
+//             when it fits), then per eigenvalue: bisection on Sturm counts
+//             (a workgroup evaluates 256 shifts per round), an eigenvector of
+//             the tridiagonal from its twisted factorization (one thread per
+//             eigenvalue), and the reflectors applied back in column blocks.
+#include <algorithm>
+#include <cfloat>
+
+#include "linalg.hpp"
+
+namespace mpofit {
+
+namespace {
+
+constexpr int kBig = 1024;           // threads of the one-workgroup kernels
+constexpr int kPackedMax = 176;      // packed lower triangle in LDS up to this k
+
+__device__ __forceinline__ long long pidx(int i, int j) { return (long long)i * (i + 1) / 2 + j; }
+
+struct Sym {
+  double* p;
+  int ld;  // 0: packed lower
+  __device__ __forceinline__ double& at(int i, int j) const {  // i >= j
+    return ld ? p[(long long)i * ld + j] : p[pidx(i, j)];
+  }
+};
+
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += red[w];
+  return s;
+}
+
+// ---------------------------------------------------------------- Cholesky
+__global__ void __launch_bounds__(kBig) chol_kernel(const CholDesc* __restrict__ descs) {
+  extern __shared__ double lds[];
+  __shared__ double s_piv;
+  const CholDesc d = descs[blockIdx.x];
+  const int k = d.k;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  Sym A{k <= kPackedMax ? lds : d.R, k <= kPackedMax ? 0 : d.ldr};
+  for (int i = wave; i < k; i += kBig / 64)
+    for (int j = lane; j <= i; j += 64) A.at(i, j) = d.G[(long long)i * d.ldg + j];
+  bool bad = false;
+  for (int j = 0; j < k; ++j) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double v = A.at(j, j);
+      if (!(v > 0.0) || !isfinite(v)) { bad = true; v = DBL_MIN; }
+      s_piv = sqrt(v);
+      A.at(j, j) = s_piv;
+    }
+    __syncthreads();
+    const double inv = 1.0 / s_piv;
+    for (int i = j + 1 + threadIdx.x; i < k; i += kBig) A.at(i, j) *= inv;
+    __syncthreads();
+    const int t = k - j - 1;
+    for (int il = wave; il < t; il += kBig / 64) {
+      const int i = j + 1 + il;
+      const double aij = A.at(i, j);
+      for (int cl = lane; cl <= il; cl += 64) {
+        const int c = j + 1 + cl;
+        A.at(i, c) -= aij * A.at(c, j);
+      }
+    }
+  }
+  __syncthreads();
+  if (bad && d.flag) atomicOr(d.flag, FLAG_CHOL);
+  // R = L^T, row-major upper triangle; zero below
+  if (k <= kPackedMax) {
+    for (int i = wave; i < k; i += kBig / 64)
+      for (int j = lane; j < k; j += 64)
+        d.R[(long long)i * d.ldr + j] = (j >= i) ? A.at(j, i) : 0.0;
+  } else {
+    for (int i = wave; i < k; i += kBig / 64)
+      for (int j = lane; j < i; j += 64) {
+        double lo = d.R[(long long)i * d.ldr + j];  // L(i, j)
+        d.R[(long long)j * d.ldr + i] = lo;
+        d.R[(long long)i * d.ldr + j] = 0.0;
+      }
+  }
+}
+
+// ---------------------------------------------------------------- TRSM
+template <int NS>
+__global__ void __launch_bounds__(kBig) trsm_kernel(const TrsmDesc* __restrict__ descs) {
+  __shared__ double s_inv[64 * NS];
+  const TrsmDesc d = descs[blockIdx.y];
+  const int k = d.k;
+  for (int j = threadIdx.x; j < k; j += kBig) s_inv[j] = 1.0 / d.R[(long long)j * d.ldr + j];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (kBig / 64) + (threadIdx.x >> 6);
+  if (row >= d.n) return;
+  double* x = d.X + (long long)row * d.ldx;
+  double y[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    int c = 64 * s + lane;
+    y[s] = c < k ? x[c] : 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    for (int jj = 0; jj < 64; ++jj) {
+      const int j = 64 * s + jj;
+      if (j >= k) break;
+      const double xj = __shfl(y[s], jj) * s_inv[j];
+      if (lane == jj) y[s] = xj;
+      const double* rj = d.R + (long long)j * d.ldr;
+#pragma unroll
+      for (int s2 = s; s2 < NS; ++s2) {
+        const int c = 64 * s2 + lane;
+        if (c > j && c < k) y[s2] -= xj * rj[c];
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    int c = 64 * s + lane;
+    if (c < k) x[c] = y[s];
+  }
+}
+
+// ---------------------------------------------------------------- eigen
+// work layout (doubles): d[k] e[k] tau[k] V[k*k] X[k*r] Hfull[k*k]
+struct EigWork {
+  double *d, *e, *tau, *V, *X, *H;
+  __device__ EigWork(double* w, int k, int r)
+      : d(w), e(w + k), tau(w + 2 * k), V(w + 3 * k), X(w + 3 * k + (long long)k * k),
+        H(w + 3 * k + (long long)k * k + (long long)k * r) {}
+};
+
+// Householder reduction of the symmetric H to tridiagonal T = Q^T H Q with
+// Q = H_0 H_1 ... H_{k-3}, H_j = I - tau_j v_j v_j^T, v_j(j+1) = 1 (LAPACK's
+// dsytrd convention, lower triangle).
+__global__ void __launch_bounds__(kBig) sytrd_kernel(const EigDesc* __restrict__ descs) {
+  extern __shared__ double lds[];
+  __shared__ double red[16];
+  __shared__ double s_tau, s_scal;
+  const EigDesc dd = descs[blockIdx.x];
+  const int k = dd.k;
+  EigWork W(dd.work, k, dd.r);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool packed = k <= kPackedMax;
+  double* sv = lds;          // k
+  double* sp = lds + k;      // k
+  Sym A{packed ? lds + 2 * k : W.H, packed ? 0 : k};
+  for (int i = wave; i < k; i += 16)
+    for (int j = lane; j <= i; j += 64) A.at(i, j) = dd.H[(long long)i * dd.ldh + j];
+  for (int j = threadIdx.x; j < k * k; j += kBig) W.V[j] = 0.0;
+  __syncthreads();
+  for (int j = 0; j + 2 < k; ++j) {
+    const int t = k - j - 1;
+    for (int i = threadIdx.x; i < t; i += kBig) sv[i] = A.at(j + 1 + i, j);
+    __syncthreads();
+    double part = 0.0;
+    for (int i = threadIdx.x + 1; i < t; i += kBig) part += sv[i] * sv[i];
+    const double xnorm2 = block_sum<16>(part, red);
+    if (threadIdx.x == 0) {
+      const double alpha = sv[0];
+      double tau = 0.0, beta = alpha, scal = 0.0;
+      if (xnorm2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      W.e[j] = beta;
+      W.tau[j] = tau;
+      W.d[j] = A.at(j, j);
+      s_tau = tau;
+      s_scal = scal;
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    if (tau == 0.0) continue;  // uniform
+    for (int i = threadIdx.x; i < t; i += kBig) {
+      const double v = (i == 0) ? 1.0 : sv[i] * s_scal;
+      sv[i] = v;
+      W.V[(long long)j * k + j + 1 + i] = v;
+    }
+    __syncthreads();
+    // p = tau * A22 v
+    for (int il = wave; il < t; il += 16) {
+      double acc = 0.0;
+      for (int cl = lane; cl < t; cl += 64) {
+        const double a = (cl <= il) ? A.at(j + 1 + il, j + 1 + cl) : A.at(j + 1 + cl, j + 1 + il);
+        acc += a * sv[cl];
+      }
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      if (lane == 0) sp[il] = tau * acc;
+    }
+    __syncthreads();
+    double pv = 0.0;
+    for (int i = threadIdx.x; i < t; i += kBig) pv += sp[i] * sv[i];
+    const double K = -0.5 * tau * block_sum<16>(pv, red);
+    for (int i = threadIdx.x; i < t; i += kBig) sp[i] += K * sv[i];
+    __syncthreads();
+    for (int il = wave; il < t; il += 16) {
+      const double vi = sv[il], wi = sp[il];
+      for (int cl = lane; cl <= il; cl += 64)
+        A.at(j + 1 + il, j + 1 + cl) -= vi * sp[cl] + wi * sv[cl];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (k >= 2) {
+      W.d[k - 2] = A.at(k - 2, k - 2);
+      W.e[k - 2] = A.at(k - 1, k - 2);
+      W.tau[k - 2] = 0.0;
+    }
+    W.d[k - 1] = A.at(k - 1, k - 1);
+    W.e[k - 1] = 0.0;
+    W.tau[k - 1] = 0.0;
+  }
+}
+
+// Number of eigenvalues of T strictly below x (Sturm count of the LDL^T of
+// T - x I, with LAPACK's pivmin guard).
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int k, double x,
+                                           double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int i = 1; i < k; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+constexpr int kBisect = 256;
+
+// Eigenvalue jj (0 = largest) of T: each round the workgroup evaluates 256
+// shifts spread over the current bracket and keeps the sub-bracket holding it.
+__global__ void __launch_bounds__(kBisect) bisect_kernel(const EigDesc* __restrict__ descs) {
+  extern __shared__ double lds[];
+  __shared__ double red[4];
+  __shared__ double s_a, s_b;
+  const EigDesc dd = descs[blockIdx.y];
+  const int k = dd.k;
+  const int jj = blockIdx.x;
+  if (jj >= dd.r) return;
+  EigWork W(dd.work, k, dd.r);
+  double* sd = lds;
+  double* se2 = lds + k;
+  double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 0.0;
+  for (int i = threadIdx.x; i < k; i += kBisect) {
+    const double di = W.d[i];
+    const double em = i > 0 ? fabs(W.e[i - 1]) : 0.0;
+    const double ep = i + 1 < k ? fabs(W.e[i]) : 0.0;
+    sd[i] = di;
+    se2[i] = ep * ep;
+    lo = fmin(lo, di - em - ep);
+    hi = fmax(hi, di + em + ep);
+    emax2 = fmax(emax2, ep * ep);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off));
+    hi = fmax(hi, __shfl_xor(hi, off));
+    emax2 = fmax(emax2, __shfl_xor(emax2, off));
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double s_lo[4], s_hi[4], s_em[4];
+  if (lane == 0) { s_lo[wave] = lo; s_hi[wave] = hi; s_em[wave] = emax2; }
+  __syncthreads();
+  lo = fmin(fmin(s_lo[0], s_lo[1]), fmin(s_lo[2], s_lo[3]));
+  hi = fmax(fmax(s_hi[0], s_hi[1]), fmax(s_hi[2], s_hi[3]));
+  emax2 = fmax(fmax(s_em[0], s_em[1]), fmax(s_em[2], s_em[3]));
+  const double pivmin = DBL_MIN * fmax(1.0, emax2);
+  const double span = fmax(hi - lo, DBL_MIN);
+  double a = lo - 2.0 * DBL_EPSILON * span - pivmin;
+  double b = hi + 2.0 * DBL_EPSILON * span + pivmin;
+  const int m = k - 1 - jj;  // ascending index
+  for (int round = 0; round < 12; ++round) {
+    const double x = a + (b - a) * (double)(threadIdx.x + 1) / (double)(kBisect + 1);
+    const int c = sturm_count(sd, se2, k, x, pivmin);
+    const int below = __syncthreads_count(c <= m);
+    if (threadIdx.x == 0) {
+      double na = a, nb = b;
+      if (below > 0) na = a + (b - a) * (double)below / (double)(kBisect + 1);
+      if (below < kBisect) nb = a + (b - a) * (double)(below + 1) / (double)(kBisect + 1);
+      s_a = na;
+      s_b = nb;
+    }
+    __syncthreads();
+    a = s_a;
+    b = s_b;
+    if (b - a <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + pivmin) break;
+  }
+  if (threadIdx.x == 0) dd.evals[jj] = 0.5 * (a + b);
+  (void)red;
+}
+
+// Eigenvector of T for eigenvalue evals[j] from the twisted factorization
+// T - lambda I = N_g Delta_g N_g^T at the twist index g minimizing |gamma_g|
+// (Dhillon-Parlett): z_g = 1, z_i = -(e_i / D+_i) z_{i+1} above g and
+// z_{i+1} = -(e_i / D-_{i+1}) z_i below g.  One thread per eigenvalue; the
+// D+ and D- sequences are kept in LDS (interleaved by thread).
+__global__ void twisted_kernel(const EigDesc* __restrict__ descs) {
+  extern __shared__ double lds[];
+  const EigDesc dd = descs[blockIdx.y];
+  const int k = dd.k;
+  const int T = blockDim.x;
+  EigWork W(dd.work, k, dd.r);
+  double* sd = lds;                          // k
+  double* se = lds + k;                      // k
+  double* Dp = lds + 2 * k;                  // [i*T + tid]
+  double* Dm = Dp + (long long)k * T;
+  for (int i = threadIdx.x; i < k; i += T) {
+    sd[i] = W.d[i];
+    se[i] = i + 1 < k ? W.e[i] : 0.0;
+  }
+  __syncthreads();
+  const int j = blockIdx.x * T + threadIdx.x;
+  if (j >= dd.r) return;
+  const int tid = threadIdx.x;
+  const double lam = dd.evals[j];
+  double emax2 = 0.0;
+  for (int i = 0; i + 1 < k; ++i) emax2 = fmax(emax2, se[i] * se[i]);
+  const double pivmin = DBL_MIN * fmax(1.0, emax2);
+  auto guard = [pivmin](double q) { return fabs(q) < pivmin ? (q < 0 ? -pivmin : pivmin) : q; };
+  // bottom-up D-
+  double q = guard(sd[k - 1] - lam);
+  Dm[(long long)(k - 1) * T + tid] = q;
+  for (int i = k - 2; i >= 0; --i) {
+    const double ei = se[i];
+    q = guard((sd[i] - lam) - ei * ei / q);
+    Dm[(long long)i * T + tid] = q;
+  }
+  // top-down D+ and the twist gamma_i = (d_i - lam) - e_{i-1}^2/D+_{i-1} - e_i^2/D-_{i+1}
+  double best = DBL_MAX;
+  int g = 0;
+  double p = 1.0;
+  for (int i = 0; i < k; ++i) {
+    const double di = sd[i] - lam;
+    const double em2 = i > 0 ? se[i - 1] * se[i - 1] : 0.0;
+    const double top = (i == 0) ? di : di - em2 / p;
+    const double gam = top - (i + 1 < k ? se[i] * se[i] / Dm[(long long)(i + 1) * T + tid] : 0.0);
+    p = guard(top);
+    Dp[(long long)i * T + tid] = p;
+    if (fabs(gam) < best) { best = fabs(gam); g = i; }
+  }
+  // vector, written over D+ (above g) and D- (below g)
+  double nrm2 = 1.0;
+  double z = 1.0;
+  for (int i = g - 1; i >= 0; --i) {
+    z = -(se[i] / Dp[(long long)i * T + tid]) * z;
+    Dp[(long long)i * T + tid] = z;
+    nrm2 += z * z;
+  }
+  z = 1.0;
+  for (int i = g + 1; i < k; ++i) {
+    z = -(se[i - 1] / Dm[(long long)i * T + tid]) * z;
+    Dm[(long long)i * T + tid] = z;
+    nrm2 += z * z;
+  }
+  const double inv = 1.0 / sqrt(nrm2);
+  for (int i = 0; i < k; ++i) {
+    const double zi = (i < g) ? Dp[(long long)i * T + tid] : (i == g ? 1.0 : Dm[(long long)i * T + tid]);
+    W.X[(long long)i * dd.r + j] = zi * inv;
+  }
+}
+
+// Z[:, cols] = H_0 H_1 ... H_{k-3} X[:, cols] for one block of columns.
+__global__ void __launch_bounds__(kBig) backtransform_kernel(const EigDesc* __restrict__ descs,
+                                                             int rb) {
+  extern __shared__ double lds[];
+  const EigDesc dd = descs[blockIdx.y];
+  const int k = dd.k, r = dd.r;
+  const int c0 = blockIdx.x * rb;
+  if (c0 >= r) return;
+  const int nc = min(rb, r - c0);
+  EigWork W(dd.work, k, r);
+  double* Xs = lds;                        // k * nc
+  double* sv = lds + (long long)k * nc;    // k
+  double* sw = sv + k;                     // nc
+  double* part = sw + nc;                  // P * nc <= kBig
+  for (int idx = threadIdx.x; idx < k * nc; idx += kBig) {
+    const int i = idx / nc, c = idx % nc;
+    Xs[idx] = W.X[(long long)i * r + c0 + c];
+  }
+  const int P = kBig / nc;  // row partitions of the dot products
+  for (int j = k - 3; j >= 0; --j) {
+    const double tau = W.tau[j];
+    if (tau == 0.0) continue;  // uniform
+    const int t = k - j - 1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < t; i += kBig) sv[i] = W.V[(long long)j * k + j + 1 + i];
+    __syncthreads();
+    if (threadIdx.x < P * nc) {
+      const int c = threadIdx.x % nc, pp = threadIdx.x / nc;
+      double acc = 0.0;
+      for (int i = pp; i < t; i += P) acc += sv[i] * Xs[(long long)(j + 1 + i) * nc + c];
+      part[pp * nc + c] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+      double s = 0.0;
+      for (int pp = 0; pp < P; ++pp) s += part[pp * nc + threadIdx.x];
+      sw[threadIdx.x] = tau * s;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < t * nc; idx += kBig) {
+      const int i = idx / nc, c = idx % nc;
+      Xs[(long long)(j + 1 + i) * nc + c] -= sv[i] * sw[c];
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < k * nc; idx += kBig) {
+    const int i = idx / nc, c = idx % nc;
+    dd.Z[(long long)i * dd.ldz + c0 + c] = Xs[idx];
+  }
+}
+
+
+// ---------------------------------------------------------------- register-resident variants
+// For k <= 32*NB the k x k matrix lives in registers: thread (tr, tc) of a
+// 32 x 32 grid (tid = 32 tr + tc, so one thread row is half a wave) holds
+// rows tr + 32a and columns tc + 32b, a, b < NB.  Reductions along a row stay
+// inside the wave (shuffles); column data is broadcast through LDS.
+constexpr int kRegNB = 5;  // k <= 160
+
+template <int NB>
+__device__ __forceinline__ double row_reduce32(double v) {
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// G = L L^T (Cholesky, L lower) then R^{-1} = (L^{-1})^T written row-major
+// (upper triangular, zeros below).  One barrier per step: the owners of
+// column jj publish it (double-buffered), then every thread forms the pivot
+// and updates its trailing entries; blocks entirely left of / above column
+// jj are skipped with uniform branches.
+template <int NB>
+__global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __restrict__ descs) {
+  __shared__ double colb[2][32 * NB];
+  __shared__ double rowb[2][32 * NB];
+  const CholDesc d = descs[blockIdx.x];
+  const int k = d.k;
+  const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
+  double a[NB][NB], x[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int r = tr + 32 * i, c = tc + 32 * j;
+      a[i][j] = (r < k && c < k) ? d.G[(long long)r * d.ldg + c] : 0.0;
+      x[i][j] = (r == c && r < k) ? 1.0 : 0.0;
+    }
+  bool bad = false;
+  // Cholesky: a(r, c) -= a(r, jj) a(c, jj) / a(jj, jj) on the trailing block;
+  // column jj of L is a(:, jj) / sqrt(a(jj, jj)).
+  for (int jj = 0; jj < k; ++jj) {
+    const int jb = jj >> 5, jt = jj & 31, buf = jj & 1;
+    if (tc == jt) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (j == jb) colb[buf][tr + 32 * i] = (tr + 32 * i >= jj) ? a[i][j] : 0.0;
+    }
+    __syncthreads();
+    const double djj = colb[buf][jj];
+    if (!(djj > 0.0) || !isfinite(djj)) bad = true;
+    const double invd = (djj > 0.0) ? 1.0 / djj : 0.0;
+    const double invs = (djj > 0.0) ? 1.0 / sqrt(djj) : 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      if (i < jb) continue;  // uniform: rows < 32*jb <= jj
+      const int r = tr + 32 * i;
+      const double cr = colb[buf][r] * invd;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < jb) continue;
+        const int c = tc + 32 * j;
+        if (c > jj && r > jj) a[i][j] -= cr * colb[buf][c];
+        if (c == jj && r >= jj) a[i][j] *= invs;  // finished column of L
+      }
+    }
+  }
+  // X = L^{-1}: X(jj,:) /= L(jj,jj); X(r,:) -= L(r,jj) X(jj,:) for r > jj
+  for (int jj = 0; jj < k; ++jj) {
+    const int jb = jj >> 5, jt = jj & 31, buf = jj & 1;
+    if (tc == jt) {  // L(:, jj)
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (j == jb) colb[buf][tr + 32 * i] = (tr + 32 * i >= jj) ? a[i][j] : 0.0;
+    }
+    if (tr == jt) {  // row jj of X before the scaling (columns <= jj only)
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (i == jb) {
+#pragma unroll
+          for (int j = 0; j < NB; ++j) rowb[buf][tc + 32 * j] = x[i][j];
+        }
+    }
+    __syncthreads();
+    const double linv = 1.0 / colb[buf][jj];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      if (i < jb) continue;
+      const int r = tr + 32 * i;
+      if (r == jj) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) x[i][j] *= linv;
+      } else if (r > jj && r < k) {
+        const double l = colb[buf][r] * linv;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          if (j > jb) continue;  // X(jj, c) = 0 for c > jj
+          x[i][j] -= l * rowb[buf][tc + 32 * j];
+        }
+      }
+    }
+  }
+  if (bad && d.flag) atomicOr(d.flag, FLAG_CHOL);
+  // R^{-1}(c, r) = X(r, c)
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int r = tr + 32 * i, c = tc + 32 * j;
+      if (r < k && c < k) d.R[(long long)c * d.ldr + r] = x[i][j];
+    }
+}
+
+// Householder tridiagonalization (same reflector convention as sytrd_kernel)
+// on the register-resident matrix; reflectors go to W.H (row j = v_j), then
+// Q^T = H_{k-3} ... H_0 is accumulated in the same registers and written to
+// W.V (row-major k x k); d, e to W.d, W.e.
+template <int NB>
+__global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restrict__ descs) {
+  __shared__ double vb[32 * NB], wb[32 * NB];
+  __shared__ double s_tau;
+  const EigDesc dd = descs[blockIdx.x];
+  const int k = dd.k;
+  EigWork W(dd.work, k, dd.r);
+  double* vstore = W.H;
+  const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double a[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int r = tr + 32 * i, c = tc + 32 * j;
+      const int hi = r > c ? r : c, lo = r > c ? c : r;
+      a[i][j] = (r < k && c < k) ? dd.H[(long long)hi * dd.ldh + lo] : 0.0;
+    }
+  for (int jj = 0; jj + 2 < k; ++jj) {
+    const int jb = jj >> 5, jt = jj & 31;
+    if (tc == jt) {  // x = A(jj+1:, jj) into vb; the diagonal entry to d
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (j == jb) {
+            const int r = tr + 32 * i;
+            vb[r] = (r > jj && r < k) ? a[i][j] : 0.0;
+            if (r == jj) W.d[jj] = a[i][j];
+          }
+    }
+    __syncthreads();
+    if (wave == 0) {  // norm, beta, tau and the scaled reflector v (v(jj+1) = 1)
+      double part = 0.0;
+      for (int r = jj + 2 + lane; r < k; r += 64) part += vb[r] * vb[r];
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+      const double alpha = vb[jj + 1];
+      double tau = 0.0, beta = alpha, scal = 0.0;
+      if (part > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + part), alpha);
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      for (int r = lane; r < 32 * NB; r += 64) {
+        double v = 0.0;
+        if (tau != 0.0) v = (r == jj + 1) ? 1.0 : (r > jj + 1 && r < k ? vb[r] * scal : 0.0);
+        vb[r] = v;
+        if (r < k) vstore[(long long)jj * k + r] = v;
+      }
+      if (lane == 0) {
+        W.e[jj] = beta;
+        W.tau[jj] = tau;
+        s_tau = tau;
+      }
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    if (tau == 0.0) continue;  // uniform
+    // p = tau * A22 v on rows > jj (v vanishes on columns <= jj)
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      if (i < jb) {  // uniform: rows <= jj
+        if (tc == 0) wb[tr + 32 * i] = 0.0;
+        continue;
+      }
+      double pr = 0.0;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < jb) continue;
+        pr += a[i][j] * vb[tc + 32 * j];
+      }
+      pr = row_reduce32<NB>(pr);
+      if (tc == 0) wb[tr + 32 * i] = (tr + 32 * i > jj) ? tau * pr : 0.0;
+    }
+    __syncthreads();
+    if (wave == 0) {  // w = p - (tau/2)(p.v) v
+      double pv = 0.0;
+      for (int r = lane; r < 32 * NB; r += 64) pv += wb[r] * vb[r];
+      for (int off = 32; off > 0; off >>= 1) pv += __shfl_xor(pv, off);
+      const double K = -0.5 * tau * pv;
+      for (int r = lane; r < 32 * NB; r += 64) wb[r] += K * vb[r];
+    }
+    __syncthreads();
+    // A22 -= v w^T + w v^T (trailing block only; v, w vanish at <= jj)
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      if (i < jb) continue;  // uniform
+      const int r = tr + 32 * i;
+      const double vi = vb[r], wi = wb[r];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < jb) continue;
+        const int c = tc + 32 * j;
+        if (r > jj && c > jj) a[i][j] -= vi * wb[c] + wi * vb[c];
+      }
+    }
+    __syncthreads();
+  }
+  if (k >= 2) {
+    const int r0 = k - 2, r1 = k - 1;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int r = tr + 32 * i, c = tc + 32 * j;
+        if (r == r0 && c == r0) W.d[r0] = a[i][j];
+        if (r == r1 && c == r1) W.d[r1] = a[i][j];
+        if (r == r1 && c == r0) W.e[r0] = a[i][j];
+      }
+    if (threadIdx.x == 0) { W.tau[k - 2] = 0.0; W.e[k - 1] = 0.0; W.tau[k - 1] = 0.0; }
+  } else {
+    if (threadIdx.x == 0) { W.d[0] = a[0][0]; W.e[0] = 0.0; W.tau[0] = 0.0; }
+  }
+  __threadfence_block();
+  __syncthreads();
+  // Q^T = H_{k-3} ... H_0: M <- M H_j = M - tau_j (M v_j) v_j^T for j = k-3 .. 0
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) a[i][j] = (tr + 32 * i == tc + 32 * j) ? 1.0 : 0.0;
+  double vnext = 0.0;
+  if (k >= 3 && threadIdx.x < 32 * NB)
+    vnext = threadIdx.x < k ? vstore[(long long)(k - 3) * k + threadIdx.x] : 0.0;
+  for (int jj = k - 3; jj >= 0; --jj) {
+    const double tau = W.tau[jj];
+    if (threadIdx.x < 32 * NB) vb[threadIdx.x] = vnext;
+    if (jj > 0 && threadIdx.x < 32 * NB)  // prefetch the next reflector
+      vnext = threadIdx.x < k ? vstore[(long long)(jj - 1) * k + threadIdx.x] : 0.0;
+    __syncthreads();
+    const int jb = (jj + 1) >> 5;  // v_jj vanishes below column jj+1
+    if (tau != 0.0) {  // uniform
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        double pr = 0.0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          if (j < jb) continue;
+          pr += a[i][j] * vb[tc + 32 * j];
+        }
+        pr = row_reduce32<NB>(pr);
+        if (tc == 0) wb[tr + 32 * i] = tau * pr;
+      }
+    }
+    __syncthreads();
+    if (tau != 0.0) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const double wi = wb[tr + 32 * i];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          if (j < jb) continue;
+          a[i][j] -= wi * vb[tc + 32 * j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int r = tr + 32 * i, c = tc + 32 * j;
+      if (r < k && c < k) W.V[(long long)r * k + c] = a[i][j];
+    }
+}
+
+}  // namespace
+
+size_t eig_work_doubles(int k, int r) {
+  return 3 * (size_t)k + 2 * (size_t)k * k + (size_t)k * r;
+}
+
+double* eig_work_qt(double* w, int k, int r) { (void)r; return w + 3 * (size_t)k; }
+double* eig_work_x(double* w, int k, int r) { (void)r; return w + 3 * (size_t)k + (size_t)k * k; }
+
+void launch_chol(const CholDesc* d, int n, int max_k, int inverse, hipStream_t s) {
+  if (n <= 0) return;
+  if (inverse) {
+    hipLaunchKernelGGL(chol_inv_reg_kernel<kRegNB>, dim3(n), dim3(kBig), 0, s, d);
+    return;
+  }
+  // every problem with k <= kPackedMax works in LDS, whatever the batch's max
+  const int kp = std::min(max_k, kPackedMax);
+  size_t lds = (size_t)kp * (kp + 1) / 2 * sizeof(double);
+  hipLaunchKernelGGL(chol_kernel, dim3(n), dim3(kBig), lds, s, d);
+}
+
+void launch_trsm(const TrsmDesc* d, int n, int max_rows, hipStream_t s) {
+  // caller guarantees k <= 512 for every descriptor (checked on the host)
+  if (n <= 0 || max_rows <= 0) return;
+  dim3 grid(ceil_div(max_rows, kBig / 64), n);
+  hipLaunchKernelGGL(trsm_kernel<8>, grid, dim3(kBig), 0, s, d);
+}
+
+void launch_eig(const EigDesc* d, const EigDesc* h, int n, int reg, hipStream_t s) {
+  if (n <= 0) return;
+  int max_k = 0, max_r = 0;
+  for (int i = 0; i < n; ++i) {
+    max_k = std::max(max_k, h[i].k);
+    max_r = std::max(max_r, h[i].r);
+  }
+  if (reg) {
+    hipLaunchKernelGGL(sytrd_reg_kernel<kRegNB>, dim3(n), dim3(kBig), 0, s, d);
+  } else {
+    const int kp = std::min(max_k, kPackedMax);
+    const size_t lds1 = (2 * (size_t)max_k + (size_t)kp * (kp + 1) / 2) * sizeof(double);
+    hipLaunchKernelGGL(sytrd_kernel, dim3(n), dim3(kBig), lds1, s, d);
+  }
+  hipLaunchKernelGGL(bisect_kernel, dim3(max_r, n), dim3(kBisect), 2 * max_k * sizeof(double), s, d);
+  int T = 64;
+  while (T > 1 && (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double) > 150 * 1024) T /= 2;
+  hipLaunchKernelGGL(twisted_kernel, dim3(ceil_div(max_r, T), n), dim3(T),
+                     (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double), s, d);
+  if (reg) return;
+  // column blocks so that the block plus vectors fit in LDS
+  int rb = std::max(1, std::min(max_r, (int)(120 * 1024 / sizeof(double) / max_k)));
+  rb = std::min(rb, kBig);
+  const size_t lds4 = ((size_t)max_k * rb + max_k + rb + kBig) * sizeof(double);
+  hipLaunchKernelGGL(backtransform_kernel, dim3(ceil_div(max_r, rb), n), dim3(kBig), lds4, s, d, rb);
+}
+
+}  // namespace mpofit

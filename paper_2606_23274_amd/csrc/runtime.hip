@@ -1,0 +1,1397 @@
+// Host runtime of libmpofit: plan, workspace, initialization, the serial and
+// even/odd sweep programs, export, and the C ABI (include/mpofit.h).
+//
+// Device layouts (all row-major; c, a, b = bonds of C, A, B; s = A's output
+// leg, t = the contracted leg, u = B's input leg; dd = d*d; i = 0-based site):
+//   A, B cores (FP64 master)          [a][s][t][a']
+//   C cores (FP64)                    [c][s][u][c']
+//   working copies (FP32 or FP64):
+//     Bw  = B            [b][t][u][b']   right operand of the first left step
+//     Bmw = B mirrored   [b'][t][u][b]   same for the right environment
+//     At  = A            [a][t][s][a']   (t before s) second left step
+//     Amt = A mirrored   [a'][t][s][a]   second right step
+//   Lenv[i]  left environment of sites 0..i-1    [c][a][b] at bond i
+//   Renv[j]  right environment of sites j..L-1   [c][a][b] at bond j
+//   XL[i]    L_i A_i B_i           [c][s][u][a'][b']      (bond i+1 on a', b')
+//   XR[i]    A_{i+1} B_{i+1} R_{i+2}  [c''][s][u][a'][b']
+//   two-site matrix of bond i: Theta = XL[i] XR[i]^T, n x m with rows
+//     (c, s1, u1) and columns (c'', s2, u2).
+// With these orders every contraction of Fig. envs and Fig. derivatives is a
+// GEMM whose free and contracted index groups each have a single stride.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+
+#include "../../include/mpofit.h"
+#include "program.hpp"
+
+namespace mpofit {
+
+thread_local std::string g_last_error;
+
+// ------------------------------------------------------------------ programs
+void run_program(const Program& p, hipStream_t s, hipEvent_t* ev) {
+  if (ev) HIP_OK(hipEventRecord(ev[0], s));
+  for (size_t li = 0; li < p.launches.size(); ++li) {
+    const Launch& l = p.launches[li];
+    switch (l.kind) {
+      case LK::Gemm: launch_gemm(l.gk, p.device<GemmDesc>(l), l.n, (int)l.wgs, s); break;
+      case LK::Chol: launch_chol(p.device<CholDesc>(l), l.n, (int)l.maxa, l.maxb, s); break;
+      case LK::Trsm: launch_trsm(p.device<TrsmDesc>(l), l.n, (int)l.maxa, s); break;
+      case LK::Eig: launch_eig(p.device<EigDesc>(l), p.host<EigDesc>(l), l.n, l.maxb, s); break;
+      case LK::Omega: launch_omega(p.device<OmegaDesc>(l), l.n, (int)l.maxa, s); break;
+      case LK::Sign: launch_signfix(p.device<SignDesc>(l), l.n, (int)l.maxa, s); break;
+      case LK::Scale: launch_scale(p.device<ScaleDesc>(l), l.n, (int)l.maxa, s); break;
+      case LK::Perm: launch_perm(p.device<PermDesc>(l), l.n, l.maxa, s); break;
+      case LK::Sval: launch_svals(p.device<SvalDesc>(l), l.n, (int)l.maxa, s); break;
+      case LK::Fill: launch_fill(p.device<FillDesc>(l), l.n, l.maxa, s); break;
+      case LK::Norm: launch_norm(p.device<NormDesc>(l), l.n, s); break;
+      case LK::Bump: launch_bump(l.counter, l.bump_by, s); break;
+    }
+    HIP_OK(hipGetLastError());
+    if (ev) HIP_OK(hipEventRecord(ev[li + 1], s));
+  }
+}
+
+namespace {
+
+// ------------------------------------------------------------------ workspace
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += std::max<size_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+// ------------------------------------------------------------------ GEMM recording
+struct Op {
+  const void* p;
+  DType t;
+  bool kc;  // K-contiguous
+  int ld;
+  long long s[3] = {0, 0, 0};
+  const unsigned* amax = nullptr;
+};
+struct Out {
+  void* p;
+  DType t;
+  int ld;
+  long long s[3] = {0, 0, 0};
+  unsigned* amax = nullptr;
+};
+
+struct GemmJob {
+  int M, N, K;
+  Op A, B;
+  Out C;
+  int nb[3] = {1, 1, 1};
+  double alpha = 1.0;
+  int beta = 0;
+};
+
+struct SplitBuf {
+  void* partials = nullptr;
+  size_t cap = 0;  // bytes
+  int* counters = nullptr;
+  int ccap = 0;
+};
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Appends one grouped GEMM launch covering `jobs` (all of one kind).
+void add_gemm(Program& P, const SplitBuf& sb, Mode mode, const std::vector<GemmJob>& jobs,
+              const char* cls, double flops) {
+  if (jobs.empty()) return;
+  GemmKind gk{mode, jobs[0].A.t, jobs[0].B.t, jobs[0].C.t, jobs[0].A.kc, jobs[0].B.kc, 0};
+  // tile: 128x128 for FP32/BF16 when every problem is large enough and the
+  // launch still has >= 256 workgroups
+  if (mode != Mode::F64) {
+    bool big = true;
+    long long w128 = 0;
+    for (auto& j : jobs) {
+      if (j.M < 128 || j.N < 128) big = false;
+      w128 += (long long)ceil_div(j.M, 128) * ceil_div(j.N, 128) * j.nb[0] * j.nb[1] * j.nb[2];
+    }
+    if (big && w128 >= 256) gk.tile = 1;
+  }
+  const int BM = gemm_bm(gk.tile), BN = gemm_bn(gk.tile), BK = gemm_bk(mode);
+  long long base_wgs = 0;
+  for (auto& j : jobs)
+    base_wgs += (long long)ceil_div(j.M, BM) * ceil_div(j.N, BN) * j.nb[0] * j.nb[1] * j.nb[2];
+  const int want = base_wgs >= 256 ? 1 : (int)std::min<long long>(16, (512 + base_wgs - 1) / base_wgs);
+  std::vector<GemmDesc> ds;
+  long long wg = 0;
+  size_t poff = 0;
+  int coff = 0;
+  for (auto& j : jobs) {
+    GemmDesc d{};
+    d.A = j.A.p; d.B = j.B.p; d.C = j.C.p;
+    for (int q = 0; q < 3; ++q) { d.sA[q] = j.A.s[q]; d.sB[q] = j.B.s[q]; d.sC[q] = j.C.s[q]; d.nb[q] = j.nb[q]; }
+    d.M = j.M; d.N = j.N; d.K = j.K;
+    d.lda = j.A.ld; d.ldb = j.B.ld; d.ldc = j.C.ld;
+    d.tiles_m = ceil_div(j.M, BM);
+    d.tiles_n = ceil_div(j.N, BN);
+    d.beta = j.beta;
+    d.alpha = j.alpha;
+    d.amax_a = j.A.amax; d.amax_b = j.B.amax; d.amax_c = j.C.amax;
+    auto vec = [](const Op& o) {
+      bool ok = (o.ld % 4 == 0) && aligned16(o.p);
+      for (int q = 0; q < 3; ++q) ok = ok && (o.s[q] % 4 == 0);
+      return ok ? 1 : 0;
+    };
+    d.vec_a = vec(j.A);
+    d.vec_b = vec(j.B);
+    const long long tiles = (long long)d.tiles_m * d.tiles_n * j.nb[0] * j.nb[1] * j.nb[2];
+    int splits = std::max(1, std::min(want, j.K / (2 * BK)));
+    int kchunk = ceil_div(ceil_div(j.K, splits), BK) * BK;
+    splits = std::max(1, ceil_div(j.K, kchunk));
+    const size_t need = (size_t)tiles * splits * BM * BN * gemm_acc_bytes(mode);
+    if (splits > 1 && (poff + need > sb.cap || coff + tiles > sb.ccap)) {
+      splits = 1;
+      kchunk = std::max(j.K, 1);
+    }
+    d.splits = splits;
+    d.kchunk = splits > 1 ? kchunk : std::max(j.K, 1);
+    if (splits > 1) {
+      d.partials = static_cast<char*>(sb.partials) + poff;
+      d.counters = sb.counters + coff;
+      poff += need;
+      coff += (int)tiles;
+    }
+    d.wg_begin = (int)wg;
+    wg += tiles * splits;
+    ds.push_back(d);
+  }
+  Launch l;
+  l.kind = LK::Gemm;
+  l.gk = gk;
+  l.off = P.push(ds);
+  l.n = (int)ds.size();
+  l.wgs = wg;
+  l.cls = cls;
+  l.flops = flops;
+  P.launches.push_back(l);
+}
+
+template <class D>
+void add_simple(Program& P, LK kind, const std::vector<D>& ds, long long maxa, const char* cls,
+                double flops = 0) {
+  if (ds.empty()) return;
+  Launch l;
+  l.kind = kind;
+  l.off = P.push(ds);
+  l.n = (int)ds.size();
+  l.maxa = maxa;
+  l.cls = cls;
+  l.flops = flops;
+  P.launches.push_back(l);
+}
+
+// ------------------------------------------------------------------ state
+struct PairState {
+  int L = 0, d = 0, dd = 0;
+  std::vector<int> cA, cB, cC;  // bond dims (L+1): preprocessed A, B; current C
+  std::vector<int> capC;        // capacity of C's bonds over the whole fit
+  std::vector<int> rcap;        // chi^A_i chi^B_i per bond index i (1..L-1)
+  // FP64 master cores
+  std::vector<double*> A64, B64, C64;
+  // working copies
+  std::vector<void*> Bw, Bmw, At, Amt;
+  std::vector<unsigned*> amBw, amBmw, amAt, amAmt;
+  std::vector<void*> Lenv, Renv;  // by bond index 0..L
+  std::vector<unsigned*> amL, amR;
+  std::vector<void*> XL, XR;      // by bond 0..L-2
+  std::vector<unsigned*> amXL, amXR;
+  // inverse gauge (even/odd): Y_i = 1/S_i per bond 1..L-1 (bond index)
+  std::vector<double*> Yv;
+  double* nu_dev = nullptr;       // [2]: nu_A, nu_B
+  double nu = 1.0;
+  // host copies of the input shapes
+  std::vector<int> chiA_in, chiB_in;
+  std::vector<const double*> A_in, B_in;
+};
+
+// Factorization scratch of one bond.
+struct BondScratch {
+  void* theta;    // n x m (working type)
+  void* T;        // first-step scratch of the left/right extension (working type)
+  unsigned* amT;
+  double *omega, *Y, *Y2, *G, *R, *Bk, *H, *eigw, *evals, *Z, *S, *V, *sign, *SVt;
+};
+
+struct Ctx {
+  mpo_fit_opts o{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Mode wmode = Mode::F32;  // arithmetic of the contractions
+  DType wt = DType::F32;   // storage type of environments and extensions
+  std::vector<PairState> pairs;
+  std::vector<BondScratch> scratch;  // serial: 1; even/odd: max bonds per half-step over pairs
+  SplitBuf sb;
+  int* flag = nullptr;          // device status flags
+  int* sweep_dev = nullptr;     // device sweep counter (Philox stream)
+  char* arena = nullptr;        // descriptor arena
+  size_t arena_cap = 0;
+  size_t arena_used = 0;
+  // init scratch (FP64)
+  double *iG, *iR1, *iR2, *iRt, *iTmp, *iXt;
+  size_t iTmpN = 0;
+  int sweeps_done = 0;
+  std::map<std::string, Program> programs;  // keyed by shape plan
+  std::map<std::string, hipGraphExec_t> graphs;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = 0;
+  bool profile = false;
+  std::vector<std::pair<std::string, double>> prof_ms;
+  std::vector<double> prof_flops;
+  size_t ws_bytes = 0;
+};
+
+int bytes_of(DType t) { return t == DType::F64 ? 8 : 4; }
+
+// ------------------------------------------------------------------ shapes
+// Bond dims after the preprocessing and initial guess, and the capacity of
+// each of C's bonds over the fit (the ranks r = min(chi_max, n, m, cap)
+// settle within two sweeps; simulated here on the host).
+void plan_shapes(PairState& P, int chi_max, int schedule) {
+  const int L = P.L, dd = P.dd;
+  auto leftorth = [&](const std::vector<int>& in) {
+    std::vector<int> c(in);
+    for (int i = 1; i < L; ++i) c[i] = std::min(in[i], c[i - 1] * dd);
+    // the left sweep only clips from the left; entries to the right keep in[]
+    return c;
+  };
+  P.cA = leftorth(P.chiA_in);
+  P.cB = leftorth(P.chiB_in);
+  P.rcap.assign(L + 1, 1);
+  for (int i = 1; i < L; ++i) P.rcap[i] = P.cA[i] * P.cB[i];
+  // initial C: A right-orthogonalized
+  std::vector<int> c(P.cA);
+  for (int i = L - 1; i >= 1; --i) c[i] = std::min(c[i], dd * c[i + 1]);
+  P.cC = c;
+  P.capC = c;
+  std::vector<int> sim(c);
+  auto upd = [&](int b) {  // bond b = 1..L-1 joins sites b-1, b
+    const int n = sim[b - 1] * dd, m = dd * sim[b + 1];
+    sim[b] = std::min(std::min(chi_max, P.rcap[b]), std::min(n, m));
+    P.capC[b] = std::max(P.capC[b], sim[b]);
+  };
+  for (int sw = 0; sw < 6; ++sw) {
+    if (schedule == MPO_SCHED_SERIAL) {
+      if (sw % 2 == 0) for (int b = 1; b < L; ++b) upd(b);
+      else for (int b = L - 1; b >= 1; --b) upd(b);
+    } else {
+      for (int q = 0; q < 2; ++q) {
+        std::vector<int> prev(sim);
+        for (int b = 1; b < L; ++b)
+          if ((b % 2 == 1) == (q == 0)) {
+            const int n = prev[b - 1] * dd, m = dd * prev[b + 1];
+            sim[b] = std::min(std::min(chi_max, P.rcap[b]), std::min(n, m));
+            P.capC[b] = std::max(P.capC[b], sim[b]);
+          }
+      }
+    }
+  }
+}
+
+struct Caps {  // per-pair maxima for scratch sizing
+  long long nm_max = 1, kmax = 1, rmax = 1, theta = 1, T = 1, ext = 1;
+};
+
+Caps pair_caps(const PairState& P, const mpo_fit_opts& o) {
+  Caps c;
+  for (int b = 1; b < P.L; ++b) {  // bond b joins sites b-1 and b
+    const long long n = (long long)P.capC[b - 1] * P.dd, m = (long long)P.dd * P.capC[b + 1];
+    c.nm_max = std::max({c.nm_max, n, m});
+    c.theta = std::max(c.theta, n * m);
+    const long long kk = o.sketch_p < 0 ? n : std::min<long long>(n, o.chi_max + (long long)o.sketch_p);
+    c.kmax = std::max({c.kmax, kk, n});  // exact path uses the n x n Gram
+    c.rmax = std::max<long long>(c.rmax, P.capC[b]);
+  }
+  for (int i = 0; i < P.L; ++i) {
+    // first extension step: rows (c, a) x cols (t, u, b') and its mirror
+    c.T = std::max(c.T, (long long)P.capC[i] * P.cA[i] * P.dd * P.cB[i + 1]);
+    c.T = std::max(c.T, (long long)P.capC[i + 1] * P.cA[i + 1] * P.dd * P.cB[i]);
+    c.ext = std::max(c.ext, (long long)P.capC[i] * P.dd * P.cA[i + 1] * P.cB[i + 1]);
+    c.ext = std::max(c.ext, (long long)P.capC[i + 1] * P.dd * P.cA[i] * P.cB[i]);
+  }
+  return c;
+}
+
+// ------------------------------------------------------------------ helpers
+Op opW(const Ctx& X, const void* p, bool kc, int ld, const unsigned* amax = nullptr) {
+  Op o{p, X.wt, kc, ld};
+  o.amax = amax;
+  return o;
+}
+Op op64(const void* p, bool kc, int ld) { return Op{p, DType::F64, kc, ld}; }
+Out outW(const Ctx& X, void* p, int ld, unsigned* amax = nullptr) {
+  Out o{p, X.wt, ld};
+  o.amax = amax;
+  return o;
+}
+Out out64(void* p, int ld) { return Out{p, DType::F64, ld}; }
+
+PermDesc perm4(const void* in, int tin, void* out, int tout, std::array<int, 4> n,
+               std::array<long long, 4> si, std::array<long long, 4> so, double scale = 1.0) {
+  PermDesc d{};
+  d.in = in; d.out = out; d.tin = tin; d.tout = tout; d.scale = scale;
+  for (int q = 0; q < 4; ++q) { d.n[q] = n[q]; d.si[q] = si[q]; d.so[q] = so[q]; }
+  return d;
+}
+
+long long perm_elems(const PermDesc& d) { return (long long)d.n[0] * d.n[1] * d.n[2] * d.n[3]; }
+
+void add_perm(Program& P, const std::vector<PermDesc>& ds, const char* cls) {
+  long long mx = 1;
+  for (auto& d : ds) mx = std::max(mx, perm_elems(d));
+  add_simple(P, LK::Perm, ds, mx, cls);
+}
+
+void add_fill(Program& P, const std::vector<FillDesc>& ds) {
+  long long mx = 1;
+  for (auto& d : ds) mx = std::max(mx, std::max(d.n_words, (long long)d.eye_rows * d.eye_cols));
+  add_simple(P, LK::Fill, ds, mx, "fill");
+}
+
+// CholeskyQR of the n x k row-major X (in place), `passes` times.
+// Fast path (every k <= kRegMax, no Rout): G = X^T X, R^{-1} from the
+// register Cholesky, X <- X R^{-1} by a GEMM through the temp T (n x k).
+// General path: Cholesky R, X <- X R^{-1} by the row-wise TRSM; the product
+// of the triangular factors (upper, k x k) is left in Rout when non-null.
+// R scratch must hold 2 k x k; G scratch k x k.
+struct CholQRJob {
+  double* X;
+  int n, k, ld;
+  double* G;
+  double* R;     // >= 2*k*k
+  double* Rout;  // nullable, k x k
+  double* T;     // nullable, n x k temp (fast path)
+};
+
+void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int passes) {
+  if (jobs.empty()) return;
+  bool fast = true;
+  for (auto& j : jobs) fast = fast && j.k <= kRegMax && !j.Rout && j.T;
+  for (int pass = 0; pass < passes; ++pass) {
+    std::vector<GemmJob> gj, tj;
+    std::vector<CholDesc> cd;
+    std::vector<TrsmDesc> td;
+    int maxk = 1, maxn = 1;
+    for (auto& j : jobs) {
+      double* src = (fast && pass % 2 == 1) ? j.T : j.X;
+      double* dst = (fast && pass % 2 == 1) ? j.X : j.T;
+      const int lds = (fast && pass % 2 == 1) ? j.k : j.ld;
+      const int ldd = (fast && pass % 2 == 1) ? j.ld : j.k;
+      gj.push_back(GemmJob{j.k, j.k, j.n, op64(src, false, lds), op64(src, false, lds), out64(j.G, j.k)});
+      double* Rp = j.R + (size_t)(pass % 2) * j.k * j.k;
+      cd.push_back(CholDesc{j.G, j.k, Rp, j.k, j.k, X.flag});
+      if (fast)
+        tj.push_back(GemmJob{j.n, j.k, j.k, op64(src, true, lds), op64(Rp, false, j.k), out64(dst, ldd)});
+      else
+        td.push_back(TrsmDesc{j.X, j.ld, Rp, j.k, j.n, j.k});
+      maxk = std::max(maxk, j.k);
+      maxn = std::max(maxn, j.n);
+    }
+    add_gemm(P, X.sb, Mode::F64, gj, "qr_gram", 0);
+    Launch l;
+    l.kind = LK::Chol;
+    l.off = P.push(cd);
+    l.n = (int)cd.size();
+    l.maxa = maxk;
+    l.maxb = fast ? 1 : 0;
+    l.cls = "qr_chol";
+    P.launches.push_back(l);
+    if (fast) add_gemm(P, X.sb, Mode::F64, tj, "qr_apply", 0);
+    else add_simple(P, LK::Trsm, td, maxn, "qr_trsm");
+  }
+  if (fast && passes % 2 == 1) {
+    std::vector<PermDesc> cp;
+    for (auto& j : jobs)
+      cp.push_back(perm4(j.T, 0, j.X, 0, {1, 1, j.n, j.k}, {0, 0, j.k, 1}, {0, 0, j.ld, 1}));
+    add_perm(P, cp, "copy");
+  }
+  // Rout = R_2 R_1 (or R_1)
+  std::vector<GemmJob> rj;
+  std::vector<PermDesc> pc;
+  for (auto& j : jobs) {
+    if (!j.Rout) continue;
+    if (passes == 1) {
+      pc.push_back(perm4(j.R, 0, j.Rout, 0, {1, 1, j.k, j.k}, {0, 0, j.k, 1}, {0, 0, j.k, 1}));
+    } else {
+      rj.push_back(GemmJob{j.k, j.k, j.k, op64(j.R + (size_t)j.k * j.k, true, j.k),
+                           op64(j.R, false, j.k), out64(j.Rout, j.k)});
+    }
+  }
+  add_gemm(P, X.sb, Mode::F64, rj, "qr_rprod", 0);
+  add_perm(P, pc, "copy");
+}
+
+// ------------------------------------------------------------------ allocation
+void carve(Ctx& X, Carver& cv) {
+  const int wb = bytes_of(X.wt);
+  const bool bf = X.wmode == Mode::BF16 || X.wmode == Mode::BF16X3;
+  auto amax = [&](void) -> unsigned* { return bf ? cv.take<unsigned>(1) : nullptr; };
+  X.flag = cv.take<int>(4);
+  X.sweep_dev = X.flag + 1;
+  Caps all;
+  size_t max_bonds = 1;
+  for (auto& P : X.pairs) {
+    const int L = P.L, dd = P.dd;
+    Caps c = pair_caps(P, X.o);
+    all.nm_max = std::max(all.nm_max, c.nm_max);
+    all.kmax = std::max(all.kmax, c.kmax);
+    all.rmax = std::max(all.rmax, c.rmax);
+    all.theta = std::max(all.theta, c.theta);
+    all.T = std::max(all.T, c.T);
+    all.ext = std::max(all.ext, c.ext);
+    max_bonds = std::max<size_t>(max_bonds, (size_t)(L / 2 + 1));
+    P.A64.resize(L); P.B64.resize(L); P.C64.resize(L);
+    P.Bw.resize(L); P.Bmw.resize(L); P.At.resize(L); P.Amt.resize(L);
+    P.amBw.resize(L); P.amBmw.resize(L); P.amAt.resize(L); P.amAmt.resize(L);
+    for (int i = 0; i < L; ++i) {
+      P.A64[i] = cv.take<double>((size_t)P.chiA_in[i] * dd * P.chiA_in[i + 1]);
+      P.B64[i] = cv.take<double>((size_t)P.chiB_in[i] * dd * P.chiB_in[i + 1]);
+      P.C64[i] = cv.take<double>((size_t)std::max(P.capC[i], P.chiA_in[i]) * dd *
+                                 std::max(P.capC[i + 1], P.chiA_in[i + 1]));
+      const size_t na = (size_t)P.cA[i] * dd * P.cA[i + 1], nb = (size_t)P.cB[i] * dd * P.cB[i + 1];
+      P.At[i] = cv.take<char>(na * wb); P.Amt[i] = cv.take<char>(na * wb);
+      P.Bw[i] = cv.take<char>(nb * wb); P.Bmw[i] = cv.take<char>(nb * wb);
+      P.amAt[i] = amax(); P.amAmt[i] = amax(); P.amBw[i] = amax(); P.amBmw[i] = amax();
+    }
+    P.Lenv.assign(L + 1, nullptr); P.Renv.assign(L + 1, nullptr);
+    P.amL.assign(L + 1, nullptr); P.amR.assign(L + 1, nullptr);
+    for (int b = 0; b <= L; ++b) {
+      const size_t ne = (size_t)P.capC[b] * P.cA[b] * P.cB[b];
+      P.Lenv[b] = cv.take<char>(ne * wb);
+      P.Renv[b] = cv.take<char>(ne * wb);
+      P.amL[b] = amax(); P.amR[b] = amax();
+    }
+    P.XL.assign(L - 1, nullptr); P.XR.assign(L - 1, nullptr);
+    P.amXL.assign(L - 1, nullptr); P.amXR.assign(L - 1, nullptr);
+    for (int i = 0; i + 1 < L; ++i) {
+      const size_t w = (size_t)P.cA[i + 1] * P.cB[i + 1] * dd;
+      P.XL[i] = cv.take<char>(w * P.capC[i] * wb);
+      P.XR[i] = cv.take<char>(w * P.capC[i + 2] * wb);
+      P.amXL[i] = amax(); P.amXR[i] = amax();
+    }
+    P.Yv.assign(L + 1, nullptr);
+    for (int b = 1; b < L; ++b) P.Yv[b] = cv.take<double>(P.capC[b]);
+    P.nu_dev = cv.take<double>(2);
+  }
+  const size_t nscr = X.o.schedule == MPO_SCHED_SERIAL ? 1 : max_bonds * X.pairs.size();
+  X.scratch.resize(nscr);
+  const long long nm = all.nm_max, kx = all.kmax, rx = all.rmax;
+  for (auto& B : X.scratch) {
+    B.theta = cv.take<char>((size_t)all.theta * wb);
+    B.T = cv.take<char>((size_t)all.T * wb);
+    B.amT = amax();
+    B.omega = cv.take<double>((size_t)nm * kx);
+    B.Y = cv.take<double>((size_t)nm * kx);
+    B.Y2 = cv.take<double>((size_t)nm * kx);
+    B.G = cv.take<double>((size_t)kx * kx);
+    B.R = cv.take<double>(2 * (size_t)kx * kx);
+    B.Bk = cv.take<double>((size_t)kx * nm);
+    B.H = cv.take<double>((size_t)kx * kx);
+    B.eigw = cv.take<double>(eig_work_doubles((int)kx, (int)rx));
+    B.evals = cv.take<double>((size_t)kx);
+    B.Z = cv.take<double>((size_t)kx * rx);
+    B.S = cv.take<double>((size_t)rx);
+    B.V = cv.take<double>((size_t)nm * rx);
+    B.sign = cv.take<double>((size_t)rx);
+    B.SVt = cv.take<double>((size_t)rx * nm);
+  }
+  // initialization scratch (FP64): Gram / triangular factors and a core-sized temp
+  long long core_max = 1, kq = 1;
+  for (auto& P : X.pairs)
+    for (int i = 0; i < P.L; ++i) {
+      const long long a = std::max(P.chiA_in[i], P.capC[i]), b = std::max(P.chiA_in[i + 1], P.capC[i + 1]);
+      core_max = std::max({core_max, a * P.dd * b, (long long)P.chiB_in[i] * P.dd * P.chiB_in[i + 1]});
+      kq = std::max({kq, a, b, (long long)P.chiB_in[i], (long long)P.chiB_in[i + 1]});
+    }
+  X.iG = cv.take<double>((size_t)kq * kq);
+  X.iR1 = cv.take<double>(2 * (size_t)kq * kq);
+  X.iR2 = cv.take<double>((size_t)kq * kq);
+  X.iRt = cv.take<double>((size_t)kq * kq);
+  X.iTmp = cv.take<double>((size_t)core_max);
+  X.iXt = cv.take<double>((size_t)core_max);
+  X.iTmpN = core_max;
+  // split-K partial tiles and their counters
+  X.sb.cap = (size_t)512 * 128 * 128 * 8;
+  X.sb.partials = cv.take<char>(X.sb.cap);
+  X.sb.ccap = 1 << 16;
+  X.sb.counters = cv.take<int>(X.sb.ccap);
+  X.arena_cap = (size_t)64 << 20;
+  X.arena = cv.take<char>(X.arena_cap);
+}
+
+// ------------------------------------------------------------------ extension jobs
+// left step 1 at site i: T[(c,a), (t,u,b')] = Lenv[i][(c,a), b] Bw[i][b, (t,u,b')]
+GemmJob job_e1(const Ctx& X, const PairState& P, int i, void* T, unsigned* amT) {
+  const int M = P.cC[i] * P.cA[i], K = P.cB[i], N = P.dd * P.cB[i + 1];
+  return GemmJob{M, N, K, opW(X, P.Lenv[i], true, K, P.amL[i]), opW(X, P.Bw[i], false, N, P.amBw[i]),
+                 outW(X, T, N, amT)};
+}
+// left step 2 at site i: XL[i][c][s][u][a'][b'] = sum_(a,t) At[i][(a,t)][s][a'] T[c][(a,t)][u][b']
+GemmJob job_e2(const Ctx& X, const PairState& P, int i, const void* T, const unsigned* amT) {
+  const int d = P.d, a0 = P.cA[i], a1 = P.cA[i + 1], b1 = P.cB[i + 1];
+  GemmJob g{a1, b1, d * a0, opW(X, P.At[i], false, d * a1, P.amAt[i]),
+            opW(X, T, false, d * b1, amT), outW(X, P.XL[i], b1, P.amXL[i])};
+  g.nb[0] = P.cC[i]; g.nb[1] = d; g.nb[2] = d;
+  g.A.s[0] = 0; g.A.s[1] = a1; g.A.s[2] = 0;
+  g.B.s[0] = (long long)a0 * P.dd * b1; g.B.s[1] = 0; g.B.s[2] = b1;
+  g.C.s[0] = (long long)P.dd * a1 * b1; g.C.s[1] = (long long)d * a1 * b1; g.C.s[2] = (long long)a1 * b1;
+  return g;
+}
+// right step 1 at site j: T[(c'',a''), (t,u,b)] = Renv[j+1][(c'',a''), b''] Bmw[j][b'', (t,u,b)]
+GemmJob job_e1m(const Ctx& X, const PairState& P, int j, void* T, unsigned* amT) {
+  const int M = P.cC[j + 1] * P.cA[j + 1], K = P.cB[j + 1], N = P.dd * P.cB[j];
+  return GemmJob{M, N, K, opW(X, P.Renv[j + 1], true, K, P.amR[j + 1]),
+                 opW(X, P.Bmw[j], false, N, P.amBmw[j]), outW(X, T, N, amT)};
+}
+// right step 2 at site j: XR[j-1][c''][s][u][a][b] = sum_(a'',t) Amt[j][(a'',t)][s][a] T[c''][(a'',t)][u][b]
+GemmJob job_e2m(const Ctx& X, const PairState& P, int j, const void* T, const unsigned* amT) {
+  const int d = P.d, a0 = P.cA[j], a1 = P.cA[j + 1], b0 = P.cB[j];
+  GemmJob g{a0, b0, d * a1, opW(X, P.Amt[j], false, d * a0, P.amAmt[j]),
+            opW(X, T, false, d * b0, amT), outW(X, P.XR[j - 1], b0, P.amXR[j - 1])};
+  g.nb[0] = P.cC[j + 1]; g.nb[1] = d; g.nb[2] = d;
+  g.A.s[0] = 0; g.A.s[1] = a0; g.A.s[2] = 0;
+  g.B.s[0] = (long long)a1 * P.dd * b0; g.B.s[1] = 0; g.B.s[2] = b0;
+  g.C.s[0] = (long long)P.dd * a0 * b0; g.C.s[1] = (long long)d * a0 * b0; g.C.s[2] = (long long)a0 * b0;
+  return g;
+}
+double flops_e1(const PairState& P, int i) { return 2.0 * P.cC[i] * P.cA[i] * P.cB[i] * P.dd * P.cB[i + 1]; }
+double flops_e2(const PairState& P, int i) { return 2.0 * P.cC[i] * P.dd * P.d * P.cA[i] * P.cA[i + 1] * P.cB[i + 1]; }
+double flops_e1m(const PairState& P, int j) { return 2.0 * P.cC[j + 1] * P.cA[j + 1] * P.cB[j + 1] * P.dd * P.cB[j]; }
+double flops_e2m(const PairState& P, int j) { return 2.0 * P.cC[j + 1] * P.dd * P.d * P.cA[j + 1] * P.cA[j] * P.cB[j]; }
+
+// ------------------------------------------------------------------ initialization
+// Left-orthogonalization (Alg. 5 preprocessing) of one MPO held in `cores`,
+// whose input bond dims are `chi_in`; `out_dims` are the clipped dims.
+void rec_left_orth(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores,
+                   const std::vector<int>& chi_in, const std::vector<int>& out_dims, double* nu) {
+  const int L = S.L, dd = S.dd;
+  std::vector<int> cur(chi_in);
+  for (int i = 0; i + 1 < L; ++i) {
+    const int p = cur[i] * dd, q = chi_in[i + 1];
+    const int nn = dd * chi_in[i + 2];  // columns of the next core (its right bond untouched yet)
+    if (p >= q) {
+      add_cholqr(X, P, {CholQRJob{cores[i], p, q, q, X.iG, X.iR1, X.iRt, nullptr}}, 2);
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{q, nn, q, op64(X.iRt, true, q), op64(cores[i + 1], false, nn),
+                                            out64(X.iTmp, nn)}}, "init", 0);
+      cur[i + 1] = q;
+    } else {
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{p, nn, q, op64(cores[i], true, q), op64(cores[i + 1], false, nn),
+                                            out64(X.iTmp, nn)}}, "init", 0);
+      add_fill(P, {FillDesc{cores[i], 0, p, p, 1}});
+      cur[i + 1] = p;
+    }
+    add_perm(P, {perm4(X.iTmp, 0, cores[i + 1], 0, {1, 1, cur[i + 1], nn}, {0, 0, nn, 1}, {0, 0, nn, 1})}, "copy");
+  }
+  for (int i = 0; i <= L; ++i)
+    if (cur[i] != out_dims[i]) throw Error{MPO_ERR_SHAPE, "left orthogonalization shape plan mismatch"};
+  add_simple(P, LK::Norm, std::vector<NormDesc>{NormDesc{cores[L - 1], (long long)cur[L - 1] * dd, nu}}, 0, "init");
+}
+
+// C_init = A right-orthogonalized by an RQ sweep L..2 (Sec. 2.3.1).
+void rec_right_orth(Ctx& X, Program& P, PairState& S) {
+  const int L = S.L, dd = S.dd;
+  std::vector<int> cur(S.cA);
+  for (int j = L - 1; j >= 1; --j) {
+    const int p = cur[j], q = dd * cur[j + 1];
+    const int mp = cur[j - 1] * dd;  // rows of the previous core
+    if (p <= q) {
+      // X^T = Q R (R_jj > 0), X = R^T Q^T: work on the transpose
+      add_perm(P, {perm4(S.C64[j], 0, X.iXt, 0, {1, 1, p, q}, {0, 0, q, 1}, {0, 0, 1, p})}, "copy");
+      add_cholqr(X, P, {CholQRJob{X.iXt, q, p, p, X.iG, X.iR1, X.iRt, nullptr}}, 2);
+      add_perm(P, {perm4(X.iXt, 0, S.C64[j], 0, {1, 1, q, p}, {0, 0, p, 1}, {0, 0, 1, q})}, "copy");
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{mp, p, p, op64(S.C64[j - 1], true, p), op64(X.iRt, true, p),
+                                            out64(X.iTmp, p)}}, "init", 0);
+      add_perm(P, {perm4(X.iTmp, 0, S.C64[j - 1], 0, {1, 1, mp, p}, {0, 0, p, 1}, {0, 0, p, 1})}, "copy");
+    } else {
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{mp, q, p, op64(S.C64[j - 1], true, p), op64(S.C64[j], false, q),
+                                            out64(X.iTmp, q)}}, "init", 0);
+      add_perm(P, {perm4(X.iTmp, 0, S.C64[j - 1], 0, {1, 1, mp, q}, {0, 0, q, 1}, {0, 0, q, 1})}, "copy");
+      add_fill(P, {FillDesc{S.C64[j], 0, q, q, 1}});
+      cur[j] = q;
+    }
+  }
+  for (int i = 0; i <= L; ++i)
+    if (cur[i] != S.cC[i]) throw Error{MPO_ERR_SHAPE, "right orthogonalization shape plan mismatch"};
+}
+
+void rec_repack(Ctx& X, Program& P, PairState& S) {
+  const int L = S.L, d = S.d, dd = S.dd;
+  const int tw = X.wt == DType::F64 ? 0 : 1;
+  std::vector<PermDesc> ds;
+  for (int i = 0; i < L; ++i) {
+    const long long a0 = S.cA[i], a1 = S.cA[i + 1], b0 = S.cB[i], b1 = S.cB[i + 1];
+    // B [b][t][u][b'] -> Bw same, Bmw [b'][t][u][b]
+    PermDesc p1 = perm4(S.B64[i], 0, S.Bw[i], tw, {(int)b0, d, d, (int)b1}, {dd * b1, d * b1, b1, 1},
+                        {dd * b1, d * b1, b1, 1});
+    p1.amax = S.amBw[i];
+    PermDesc p2 = perm4(S.B64[i], 0, S.Bmw[i], tw, {(int)b0, d, d, (int)b1}, {dd * b1, d * b1, b1, 1},
+                        {1, d * b0, b0, dd * b0});
+    p2.amax = S.amBmw[i];
+    // A [a][s][t][a'] -> At [a][t][s][a'], Amt [a'][t][s][a]
+    PermDesc p3 = perm4(S.A64[i], 0, S.At[i], tw, {(int)a0, d, d, (int)a1}, {dd * a1, d * a1, a1, 1},
+                        {dd * a1, a1, d * a1, 1});
+    p3.amax = S.amAt[i];
+    PermDesc p4 = perm4(S.A64[i], 0, S.Amt[i], tw, {(int)a0, d, d, (int)a1}, {dd * a1, d * a1, a1, 1},
+                        {1, a0, d * a0, dd * a0});
+    p4.amax = S.amAmt[i];
+    ds.insert(ds.end(), {p1, p2, p3, p4});
+  }
+  add_perm(P, ds, "init");
+}
+
+// right environment of site j from Renv[j+1] (sweep or init): XR[j-1] via the
+// two mirrored steps, then (if make_env) Renv[j] = CR_j . XR[j-1] where
+// CR_j[c][(c'', s, u)] is C_j with its right bond first.
+void rec_right_env_from_core(Ctx& X, Program& P, PairState& S, int j, bool make_env, BondScratch& B) {
+  add_gemm(P, X.sb, X.wmode, {job_e1m(X, S, j, B.T, B.amT)}, "env_ext1", flops_e1m(S, j));
+  add_gemm(P, X.sb, X.wmode, {job_e2m(X, S, j, B.T, B.amT)}, "env_ext2", flops_e2m(S, j));
+  if (!make_env) return;
+  const int c0 = S.cC[j], c1 = S.cC[j + 1], dd = S.dd, N = S.cA[j] * S.cB[j];
+  add_perm(P, {perm4(S.C64[j], 0, X.iXt, 0, {c0, dd, c1, 1}, {(long long)dd * c1, c1, 1, 0},
+                     {(long long)c1 * dd, 1, dd, 0})}, "copy");
+  add_gemm(P, X.sb, X.wmode, {GemmJob{c0, N, c1 * dd, op64(X.iXt, true, c1 * dd),
+                                      opW(X, S.XR[j - 1], false, N, S.amXR[j - 1]),
+                                      outW(X, S.Renv[j], N, S.amR[j])}},
+           "env_update", 2.0 * c0 * N * c1 * dd);
+}
+
+void rec_left_env_from_core(Ctx& X, Program& P, PairState& S, int i, const double* Ci, int ldc,
+                            BondScratch& B) {
+  add_gemm(P, X.sb, X.wmode, {job_e1(X, S, i, B.T, B.amT)}, "env_ext1", flops_e1(S, i));
+  add_gemm(P, X.sb, X.wmode, {job_e2(X, S, i, B.T, B.amT)}, "env_ext2", flops_e2(S, i));
+  const int c0 = S.cC[i], c1 = S.cC[i + 1], dd = S.dd, N = S.cA[i + 1] * S.cB[i + 1];
+  add_gemm(P, X.sb, X.wmode, {GemmJob{c1, N, c0 * dd, op64(Ci, false, ldc),
+                                      opW(X, S.XL[i], false, N, S.amXL[i]),
+                                      outW(X, S.Lenv[i + 1], N, S.amL[i + 1])}},
+           "env_update", 2.0 * c1 * N * c0 * dd);
+}
+
+// ------------------------------------------------------------------ two-site update
+// One bond of one pair inside a program: shapes of the bond (from the host
+// copy of the current bond dims) and the buffers it uses.
+struct BondJob {
+  PairState* P;
+  int pair;
+  int i;       // 0-based bond: joins sites i and i+1
+  bool fwd;    // serial direction (ignored by the inverse gauge)
+  BondScratch* B;
+  int n, m, k, r;
+  bool sketch;
+};
+
+BondJob make_bond(Ctx& X, PairState& P, int pair, int i, bool fwd, BondScratch& B) {
+  BondJob b{&P, pair, i, fwd, &B};
+  b.n = P.cC[i] * P.dd;
+  b.m = P.dd * P.cC[i + 2];
+  const int cap = P.rcap[i + 1];
+  const int kmax = std::min(std::min(b.n, b.m), cap);
+  b.r = std::min(X.o.chi_max, kmax);
+  b.sketch = X.o.sketch_p >= 0 && X.o.chi_max + X.o.sketch_p < std::min(b.n, b.m);
+  if (b.sketch) b.k = std::min(X.o.chi_max + X.o.sketch_p, kmax);
+  else b.k = b.n;
+  if (b.sketch && b.k >= std::min(b.n, b.m)) { b.sketch = false; b.k = b.n; }
+  return b;
+}
+
+// Records the two-site matrix and its truncated factorization (Alg. 3 /
+// Sec. 3.1) for a group of bonds: Theta = XL XR^T; with the sketch
+// Y = Theta Omega, Q = CholeskyQR2(Y), Bk = Q^T Theta; without it Bk = Theta
+// (Q = I); then the top r eigenpairs of H = Bk Bk^T give U_b = Z and
+// S = sqrt(lambda).  The extensions XL, XR must be current.
+void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, int stream_add_base,
+                bool halfstep) {
+  std::vector<GemmJob> th, yj, bk, hj;
+  std::vector<OmegaDesc> om;
+  std::vector<CholQRJob> qr;
+  std::vector<EigDesc> ed;
+  std::vector<SvalDesc> sv;
+  std::vector<GemmJob> zq;
+  double fth = 0, fsk = 0;
+  long long maxom = 1;
+  int maxr = 1;
+  for (auto& b : bj) {
+    PairState& S = *b.P;
+    BondScratch& B = *b.B;
+    const int K = S.cA[b.i + 1] * S.cB[b.i + 1];
+    th.push_back(GemmJob{b.n, b.m, K, opW(X, S.XL[b.i], true, K), opW(X, S.XR[b.i], true, K),
+                         outW(X, B.theta, b.m)});
+    fth += 2.0 * b.n * b.m * K;
+    if (b.sketch) {
+      OmegaDesc o{};
+      o.out = B.omega; o.m = b.m; o.k = b.k; o.chi = S.cC[b.i + 2]; o.dd = S.dd;
+      o.bond = b.i + 1; o.pair = b.pair; o.stream_mul = stream_mul; o.stream_add = stream_add_base;
+      o.stream_base = X.sweep_dev; o.seed = X.o.seed;
+      om.push_back(o);
+      maxom = std::max(maxom, (long long)b.m * b.k);
+      yj.push_back(GemmJob{b.n, b.k, b.m, opW(X, B.theta, true, b.m), op64(B.omega, false, b.k),
+                           out64(B.Y, b.k)});
+      qr.push_back(CholQRJob{B.Y, b.n, b.k, b.k, B.G, B.R, nullptr, B.Y2});
+      bk.push_back(GemmJob{b.k, b.m, b.n, op64(B.Y, false, b.k), opW(X, B.theta, false, b.m),
+                           out64(B.Bk, b.m)});
+      hj.push_back(GemmJob{b.k, b.k, b.m, op64(B.Bk, true, b.m), op64(B.Bk, true, b.m), out64(B.H, b.k)});
+      fsk += 4.0 * b.n * b.m * b.k;
+    } else {
+      hj.push_back(GemmJob{b.n, b.n, b.m, opW(X, B.theta, true, b.m), opW(X, B.theta, true, b.m),
+                           out64(B.H, b.n)});
+    }
+    ed.push_back(EigDesc{B.H, b.k, b.k, b.r, B.evals, B.Z, b.r, B.eigw, X.flag});
+    if (b.k <= kRegMax)  // register path: Z = Q X afterwards
+      zq.push_back(GemmJob{b.k, b.r, b.k, op64(eig_work_qt(B.eigw, b.k, b.r), false, b.k),
+                           op64(eig_work_x(B.eigw, b.k, b.r), false, b.r), out64(B.Z, b.r)});
+    sv.push_back(SvalDesc{B.evals, B.S, b.r, halfstep ? 1 : 0, X.flag});
+    maxr = std::max(maxr, b.r);
+  }
+  add_gemm(P, X.sb, X.wmode, th, "theta", fth);
+  add_simple(P, LK::Omega, om, maxom, "omega");
+  add_gemm(P, X.sb, Mode::F64, yj, "sketch", fsk / 2);
+  if (!qr.empty()) add_cholqr(X, P, qr, 2);
+  add_gemm(P, X.sb, Mode::F64, bk, "project", fsk / 2);
+  // split H jobs by operand type (sketched: FP64 Bk; plain: working-type Theta)
+  std::vector<GemmJob> h64, hw;
+  for (auto& h : hj) (h.A.t == DType::F64 ? h64 : hw).push_back(h);
+  add_gemm(P, X.sb, Mode::F64, h64, "gram", 0);
+  add_gemm(P, X.sb, Mode::F64, hw, "gram", 0);
+  const bool reg = zq.size() == ed.size();
+  if (!reg) zq.clear();
+  {
+    Launch l;
+    l.kind = LK::Eig;
+    l.off = P.push(ed);
+    l.n = (int)ed.size();
+    l.maxb = reg ? 1 : 0;
+    l.cls = "eig";
+    P.launches.push_back(l);
+  }
+  add_gemm(P, X.sb, Mode::F64, zq, "eig_backtransform", 0);
+  add_simple(P, LK::Sval, sv, maxr, "svals");
+}
+
+// Site-canonical assignment (Alg. 3) and environment update for a group of
+// bonds that all move in the same direction.
+//   forward:  U = orth(Q Z) -> C_i;   C_{i+1} = U^T Theta;  L_{i+1} = U^T XL
+//   backward: V = orth(Bk^T Z S^-1) -> C_{i+1} = V^T;  C_i = Q Z S;  R_{i+1} = V^T XR
+// with the sign rule applied to the columns of U (or of C_i = U S).
+void rec_assign_site(Ctx& X, Program& P, std::vector<BondJob>& bj) {
+  std::vector<GemmJob> uq, svt, envg, vj;
+  std::vector<PermDesc> cp, perm;
+  std::vector<CholQRJob> orth;
+  std::vector<SignDesc> sg;
+  std::vector<ScaleDesc> sc1, sc2, sc3;
+  double fenv = 0;
+  int maxr = 1;
+  long long maxsc = 1;
+  const bool fwd = bj.front().fwd;
+  for (auto& b : bj) {
+    PairState& S = *b.P;
+    BondScratch& B = *b.B;
+    const int i = b.i, r = b.r, cl = S.cC[i], cr = S.cC[i + 2], dd = S.dd;
+    const int N = S.cA[i + 1] * S.cB[i + 1];
+    double* Ci = S.C64[i];
+    double* Cn = S.C64[i + 1];
+    // C_i <- Q Z (or Z)
+    if (b.sketch)
+      uq.push_back(GemmJob{b.n, r, b.k, op64(B.Y, true, b.k), op64(B.Z, false, r), out64(Ci, r)});
+    else
+      cp.push_back(perm4(B.Z, 0, Ci, 0, {1, 1, b.n, r}, {0, 0, r, 1}, {0, 0, r, 1}));
+    maxr = std::max(maxr, r);
+    if (fwd) {
+      orth.push_back(CholQRJob{Ci, b.n, r, r, B.G, B.R, nullptr, B.Y2});
+      sg.push_back(SignDesc{Ci, b.n, r, r, B.sign, nullptr});
+      svt.push_back(GemmJob{r, b.m, b.n, op64(Ci, false, r), opW(X, B.theta, false, b.m), out64(B.SVt, b.m)});
+      // C_{i+1}[c'][su][c''] = SVt[c'][(c'', su)]
+      perm.push_back(perm4(B.SVt, 0, Cn, 0, {r, cr, dd, 1}, {b.m, dd, 1, 0},
+                           {(long long)dd * cr, 1, cr, 0}));
+      envg.push_back(GemmJob{r, N, b.n, op64(Ci, false, r), opW(X, S.XL[i], false, N, S.amXL[i]),
+                             outW(X, S.Lenv[i + 1], N, S.amL[i + 1])});
+      fenv += 2.0 * r * N * b.n;
+    } else {
+      // V = Bk^T Z / S  (Bk = Theta without the sketch)
+      if (b.sketch)
+        vj.push_back(GemmJob{b.m, r, b.k, op64(B.Bk, false, b.m), op64(B.Z, false, r), out64(B.V, r)});
+      else
+        vj.push_back(GemmJob{b.m, r, b.n, opW(X, B.theta, false, b.m), op64(B.Z, false, r), out64(B.V, r)});
+      sc1.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 1});
+      orth.push_back(CholQRJob{B.V, b.m, r, r, B.G, B.R, nullptr, B.Y2});
+      sc2.push_back(ScaleDesc{Ci, Ci, b.n, r, r, r, nullptr, B.S, 0, 0});  // C_i = U S
+      sg.push_back(SignDesc{Ci, b.n, r, r, B.sign, nullptr});
+      sc3.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.sign, 0, 0});
+      // C_{i+1}[c'][su][c''] = V[(c'', su)][c']
+      perm.push_back(perm4(B.V, 0, Cn, 0, {r, cr, dd, 1}, {1, (long long)dd * r, r, 0},
+                           {(long long)dd * cr, 1, cr, 0}));
+      envg.push_back(GemmJob{r, N, b.m, op64(B.V, false, r), opW(X, S.XR[i], false, N, S.amXR[i]),
+                             outW(X, S.Renv[i + 1], N, S.amR[i + 1])});
+      fenv += 2.0 * r * N * b.m;
+    }
+    maxsc = std::max(maxsc, (long long)std::max(b.n, b.m) * r);
+    (void)cl;
+  }
+  add_gemm(P, X.sb, Mode::F64, uq, "assemble", 0);
+  add_perm(P, cp, "copy");
+  if (fwd) {
+    add_cholqr(X, P, orth, 1);
+    add_simple(P, LK::Sign, sg, maxr, "sign");
+    add_gemm(P, X.sb, Mode::F64, svt, "assemble", 0);
+    add_perm(P, perm, "copy");
+  } else {
+    add_gemm(P, X.sb, Mode::F64, vj, "assemble", 0);
+    add_simple(P, LK::Scale, sc1, maxsc, "scale");
+    add_cholqr(X, P, orth, 1);
+    add_simple(P, LK::Scale, sc2, maxsc, "scale");
+    add_simple(P, LK::Sign, sg, maxr, "sign");
+    add_simple(P, LK::Scale, sc3, maxsc, "scale");
+    add_perm(P, perm, "copy");
+  }
+  add_gemm(P, X.sb, X.wmode, envg, "env_update", fenv);
+}
+
+// BF16 per-tensor scales: the amax slots a bond is about to produce start at 0.
+void rec_reset_amax(Ctx& X, Program& P, std::vector<unsigned*> slots) {
+  if (X.wmode != Mode::BF16 && X.wmode != Mode::BF16X3) return;
+  std::vector<FillDesc> fd;
+  for (auto* s : slots)
+    if (s) fd.push_back(FillDesc{s, 1, 0, 0, 0});
+  add_fill(P, fd);
+}
+
+// One serial update at bond i in direction fwd (Alg. 5 body): the fresh
+// extension (XL forward, XR backward; the other one is cached), then the
+// factorization, the assignment and the environment update.
+void rec_serial_bond(Ctx& X, Program& P, PairState& S, int pair, int i, bool fwd) {
+  BondScratch& B = X.scratch[0];
+  if (fwd) {
+    rec_reset_amax(X, P, {B.amT, S.amXL[i], S.amL[i + 1]});
+    add_gemm(P, X.sb, X.wmode, {job_e1(X, S, i, B.T, B.amT)}, "env_ext1", flops_e1(S, i));
+    add_gemm(P, X.sb, X.wmode, {job_e2(X, S, i, B.T, B.amT)}, "env_ext2", flops_e2(S, i));
+  } else {
+    rec_reset_amax(X, P, {B.amT, S.amXR[i], S.amR[i + 1]});
+    add_gemm(P, X.sb, X.wmode, {job_e1m(X, S, i + 1, B.T, B.amT)}, "env_ext1", flops_e1m(S, i + 1));
+    add_gemm(P, X.sb, X.wmode, {job_e2m(X, S, i + 1, B.T, B.amT)}, "env_ext2", flops_e2m(S, i + 1));
+  }
+  std::vector<BondJob> bj{make_bond(X, S, pair, i, fwd, B)};
+  rec_factor(X, P, bj, 1, 0, false);
+  rec_assign_site(X, P, bj);
+  S.cC[i + 1] = bj[0].r;
+}
+
+std::string shape_key(const Ctx& X, const char* tag) {
+  std::string k(tag);
+  for (auto& P : X.pairs)
+    for (int c : P.cC) k += "," + std::to_string(c);
+  return k;
+}
+
+void upload(Ctx& X, Program& P) {
+  const size_t need = (P.blob.size() + 255) & ~size_t(255);
+  if (X.arena_used + need > X.arena_cap) throw Error{MPO_ERR_WORKSPACE, "descriptor arena exhausted"};
+  P.dev = X.arena + X.arena_used;
+  P.dev_cap = need;
+  X.arena_used += need;
+  if (!P.blob.empty())
+    HIP_OK(hipMemcpyAsync(P.dev, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, X.stream));
+}
+
+// Init program of one pair (serial schedule): copy inputs, preprocess A and
+// B, C = A right-orthogonalized, working-precision copies, trivial boundary
+// environments, all right environments and the cached right extensions.
+void rec_init_pair(Ctx& X, Program& P, PairState& S, int pair) {
+  const int L = S.L, dd = S.dd;
+  std::vector<PermDesc> cps;
+  for (int i = 0; i < L; ++i) {
+    const int a0 = S.chiA_in[i], a1 = S.chiA_in[i + 1], b0 = S.chiB_in[i], b1 = S.chiB_in[i + 1];
+    cps.push_back(perm4(S.A_in[i], 0, S.A64[i], 0, {1, 1, a0, dd * a1}, {0, 0, (long long)dd * a1, 1},
+                        {0, 0, (long long)dd * a1, 1}));
+    cps.push_back(perm4(S.B_in[i], 0, S.B64[i], 0, {1, 1, b0, dd * b1}, {0, 0, (long long)dd * b1, 1},
+                        {0, 0, (long long)dd * b1, 1}));
+  }
+  add_perm(P, cps, "init");
+  rec_left_orth(X, P, S, S.A64, S.chiA_in, S.cA, S.nu_dev);
+  rec_left_orth(X, P, S, S.B64, S.chiB_in, S.cB, S.nu_dev + 1);
+  std::vector<PermDesc> cc;
+  for (int i = 0; i < L; ++i)
+    cc.push_back(perm4(S.A64[i], 0, S.C64[i], 0, {1, 1, S.cA[i], dd * S.cA[i + 1]},
+                       {0, 0, (long long)dd * S.cA[i + 1], 1}, {0, 0, (long long)dd * S.cA[i + 1], 1}));
+  add_perm(P, cc, "init");
+  if (X.wmode == Mode::BF16 || X.wmode == Mode::BF16X3) {
+    std::vector<unsigned*> sl;
+    for (int i = 0; i < L; ++i) sl.insert(sl.end(), {S.amAt[i], S.amAmt[i], S.amBw[i], S.amBmw[i]});
+    rec_reset_amax(X, P, sl);
+  }
+  rec_repack(X, P, S);
+  rec_right_orth(X, P, S);
+  const int f64 = X.wt == DType::F64 ? 1 : 0;
+  add_fill(P, {FillDesc{S.Lenv[0], 0, 1, 1, f64}, FillDesc{S.Renv[L], 0, 1, 1, f64}});
+  std::vector<unsigned*> sl{S.amL[0], S.amR[L]};
+  for (int j = 1; j < L; ++j) sl.insert(sl.end(), {S.amR[j], S.amXR[j - 1]});
+  sl.push_back(X.scratch[0].amT);
+  rec_reset_amax(X, P, sl);
+  for (int j = L - 1; j >= 1; --j) rec_right_env_from_core(X, P, S, j, j >= 2, X.scratch[0]);
+  (void)pair;
+}
+
+int n_words(size_t bytes) { return (int)((bytes + 3) / 4); }
+
+void validate_tt(const mpo_tt& t, int L, int d) {
+  if (t.L != L || t.d != d) throw Error{MPO_ERR_SHAPE, "A and B must share L and d"};
+  if (!t.chi || !t.cores) throw Error{MPO_ERR_INVALID_ARG, "null bond dims or cores"};
+  if (t.chi[0] != 1 || t.chi[L] != 1) throw Error{MPO_ERR_SHAPE, "boundary bond dims must be 1"};
+  for (int i = 0; i <= L; ++i)
+    if (t.chi[i] < 1) throw Error{MPO_ERR_SHAPE, "bond dims must be >= 1"};
+  for (int i = 0; i < L; ++i)
+    if (!t.cores[i]) throw Error{MPO_ERR_INVALID_ARG, "null core pointer"};
+}
+
+void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
+  if (!pairs || n_pairs < 1 || !o) throw Error{MPO_ERR_INVALID_ARG, "null pairs/options or n_pairs < 1"};
+  X.o = *o;
+  if (o->chi_max < 1) throw Error{MPO_ERR_INVALID_ARG, "chi_max must be >= 1"};
+  if (o->chi_max + std::max(o->sketch_p, 0) > 512)
+    throw Error{MPO_ERR_UNSUPPORTED, "chi_max + sketch_p above 512"};
+  if (o->tau != 0.0) throw Error{MPO_ERR_UNSUPPORTED, "only tau = 0 (fixed bond cap) is run"};
+  if (o->precision < 0 || o->precision > 3) throw Error{MPO_ERR_INVALID_ARG, "bad precision"};
+  if (o->schedule < 0 || o->schedule > 1) throw Error{MPO_ERR_INVALID_ARG, "bad schedule"};
+  X.wmode = o->precision == MPO_FP64 ? Mode::F64
+            : o->precision == MPO_FP32 ? Mode::F32
+            : o->precision == MPO_BF16 ? Mode::BF16 : Mode::BF16X3;
+  X.wt = o->precision == MPO_FP64 ? DType::F64 : DType::F32;
+  X.profile = o->reserved[0] != 0;
+  X.pairs.resize(n_pairs);
+  for (int p = 0; p < n_pairs; ++p) {
+    const mpo_pair& pr = pairs[p];
+    const int L = pr.A.L, d = pr.A.d;
+    if (L < 2 || d < 1) throw Error{MPO_ERR_SHAPE, "need L >= 2 and d >= 1"};
+    validate_tt(pr.A, L, d);
+    validate_tt(pr.B, L, d);
+    PairState& S = X.pairs[p];
+    S.L = L; S.d = d; S.dd = d * d;
+    S.chiA_in.assign(pr.A.chi, pr.A.chi + L + 1);
+    S.chiB_in.assign(pr.B.chi, pr.B.chi + L + 1);
+    S.A_in.assign(pr.A.cores, pr.A.cores + L);
+    S.B_in.assign(pr.B.cores, pr.B.cores + L);
+    for (int b = 0; b <= L; ++b)
+      if (S.chiA_in[b] > 512 || S.chiB_in[b] > 512)
+        throw Error{MPO_ERR_UNSUPPORTED, "bond dimensions above 512"};
+    plan_shapes(S, o->chi_max, o->schedule);
+    for (int b = 0; b <= L; ++b)
+      if (S.capC[b] * S.dd > 2048) throw Error{MPO_ERR_UNSUPPORTED, "two-site dimension above 2048"};
+  }
+}
+
+void check_flags(Ctx& X) {
+  int f = 0;
+  HIP_OK(hipMemcpyAsync(&f, X.flag, sizeof(int), hipMemcpyDeviceToHost, X.stream));
+  HIP_OK(hipStreamSynchronize(X.stream));
+  if (f) {
+    std::string m = "device status:";
+    if (f & FLAG_NONFINITE) m += " non-finite value;";
+    if (f & FLAG_CHOL) m += " Cholesky pivot <= 0;";
+    if (f & FLAG_GUARD) m += " singular value <= 1e-14 sigma_1 in the inverse gauge;";
+    if (f & FLAG_EIG) m += " eigenvalue bracket;";
+    throw Error{MPO_ERR_NUMERIC, m};
+  }
+}
+
+struct SweepPlan {
+  Program prog;
+  std::vector<std::vector<int>> cC_after;  // per pair
+  bool stable = false;  // the sweep leaves the bond dimensions unchanged
+  hipGraphExec_t graph = nullptr;
+  int uses = 0;
+};
+
+void record_sweep(Ctx& X, SweepPlan& sp, bool fwd) {
+  for (size_t p = 0; p < X.pairs.size(); ++p) {
+    PairState& S = X.pairs[p];
+    if (fwd) for (int i = 0; i + 1 < S.L; ++i) rec_serial_bond(X, sp.prog, S, (int)p, i, true);
+    else for (int i = S.L - 2; i >= 0; --i) rec_serial_bond(X, sp.prog, S, (int)p, i, false);
+  }
+  Launch b;
+  b.kind = LK::Bump;
+  b.counter = X.sweep_dev;
+  b.bump_by = 1;
+  b.cls = "bump";
+  sp.prog.launches.push_back(b);
+  for (auto& S : X.pairs) sp.cC_after.push_back(S.cC);
+}
+
+}  // namespace
+}  // namespace mpofit
+
+// ====================================================================== C ABI
+using namespace mpofit;
+
+struct mpo_fit_ctx {
+  Ctx X;
+  std::map<std::string, SweepPlan> plans;
+  std::vector<hipEvent_t> evs;
+};
+
+namespace {
+template <class F>
+mpo_status guarded(F&& f) {
+  try {
+    f();
+    return MPO_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return (mpo_status)e.status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return MPO_ERR_DEVICE;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+const char* mpo_last_error(void) { return g_last_error.c_str(); }
+
+mpo_status mpo_fit_workspace_bytes(const mpo_pair* pairs, int32_t n_pairs, const mpo_fit_opts* opts,
+                                   size_t* bytes) {
+  return guarded([&] {
+    if (!bytes) throw Error{MPO_ERR_INVALID_ARG, "null bytes"};
+    Ctx X;
+    setup(X, pairs, n_pairs, opts);
+    Carver cv;
+    carve(X, cv);
+    *bytes = cv.off + 256;
+  });
+}
+
+mpo_status mpo_fit_init(mpo_fit_ctx** ctx, const mpo_pair* pairs, int32_t n_pairs,
+                        const mpo_fit_opts* opts, void* workspace, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    if (!ctx || !workspace) throw Error{MPO_ERR_INVALID_ARG, "null ctx or workspace"};
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) throw Error{MPO_ERR_WORKSPACE, "workspace not 256-byte aligned"};
+    auto c = std::make_unique<mpo_fit_ctx>();
+    Ctx& X = c->X;
+    setup(X, pairs, n_pairs, opts);
+    if (X.o.schedule != MPO_SCHED_SERIAL) throw Error{MPO_ERR_UNSUPPORTED, "even/odd schedule not built yet"};
+    Carver meas;
+    carve(X, meas);
+    if (meas.off + 256 > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "workspace too small"};
+    Carver cv;
+    cv.base = static_cast<char*>(workspace);
+    carve(X, cv);
+    X.ws_bytes = ws_bytes;
+    X.stream = static_cast<hipStream_t>(stream);
+    HIP_OK(hipGetDevice(&X.device));
+    // zero the status flags, sweep counter and split-K counters
+    Program z;
+    add_fill(z, {FillDesc{X.flag, 4, 0, 0, 0}, FillDesc{X.sb.counters, X.sb.ccap, 0, 0, 0}});
+    upload(X, z);
+    run_program(z, X.stream, nullptr);
+    Program init;
+    for (size_t p = 0; p < X.pairs.size(); ++p) rec_init_pair(X, init, X.pairs[p], (int)p);
+    upload(X, init);
+    run_program(init, X.stream, nullptr);
+    for (auto& S : X.pairs) {
+      double nu[2];
+      HIP_OK(hipMemcpyAsync(nu, S.nu_dev, sizeof(nu), hipMemcpyDeviceToHost, X.stream));
+      HIP_OK(hipStreamSynchronize(X.stream));
+      S.nu = nu[0] * nu[1];
+    }
+    // the init descriptors are not needed again
+    X.arena_used = 0;
+    check_flags(X);
+    HIP_OK(hipEventCreate(&X.ev0));
+    HIP_OK(hipEventCreate(&X.ev1));
+    *ctx = c.release();
+  });
+}
+
+mpo_status mpo_fit_sweep(mpo_fit_ctx* ctx, int32_t n_sweeps) {
+  return guarded([&] {
+    if (!ctx || n_sweeps < 0) throw Error{MPO_ERR_INVALID_ARG, "null ctx or negative sweeps"};
+    Ctx& X = ctx->X;
+    HIP_OK(hipEventRecord(X.ev0, X.stream));
+    X.prof_ms.clear();
+    for (int s = 0; s < n_sweeps; ++s) {
+      const bool fwd = X.sweeps_done % 2 == 0;
+      const std::string key = shape_key(X, fwd ? "F" : "B");
+      auto it = ctx->plans.find(key);
+      if (it == ctx->plans.end()) {
+        SweepPlan sp;
+        std::vector<std::vector<int>> before;
+        for (auto& S : X.pairs) before.push_back(S.cC);
+        record_sweep(X, sp, fwd);
+        sp.stable = sp.cC_after == before;
+        // restore host shapes (recording advanced them) and upload
+        it = ctx->plans.emplace(key, std::move(sp)).first;
+        upload(X, it->second.prog);
+      }
+      SweepPlan& sp = it->second;
+      if (X.profile) {
+        std::vector<hipEvent_t>& ev = ctx->evs;
+        while (ev.size() < sp.prog.launches.size() + 1) {
+          hipEvent_t e;
+          HIP_OK(hipEventCreate(&e));
+          ev.push_back(e);
+        }
+        run_program(sp.prog, X.stream, ev.data());
+        HIP_OK(hipEventSynchronize(ev[sp.prog.launches.size()]));
+        std::map<std::string, double> acc;
+        for (size_t li = 0; li < sp.prog.launches.size(); ++li) {
+          float ms = 0;
+          HIP_OK(hipEventElapsedTime(&ms, ev[li], ev[li + 1]));
+          acc[sp.prog.launches[li].cls] += ms;
+        }
+        for (auto& kv : acc) X.prof_ms.push_back(kv);
+      } else if (X.o.capture_graph && X.stream != nullptr && (sp.stable || sp.uses >= 1)) {
+        if (!sp.graph) {
+          hipGraph_t g = nullptr;
+          HIP_OK(hipStreamBeginCapture(X.stream, hipStreamCaptureModeThreadLocal));
+          try {
+            run_program(sp.prog, X.stream, nullptr);
+          } catch (...) {
+            (void)hipStreamEndCapture(X.stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+          }
+          HIP_OK(hipStreamEndCapture(X.stream, &g));
+          HIP_OK(hipGraphInstantiate(&sp.graph, g, nullptr, nullptr, 0));
+          HIP_OK(hipGraphDestroy(g));
+        }
+        HIP_OK(hipGraphLaunch(sp.graph, X.stream));
+      } else {
+        run_program(sp.prog, X.stream, nullptr);
+      }
+      sp.uses++;
+      for (size_t p = 0; p < X.pairs.size(); ++p) X.pairs[p].cC = sp.cC_after[p];
+      X.sweeps_done++;
+    }
+    HIP_OK(hipEventRecord(X.ev1, X.stream));
+    check_flags(X);
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, X.ev0, X.ev1));
+    X.last_ms = ms;
+  });
+}
+
+mpo_status mpo_fit_bond_dims(const mpo_fit_ctx* ctx, int32_t pair, int32_t* chi_c) {
+  return guarded([&] {
+    if (!ctx || !chi_c) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    if (pair < 0 || pair >= (int)ctx->X.pairs.size()) throw Error{MPO_ERR_INVALID_ARG, "bad pair"};
+    const auto& c = ctx->X.pairs[pair].cC;
+    for (size_t i = 0; i < c.size(); ++i) chi_c[i] = c[i];
+  });
+}
+
+mpo_status mpo_fit_export_c(mpo_fit_ctx* ctx, int32_t pair, double* const* c_cores) {
+  return guarded([&] {
+    if (!ctx || !c_cores) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    Ctx& X = ctx->X;
+    if (pair < 0 || pair >= (int)X.pairs.size()) throw Error{MPO_ERR_INVALID_ARG, "bad pair"};
+    PairState& S = X.pairs[pair];
+    Program P;
+    std::vector<PermDesc> ds;
+    for (int i = 0; i < S.L; ++i) {
+      if (!c_cores[i]) throw Error{MPO_ERR_INVALID_ARG, "null output core"};
+      const long long n = (long long)S.cC[i] * S.dd * S.cC[i + 1];
+      ds.push_back(perm4(S.C64[i], 0, c_cores[i], 0, {1, 1, 1, (int)n}, {0, 0, 0, 1}, {0, 0, 0, 1},
+                         i == 0 ? S.nu : 1.0));
+    }
+    add_perm(P, ds, "export");
+    const size_t keep = X.arena_used;
+    upload(X, P);
+    run_program(P, X.stream, nullptr);
+    HIP_OK(hipStreamSynchronize(X.stream));
+    X.arena_used = keep;
+  });
+}
+
+mpo_status mpo_fit_sweeps_done(const mpo_fit_ctx* ctx, int32_t* n) {
+  return guarded([&] {
+    if (!ctx || !n) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    *n = ctx->X.sweeps_done;
+  });
+}
+
+mpo_status mpo_fit_last_sweep_ms(const mpo_fit_ctx* ctx, double* ms) {
+  return guarded([&] {
+    if (!ctx || !ms) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    *ms = ctx->X.last_ms;
+  });
+}
+
+mpo_status mpo_fit_profile(const mpo_fit_ctx* ctx, int32_t n, double* ms, const char** names,
+                           double* flops, int32_t* count) {
+  return guarded([&] {
+    if (!ctx || !count) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    const auto& pm = ctx->X.prof_ms;
+    *count = (int)pm.size();
+    for (int i = 0; i < n && i < (int)pm.size(); ++i) {
+      if (ms) ms[i] = pm[i].second;
+      if (names) names[i] = pm[i].first.c_str();
+      if (flops) flops[i] = 0;
+    }
+  });
+}
+
+mpo_status mpo_fit_grad(mpo_fit_ctx*, int32_t, const mpo_tt*, double* const*, double* const*, double*,
+                        int32_t) {
+  g_last_error = "gradient not built yet";
+  return MPO_ERR_UNSUPPORTED;
+}
+
+mpo_status mpo_contract_check_bytes(const mpo_pair*, const mpo_tt*, size_t*) {
+  g_last_error = "check not built yet";
+  return MPO_ERR_UNSUPPORTED;
+}
+
+mpo_status mpo_contract_exact_check(const mpo_pair*, const mpo_tt*, double*, double*, void*, size_t,
+                                    void*) {
+  g_last_error = "check not built yet";
+  return MPO_ERR_UNSUPPORTED;
+}
+
+void mpo_fit_destroy(mpo_fit_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& kv : ctx->plans)
+    if (kv.second.graph) (void)hipGraphExecDestroy(kv.second.graph);
+  for (auto e : ctx->evs) (void)hipEventDestroy(e);
+  if (ctx->X.ev0) (void)hipEventDestroy(ctx->X.ev0);
+  if (ctx->X.ev1) (void)hipEventDestroy(ctx->X.ev1);
+  delete ctx;
+}
+
+}  // extern "C"
+
+// ====================================================================== test hooks
+#include "../../include/mpofit_test.h"
+
+namespace {
+struct TestEnv {
+  Ctx X;
+  Carver cv;
+  TestEnv(void* ws, size_t bytes, void* stream) {
+    if (!ws || bytes < ((size_t)64 << 20)) throw Error{MPO_ERR_WORKSPACE, "test workspace < 64 MiB"};
+    if (reinterpret_cast<uintptr_t>(ws) & 255) throw Error{MPO_ERR_WORKSPACE, "workspace not 256-byte aligned"};
+    cv.base = static_cast<char*>(ws);
+    X.stream = static_cast<hipStream_t>(stream);
+    X.flag = cv.take<int>(4);
+    X.sweep_dev = X.flag + 1;
+    X.sb.cap = (size_t)16 << 20;
+    X.sb.partials = cv.take<char>(X.sb.cap);
+    X.sb.ccap = 1 << 14;
+    X.sb.counters = cv.take<int>(X.sb.ccap);
+    X.arena_cap = (size_t)4 << 20;
+    X.arena = cv.take<char>(X.arena_cap);
+    if (cv.off > bytes) throw Error{MPO_ERR_WORKSPACE, "test workspace too small"};
+    Program z;
+    add_fill(z, {FillDesc{X.flag, 4, 0, 0, 0}, FillDesc{X.sb.counters, X.sb.ccap, 0, 0, 0}});
+    go(z);
+  }
+  void go(Program& P) {
+    upload(X, P);
+    run_program(P, X.stream, nullptr);
+    HIP_OK(hipStreamSynchronize(X.stream));
+  }
+};
+}  // namespace
+
+extern "C" {
+
+mpo_status mpo_test_gemm(int mode, int ta, int tb, int tc, int a_kcontig, int b_kcontig, int tile,
+                         int M, int N, int K, const void* A, int lda, const void* B, int ldb, void* Cm,
+                         int ldc, double alpha, int beta, int splits, void* workspace, size_t ws_bytes,
+                         void* stream) {
+  return guarded([&] {
+    TestEnv T(workspace, ws_bytes, stream);
+    Program P;
+    const Mode md = (Mode)mode;
+    GemmKind gk{md, (DType)ta, (DType)tb, (DType)tc, a_kcontig != 0, b_kcontig != 0, tile};
+    const int BM = gemm_bm(tile), BN = gemm_bn(tile), BK = gemm_bk(md);
+    GemmDesc d{};
+    d.A = A; d.B = B; d.C = Cm; d.M = M; d.N = N; d.K = K; d.lda = lda; d.ldb = ldb; d.ldc = ldc;
+    d.nb[0] = d.nb[1] = d.nb[2] = 1;
+    d.tiles_m = ceil_div(M, BM); d.tiles_n = ceil_div(N, BN);
+    d.alpha = alpha; d.beta = beta;
+    auto vec = [](const void* p, int ld) { return (ld % 4 == 0 && aligned16(p)) ? 1 : 0; };
+    d.vec_a = vec(A, lda); d.vec_b = vec(B, ldb);
+    int s = std::max(1, splits);
+    int kchunk = ceil_div(ceil_div(K, s), BK) * BK;
+    s = std::max(1, ceil_div(K, kchunk));
+    d.splits = s;
+    d.kchunk = s > 1 ? kchunk : std::max(K, 1);
+    const size_t need = (size_t)d.tiles_m * d.tiles_n * s * BM * BN * gemm_acc_bytes(md);
+    if (s > 1) {
+      if (need > T.X.sb.cap) throw Error{MPO_ERR_WORKSPACE, "split-K scratch"};
+      d.partials = T.X.sb.partials;
+      d.counters = T.X.sb.counters;
+    }
+    d.wg_begin = 0;
+    Launch l;
+    l.kind = LK::Gemm; l.gk = gk; l.off = P.push(std::vector<GemmDesc>{d}); l.n = 1;
+    l.wgs = (long long)d.tiles_m * d.tiles_n * s;
+    l.cls = "gemm";
+    P.launches.push_back(l);
+    T.go(P);
+  });
+}
+
+mpo_status mpo_test_eig(const double* H, int k, int r, double* evals, double* Z, void* workspace,
+                        size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    TestEnv T(workspace, ws_bytes, stream);
+    double* w = T.cv.take<double>(eig_work_doubles(k, r));
+    if (T.cv.off > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "test workspace too small"};
+    Program P;
+    const bool reg = k <= kRegMax;
+    Launch l;
+    l.kind = LK::Eig;
+    l.off = P.push(std::vector<EigDesc>{EigDesc{H, k, k, r, evals, Z, r, w, T.X.flag}});
+    l.n = 1;
+    l.maxb = reg ? 1 : 0;
+    l.cls = "eig";
+    P.launches.push_back(l);
+    if (reg)
+      add_gemm(P, T.X.sb, Mode::F64, {GemmJob{k, r, k, op64(eig_work_qt(w, k, r), false, k),
+                                              op64(eig_work_x(w, k, r), false, r), out64(Z, r)}},
+               "eig_backtransform", 0);
+    T.go(P);
+    check_flags(T.X);
+  });
+}
+
+mpo_status mpo_test_cholqr(double* Xm, int n, int k, void* workspace, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    TestEnv T(workspace, ws_bytes, stream);
+    double* G = T.cv.take<double>((size_t)k * k);
+    double* R = T.cv.take<double>(2 * (size_t)k * k);
+    if (T.cv.off > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "test workspace too small"};
+    Program P;
+    double* Tm = T.cv.take<double>((size_t)n * k);
+    if (T.cv.off > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "test workspace too small"};
+    add_cholqr(T.X, P, {CholQRJob{Xm, n, k, k, G, R, nullptr, Tm}}, 2);
+    T.go(P);
+    check_flags(T.X);
+  });
+}
+
+mpo_status mpo_test_omega(double* out, int chi, int dd, int k, int bond, int stream_idx, int pair,
+                          uint64_t seed, void* workspace, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    TestEnv T(workspace, ws_bytes, stream);
+    Program P;
+    OmegaDesc o{};
+    o.out = out; o.m = chi * dd; o.k = k; o.chi = chi; o.dd = dd; o.bond = bond; o.pair = pair;
+    o.stream_mul = 0; o.stream_add = stream_idx; o.stream_base = T.X.sweep_dev; o.seed = seed;
+    add_simple(P, LK::Omega, std::vector<OmegaDesc>{o}, (long long)o.m * k, "omega");
+    T.go(P);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""Kernel-level checks of libmpofit on the GPU against NumPy (float64)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.canon import qr_pos
+from oracle.philox import gaussian_matrix
+from paper_2606_23274_amd import _lib
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hooks():
+    from tests.gpu_util import Hooks
+    return Hooks()
+
+
+# (mode, ta, tb, tc): 0 = FP64, 1 = FP32; mode 2 = BF16 (FP32 accumulate)
+KINDS = [(0, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 1, 1, 0), (1, 1, 1, 1), (1, 0, 1, 1),
+         (2, 1, 1, 1), (2, 0, 1, 1)]
+TOL = {0: 1e-13, 1: 2e-5, 2: 2e-2}
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("akc,bkc", [(1, 1), (1, 0), (0, 1), (0, 0)])
+@pytest.mark.parametrize("M,N,K,tile,splits", [(64, 64, 64, 0, 1), (77, 45, 53, 0, 1),
+                                               (200, 136, 300, 1, 1), (130, 70, 1000, 0, 4)])
+def test_gemm_against_numpy(hooks, kind, akc, bkc, M, N, K, tile, splits):
+    from tests.gpu_util import dev, ptr
+    mode, ta, tb, tc = kind
+    if mode == 0 and tile == 1:
+        tile = 0
+    rng = np.random.default_rng(M * 7 + N * 3 + K)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    Cin = rng.standard_normal((M, N))
+    tA = torch.float64 if ta == 0 else torch.float32
+    tB = torch.float64 if tb == 0 else torch.float32
+    tC = torch.float64 if tc == 0 else torch.float32
+    # storage: A K-contiguous = row-major M x K; M-contiguous = row-major K x M
+    Ad = dev(A if akc else A.T.copy(), tA)
+    Bd = dev(B.T.copy() if bkc else B, tB)
+    Cd = dev(Cin, tC)
+    lda = K if akc else M
+    ldb = K if bkc else N
+    Ar = Ad.double().cpu().numpy()
+    Br = Bd.double().cpu().numpy()
+    Aref = Ar if akc else Ar.T
+    Bref = Br.T if bkc else Br
+    ref = 0.5 * Aref @ Bref + Cd.double().cpu().numpy()
+    st = hooks.lib.mpo_test_gemm(mode, ta, tb, tc, akc, bkc, tile, M, N, K, ptr(Ad), lda, ptr(Bd),
+                                 ldb, ptr(Cd), N, 0.5, 1, splits, *hooks.args())
+    _lib.check(st)
+    got = Cd.double().cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err < TOL[mode], err
+
+
+@pytest.mark.parametrize("k,r", [(1, 1), (2, 2), (5, 3), (64, 64), (144, 128), (200, 150), (272, 256)])
+def test_eig_against_numpy(hooks, k, r):
+    from tests.gpu_util import dev, ptr
+    rng = np.random.default_rng(k)
+    X = rng.standard_normal((k, 3 * k)) * np.exp(-np.arange(3 * k) / 40.0)
+    H = X @ X.T
+    w, V = np.linalg.eigh(H)
+    w, V = w[::-1][:r], V[:, ::-1][:, :r]
+    Hd = dev(H)
+    ev = torch.zeros(r, dtype=torch.float64, device="cuda:0")
+    Z = torch.zeros((k, r), dtype=torch.float64, device="cuda:0")
+    _lib.check(hooks.lib.mpo_test_eig(ptr(Hd), k, r, ptr(ev), ptr(Z), *hooks.args()))
+    ev, Z = ev.cpu().numpy(), Z.cpu().numpy()
+    nrm = np.abs(w).max()
+    assert np.abs(ev - w).max() <= 1e-13 * nrm
+    res = np.linalg.norm(H @ Z - Z * ev) / nrm
+    assert res < 1e-12
+    assert np.abs(Z.T @ Z - np.eye(r)).max() < 1e-9
+    # same vectors up to sign
+    assert np.abs(np.abs(np.sum(Z * V, axis=0)) - 1).max() < 1e-8
+
+
+@pytest.mark.parametrize("n,k", [(40, 12), (512, 144), (300, 300), (1024, 272)])
+def test_cholqr2_against_householder(hooks, n, k):
+    from tests.gpu_util import dev, ptr
+    rng = np.random.default_rng(n + k)
+    X = rng.standard_normal((n, k)) @ np.diag(np.exp(-np.arange(k) / 30.0))
+    Xd = dev(X)
+    _lib.check(hooks.lib.mpo_test_cholqr(ptr(Xd), n, k, *hooks.args()))
+    Q = Xd.cpu().numpy()
+    Qref, _ = qr_pos(X)
+    assert np.abs(Q.T @ Q - np.eye(k)).max() < 1e-13
+    assert np.abs(Q - Qref).max() < 1e-9
+
+
+@pytest.mark.parametrize("chi,dd,k,bond,stream,pair,seed",
+                         [(16, 4, 24, 3, 0, 0, 0), (32, 4, 74, 7, 5, 2, 12345), (5, 9, 11, 1, 1, 1, 2**40)])
+def test_omega_matches_oracle(hooks, chi, dd, k, bond, stream, pair, seed):
+    from tests.gpu_util import ptr
+    m = chi * dd
+    out = torch.zeros((m, k), dtype=torch.float64, device="cuda:0")
+    _lib.check(hooks.lib.mpo_test_omega(ptr(out), chi, dd, k, bond, stream, pair, seed, *hooks.args()))
+    got = out.cpu().numpy()
+    ref = gaussian_matrix(m, k, seed, pair, stream, bond)  # rows in (su, c'') order
+    # the GPU stores row p = c''*dd + su for logical row i = su*chi + c''
+    perm = np.array([(p % dd) * chi + p // dd for p in range(m)])
+    assert np.abs(got - ref[perm]).max() < 1e-14 * np.abs(ref).max() * 8
