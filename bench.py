@@ -65,11 +65,31 @@ def settled_dims(L, d, chi, chi_c):
     return dims
 
 
-def run_gpu(A, B, precision, sketch_p, steps, warmup, profile=False):
+def batched_sweep_flops(L, d, chi, chi_c, dims_c):
+    """Algorithmic MFMA flops of one even/odd sweep: both extensions, the
+    two-site matrix and both environment updates at every bond."""
+    dd = d * d
+    chiA = [1] + [chi] * (L - 1) + [1]
+    for i in range(1, L + 1):
+        chiA[i] = min(chiA[i], chiA[i - 1] * dd)
+    tot = 0.0
+    for i in range(L - 1):
+        cl, cr, r = dims_c[i], dims_c[i + 2], dims_c[i + 1]
+        n, m = cl * dd, dd * cr
+        a0, a1, a2 = chiA[i], chiA[i + 1], chiA[i + 2]
+        K = a1 * a1
+        tot += 2.0 * cl * a0 * a0 * dd * a1 + 2.0 * cl * dd * d * a0 * a1 * a1
+        tot += 2.0 * cr * a2 * a2 * dd * a1 + 2.0 * cr * dd * d * a2 * a1 * a1
+        tot += 2.0 * n * m * K + 2.0 * r * K * (n + m)
+    return tot
+
+
+def run_gpu(A, B, precision, sketch_p, steps, warmup, profile=False, schedule="serial", chi_c=None):
     import torch
     from paper_2606_23274_amd.api import FitContext
-    ctx = FitContext([(A, B)], WORKLOAD["chi_c"], precision=precision, sketch_p=sketch_p,
-                     seed=WORKLOAD["seed"], capture_graph=not profile, profile=profile)
+    ctx = FitContext([(A, B)], chi_c or WORKLOAD["chi_c"], precision=precision, sketch_p=sketch_p,
+                     seed=WORKLOAD["seed"], capture_graph=not profile, profile=profile,
+                     schedule=schedule)
     ctx.sweep(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -152,6 +172,28 @@ def main():
                            "tflops": round(mfp / (wl / st) / 1e12, 3),
                            "mfma_frac": round(mfp / (wl / st) / PEAK[prec], 5)}
 
+    # batched even/odd inverse-gauge schedule (all bonds of one parity per launch)
+    batched = {}
+    if not args.quick:
+        wl, _, _, bd = run_gpu(A, B, "fp32", w["p"], args.steps, args.warmup, schedule="even_odd")
+        fb = batched_sweep_flops(w["L"], w["d"], w["chi"], w["chi_c"], bd)
+        batched["even_odd_L40_chi64_fp32"] = {
+            "sweeps_per_s": round(args.steps / wl, 3), "ms_per_sweep": round(wl / args.steps * 1e3, 3),
+            "tflops": round(fb / (wl / args.steps) / 1e12, 3),
+            "mfma_frac": round(fb / (wl / args.steps) / PEAK["fp32"], 5)}
+        from paper_2606_23274_amd._lib import MpoError
+        A4, B4 = make_pair(64, 2, 128, seed=0, decay=True)
+        st4 = max(2, args.steps // 3)
+        try:
+            wl, _, _, bd = run_gpu(A4, B4, "fp32", 16, st4, 2, schedule="even_odd", chi_c=256)
+            fb = batched_sweep_flops(64, 2, 128, 256, bd)
+            batched["even_odd_L64_chi128_fp32"] = {
+                "sweeps_per_s": round(st4 / wl, 3), "ms_per_sweep": round(wl / st4 * 1e3, 3),
+                "tflops": round(fb / (wl / st4) / 1e12, 3),
+                "mfma_frac": round(fb / (wl / st4) / PEAK["fp32"], 5)}
+        except MpoError as e:
+            batched["even_odd_L64_chi128_fp32"] = {"error": str(e)}
+
     # roofline of the dominant kernel class (per-launch average)
     dom = max(prof, key=prof.get)
     nb = w["L"] - 1
@@ -189,6 +231,7 @@ def main():
         "bond_dims_settled": got_dims == dims,
         "kernel_ms_per_sweep": {kk: round(v, 4) for kk, v in sorted(prof.items(), key=lambda x: -x[1])},
         "other_precisions": others,
+        "batched_schedule": batched,
         "roofline": roof,
     }
     if not args.no_cpu:

@@ -82,6 +82,7 @@ typedef struct {
 
 typedef struct {
   mpo_tt A, B;               /* C ~ A B; A and B must share L and d           */
+  int32_t chi_max;           /* bond cap of this pair's C; 0 = opts->chi_max  */
 } mpo_pair;
 
 typedef struct {

@@ -20,7 +20,7 @@ class MpoTT(C.Structure):
 
 
 class MpoPair(C.Structure):
-    _fields_ = [("A", MpoTT), ("B", MpoTT)]
+    _fields_ = [("A", MpoTT), ("B", MpoTT), ("chi_max", C.c_int32)]
 
 
 class MpoFitOpts(C.Structure):

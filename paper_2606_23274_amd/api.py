@@ -39,13 +39,13 @@ class _TT:
 class FitContext:
     """One fit of one or several independent MPO pairs.
 
-    precision: 'fp64' | 'fp32' | 'bf16'; schedule: 'serial' | 'even_odd';
-    sketch_p < 0 runs the plain SVD, >= 0 the randomized SVD with chi_max + p
-    sketch columns.
+    precision: 'fp64' | 'fp32' | 'bf16' | 'bf16x3'; schedule: 'serial' |
+    'even_odd'; sketch_p < 0 runs the plain SVD, >= 0 the randomized SVD with
+    chi_max + p sketch columns; pair_chi_max optionally sets each pair's cap.
     """
 
     def __init__(self, pairs, chi_max, precision="fp32", schedule="serial", sketch_p=-1, seed=0,
-                 capture_graph=True, device="cuda:0", profile=False):
+                 capture_graph=True, device="cuda:0", profile=False, pair_chi_max=None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self._tts = []
@@ -53,7 +53,8 @@ class FitContext:
         for i, (A, B) in enumerate(pairs):
             ta, tb = _TT(_dev_cores(A, self.device)), _TT(_dev_cores(B, self.device))
             self._tts += [ta, tb]
-            arr[i] = _lib.MpoPair(ta.tt, tb.tt)
+            cm = 0 if pair_chi_max is None else int(pair_chi_max[i])
+            arr[i] = _lib.MpoPair(ta.tt, tb.tt, cm)
         self._pairs = arr
         self.n_pairs = len(pairs)
         self.L = [len(A) for A, _ in pairs]

@@ -464,7 +464,9 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
     }
   bool bad = false;
   // Cholesky: a(r, c) -= a(r, jj) a(c, jj) / a(jj, jj) on the trailing block;
-  // column jj of L is a(:, jj) / sqrt(a(jj, jj)).
+  // column jj of L is a(:, jj) / sqrt(a(jj, jj)).  The masks live in the
+  // broadcast vectors (zero at indices <= jj), so the update is a plain
+  // rank-1 FMA over the register block.
   for (int jj = 0; jj < k; ++jj) {
     const int jb = jj >> 5, jt = jj & 31, buf = jj & 1;
     if (tc == jt) {
@@ -478,18 +480,28 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
     const double djj = colb[buf][jj];
     if (!(djj > 0.0) || !isfinite(djj)) bad = true;
     const double invd = (djj > 0.0) ? 1.0 / djj : 0.0;
-    const double invs = (djj > 0.0) ? 1.0 / sqrt(djj) : 0.0;
+    double cr[NB], cc[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int r = tr + 32 * i, c = tc + 32 * i;
+      cr[i] = (r > jj) ? colb[buf][r] * invd : 0.0;
+      cc[i] = (c > jj) ? colb[buf][c] : 0.0;
+    }
+    if (tc == jt) {  // finish column jj of L: scale by 1/sqrt(d)
+      const double invs = (djj > 0.0) ? 1.0 / sqrt(djj) : 0.0;
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (j == jb && tr + 32 * i >= jj) a[i][j] *= invs;
+    }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       if (i < jb) continue;  // uniform: rows < 32*jb <= jj
-      const int r = tr + 32 * i;
-      const double cr = colb[buf][r] * invd;
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (j < jb) continue;
-        const int c = tc + 32 * j;
-        if (c > jj && r > jj) a[i][j] -= cr * colb[buf][c];
-        if (c == jj && r >= jj) a[i][j] *= invs;  // finished column of L
+        a[i][j] -= cr[i] * cc[j];
       }
     }
   }
@@ -503,7 +515,7 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
         for (int j = 0; j < NB; ++j)
           if (j == jb) colb[buf][tr + 32 * i] = (tr + 32 * i >= jj) ? a[i][j] : 0.0;
     }
-    if (tr == jt) {  // row jj of X before the scaling (columns <= jj only)
+    if (tr == jt) {  // row jj of X before the scaling
 #pragma unroll
       for (int i = 0; i < NB; ++i)
         if (i == jb) {
@@ -513,20 +525,28 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
     }
     __syncthreads();
     const double linv = 1.0 / colb[buf][jj];
+    double l[NB], rw[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int r = tr + 32 * i;
+      l[i] = (r > jj && r < k) ? colb[buf][r] * linv : 0.0;
+      rw[i] = rowb[buf][tc + 32 * i];
+    }
+    if (tr == jt) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (i == jb) {
+#pragma unroll
+          for (int j = 0; j < NB; ++j) x[i][j] *= linv;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       if (i < jb) continue;
-      const int r = tr + 32 * i;
-      if (r == jj) {
 #pragma unroll
-        for (int j = 0; j < NB; ++j) x[i][j] *= linv;
-      } else if (r > jj && r < k) {
-        const double l = colb[buf][r] * linv;
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          if (j > jb) continue;  // X(jj, c) = 0 for c > jj
-          x[i][j] -= l * rowb[buf][tc + 32 * j];
-        }
+      for (int j = 0; j < NB; ++j) {
+        if (j > jb) continue;  // X(jj, c) = 0 for c > jj
+        x[i][j] -= l[i] * rw[j];
       }
     }
   }
@@ -630,6 +650,9 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
     }
     __syncthreads();
     // A22 -= v w^T + w v^T (trailing block only; v, w vanish at <= jj)
+    double vc[NB], wc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) { vc[j] = vb[tc + 32 * j]; wc[j] = wb[tc + 32 * j]; }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       if (i < jb) continue;  // uniform
@@ -638,8 +661,7 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (j < jb) continue;
-        const int c = tc + 32 * j;
-        if (r > jj && c > jj) a[i][j] -= vi * wb[c] + wi * vb[c];
+        a[i][j] -= vi * wc[j] + wi * vc[j];
       }
     }
     __syncthreads();

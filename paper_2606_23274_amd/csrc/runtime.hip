@@ -105,9 +105,29 @@ struct SplitBuf {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-// Appends one grouped GEMM launch covering `jobs` (all of one kind).
+void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<GemmJob>& jobs,
+                   const char* cls, double flops);
+
+// Appends grouped GEMM launches covering `jobs`: one launch per operand
+// kind (element types and contiguity), since a launch is compiled for one.
 void add_gemm(Program& P, const SplitBuf& sb, Mode mode, const std::vector<GemmJob>& jobs,
               const char* cls, double flops) {
+  if (jobs.empty()) return;
+  std::map<std::tuple<int, int, int, int, int>, std::vector<GemmJob>> groups;
+  double total = 0;
+  for (auto& j : jobs) total += 2.0 * j.M * j.N * j.K * j.nb[0] * j.nb[1] * j.nb[2];
+  for (auto& j : jobs)
+    groups[{(int)j.A.t, (int)j.B.t, (int)j.C.t, (int)j.A.kc, (int)j.B.kc}].push_back(j);
+  for (auto& kv : groups) {
+    double part = 0;
+    for (auto& j : kv.second) part += 2.0 * j.M * j.N * j.K * j.nb[0] * j.nb[1] * j.nb[2];
+    add_gemm_kind(P, sb, mode, kv.second, cls, total > 0 ? flops * part / total : 0);
+  }
+}
+
+// One grouped GEMM launch covering `jobs` (all of one kind).
+void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<GemmJob>& jobs,
+                   const char* cls, double flops) {
   if (jobs.empty()) return;
   GemmKind gk{mode, jobs[0].A.t, jobs[0].B.t, jobs[0].C.t, jobs[0].A.kc, jobs[0].B.kc, 0};
   // tile: 128x128 for FP32/BF16 when every problem is large enough and the
@@ -197,6 +217,7 @@ void add_simple(Program& P, LK kind, const std::vector<D>& ds, long long maxa, c
 // ------------------------------------------------------------------ state
 struct PairState {
   int L = 0, d = 0, dd = 0;
+  int chi_max = 1;
   std::vector<int> cA, cB, cC;  // bond dims (L+1): preprocessed A, B; current C
   std::vector<int> capC;        // capacity of C's bonds over the whole fit
   std::vector<int> rcap;        // chi^A_i chi^B_i per bond index i (1..L-1)
@@ -311,7 +332,7 @@ Caps pair_caps(const PairState& P, const mpo_fit_opts& o) {
     const long long n = (long long)P.capC[b - 1] * P.dd, m = (long long)P.dd * P.capC[b + 1];
     c.nm_max = std::max({c.nm_max, n, m});
     c.theta = std::max(c.theta, n * m);
-    const long long kk = o.sketch_p < 0 ? n : std::min<long long>(n, o.chi_max + (long long)o.sketch_p);
+    const long long kk = o.sketch_p < 0 ? n : std::min<long long>(n, P.chi_max + (long long)o.sketch_p);
     c.kmax = std::max({c.kmax, kk, n});  // exact path uses the n x n Gram
     c.rmax = std::max<long long>(c.rmax, P.capC[b]);
   }
@@ -655,12 +676,13 @@ void rec_repack(Ctx& X, Program& P, PairState& S) {
 // right environment of site j from Renv[j+1] (sweep or init): XR[j-1] via the
 // two mirrored steps, then (if make_env) Renv[j] = CR_j . XR[j-1] where
 // CR_j[c][(c'', s, u)] is C_j with its right bond first.
-void rec_right_env_from_core(Ctx& X, Program& P, PairState& S, int j, bool make_env, BondScratch& B) {
+void rec_right_env_from_core(Ctx& X, Program& P, PairState& S, int j, bool make_env, BondScratch& B,
+                             const double* core = nullptr) {
   add_gemm(P, X.sb, X.wmode, {job_e1m(X, S, j, B.T, B.amT)}, "env_ext1", flops_e1m(S, j));
   add_gemm(P, X.sb, X.wmode, {job_e2m(X, S, j, B.T, B.amT)}, "env_ext2", flops_e2m(S, j));
   if (!make_env) return;
   const int c0 = S.cC[j], c1 = S.cC[j + 1], dd = S.dd, N = S.cA[j] * S.cB[j];
-  add_perm(P, {perm4(S.C64[j], 0, X.iXt, 0, {c0, dd, c1, 1}, {(long long)dd * c1, c1, 1, 0},
+  add_perm(P, {perm4(core ? core : S.C64[j], 0, X.iXt, 0, {c0, dd, c1, 1}, {(long long)dd * c1, c1, 1, 0},
                      {(long long)c1 * dd, 1, dd, 0})}, "copy");
   add_gemm(P, X.sb, X.wmode, {GemmJob{c0, N, c1 * dd, op64(X.iXt, true, c1 * dd),
                                       opW(X, S.XR[j - 1], false, N, S.amXR[j - 1]),
@@ -698,9 +720,9 @@ BondJob make_bond(Ctx& X, PairState& P, int pair, int i, bool fwd, BondScratch& 
   b.m = P.dd * P.cC[i + 2];
   const int cap = P.rcap[i + 1];
   const int kmax = std::min(std::min(b.n, b.m), cap);
-  b.r = std::min(X.o.chi_max, kmax);
-  b.sketch = X.o.sketch_p >= 0 && X.o.chi_max + X.o.sketch_p < std::min(b.n, b.m);
-  if (b.sketch) b.k = std::min(X.o.chi_max + X.o.sketch_p, kmax);
+  b.r = std::min(P.chi_max, kmax);
+  b.sketch = X.o.sketch_p >= 0 && P.chi_max + X.o.sketch_p < std::min(b.n, b.m);
+  if (b.sketch) b.k = std::min(P.chi_max + X.o.sketch_p, kmax);
   else b.k = b.n;
   if (b.sketch && b.k >= std::min(b.n, b.m)) { b.sketch = false; b.k = b.n; }
   return b;
@@ -886,6 +908,170 @@ void rec_serial_bond(Ctx& X, Program& P, PairState& S, int pair, int i, bool fwd
   S.cC[i + 1] = bj[0].r;
 }
 
+// Inverse canonical form of the right-canonical C (Sec. 2.3.1): a left-to-
+// right SVD sweep X_i = carry C_i = U S V^T (from the eigenpairs of X^T X),
+// Psi_i = U S, S kept per bond (Y_i = 1/S), carry S V^T into the next core.
+// Then the environments: L_{i+1} from Psi_i Y_i = U_i, R_j from
+// Y_{j-1} Psi_j (rows of Psi_j divided by S_{j-1}).
+void rec_inverse_canonical(Ctx& X, Program& P, PairState& S) {
+  const int L = S.L, dd = S.dd;
+  BondScratch& B = X.scratch[0];
+  for (int i = 0; i + 1 < L; ++i) {
+    const int p = S.cC[i] * dd, q = S.cC[i + 1], nn = dd * S.cC[i + 2];
+    double* Xi = S.C64[i];
+    add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, p, op64(Xi, false, q), op64(Xi, false, q), out64(B.H, q)}},
+             "init", 0);
+    const bool reg = q <= kRegMax;
+    {
+      Launch l;
+      l.kind = LK::Eig;
+      l.off = P.push(std::vector<EigDesc>{EigDesc{B.H, q, q, q, B.evals, B.Z, q, B.eigw, X.flag}});
+      l.n = 1;
+      l.maxb = reg ? 1 : 0;
+      l.cls = "init";
+      P.launches.push_back(l);
+    }
+    if (reg)
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(eig_work_qt(B.eigw, q, q), false, q),
+                                            op64(eig_work_x(B.eigw, q, q), false, q), out64(B.Z, q)}},
+               "init", 0);
+    add_simple(P, LK::Sval, std::vector<SvalDesc>{SvalDesc{B.evals, S.Yv[i + 1], q, 1, X.flag}}, q, "init");
+    // U = X V / S (into Y), orthonormalized; sign rule on U, applied to V
+    add_gemm(P, X.sb, Mode::F64, {GemmJob{p, q, q, op64(Xi, true, q), op64(B.Z, false, q), out64(B.Y, q)}},
+             "init", 0);
+    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{B.Y, B.Y, p, q, q, q, nullptr, S.Yv[i + 1], 0, 1}},
+               (long long)p * q, "init");
+    add_cholqr(X, P, {CholQRJob{B.Y, p, q, q, B.G, B.R, nullptr, q <= kRegMax ? B.Y2 : nullptr}}, 1);
+    add_simple(P, LK::Sign, std::vector<SignDesc>{SignDesc{B.Y, p, q, q, B.sign, nullptr}}, q, "init");
+    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{B.Z, B.Z, q, q, q, q, nullptr, B.sign, 0, 0}},
+               (long long)q * q, "init");
+    // Psi_i = U S
+    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{B.Y, Xi, p, q, q, q, nullptr, S.Yv[i + 1], 0, 0}},
+               (long long)p * q, "init");
+    // carry: next <- (S V^T) next
+    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{B.Z, B.Z, q, q, q, q, nullptr, S.Yv[i + 1], 0, 0}},
+               (long long)q * q, "init");
+    add_gemm(P, X.sb, Mode::F64, {GemmJob{q, nn, q, op64(B.Z, false, q), op64(S.C64[i + 1], false, nn),
+                                          out64(X.iTmp, nn)}}, "init", 0);
+    add_perm(P, {perm4(X.iTmp, 0, S.C64[i + 1], 0, {1, 1, q, nn}, {0, 0, nn, 1}, {0, 0, nn, 1})}, "init");
+  }
+  const int f64 = X.wt == DType::F64 ? 1 : 0;
+  add_fill(P, {FillDesc{S.Lenv[0], 0, 1, 1, f64}, FillDesc{S.Renv[L], 0, 1, 1, f64}});
+  std::vector<unsigned*> sl{S.amL[0], S.amR[L], B.amT};
+  for (int j = 1; j < L; ++j) sl.insert(sl.end(), {S.amR[j], S.amL[j], S.amXR[j - 1], S.amXL[j - 1]});
+  rec_reset_amax(X, P, sl);
+  for (int i = 0; i + 2 < L; ++i) {  // L_{i+1} from U_i = Psi_i / S_{i+1}
+    const int p = S.cC[i] * dd, q = S.cC[i + 1];
+    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{S.C64[i], X.iTmp, p, q, q, q, nullptr,
+                                                              S.Yv[i + 1], 0, 1}}, (long long)p * q, "init");
+    rec_left_env_from_core(X, P, S, i, X.iTmp, q, B);
+  }
+  for (int j = L - 1; j >= 2; --j) {  // R_j from Y_{j-1} Psi_j
+    const int p = S.cC[j], q = dd * S.cC[j + 1];
+    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{S.C64[j], X.iTmp, p, q, q, q, S.Yv[j],
+                                                              nullptr, 1, 0}}, (long long)p * q, "init");
+    rec_right_env_from_core(X, P, S, j, true, B, X.iTmp);
+  }
+}
+
+// Inverse-gauge assignment (Alg. 4) for all bonds of a half-step:
+//   U = orth(Q Z), V = orth(Bk^T Z / S) with the sign rule on U;
+//   L_{i+1} = U^T XL_i, R_{i+1} = V^T XR_i;
+//   Psi_i = U S, Psi_{i+1} = S V^T, Y_i = 1/S (S kept in Yv).
+void rec_assign_inverse(Ctx& X, Program& P, std::vector<BondJob>& bj) {
+  std::vector<GemmJob> uq, vj, envl, envr;
+  std::vector<PermDesc> cp, perm;
+  std::vector<CholQRJob> orthU, orthV;
+  std::vector<SignDesc> sg;
+  std::vector<ScaleDesc> sv1, sv2, su, sv3;
+  double fenv = 0;
+  int maxr = 1;
+  long long maxsc = 1;
+  for (auto& b : bj) {
+    PairState& S = *b.P;
+    BondScratch& B = *b.B;
+    const int i = b.i, r = b.r, cr = S.cC[i + 2], dd = S.dd;
+    const int N = S.cA[i + 1] * S.cB[i + 1];
+    double* Ci = S.C64[i];
+    double* Cn = S.C64[i + 1];
+    if (b.sketch)
+      uq.push_back(GemmJob{b.n, r, b.k, op64(B.Y, true, b.k), op64(B.Z, false, r), out64(Ci, r)});
+    else
+      cp.push_back(perm4(B.Z, 0, Ci, 0, {1, 1, b.n, r}, {0, 0, r, 1}, {0, 0, r, 1}));
+    if (b.sketch)
+      vj.push_back(GemmJob{b.m, r, b.k, op64(B.Bk, false, b.m), op64(B.Z, false, r), out64(B.V, r)});
+    else
+      vj.push_back(GemmJob{b.m, r, b.n, opW(X, B.theta, false, b.m), op64(B.Z, false, r), out64(B.V, r)});
+    sv1.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 1});
+    orthU.push_back(CholQRJob{Ci, b.n, r, r, B.G, B.R, nullptr, r <= kRegMax ? B.Y2 : nullptr});
+    // runs after orthU in stream order, so it reuses the same G and R scratch
+    orthV.push_back(CholQRJob{B.V, b.m, r, r, B.G, B.R, nullptr, r <= kRegMax ? B.SVt : nullptr});
+    sg.push_back(SignDesc{Ci, b.n, r, r, B.sign, nullptr});
+    sv2.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.sign, 0, 0});
+    envl.push_back(GemmJob{r, N, b.n, op64(Ci, false, r), opW(X, S.XL[i], false, N, S.amXL[i]),
+                           outW(X, S.Lenv[i + 1], N, S.amL[i + 1])});
+    envr.push_back(GemmJob{r, N, b.m, op64(B.V, false, r), opW(X, S.XR[i], false, N, S.amXR[i]),
+                           outW(X, S.Renv[i + 1], N, S.amR[i + 1])});
+    fenv += 2.0 * r * N * (b.n + b.m);
+    su.push_back(ScaleDesc{Ci, Ci, b.n, r, r, r, nullptr, B.S, 0, 0});      // Psi_i = U S
+    sv3.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 0});   // V S
+    perm.push_back(perm4(B.V, 0, Cn, 0, {r, cr, dd, 1}, {1, (long long)dd * r, r, 0},
+                         {(long long)dd * cr, 1, cr, 0}));                  // Psi_{i+1} = S V^T
+    cp.push_back(perm4(B.S, 0, S.Yv[i + 1], 0, {1, 1, 1, r}, {0, 0, 0, 1}, {0, 0, 0, 1}));
+    maxr = std::max(maxr, r);
+    maxsc = std::max(maxsc, (long long)std::max(b.n, b.m) * r);
+  }
+  add_gemm(P, X.sb, Mode::F64, uq, "assemble", 0);
+  add_gemm(P, X.sb, Mode::F64, vj, "assemble", 0);
+  add_perm(P, cp, "copy");
+  add_simple(P, LK::Scale, sv1, maxsc, "scale");
+  add_cholqr(X, P, orthU, 1);
+  add_cholqr(X, P, orthV, 1);
+  add_simple(P, LK::Sign, sg, maxr, "sign");
+  add_simple(P, LK::Scale, sv2, maxsc, "scale");
+  add_gemm(P, X.sb, X.wmode, envl, "env_update", fenv / 2);
+  add_gemm(P, X.sb, X.wmode, envr, "env_update", fenv / 2);
+  add_simple(P, LK::Scale, su, maxsc, "scale");
+  add_simple(P, LK::Scale, sv3, maxsc, "scale");
+  add_perm(P, perm, "copy");
+}
+
+// One half-step q of the even/odd schedule (all pairs): bonds with
+// (1-based) index = 1 (mod 2) for q = 0, = 0 (mod 2) for q = 1.
+void rec_half_step(Ctx& X, Program& P, int q) {
+  std::vector<BondJob> bj;
+  std::vector<GemmJob> e1, e2, e1m, e2m;
+  std::vector<unsigned*> slots;
+  double f1 = 0, f2 = 0, f1m = 0, f2m = 0;
+  size_t si = 0;
+  for (size_t p = 0; p < X.pairs.size(); ++p) {
+    PairState& S = X.pairs[p];
+    for (int i = 0; i + 1 < S.L; ++i) {
+      const int bond = i + 1;
+      if ((bond % 2 == 1) != (q == 0)) continue;
+      BondScratch& B = X.scratch.at(si++);
+      bj.push_back(make_bond(X, S, (int)p, i, true, B));
+      e1.push_back(job_e1(X, S, i, B.T, B.amT));
+      e2.push_back(job_e2(X, S, i, B.T, B.amT));
+      e1m.push_back(job_e1m(X, S, i + 1, B.T, B.amT));
+      e2m.push_back(job_e2m(X, S, i + 1, B.T, B.amT));
+      f1 += flops_e1(S, i); f2 += flops_e2(S, i); f1m += flops_e1m(S, i + 1); f2m += flops_e2m(S, i + 1);
+      slots.insert(slots.end(), {B.amT, S.amXL[i], S.amXR[i], S.amL[i + 1], S.amR[i + 1]});
+    }
+  }
+  rec_reset_amax(X, P, slots);
+  add_gemm(P, X.sb, X.wmode, e1, "env_ext1", f1);
+  add_gemm(P, X.sb, X.wmode, e2, "env_ext2", f2);
+  std::vector<unsigned*> tslots;
+  for (auto& b : bj) tslots.push_back(b.B->amT);
+  rec_reset_amax(X, P, tslots);
+  add_gemm(P, X.sb, X.wmode, e1m, "env_ext1", f1m);
+  add_gemm(P, X.sb, X.wmode, e2m, "env_ext2", f2m);
+  rec_factor(X, P, bj, 2, q, true);
+  rec_assign_inverse(X, P, bj);
+  for (auto& b : bj) b.P->cC[b.i + 1] = b.r;
+}
+
 std::string shape_key(const Ctx& X, const char* tag) {
   std::string k(tag);
   for (auto& P : X.pairs)
@@ -937,6 +1123,11 @@ void rec_init_pair(Ctx& X, Program& P, PairState& S, int pair) {
   for (int j = 1; j < L; ++j) sl.insert(sl.end(), {S.amR[j], S.amXR[j - 1]});
   sl.push_back(X.scratch[0].amT);
   rec_reset_amax(X, P, sl);
+  if (X.o.schedule == MPO_SCHED_EVEN_ODD) {
+    rec_inverse_canonical(X, P, S);
+    (void)pair;
+    return;
+  }
   for (int j = L - 1; j >= 1; --j) rec_right_env_from_core(X, P, S, j, j >= 2, X.scratch[0]);
   (void)pair;
 }
@@ -983,7 +1174,10 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
     for (int b = 0; b <= L; ++b)
       if (S.chiA_in[b] > 512 || S.chiB_in[b] > 512)
         throw Error{MPO_ERR_UNSUPPORTED, "bond dimensions above 512"};
-    plan_shapes(S, o->chi_max, o->schedule);
+    S.chi_max = pr.chi_max > 0 ? pr.chi_max : o->chi_max;
+    if (S.chi_max + std::max(o->sketch_p, 0) > 512)
+      throw Error{MPO_ERR_UNSUPPORTED, "chi_max + sketch_p above 512"};
+    plan_shapes(S, S.chi_max, o->schedule);
     for (int b = 0; b <= L; ++b)
       if (S.capC[b] * S.dd > 2048) throw Error{MPO_ERR_UNSUPPORTED, "two-site dimension above 2048"};
   }
@@ -1012,6 +1206,18 @@ struct SweepPlan {
 };
 
 void record_sweep(Ctx& X, SweepPlan& sp, bool fwd) {
+  if (X.o.schedule == MPO_SCHED_EVEN_ODD) {
+    rec_half_step(X, sp.prog, 0);
+    rec_half_step(X, sp.prog, 1);
+    Launch b;
+    b.kind = LK::Bump;
+    b.counter = X.sweep_dev;
+    b.bump_by = 1;
+    b.cls = "bump";
+    sp.prog.launches.push_back(b);
+    for (auto& S : X.pairs) sp.cC_after.push_back(S.cC);
+    return;
+  }
   for (size_t p = 0; p < X.pairs.size(); ++p) {
     PairState& S = X.pairs[p];
     if (fwd) for (int i = 0; i + 1 < S.L; ++i) rec_serial_bond(X, sp.prog, S, (int)p, i, true);
@@ -1078,7 +1284,6 @@ mpo_status mpo_fit_init(mpo_fit_ctx** ctx, const mpo_pair* pairs, int32_t n_pair
     auto c = std::make_unique<mpo_fit_ctx>();
     Ctx& X = c->X;
     setup(X, pairs, n_pairs, opts);
-    if (X.o.schedule != MPO_SCHED_SERIAL) throw Error{MPO_ERR_UNSUPPORTED, "even/odd schedule not built yet"};
     Carver meas;
     carve(X, meas);
     if (meas.off + 256 > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "workspace too small"};
@@ -1197,13 +1402,21 @@ mpo_status mpo_fit_export_c(mpo_fit_ctx* ctx, int32_t pair, double* const* c_cor
     PairState& S = X.pairs[pair];
     Program P;
     std::vector<PermDesc> ds;
+    std::vector<ScaleDesc> sc;
+    const bool inv = X.o.schedule == MPO_SCHED_EVEN_ODD;
     for (int i = 0; i < S.L; ++i) {
       if (!c_cores[i]) throw Error{MPO_ERR_INVALID_ARG, "null output core"};
       const long long n = (long long)S.cC[i] * S.dd * S.cC[i + 1];
       ds.push_back(perm4(S.C64[i], 0, c_cores[i], 0, {1, 1, 1, (int)n}, {0, 0, 0, 1}, {0, 0, 0, 1},
                          i == 0 ? S.nu : 1.0));
+      if (inv && i + 1 < S.L)  // merged form C_l = Psi_l Y_l
+        sc.push_back(ScaleDesc{c_cores[i], c_cores[i], S.cC[i] * S.dd, S.cC[i + 1], S.cC[i + 1],
+                               S.cC[i + 1], nullptr, S.Yv[i + 1], 0, 1});
     }
     add_perm(P, ds, "export");
+    long long mx = 1;
+    for (auto& d : sc) mx = std::max(mx, (long long)d.n * d.r);
+    add_simple(P, LK::Scale, sc, mx, "export");
     const size_t keep = X.arena_used;
     upload(X, P);
     run_program(P, X.stream, nullptr);
