@@ -25,6 +25,12 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks
 PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "bf16x3": 2.5e15, "fp64": 78.6e12}
 HBM_PEAK = 8.0e12
+# kernel classes timed by the library's profiling mode, and the kernel each
+# one launches (its name in a rocprofv3 kernel trace)
+MFMA_CLASSES = ("theta", "env_update", "env_ext1", "env_ext2", "sketch", "project")
+KERNEL_OF_CLASS = {"qr_chol_inv": "chol_inv_reg_kernel<5>", "eig_tridiag": "sytrd_reg_kernel<5>",
+                   "eig_bisect": "bisect_kernel", "eig_vectors": "twisted_kernel",
+                   "theta": "gemm_kernel<Mode::F32, float, float, float, true, true, 0|1>"}
 WORKLOAD = dict(L=40, d=2, chi=64, chi_c=128, p=16, seed=0)
 
 
@@ -160,7 +166,7 @@ def main():
 
     # per-kernel-class device time from HIP events around each launch
     _, _, prof, _ = run_gpu(A, B, "fp32", w["p"], 2, args.warmup, profile=True)
-    prof = {k: v / 2 for k, v in prof.items()}  # ms per sweep
+    ms_per_class = {k: v[0] / 2 for k, v in prof.items()}  # ms per sweep
     others = {}
     if not args.quick:
         for prec, p, st in (("bf16x3", w["p"], args.steps), ("bf16", w["p"], args.steps),
@@ -194,28 +200,22 @@ def main():
         except MpoError as e:
             batched["even_odd_L64_chi128_fp32"] = {"error": str(e)}
 
-    # roofline of the dominant kernel class (per-launch average)
-    dom = max(prof, key=prof.get)
-    nb = w["L"] - 1
-    n = m = w["chi_c"] * w["d"] ** 2
-    K = w["chi"] ** 2
-    k = w["chi_c"] + w["p"]
-    per_launch_flops = {
-        "theta": 2.0 * n * m * K, "env_update": 2.0 * w["chi_c"] * K * n,
-        "eig": (4.0 / 3.0) * k ** 3 + 2.0 * k ** 3 + 4.0 * k * k,
-        "qr_chol": (2.0 / 3.0) * k ** 3, "sketch": 2.0 * n * m * k, "project": 2.0 * n * m * k,
-    }
-    launches_per_sweep = {"qr_chol": 3 * nb}
+    # roofline of the dominant kernel class: algorithmic flops credited to its
+    # launches / their average device time (HIP events around each launch)
+    dom = max(prof, key=lambda c: prof[c][0])
+    ms_dom, fl_dom, nl_dom = prof[dom]
     roof = None
-    if dom in per_launch_flops:
-        nl = launches_per_sweep.get(dom, nb)
-        avg_s = prof[dom] / nl * 1e-3
-        ach = per_launch_flops[dom] / avg_s
-        bound = "mfma" if dom in ("theta", "env_update", "sketch", "project") else "alu"
-        peak = PEAK["fp32"] if dom in ("theta", "env_update") else PEAK["fp64"]
-        roof = {"bound": bound, "kernel": dom, "achieved": round(ach / 1e12, 4), "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": round(ach / peak, 6), "traffic": None,
-                "avg_launch_us": round(avg_s * 1e6, 2)}
+    if fl_dom > 0 and nl_dom > 0:
+        avg_s = ms_dom / nl_dom * 1e-3
+        ach = fl_dom / nl_dom / avg_s
+        mfma = dom in MFMA_CLASSES
+        peak = PEAK["fp32"] if mfma else PEAK["fp64"]
+        roof = {"bound": "mfma" if mfma else "alu", "kernel_class": dom,
+                "kernel": KERNEL_OF_CLASS.get(dom, dom),
+                "achieved": round(ach / 1e12, 5), "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 7), "traffic": None,
+                "avg_launch_us": round(avg_s * 1e6, 2), "launches_per_sweep": nl_dom / 2,
+                "algorithmic_flops_per_launch": round(fl_dom / nl_dom)}
     line = {
         "metric": "fit sweeps/s + TFLOP/s (MFMA frac), L=40 chi=64 chi_C=128, mixed vs FP64",
         "value": round(value, 4), "unit": "sweeps/s", "n_gpus": 1, "steps": args.steps,
@@ -229,7 +229,8 @@ def main():
         "device_ms_per_sweep": round(dev_ms / args.steps, 4),
         "algorithmic_gflop_per_sweep": {"mfma": round(mf / 1e9, 3), "fp64_factorization": round(f64 / 1e9, 3)},
         "bond_dims_settled": got_dims == dims,
-        "kernel_ms_per_sweep": {kk: round(v, 4) for kk, v in sorted(prof.items(), key=lambda x: -x[1])},
+        "kernel_ms_per_sweep": {kk: round(v, 4) for kk, v in
+                                sorted(ms_per_class.items(), key=lambda x: -x[1])},
         "other_precisions": others,
         "batched_schedule": batched,
         "roofline": roof,

@@ -160,11 +160,15 @@ mpo_status mpo_contract_exact_check(const mpo_pair* pair, const mpo_tt* C, doubl
    between its first and last launch (HIP events on the context stream). */
 mpo_status mpo_fit_last_sweep_ms(const mpo_fit_ctx* ctx, double* ms);
 
-/* Per-kernel-class device time of the last mpo_fit_sweep call when the
-   context was created with profiling (opts.reserved[0] = 1): fills up to
-   `n` entries of ms[] and names[] (static strings) and writes the count. */
+/* Per-kernel-class figures of the last mpo_fit_sweep call when the context
+   was created with profiling (opts.reserved[0] = 1; launches then run eagerly,
+   each bracketed by HIP events on the context stream).  For up to `n` classes:
+   ms[] device time, flops[] algorithmic flops credited to the class,
+   launches[] launch count, all summed over that call's sweeps, and names[]
+   (strings owned by the context, valid until the next mpo_fit_sweep).  Any of
+   the arrays may be NULL; *count receives the number of classes. */
 mpo_status mpo_fit_profile(const mpo_fit_ctx* ctx, int32_t n, double* ms, const char** names,
-                           double* flops, int32_t* count);
+                           double* flops, int32_t* launches, int32_t* count);
 
 void mpo_fit_destroy(mpo_fit_ctx* ctx);
 

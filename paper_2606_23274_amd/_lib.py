@@ -69,7 +69,7 @@ def load() -> C.CDLL:
                                              C.c_void_p, C.c_size_t, C.c_void_p]
     lib.mpo_fit_last_sweep_ms.argtypes = [C.c_void_p, P(C.c_double)]
     lib.mpo_fit_profile.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_char_p),
-                                    P(C.c_double), P(C.c_int32)]
+                                    P(C.c_double), P(C.c_int32), P(C.c_int32)]
     lib.mpo_fit_destroy.argtypes = [C.c_void_p]
     lib.mpo_fit_destroy.restype = None
     for name in EXPORTS:

@@ -121,12 +121,16 @@ class FitContext:
         return [c.cpu().numpy() for c in self.export(pair)]
 
     def profile(self):
+        """Per kernel class of the last sweep() call (profiling contexts):
+        {class: (device ms, algorithmic flops, launches)}, summed over its sweeps."""
         n = C.c_int32()
-        _lib.check(self.lib.mpo_fit_profile(self.ctx, 0, None, None, None, C.byref(n)))
+        _lib.check(self.lib.mpo_fit_profile(self.ctx, 0, None, None, None, None, C.byref(n)))
         ms = (C.c_double * n.value)()
+        fl = (C.c_double * n.value)()
+        nl = (C.c_int32 * n.value)()
         names = (C.c_char_p * n.value)()
-        _lib.check(self.lib.mpo_fit_profile(self.ctx, n.value, ms, names, None, C.byref(n)))
-        return {names[i].decode(): ms[i] for i in range(n.value)}
+        _lib.check(self.lib.mpo_fit_profile(self.ctx, n.value, ms, names, fl, nl, C.byref(n)))
+        return {names[i].decode(): (ms[i], fl[i], nl[i]) for i in range(n.value)}
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -2,17 +2,20 @@
 //
 // Workgroup = 256 threads = 4 wave64s in a 2x2 grid; each wave owns a
 // (BM/2) x (BN/2) block of the tile made of 16x16 MFMA blocks.
-//   FP64: v_mfma_f64_16x16x4f64,  BK = 16 (4 MFMA k-steps)
-//   FP32: v_mfma_f32_16x16x4f32,  BK = 16
-//   BF16: v_mfma_f32_16x16x32_bf16, BK = 32, FP32 accumulation
+//   FP64: v_mfma_f64_16x16x4f64
+//   FP32: v_mfma_f32_16x16x4f32
+//   BF16: v_mfma_f32_16x16x32_bf16, FP32 accumulation
 //   BF16X3: each operand x = hi + lo with hi = bf16(x), lo = bf16(x - hi);
 //         three BF16 MFMAs per product (lo*hi + hi*lo + hi*hi), FP32 accumulation
 // Both operand tiles sit in LDS as [row][BK + pad] with K contiguous, so each
-// lane fetches its fragment with one wide LDS read.  Within a 16-wide K slab
-// lane group g = lane/16 feeds k = 4g + s to MFMA step s (a permutation of
-// the summation order that lets the 4 values be one vector read).  The LDS is
-// double-buffered: the global loads of slab t+1 are in flight while slab t is
-// multiplied.
+// lane fetches its fragment with one wide LDS read.  Within each 16-wide
+// (FP32/FP64) or 32-wide (BF16) sub-slab, lane group g = lane/16 feeds
+// k = 4g + s (k = 8g + s) to MFMA step s: a permutation of the summation order
+// that lets those values be one vector read.  The LDS is double-buffered: the
+// global loads of slab t+1 are in flight while slab t is multiplied.  The
+// slab depth BK is chosen so that one slab's MFMA work (about 2000 cycles per
+// wave) covers the latency of the next slab's global loads; the two LDS
+// buffers then take about 70 KB, two workgroups per CU.
 #include <tuple>
 
 #include "gemm.hpp"
@@ -32,24 +35,32 @@ template <> struct ModeT<Mode::F64> {
   using acc_t = double;
   using lds_t = double;
   using accv_t = doublex4;
-  static constexpr int BK = 16;
+  static constexpr int KSUB = 16;  // K per sub-slab (4 MFMA steps of 4)
   static constexpr int PAD = 2;
 };
 template <> struct ModeT<Mode::F32> {
   using acc_t = float;
   using lds_t = float;
   using accv_t = floatx4;
-  static constexpr int BK = 16;
+  static constexpr int KSUB = 16;
   static constexpr int PAD = 4;
 };
 template <> struct ModeT<Mode::BF16> {
   using acc_t = float;
   using lds_t = unsigned short;
   using accv_t = floatx4;
-  static constexpr int BK = 32;
+  static constexpr int KSUB = 32;  // one MFMA step
   static constexpr int PAD = 8;
 };
 template <> struct ModeT<Mode::BF16X3> : ModeT<Mode::BF16> {};
+
+// Slab depth per (mode, tile); must agree with gemm_bk() below.
+constexpr int slab_k(Mode m, int tile) {
+  return m == Mode::F64 ? 32
+         : m == Mode::F32 ? (tile == 1 ? 32 : 64)
+         : m == Mode::BF16 ? (tile == 1 ? 64 : 128)
+                           : (tile == 1 ? 32 : 64);
+}
 
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
@@ -184,7 +195,8 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
   using lds_t = typename MT::lds_t;
   using accv_t = typename MT::accv_t;
   constexpr int BM = TileShape<TILE>::BM, BN = TileShape<TILE>::BN;
-  constexpr int BK = MT::BK, LDL = BK + MT::PAD;
+  constexpr int BK = slab_k(MODE, TILE), LDL = BK + MT::PAD;
+  constexpr int NSUB = BK / MT::KSUB;
   constexpr int WM = BM / 2, WN = BN / 2;       // wave tile
   constexpr int FM = WM / 16, FN = WN / 16;     // MFMA blocks per wave
 
@@ -260,11 +272,13 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
       la.load(Ap, d.lda, rows_a, kbeg + (t + 1) * BK, kend, d.vec_a);
       lb.load(Bp, d.ldb, rows_b, kbeg + (t + 1) * BK, kend, d.vec_b);
     }
-    const lds_t* As = sA[0][cur];
-    const lds_t* Bs = sB[0][cur];
+#pragma unroll
+    for (int ks = 0; ks < NSUB; ++ks) {
+    const lds_t* As = sA[0][cur] + ks * MT::KSUB;
+    const lds_t* Bs = sB[0][cur] + ks * MT::KSUB;
     if constexpr (MODE == Mode::BF16X3) {
-      const lds_t* Al = sA[NLO - 1][cur];
-      const lds_t* Bl = sB[NLO - 1][cur];
+      const lds_t* Al = sA[NLO - 1][cur] + ks * MT::KSUB;
+      const lds_t* Bl = sB[NLO - 1][cur] + ks * MT::KSUB;
       bf16x8 af[FM], bfr[FN], afl[FM], bfl[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
@@ -323,6 +337,7 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s], bfr[j][s], acc[i][j], 0, 0, 0);
           }
     }
+    }  // sub-slab
     if (more) {
       la.template store<MODE>(sA[0][cur ^ 1], sA[NLO - 1][cur ^ 1], LDL, inv_sa);
       lb.template store<MODE>(sB[0][cur ^ 1], sB[NLO - 1][cur ^ 1], LDL, inv_sb);
@@ -436,7 +451,7 @@ void launch_types(const GemmKind& k, const GemmDesc* d, int n, int wgs, hipStrea
 
 int gemm_bm(int tile) { return tile == 1 ? 128 : 64; }
 int gemm_bn(int tile) { return tile == 1 ? 128 : 64; }
-int gemm_bk(Mode mode) { return (mode == Mode::BF16 || mode == Mode::BF16X3) ? 32 : 16; }
+int gemm_bk(Mode mode, int tile) { return slab_k(mode, mode == Mode::F64 ? 0 : tile); }
 size_t gemm_acc_bytes(Mode mode) { return mode == Mode::F64 ? 8 : 4; }
 
 void launch_gemm(const GemmKind& kind, const GemmDesc* d_descs, int n_desc, int total_wgs,

@@ -50,7 +50,7 @@ struct GemmKind {
 
 int gemm_bm(int tile);
 int gemm_bn(int tile);
-int gemm_bk(Mode mode);
+int gemm_bk(Mode mode, int tile);
 size_t gemm_acc_bytes(Mode mode);
 
 // Launches one grouped GEMM: `d_descs` is a device array of `n_desc`

@@ -441,11 +441,30 @@ __device__ __forceinline__ double row_reduce32(double v) {
   return v;
 }
 
+// 1/x and 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton
+// steps (about 1 ulp), a shorter dependency chain than the IEEE division.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
 // G = L L^T (Cholesky, L lower) then R^{-1} = (L^{-1})^T written row-major
 // (upper triangular, zeros below).  One barrier per step: the owners of
-// column jj publish it (double-buffered), then every thread forms the pivot
-// and updates its trailing entries; blocks entirely left of / above column
-// jj are skipped with uniform branches.
+// column jj (and, for the inverse, of row jj) publish it (double-buffered),
+// then every thread updates its trailing entries with masks folded into the
+// broadcast vectors; blocks outside the active region are skipped with
+// uniform branches.  The inverse X = L^{-1} overwrites L in place (row jj of
+// X only mixes columns <= jj, whose L entries are no longer needed), so one
+// register block holds the matrix.
 template <int NB>
 __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __restrict__ descs) {
   __shared__ double colb[2][32 * NB];
@@ -453,111 +472,102 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
   const CholDesc d = descs[blockIdx.x];
   const int k = d.k;
   const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
-  double a[NB][NB], x[NB][NB];
+  double a[NB][NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int r = tr + 32 * i, c = tc + 32 * j;
-      a[i][j] = (r < k && c < k) ? d.G[(long long)r * d.ldg + c] : 0.0;
-      x[i][j] = (r == c && r < k) ? 1.0 : 0.0;
+      a[i][j] = (r < k && c < k) ? d.G[(long long)r * d.ldg + c] : (r == c ? 1.0 : 0.0);
     }
   bool bad = false;
   // Cholesky: a(r, c) -= a(r, jj) a(c, jj) / a(jj, jj) on the trailing block;
-  // column jj of L is a(:, jj) / sqrt(a(jj, jj)).  The masks live in the
-  // broadcast vectors (zero at indices <= jj), so the update is a plain
-  // rank-1 FMA over the register block.
-  for (int jj = 0; jj < k; ++jj) {
-    const int jb = jj >> 5, jt = jj & 31, buf = jj & 1;
-    if (tc == jt) {
+  // column jj of L is a(:, jj) / sqrt(a(jj, jj)).  The loop over the column
+  // block JB is unrolled, so every register index below is a constant.
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
+  for (int JB = 0; JB < NB; ++JB) {
+    const int jend = min(k, 32 * JB + 32);
+    for (int jj = 32 * JB; jj < jend; ++jj) {
+      const int jt = jj & 31, buf = jj & 1;
+      if (tc == jt) {
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
-          if (j == jb) colb[buf][tr + 32 * i] = (tr + 32 * i >= jj) ? a[i][j] : 0.0;
-    }
-    __syncthreads();
-    const double djj = colb[buf][jj];
-    if (!(djj > 0.0) || !isfinite(djj)) bad = true;
-    const double invd = (djj > 0.0) ? 1.0 / djj : 0.0;
-    double cr[NB], cc[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int r = tr + 32 * i, c = tc + 32 * i;
-      cr[i] = (r > jj) ? colb[buf][r] * invd : 0.0;
-      cc[i] = (c > jj) ? colb[buf][c] : 0.0;
-    }
-    if (tc == jt) {  // finish column jj of L: scale by 1/sqrt(d)
-      const double invs = (djj > 0.0) ? 1.0 / sqrt(djj) : 0.0;
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-          if (j == jb && tr + 32 * i >= jj) a[i][j] *= invs;
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      if (i < jb) continue;  // uniform: rows < 32*jb <= jj
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < jb) continue;
-        a[i][j] -= cr[i] * cc[j];
+        for (int i = JB; i < NB; ++i) colb[buf][tr + 32 * i] = (tr + 32 * i >= jj) ? a[i][JB] : 0.0;
       }
+      __syncthreads();
+      const double djj = colb[buf][jj];
+      const bool ok = djj > 0.0 && djj < INFINITY;
+      if (!ok) bad = true;
+      const double invd = ok ? rcp_nr(djj) : 0.0;
+      double cr[NB], cc[NB];
+#pragma unroll
+      for (int i = JB; i < NB; ++i) {
+        const int r = tr + 32 * i, c = tc + 32 * i;
+        cr[i] = (r > jj) ? colb[buf][r] * invd : 0.0;
+        cc[i] = (c > jj) ? colb[buf][c] : 0.0;
+      }
+      if (tc == jt) {  // finish column jj of L: scale by 1/sqrt(d)
+        const double invs = ok ? rsq_nr(djj) : 0.0;
+#pragma unroll
+        for (int i = JB; i < NB; ++i)
+          if (tr + 32 * i >= jj) a[i][JB] *= invs;
+      }
+#pragma unroll
+      for (int i = JB; i < NB; ++i)
+#pragma unroll
+        for (int j = JB; j < NB; ++j) a[i][j] -= cr[i] * cc[j];
     }
   }
-  // X = L^{-1}: X(jj,:) /= L(jj,jj); X(r,:) -= L(r,jj) X(jj,:) for r > jj
-  for (int jj = 0; jj < k; ++jj) {
-    const int jb = jj >> 5, jt = jj & 31, buf = jj & 1;
-    if (tc == jt) {  // L(:, jj)
+  // In-place X = L^{-1}, row by row: X(jj, c) = X(jj, c) / L(jj, jj) for
+  // c < jj, X(jj, jj) = 1 / L(jj, jj); then for r > jj
+  // X(r, c) -= L(r, jj) X(jj, c) (c < jj) and X(r, jj) = -L(r, jj) X(jj, jj).
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
+  for (int JB = 0; JB < NB; ++JB) {
+    const int jend = min(k, 32 * JB + 32);
+    for (int jj = 32 * JB; jj < jend; ++jj) {
+      const int jt = jj & 31, buf = jj & 1;
+      if (tc == jt) {  // L(:, jj)
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
-          if (j == jb) colb[buf][tr + 32 * i] = (tr + 32 * i >= jj) ? a[i][j] : 0.0;
-    }
-    if (tr == jt) {  // row jj of X before the scaling
+        for (int i = JB; i < NB; ++i) colb[buf][tr + 32 * i] = (tr + 32 * i >= jj) ? a[i][JB] : 0.0;
+      }
+      if (tr == jt) {  // row jj of X (columns < jj; the rest masked)
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
-        if (i == jb) {
+        for (int j = 0; j <= JB; ++j) rowb[buf][tc + 32 * j] = (tc + 32 * j < jj) ? a[JB][j] : 0.0;
+      }
+      __syncthreads();
+      const double ljj = colb[buf][jj];
+      const double linv = ljj > 0.0 ? rcp_nr(ljj) : 0.0;
+      double l[NB], xr[NB];
 #pragma unroll
-          for (int j = 0; j < NB; ++j) rowb[buf][tc + 32 * j] = x[i][j];
+      for (int i = JB; i < NB; ++i) l[i] = (tr + 32 * i > jj) ? colb[buf][tr + 32 * i] : 0.0;
+#pragma unroll
+      for (int j = 0; j <= JB; ++j) xr[j] = rowb[buf][tc + 32 * j] * linv;  // zero at columns >= jj
+#pragma unroll
+      for (int i = JB; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j <= JB; ++j) a[i][j] -= l[i] * xr[j];
+      if (tr == jt) {  // row jj: scale the X part
+#pragma unroll
+        for (int j = 0; j <= JB; ++j)
+          if (tc + 32 * j < jj) a[JB][j] *= linv;
+      }
+      if (tc == jt) {  // column jj: X(jj, jj) and X(r, jj) for r > jj
+#pragma unroll
+        for (int i = JB; i < NB; ++i) {
+          const int r = tr + 32 * i;
+          if (r == jj) a[i][JB] = linv;
+          else if (r > jj) a[i][JB] = -l[i] * linv;
         }
-    }
-    __syncthreads();
-    const double linv = 1.0 / colb[buf][jj];
-    double l[NB], rw[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int r = tr + 32 * i;
-      l[i] = (r > jj && r < k) ? colb[buf][r] * linv : 0.0;
-      rw[i] = rowb[buf][tc + 32 * i];
-    }
-    if (tr == jt) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-        if (i == jb) {
-#pragma unroll
-          for (int j = 0; j < NB; ++j) x[i][j] *= linv;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      if (i < jb) continue;
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j > jb) continue;  // X(jj, c) = 0 for c > jj
-        x[i][j] -= l[i] * rw[j];
       }
     }
   }
   if (bad && d.flag) atomicOr(d.flag, FLAG_CHOL);
-  // R^{-1}(c, r) = X(r, c)
+  // R^{-1}(c, r) = X(r, c) for r >= c; zeros below the diagonal of R^{-1}
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int r = tr + 32 * i, c = tc + 32 * j;
-      if (r < k && c < k) d.R[(long long)c * d.ldr + r] = x[i][j];
+      if (r < k && c < k) d.R[(long long)c * d.ldr + r] = (r >= c) ? a[i][j] : 0.0;
     }
 }
 
@@ -567,8 +577,8 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
 // W.V (row-major k x k); d, e to W.d, W.e.
 template <int NB>
 __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restrict__ descs) {
-  __shared__ double vb[32 * NB], wb[32 * NB];
-  __shared__ double s_tau;
+  __shared__ double vb[2][32 * NB], wb[2][32 * NB];
+  __shared__ double s_taus[32 * NB];
   const EigDesc dd = descs[blockIdx.x];
   const int k = dd.k;
   EigWork W(dd.work, k, dd.r);
@@ -584,87 +594,92 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
       const int hi = r > c ? r : c, lo = r > c ? c : r;
       a[i][j] = (r < k && c < k) ? dd.H[(long long)hi * dd.ldh + lo] : 0.0;
     }
-  for (int jj = 0; jj + 2 < k; ++jj) {
-    const int jb = jj >> 5, jt = jj & 31;
-    if (tc == jt) {  // x = A(jj+1:, jj) into vb; the diagonal entry to d
+  // Step jj works on the trailing block (rows and columns > jj), which lies
+  // in register blocks >= JB = jj / 32; the JB loop is unrolled so register
+  // indices are constants.  vb / wb alternate between two buffers so that a
+  // step's last reads and the next step's first writes need no barrier.
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
+  for (int JB = 0; JB < NB; ++JB) {
+    const int jend = min(k - 2, 32 * JB + 32);
+    for (int jj = 32 * JB; jj < jend; ++jj) {
+      const int jt = jj & 31, buf = jj & 1;
+      double* v = vb[buf];
+      double* w = wb[buf];
+      if (tc == jt) {  // x = A(jj+1:, jj) into v; the diagonal entry to d
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
-          if (j == jb) {
-            const int r = tr + 32 * i;
-            vb[r] = (r > jj && r < k) ? a[i][j] : 0.0;
-            if (r == jj) W.d[jj] = a[i][j];
-          }
-    }
-    __syncthreads();
-    if (wave == 0) {  // norm, beta, tau and the scaled reflector v (v(jj+1) = 1)
-      double part = 0.0;
-      for (int r = jj + 2 + lane; r < k; r += 64) part += vb[r] * vb[r];
-      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-      const double alpha = vb[jj + 1];
-      double tau = 0.0, beta = alpha, scal = 0.0;
-      if (part > 0.0) {
-        beta = -copysign(sqrt(alpha * alpha + part), alpha);
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
+        for (int i = JB; i < NB; ++i) {
+          const int r = tr + 32 * i;
+          v[r] = (r > jj && r < k) ? a[i][JB] : 0.0;
+          if (r == jj) W.d[jj] = a[i][JB];
+        }
       }
-      for (int r = lane; r < 32 * NB; r += 64) {
-        double v = 0.0;
-        if (tau != 0.0) v = (r == jj + 1) ? 1.0 : (r > jj + 1 && r < k ? vb[r] * scal : 0.0);
-        vb[r] = v;
-        if (r < k) vstore[(long long)jj * k + r] = v;
-      }
-      if (lane == 0) {
-        W.e[jj] = beta;
-        W.tau[jj] = tau;
-        s_tau = tau;
-      }
-    }
-    __syncthreads();
-    const double tau = s_tau;
-    if (tau == 0.0) continue;  // uniform
-    // p = tau * A22 v on rows > jj (v vanishes on columns <= jj)
+      if (tc == 0 && JB > 0) {  // rows of earlier blocks stay zero in v and w
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      if (i < jb) {  // uniform: rows <= jj
-        if (tc == 0) wb[tr + 32 * i] = 0.0;
-        continue;
+        for (int i = 0; i < JB; ++i) { v[tr + 32 * i] = 0.0; w[tr + 32 * i] = 0.0; }
       }
-      double pr = 0.0;
+      __syncthreads();
+      if (wave == 0) {  // norm, beta, tau and the scaled reflector v (v(jj+1) = 1)
+        double part = 0.0;
+        for (int r = jj + 2 + lane; r < k; r += 64) part += v[r] * v[r];
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        const double alpha = v[jj + 1];
+        double tau = 0.0, beta = alpha, scal = 0.0;
+        if (part > 0.0) {
+          beta = -copysign(sqrt(alpha * alpha + part), alpha);
+          tau = (beta - alpha) / beta;
+          scal = 1.0 / (alpha - beta);
+        }
+        for (int r = 32 * JB + lane; r < 32 * NB; r += 64) {
+          double vr = 0.0;
+          if (tau != 0.0) vr = (r == jj + 1) ? 1.0 : (r > jj + 1 && r < k ? v[r] * scal : 0.0);
+          v[r] = vr;
+          if (r < k) vstore[(long long)jj * k + r] = vr;
+        }
+        for (int r = lane; r < 32 * JB && r < k; r += 64) vstore[(long long)jj * k + r] = 0.0;
+        if (lane == 0) {
+          W.e[jj] = beta;
+          W.tau[jj] = tau;
+          s_taus[jj] = tau;
+        }
+      }
+      __syncthreads();
+      const double tau = s_taus[jj];
+      if (tau == 0.0) continue;  // uniform
+      // p = tau * A22 v on rows > jj (v vanishes on rows and columns <= jj)
+      double vc[NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < jb) continue;
-        pr += a[i][j] * vb[tc + 32 * j];
+      for (int j = JB; j < NB; ++j) vc[j] = v[tc + 32 * j];
+#pragma unroll
+      for (int i = JB; i < NB; ++i) {
+        double pr = 0.0;
+#pragma unroll
+        for (int j = JB; j < NB; ++j) pr += a[i][j] * vc[j];
+        pr = row_reduce32<NB>(pr);
+        if (tc == 0) w[tr + 32 * i] = (tr + 32 * i > jj) ? tau * pr : 0.0;
       }
-      pr = row_reduce32<NB>(pr);
-      if (tc == 0) wb[tr + 32 * i] = (tr + 32 * i > jj) ? tau * pr : 0.0;
-    }
-    __syncthreads();
-    if (wave == 0) {  // w = p - (tau/2)(p.v) v
+      __syncthreads();
+      // w = p - (tau/2)(p.v) v: every thread forms p.v from the trailing rows
+      // (its wave's half-rows reduce the products; the halves meet in LDS)
       double pv = 0.0;
-      for (int r = lane; r < 32 * NB; r += 64) pv += wb[r] * vb[r];
-      for (int off = 32; off > 0; off >>= 1) pv += __shfl_xor(pv, off);
+#pragma unroll
+      for (int i = JB; i < NB; ++i) {
+        const int r = tc + 32 * i;
+        pv += w[r] * v[r];
+      }
+      pv = row_reduce32<NB>(pv);
       const double K = -0.5 * tau * pv;
-      for (int r = lane; r < 32 * NB; r += 64) wb[r] += K * vb[r];
-    }
-    __syncthreads();
-    // A22 -= v w^T + w v^T (trailing block only; v, w vanish at <= jj)
-    double vc[NB], wc[NB];
+      // A22 -= v w^T + w v^T with w = p + K v (trailing block only)
+      double wc[NB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) { vc[j] = vb[tc + 32 * j]; wc[j] = wb[tc + 32 * j]; }
+      for (int j = JB; j < NB; ++j) wc[j] = w[tc + 32 * j] + K * vc[j];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      if (i < jb) continue;  // uniform
-      const int r = tr + 32 * i;
-      const double vi = vb[r], wi = wb[r];
+      for (int i = JB; i < NB; ++i) {
+        const int r = tr + 32 * i;
+        const double vi = v[r], wi = w[r] + K * vi;
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < jb) continue;
-        a[i][j] -= vi * wc[j] + wi * vc[j];
+        for (int j = JB; j < NB; ++j) a[i][j] -= vi * wc[j] + wi * vc[j];
       }
     }
-    __syncthreads();
   }
   if (k >= 2) {
     const int r0 = k - 2, r1 = k - 1;
@@ -683,7 +698,10 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
   }
   __threadfence_block();
   __syncthreads();
-  // Q^T = H_{k-3} ... H_0: M <- M H_j = M - tau_j (M v_j) v_j^T for j = k-3 .. 0
+  // Q^T = H_{k-3} ... H_0: M <- M H_j = M - tau_j (M v_j) v_j^T for j = k-3 .. 0.
+  // v_j vanishes on columns <= j, i.e. below register block JB = (j + 1) / 32,
+  // and rows <= j of M = H_{k-3} ... H_{j+1} are rows of the identity, so
+  // (M v_j) vanishes there too: only register blocks >= JB take part.
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
@@ -691,39 +709,44 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
   double vnext = 0.0;
   if (k >= 3 && threadIdx.x < 32 * NB)
     vnext = threadIdx.x < k ? vstore[(long long)(k - 3) * k + threadIdx.x] : 0.0;
-  for (int jj = k - 3; jj >= 0; --jj) {
-    const double tau = W.tau[jj];
-    if (threadIdx.x < 32 * NB) vb[threadIdx.x] = vnext;
-    if (jj > 0 && threadIdx.x < 32 * NB)  // prefetch the next reflector
-      vnext = threadIdx.x < k ? vstore[(long long)(jj - 1) * k + threadIdx.x] : 0.0;
-    __syncthreads();
-    const int jb = (jj + 1) >> 5;  // v_jj vanishes below column jj+1
-    if (tau != 0.0) {  // uniform
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        double pr = 0.0;
+  for (int JB = NB - 1; JB >= 0; --JB) {
+    const int jhi = min(k - 3, 32 * JB + 30), jlo = max(0, 32 * JB - 1);
+    for (int jj = jhi; jj >= jlo; --jj) {
+      const int buf = jj & 1;
+      const double tau = s_taus[jj];
+      double* v = vb[buf];
+      double* w = wb[buf];
+      if (threadIdx.x < 32 * NB) v[threadIdx.x] = vnext;
+      if (jj > 0 && threadIdx.x < 32 * NB)  // prefetch the next reflector
+        vnext = threadIdx.x < k ? vstore[(long long)(jj - 1) * k + threadIdx.x] : 0.0;
+      __syncthreads();
+      if (tau != 0.0) {  // uniform
+        double vc[NB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          if (j < jb) continue;
-          pr += a[i][j] * vb[tc + 32 * j];
-        }
-        pr = row_reduce32<NB>(pr);
-        if (tc == 0) wb[tr + 32 * i] = tau * pr;
-      }
-    }
-    __syncthreads();
-    if (tau != 0.0) {
+        for (int j = JB; j < NB; ++j) vc[j] = v[tc + 32 * j];
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const double wi = wb[tr + 32 * i];
+        for (int i = JB; i < NB; ++i) {
+          double pr = 0.0;
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          if (j < jb) continue;
-          a[i][j] -= wi * vb[tc + 32 * j];
+          for (int j = JB; j < NB; ++j) pr += a[i][j] * vc[j];
+          pr = row_reduce32<NB>(pr);
+          if (tc == 0) w[tr + 32 * i] = tau * pr;
         }
       }
+      __syncthreads();
+      if (tau != 0.0) {
+        double vc[NB];
+#pragma unroll
+        for (int j = JB; j < NB; ++j) vc[j] = v[tc + 32 * j];
+#pragma unroll
+        for (int i = JB; i < NB; ++i) {
+          const double wi = w[tr + 32 * i];
+#pragma unroll
+          for (int j = JB; j < NB; ++j) a[i][j] -= wi * vc[j];
+        }
+      }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i)
@@ -762,26 +785,32 @@ void launch_trsm(const TrsmDesc* d, int n, int max_rows, hipStream_t s) {
   hipLaunchKernelGGL(trsm_kernel<8>, grid, dim3(kBig), 0, s, d);
 }
 
-void launch_eig(const EigDesc* d, const EigDesc* h, int n, int reg, hipStream_t s) {
+void launch_eig(const EigDesc* d, const EigDesc* h, int n, int reg, int stage, hipStream_t s) {
   if (n <= 0) return;
   int max_k = 0, max_r = 0;
   for (int i = 0; i < n; ++i) {
     max_k = std::max(max_k, h[i].k);
     max_r = std::max(max_r, h[i].r);
   }
-  if (reg) {
-    hipLaunchKernelGGL(sytrd_reg_kernel<kRegNB>, dim3(n), dim3(kBig), 0, s, d);
-  } else {
-    const int kp = std::min(max_k, kPackedMax);
-    const size_t lds1 = (2 * (size_t)max_k + (size_t)kp * (kp + 1) / 2) * sizeof(double);
-    hipLaunchKernelGGL(sytrd_kernel, dim3(n), dim3(kBig), lds1, s, d);
+  const bool all = stage < 0;
+  if (all || stage == 0) {
+    if (reg) {
+      hipLaunchKernelGGL(sytrd_reg_kernel<kRegNB>, dim3(n), dim3(kBig), 0, s, d);
+    } else {
+      const int kp = std::min(max_k, kPackedMax);
+      const size_t lds1 = (2 * (size_t)max_k + (size_t)kp * (kp + 1) / 2) * sizeof(double);
+      hipLaunchKernelGGL(sytrd_kernel, dim3(n), dim3(kBig), lds1, s, d);
+    }
   }
-  hipLaunchKernelGGL(bisect_kernel, dim3(max_r, n), dim3(kBisect), 2 * max_k * sizeof(double), s, d);
-  int T = 64;
-  while (T > 1 && (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double) > 150 * 1024) T /= 2;
-  hipLaunchKernelGGL(twisted_kernel, dim3(ceil_div(max_r, T), n), dim3(T),
-                     (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double), s, d);
-  if (reg) return;
+  if (all || stage == 1)
+    hipLaunchKernelGGL(bisect_kernel, dim3(max_r, n), dim3(kBisect), 2 * max_k * sizeof(double), s, d);
+  if (all || stage == 2) {
+    int T = 64;
+    while (T > 1 && (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double) > 150 * 1024) T /= 2;
+    hipLaunchKernelGGL(twisted_kernel, dim3(ceil_div(max_r, T), n), dim3(T),
+                       (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double), s, d);
+  }
+  if (reg || !(all || stage == 3)) return;
   // column blocks so that the block plus vectors fit in LDS
   int rb = std::max(1, std::min(max_r, (int)(120 * 1024 / sizeof(double) / max_k)));
   rb = std::min(rb, kBig);

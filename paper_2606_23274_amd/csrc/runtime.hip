@@ -40,7 +40,7 @@ void run_program(const Program& p, hipStream_t s, hipEvent_t* ev) {
       case LK::Gemm: launch_gemm(l.gk, p.device<GemmDesc>(l), l.n, (int)l.wgs, s); break;
       case LK::Chol: launch_chol(p.device<CholDesc>(l), l.n, (int)l.maxa, l.maxb, s); break;
       case LK::Trsm: launch_trsm(p.device<TrsmDesc>(l), l.n, (int)l.maxa, s); break;
-      case LK::Eig: launch_eig(p.device<EigDesc>(l), p.host<EigDesc>(l), l.n, l.maxb, s); break;
+      case LK::Eig: launch_eig(p.device<EigDesc>(l), p.host<EigDesc>(l), l.n, l.maxb, (int)l.maxa, s); break;
       case LK::Omega: launch_omega(p.device<OmegaDesc>(l), l.n, (int)l.maxa, s); break;
       case LK::Sign: launch_signfix(p.device<SignDesc>(l), l.n, (int)l.maxa, s); break;
       case LK::Scale: launch_scale(p.device<ScaleDesc>(l), l.n, (int)l.maxa, s); break;
@@ -141,7 +141,7 @@ void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<
     }
     if (big && w128 >= 256) gk.tile = 1;
   }
-  const int BM = gemm_bm(gk.tile), BN = gemm_bn(gk.tile), BK = gemm_bk(mode);
+  const int BM = gemm_bm(gk.tile), BN = gemm_bn(gk.tile), BK = gemm_bk(mode, gk.tile);
   long long base_wgs = 0;
   for (auto& j : jobs)
     base_wgs += (long long)ceil_div(j.M, BM) * ceil_div(j.N, BN) * j.nb[0] * j.nb[1] * j.nb[2];
@@ -214,6 +214,29 @@ void add_simple(Program& P, LK kind, const std::vector<D>& ds, long long maxa, c
   P.launches.push_back(l);
 }
 
+// The eigen pipeline as one launch per stage (tridiagonalization, bisection,
+// eigenvectors, back-transformation) over one descriptor array, so that each
+// stage is timed on its own.  Tridiagonalization is credited (4/3) k^3 flops.
+void add_eig(Program& P, const std::vector<EigDesc>& ed, bool reg, const char* prefix) {
+  if (ed.empty()) return;
+  const size_t off = P.push(ed);
+  double ftri = 0;
+  for (auto& e : ed) ftri += (4.0 / 3.0) * e.k * (double)e.k * e.k;
+  const bool init = std::string(prefix) == "init";
+  const char* names[4] = {"eig_tridiag", "eig_bisect", "eig_vectors", "eig_backtransform"};
+  for (int st = 0; st < (reg ? 3 : 4); ++st) {
+    Launch l;
+    l.kind = LK::Eig;
+    l.off = off;
+    l.n = (int)ed.size();
+    l.maxb = reg ? 1 : 0;
+    l.maxa = st;
+    l.cls = init ? "init" : names[st];
+    l.flops = st == 0 ? ftri : 0;
+    P.launches.push_back(l);
+  }
+}
+
 // ------------------------------------------------------------------ state
 struct PairState {
   int L = 0, d = 0, dd = 0;
@@ -270,7 +293,12 @@ struct Ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0;
   bool profile = false;
-  std::vector<std::pair<std::string, double>> prof_ms;
+  struct ProfEntry {
+    std::string cls;
+    double ms = 0, flops = 0;
+    int launches = 0;
+  };
+  std::vector<ProfEntry> prof;  // per kernel class, summed over the last call's sweeps
   std::vector<double> prof_flops;
   size_t ws_bytes = 0;
 };
@@ -428,7 +456,8 @@ void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int pass
     l.n = (int)cd.size();
     l.maxa = maxk;
     l.maxb = fast ? 1 : 0;
-    l.cls = "qr_chol";
+    l.cls = fast ? "qr_chol_inv" : "qr_chol";
+    for (auto& j : jobs) l.flops += (fast ? 2.0 : 1.0) / 3.0 * j.k * (double)j.k * j.k;
     P.launches.push_back(l);
     if (fast) add_gemm(P, X.sb, Mode::F64, tj, "qr_apply", 0);
     else add_simple(P, LK::Trsm, td, maxn, "qr_trsm");
@@ -712,6 +741,7 @@ struct BondJob {
   BondScratch* B;
   int n, m, k, r;
   bool sketch;
+  bool tr = false;  // plain SVD from the m x m Gram Theta^T Theta (m < n)
 };
 
 BondJob make_bond(Ctx& X, PairState& P, int pair, int i, bool fwd, BondScratch& B) {
@@ -725,6 +755,7 @@ BondJob make_bond(Ctx& X, PairState& P, int pair, int i, bool fwd, BondScratch& 
   if (b.sketch) b.k = std::min(P.chi_max + X.o.sketch_p, kmax);
   else b.k = b.n;
   if (b.sketch && b.k >= std::min(b.n, b.m)) { b.sketch = false; b.k = b.n; }
+  if (!b.sketch && b.m < b.n) { b.tr = true; b.k = b.m; }
   return b;
 }
 
@@ -765,6 +796,9 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
                            out64(B.Bk, b.m)});
       hj.push_back(GemmJob{b.k, b.k, b.m, op64(B.Bk, true, b.m), op64(B.Bk, true, b.m), out64(B.H, b.k)});
       fsk += 4.0 * b.n * b.m * b.k;
+    } else if (b.tr) {  // eigenvectors of Theta^T Theta are V
+      hj.push_back(GemmJob{b.m, b.m, b.n, opW(X, B.theta, false, b.m), opW(X, B.theta, false, b.m),
+                           out64(B.H, b.m)});
     } else {
       hj.push_back(GemmJob{b.n, b.n, b.m, opW(X, B.theta, true, b.m), opW(X, B.theta, true, b.m),
                            out64(B.H, b.n)});
@@ -788,15 +822,7 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
   add_gemm(P, X.sb, Mode::F64, hw, "gram", 0);
   const bool reg = zq.size() == ed.size();
   if (!reg) zq.clear();
-  {
-    Launch l;
-    l.kind = LK::Eig;
-    l.off = P.push(ed);
-    l.n = (int)ed.size();
-    l.maxb = reg ? 1 : 0;
-    l.cls = "eig";
-    P.launches.push_back(l);
-  }
+  add_eig(P, ed, reg, "eig");
   add_gemm(P, X.sb, Mode::F64, zq, "eig_backtransform", 0);
   add_simple(P, LK::Sval, sv, maxr, "svals");
 }
@@ -807,11 +833,11 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
 //   backward: V = orth(Bk^T Z S^-1) -> C_{i+1} = V^T;  C_i = Q Z S;  R_{i+1} = V^T XR
 // with the sign rule applied to the columns of U (or of C_i = U S).
 void rec_assign_site(Ctx& X, Program& P, std::vector<BondJob>& bj) {
-  std::vector<GemmJob> uq, svt, envg, vj;
-  std::vector<PermDesc> cp, perm;
+  std::vector<GemmJob> uq, tq, svt, envg, vj;
+  std::vector<PermDesc> cp, cpv, perm;
   std::vector<CholQRJob> orth;
   std::vector<SignDesc> sg;
-  std::vector<ScaleDesc> sc1, sc2, sc3;
+  std::vector<ScaleDesc> sc0, sc1, sc2, sc3;
   double fenv = 0;
   int maxr = 1;
   long long maxsc = 1;
@@ -823,12 +849,15 @@ void rec_assign_site(Ctx& X, Program& P, std::vector<BondJob>& bj) {
     const int N = S.cA[i + 1] * S.cB[i + 1];
     double* Ci = S.C64[i];
     double* Cn = S.C64[i + 1];
-    // C_i <- Q Z (or Z)
+    // C_i <- Q Z (or Z); with the m-side Gram C_i <- Theta V (= U S)
     if (b.sketch)
       uq.push_back(GemmJob{b.n, r, b.k, op64(B.Y, true, b.k), op64(B.Z, false, r), out64(Ci, r)});
+    else if (b.tr)
+      tq.push_back(GemmJob{b.n, r, b.m, opW(X, B.theta, true, b.m), op64(B.Z, false, r), out64(Ci, r)});
     else
       cp.push_back(perm4(B.Z, 0, Ci, 0, {1, 1, b.n, r}, {0, 0, r, 1}, {0, 0, r, 1}));
     maxr = std::max(maxr, r);
+    if (fwd && b.tr) sc0.push_back(ScaleDesc{Ci, Ci, b.n, r, r, r, nullptr, B.S, 0, 1});
     if (fwd) {
       orth.push_back(CholQRJob{Ci, b.n, r, r, B.G, B.R, nullptr, B.Y2});
       sg.push_back(SignDesc{Ci, b.n, r, r, B.sign, nullptr});
@@ -840,14 +869,19 @@ void rec_assign_site(Ctx& X, Program& P, std::vector<BondJob>& bj) {
                              outW(X, S.Lenv[i + 1], N, S.amL[i + 1])});
       fenv += 2.0 * r * N * b.n;
     } else {
-      // V = Bk^T Z / S  (Bk = Theta without the sketch)
-      if (b.sketch)
-        vj.push_back(GemmJob{b.m, r, b.k, op64(B.Bk, false, b.m), op64(B.Z, false, r), out64(B.V, r)});
-      else
-        vj.push_back(GemmJob{b.m, r, b.n, opW(X, B.theta, false, b.m), op64(B.Z, false, r), out64(B.V, r)});
-      sc1.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 1});
-      orth.push_back(CholQRJob{B.V, b.m, r, r, B.G, B.R, nullptr, B.Y2});
-      sc2.push_back(ScaleDesc{Ci, Ci, b.n, r, r, r, nullptr, B.S, 0, 0});  // C_i = U S
+      // V = Bk^T Z / S  (Bk = Theta without the sketch); V = Z from the m-side Gram
+      if (b.tr) {
+        cpv.push_back(perm4(B.Z, 0, B.V, 0, {1, 1, b.m, r}, {0, 0, r, 1}, {0, 0, r, 1}));
+      } else {
+        if (b.sketch)
+          vj.push_back(GemmJob{b.m, r, b.k, op64(B.Bk, false, b.m), op64(B.Z, false, r), out64(B.V, r)});
+        else
+          vj.push_back(GemmJob{b.m, r, b.n, opW(X, B.theta, false, b.m), op64(B.Z, false, r),
+                               out64(B.V, r)});
+        sc1.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 1});
+        orth.push_back(CholQRJob{B.V, b.m, r, r, B.G, B.R, nullptr, B.Y2});
+        sc2.push_back(ScaleDesc{Ci, Ci, b.n, r, r, r, nullptr, B.S, 0, 0});  // C_i = U S
+      }
       sg.push_back(SignDesc{Ci, b.n, r, r, B.sign, nullptr});
       sc3.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.sign, 0, 0});
       // C_{i+1}[c'][su][c''] = V[(c'', su)][c']
@@ -861,14 +895,17 @@ void rec_assign_site(Ctx& X, Program& P, std::vector<BondJob>& bj) {
     (void)cl;
   }
   add_gemm(P, X.sb, Mode::F64, uq, "assemble", 0);
+  add_gemm(P, X.sb, Mode::F64, tq, "assemble", 0);
   add_perm(P, cp, "copy");
   if (fwd) {
+    add_simple(P, LK::Scale, sc0, maxsc, "scale");
     add_cholqr(X, P, orth, 1);
     add_simple(P, LK::Sign, sg, maxr, "sign");
     add_gemm(P, X.sb, Mode::F64, svt, "assemble", 0);
     add_perm(P, perm, "copy");
   } else {
     add_gemm(P, X.sb, Mode::F64, vj, "assemble", 0);
+    add_perm(P, cpv, "copy");
     add_simple(P, LK::Scale, sc1, maxsc, "scale");
     add_cholqr(X, P, orth, 1);
     add_simple(P, LK::Scale, sc2, maxsc, "scale");
@@ -922,15 +959,7 @@ void rec_inverse_canonical(Ctx& X, Program& P, PairState& S) {
     add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, p, op64(Xi, false, q), op64(Xi, false, q), out64(B.H, q)}},
              "init", 0);
     const bool reg = q <= kRegMax;
-    {
-      Launch l;
-      l.kind = LK::Eig;
-      l.off = P.push(std::vector<EigDesc>{EigDesc{B.H, q, q, q, B.evals, B.Z, q, B.eigw, X.flag}});
-      l.n = 1;
-      l.maxb = reg ? 1 : 0;
-      l.cls = "init";
-      P.launches.push_back(l);
-    }
+    add_eig(P, {EigDesc{B.H, q, q, q, B.evals, B.Z, q, B.eigw, X.flag}}, reg, "init");
     if (reg)
       add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(eig_work_qt(B.eigw, q, q), false, q),
                                             op64(eig_work_x(B.eigw, q, q), false, q), out64(B.Z, q)}},
@@ -996,13 +1025,21 @@ void rec_assign_inverse(Ctx& X, Program& P, std::vector<BondJob>& bj) {
     double* Cn = S.C64[i + 1];
     if (b.sketch)
       uq.push_back(GemmJob{b.n, r, b.k, op64(B.Y, true, b.k), op64(B.Z, false, r), out64(Ci, r)});
+    else if (b.tr)
+      uq.push_back(GemmJob{b.n, r, b.m, opW(X, B.theta, true, b.m), op64(B.Z, false, r), out64(Ci, r)});
     else
       cp.push_back(perm4(B.Z, 0, Ci, 0, {1, 1, b.n, r}, {0, 0, r, 1}, {0, 0, r, 1}));
-    if (b.sketch)
-      vj.push_back(GemmJob{b.m, r, b.k, op64(B.Bk, false, b.m), op64(B.Z, false, r), out64(B.V, r)});
-    else
-      vj.push_back(GemmJob{b.m, r, b.n, opW(X, B.theta, false, b.m), op64(B.Z, false, r), out64(B.V, r)});
-    sv1.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 1});
+    if (b.tr) {  // V = Z, U = Theta V / S
+      cp.push_back(perm4(B.Z, 0, B.V, 0, {1, 1, b.m, r}, {0, 0, r, 1}, {0, 0, r, 1}));
+      sv1.push_back(ScaleDesc{Ci, Ci, b.n, r, r, r, nullptr, B.S, 0, 1});
+    } else {
+      if (b.sketch)
+        vj.push_back(GemmJob{b.m, r, b.k, op64(B.Bk, false, b.m), op64(B.Z, false, r), out64(B.V, r)});
+      else
+        vj.push_back(GemmJob{b.m, r, b.n, opW(X, B.theta, false, b.m), op64(B.Z, false, r),
+                             out64(B.V, r)});
+      sv1.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 1});
+    }
     orthU.push_back(CholQRJob{Ci, b.n, r, r, B.G, B.R, nullptr, r <= kRegMax ? B.Y2 : nullptr});
     // runs after orthU in stream order, so it reuses the same G and R scratch
     orthV.push_back(CholQRJob{B.V, b.m, r, r, B.G, B.R, nullptr, r <= kRegMax ? B.SVt : nullptr});
@@ -1322,7 +1359,7 @@ mpo_status mpo_fit_sweep(mpo_fit_ctx* ctx, int32_t n_sweeps) {
     if (!ctx || n_sweeps < 0) throw Error{MPO_ERR_INVALID_ARG, "null ctx or negative sweeps"};
     Ctx& X = ctx->X;
     HIP_OK(hipEventRecord(X.ev0, X.stream));
-    X.prof_ms.clear();
+    X.prof.clear();
     for (int s = 0; s < n_sweeps; ++s) {
       const bool fwd = X.sweeps_done % 2 == 0;
       const std::string key = shape_key(X, fwd ? "F" : "B");
@@ -1347,13 +1384,20 @@ mpo_status mpo_fit_sweep(mpo_fit_ctx* ctx, int32_t n_sweeps) {
         }
         run_program(sp.prog, X.stream, ev.data());
         HIP_OK(hipEventSynchronize(ev[sp.prog.launches.size()]));
-        std::map<std::string, double> acc;
         for (size_t li = 0; li < sp.prog.launches.size(); ++li) {
           float ms = 0;
           HIP_OK(hipEventElapsedTime(&ms, ev[li], ev[li + 1]));
-          acc[sp.prog.launches[li].cls] += ms;
+          const Launch& l = sp.prog.launches[li];
+          auto pe = std::find_if(X.prof.begin(), X.prof.end(),
+                                 [&](const Ctx::ProfEntry& e) { return e.cls == l.cls; });
+          if (pe == X.prof.end()) {
+            X.prof.push_back(Ctx::ProfEntry{l.cls});
+            pe = X.prof.end() - 1;
+          }
+          pe->ms += ms;
+          pe->flops += l.flops;
+          pe->launches += 1;
         }
-        for (auto& kv : acc) X.prof_ms.push_back(kv);
       } else if (X.o.capture_graph && X.stream != nullptr && (sp.stable || sp.uses >= 1)) {
         if (!sp.graph) {
           hipGraph_t g = nullptr;
@@ -1440,15 +1484,16 @@ mpo_status mpo_fit_last_sweep_ms(const mpo_fit_ctx* ctx, double* ms) {
 }
 
 mpo_status mpo_fit_profile(const mpo_fit_ctx* ctx, int32_t n, double* ms, const char** names,
-                           double* flops, int32_t* count) {
+                           double* flops, int32_t* launches, int32_t* count) {
   return guarded([&] {
     if (!ctx || !count) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
-    const auto& pm = ctx->X.prof_ms;
+    const auto& pm = ctx->X.prof;
     *count = (int)pm.size();
     for (int i = 0; i < n && i < (int)pm.size(); ++i) {
-      if (ms) ms[i] = pm[i].second;
-      if (names) names[i] = pm[i].first.c_str();
-      if (flops) flops[i] = 0;
+      if (ms) ms[i] = pm[i].ms;
+      if (names) names[i] = pm[i].cls.c_str();
+      if (flops) flops[i] = pm[i].flops;
+      if (launches) launches[i] = pm[i].launches;
     }
   });
 }
@@ -1526,7 +1571,7 @@ mpo_status mpo_test_gemm(int mode, int ta, int tb, int tc, int a_kcontig, int b_
     Program P;
     const Mode md = (Mode)mode;
     GemmKind gk{md, (DType)ta, (DType)tb, (DType)tc, a_kcontig != 0, b_kcontig != 0, tile};
-    const int BM = gemm_bm(tile), BN = gemm_bn(tile), BK = gemm_bk(md);
+    const int BM = gemm_bm(tile), BN = gemm_bn(tile), BK = gemm_bk(md, tile);
     GemmDesc d{};
     d.A = A; d.B = B; d.C = Cm; d.M = M; d.N = N; d.K = K; d.lda = lda; d.ldb = ldb; d.ldc = ldc;
     d.nb[0] = d.nb[1] = d.nb[2] = 1;
@@ -1563,13 +1608,7 @@ mpo_status mpo_test_eig(const double* H, int k, int r, double* evals, double* Z,
     if (T.cv.off > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "test workspace too small"};
     Program P;
     const bool reg = k <= kRegMax;
-    Launch l;
-    l.kind = LK::Eig;
-    l.off = P.push(std::vector<EigDesc>{EigDesc{H, k, k, r, evals, Z, r, w, T.X.flag}});
-    l.n = 1;
-    l.maxb = reg ? 1 : 0;
-    l.cls = "eig";
-    P.launches.push_back(l);
+    add_eig(P, {EigDesc{H, k, k, r, evals, Z, r, w, T.X.flag}}, reg, "eig");
     if (reg)
       add_gemm(P, T.X.sb, Mode::F64, {GemmJob{k, r, k, op64(eig_work_qt(w, k, r), false, k),
                                               op64(eig_work_x(w, k, r), false, r), out64(Z, r)}},

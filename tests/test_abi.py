@@ -1,0 +1,121 @@
+"""The C-ABI library on the host: it loads, exports every function the public
+headers declare, and rejects bad arguments with the documented status codes
+(mpo_fit_workspace_bytes does all its validation on the host, so these run
+without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+lib_mod = pytest.importorskip("paper_2606_23274_amd._lib")
+
+
+def _lib():
+    if not os.path.exists(lib_mod.LIB_PATH):
+        pytest.skip("libmpofit.so not built")
+    return lib_mod.load()
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^(?:mpo_status|void|const char\*)\s+(mpo_\w+)\s*\(", text, re.M)))
+
+
+@pytest.mark.parametrize("header", sorted(h for h in os.listdir(os.path.join(ROOT, "include"))
+                                          if h.endswith(".h")))
+def test_exports_every_declared_symbol(header):
+    lib = _lib()
+    names = _declared(header)
+    assert names, header
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_public_header():
+    assert set(_declared("mpofit.h")) == set(lib_mod.EXPORTS)
+
+
+class _Pair:
+    """Host-side descriptors with placeholder (never dereferenced) core
+    pointers: the workspace query validates shapes and options only."""
+
+    def __init__(self, L=6, d=2, chi_a=4, chi_b=4, chi_max=0):
+        self.keep = []
+        self.pair = lib_mod.MpoPair(self._tt(L, d, chi_a), self._tt(L, d, chi_b), chi_max)
+
+    def _tt(self, L, d, chi):
+        dims = [1] + [chi] * (L - 1) + [1]
+        chi_arr = (C.c_int32 * (L + 1))(*dims)
+        cores = (C.c_void_p * L)(*([0x1000] * L))
+        self.keep += [chi_arr, cores]
+        return lib_mod.MpoTT(L, d, chi_arr, cores)
+
+
+def _opts(**kw):
+    o = lib_mod.MpoFitOpts()
+    o.chi_max, o.tau, o.precision, o.schedule, o.sketch_p, o.seed = 8, 0.0, 1, 0, 4, 0
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _query(pairs, opts, n=None):
+    lib = _lib()
+    arr = (lib_mod.MpoPair * len(pairs))(*[p.pair for p in pairs])
+    nbytes = C.c_size_t(0)
+    st = lib.mpo_fit_workspace_bytes(arr, len(pairs) if n is None else n, C.byref(opts),
+                                     C.byref(nbytes))
+    return st, nbytes.value
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2, 3])
+def test_workspace_query_ok(schedule, precision):
+    st, n = _query([_Pair()], _opts(schedule=schedule, precision=precision))
+    assert st == 0 and n > 0 and n % 256 == 0
+
+
+def test_workspace_grows_with_pairs_and_bond():
+    _, one = _query([_Pair()], _opts())
+    _, two = _query([_Pair(), _Pair()], _opts())
+    _, big = _query([_Pair(chi_a=16, chi_b=16)], _opts(chi_max=32))
+    assert two > one and big > one
+
+
+@pytest.mark.parametrize("opts, status", [
+    (dict(tau=1e-3), 6),            # tau > 0 is not run
+    (dict(precision=9), 1),
+    (dict(schedule=5), 1),
+    (dict(chi_max=0), 1),
+    (dict(chi_max=500, sketch_p=16), 6),
+])
+def test_bad_options(opts, status):
+    st, _ = _query([_Pair()], _opts(**opts))
+    assert st == status
+    assert _lib().mpo_last_error()
+
+
+def test_bad_shapes():
+    p = _Pair()
+    p.pair.B.L = 5                      # A and B must share L
+    assert _query([p], _opts())[0] == 2
+    q = _Pair()
+    q.keep[0][0] = 2                     # boundary bond must be 1
+    assert _query([q], _opts())[0] == 2
+    r = _Pair(L=1)
+    assert _query([r], _opts())[0] == 2
+    assert _query([_Pair()], _opts(), n=0)[0] == 1
+
+
+def test_null_pointers():
+    lib = _lib()
+    nbytes = C.c_size_t(0)
+    assert lib.mpo_fit_workspace_bytes(None, 1, C.byref(_opts()), C.byref(nbytes)) == 1
+    p = _Pair()
+    p.pair.A.cores = C.cast(None, C.POINTER(C.c_void_p))
+    assert _query([p], _opts())[0] == 1
+    assert lib.mpo_fit_sweep(None, 1) == 1
