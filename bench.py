@@ -90,12 +90,13 @@ def batched_sweep_flops(L, d, chi, chi_c, dims_c):
     return tot
 
 
-def run_gpu(A, B, precision, sketch_p, steps, warmup, profile=False, schedule="serial", chi_c=None):
+def run_gpu(A, B, precision, sketch_p, steps, warmup, profile=False, schedule="serial", chi_c=None,
+            tuning=None):
     import torch
     from paper_2606_23274_amd.api import FitContext
     ctx = FitContext([(A, B)], chi_c or WORKLOAD["chi_c"], precision=precision, sketch_p=sketch_p,
                      seed=WORKLOAD["seed"], capture_graph=not profile, profile=profile,
-                     schedule=schedule)
+                     schedule=schedule, tuning=tuning)
     ctx.sweep(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -159,13 +160,19 @@ def main():
     dims = settled_dims(w["L"], w["d"], w["chi"], w["chi_c"])
     mf, f64 = sweep_flops(w["L"], w["d"], w["chi"], w["chi_c"], w["p"], dims, True)
 
-    wall, dev_ms, _, got_dims = run_gpu(A, B, "fp32", w["p"], args.steps, args.warmup)
+    # GEMM tile / split-K choice from the project's autotuner (untimed)
+    from paper_2606_23274_amd.api import autotune
+    t0 = time.perf_counter()
+    table = autotune([(A, B)], w["chi_c"], precision="fp32", sketch_p=w["p"], seed=w["seed"], reps=3)
+    tune_s = time.perf_counter() - t0
+    wall, dev_ms, _, got_dims = run_gpu(A, B, "fp32", w["p"], args.steps, args.warmup, tuning=table)
+    wall_b, _, _, _ = run_gpu(A, B, "fp32", w["p"], args.steps, args.warmup)
     ms = wall / args.steps * 1e3
     value = args.steps / wall
     tflops = mf / (ms * 1e-3) / 1e12
 
     # per-kernel-class device time from HIP events around each launch
-    _, _, prof, _ = run_gpu(A, B, "fp32", w["p"], 2, args.warmup, profile=True)
+    _, _, prof, _ = run_gpu(A, B, "fp32", w["p"], 2, args.warmup, profile=True, tuning=table)
     ms_per_class = {k: v[0] / 2 for k, v in prof.items()}  # ms per sweep
     others = {}
     if not args.quick:
@@ -231,6 +238,8 @@ def main():
         "bond_dims_settled": got_dims == dims,
         "kernel_ms_per_sweep": {kk: round(v, 4) for kk, v in
                                 sorted(ms_per_class.items(), key=lambda x: -x[1])},
+        "autotune": {"classes": len(table), "seconds": round(tune_s, 2),
+                     "built_in_choice_sweeps_per_s": round(args.steps / wall_b, 4)},
         "other_precisions": others,
         "batched_schedule": batched,
         "roofline": roof,

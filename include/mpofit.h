@@ -95,8 +95,24 @@ typedef struct {
   uint64_t seed;      /* Philox key word 0 of the Gaussian test matrix        */
   int32_t capture_graph; /* 1: replay each sweep as a captured hipGraph once
                             the bond dimensions have settled                  */
+  const struct mpo_gemm_tune* tune; /* optional host table from
+                            mpo_gemm_autotune (copied at init); NULL = built-in
+                            tile and split-K choice                          */
+  int32_t n_tune;
   int32_t reserved[3];
 } mpo_fit_opts;
+
+/* One tuned class of grouped GEMM launches: the operand kind (mode as
+   mpo_precision, operand types 0 = FP64 / 1 = FP32, K-contiguity of A and B),
+   the largest problem of the launch (M, N, K) and its problem count; the
+   chosen output tile (0: 64x64, 1: 128x128) and split-K count, and the
+   measured average launch time of that choice. */
+typedef struct mpo_gemm_tune {
+  int32_t mode, ta, tb, tc, a_kcontig, b_kcontig;
+  int32_t M, N, K, count;
+  int32_t tile, splits;
+  float us;
+} mpo_gemm_tune;
 
 typedef struct mpo_fit_ctx mpo_fit_ctx;
 
@@ -169,6 +185,19 @@ mpo_status mpo_fit_last_sweep_ms(const mpo_fit_ctx* ctx, double* ms);
    the arrays may be NULL; *count receives the number of classes. */
 mpo_status mpo_fit_profile(const mpo_fit_ctx* ctx, int32_t n, double* ms, const char** names,
                            double* flops, int32_t* launches, int32_t* count);
+
+/* Autotuner of the contraction GEMMs.  Builds a throw-away fit of these
+   pairs with these options in `workspace` (at least mpo_fit_workspace_bytes),
+   runs one sweep so that the bond dimensions settle, then times every GEMM
+   launch class of the next sweep's launch program under each candidate
+   (tile 64x64, and 128x128 for FP32/BF16 when every problem is large enough;
+   split-K 1, 2, 4, 8, 16 where K allows), `reps` launches per candidate with
+   HIP events, and writes the fastest per class into out[0 .. *n_out - 1]
+   (at most `cap`).  Pass the table back through mpo_fit_opts.tune.  The
+   workspace contents are undefined afterwards; synchronizes `stream`. */
+mpo_status mpo_gemm_autotune(const mpo_pair* pairs, int32_t n_pairs, const mpo_fit_opts* opts,
+                             void* workspace, size_t ws_bytes, void* stream, int32_t reps,
+                             mpo_gemm_tune* out, int32_t cap, int32_t* n_out);
 
 void mpo_fit_destroy(mpo_fit_ctx* ctx);
 

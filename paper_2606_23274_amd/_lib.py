@@ -23,10 +23,16 @@ class MpoPair(C.Structure):
     _fields_ = [("A", MpoTT), ("B", MpoTT), ("chi_max", C.c_int32)]
 
 
+class MpoGemmTune(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("mode", "ta", "tb", "tc", "a_kcontig", "b_kcontig", "M", "N",
+                                          "K", "count", "tile", "splits")] + [("us", C.c_float)]
+
+
 class MpoFitOpts(C.Structure):
     _fields_ = [("chi_max", C.c_int32), ("tau", C.c_double), ("precision", C.c_int32),
                 ("schedule", C.c_int32), ("sketch_p", C.c_int32), ("seed", C.c_uint64),
-                ("capture_graph", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("capture_graph", C.c_int32), ("tune", C.POINTER(MpoGemmTune)),
+                ("n_tune", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class MpoError(RuntimeError):
@@ -38,8 +44,8 @@ class MpoError(RuntimeError):
 EXPORTS = [
     "mpo_fit_workspace_bytes", "mpo_fit_init", "mpo_fit_sweep", "mpo_fit_bond_dims",
     "mpo_fit_export_c", "mpo_fit_sweeps_done", "mpo_fit_grad", "mpo_contract_check_bytes",
-    "mpo_contract_exact_check", "mpo_fit_last_sweep_ms", "mpo_fit_profile", "mpo_fit_destroy",
-    "mpo_last_error",
+    "mpo_contract_exact_check", "mpo_fit_last_sweep_ms", "mpo_fit_profile", "mpo_gemm_autotune",
+    "mpo_fit_destroy", "mpo_last_error",
 ]
 
 _lib = None
@@ -70,6 +76,8 @@ def load() -> C.CDLL:
     lib.mpo_fit_last_sweep_ms.argtypes = [C.c_void_p, P(C.c_double)]
     lib.mpo_fit_profile.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_char_p),
                                     P(C.c_double), P(C.c_int32), P(C.c_int32)]
+    lib.mpo_gemm_autotune.argtypes = [P(MpoPair), C.c_int32, P(MpoFitOpts), C.c_void_p, C.c_size_t,
+                                      C.c_void_p, C.c_int32, P(MpoGemmTune), C.c_int32, P(C.c_int32)]
     lib.mpo_fit_destroy.argtypes = [C.c_void_p]
     lib.mpo_fit_destroy.restype = None
     for name in EXPORTS:

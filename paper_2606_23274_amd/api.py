@@ -13,6 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
+from . import tune as tune_mod
 
 
 def _dev_cores(cores, device):
@@ -36,28 +37,21 @@ class _TT:
         self.tt = _lib.MpoTT(L, self.d, self.chi, self.ptrs)
 
 
-class FitContext:
-    """One fit of one or several independent MPO pairs.
+class _Setup:
+    """Device copies of the cores, the ctypes pair array and the options."""
 
-    precision: 'fp64' | 'fp32' | 'bf16' | 'bf16x3'; schedule: 'serial' |
-    'even_odd'; sketch_p < 0 runs the plain SVD, >= 0 the randomized SVD with
-    chi_max + p sketch columns; pair_chi_max optionally sets each pair's cap.
-    """
-
-    def __init__(self, pairs, chi_max, precision="fp32", schedule="serial", sketch_p=-1, seed=0,
-                 capture_graph=True, device="cuda:0", profile=False, pair_chi_max=None):
+    def __init__(self, pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
+                 profile, pair_chi_max, tuning):
         self.lib = _lib.load()
         self.device = torch.device(device)
-        self._tts = []
+        self.tts = []
         arr = (_lib.MpoPair * len(pairs))()
         for i, (A, B) in enumerate(pairs):
             ta, tb = _TT(_dev_cores(A, self.device)), _TT(_dev_cores(B, self.device))
-            self._tts += [ta, tb]
+            self.tts += [ta, tb]
             cm = 0 if pair_chi_max is None else int(pair_chi_max[i])
             arr[i] = _lib.MpoPair(ta.tt, tb.tt, cm)
-        self._pairs = arr
-        self.n_pairs = len(pairs)
-        self.L = [len(A) for A, _ in pairs]
+        self.pairs = arr
         opts = _lib.MpoFitOpts()
         opts.chi_max = int(chi_max)
         opts.tau = 0.0
@@ -67,22 +61,47 @@ class FitContext:
         opts.seed = int(seed)
         opts.capture_graph = 1 if capture_graph else 0
         opts.reserved[0] = 1 if profile else 0
-        self._opts = opts
+        self.tune = tune_mod.to_ctypes(tune_mod.load(tuning)) if tuning is not None else None
+        if self.tune is not None and len(self.tune):
+            opts.tune = self.tune
+            opts.n_tune = len(self.tune)
+        self.opts = opts
         nbytes = C.c_size_t()
         _lib.check(self.lib.mpo_fit_workspace_bytes(arr, len(pairs), C.byref(opts), C.byref(nbytes)))
         self.workspace_bytes = nbytes.value
         # 256-byte alignment: over-allocate and offset
-        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
-        base = self._ws.data_ptr()
-        self._ws_ptr = (base + 255) & ~255
+        self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
+
+
+class FitContext:
+    """One fit of one or several independent MPO pairs.
+
+    precision: 'fp64' | 'fp32' | 'bf16' | 'bf16x3'; schedule: 'serial' |
+    'even_odd'; sketch_p < 0 runs the plain SVD, >= 0 the randomized SVD with
+    chi_max + p sketch columns; pair_chi_max optionally sets each pair's cap;
+    tuning: a GEMM tuning table (list of entries, or a JSON path) from
+    autotune().
+    """
+
+    def __init__(self, pairs, chi_max, precision="fp32", schedule="serial", sketch_p=-1, seed=0,
+                 capture_graph=True, device="cuda:0", profile=False, pair_chi_max=None, tuning=None):
+        su = _Setup(pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
+                    profile, pair_chi_max, tuning)
+        self._setup = su
+        self.lib = su.lib
+        self.device = su.device
+        self.n_pairs = len(pairs)
+        self.L = [len(A) for A, _ in pairs]
+        self.workspace_bytes = su.workspace_bytes
         # a stream of our own (default priority): the legacy null stream
         # cannot be captured into a graph
         with torch.cuda.device(self.device):
             torch.cuda.current_stream().synchronize()
             self.stream = torch.cuda.Stream(device=self.device)
         ctx = C.c_void_p()
-        _lib.check(self.lib.mpo_fit_init(C.byref(ctx), arr, len(pairs), C.byref(opts),
-                                         C.c_void_p(self._ws_ptr), nbytes.value,
+        _lib.check(self.lib.mpo_fit_init(C.byref(ctx), su.pairs, len(pairs), C.byref(su.opts),
+                                         C.c_void_p(su.ws_ptr), su.workspace_bytes,
                                          C.c_void_p(self.stream.cuda_stream)))
         self.ctx = ctx
 
@@ -109,7 +128,7 @@ class FitContext:
         """C of one pair (scaled so that C ~ A B) as float64 device tensors."""
         dims = self.bond_dims(pair)
         L = self.L[pair]
-        d = self._tts[2 * pair].d
+        d = self._setup.tts[2 * pair].d
         cores = [torch.empty((dims[i], d, d, dims[i + 1]), dtype=torch.float64, device=self.device)
                  for i in range(L)]
         ptrs = (C.c_void_p * L)(*[c.data_ptr() for c in cores])
@@ -152,3 +171,22 @@ def fit(A, B, chi_max, sweeps, **kw):
         return ctx.export_numpy(0)
     finally:
         ctx.close()
+
+
+def autotune(pairs, chi_max, precision="fp32", schedule="serial", sketch_p=-1, seed=0,
+             device="cuda:0", pair_chi_max=None, reps=5):
+    """Times the GEMM launch classes of one sweep of this fit under every
+    tile / split-K candidate (mpo_gemm_autotune) and returns the table of
+    winners (list of dicts, see tune.py)."""
+    su = _Setup(pairs, chi_max, precision, schedule, sketch_p, seed, False, device, False,
+                pair_chi_max, None)
+    with torch.cuda.device(su.device):
+        torch.cuda.current_stream().synchronize()
+        stream = torch.cuda.Stream(device=su.device)
+    cap = 256
+    out = (_lib.MpoGemmTune * cap)()
+    n = C.c_int32()
+    _lib.check(su.lib.mpo_gemm_autotune(su.pairs, len(pairs), C.byref(su.opts), C.c_void_p(su.ws_ptr),
+                                        su.workspace_bytes, C.c_void_p(stream.cuda_stream), int(reps),
+                                        out, cap, C.byref(n)))
+    return [tune_mod.entry_to_dict(out[i]) for i in range(n.value)]

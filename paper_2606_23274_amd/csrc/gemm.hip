@@ -368,18 +368,23 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
     __syncthreads();
     if (!s_last) return;
     __threadfence();
+    // sum in split order; the loop is unrolled so that the loads of several
+    // partial tiles are in flight together
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
+      for (int j = 0; j < FN; ++j) acc[i][j] = accv_t{0, 0, 0, 0};
+#pragma unroll 4
+    for (int s = 0; s < d.splits; ++s) {
+      const acc_t* ps = part + (long long)s * (BM * BN) + lane;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          acc_t sum = 0;
-          for (int s = 0; s < d.splits; ++s)
-            sum += __builtin_nontemporal_load(
-                part + (long long)s * (BM * BN) + (((wave * FM + i) * FN + j) * 4 + e) * 64 + lane);
-          acc[i][j][e] = sum;
-        }
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            acc[i][j][e] += __builtin_nontemporal_load(ps + (((wave * FM + i) * FN + j) * 4 + e) * 64);
+    }
     if (threadIdx.x == 0) d.counters[tile_id] = 0;
   }
 

@@ -435,10 +435,24 @@ __global__ void __launch_bounds__(kBig) backtransform_kernel(const EigDesc* __re
 // inside the wave (shuffles); column data is broadcast through LDS.
 constexpr int kRegNB = 5;  // k <= 160
 
+// One DPP move of a double (both 32-bit halves) with a row_ror control.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 32 lanes of a half-wave, returned to all of them: rotations
+// by 8, 4, 2, 1 inside each 16-lane DPP row, then one exchange between the
+// two rows (a single cross-lane permute instead of five).
 template <int NB>
 __device__ __forceinline__ double row_reduce32(double v) {
-  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  v += dpp_d<0x128>(v);  // row_ror:8
+  v += dpp_d<0x124>(v);  // row_ror:4
+  v += dpp_d<0x122>(v);  // row_ror:2
+  v += dpp_d<0x121>(v);  // row_ror:1
+  return v + __shfl_xor(v, 16);
 }
 
 // 1/x and 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton

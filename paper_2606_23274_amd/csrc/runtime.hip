@@ -96,12 +96,43 @@ struct GemmJob {
   int beta = 0;
 };
 
+// Split-K scratch plus the GEMM configuration hooks: the tuning table, a
+// recorder of launch classes (autotuner) and a forced choice (autotuner).
 struct SplitBuf {
   void* partials = nullptr;
   size_t cap = 0;  // bytes
   int* counters = nullptr;
   int ccap = 0;
+  const std::vector<mpo_gemm_tune>* tune = nullptr;
+  std::vector<std::pair<Mode, std::vector<GemmJob>>>* record = nullptr;
+  int force_tile = -1, force_splits = 0;
 };
+
+// Tuning-table key of a grouped launch: operand kind, largest problem, count.
+mpo_gemm_tune gemm_class(Mode mode, const std::vector<GemmJob>& jobs) {
+  mpo_gemm_tune t{};
+  t.mode = mode == Mode::F64 ? MPO_FP64 : mode == Mode::F32 ? MPO_FP32 : mode == Mode::BF16 ? MPO_BF16
+                                                                                              : MPO_BF16X3;
+  t.ta = jobs[0].A.t == DType::F64 ? 0 : 1;
+  t.tb = jobs[0].B.t == DType::F64 ? 0 : 1;
+  t.tc = jobs[0].C.t == DType::F64 ? 0 : 1;
+  t.a_kcontig = jobs[0].A.kc;
+  t.b_kcontig = jobs[0].B.kc;
+  double best = -1;
+  for (auto& j : jobs) {
+    const double w = (double)j.M * j.N * j.K * j.nb[0] * j.nb[1] * j.nb[2];
+    if (w > best) { best = w; t.M = j.M; t.N = j.N; t.K = j.K; }
+  }
+  t.count = 0;
+  for (auto& j : jobs) t.count += j.nb[0] * j.nb[1] * j.nb[2];
+  return t;
+}
+
+bool same_class(const mpo_gemm_tune& a, const mpo_gemm_tune& b) {
+  return a.mode == b.mode && a.ta == b.ta && a.tb == b.tb && a.tc == b.tc &&
+         a.a_kcontig == b.a_kcontig && a.b_kcontig == b.b_kcontig && a.M == b.M && a.N == b.N &&
+         a.K == b.K && a.count == b.count;
+}
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
@@ -129,23 +160,43 @@ void add_gemm(Program& P, const SplitBuf& sb, Mode mode, const std::vector<GemmJ
 void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<GemmJob>& jobs,
                    const char* cls, double flops) {
   if (jobs.empty()) return;
+  if (sb.record) sb.record->emplace_back(mode, jobs);
   GemmKind gk{mode, jobs[0].A.t, jobs[0].B.t, jobs[0].C.t, jobs[0].A.kc, jobs[0].B.kc, 0};
-  // tile: 128x128 for FP32/BF16 when every problem is large enough and the
-  // launch still has >= 256 workgroups
-  if (mode != Mode::F64) {
-    bool big = true;
-    long long w128 = 0;
-    for (auto& j : jobs) {
-      if (j.M < 128 || j.N < 128) big = false;
-      w128 += (long long)ceil_div(j.M, 128) * ceil_div(j.N, 128) * j.nb[0] * j.nb[1] * j.nb[2];
-    }
-    if (big && w128 >= 256) gk.tile = 1;
+  // tile 128x128 is possible for FP32/BF16 when every problem is large enough
+  bool big = mode != Mode::F64;
+  long long w128 = 0;
+  for (auto& j : jobs) {
+    if (j.M < 128 || j.N < 128) big = false;
+    w128 += (long long)ceil_div(j.M, 128) * ceil_div(j.N, 128) * j.nb[0] * j.nb[1] * j.nb[2];
+  }
+  const mpo_gemm_tune* tuned = nullptr;
+  if (sb.tune) {
+    const mpo_gemm_tune key = gemm_class(mode, jobs);
+    for (auto& t : *sb.tune)
+      if (same_class(t, key)) { tuned = &t; break; }
+  }
+  int split_cap = 0;  // 0: built-in rule
+  if (sb.force_tile >= 0) {
+    gk.tile = (sb.force_tile == 1 && big) ? 1 : 0;
+    split_cap = std::max(1, sb.force_splits);
+  } else if (tuned) {
+    gk.tile = (tuned->tile == 1 && big) ? 1 : 0;
+    split_cap = std::max(1, tuned->splits);
+  } else if (big && w128 >= 256) {
+    // built-in: the large tile when the launch still fills the chip
+    gk.tile = 1;
   }
   const int BM = gemm_bm(gk.tile), BN = gemm_bn(gk.tile), BK = gemm_bk(mode, gk.tile);
   long long base_wgs = 0;
   for (auto& j : jobs)
     base_wgs += (long long)ceil_div(j.M, BM) * ceil_div(j.N, BN) * j.nb[0] * j.nb[1] * j.nb[2];
-  const int want = base_wgs >= 256 ? 1 : (int)std::min<long long>(16, (512 + base_wgs - 1) / base_wgs);
+  // built-in split-K rule: only launches of fewer than 128 tiles are split,
+  // up to filling 256 CUs once, with at least four K slabs per split (the
+  // deterministic reduction costs a device-scope fence per tile)
+  const int want = split_cap > 0 ? split_cap
+                   : base_wgs >= 128 ? 1
+                                     : (int)std::min<long long>(8, (256 + base_wgs - 1) / base_wgs);
+  const int min_slabs = split_cap > 0 ? 1 : 4;
   std::vector<GemmDesc> ds;
   long long wg = 0;
   size_t poff = 0;
@@ -169,7 +220,7 @@ void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<
     d.vec_a = vec(j.A);
     d.vec_b = vec(j.B);
     const long long tiles = (long long)d.tiles_m * d.tiles_n * j.nb[0] * j.nb[1] * j.nb[2];
-    int splits = std::max(1, std::min(want, j.K / (2 * BK)));
+    int splits = std::max(1, std::min(want, j.K / (min_slabs * BK)));
     int kchunk = ceil_div(ceil_div(j.K, splits), BK) * BK;
     splits = std::max(1, ceil_div(j.K, kchunk));
     const size_t need = (size_t)tiles * splits * BM * BN * gemm_acc_bytes(mode);
@@ -299,6 +350,7 @@ struct Ctx {
     int launches = 0;
   };
   std::vector<ProfEntry> prof;  // per kernel class, summed over the last call's sweeps
+  std::vector<mpo_gemm_tune> tune;  // GEMM tuning table (copied from the options)
   std::vector<double> prof_flops;
   size_t ws_bytes = 0;
 };
@@ -1195,6 +1247,13 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
             : o->precision == MPO_BF16 ? Mode::BF16 : Mode::BF16X3;
   X.wt = o->precision == MPO_FP64 ? DType::F64 : DType::F32;
   X.profile = o->reserved[0] != 0;
+  if (o->n_tune < 0 || (o->n_tune > 0 && !o->tune))
+    throw Error{MPO_ERR_INVALID_ARG, "bad tuning table"};
+  X.tune.assign(o->tune, o->tune + o->n_tune);
+  for (auto& t : X.tune)
+    if (t.tile < 0 || t.tile > 1 || t.splits < 1 || t.splits > 64)
+      throw Error{MPO_ERR_INVALID_ARG, "bad tuning entry"};
+  X.sb.tune = X.tune.empty() ? nullptr : &X.tune;
   X.pairs.resize(n_pairs);
   for (int p = 0; p < n_pairs; ++p) {
     const mpo_pair& pr = pairs[p];
@@ -1495,6 +1554,93 @@ mpo_status mpo_fit_profile(const mpo_fit_ctx* ctx, int32_t n, double* ms, const 
       if (flops) flops[i] = pm[i].flops;
       if (launches) launches[i] = pm[i].launches;
     }
+  });
+}
+
+mpo_status mpo_gemm_autotune(const mpo_pair* pairs, int32_t n_pairs, const mpo_fit_opts* opts,
+                             void* workspace, size_t ws_bytes, void* stream, int32_t reps,
+                             mpo_gemm_tune* out, int32_t cap, int32_t* n_out) {
+  return guarded([&] {
+    if (!out || !n_out || cap < 0 || reps < 1) throw Error{MPO_ERR_INVALID_ARG, "bad output or reps"};
+    mpo_fit_opts o = *opts;
+    o.tune = nullptr;
+    o.n_tune = 0;
+    o.capture_graph = 0;
+    o.reserved[0] = 0;
+    mpo_fit_ctx* raw = nullptr;
+    const mpo_status st = mpo_fit_init(&raw, pairs, n_pairs, &o, workspace, ws_bytes, stream);
+    if (st != MPO_OK) throw Error{st, g_last_error};
+    std::unique_ptr<mpo_fit_ctx, void (*)(mpo_fit_ctx*)> ctx(raw, mpo_fit_destroy);
+    const mpo_status st2 = mpo_fit_sweep(raw, 1);
+    if (st2 != MPO_OK) throw Error{st2, g_last_error};
+    Ctx& X = raw->X;
+    // the launch classes of the next sweep
+    std::vector<std::pair<Mode, std::vector<GemmJob>>> rec;
+    {
+      SweepPlan sp;
+      X.sb.record = &rec;
+      const std::vector<std::vector<int>> keep = [&] {
+        std::vector<std::vector<int>> v;
+        for (auto& S : X.pairs) v.push_back(S.cC);
+        return v;
+      }();
+      record_sweep(X, sp, X.sweeps_done % 2 == 0);
+      X.sb.record = nullptr;
+      for (size_t p = 0; p < X.pairs.size(); ++p) X.pairs[p].cC = keep[p];
+    }
+    std::vector<mpo_gemm_tune> best;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    const size_t arena_mark = X.arena_used;
+    try {
+      for (auto& r : rec) {
+        const mpo_gemm_tune key = gemm_class(r.first, r.second);
+        bool seen = false;
+        for (auto& b : best) seen = seen || same_class(b, key);
+        if (seen) continue;
+        mpo_gemm_tune win = key;
+        win.us = -1;
+        for (int tile = 0; tile < (r.first == Mode::F64 ? 1 : 2); ++tile) {
+          for (int sp : {1, 2, 4, 8, 16}) {
+            if (sp > 1 && key.K / sp < gemm_bk(r.first, tile)) continue;
+            Program P;
+            X.sb.force_tile = tile;
+            X.sb.force_splits = sp;
+            add_gemm_kind(P, X.sb, r.first, r.second, "tune", 0);
+            X.sb.force_tile = -1;
+            X.sb.force_splits = 0;
+            if (tile == 1 && P.launches[0].gk.tile != 1) continue;  // tile not possible here
+            upload(X, P);
+            run_program(P, X.stream, nullptr);  // warm-up
+            HIP_OK(hipEventRecord(e0, X.stream));
+            for (int q = 0; q < reps; ++q) run_program(P, X.stream, nullptr);
+            HIP_OK(hipEventRecord(e1, X.stream));
+            HIP_OK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+            X.arena_used = arena_mark;
+            const float us = ms * 1000.f / reps;
+            if (win.us < 0 || us < win.us) {
+              win.us = us;
+              win.tile = tile;
+              win.splits = sp;
+            }
+          }
+        }
+        best.push_back(win);
+      }
+    } catch (...) {
+      X.sb.force_tile = -1;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    HIP_OK(hipEventDestroy(e0));
+    HIP_OK(hipEventDestroy(e1));
+    HIP_OK(hipStreamSynchronize(X.stream));
+    *n_out = (int32_t)std::min<size_t>(best.size(), (size_t)cap);
+    for (int i = 0; i < *n_out; ++i) out[i] = best[i];
   });
 }
 
