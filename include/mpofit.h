@@ -43,9 +43,7 @@ typedef enum {
   MPO_ERR_SHAPE = 2,       /* inconsistent bond or physical dimensions        */
   MPO_ERR_WORKSPACE = 3,   /* workspace too small or misaligned (256 bytes)   */
   MPO_ERR_DEVICE = 4,      /* a HIP runtime call failed                       */
-  MPO_ERR_NUMERIC = 5,     /* non-finite value, failed Cholesky, or a singular
-                              value at or below 1e-14 sigma_1 that the inverse
-                              gauge would invert                             */
+  MPO_ERR_NUMERIC = 5,     /* non-finite value or failed Cholesky            */
   MPO_ERR_UNSUPPORTED = 6  /* option combination this build does not run     */
 } mpo_status;
 
@@ -68,7 +66,11 @@ typedef enum {
   MPO_SCHED_EVEN_ODD = 1 /* inverse canonical gauge (Alg. 4): every bond
                             l = 1 (mod 2) together, then every l = 0 (mod 2),
                             from the environments at the half-step's start;
-                            one sweep = both half-steps (Sec. 4)              */
+                            one sweep = both half-steps (Sec. 4).  Singular
+                            values at or below 1e-12 sigma_1 are truncated
+                            before they are inverted (Sec. 2.3.1 allows it):
+                            value, Y entry and singular vectors become zero,
+                            the bond keeps its size; see mpo_fit_truncations */
 } mpo_schedule;
 
 /* One MPO: L cores, core l (0-based) is a device array of
@@ -148,6 +150,11 @@ mpo_status mpo_fit_export_c(mpo_fit_ctx* ctx, int32_t pair, double* const* c_cor
 
 /* Number of sweeps run so far. */
 mpo_status mpo_fit_sweeps_done(const mpo_fit_ctx* ctx, int32_t* n);
+
+/* Even/odd schedule: number of singular values truncated before inversion
+   so far (initialization and sweeps, all pairs), as of the last call that
+   synchronized (mpo_fit_init, mpo_fit_sweep). */
+mpo_status mpo_fit_truncations(const mpo_fit_ctx* ctx, int64_t* n);
 
 /* Gradient of loss(A, B) = <W, P(A B)>_F with respect to every core of A and
    B, where P is the orthogonal projector onto the MPOs that share C's

@@ -9,7 +9,11 @@
 * Vidal / inverse canonical form: from a right-canonical train, a left-to-right
   SVD sweep gives Lambda_l and Psi_l = Lambda_{l-1} Gamma_l Lambda_l = U_l S_l,
   Y_l = Lambda_l^{-1}; then every Psi_l Y_l is left orthogonal and every
-  Y_{l-1} Psi_l is right orthogonal.
+  Y_{l-1} Psi_l is right orthogonal.  Singular values at or below
+  INV_TRUNC * sigma_1 are truncated before the inversion, as the paper allows
+  for stability (Sec. 2.3.1, inverse canonical form): they, their singular
+  vectors and their Y entries become zero, so the bond keeps its size with
+  zero padding and Psi_l Y_l stays a (partial) isometry.
 
 Pins (tests/test_oracle_canon.py): the dense operator is unchanged by every
 gauge routine; orthogonality relations of each form; Householder QR with the
@@ -73,13 +77,29 @@ def right_orthogonalize(cores):
     return cores
 
 
-def inverse_canonical(right_canonical_cores, guard: float = 1e-14):
+INV_TRUNC = 1e-12
+
+
+def truncate_inverse(U, S, Vt, thresh: float = INV_TRUNC):
+    """Zero the singular triplets with S_j <= thresh * S_0 (Sec. 2.3.1: very
+    small singular values may be truncated before they are inverted).
+    Returns (U, S, Vt, Y, count) with Y the pseudo-inverse of diag(S)."""
+    keep = S > thresh * S[0] if len(S) else np.zeros(0, dtype=bool)
+    U = U * keep[None, :]
+    Vt = Vt * keep[:, None]
+    S = np.where(keep, S, 0.0)
+    Y = np.where(keep, 1.0 / np.where(keep, S, 1.0), 0.0)
+    return U, S, Vt, Y, int(np.sum(~keep))
+
+
+def inverse_canonical(right_canonical_cores, thresh: float = INV_TRUNC):
     """Left-to-right SVD sweep of a right-canonical train into the inverse
     canonical form (Psi_1..Psi_L, Y_1..Y_{L-1}) of Sec. 2.3.1.
 
     SVD signs follow the same rule as the 2-site update (largest-magnitude
-    entry of each U column positive).  Returns (Psi, Y, n_guard) where n_guard
-    counts singular values below guard * sigma_1 before inversion."""
+    entry of each U column positive).  Singular values at or below
+    thresh * sigma_1 are truncated (truncate_inverse).  Returns
+    (Psi, Y, n_trunc)."""
     cores = [np.array(c, dtype=np.float64, copy=True) for c in right_canonical_cores]
     L = len(cores)
     Psi, Y = [None] * L, [None] * (L - 1)
@@ -97,9 +117,10 @@ def inverse_canonical(right_canonical_cores, guard: float = 1e-14):
         U, S, Vt = U[:, :r], S[:r], Vt[:r]
         s = sign_fix_columns(U)
         U, Vt = U * s[None, :], Vt * s[:, None]
-        n_guard += int(np.sum(S <= guard * S[0]))
+        U, S, Vt, Yl, nt = truncate_inverse(U, S, Vt, thresh)
+        n_guard += nt
         Psi[l] = (U * S[None, :]).reshape(cl, d1, d2, r)
-        Y[l] = 1.0 / S
+        Y[l] = Yl
         carry = S[:, None] * Vt
     return Psi, Y, n_guard
 

@@ -214,7 +214,7 @@ def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
     L = len(A)
     A1, B1, nu, caps = _preprocess(A, B)
     C0 = canon.right_orthogonalize(A1)
-    Psi, Y, n_guard = canon.inverse_canonical(C0, GUARD)
+    Psi, Y, n_guard = canon.inverse_canonical(C0)
     ones = np.ones((1, 1, 1))
     Lenv = [None] * (L + 1)
     Renv = [None] * (L + 2)
@@ -243,12 +243,13 @@ def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
                 cr = Psi[l].shape[3]
                 d1, d2 = A1[l - 1].shape[1], B1[l - 1].shape[2]
                 r = len(f.S)
-                U4 = f.U.reshape(cl, d1, d2, r)
-                V4 = f.Vt.reshape(r, d1, d2, cr)
-                Psi[l - 1] = U4 * f.S[None, None, None, :]
-                Psi[l] = f.S[:, None, None, None] * V4
-                Y[l - 1] = 1.0 / f.S
-                n_guard += f.n_guard
+                U, S, Vt, Yl, nt = canon.truncate_inverse(f.U, f.S, f.Vt)
+                U4 = U.reshape(cl, d1, d2, r)
+                V4 = Vt.reshape(r, d1, d2, cr)
+                Psi[l - 1] = U4 * S[None, None, None, :]
+                Psi[l] = S[:, None, None, None] * V4
+                Y[l - 1] = Yl
+                n_guard += nt
                 min_gap = min(min_gap, f.gap)
                 ks.append(f.k)
                 if l <= L - 2:

@@ -43,7 +43,7 @@ class MpoError(RuntimeError):
 
 EXPORTS = [
     "mpo_fit_workspace_bytes", "mpo_fit_init", "mpo_fit_sweep", "mpo_fit_bond_dims",
-    "mpo_fit_export_c", "mpo_fit_sweeps_done", "mpo_fit_grad", "mpo_contract_check_bytes",
+    "mpo_fit_export_c", "mpo_fit_sweeps_done", "mpo_fit_truncations", "mpo_fit_grad", "mpo_contract_check_bytes",
     "mpo_contract_exact_check", "mpo_fit_last_sweep_ms", "mpo_fit_profile", "mpo_gemm_autotune",
     "mpo_fit_destroy", "mpo_last_error",
 ]
@@ -68,6 +68,7 @@ def load() -> C.CDLL:
     lib.mpo_fit_bond_dims.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.mpo_fit_export_c.argtypes = [C.c_void_p, C.c_int32, P(C.c_void_p)]
     lib.mpo_fit_sweeps_done.argtypes = [C.c_void_p, P(C.c_int32)]
+    lib.mpo_fit_truncations.argtypes = [C.c_void_p, P(C.c_int64)]
     lib.mpo_fit_grad.argtypes = [C.c_void_p, C.c_int32, P(MpoTT), P(C.c_void_p), P(C.c_void_p),
                                  P(C.c_double), C.c_int32]
     lib.mpo_contract_check_bytes.argtypes = [P(MpoPair), P(MpoTT), P(C.c_size_t)]

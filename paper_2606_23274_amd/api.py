@@ -113,6 +113,12 @@ class FitContext:
         _lib.check(self.lib.mpo_fit_sweeps_done(self.ctx, C.byref(n)))
         return n.value
 
+    def truncations(self):
+        """Singular values truncated before inversion so far (even/odd)."""
+        v = C.c_int64()
+        _lib.check(self.lib.mpo_fit_truncations(self.ctx, C.byref(v)))
+        return v.value
+
     def last_sweep_ms(self):
         v = C.c_double()
         _lib.check(self.lib.mpo_fit_last_sweep_ms(self.ctx, C.byref(v)))

@@ -23,7 +23,7 @@ enum class DType : int { F64 = 0, F32 = 1 };
 enum : int {
   FLAG_NONFINITE = 1,
   FLAG_CHOL = 2,      // non-positive pivot in a Cholesky factorization
-  FLAG_GUARD = 4,     // a kept singular value <= 1e-14 sigma_1 in the inverse gauge
+  FLAG_GUARD = 4,     // unused (small singular values are truncated, not flagged)
   FLAG_EIG = 8,       // eigenvalue search did not bracket
 };
 

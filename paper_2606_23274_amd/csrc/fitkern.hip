@@ -114,8 +114,9 @@ __global__ void scale_kernel(const ScaleDesc* __restrict__ descs) {
        e += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(e / d.r), j = (int)(e % d.r);
     double v = d.in[(long long)i * d.ldi + j];
-    if (d.row) v = d.row_inv ? v / d.row[i] : v * d.row[i];
-    if (d.col) v = d.col_inv ? v / d.col[j] : v * d.col[j];
+    // the inverse is the pseudo-inverse: a zero scale gives zero
+    if (d.row) v = d.row_inv ? (d.row[i] != 0.0 ? v / d.row[i] : 0.0) : v * d.row[i];
+    if (d.col) v = d.col_inv ? (d.col[j] != 0.0 ? v / d.col[j] : 0.0) : v * d.col[j];
     d.out[(long long)i * d.ldo + j] = v;
   }
 }
@@ -154,9 +155,11 @@ __global__ void svals_kernel(const SvalDesc* __restrict__ descs) {
   const double s0 = sqrt(fmax(l0, 0.0));
   const double sj = sqrt(fmax(lj, 0.0));
   d.S[j] = sj;
-  if (d.flag) {
-    if (!isfinite(lj)) atomicOr(d.flag, FLAG_NONFINITE);
-    if (d.guard && !(sj > 1e-14 * s0)) atomicOr(d.flag, FLAG_GUARD);
+  if (d.flag && !isfinite(lj)) atomicOr(d.flag, FLAG_NONFINITE);
+  if (d.guard) {
+    const bool keep = sj > kInvTrunc * s0;
+    d.keep[j] = keep ? 1.0 : 0.0;
+    if (!keep && d.count) atomicAdd(d.count, 1);
   }
 }
 

@@ -62,14 +62,20 @@ struct PermDesc {
 void launch_perm(const PermDesc* d, int n, long long max_elems, hipStream_t s);
 
 // Singular values S_j = sqrt(max(lambda_j, 0)) of r eigenvalues; raises
-// FLAG_GUARD when `guard` and S_j <= 1e-14 S_0, FLAG_NONFINITE on NaN/Inf.
+// FLAG_NONFINITE on NaN/Inf.
+// S = sqrt(max(lambda, 0)).  With `guard` (inverse gauge) keep[j] = 1 if
+// S_j > kInvTrunc S_0 else 0 (the value is then truncated before inversion,
+// and counted in *count).
 struct SvalDesc {
   const double* evals;
   double* S;
   int r;
   int guard;
   int* flag;
+  double* keep = nullptr;
+  int* count = nullptr;
 };
+constexpr double kInvTrunc = 1e-12;
 void launch_svals(const SvalDesc* d, int n, int max_r, hipStream_t s);
 
 // Zero `n_words` 32-bit words at each pointer; when eye_rows > 0 write an

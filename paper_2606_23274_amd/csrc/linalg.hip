@@ -54,6 +54,17 @@ __global__ void __launch_bounds__(kBig) chol_kernel(const CholDesc* __restrict__
   Sym A{k <= kPackedMax ? lds : d.R, k <= kPackedMax ? 0 : d.ldr};
   for (int i = wave; i < k; i += kBig / 64)
     for (int j = lane; j <= i; j += 64) A.at(i, j) = d.G[(long long)i * d.ldg + j];
+  if (d.shift > 0.0) {  // G + shift * trace(G) I
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tr = 0.0;
+      for (int j = 0; j < k; ++j) tr += A.at(j, j);
+      s_piv = d.shift * tr;
+    }
+    __syncthreads();
+    const double sh = s_piv;
+    for (int j = threadIdx.x; j < k; j += kBig) A.at(j, j) += sh;
+  }
   bool bad = false;
   for (int j = 0; j < k; ++j) {
     __syncthreads();
@@ -771,6 +782,98 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
     }
 }
 
+
+// ---------------------------------------------------------------- one-sided Jacobi SVD
+// Sum over the 64 lanes of a wave, returned to all of them.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0x128>(v);
+  v += dpp_d<0x124>(v);
+  v += dpp_d<0x122>(v);
+  v += dpp_d<0x121>(v);
+  v += __shfl_xor(v, 16);
+  return v + __shfl_xor(v, 32);
+}
+
+// Round-robin pairing of qq (even) columns: player qq-1 stays, the others
+// rotate; round t pairs (qq-1, t) and (t+k, t-k) mod (qq-1), k = 1 .. qq/2-1.
+__device__ __forceinline__ void rr_pair(int t, int k, int qq, int& i, int& j) {
+  if (k == 0) { i = qq - 1; j = t; return; }
+  i = (t + k) % (qq - 1);
+  j = (t - k + (qq - 1)) % (qq - 1);
+}
+
+__global__ void __launch_bounds__(kBig) jacobi_kernel(const JacobiDesc* __restrict__ descs, int in_lds) {
+  extern __shared__ double lds[];
+  __shared__ double s_n[512];
+  __shared__ int s_rot;
+  const JacobiDesc d = descs[blockIdx.x];
+  const int q = d.q, qq = q + (q & 1);
+  double* M = in_lds ? lds : d.work;  // column-major: column c at M + c q
+  for (int idx = threadIdx.x; idx < q * q; idx += kBig) {
+    const int r = idx % q, c = idx / q;
+    M[idx] = d.R[(long long)r * d.ldr + c];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int kWaves = kBig / 64;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (threadIdx.x == 0) s_rot = 0;
+    __syncthreads();
+    for (int t = 0; t + 1 < qq; ++t) {
+      for (int pk = wave; pk < qq / 2; pk += kWaves) {
+        int i, j;
+        rr_pair(t, pk, qq, i, j);
+        if (i >= q || j >= q) continue;  // the padding column
+        double* ci = M + (long long)i * q;
+        double* cj = M + (long long)j * q;
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int r = lane; r < q; r += 64) {
+          const double x = ci[r], y = cj[r];
+          a = fma(x, x, a);
+          b = fma(y, y, b);
+          c = fma(x, y, c);
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        c = wave_sum(c);
+        if (c != 0.0 && fabs(c) > 1e-15 * sqrt(a * b)) {
+          const double z = (b - a) / (2.0 * c);
+          const double tt = copysign(1.0, z) / (fabs(z) + sqrt(fma(z, z, 1.0)));
+          const double cs = 1.0 / sqrt(fma(tt, tt, 1.0)), sn = cs * tt;
+          for (int r = lane; r < q; r += 64) {
+            const double x = ci[r], y = cj[r];
+            ci[r] = cs * x - sn * y;
+            cj[r] = sn * x + cs * y;
+          }
+          if (lane == 0) s_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int rot = s_rot;
+    __syncthreads();
+    if (rot == 0) break;
+  }
+  // column norms, their descending order, the unit columns
+  for (int c = wave; c < q; c += kWaves) {
+    double a = 0.0;
+    for (int r = lane; r < q; r += 64) a = fma(M[(long long)c * q + r], M[(long long)c * q + r], a);
+    a = wave_sum(a);
+    if (lane == 0) s_n[c] = sqrt(a);
+  }
+  __syncthreads();
+  double smax = 0.0;
+  for (int i = 0; i < q; ++i) smax = fmax(smax, s_n[i]);
+  for (int c = threadIdx.x; c < q; c += kBig) {
+    const double sc = s_n[c];
+    int rank = 0;
+    for (int i = 0; i < q; ++i) rank += (s_n[i] > sc || (s_n[i] == sc && i < c)) ? 1 : 0;
+    const bool keep = sc > d.trunc * smax;
+    if (!keep && d.count) atomicAdd(d.count, 1);
+    d.S[rank] = keep ? sc : 0.0;
+    const double inv = keep ? 1.0 / sc : 0.0;
+    for (int r = 0; r < q; ++r) d.Ur[(long long)r * d.ldu + rank] = M[(long long)c * q + r] * inv;
+  }
+}
 }  // namespace
 
 size_t eig_work_doubles(int k, int r) {
@@ -797,6 +900,13 @@ void launch_trsm(const TrsmDesc* d, int n, int max_rows, hipStream_t s) {
   if (n <= 0 || max_rows <= 0) return;
   dim3 grid(ceil_div(max_rows, kBig / 64), n);
   hipLaunchKernelGGL(trsm_kernel<8>, grid, dim3(kBig), 0, s, d);
+}
+
+void launch_jacobi(const JacobiDesc* d, int n, int max_q, hipStream_t s) {
+  if (n <= 0) return;
+  const int in_lds = max_q <= kJacobiLds ? 1 : 0;
+  const size_t lds = in_lds ? (size_t)max_q * max_q * sizeof(double) : 0;
+  hipLaunchKernelGGL(jacobi_kernel, dim3(n), dim3(kBig), lds, s, d, in_lds);
 }
 
 void launch_eig(const EigDesc* d, const EigDesc* h, int n, int reg, int stage, hipStream_t s) {

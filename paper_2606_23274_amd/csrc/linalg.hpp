@@ -17,6 +17,7 @@ struct CholDesc {
   int ldr;
   int k;
   int* flag;  // FLAG_CHOL on a non-positive pivot
+  double shift = 0;  // > 0: factor G + shift * trace(G) I instead (general kernel)
 };
 
 // X <- X R^{-1} for an n x k row-major X (ldx) and upper triangular R (ldr).
@@ -41,6 +42,27 @@ struct EigDesc {
   double* work;  // >= eig_work_doubles(k, r) doubles
   int* flag;
 };
+
+// One-sided Jacobi SVD (Hestenes) of a q x q row-major matrix R: columns are
+// rotated pairwise (round-robin order) until every pair is orthogonal to
+// 1e-15 relative, then the column norms S (descending) and the unit columns
+// Ur (row-major q x q, ldu, same order) are written, so that R V = Ur diag(S)
+// for an orthogonal V that is not formed.  Small singular values keep high
+// relative accuracy (no Gram matrix is formed).  work: q*q doubles, used
+// when q > kJacobiLds.  Singular values S_j <= trunc S_0 are truncated (S_j
+// and column j of Ur set to zero) and counted in *count.
+struct JacobiDesc {
+  const double* R;
+  int ldr, q;
+  double* Ur;
+  int ldu;
+  double* S;
+  double* work;
+  double trunc;
+  int* count;
+};
+constexpr int kJacobiLds = 128;
+void launch_jacobi(const JacobiDesc* d, int n, int max_q, hipStream_t s);
 
 size_t eig_work_doubles(int k, int r);
 // Offsets inside the eigen work area: Q^T (k x k, row-major) of the

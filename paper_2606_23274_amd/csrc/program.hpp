@@ -14,7 +14,7 @@
 
 namespace mpofit {
 
-enum class LK { Gemm, Chol, Trsm, Eig, Omega, Sign, Scale, Perm, Sval, Fill, Norm, Bump };
+enum class LK { Gemm, Chol, Trsm, Eig, Omega, Sign, Scale, Perm, Sval, Fill, Norm, Bump, Jacobi };
 
 struct Launch {
   LK kind;

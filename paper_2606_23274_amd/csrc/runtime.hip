@@ -49,6 +49,7 @@ void run_program(const Program& p, hipStream_t s, hipEvent_t* ev) {
       case LK::Fill: launch_fill(p.device<FillDesc>(l), l.n, l.maxa, s); break;
       case LK::Norm: launch_norm(p.device<NormDesc>(l), l.n, s); break;
       case LK::Bump: launch_bump(l.counter, l.bump_by, s); break;
+      case LK::Jacobi: launch_jacobi(p.device<JacobiDesc>(l), l.n, (int)l.maxa, s); break;
     }
     HIP_OK(hipGetLastError());
     if (ev) HIP_OK(hipEventRecord(ev[li + 1], s));
@@ -319,6 +320,7 @@ struct BondScratch {
   void* T;        // first-step scratch of the left/right extension (working type)
   unsigned* amT;
   double *omega, *Y, *Y2, *G, *R, *Bk, *H, *eigw, *evals, *Z, *S, *V, *sign, *SVt;
+  double* keep;  // inverse gauge: 1 for kept singular values, 0 for truncated
 };
 
 struct Ctx {
@@ -336,7 +338,8 @@ struct Ctx {
   size_t arena_cap = 0;
   size_t arena_used = 0;
   // init scratch (FP64)
-  double *iG, *iR1, *iR2, *iRt, *iTmp, *iXt;
+  double *iG, *iR1, *iR2, *iRt, *iTmp, *iXt, *iJ;
+  double *iH, *iZ, *iEw, *iEv, *iSg;  // eigenproblem of the inverse-canonical init
   size_t iTmpN = 0;
   int sweeps_done = 0;
   std::map<std::string, Program> programs;  // keyed by shape plan
@@ -351,6 +354,7 @@ struct Ctx {
   };
   std::vector<ProfEntry> prof;  // per kernel class, summed over the last call's sweeps
   std::vector<mpo_gemm_tune> tune;  // GEMM tuning table (copied from the options)
+  long long n_trunc = 0;            // singular values truncated before inversion
   std::vector<double> prof_flops;
   size_t ws_bytes = 0;
 };
@@ -475,7 +479,16 @@ struct CholQRJob {
   double* R;     // >= 2*k*k
   double* Rout;  // nullable, k x k
   double* T;     // nullable, n x k temp (fast path)
+  bool shifted = false;  // shifted first pass (general path only)
 };
+
+// Diagonal shift of shifted CholeskyQR (Fukaya, Kannan, Nakatsukasa,
+// Yamamoto, Yanagisawa, SIAM J. Sci. Comput. 2020): s = 11 (n k + k (k+1)) u
+// ||X||_2^2 with u = 2^-53; ||X||_F^2 = trace(X^T X) stands in for ||X||_2^2
+// (an upper bound, so the shift stays large enough).  One shifted pass leaves
+// cond(Q) of order u^{-1/2}, which two plain passes then clean up, for inputs
+// with cond(X) up to about u^{-1}.
+double chol_shift(int n, int k) { return 11.0 * ((double)n * k + (double)k * (k + 1)) * 0x1p-53; }
 
 void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int passes) {
   if (jobs.empty()) return;
@@ -492,8 +505,10 @@ void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int pass
       const int lds = (fast && pass % 2 == 1) ? j.k : j.ld;
       const int ldd = (fast && pass % 2 == 1) ? j.ld : j.k;
       gj.push_back(GemmJob{j.k, j.k, j.n, op64(src, false, lds), op64(src, false, lds), out64(j.G, j.k)});
-      double* Rp = j.R + (size_t)(pass % 2) * j.k * j.k;
-      cd.push_back(CholDesc{j.G, j.k, Rp, j.k, j.k, X.flag});
+      double* Rp = j.Rout ? j.R : j.R + (size_t)(pass % 2) * j.k * j.k;
+      CholDesc c{j.G, j.k, Rp, j.k, j.k, X.flag};
+      if (j.shifted && pass == 0 && !fast) c.shift = chol_shift(j.n, j.k);
+      cd.push_back(c);
       if (fast)
         tj.push_back(GemmJob{j.n, j.k, j.k, op64(src, true, lds), op64(Rp, false, j.k), out64(dst, ldd)});
       else
@@ -513,6 +528,22 @@ void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int pass
     P.launches.push_back(l);
     if (fast) add_gemm(P, X.sb, Mode::F64, tj, "qr_apply", 0);
     else add_simple(P, LK::Trsm, td, maxn, "qr_trsm");
+    // Rout <- R_pass Rout (the second R block is the product's temp)
+    std::vector<GemmJob> rj;
+    std::vector<PermDesc> pc;
+    for (auto& j : jobs) {
+      if (!j.Rout) continue;
+      const size_t kk = (size_t)j.k * j.k;
+      if (pass == 0) {
+        pc.push_back(perm4(j.R, 0, j.Rout, 0, {1, 1, j.k, j.k}, {0, 0, j.k, 1}, {0, 0, j.k, 1}));
+      } else {
+        rj.push_back(GemmJob{j.k, j.k, j.k, op64(j.R, true, j.k), op64(j.Rout, false, j.k),
+                             out64(j.R + kk, j.k)});
+        pc.push_back(perm4(j.R + kk, 0, j.Rout, 0, {1, 1, j.k, j.k}, {0, 0, j.k, 1}, {0, 0, j.k, 1}));
+      }
+    }
+    add_gemm(P, X.sb, Mode::F64, rj, "qr_rprod", 0);
+    add_perm(P, pc, "copy");
   }
   if (fast && passes % 2 == 1) {
     std::vector<PermDesc> cp;
@@ -520,20 +551,6 @@ void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int pass
       cp.push_back(perm4(j.T, 0, j.X, 0, {1, 1, j.n, j.k}, {0, 0, j.k, 1}, {0, 0, j.ld, 1}));
     add_perm(P, cp, "copy");
   }
-  // Rout = R_2 R_1 (or R_1)
-  std::vector<GemmJob> rj;
-  std::vector<PermDesc> pc;
-  for (auto& j : jobs) {
-    if (!j.Rout) continue;
-    if (passes == 1) {
-      pc.push_back(perm4(j.R, 0, j.Rout, 0, {1, 1, j.k, j.k}, {0, 0, j.k, 1}, {0, 0, j.k, 1}));
-    } else {
-      rj.push_back(GemmJob{j.k, j.k, j.k, op64(j.R + (size_t)j.k * j.k, true, j.k),
-                           op64(j.R, false, j.k), out64(j.Rout, j.k)});
-    }
-  }
-  add_gemm(P, X.sb, Mode::F64, rj, "qr_rprod", 0);
-  add_perm(P, pc, "copy");
 }
 
 // ------------------------------------------------------------------ allocation
@@ -608,6 +625,7 @@ void carve(Ctx& X, Carver& cv) {
     B.S = cv.take<double>((size_t)rx);
     B.V = cv.take<double>((size_t)nm * rx);
     B.sign = cv.take<double>((size_t)rx);
+    B.keep = cv.take<double>((size_t)rx);
     B.SVt = cv.take<double>((size_t)rx * nm);
   }
   // initialization scratch (FP64): Gram / triangular factors and a core-sized temp
@@ -624,6 +642,14 @@ void carve(Ctx& X, Carver& cv) {
   X.iRt = cv.take<double>((size_t)kq * kq);
   X.iTmp = cv.take<double>((size_t)core_max);
   X.iXt = cv.take<double>((size_t)core_max);
+  X.iJ = cv.take<double>((size_t)kq * kq);
+  if (X.o.schedule == MPO_SCHED_EVEN_ODD) {
+    X.iH = cv.take<double>((size_t)kq * kq);
+    X.iZ = cv.take<double>((size_t)kq * kq);
+    X.iEw = cv.take<double>(eig_work_doubles((int)kq, (int)kq));
+    X.iEv = cv.take<double>((size_t)kq);
+    X.iSg = cv.take<double>((size_t)kq);
+  }
   X.iTmpN = core_max;
   // split-K partial tiles and their counters
   X.sb.cap = (size_t)512 * 128 * 128 * 8;
@@ -685,7 +711,7 @@ void rec_left_orth(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores
     const int p = cur[i] * dd, q = chi_in[i + 1];
     const int nn = dd * chi_in[i + 2];  // columns of the next core (its right bond untouched yet)
     if (p >= q) {
-      add_cholqr(X, P, {CholQRJob{cores[i], p, q, q, X.iG, X.iR1, X.iRt, nullptr}}, 2);
+      add_cholqr(X, P, {CholQRJob{cores[i], p, q, q, X.iG, X.iR1, X.iRt, nullptr, true}}, 3);
       add_gemm(P, X.sb, Mode::F64, {GemmJob{q, nn, q, op64(X.iRt, true, q), op64(cores[i + 1], false, nn),
                                             out64(X.iTmp, nn)}}, "init", 0);
       cur[i + 1] = q;
@@ -712,7 +738,7 @@ void rec_right_orth(Ctx& X, Program& P, PairState& S) {
     if (p <= q) {
       // X^T = Q R (R_jj > 0), X = R^T Q^T: work on the transpose
       add_perm(P, {perm4(S.C64[j], 0, X.iXt, 0, {1, 1, p, q}, {0, 0, q, 1}, {0, 0, 1, p})}, "copy");
-      add_cholqr(X, P, {CholQRJob{X.iXt, q, p, p, X.iG, X.iR1, X.iRt, nullptr}}, 2);
+      add_cholqr(X, P, {CholQRJob{X.iXt, q, p, p, X.iG, X.iR1, X.iRt, nullptr, true}}, 3);
       add_perm(P, {perm4(X.iXt, 0, S.C64[j], 0, {1, 1, q, p}, {0, 0, p, 1}, {0, 0, 1, q})}, "copy");
       add_gemm(P, X.sb, Mode::F64, {GemmJob{mp, p, p, op64(S.C64[j - 1], true, p), op64(X.iRt, true, p),
                                             out64(X.iTmp, p)}}, "init", 0);
@@ -859,7 +885,7 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
     if (b.k <= kRegMax)  // register path: Z = Q X afterwards
       zq.push_back(GemmJob{b.k, b.r, b.k, op64(eig_work_qt(B.eigw, b.k, b.r), false, b.k),
                            op64(eig_work_x(B.eigw, b.k, b.r), false, b.r), out64(B.Z, b.r)});
-    sv.push_back(SvalDesc{B.evals, B.S, b.r, halfstep ? 1 : 0, X.flag});
+    sv.push_back(SvalDesc{B.evals, B.S, b.r, halfstep ? 1 : 0, X.flag, B.keep, X.flag + 2});
     maxr = std::max(maxr, b.r);
   }
   add_gemm(P, X.sb, X.wmode, th, "theta", fth);
@@ -998,8 +1024,11 @@ void rec_serial_bond(Ctx& X, Program& P, PairState& S, int pair, int i, bool fwd
 }
 
 // Inverse canonical form of the right-canonical C (Sec. 2.3.1): a left-to-
-// right SVD sweep X_i = carry C_i = U S V^T (from the eigenpairs of X^T X),
-// Psi_i = U S, S kept per bond (Y_i = 1/S), carry S V^T into the next core.
+// right SVD sweep X_i = carry C_i = U S V^T, Psi_i = U S, S kept per bond
+// (Y_i = 1/S), carry S V^T into the next core.  The SVD keeps small singular
+// values accurate (A's Schmidt values can span many orders of magnitude):
+// shifted CholeskyQR3 X = Q R, then one-sided Jacobi on R Z (Z from the
+// eigenvectors of R^T R as a preconditioner).
 // Then the environments: L_{i+1} from Psi_i Y_i = U_i, R_j from
 // Y_{j-1} Psi_j (rows of Psi_j divided by S_{j-1}).
 void rec_inverse_canonical(Ctx& X, Program& P, PairState& S) {
@@ -1007,32 +1036,46 @@ void rec_inverse_canonical(Ctx& X, Program& P, PairState& S) {
   BondScratch& B = X.scratch[0];
   for (int i = 0; i + 1 < L; ++i) {
     const int p = S.cC[i] * dd, q = S.cC[i + 1], nn = dd * S.cC[i + 2];
+    if (q > 512 || p < q) throw Error{MPO_ERR_UNSUPPORTED, "inverse canonical form: bond above 512"};
     double* Xi = S.C64[i];
-    add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, p, op64(Xi, false, q), op64(Xi, false, q), out64(B.H, q)}},
-             "init", 0);
+    // X = Q R (shifted CholeskyQR3; R accumulated in iRt)
+    add_cholqr(X, P, {CholQRJob{Xi, p, q, q, X.iG, X.iR1, X.iRt, nullptr, true}}, 3);
+    // precondition: W0 = R Z with Z the eigenvectors of R^T R (its columns
+    // are then orthogonal up to clusters of tiny singular values), then
+    // one-sided Jacobi on W0: W0 V' = Ur diag(S) with high relative accuracy
+    add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(X.iRt, false, q), op64(X.iRt, false, q),
+                                          out64(X.iH, q)}}, "init", 0);
     const bool reg = q <= kRegMax;
-    add_eig(P, {EigDesc{B.H, q, q, q, B.evals, B.Z, q, B.eigw, X.flag}}, reg, "init");
+    add_eig(P, {EigDesc{X.iH, q, q, q, X.iEv, X.iZ, q, X.iEw, X.flag}}, reg, "init");
     if (reg)
-      add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(eig_work_qt(B.eigw, q, q), false, q),
-                                            op64(eig_work_x(B.eigw, q, q), false, q), out64(B.Z, q)}},
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(eig_work_qt(X.iEw, q, q), false, q),
+                                            op64(eig_work_x(X.iEw, q, q), false, q), out64(X.iZ, q)}},
                "init", 0);
-    add_simple(P, LK::Sval, std::vector<SvalDesc>{SvalDesc{B.evals, S.Yv[i + 1], q, 1, X.flag}}, q, "init");
-    // U = X V / S (into Y), orthonormalized; sign rule on U, applied to V
-    add_gemm(P, X.sb, Mode::F64, {GemmJob{p, q, q, op64(Xi, true, q), op64(B.Z, false, q), out64(B.Y, q)}},
-             "init", 0);
-    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{B.Y, B.Y, p, q, q, q, nullptr, S.Yv[i + 1], 0, 1}},
-               (long long)p * q, "init");
-    add_cholqr(X, P, {CholQRJob{B.Y, p, q, q, B.G, B.R, nullptr, q <= kRegMax ? B.Y2 : nullptr}}, 1);
-    add_simple(P, LK::Sign, std::vector<SignDesc>{SignDesc{B.Y, p, q, q, B.sign, nullptr}}, q, "init");
-    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{B.Z, B.Z, q, q, q, q, nullptr, B.sign, 0, 0}},
+    add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(X.iRt, true, q), op64(X.iZ, false, q),
+                                          out64(X.iG, q)}}, "init", 0);
+    {
+      Launch l;
+      l.kind = LK::Jacobi;
+      l.off = P.push(std::vector<JacobiDesc>{
+          JacobiDesc{X.iG, q, q, X.iR2, q, S.Yv[i + 1], X.iJ, kInvTrunc, X.flag + 2}});
+      l.n = 1;
+      l.maxa = q;
+      l.cls = "init";
+      P.launches.push_back(l);
+    }
+    // U = Q Ur (into iTmp), sign rule on U, the same flips on Ur
+    add_gemm(P, X.sb, Mode::F64, {GemmJob{p, q, q, op64(Xi, true, q), op64(X.iR2, false, q),
+                                          out64(X.iTmp, q)}}, "init", 0);
+    add_simple(P, LK::Sign, std::vector<SignDesc>{SignDesc{X.iTmp, p, q, q, X.iSg, nullptr}}, q, "init");
+    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{X.iR2, X.iR2, q, q, q, q, nullptr, X.iSg, 0, 0}},
                (long long)q * q, "init");
     // Psi_i = U S
-    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{B.Y, Xi, p, q, q, q, nullptr, S.Yv[i + 1], 0, 0}},
+    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{X.iTmp, Xi, p, q, q, q, nullptr, S.Yv[i + 1], 0, 0}},
                (long long)p * q, "init");
-    // carry: next <- (S V^T) next
-    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{B.Z, B.Z, q, q, q, q, nullptr, S.Yv[i + 1], 0, 0}},
-               (long long)q * q, "init");
-    add_gemm(P, X.sb, Mode::F64, {GemmJob{q, nn, q, op64(B.Z, false, q), op64(S.C64[i + 1], false, nn),
+    // carry S V^T = Ur^T R (W0 V' = R Z V' = Ur S), into the next core
+    add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(X.iR2, false, q), op64(X.iRt, false, q),
+                                          out64(X.iG, q)}}, "init", 0);
+    add_gemm(P, X.sb, Mode::F64, {GemmJob{q, nn, q, op64(X.iG, true, q), op64(S.C64[i + 1], false, nn),
                                           out64(X.iTmp, nn)}}, "init", 0);
     add_perm(P, {perm4(X.iTmp, 0, S.C64[i + 1], 0, {1, 1, q, nn}, {0, 0, nn, 1}, {0, 0, nn, 1})}, "init");
   }
@@ -1064,7 +1107,8 @@ void rec_assign_inverse(Ctx& X, Program& P, std::vector<BondJob>& bj) {
   std::vector<PermDesc> cp, perm;
   std::vector<CholQRJob> orthU, orthV;
   std::vector<SignDesc> sg;
-  std::vector<ScaleDesc> sv1, sv2, su, sv3;
+  std::vector<ScaleDesc> sv1, sv2, su, sv3, mk;
+  std::vector<PermDesc> cpS;
   double fenv = 0;
   int maxr = 1;
   long long maxsc = 1;
@@ -1106,7 +1150,11 @@ void rec_assign_inverse(Ctx& X, Program& P, std::vector<BondJob>& bj) {
     sv3.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 0});   // V S
     perm.push_back(perm4(B.V, 0, Cn, 0, {r, cr, dd, 1}, {1, (long long)dd * r, r, 0},
                          {(long long)dd * cr, 1, cr, 0}));                  // Psi_{i+1} = S V^T
-    cp.push_back(perm4(B.S, 0, S.Yv[i + 1], 0, {1, 1, 1, r}, {0, 0, 0, 1}, {0, 0, 0, 1}));
+    cpS.push_back(perm4(B.S, 0, S.Yv[i + 1], 0, {1, 1, 1, r}, {0, 0, 0, 1}, {0, 0, 0, 1}));
+    // truncation before inversion: zero U, V columns and S for dropped values
+    mk.push_back(ScaleDesc{Ci, Ci, b.n, r, r, r, nullptr, B.keep, 0, 0});
+    mk.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.keep, 0, 0});
+    mk.push_back(ScaleDesc{B.S, B.S, 1, r, r, r, nullptr, B.keep, 0, 0});
     maxr = std::max(maxr, r);
     maxsc = std::max(maxsc, (long long)std::max(b.n, b.m) * r);
   }
@@ -1118,11 +1166,13 @@ void rec_assign_inverse(Ctx& X, Program& P, std::vector<BondJob>& bj) {
   add_cholqr(X, P, orthV, 1);
   add_simple(P, LK::Sign, sg, maxr, "sign");
   add_simple(P, LK::Scale, sv2, maxsc, "scale");
+  add_simple(P, LK::Scale, mk, maxsc, "scale");
   add_gemm(P, X.sb, X.wmode, envl, "env_update", fenv / 2);
   add_gemm(P, X.sb, X.wmode, envr, "env_update", fenv / 2);
   add_simple(P, LK::Scale, su, maxsc, "scale");
   add_simple(P, LK::Scale, sv3, maxsc, "scale");
   add_perm(P, perm, "copy");
+  add_perm(P, cpS, "copy");
 }
 
 // One half-step q of the even/odd schedule (all pairs): bonds with
@@ -1280,14 +1330,15 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
 }
 
 void check_flags(Ctx& X) {
-  int f = 0;
-  HIP_OK(hipMemcpyAsync(&f, X.flag, sizeof(int), hipMemcpyDeviceToHost, X.stream));
+  int fl[4] = {0, 0, 0, 0};
+  HIP_OK(hipMemcpyAsync(fl, X.flag, sizeof(fl), hipMemcpyDeviceToHost, X.stream));
   HIP_OK(hipStreamSynchronize(X.stream));
+  X.n_trunc = fl[2];
+  const int f = fl[0];
   if (f) {
     std::string m = "device status:";
     if (f & FLAG_NONFINITE) m += " non-finite value;";
     if (f & FLAG_CHOL) m += " Cholesky pivot <= 0;";
-    if (f & FLAG_GUARD) m += " singular value <= 1e-14 sigma_1 in the inverse gauge;";
     if (f & FLAG_EIG) m += " eigenvalue bracket;";
     throw Error{MPO_ERR_NUMERIC, m};
   }
@@ -1532,6 +1583,13 @@ mpo_status mpo_fit_sweeps_done(const mpo_fit_ctx* ctx, int32_t* n) {
   return guarded([&] {
     if (!ctx || !n) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
     *n = ctx->X.sweeps_done;
+  });
+}
+
+mpo_status mpo_fit_truncations(const mpo_fit_ctx* ctx, int64_t* n) {
+  return guarded([&] {
+    if (!ctx || !n) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    *n = ctx->X.n_trunc;
   });
 }
 

@@ -1,0 +1,70 @@
+"""The batched even/odd configuration at its full size: L=64, d=2,
+chi_A=chi_B=128 with exp(-k/6) bond weights, chi_C=256, sketch p=16.
+
+The initial guess in inverse canonical form (A right-orthogonalized, then the
+left-to-right SVD sweep with truncation of singular values <= 1e-12 sigma_1
+before inversion) is compared element by element, through the exported
+merged train, with the oracle's.  The sweeps are checked on properties that
+hold at any size: bond dimensions follow the plan, the truncations are
+counted, the exported train is finite, and the fit error does not grow."""
+import numpy as np
+import pytest
+
+from oracle import canon, mpo
+from oracle import fit as ofit
+from synth import make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pair():
+    return make_pair(64, 2, 128, seed=0, decay=True)
+
+
+def test_init_parity_full_size(pair):
+    from paper_2606_23274_amd.api import FitContext
+    A, B = pair
+    ctx = FitContext([(A, B)], 256, precision="fp64", schedule="even_odd", sketch_p=16, seed=0)
+    try:
+        C = ctx.export_numpy(0)
+        n_gpu = ctx.truncations()
+    finally:
+        ctx.close()
+    A1, B1, nu, _ = ofit._preprocess(A, B)
+    Psi, Y, n_orc = canon.inverse_canonical(canon.right_orthogonalize(A1))
+    ref = canon.merge_inverse_canonical(Psi, Y)
+    ref[0] = ref[0] * nu
+    assert [c.shape for c in C] == [c.shape for c in ref]
+    assert mpo.rel_diff(C, ref) < 1e-10
+    # the count depends on values within rounding of the threshold only
+    assert n_orc > 0 and abs(n_gpu - n_orc) <= max(2, n_orc // 10)
+
+
+def _gap(A, B, C):
+    """||C||^2 - 2 <C, A B> = eps^2 ||AB||^2 - ||AB||^2: the fit error up to
+    a constant, from a two- and a three-layer transfer pass."""
+    return mpo.left_orth_norm(C) ** 2 - 2.0 * mpo.three_layer_inner(C, A, B)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_sweeps_full_size(pair, precision):
+    from paper_2606_23274_amd.api import FitContext
+    A, B = pair
+    ctx = FitContext([(A, B)], 256, precision=precision, schedule="even_odd", sketch_p=16, seed=0)
+    try:
+        gaps = [_gap(A, B, ctx.export_numpy(0))]
+        for s in range(2):
+            ctx.sweep(1)
+            C = ctx.export_numpy(0)
+            assert all(np.isfinite(c).all() for c in C)
+            gaps.append(_gap(A, B, C))
+        dims = ctx.bond_dims(0)
+    finally:
+        ctx.close()
+    print(precision, "gaps", gaps)
+    plan = [min(256, 4 ** min(b, 64 - b)) for b in range(65)]
+    assert dims == plan
+    scale = abs(gaps[0])
+    assert gaps[1] < gaps[0] - 1e-3 * scale      # the first sweep improves on the guess A
+    assert gaps[2] <= gaps[1] + 1e-6 * scale     # and the second does not undo it

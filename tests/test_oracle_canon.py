@@ -74,3 +74,42 @@ def test_sign_rule():
     U = np.array([[0.1, -0.9], [-0.8, 0.2], [0.3, 0.9]])
     s = canon.sign_fix_columns(U)
     assert list(s) == [-1.0, -1.0]  # first index wins the tie in column 2
+
+
+def test_inverse_canonical_truncates_tiny_schmidt_values():
+    """A train whose middle bond carries one Schmidt value of relative size
+    1e-15: it is truncated before inversion (zero S, Y and singular vectors),
+    the merged train reproduces the operator to that size, and Psi Y stays a
+    partial isometry (identity on the kept directions, zero on the dropped)."""
+    rng = np.random.default_rng(7)
+    L, d, chi = 4, 2, 3
+    # left-orthonormal cores with a prescribed spectrum at bond 2 (0-based 1)
+    lam = np.array([1.0, 0.5, 1e-15])
+    cores = []
+    dims = [1, 4, 3, 4, 1]
+    for l in range(L):
+        a, b = dims[l], dims[l + 1]
+        X = rng.standard_normal((a * d * d, b))
+        Q, _ = np.linalg.qr(X) if a * d * d >= b else (np.eye(a * d * d, b), None)
+        cores.append(Q[:, :b].reshape(a, d, d, b))
+    cores[1] = cores[1] * lam[None, None, None, :]
+    # right-canonicalize, which keeps the Schmidt spectrum of the operator
+    Cr = canon.right_orthogonalize(cores)
+    D0 = mpo.dense(Cr)
+    Psi, Y, n_trunc = canon.inverse_canonical(Cr)
+    assert n_trunc == 1
+    assert np.count_nonzero(Y[1]) == 2 and Y[1][2] == 0.0
+    C = canon.merge_inverse_canonical(Psi, Y)
+    assert np.linalg.norm(mpo.dense(C) - D0) <= 1e-14 * np.linalg.norm(D0)
+    W = (Psi[1] * Y[1][None, None, None, :]).reshape(-1, 3)
+    assert np.allclose(W.T @ W, np.diag([1.0, 1.0, 0.0]), atol=1e-12)
+
+
+def test_truncate_inverse_rule():
+    U = np.eye(3)
+    S = np.array([2.0, 1e-11, 1e-13])
+    Vt = np.eye(3)
+    U2, S2, Vt2, Y, n = canon.truncate_inverse(U, S, Vt, 1e-12)
+    assert n == 1 and list(S2) == [2.0, 1e-11, 0.0]
+    assert np.allclose(Y, [0.5, 1e11, 0.0])
+    assert not U2[:, 2].any() and not Vt2[2].any()
