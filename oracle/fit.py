@@ -133,6 +133,8 @@ class FitResult:
     n_guard: int
     ks: list
     records: list = field(default_factory=list)
+    C_norm: list = field(default_factory=list)  # C before the norms are put back
+    centre: int = 0  # 0-based site of the orthogonality centre (serial schedule)
 
 
 def _preprocess(A, B):
@@ -197,7 +199,8 @@ def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
     out = [c.copy() for c in C]
     out[0] = out[0] * nu
     dims = [1] + [c.shape[3] for c in C]
-    return FitResult(out, nu, dims, min_gap, n_guard, ks)
+    centre = L - 1 if n_sweeps % 2 == 1 else 0
+    return FitResult(out, nu, dims, min_gap, n_guard, ks, C_norm=[c.copy() for c in C], centre=centre)
 
 
 def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
