@@ -151,22 +151,37 @@ mpo_status mpo_fit_export_c(mpo_fit_ctx* ctx, int32_t pair, double* const* c_cor
 /* Number of sweeps run so far. */
 mpo_status mpo_fit_sweeps_done(const mpo_fit_ctx* ctx, int32_t* n);
 
+/* The factor nu = ||A|| ||B|| split off by the preprocessing (Alg. 5): the
+   fit runs on normalized cores and mpo_fit_export_c multiplies core 0 by nu. */
+mpo_status mpo_fit_norm_factor(const mpo_fit_ctx* ctx, int32_t pair, double* nu);
+
 /* Even/odd schedule: number of singular values truncated before inversion
    so far (initialization and sweeps, all pairs), as of the last call that
    synchronized (mpo_fit_init, mpo_fit_sweep). */
 mpo_status mpo_fit_truncations(const mpo_fit_ctx* ctx, int64_t* n);
 
-/* Gradient of loss(A, B) = <W, P(A B)>_F with respect to every core of A and
-   B, where P is the orthogonal projector onto the MPOs that share C's
-   isometries after the last sweep (the frozen truncation bases) and have a
-   free bond matrix at the orthogonality centre; equivalently
-   loss = <P(W), A B>_F.  W is an MPO on the same sites (device FP64 cores).
-   gA and gB are caller-owned device arrays shaped like the cores of A and B
-   as passed to mpo_fit_init.  *loss (host) receives the loss; the call
-   synchronizes the stream.  Serial schedule only.  `recompute_env` = 1 keeps
-   only every ceil(sqrt(L))-th left environment and recomputes the rest. */
-mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_tt* W, double* const* gA,
-                        double* const* gB, double* loss, int32_t recompute_env);
+/* Gradient at frozen truncation bases (not a step of the paper's method; it
+   differentiates the fit's result).  After the last sweep C is site-canonical
+   with its centre at the last site (after a forward sweep) or the first
+   (otherwise, Alg. 3); every other core is an isometry.  With those frozen,
+   the fit of a product X is the orthogonal projection Pi(X) onto the MPOs
+   that share them and have a free centre core.  For an MPO W on the same
+   sites (FP64 device cores):
+       loss(A, B) = <W, Pi(A B)>_F = <Pi(W), A B>_F,
+   linear in every core; gA[l] = d loss / d A_l and gB[l] = d loss / d B_l are
+   written into caller-owned FP64 device arrays shaped like the cores of
+   `ab`, which must have the bond dimensions of the fitted pair (usually the
+   same A and B; other values give the gradient there, at the same bases).
+   Arithmetic: FP64 for an FP64 fit, FP32 otherwise.  `recompute_env` = 1
+   stores only every ceil(sqrt(L))-th right environment and recomputes the
+   others segment by segment.  Serial schedule only.  `workspace` (256-byte
+   aligned) of mpo_fit_grad_workspace_bytes bytes; *loss (host) receives the
+   loss; synchronizes the context stream. */
+mpo_status mpo_fit_grad_workspace_bytes(const mpo_fit_ctx* ctx, int32_t pair, const mpo_tt* W,
+                                        int32_t recompute_env, size_t* bytes);
+mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_pair* ab, const mpo_tt* W,
+                        double* const* gA, double* const* gB, double* loss, int32_t recompute_env,
+                        void* workspace, size_t ws_bytes);
 
 /* Fit error ||A B - C||_F / ||A B||_F in FP64 from transfer passes:
    ||AB||^2 by a four-layer pass, <C, AB> by a three-layer pass and ||C||^2

@@ -113,6 +113,42 @@ class FitContext:
         _lib.check(self.lib.mpo_fit_sweeps_done(self.ctx, C.byref(n)))
         return n.value
 
+    def norm_factor(self, pair=0):
+        """nu = ||A|| ||B|| split off by the preprocessing (export = nu * core 0)."""
+        v = C.c_double()
+        _lib.check(self.lib.mpo_fit_norm_factor(self.ctx, pair, C.byref(v)))
+        return v.value
+
+    def grad(self, W, A=None, B=None, pair=0, recompute_env=False):
+        """loss = <W, Pi(A B)> at the frozen truncation bases of the last sweep
+        and its gradient (mpo_fit_grad): returns (loss, [dA_l], [dB_l]) with
+        float64 device tensors.  A, B default to the fitted pair."""
+        su = self._setup
+        if A is None:
+            A = [t for t in su.tts[2 * pair].cores]
+        if B is None:
+            B = [t for t in su.tts[2 * pair + 1].cores]
+        ta = _TT(_dev_cores(A, self.device))
+        tb = _TT(_dev_cores(B, self.device))
+        tw = _TT(_dev_cores(W, self.device))
+        ab = _lib.MpoPair(ta.tt, tb.tt, 0)
+        nbytes = C.c_size_t()
+        _lib.check(self.lib.mpo_fit_grad_workspace_bytes(self.ctx, pair, C.byref(tw.tt),
+                                                         int(bool(recompute_env)), C.byref(nbytes)))
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        ws_ptr = (ws.data_ptr() + 255) & ~255
+        gA = [torch.empty_like(t) for t in ta.cores]
+        gB = [torch.empty_like(t) for t in tb.cores]
+        pa = (C.c_void_p * len(gA))(*[g.data_ptr() for g in gA])
+        pb = (C.c_void_p * len(gB))(*[g.data_ptr() for g in gB])
+        loss = C.c_double()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        _lib.check(self.lib.mpo_fit_grad(self.ctx, pair, C.byref(ab), C.byref(tw.tt), pa, pb,
+                                         C.byref(loss), int(bool(recompute_env)), C.c_void_p(ws_ptr),
+                                         nbytes.value))  # synchronizes our stream
+        self.last_grad_workspace_bytes = nbytes.value
+        return loss.value, gA, gB
+
     def truncations(self):
         """Singular values truncated before inversion so far (even/odd)."""
         v = C.c_int64()
@@ -196,3 +232,25 @@ def autotune(pairs, chi_max, precision="fp32", schedule="serial", sketch_p=-1, s
                                         su.workspace_bytes, C.c_void_p(stream.cuda_stream), int(reps),
                                         out, cap, C.byref(n)))
     return [tune_mod.entry_to_dict(out[i]) for i in range(n.value)]
+
+
+class FitContract(torch.autograd.Function):
+    """loss = <W, Pi(A B)>_F at the frozen truncation bases of a fit (the
+    state of `fit_ctx` after its last sweep), differentiable in every core of
+    A and B through the library's adjoint (mpo_fit_grad):
+
+        loss = FitContract.apply(fit_ctx, W, *A_cores, *B_cores)
+        loss.backward()
+    """
+
+    @staticmethod
+    def forward(ctx, fit_ctx, W, *cores):
+        L = len(cores) // 2
+        loss, gA, gB = fit_ctx.grad(W, list(cores[:L]), list(cores[L:]),
+                                    recompute_env=getattr(fit_ctx, "recompute_env", False))
+        ctx.save_for_backward(*gA, *gB)
+        return torch.tensor(loss, dtype=torch.float64, device=cores[0].device)
+
+    @staticmethod
+    def backward(ctx, g):
+        return (None, None, *[g * t for t in ctx.saved_tensors])

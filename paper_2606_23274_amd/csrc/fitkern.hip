@@ -123,17 +123,26 @@ __global__ void scale_kernel(const ScaleDesc* __restrict__ descs) {
 
 __global__ void perm_kernel(const PermDesc* __restrict__ descs) {
   const PermDesc d = descs[blockIdx.y];
-  const long long n = (long long)d.n[0] * d.n[1] * d.n[2] * d.n[3];
+  const long long n4 = (long long)d.n[0] * d.n[1] * d.n[2] * d.n[3];
+  const long long n45 = (long long)d.n[4] * d.n[5];
+  const long long n = n4 * n45;
   float amax = 0.f;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x) {
     long long r = e;
+    long long ii = 0, oo = 0;
+    if (n45 != 1) {  // uniform: the two extra axes
+      const int i5 = (int)(r % d.n[5]); r /= d.n[5];
+      const int i4 = (int)(r % d.n[4]); r /= d.n[4];
+      ii = i4 * d.si[4] + i5 * d.si[5];
+      oo = i4 * d.so[4] + i5 * d.so[5];
+    }
     const int i3 = (int)(r % d.n[3]); r /= d.n[3];
     const int i2 = (int)(r % d.n[2]); r /= d.n[2];
     const int i1 = (int)(r % d.n[1]);
     const int i0 = (int)(r / d.n[1]);
-    const long long ii = i0 * d.si[0] + i1 * d.si[1] + i2 * d.si[2] + i3 * d.si[3];
-    const long long oo = i0 * d.so[0] + i1 * d.so[1] + i2 * d.so[2] + i3 * d.so[3];
+    ii += i0 * d.si[0] + i1 * d.si[1] + i2 * d.si[2] + i3 * d.si[3];
+    oo += i0 * d.so[0] + i1 * d.so[1] + i2 * d.so[2] + i3 * d.so[3];
     const double v = (d.tin == 0 ? reinterpret_cast<const double*>(d.in)[ii]
                                  : (double)reinterpret_cast<const float*>(d.in)[ii]) * d.scale;
     if (d.tout == 0) reinterpret_cast<double*>(d.out)[oo] = v;

@@ -50,11 +50,13 @@ void launch_scale(const ScaleDesc* d, int n, int max_elems, hipStream_t s);
 // input index is (i0, i1, i2, i3) with extents n[] and strides si[], and the
 // output index uses strides so[] for the same (i0..i3).  Types: 0 = FP64,
 // 1 = FP32.  Scale multiplies every element.
+// Strided copy / permutation of up to 6 axes (axis 5 fastest), with type
+// conversion (0 = FP64, 1 = FP32) and a scale.
 struct PermDesc {
   const void* in;
   void* out;
-  int n[4];
-  long long si[4], so[4];
+  int n[6];
+  long long si[6], so[6];
   int tin, tout;
   double scale;
   unsigned* amax;  // nullable: atomic max of |out| (float bits)

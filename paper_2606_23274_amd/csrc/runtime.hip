@@ -449,10 +449,13 @@ PermDesc perm4(const void* in, int tin, void* out, int tout, std::array<int, 4> 
   PermDesc d{};
   d.in = in; d.out = out; d.tin = tin; d.tout = tout; d.scale = scale;
   for (int q = 0; q < 4; ++q) { d.n[q] = n[q]; d.si[q] = si[q]; d.so[q] = so[q]; }
+  d.n[4] = d.n[5] = 1;
   return d;
 }
 
-long long perm_elems(const PermDesc& d) { return (long long)d.n[0] * d.n[1] * d.n[2] * d.n[3]; }
+long long perm_elems(const PermDesc& d) {
+  return (long long)d.n[0] * d.n[1] * d.n[2] * d.n[3] * d.n[4] * d.n[5];
+}
 
 void add_perm(Program& P, const std::vector<PermDesc>& ds, const char* cls) {
   long long mx = 1;
@@ -1379,6 +1382,333 @@ void record_sweep(Ctx& X, SweepPlan& sp, bool fwd) {
   for (auto& S : X.pairs) sp.cC_after.push_back(S.cC);
 }
 
+
+// ------------------------------------------------------------------ adjoint
+// Gradient of loss(A, B) = <Pi(W), A B> at frozen truncation bases: Pi(W)
+// keeps C's isometries and takes its centre core from the two-layer
+// environment of (isometries, W); the gradient of the multilinear loss with
+// respect to A_l (B_l) is the network with A_l (B_l) removed, closed by the
+// three-layer environments of (Pi(W), A, B) (Sec. 2.3.3, Fig. envs).  Every
+// contraction is one GEMM between operands brought into matrix form by the
+// strided permutation kernel where their axes are not already grouped.
+
+struct Ten {
+  void* p = nullptr;
+  DType t = DType::F64;
+  std::vector<int> dims;
+  long long size() const {
+    long long n = 1;
+    for (int d : dims) n *= d;
+    return n;
+  }
+};
+
+// Bump allocator over a caller workspace (null base: measuring only).
+struct Arena {
+  Carver cv;
+  size_t peak = 0;
+  Ten take(DType t, std::vector<int> dims) {
+    Ten x;
+    x.t = t;
+    x.dims = std::move(dims);
+    x.p = t == DType::F64 ? static_cast<void*>(cv.take<double>(x.size()))
+                          : static_cast<void*>(cv.take<float>(x.size()));
+    peak = std::max(peak, cv.off);
+    return x;
+  }
+};
+
+// out = in with axes reordered: out axis i is in axis perm[i] (row-major).
+void permute(Program& P, const Ten& in, const std::vector<int>& perm, const Ten& out) {
+  const int nd = (int)in.dims.size();
+  if (nd > 6 || (int)perm.size() != nd) throw Error{MPO_ERR_UNSUPPORTED, "permutation of > 6 axes"};
+  std::vector<long long> st(nd, 1);
+  for (int i = nd - 2; i >= 0; --i) st[i] = st[i + 1] * in.dims[i + 1];
+  PermDesc d{};
+  d.in = in.p;
+  d.out = out.p;
+  d.tin = in.t == DType::F64 ? 0 : 1;
+  d.tout = out.t == DType::F64 ? 0 : 1;
+  d.scale = 1.0;
+  for (int q = 0; q < 6; ++q) { d.n[q] = 1; d.si[q] = 0; d.so[q] = 0; }
+  const int off = 6 - nd;
+  long long so = 1;
+  for (int i = nd - 1; i >= 0; --i) {
+    d.n[off + i] = in.dims[perm[i]];
+    d.si[off + i] = st[perm[i]];
+    d.so[off + i] = so;
+    so *= in.dims[perm[i]];
+  }
+  add_perm(P, {d}, "grad_perm");
+}
+
+bool is_iota(const std::vector<int>& v) {
+  for (size_t i = 0; i < v.size(); ++i)
+    if (v[i] != (int)i) return false;
+  return true;
+}
+
+// out[free(a)..., free(b)...] (then reordered by out_order) =
+//   sum over the paired axes ca of a and cb of b.
+void contract(Program& P, Arena& ar, const SplitBuf& sb, Mode mode, const Ten& a,
+              const std::vector<int>& ca, const Ten& b, const std::vector<int>& cb, const Ten& out,
+              const std::vector<int>& out_order, const char* cls) {
+  const int na = (int)a.dims.size(), nb = (int)b.dims.size();
+  if (ca.size() != cb.size()) throw Error{MPO_ERR_SHAPE, "contraction axes"};
+  std::vector<int> fa, fb;
+  for (int i = 0; i < na; ++i)
+    if (std::find(ca.begin(), ca.end(), i) == ca.end()) fa.push_back(i);
+  for (int i = 0; i < nb; ++i)
+    if (std::find(cb.begin(), cb.end(), i) == cb.end()) fb.push_back(i);
+  long long M = 1, K = 1, N = 1;
+  for (int i : fa) M *= a.dims[i];
+  for (int i : fb) N *= b.dims[i];
+  for (size_t q = 0; q < ca.size(); ++q) {
+    if (a.dims[ca[q]] != b.dims[cb[q]]) throw Error{MPO_ERR_SHAPE, "contracted dims differ"};
+    K *= a.dims[ca[q]];
+  }
+  const DType gt = mode == Mode::F64 ? DType::F64 : DType::F32;
+  auto cat = [](std::vector<int> x, const std::vector<int>& y) {
+    x.insert(x.end(), y.begin(), y.end());
+    return x;
+  };
+  auto dims_of = [](const Ten& t, const std::vector<int>& ax) {
+    std::vector<int> d;
+    for (int i : ax) d.push_back(t.dims[i]);
+    return d;
+  };
+  Op oa{a.p, a.t, true, (int)K}, ob{b.p, b.t, false, (int)N};
+  if (!is_iota(cat(fa, ca))) {
+    if (is_iota(cat(ca, fa))) {
+      oa = Op{a.p, a.t, false, (int)M};
+    } else {
+      Ten t = ar.take(gt, cat(dims_of(a, fa), dims_of(a, ca)));
+      permute(P, a, cat(fa, ca), t);
+      oa = Op{t.p, gt, true, (int)K};
+    }
+  }
+  if (!is_iota(cat(cb, fb))) {
+    if (is_iota(cat(fb, cb))) {
+      ob = Op{b.p, b.t, true, (int)K};
+    } else {
+      Ten t = ar.take(gt, cat(dims_of(b, cb), dims_of(b, fb)));
+      permute(P, b, cat(cb, fb), t);
+      ob = Op{t.p, gt, false, (int)N};
+    }
+  }
+  // FP32 modes take an FP32 second operand
+  if (gt == DType::F32 && ob.t != DType::F32) {
+    Ten t = ar.take(gt, {(int)K, (int)N});
+    Ten src{const_cast<void*>(ob.p), ob.t, ob.kc ? std::vector<int>{(int)N, (int)K} : std::vector<int>{(int)K, (int)N}};
+    permute(P, src, ob.kc ? std::vector<int>{1, 0} : std::vector<int>{0, 1}, t);
+    ob = Op{t.p, gt, false, (int)N};
+  }
+  std::vector<int> gdims = cat(dims_of(a, fa), dims_of(b, fb));
+  if (gdims.empty()) gdims = {1};
+  const bool direct = is_iota(out_order) && out.t == gt;
+  Ten g = direct ? out : ar.take(gt, gdims);
+  add_gemm(P, sb, mode, {GemmJob{(int)M, (int)N, (int)K, oa, ob, Out{g.p, gt, (int)N}}}, cls,
+           2.0 * M * N * K);
+  if (!direct) {
+    Ten gg = g;
+    gg.dims = gdims;
+    permute(P, gg, out_order.empty() ? std::vector<int>{0} : out_order, out);
+  }
+}
+
+std::vector<int> iota(int n) {
+  std::vector<int> v(n);
+  for (int i = 0; i < n; ++i) v[i] = i;
+  return v;
+}
+
+struct GradPlan {
+  long long bytes = 0;
+  double* loss_dev = nullptr;
+};
+
+// Records the whole adjoint into P.  Tensors: A, B (the cores to
+// differentiate at, FP64 caller arrays), W (FP64), C (the context's FP64
+// normalized cores, isometries except the centre), gradients into gA, gB.
+void rec_grad(Ctx& X, Program& P, Arena& ar, PairState& S, const mpo_tt& A, const mpo_tt& B,
+              const mpo_tt& W, double* const* gA, double* const* gB, int centre, bool recompute,
+              double* loss_dev) {
+  const int L = S.L, d = S.d;
+  const Mode mode = X.wt == DType::F64 ? Mode::F64 : Mode::F32;
+  const DType wt = mode == Mode::F64 ? DType::F64 : DType::F32;
+  auto core = [&](const mpo_tt& t, int l) {
+    return Ten{const_cast<double*>(t.cores[l]), DType::F64, {t.chi[l], d, d, t.chi[l + 1]}};
+  };
+  // working-precision copies
+  std::vector<Ten> Aw(L), Bw(L), Ww(L), Pw(L);
+  for (int l = 0; l < L; ++l) {
+    Aw[l] = ar.take(wt, core(A, l).dims);
+    permute(P, core(A, l), iota(4), Aw[l]);
+    Bw[l] = ar.take(wt, core(B, l).dims);
+    permute(P, core(B, l), iota(4), Bw[l]);
+    Ww[l] = ar.take(wt, core(W, l).dims);
+    permute(P, core(W, l), iota(4), Ww[l]);
+    const Ten Cl{S.C64[l], DType::F64, {S.cC[l], d, d, S.cC[l + 1]}};
+    if (l != centre) {
+      Pw[l] = ar.take(wt, Cl.dims);
+      permute(P, Cl, iota(4), Pw[l]);
+    }
+  }
+  auto one = [&](std::vector<int> dims) {
+    Ten t = ar.take(wt, dims);
+    add_fill(P, {FillDesc{t.p, 0, 1, 1, wt == DType::F64 ? 1 : 0}});
+    return t;
+  };
+  auto as = [](Ten t, std::vector<int> dims) {  // view of a buffer with other dims
+    t.dims = std::move(dims);
+    return t;
+  };
+  // Pi(W): centre core from the two-layer environment of (isometries, W)
+  {
+    long long emax = 1;
+    for (int l = 0; l <= L; ++l) emax = std::max(emax, (long long)S.cC[l] * W.chi[l]);
+    Ten E0 = ar.take(wt, {(int)emax}), E1 = ar.take(wt, {(int)emax});
+    add_fill(P, {FillDesc{E0.p, 0, 1, 1, wt == DType::F64 ? 1 : 0}});
+    const size_t mark = ar.cv.off;
+    if (centre == L - 1) {
+      Ten E = as(E0, {1, 1});
+      for (int l = 0; l + 1 < L; ++l) {
+        Ten T = ar.take(wt, {Ww[l].dims[0], d, d, Pw[l].dims[3]});
+        contract(P, ar, X.sb, mode, E, {0}, Pw[l], {0}, T, iota(4), "grad_proj");
+        Ten E2 = as(E.p == E0.p ? E1 : E0, {Pw[l].dims[3], Ww[l].dims[3]});
+        contract(P, ar, X.sb, mode, T, {0, 1, 2}, Ww[l], {0, 1, 2}, E2, iota(2), "grad_proj");
+        E = E2;
+        ar.cv.off = mark;
+      }
+      Pw[L - 1] = ar.take(wt, {E.dims[0], d, d, 1});
+      contract(P, ar, X.sb, mode, E, {1}, Ww[L - 1], {0}, Pw[L - 1], iota(4), "grad_proj");
+    } else {
+      Ten F = as(E0, {1, 1});
+      for (int l = L - 1; l >= 1; --l) {
+        Ten T = ar.take(wt, {Pw[l].dims[0], d, d, Ww[l].dims[3]});
+        contract(P, ar, X.sb, mode, Pw[l], {3}, F, {0}, T, iota(4), "grad_proj");
+        Ten F2 = as(F.p == E0.p ? E1 : E0, {Pw[l].dims[0], Ww[l].dims[0]});
+        contract(P, ar, X.sb, mode, T, {1, 2, 3}, Ww[l], {1, 2, 3}, F2, iota(2), "grad_proj");
+        F = F2;
+        ar.cv.off = mark;
+      }
+      Pw[0] = ar.take(wt, {1, d, d, F.dims[0]});
+      contract(P, ar, X.sb, mode, Ww[0], {3}, F, {1}, Pw[0], iota(4), "grad_proj");
+    }
+  }
+  auto env_dims = [&](int l) {  // environment across bond l (left of site l)
+    return std::vector<int>{Pw[std::max(l - 1, 0)].dims[l == 0 ? 0 : 3], A.chi[l], B.chi[l]};
+  };
+  long long emax = 1;
+  for (int l = 0; l <= L; ++l) {
+    const auto e = env_dims(l);
+    emax = std::max(emax, (long long)e[0] * e[1] * e[2]);
+  }
+  auto env_left = [&](const Ten& Le, int l, const Ten& out) {
+    const int x = Le.dims[0], b = Le.dims[2], a2 = A.chi[l + 1], b2 = B.chi[l + 1];
+    Ten T = ar.take(wt, {x, b, d, d, a2});
+    contract(P, ar, X.sb, mode, Le, {1}, Aw[l], {0}, T, iota(5), "grad_env");
+    Ten T2 = ar.take(wt, {x, d, a2, d, b2});
+    contract(P, ar, X.sb, mode, T, {1, 3}, Bw[l], {0, 1}, T2, iota(5), "grad_env");
+    contract(P, ar, X.sb, mode, Pw[l], {0, 1, 2}, T2, {0, 1, 3}, out, iota(3), "grad_env");
+  };
+  auto env_right = [&](const Ten& Re, int l, const Ten& out) {
+    const int a = A.chi[l], b = B.chi[l], x2 = Re.dims[0], b2 = Re.dims[2];
+    Ten T = ar.take(wt, {a, d, d, x2, b2});
+    contract(P, ar, X.sb, mode, Aw[l], {3}, Re, {1}, T, iota(5), "grad_env");
+    Ten X2 = ar.take(wt, {a, d, x2, b, d});
+    contract(P, ar, X.sb, mode, T, {2, 4}, Bw[l], {1, 3}, X2, iota(5), "grad_env");
+    contract(P, ar, X.sb, mode, X2, {1, 2, 4}, Pw[l], {1, 3, 2}, out, {2, 0, 1}, "grad_env");
+  };
+  // right environments: all of them, or every k-th (the others recomputed
+  // per segment of k sites during the left-to-right pass)
+  const int k = recompute ? std::max(1, (int)std::ceil(std::sqrt((double)L))) : 1;
+  std::vector<Ten> Re(L + 1);
+  std::vector<bool> ck(L + 1, false);
+  Re[L] = one({1, 1, 1});
+  ck[L] = true;
+  for (int l = 1; l < L; ++l) {
+    ck[l] = !recompute || l % k == 0;
+    if (ck[l]) Re[l] = ar.take(wt, env_dims(l));
+  }
+  Ten roll[2] = {ar.take(wt, {(int)emax}), ar.take(wt, {(int)emax})};
+  std::vector<Ten> seg(recompute ? k : 0);
+  for (auto& t : seg) t = ar.take(wt, {(int)emax});
+  Ten Lb[2] = {ar.take(wt, {(int)emax}), ar.take(wt, {(int)emax})};
+  const size_t mark = ar.cv.off;  // temporaries above this point, reused per step
+  {
+    Ten cur = Re[L];
+    int f = 0;
+    for (int l = L - 1; l >= 1; --l) {
+      Ten nx = ck[l] ? Re[l] : as(roll[f ^= 1], env_dims(l));
+      env_right(cur, l, nx);
+      cur = nx;
+      ar.cv.off = mark;
+    }
+  }
+  Ten Le = as(Lb[0], {1, 1, 1});
+  add_fill(P, {FillDesc{Le.p, 0, 1, 1, wt == DType::F64 ? 1 : 0}});
+  int seg_hi = 0;  // Re[m] for m <= seg_hi of the current segment are in seg
+  for (int l = 0; l < L; ++l) {
+    if (!ck[l + 1] && l + 1 > seg_hi) {
+      // recompute the right environments of this segment from its checkpoint
+      int top = l + 1;
+      while (!ck[top]) ++top;
+      Ten cur = Re[top];
+      for (int m = top - 1; m >= l + 1; --m) {
+        Re[m] = as(seg[m % k], env_dims(m));
+        env_right(cur, m, Re[m]);
+        cur = Re[m];
+        ar.cv.off = mark;
+      }
+      seg_hi = top - 1;
+    }
+    const Ten& R = Re[l + 1];
+    const int a = A.chi[l], b = B.chi[l], a2 = A.chi[l + 1], b2 = B.chi[l + 1], x = Le.dims[0];
+    const int x2 = Pw[l].dims[3];
+    // dA[a, s, t, a'] = sum Le[x, a, b] P[x, s, u, x'] B[b, t, u, b'] R[x', a', b']
+    {
+      Ten V1 = ar.take(wt, {x, a, d, d, b2});
+      contract(P, ar, X.sb, mode, Le, {2}, Bw[l], {0}, V1, iota(5), "grad_adj");
+      Ten V2 = ar.take(wt, {a, d, b2, d, x2});
+      contract(P, ar, X.sb, mode, V1, {0, 3}, Pw[l], {0, 2}, V2, iota(5), "grad_adj");
+      const Ten G{gA[l], DType::F64, {a, d, d, a2}};
+      contract(P, ar, X.sb, mode, V2, {2, 4}, R, {2, 0}, G, {0, 2, 1, 3}, "grad_adj");
+      ar.cv.off = mark;
+    }
+    // dB[b, t, u, b'] = sum Le[x, a, b] P[x, s, u, x'] A[a, s, t, a'] R[x', a', b']
+    {
+      Ten V1 = ar.take(wt, {x, b, d, d, a2});
+      contract(P, ar, X.sb, mode, Le, {1}, Aw[l], {0}, V1, iota(5), "grad_adj");
+      Ten V2 = ar.take(wt, {b, d, a2, d, x2});
+      contract(P, ar, X.sb, mode, V1, {0, 2}, Pw[l], {0, 1}, V2, iota(5), "grad_adj");
+      const Ten G{gB[l], DType::F64, {b, d, d, b2}};
+      contract(P, ar, X.sb, mode, V2, {2, 4}, R, {1, 0}, G, iota(4), "grad_adj");
+      ar.cv.off = mark;
+    }
+    Ten Ln = as(Le.p == Lb[0].p ? Lb[1] : Lb[0], env_dims(l + 1));
+    env_left(Le, l, Ln);
+    Le = Ln;
+    ar.cv.off = mark;
+  }
+  permute(P, Ten{Le.p, wt, {1}}, {0}, Ten{loss_dev, DType::F64, {1}});
+}
+
+int grad_centre(const Ctx& X) {
+  if (X.o.schedule != MPO_SCHED_SERIAL) throw Error{MPO_ERR_UNSUPPORTED, "gradient: serial schedule only"};
+  return X.sweeps_done % 2 == 1 ? -1 : 0;  // -1: last site
+}
+
+void validate_grad(const Ctx& X, const PairState& S, const mpo_pair* ab, const mpo_tt* W) {
+  if (!ab || !W) throw Error{MPO_ERR_INVALID_ARG, "null pair or W"};
+  validate_tt(ab->A, S.L, S.d);
+  validate_tt(ab->B, S.L, S.d);
+  validate_tt(*W, S.L, S.d);
+  for (int l = 0; l <= S.L; ++l)
+    if (ab->A.chi[l] != S.chiA_in[l] || ab->B.chi[l] != S.chiB_in[l])
+      throw Error{MPO_ERR_SHAPE, "A and B must have the fitted bond dimensions"};
+  (void)X;
+}
 }  // namespace
 }  // namespace mpofit
 
@@ -1586,6 +1916,14 @@ mpo_status mpo_fit_sweeps_done(const mpo_fit_ctx* ctx, int32_t* n) {
   });
 }
 
+mpo_status mpo_fit_norm_factor(const mpo_fit_ctx* ctx, int32_t pair, double* nu) {
+  return guarded([&] {
+    if (!ctx || !nu) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    if (pair < 0 || pair >= (int)ctx->X.pairs.size()) throw Error{MPO_ERR_INVALID_ARG, "bad pair"};
+    *nu = ctx->X.pairs[pair].nu;
+  });
+}
+
 mpo_status mpo_fit_truncations(const mpo_fit_ctx* ctx, int64_t* n) {
   return guarded([&] {
     if (!ctx || !n) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
@@ -1702,10 +2040,54 @@ mpo_status mpo_gemm_autotune(const mpo_pair* pairs, int32_t n_pairs, const mpo_f
   });
 }
 
-mpo_status mpo_fit_grad(mpo_fit_ctx*, int32_t, const mpo_tt*, double* const*, double* const*, double*,
-                        int32_t) {
-  g_last_error = "gradient not built yet";
-  return MPO_ERR_UNSUPPORTED;
+mpo_status mpo_fit_grad_workspace_bytes(const mpo_fit_ctx* ctx, int32_t pair, const mpo_tt* W,
+                                        int32_t recompute_env, size_t* bytes) {
+  return guarded([&] {
+    if (!ctx || !W || !bytes) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    Ctx& X = const_cast<Ctx&>(ctx->X);
+    if (pair < 0 || pair >= (int)X.pairs.size()) throw Error{MPO_ERR_INVALID_ARG, "bad pair index"};
+    PairState& S = X.pairs[pair];
+    const int centre = grad_centre(X) < 0 ? S.L - 1 : 0;
+    validate_tt(*W, S.L, S.d);
+    std::vector<const double*> nulls(S.L, nullptr);
+    std::vector<double*> gnull(S.L, nullptr);
+    mpo_tt A{S.L, S.d, S.chiA_in.data(), nulls.data()}, B{S.L, S.d, S.chiB_in.data(), nulls.data()};
+    Program P;
+    Arena ar;
+    ar.cv.off = 256;  // the loss slot
+    rec_grad(X, P, ar, S, A, B, *W, gnull.data(), gnull.data(), centre, recompute_env != 0, nullptr);
+    *bytes = ar.peak + 256;
+  });
+}
+
+mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_pair* ab, const mpo_tt* W,
+                        double* const* gA, double* const* gB, double* loss, int32_t recompute_env,
+                        void* workspace, size_t ws_bytes) {
+  return guarded([&] {
+    if (!ctx || !gA || !gB || !loss || !workspace) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) throw Error{MPO_ERR_WORKSPACE, "workspace not 256-byte aligned"};
+    Ctx& X = ctx->X;
+    if (pair < 0 || pair >= (int)X.pairs.size()) throw Error{MPO_ERR_INVALID_ARG, "bad pair index"};
+    PairState& S = X.pairs[pair];
+    const int centre = grad_centre(X) < 0 ? S.L - 1 : 0;
+    validate_grad(X, S, ab, W);
+    for (int l = 0; l < S.L; ++l)
+      if (!gA[l] || !gB[l]) throw Error{MPO_ERR_INVALID_ARG, "null gradient core"};
+    Program P;
+    Arena ar;
+    ar.cv.base = static_cast<char*>(workspace);
+    ar.cv.off = 256;
+    double* loss_dev = static_cast<double*>(workspace);
+    rec_grad(X, P, ar, S, ab->A, ab->B, *W, gA, gB, centre, recompute_env != 0, loss_dev);
+    if (ar.peak > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "gradient workspace too small"};
+    const size_t arena_mark = X.arena_used;
+    upload(X, P);
+    run_program(P, X.stream, nullptr);
+    HIP_OK(hipMemcpyAsync(loss, loss_dev, sizeof(double), hipMemcpyDeviceToHost, X.stream));
+    HIP_OK(hipStreamSynchronize(X.stream));
+    X.arena_used = arena_mark;
+    check_flags(X);
+  });
 }
 
 mpo_status mpo_contract_check_bytes(const mpo_pair*, const mpo_tt*, size_t*) {
