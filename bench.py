@@ -1,13 +1,19 @@
 """Benchmark of the randomized two-site MPO-MPO fit on one MI355X.
 
-One step = one sweep of the serial fit (L-1 two-site updates) of the
-precision workload: L=40, d=2, chi_A=chi_B=64, chi_C=128, decaying-spectrum
-Gaussian cores (seed 0), randomized SVD with p=16 (k=144).  The headline runs
-the contractions in FP32 on the matrix cores (QR, SVD and 1/S in FP64); the
-split-BF16, pure BF16, FP64 and plain (unsketched) FP64 sweeps are reported
-beside it.  Inputs are resident in device memory before timing starts.
+One step = one sweep of the serial fit (L-1 two-site updates, Alg. 5) of the
+precision workload: L=40, d=2, chi_A=chi_B=64, chi_C=128, Gaussian cores with
+exp(-k/6) bond weights (seed 0), randomized SVD with p=16 (k=144).  The
+headline runs the contractions in FP32 on the matrix cores (QR, SVD in FP64),
+with GEMM tiles from the project's autotuner.  Inputs are resident in device
+memory before timing starts.
 
-Prints one JSON line (see the repository documentation for the fields).
+Beside it (unless --quick): the split-BF16, pure-BF16 and FP64 sweeps and the
+plain (unsketched) FP64 sweep; the fit error per sweep of every precision and
+of the FP64 oracle, and the distance to the oracle; the batched even/odd
+schedule at L=64, chi=128, chi_C=256 and over 16 pairs of uneven chi; the
+gradient at frozen bases at L=30, chi=64; the oracle timed on the host.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -22,26 +28,34 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks
+# MI355X published peaks (dense)
 PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "bf16x3": 2.5e15, "fp64": 78.6e12}
-HBM_PEAK = 8.0e12
+WORKLOAD = dict(L=40, d=2, chi=64, chi_c=128, p=16, seed=0)
 # kernel classes timed by the library's profiling mode, and the kernel each
 # one launches (its name in a rocprofv3 kernel trace)
 MFMA_CLASSES = ("theta", "env_update", "env_ext1", "env_ext2", "sketch", "project")
 KERNEL_OF_CLASS = {"qr_chol_inv": "chol_inv_reg_kernel<5>", "eig_tridiag": "sytrd_reg_kernel<5>",
                    "eig_bisect": "bisect_kernel", "eig_vectors": "twisted_kernel",
                    "theta": "gemm_kernel<Mode::F32, float, float, float, true, true, 0|1>"}
-WORKLOAD = dict(L=40, d=2, chi=64, chi_c=128, p=16, seed=0)
+
+
+def bonds_of(L, d, chi):
+    dd = d * d
+    c = [1] + [chi] * (L - 1) + [1]
+    for i in range(1, L + 1):
+        c[i] = min(c[i], c[i - 1] * dd)
+    for i in range(L - 1, -1, -1):
+        c[i] = min(c[i], c[i + 1] * dd)
+    return c
 
 
 def sweep_flops(L, d, chi, chi_c, p, dims_c, sketch=True):
-    """Algorithmic flops of one serial sweep (one fresh extension per bond,
-    dense two-site matrix + sketch + projection, one environment update; the
-    FP64 factorization work separately)."""
+    """Algorithmic flops of one serial sweep: one fresh extension per bond
+    (the other is cached), the dense two-site matrix, sketch and projection
+    when sketched, one environment update; the FP64 factorization apart."""
     dd = d * d
     mfma, f64 = 0.0, 0.0
     chiA = [1] + [chi] * (L - 1) + [1]
-    # preprocessed A/B bond dims (left orthogonalization clips from the left)
     for i in range(1, L + 1):
         chiA[i] = min(chiA[i], chiA[i - 1] * dd)
     for i in range(L - 1):  # bond i joins sites i, i+1
@@ -51,14 +65,13 @@ def sweep_flops(L, d, chi, chi_c, p, dims_c, sketch=True):
         K = a1 * a1
         r = dims_c[i + 1]
         ext = 2.0 * cl * a0 * a0 * dd * a1 + 2.0 * cl * dd * d * a0 * a1 * a1
-        theta = 2.0 * n * m * K
-        env = 2.0 * r * K * n
-        mfma += ext + theta + env
+        mfma += ext + 2.0 * n * m * K + 2.0 * r * K * n
         k = min(chi_c + p, n, m, K) if sketch else min(n, m)
         if sketch and k < min(n, m):
             f64 += 4.0 * n * m * k + 4.0 * n * k * k + 4.0 * m * k * k + 10.0 * k ** 3
         else:
-            f64 += 2.0 * n * n * m + 10.0 * n ** 3
+            s = min(n, m)
+            f64 += 2.0 * s * s * max(n, m) + 10.0 * s ** 3
     return mfma, f64
 
 
@@ -67,11 +80,10 @@ def settled_dims(L, d, chi, chi_c):
     cA = [1] + [chi] * (L - 1) + [1]
     for i in range(1, L + 1):
         cA[i] = min(cA[i], cA[i - 1] * dd)
-    dims = [1] + [min(chi_c, dd ** i, dd ** (L - i), cA[i] * cA[i]) for i in range(1, L)] + [1]
-    return dims
+    return [1] + [min(chi_c, dd ** i, dd ** (L - i), cA[i] * cA[i]) for i in range(1, L)] + [1]
 
 
-def batched_sweep_flops(L, d, chi, chi_c, dims_c):
+def batched_sweep_flops(L, d, chi, dims_c):
     """Algorithmic MFMA flops of one even/odd sweep: both extensions, the
     two-site matrix and both environment updates at every bond."""
     dd = d * d
@@ -88,6 +100,21 @@ def batched_sweep_flops(L, d, chi, chi_c, dims_c):
         tot += 2.0 * cr * a2 * a2 * dd * a1 + 2.0 * cr * dd * d * a2 * a1 * a1
         tot += 2.0 * n * m * K + 2.0 * r * K * (n + m)
     return tot
+
+
+def grad_flops(L, d, chiA, chiB, chiP):
+    """Algorithmic flops of the adjoint: one pass of right and one of left
+    three-layer environments, and per site the two gradient contractions
+    (three GEMMs each); the small two-layer projection pass is left out."""
+    dd = d * d
+    t = 0.0
+    for l in range(L):
+        a, b, x = chiA[l], chiB[l], chiP[l]
+        a2, b2, x2 = chiA[l + 1], chiB[l + 1], chiP[l + 1]
+        env = 2.0 * x * b * a * dd * a2 + 2.0 * x * a2 * b * dd * d * b2 + 2.0 * x * dd * a2 * b2 * x2
+        t += 2 * env
+        t += 2 * (2.0 * x * a * b * dd * b2 + 2.0 * x * a * d * b2 * dd * x2 + 2.0 * a * dd * b2 * x2 * a2)
+    return t
 
 
 def run_gpu(A, B, precision, sketch_p, steps, warmup, profile=False, schedule="serial", chi_c=None,
@@ -110,36 +137,132 @@ def run_gpu(A, B, precision, sketch_p, steps, warmup, profile=False, schedule="s
     return wall, dev_ms, prof, dims
 
 
-def cpu_baseline(A, B, budget_s=25.0):
-    """The FP64 oracle's randomized serial sweep, timed on the host on a
-    bounded sample: the first `nb` bond updates of the first sweep."""
+def oracle_run(A, B, n_sweeps, budget_s):
+    """The FP64 oracle's serial randomized fit on the host (threads = cores
+    this process may use), stopped after the first sweep that ends past
+    `budget_s`; returns the C after each completed sweep and the timing."""
     import threadpoolctl
     from oracle import fit as ofit
     cores = len(os.sched_getaffinity(0))
+    w = WORKLOAD
+    Cs, t_end = [], []
+
+    class Budget(Exception):
+        pass
+
     with threadpoolctl.threadpool_limits(cores):
         t0 = time.perf_counter()
-        count = [0]
 
-        class Budget(Exception):
-            pass
-
-        def stop_after(sweep, l, C):
-            count[0] += 1
-            if time.perf_counter() - t0 > budget_s:
-                raise Budget
+        def on_update(sweep, l, C):
+            fwd = sweep % 2 == 0
+            if (fwd and l == w["L"] - 1) or (not fwd and l == 1):
+                Cs.append(C)
+                t_end.append(time.perf_counter() - t0)
+                if t_end[-1] > budget_s:
+                    raise Budget
 
         try:
-            ofit.fit_serial(A, B, WORKLOAD["chi_c"], 1, sketch_p=WORKLOAD["p"], seed=WORKLOAD["seed"],
-                            on_update=stop_after)
+            ofit.fit_serial(A, B, w["chi_c"], n_sweeps, sketch_p=w["p"], seed=w["seed"], on_update=on_update)
         except Budget:
             pass
-        dt = time.perf_counter() - t0
-    nb = count[0]
-    L = WORKLOAD["L"]
-    per_sweep = dt / max(nb, 1) * (L - 1)
-    return {"value": 1.0 / per_sweep, "unit": "sweeps/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {nb} of {L - 1} bond updates of one randomized FP64 sweep "
-                      f"(incl. preprocessing), {dt:.1f}s, extrapolated to a sweep"}
+    return Cs, t_end, cores
+
+
+def accuracy(A, B, n_sweeps, Cs_oracle, tuning):
+    """Fit error eps (GPU transfer-pass check, FP64) after every sweep of each
+    precision and of the oracle; distance delta to the oracle's C after the
+    first and the last common sweep."""
+    import torch
+    from oracle import mpo
+    from paper_2606_23274_amd.api import FitContext, fit_error
+    w = WORKLOAD
+    out = {}
+    if Cs_oracle:
+        out["oracle_fp64"] = {"eps": [fit_error(A, B, C)[0] for C in Cs_oracle]}
+    for prec, p in (("fp32", w["p"]), ("bf16x3", w["p"]), ("bf16", w["p"]), ("fp64", w["p"]),
+                    ("fp64", -1)):
+        key = prec + ("_plain" if p < 0 else "")
+        ctx = FitContext([(A, B)], w["chi_c"], precision=prec, sketch_p=p, seed=w["seed"],
+                         tuning=tuning if prec == "fp32" else None)
+        eps, delta = [], {}
+        last = min(n_sweeps, len(Cs_oracle)) - 1
+        for s in range(n_sweeps):
+            ctx.sweep(1)
+            C = ctx.export_numpy(0)
+            eps.append(fit_error(A, B, C)[0])
+            if p >= 0 and s <= last and s in (0, last):
+                delta[f"sweep{s + 1}"] = mpo.rel_diff(C, Cs_oracle[s])
+        ctx.close()
+        torch.cuda.synchronize()
+        rec = {"eps": eps}
+        if delta:
+            rec["delta_vs_oracle"] = delta
+        if "oracle_fp64" in out:
+            k = min(len(eps), len(out["oracle_fp64"]["eps"]))
+            rec["eps_minus_oracle"] = [eps[i] - out["oracle_fp64"]["eps"][i] for i in range(k)]
+        out[key] = rec
+    return out
+
+
+def batched_section(steps):
+    import torch
+    from paper_2606_23274_amd.api import FitContext, autotune
+    from synth import make_multi_pair, make_pair
+    res = {}
+    # one pair, L=64 chi=128 chi_C=256, all bonds of one parity per launch
+    A4, B4 = make_pair(64, 2, 128, seed=0, decay=True)
+    table = autotune([(A4, B4)], 256, precision="fp32", schedule="even_odd", sketch_p=16, reps=2)
+    for prec in ("fp32", "bf16x3"):
+        wl, _, _, bd = run_gpu(A4, B4, prec, 16, steps, 2, schedule="even_odd", chi_c=256,
+                               tuning=table if prec == "fp32" else None)
+        fb = batched_sweep_flops(64, 2, 128, bd)
+        res[f"even_odd_L64_chi128_{prec}"] = {
+            "sweeps_per_s": round(steps / wl, 3), "ms_per_sweep": round(wl / steps * 1e3, 3),
+            "tflops": round(fb / (wl / steps) / 1e12, 3),
+            "mfma_frac": round(fb / (wl / steps) / PEAK[prec], 5)}
+    # 16 pairs, L=24, chi from {16, 32, 64, 128}, chi_C = 2 chi, one grouped
+    # launch per half-step over all pairs
+    mp = make_multi_pair()
+    pairs = [(A, B) for A, B, _ in mp]
+    chis = [c for _, _, c in mp]
+    ctx = FitContext(pairs, 256, precision="fp32", schedule="even_odd", sketch_p=16, seed=0,
+                     pair_chi_max=[2 * c for c in chis])
+    ctx.sweep(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.sweep(steps)
+    torch.cuda.synchronize()
+    wl = time.perf_counter() - t0
+    fb = sum(batched_sweep_flops(24, 2, c, ctx.bond_dims(i)) for i, c in enumerate(chis))
+    ctx.close()
+    res["multi_pair_16xL24_fp32"] = {
+        "chi": chis, "sweeps_per_s": round(steps / wl, 3),
+        "ms_per_sweep": round(wl / steps * 1e3, 3), "tflops": round(fb / (wl / steps) / 1e12, 3),
+        "mfma_frac": round(fb / (wl / steps) / PEAK["fp32"], 5)}
+    return res
+
+
+def gradient_section():
+    import torch
+    from paper_2606_23274_amd.api import FitContext
+    from synth import gaussian_mpo, make_pair
+    A, B = make_pair(30, 2, 64, seed=0, decay=True)
+    W = gaussian_mpo(np.random.default_rng(2024), 30, 2, 32)
+    ctx = FitContext([(A, B)], 128, precision="fp32", sketch_p=16, seed=0)
+    ctx.sweep(4)
+    ctx.grad(W, recompute_env=True)  # warm-up
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.grad(W, recompute_env=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    dims = ctx.bond_dims(0)
+    ctx.close()
+    fl = grad_flops(30, 2, bonds_of(30, 2, 64), bonds_of(30, 2, 64), dims)
+    return {"grad_L30_chi64_fp32": {"ms_per_gradient": round(ms, 3), "algorithmic_gflop": round(fl / 1e9, 2),
+                                    "tflops": round(fl / (ms * 1e-3) / 1e12, 3), "env_recomputed": True}}
 
 
 def main():
@@ -147,68 +270,34 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sweeps", type=int, default=6, help="sweeps of the accuracy comparison")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="headline only")
+    ap.add_argument("--quick", action="store_true", help="headline, profile and roofline only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the fit on a single MI355X "
               "(multi-GPU sharding of the even/odd schedule is a design, not built).", file=sys.stderr)
         sys.exit(2)
     from synth import make_pair
+    from paper_2606_23274_amd.api import autotune
     w = WORKLOAD
     A, B = make_pair(w["L"], w["d"], w["chi"], seed=w["seed"], decay=True)
     dims = settled_dims(w["L"], w["d"], w["chi"], w["chi_c"])
     mf, f64 = sweep_flops(w["L"], w["d"], w["chi"], w["chi_c"], w["p"], dims, True)
 
     # GEMM tile / split-K choice from the project's autotuner (untimed)
-    from paper_2606_23274_amd.api import autotune
     t0 = time.perf_counter()
     table = autotune([(A, B)], w["chi_c"], precision="fp32", sketch_p=w["p"], seed=w["seed"], reps=3)
     tune_s = time.perf_counter() - t0
     wall, dev_ms, _, got_dims = run_gpu(A, B, "fp32", w["p"], args.steps, args.warmup, tuning=table)
-    wall_b, _, _, _ = run_gpu(A, B, "fp32", w["p"], args.steps, args.warmup)
     ms = wall / args.steps * 1e3
     value = args.steps / wall
     tflops = mf / (ms * 1e-3) / 1e12
+    print(f"headline: {value:.3f} sweeps/s", file=sys.stderr, flush=True)
 
-    # per-kernel-class device time from HIP events around each launch
+    # per-kernel-class device time from HIP events around each launch (eager)
     _, _, prof, _ = run_gpu(A, B, "fp32", w["p"], 2, args.warmup, profile=True, tuning=table)
-    ms_per_class = {k: v[0] / 2 for k, v in prof.items()}  # ms per sweep
-    others = {}
-    if not args.quick:
-        for prec, p, st in (("bf16x3", w["p"], args.steps), ("bf16", w["p"], args.steps),
-                            ("fp64", w["p"], args.steps), ("fp64", -1, 2)):
-            wl, _, _, _ = run_gpu(A, B, prec, p, st, args.warmup if p >= 0 else 2)
-            key = prec + ("_plain" if p < 0 else "")
-            mfp, _ = sweep_flops(w["L"], w["d"], w["chi"], w["chi_c"], w["p"], dims, p >= 0)
-            others[key] = {"sweeps_per_s": round(st / wl, 3), "ms_per_sweep": round(wl / st * 1e3, 3),
-                           "tflops": round(mfp / (wl / st) / 1e12, 3),
-                           "mfma_frac": round(mfp / (wl / st) / PEAK[prec], 5)}
-
-    # batched even/odd inverse-gauge schedule (all bonds of one parity per launch)
-    batched = {}
-    if not args.quick:
-        wl, _, _, bd = run_gpu(A, B, "fp32", w["p"], args.steps, args.warmup, schedule="even_odd")
-        fb = batched_sweep_flops(w["L"], w["d"], w["chi"], w["chi_c"], bd)
-        batched["even_odd_L40_chi64_fp32"] = {
-            "sweeps_per_s": round(args.steps / wl, 3), "ms_per_sweep": round(wl / args.steps * 1e3, 3),
-            "tflops": round(fb / (wl / args.steps) / 1e12, 3),
-            "mfma_frac": round(fb / (wl / args.steps) / PEAK["fp32"], 5)}
-        from paper_2606_23274_amd._lib import MpoError
-        A4, B4 = make_pair(64, 2, 128, seed=0, decay=True)
-        st4 = max(2, args.steps // 3)
-        try:
-            wl, _, _, bd = run_gpu(A4, B4, "fp32", 16, st4, 2, schedule="even_odd", chi_c=256)
-            fb = batched_sweep_flops(64, 2, 128, 256, bd)
-            batched["even_odd_L64_chi128_fp32"] = {
-                "sweeps_per_s": round(st4 / wl, 3), "ms_per_sweep": round(wl / st4 * 1e3, 3),
-                "tflops": round(fb / (wl / st4) / 1e12, 3),
-                "mfma_frac": round(fb / (wl / st4) / PEAK["fp32"], 5)}
-        except MpoError as e:
-            batched["even_odd_L64_chi128_fp32"] = {"error": str(e)}
-
-    # roofline of the dominant kernel class: algorithmic flops credited to its
-    # launches / their average device time (HIP events around each launch)
+    ms_per_class = {k: v[0] / 2 for k, v in prof.items()}
     dom = max(prof, key=lambda c: prof[c][0])
     ms_dom, fl_dom, nl_dom = prof[dom]
     roof = None
@@ -223,12 +312,48 @@ def main():
                 "frac": round(ach / peak, 7), "traffic": None,
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches_per_sweep": nl_dom / 2,
                 "algorithmic_flops_per_launch": round(fl_dom / nl_dom)}
+
+    others, batched, grad, acc, cpu = {}, {}, {}, {}, None
+    if not args.quick:
+        wall_b, _, _, _ = run_gpu(A, B, "fp32", w["p"], args.steps, args.warmup)
+        others["fp32_built_in_gemm_choice"] = {"sweeps_per_s": round(args.steps / wall_b, 3)}
+        for prec, p, st in (("bf16x3", w["p"], args.steps), ("bf16", w["p"], args.steps),
+                            ("fp64", w["p"], args.steps), ("fp64", -1, 2)):
+            wl, _, _, _ = run_gpu(A, B, prec, p, st, args.warmup if p >= 0 else 2)
+            key = prec + ("_plain" if p < 0 else "")
+            mfp, _ = sweep_flops(w["L"], w["d"], w["chi"], w["chi_c"], w["p"], dims, p >= 0)
+            others[key] = {"sweeps_per_s": round(st / wl, 3), "ms_per_sweep": round(wl / st * 1e3, 3),
+                           "tflops": round(mfp / (wl / st) / 1e12, 3),
+                           "mfma_frac": round(mfp / (wl / st) / PEAK[prec], 5)}
+        print("precisions done", file=sys.stderr, flush=True)
+        batched = batched_section(max(2, args.steps // 2))
+        print("batched done", file=sys.stderr, flush=True)
+        grad = gradient_section()
+        print("gradient done", file=sys.stderr, flush=True)
+        Cs = []
+        if not args.no_cpu:
+            Cs, t_end, cores = oracle_run(A, B, args.sweeps, budget_s=30.0)
+            n = len(Cs)
+            cpu = {"value": round(n / t_end[-1], 5) if n else None, "unit": "sweeps/s", "cores": cores,
+                   "kind": "oracle",
+                   "sample": (f"the FP64 oracle's serial randomized fit of this workload (preprocessing "
+                              f"included), {n} full sweep(s) in {t_end[-1]:.1f} s") if n else "none"}
+            print("oracle done", file=sys.stderr, flush=True)
+        acc = accuracy(A, B, args.sweeps, Cs, table)
+        # time to the plain FP64 path's final accuracy
+        target = acc["fp64_plain"]["eps"][-1] * 1.01
+        for key, rate in (("fp32", value), ("fp64_plain", others["fp64_plain"]["sweeps_per_s"])):
+            e = acc[key]["eps"]
+            n_need = next((i + 1 for i, v in enumerate(e) if v <= target), None)
+            acc[key]["sweeps_to_1pct_of_fp64_plain_final_eps"] = n_need
+            acc[key]["seconds_to_it"] = round(n_need / rate, 4) if n_need else None
+
     line = {
         "metric": "fit sweeps/s + TFLOP/s (MFMA frac), L=40 chi=64 chi_C=128, mixed vs FP64",
         "value": round(value, 4), "unit": "sweeps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
-        "data": "synthetic: Gaussian MPO cores with exp(-k/6) bond weights, seed 0",
+        "data": "synthetic: Gaussian MPO cores scaled 1/sqrt(chi) with exp(-k/6) bond weights, seed 0",
         "config": {"workload": "precision_L40: serial randomized fit sweep, L=40 d=2 chi_A=chi_B=64 "
                                "chi_C=128 p=16, FP32 contractions, FP64 QR/SVD",
                    "global_batch": 1, "seq_len": w["L"], "parallelism": "single GPU"},
@@ -236,16 +361,16 @@ def main():
         "device_ms_per_sweep": round(dev_ms / args.steps, 4),
         "algorithmic_gflop_per_sweep": {"mfma": round(mf / 1e9, 3), "fp64_factorization": round(f64 / 1e9, 3)},
         "bond_dims_settled": got_dims == dims,
+        "autotune": {"classes": len(table), "seconds": round(tune_s, 2)},
         "kernel_ms_per_sweep": {kk: round(v, 4) for kk, v in
                                 sorted(ms_per_class.items(), key=lambda x: -x[1])},
-        "autotune": {"classes": len(table), "seconds": round(tune_s, 2),
-                     "built_in_choice_sweeps_per_s": round(args.steps / wall_b, 4)},
-        "other_precisions": others,
-        "batched_schedule": batched,
         "roofline": roof,
     }
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(A, B)
+    if not args.quick:
+        line.update({"other_precisions": others, "accuracy": acc, "batched_schedule": batched,
+                     "gradient": grad})
+        if cpu is not None:
+            line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

@@ -183,12 +183,18 @@ mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_pair* ab, cons
                         double* const* gA, double* const* gB, double* loss, int32_t recompute_env,
                         void* workspace, size_t ws_bytes);
 
-/* Fit error ||A B - C||_F / ||A B||_F in FP64 from transfer passes:
-   ||AB||^2 by a four-layer pass, <C, AB> by a three-layer pass and ||C||^2
-   by a two-layer pass, all on the device (the naive product of Alg. 1 is
-   never formed).  The difference of squares floors near 1e-8 (Sec. 5.2).
-   Needs `workspace` of mpo_contract_check_bytes bytes.  Synchronizes
-   `stream`; *rel_err and (if non-null) *ab_norm2 are host outputs. */
+/* Fit error ||A B - C||_F / ||A B||_F (Sec. 2.3, Eq. fit_min) in FP64 from
+   transfer passes on the device: ||A B||^2 by a four-layer pass, <C, A B> by
+   a three-layer pass and ||C||^2 by a two-layer pass, each environment
+   renormalized after every site (logarithms summed on the host, so long
+   chains neither under- nor overflow); the naive product of Alg. 1 is never
+   formed.  eps^2 = 1 - 2 <C, AB>/||AB||^2 + ||C||^2/||AB||^2 floors near
+   1e-8 relative (difference of squares).  pair->A, pair->B and C are FP64
+   device cores on one set of L sites with one d; the four-layer pass holds
+   (chi_A chi_B)^2 d^2 doubles per intermediate.  `workspace` (256-byte
+   aligned) of mpo_contract_check_bytes bytes.  Synchronizes `stream`;
+   *rel_err and (if non-null) *ab_norm2 = ||A B||_F^2 are host outputs;
+   MPO_ERR_NUMERIC if A B is zero or a pass is not finite. */
 mpo_status mpo_contract_check_bytes(const mpo_pair* pair, const mpo_tt* C, size_t* bytes);
 mpo_status mpo_contract_exact_check(const mpo_pair* pair, const mpo_tt* C, double* rel_err,
                                     double* ab_norm2, void* workspace, size_t ws_bytes,

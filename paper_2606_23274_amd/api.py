@@ -8,6 +8,7 @@ output leg.
 from __future__ import annotations
 
 import ctypes as C
+import ctypes as C_
 
 import numpy as np
 import torch
@@ -254,3 +255,24 @@ class FitContract(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         return (None, None, *[g * t for t in ctx.saved_tensors])
+
+
+def fit_error(A, B, C, device="cuda:0"):
+    """||A B - C||_F / ||A B||_F and ||A B||_F^2 in FP64 from transfer passes
+    on the GPU (mpo_contract_exact_check); the difference of squares floors
+    near 1e-8 relative."""
+    lib = _lib.load()
+    dev = torch.device(device)
+    ta, tb, tc = (_TT(_dev_cores(X, dev)) for X in (A, B, C))
+    pair = _lib.MpoPair(ta.tt, tb.tt, 0)
+    nbytes = C_.c_size_t()
+    _lib.check(lib.mpo_contract_check_bytes(C_.byref(pair), C_.byref(tc.tt), C_.byref(nbytes)))
+    ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+    ws_ptr = (ws.data_ptr() + 255) & ~255
+    err, n2 = C_.c_double(), C_.c_double()
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev)
+        _lib.check(lib.mpo_contract_exact_check(C_.byref(pair), C_.byref(tc.tt), C_.byref(err),
+                                                C_.byref(n2), C_.c_void_p(ws_ptr), nbytes.value,
+                                                C_.c_void_p(stream.cuda_stream)))
+    return err.value, n2.value

@@ -210,6 +210,37 @@ __global__ void __launch_bounds__(1024) norm_kernel(const NormDesc* __restrict__
   for (long long e = threadIdx.x; e < d.n; e += blockDim.x) d.x[e] *= inv;
 }
 
+__global__ void __launch_bounds__(256) sumsq_kernel(const double* __restrict__ x, long long n,
+                                                    double* __restrict__ part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256)
+    acc = fma(x[e], x[e], acc);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256) sumsq_finish_kernel(const double* __restrict__ part, int np,
+                                                           double* __restrict__ nu_out) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) acc += part[i];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *nu_out = sqrt(red[0] + red[1] + red[2] + red[3]);
+}
+
+__global__ void __launch_bounds__(256) divide_kernel(double* __restrict__ x, long long n,
+                                                     const double* __restrict__ nu) {
+  const double v = *nu;
+  const double inv = v > 0.0 ? 1.0 / v : 1.0;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256)
+    x[e] *= inv;
+}
+
 __global__ void bump_kernel(int* c, int by) {
   if (threadIdx.x == 0) c[0] += by;
 }
@@ -255,6 +286,13 @@ void launch_fill(const FillDesc* d, int n, long long max_words, hipStream_t s) {
 void launch_norm(const NormDesc* d, int n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(norm_kernel, dim3(n), dim3(1024), 0, s, d);
+}
+
+void launch_norm_big(double* x, long long n, double* part, double* nu_out, hipStream_t s) {
+  const int g = (int)std::min<long long>(1024, std::max<long long>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(sumsq_kernel, dim3(g), dim3(256), 0, s, x, n, part);
+  hipLaunchKernelGGL(sumsq_finish_kernel, dim3(1), dim3(256), 0, s, part, g, nu_out);
+  hipLaunchKernelGGL(divide_kernel, dim3(g), dim3(256), 0, s, x, n, nu_out);
 }
 
 void launch_bump(int* counter, int by, hipStream_t s) {

@@ -95,6 +95,9 @@ struct NormDesc {
   double* nu_out;
 };
 void launch_norm(const NormDesc* d, int n, hipStream_t s);
+// The same for one large array, over many workgroups: partial sums of
+// squares into `part` (>= 1024 doubles), then nu, then the division.
+void launch_norm_big(double* x, long long n, double* part, double* nu_out, hipStream_t s);
 void launch_fill(const FillDesc* d, int n, long long max_words, hipStream_t s);
 
 // *counter += 1 (one thread); used to advance the sweep index inside a graph.

@@ -14,7 +14,7 @@
 
 namespace mpofit {
 
-enum class LK { Gemm, Chol, Trsm, Eig, Omega, Sign, Scale, Perm, Sval, Fill, Norm, Bump, Jacobi };
+enum class LK { Gemm, Chol, Trsm, Eig, Omega, Sign, Scale, Perm, Sval, Fill, Norm, Bump, Jacobi, NormBig };
 
 struct Launch {
   LK kind;
@@ -25,6 +25,7 @@ struct Launch {
   long long maxa = 0;   // per-kind size hint (rows, elements, ...)
   int maxb = 0;
   int* counter = nullptr;  // Bump target
+  void* aux = nullptr;     // NormBig: partial-sum buffer
   int bump_by = 0;
   std::string cls;      // kernel class for profiling
   double flops = 0;     // algorithmic flops credited to this launch

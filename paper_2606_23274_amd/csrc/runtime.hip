@@ -50,6 +50,11 @@ void run_program(const Program& p, hipStream_t s, hipEvent_t* ev) {
       case LK::Norm: launch_norm(p.device<NormDesc>(l), l.n, s); break;
       case LK::Bump: launch_bump(l.counter, l.bump_by, s); break;
       case LK::Jacobi: launch_jacobi(p.device<JacobiDesc>(l), l.n, (int)l.maxa, s); break;
+      case LK::NormBig: {
+        const NormDesc& nd = p.host<NormDesc>(l)[0];
+        launch_norm_big(nd.x, nd.n, static_cast<double*>(l.aux), nd.nu_out, s);
+        break;
+      }
     }
     HIP_OK(hipGetLastError());
     if (ev) HIP_OK(hipEventRecord(ev[li + 1], s));
@@ -1694,6 +1699,129 @@ void rec_grad(Ctx& X, Program& P, Arena& ar, PairState& S, const mpo_tt& A, cons
   permute(P, Ten{Le.p, wt, {1}}, {0}, Ten{loss_dev, DType::F64, {1}});
 }
 
+// ------------------------------------------------------------------ fit error check
+// ||A B - C||_F / ||A B||_F from transfer passes in FP64 (Sec. 2.3, Eq.
+// fit_min): ||A B||^2 by a four-layer pass, <C, A B> by a three-layer pass,
+// ||C||^2 by a two-layer pass; the naive product of Alg. 1 is never formed.
+// After every site the running environment is divided by its Frobenius
+// norm, whose logarithms are summed on the host (no under- or overflow).
+struct CheckPlan {
+  double* logs = nullptr;  // 3 (L + 1) norms: passes n2, cab, cc
+  double* part = nullptr;  // NormBig partial sums
+};
+
+void add_normalize(Program& P, const Ten& t, double* nu_out, double* part) {
+  Launch l;
+  l.kind = LK::NormBig;
+  l.off = P.push(std::vector<NormDesc>{NormDesc{static_cast<double*>(t.p), t.size(), nu_out}});
+  l.n = 1;
+  l.aux = part;
+  l.cls = "check";
+  P.launches.push_back(l);
+}
+
+void rec_check(Program& P, Arena& ar, const SplitBuf& sb, const mpo_tt& A, const mpo_tt& B,
+               const mpo_tt& Cm, const CheckPlan& cp) {
+  const int L = A.L, d = A.d;
+  const Mode mode = Mode::F64;
+  const DType t64 = DType::F64;
+  auto core = [&](const mpo_tt& t, int l) {
+    return Ten{const_cast<double*>(t.cores[l]), t64, {t.chi[l], d, d, t.chi[l + 1]}};
+  };
+  auto one = [&](std::vector<int> dims) {
+    Ten t = ar.take(t64, dims);
+    add_fill(P, {FillDesc{t.p, 0, 1, 1, 1}});
+    return t;
+  };
+  auto as = [](Ten t, std::vector<int> dims) {
+    t.dims = std::move(dims);
+    return t;
+  };
+  long long e4 = 1, e3 = 1, e2 = 1;
+  for (int l = 0; l <= L; ++l) {
+    const long long a = A.chi[l], b = B.chi[l], c = Cm.chi[l];
+    e4 = std::max(e4, a * b * a * b);
+    e3 = std::max(e3, c * a * b);
+    e2 = std::max(e2, c * c);
+  }
+  Ten E4[2] = {ar.take(t64, {(int)e4}), ar.take(t64, {(int)e4})};
+  Ten E3[2] = {ar.take(t64, {(int)e3}), ar.take(t64, {(int)e3})};
+  Ten E2[2] = {ar.take(t64, {(int)e2}), ar.take(t64, {(int)e2})};
+  const size_t mark = ar.cv.off;
+  // four layers: E[a1, b1, a2, b2] -> sum over x, u of (A B)(x, u) (A B)(x, u)
+  {
+    Ten E = as(E4[0], {1, 1, 1, 1});
+    add_fill(P, {FillDesc{E.p, 0, 1, 1, 1}});
+    for (int l = 0; l < L; ++l) {
+      const Ten Al = core(A, l), Bl = core(B, l);
+      const int a1 = A.chi[l + 1], b1 = B.chi[l + 1];
+      Ten T1 = ar.take(t64, {B.chi[l], A.chi[l], B.chi[l], d, d, a1});          // [b1 a2 b2 x t a1']
+      contract(P, ar, sb, mode, E, {0}, Al, {0}, T1, iota(6), "check");
+      Ten T2 = ar.take(t64, {B.chi[l], B.chi[l], d, a1, d, a1});                // [b1 b2 t a1' v a2']
+      contract(P, ar, sb, mode, T1, {1, 3}, Al, {0, 1}, T2, iota(6), "check");
+      Ten T3 = ar.take(t64, {B.chi[l], a1, d, a1, d, b1});                      // [b2 a1' v a2' u b1']
+      contract(P, ar, sb, mode, T2, {0, 2}, Bl, {0, 1}, T3, iota(6), "check");
+      Ten En = as(E.p == E4[0].p ? E4[1] : E4[0], {a1, b1, a1, b1});
+      // [a1' a2' b1' b2'] -> [a1' b1' a2' b2']
+      contract(P, ar, sb, mode, T3, {0, 2, 4}, Bl, {0, 1, 2}, En, {0, 2, 1, 3}, "check");
+      add_normalize(P, En, cp.logs + l, cp.part);
+      E = En;
+      ar.cv.off = mark;
+    }
+    add_normalize(P, E, cp.logs + L, cp.part);  // the last is the scalar itself
+  }
+  // three layers: E[c, a, b]
+  {
+    Ten E = as(E3[0], {1, 1, 1});
+    add_fill(P, {FillDesc{E.p, 0, 1, 1, 1}});
+    for (int l = 0; l < L; ++l) {
+      const Ten Al = core(A, l), Bl = core(B, l), Cl = core(Cm, l);
+      const int x = Cm.chi[l], b = B.chi[l], a2 = A.chi[l + 1], b2 = B.chi[l + 1];
+      Ten T = ar.take(t64, {x, b, d, d, a2});
+      contract(P, ar, sb, mode, E, {1}, Al, {0}, T, iota(5), "check");
+      Ten T2 = ar.take(t64, {x, d, a2, d, b2});
+      contract(P, ar, sb, mode, T, {1, 3}, Bl, {0, 1}, T2, iota(5), "check");
+      Ten En = as(E.p == E3[0].p ? E3[1] : E3[0], {Cm.chi[l + 1], a2, b2});
+      contract(P, ar, sb, mode, Cl, {0, 1, 2}, T2, {0, 1, 3}, En, iota(3), "check");
+      if (l + 1 < L) add_normalize(P, En, cp.logs + (L + 1) + l, cp.part);
+      E = En;
+      ar.cv.off = mark;
+    }
+    // the last value keeps its sign: copy it out instead of normalizing
+    permute(P, as(E, {1}), {0}, Ten{cp.logs + (L + 1) + L, t64, {1}});
+  }
+  // two layers: E[c, c']
+  {
+    Ten E = as(E2[0], {1, 1});
+    add_fill(P, {FillDesc{E.p, 0, 1, 1, 1}});
+    for (int l = 0; l < L; ++l) {
+      const Ten Cl = core(Cm, l);
+      const int c2 = Cm.chi[l + 1];
+      Ten T = ar.take(t64, {Cm.chi[l], d, d, c2});
+      contract(P, ar, sb, mode, E, {0}, Cl, {0}, T, iota(4), "check");
+      Ten En = as(E.p == E2[0].p ? E2[1] : E2[0], {c2, c2});
+      contract(P, ar, sb, mode, T, {0, 1, 2}, Cl, {0, 1, 2}, En, iota(2), "check");
+      add_normalize(P, En, cp.logs + 2 * (L + 1) + l, cp.part);
+      E = En;
+      ar.cv.off = mark;
+    }
+    add_normalize(P, E, cp.logs + 2 * (L + 1) + L, cp.part);
+  }
+}
+
+// Small context for calls that are not tied to a fit: status flags, split-K
+// scratch and a descriptor arena carved from the caller's workspace.
+void carve_aux(Ctx& X, Carver& cv) {
+  X.flag = cv.take<int>(4);
+  X.sweep_dev = X.flag + 1;
+  X.sb.cap = (size_t)32 << 20;
+  X.sb.partials = cv.take<char>(X.sb.cap);
+  X.sb.ccap = 1 << 14;
+  X.sb.counters = cv.take<int>(X.sb.ccap);
+  X.arena_cap = (size_t)8 << 20;
+  X.arena = cv.take<char>(X.arena_cap);
+}
+
 int grad_centre(const Ctx& X) {
   if (X.o.schedule != MPO_SCHED_SERIAL) throw Error{MPO_ERR_UNSUPPORTED, "gradient: serial schedule only"};
   return X.sweeps_done % 2 == 1 ? -1 : 0;  // -1: last site
@@ -2090,15 +2218,84 @@ mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_pair* ab, cons
   });
 }
 
-mpo_status mpo_contract_check_bytes(const mpo_pair*, const mpo_tt*, size_t*) {
-  g_last_error = "check not built yet";
-  return MPO_ERR_UNSUPPORTED;
+mpo_status mpo_contract_check_bytes(const mpo_pair* pair, const mpo_tt* C, size_t* bytes) {
+  return guarded([&] {
+    if (!pair || !C || !bytes) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    const int L = pair->A.L, d = pair->A.d;
+    if (L < 1 || d < 1) throw Error{MPO_ERR_SHAPE, "bad L or d"};
+    validate_tt(pair->A, L, d);
+    validate_tt(pair->B, L, d);
+    validate_tt(*C, L, d);
+    Ctx X;
+    Carver cv;
+    carve_aux(X, cv);
+    CheckPlan cp;
+    cp.logs = cv.take<double>(3 * (L + 1));
+    cp.part = cv.take<double>(1024);
+    Program P;
+    Arena ar;
+    ar.cv.off = cv.off;
+    rec_check(P, ar, X.sb, pair->A, pair->B, *C, cp);
+    *bytes = std::max(ar.peak, cv.off) + 256;
+  });
 }
 
-mpo_status mpo_contract_exact_check(const mpo_pair*, const mpo_tt*, double*, double*, void*, size_t,
-                                    void*) {
-  g_last_error = "check not built yet";
-  return MPO_ERR_UNSUPPORTED;
+mpo_status mpo_contract_exact_check(const mpo_pair* pair, const mpo_tt* C, double* rel_err,
+                                    double* ab_norm2, void* workspace, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    if (!pair || !C || !rel_err || !workspace) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) throw Error{MPO_ERR_WORKSPACE, "workspace not 256-byte aligned"};
+    size_t need = 0;
+    const mpo_status st = mpo_contract_check_bytes(pair, C, &need);
+    if (st != MPO_OK) throw Error{st, g_last_error};
+    if (need > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "workspace too small"};
+    const int L = pair->A.L;
+    Ctx X;
+    X.stream = static_cast<hipStream_t>(stream);
+    Carver cv;
+    cv.base = static_cast<char*>(workspace);
+    carve_aux(X, cv);
+    CheckPlan cp;
+    cp.logs = cv.take<double>(3 * (L + 1));
+    cp.part = cv.take<double>(1024);
+    Program z;
+    add_fill(z, {FillDesc{X.flag, 4, 0, 0, 0}, FillDesc{X.sb.counters, X.sb.ccap, 0, 0, 0}});
+    upload(X, z);
+    run_program(z, X.stream, nullptr);
+    Program P;
+    Arena ar;
+    ar.cv.base = cv.base;
+    ar.cv.off = cv.off;
+    rec_check(P, ar, X.sb, pair->A, pair->B, *C, cp);
+    upload(X, P);
+    run_program(P, X.stream, nullptr);
+    std::vector<double> lg(3 * (L + 1));
+    HIP_OK(hipMemcpyAsync(lg.data(), cp.logs, lg.size() * sizeof(double), hipMemcpyDeviceToHost, X.stream));
+    HIP_OK(hipStreamSynchronize(X.stream));
+    check_flags(X);
+    // log ||AB||^2, log |<C, AB>| (with sign), log ||C||^2; a zero norm on
+    // the way makes that pass exactly zero
+    for (double v : lg)
+      if (!std::isfinite(v)) throw Error{MPO_ERR_NUMERIC, "non-finite transfer pass"};
+    double l4 = 0, l3 = 0, l2 = 0;
+    bool z3 = false, z2 = false;
+    for (int i = 0; i <= L; ++i) {
+      if (!(lg[i] > 0)) throw Error{MPO_ERR_NUMERIC, "A B is zero"};
+      l4 += std::log(lg[i]);
+      const double c2 = lg[2 * (L + 1) + i];
+      if (c2 > 0) l2 += std::log(c2); else z2 = true;
+    }
+    for (int i = 0; i < L - 1; ++i) {
+      const double c3 = lg[(L + 1) + i];
+      if (c3 > 0) l3 += std::log(c3); else z3 = true;
+    }
+    const double last = lg[(L + 1) + L];
+    const double cab = (z3 || last == 0.0) ? 0.0
+                       : (last > 0 ? 1.0 : -1.0) * std::exp(l3 + std::log(std::fabs(last)) - l4);
+    const double cc = z2 ? 0.0 : std::exp(l2 - l4);
+    *rel_err = std::sqrt(std::max(0.0, 1.0 - 2.0 * cab + cc));
+    if (ab_norm2) *ab_norm2 = std::exp(l4);
+  });
 }
 
 void mpo_fit_destroy(mpo_fit_ctx* ctx) {

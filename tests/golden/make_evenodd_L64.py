@@ -2,8 +2,9 @@
 even/odd sweep at the batched configuration's full size (L=64, d=2,
 chi_A=chi_B=128 with exp(-k/6) bond weights, seed 0, chi_C=256, p=16, Philox
 seed 0), small enough to store: the bond dimensions, the number of singular
-values truncated before inversion, the fit functional ||C||^2 - 2 <C, A B>,
-and <C, G_i> for three seeded Gaussian MPOs G_i of bond dimension 4.
+values truncated before inversion, ||C||^2, <C, A B>, and <C, A B_i> for
+three probes B_i: B with the core at site 5, 32 or 58 replaced by a seeded
+Gaussian core of the same shape (each probes C around that site).
 
 Run: python tests/golden/make_evenodd_L64.py   (about 4 minutes on 8 cores)
 """
@@ -18,11 +19,20 @@ sys.path.insert(0, ROOT)
 
 from oracle import fit as ofit  # noqa: E402
 from oracle import mpo  # noqa: E402
-from synth import gaussian_mpo, make_pair  # noqa: E402
+from synth import make_pair  # noqa: E402
 
 
-def probes(L):
-    return [gaussian_mpo(np.random.default_rng(500 + i), L, 2, 4) for i in range(3)]
+PROBE_SITES = (5, 32, 58)
+
+
+def probes(B):
+    out = []
+    for i, l in enumerate(PROBE_SITES):
+        Bi = [c for c in B]
+        rng = np.random.default_rng(500 + i)
+        Bi[l] = rng.standard_normal(B[l].shape) * np.linalg.norm(B[l]) / np.sqrt(B[l].size)
+        out.append(Bi)
+    return out
 
 
 def main():
@@ -35,7 +45,7 @@ def main():
         "truncated": res.n_guard,
         "norm2": mpo.left_orth_norm(C) ** 2,
         "inner_ab": mpo.three_layer_inner(C, A, B),
-        "probes": [mpo.transfer_inner(C, G) for G in probes(64)],
+        "probes": [mpo.three_layer_inner(C, A, Bi) for Bi in probes(B)],
     }
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "evenodd_L64_chi128.json")
     with open(path, "w") as f:

@@ -68,3 +68,40 @@ def test_sweeps_full_size(pair, precision):
     scale = abs(gaps[0])
     assert gaps[1] < gaps[0] - 1e-3 * scale      # the first sweep improves on the guess A
     assert gaps[2] <= gaps[1] + 1e-6 * scale     # and the second does not undo it
+
+
+def test_first_sweep_against_stored_oracle(pair):
+    """Sampled outputs of the FP64 oracle's first sweep at full size (written
+    by tests/golden/make_evenodd_L64.py, which calls only the oracle): bond
+    dimensions, the truncation count, ||C||^2, <C, A B> and <C, A B_i> for
+    three probes B_i (B with one core replaced by a seeded Gaussian core)."""
+    import json
+    import os
+    from paper_2606_23274_amd.api import FitContext
+    sys_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    with open(os.path.join(sys_path, "evenodd_L64_chi128.json")) as f:
+        ref = json.load(f)
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("mk", os.path.join(sys_path, "make_evenodd_L64.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    A, B = pair
+    ctx = FitContext([(A, B)], 256, precision="fp64", schedule="even_odd", sketch_p=16, seed=0)
+    try:
+        n0 = ctx.truncations()
+        ctx.sweep(1)
+        C = ctx.export_numpy(0)
+        dims = ctx.bond_dims(0)
+        n1 = ctx.truncations()
+    finally:
+        ctx.close()
+    assert dims == ref["bond_dims"]
+    # the oracle's count covers the initialization and the sweep
+    assert n0 <= n1
+    assert abs(n1 - ref["truncated"]) <= max(2, ref["truncated"] // 20)
+    norm2 = mpo.left_orth_norm(C) ** 2
+    assert abs(norm2 - ref["norm2"]) <= 1e-10 * ref["norm2"]
+    inner = mpo.three_layer_inner(C, A, B)
+    assert abs(inner - ref["inner_ab"]) <= 1e-10 * ref["inner_ab"]
+    for Bi, v in zip(mk.probes(B), ref["probes"]):
+        assert abs(mpo.three_layer_inner(C, A, Bi) - v) <= 1e-9 * abs(v)
