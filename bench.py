@@ -117,6 +117,24 @@ def grad_flops(L, d, chiA, chiB, chiP):
     return t
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs (profiles/traffic_*.json), scaled by the copy-probe calibration;
+    None when no such record exists or the kernel's source has changed."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+        with open(path) as f:
+            rec = json.load(f)
+        if rec.get("kernel") != kernel:
+            continue
+        with open(os.path.join(ROOT, rec["source_file"]), "rb") as f:
+            if hashlib.sha1(f.read()).hexdigest() != rec["source_sha1"]:
+                return None
+        return rec["traffic_bytes_per_dispatch"]
+    return None
+
+
 def run_gpu(A, B, precision, sketch_p, steps, warmup, profile=False, schedule="serial", chi_c=None,
             tuning=None):
     import torch
@@ -273,7 +291,25 @@ def main():
     ap.add_argument("--sweeps", type=int, default=6, help="sweeps of the accuracy comparison")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline, profile and roofline only")
+    ap.add_argument("--section", choices=["batched", "gradient"],
+                    help="run only that section (for profiling) and print its JSON")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of 256 MiB (4 times): the reference for "
+                         "scaling HBM traffic counters")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": src.numel() * 4, "copies": 4}), flush=True)
+        return
+    if args.section:
+        out = batched_section(max(2, args.steps // 2)) if args.section == "batched" else gradient_section()
+        print(json.dumps(out), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the fit on a single MI355X "
               "(multi-GPU sharding of the even/odd schedule is a design, not built).", file=sys.stderr)
@@ -312,6 +348,7 @@ def main():
                 "frac": round(ach / peak, 7), "traffic": None,
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches_per_sweep": nl_dom / 2,
                 "algorithmic_flops_per_launch": round(fl_dom / nl_dom)}
+        roof["traffic"] = measured_traffic(roof["kernel"])
 
     others, batched, grad, acc, cpu = {}, {}, {}, {}, None
     if not args.quick:
