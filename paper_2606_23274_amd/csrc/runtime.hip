@@ -498,10 +498,84 @@ struct CholQRJob {
 // with cond(X) up to about u^{-1}.
 double chol_shift(int n, int k) { return 11.0 * ((double)n * k + (double)k * (k + 1)) * 0x1p-53; }
 
+// Blocked inverse Cholesky for kRegMax < k <= 2 kRegMax: with
+// G = [[G11, G21^T], [G21, G22]] and k1 = ceil(k/2),
+//   R11^{-1} = reg(G11), L21 = G21 R11^{-1}, S = G22 - L21 L21^T,
+//   R22^{-1} = reg(S), X12 = -R11^{-1} (L21^T R22^{-1}),
+// so R^{-1} = [[R11^{-1}, X12], [., R22^{-1}]] (the lower-left block is never
+// read), and X R^{-1} = [X1 R11^{-1}, X [X12; R22^{-1}]].  Temporaries live in
+// the second k x k block of the job's R scratch.
+void add_chol_inv_blocked(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int pass) {
+  std::vector<GemmJob> gj, l21, s22, t2, x12, ap;
+  std::vector<CholDesc> c1, c2;
+  std::vector<PermDesc> cp;
+  for (auto& j : jobs) {
+    double* src = pass % 2 == 1 ? j.T : j.X;
+    double* dst = pass % 2 == 1 ? j.X : j.T;
+    const int lds = pass % 2 == 1 ? j.k : j.ld;
+    const int ldd = pass % 2 == 1 ? j.ld : j.k;
+    const int k = j.k, k1 = k <= kRegMax ? k : (k + 1) / 2, k2 = k - k1;
+    double* Rp = j.R;
+    double* L21 = j.R + (size_t)k * k;
+    double* S = L21 + (size_t)k2 * k1;
+    double* T2 = S + (size_t)k2 * k2;
+    gj.push_back(GemmJob{k, k, j.n, op64(src, false, lds), op64(src, false, lds), out64(j.G, k)});
+    c1.push_back(CholDesc{j.G, k, Rp, k, k1, X.flag});
+    ap.push_back(GemmJob{j.n, k1, k1, op64(src, true, lds), op64(Rp, false, k), out64(dst, ldd)});
+    if (k2 == 0) continue;
+    l21.push_back(GemmJob{k2, k1, k1, op64(j.G + (size_t)k1 * k, true, k), op64(Rp, false, k), out64(L21, k1)});
+    cp.push_back(perm4(j.G + (size_t)k1 * k + k1, 0, S, 0, {1, 1, k2, k2}, {0, 0, k, 1}, {0, 0, k2, 1}));
+    GemmJob sj{k2, k2, k1, op64(L21, true, k1), op64(L21, true, k1), out64(S, k2)};
+    sj.alpha = -1.0;
+    sj.beta = 1;
+    s22.push_back(sj);
+    c2.push_back(CholDesc{S, k2, Rp + (size_t)k1 * k + k1, k, k2, X.flag});
+    t2.push_back(GemmJob{k1, k2, k2, op64(L21, false, k1), op64(Rp + (size_t)k1 * k + k1, false, k), out64(T2, k2)});
+    GemmJob xj{k1, k2, k1, op64(Rp, true, k), op64(T2, false, k2), out64(Rp + k1, k)};
+    xj.alpha = -1.0;
+    x12.push_back(xj);
+    ap.push_back(GemmJob{j.n, k2, k, op64(src, true, lds), op64(Rp + k1, false, k), out64(dst + k1, ldd)});
+  }
+  auto chol = [&](const std::vector<CholDesc>& cd) {
+    if (cd.empty()) return;
+    Launch l;
+    l.kind = LK::Chol;
+    l.off = P.push(cd);
+    l.n = (int)cd.size();
+    l.maxa = kRegMax;
+    l.maxb = 1;
+    l.cls = "qr_chol_inv";
+    for (auto& c : cd) l.flops += 2.0 / 3.0 * c.k * (double)c.k * c.k;
+    P.launches.push_back(l);
+  };
+  add_gemm(P, X.sb, Mode::F64, gj, "qr_gram", 0);
+  chol(c1);
+  add_gemm(P, X.sb, Mode::F64, l21, "qr_block", 0);
+  add_perm(P, cp, "qr_block");
+  add_gemm(P, X.sb, Mode::F64, s22, "qr_block", 0);
+  chol(c2);
+  add_gemm(P, X.sb, Mode::F64, t2, "qr_block", 0);
+  add_gemm(P, X.sb, Mode::F64, x12, "qr_block", 0);
+  add_gemm(P, X.sb, Mode::F64, ap, "qr_apply", 0);
+}
+
 void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int passes) {
   if (jobs.empty()) return;
-  bool fast = true;
-  for (auto& j : jobs) fast = fast && j.k <= kRegMax && !j.Rout && j.T;
+  bool fast = true, blocked = true;
+  for (auto& j : jobs) {
+    fast = fast && j.k <= kRegMax && !j.Rout && j.T;
+    blocked = blocked && j.k <= 2 * kRegMax && !j.Rout && j.T;
+  }
+  if (!fast && blocked) {
+    for (int pass = 0; pass < passes; ++pass) add_chol_inv_blocked(X, P, jobs, pass);
+    if (passes % 2 == 1) {
+      std::vector<PermDesc> cp;
+      for (auto& j : jobs)
+        cp.push_back(perm4(j.T, 0, j.X, 0, {1, 1, j.n, j.k}, {0, 0, j.k, 1}, {0, 0, j.ld, 1}));
+      add_perm(P, cp, "copy");
+    }
+    return;
+  }
   for (int pass = 0; pass < passes; ++pass) {
     std::vector<GemmJob> gj, tj;
     std::vector<CholDesc> cd;
@@ -1144,9 +1218,9 @@ void rec_assign_inverse(Ctx& X, Program& P, std::vector<BondJob>& bj) {
                              out64(B.V, r)});
       sv1.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 1});
     }
-    orthU.push_back(CholQRJob{Ci, b.n, r, r, B.G, B.R, nullptr, r <= kRegMax ? B.Y2 : nullptr});
+    orthU.push_back(CholQRJob{Ci, b.n, r, r, B.G, B.R, nullptr, r <= 2 * kRegMax ? B.Y2 : nullptr});
     // runs after orthU in stream order, so it reuses the same G and R scratch
-    orthV.push_back(CholQRJob{B.V, b.m, r, r, B.G, B.R, nullptr, r <= kRegMax ? B.SVt : nullptr});
+    orthV.push_back(CholQRJob{B.V, b.m, r, r, B.G, B.R, nullptr, r <= 2 * kRegMax ? B.SVt : nullptr});
     sg.push_back(SignDesc{Ci, b.n, r, r, B.sign, nullptr});
     sv2.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.sign, 0, 0});
     envl.push_back(GemmJob{r, N, b.n, op64(Ci, false, r), opW(X, S.XL[i], false, N, S.amXL[i]),

@@ -79,7 +79,7 @@ def test_eig_against_numpy(hooks, k, r):
     assert np.abs(np.abs(np.sum(Z * V, axis=0)) - 1).max() < 1e-8
 
 
-@pytest.mark.parametrize("n,k", [(40, 12), (512, 144), (300, 300), (1024, 272)])
+@pytest.mark.parametrize("n,k", [(40, 12), (512, 144), (600, 161), (300, 300), (1024, 272), (900, 321)])
 def test_cholqr2_against_householder(hooks, n, k):
     from tests.gpu_util import dev, ptr
     rng = np.random.default_rng(n + k)
