@@ -100,6 +100,16 @@ __device__ __forceinline__ unsigned short lo_part(T v, float inv_scale) {
   return f2bf(x - bf2f(f2bf(x)));
 }
 
+// Global-memory views of generic pointers: loads and stores then use the
+// global instructions, whose completion is tracked apart from LDS traffic
+// (generic "flat" accesses would make every LDS wait also wait for them).
+#define GAS __attribute__((address_space(1)))
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ const GAS T* gload_ptr(const T* p) { return (const GAS T*)p; }
+template <typename T>
+__device__ __forceinline__ GAS T* gstore_ptr(T* p) { return (GAS T*)p; }
+
 // Loads a (ROWS x BK) operand tile into registers in the stored type; the
 // conversion to the LDS type (and the BF16 scale) happens at the LDS store.
 template <typename T, bool KCONTIG, int ROWS, int BK>
@@ -121,37 +131,23 @@ struct TileLoader {
         k = k0 + idx / (ROWS / 4);
         r = 4 * (idx % (ROWS / 4));
       }
-      if constexpr (KCONTIG) {
-        const T* p = base + (long long)r * ld + k;
-        if (vec_ok && r < rows_valid && k + 3 < kend) {
-          if constexpr (sizeof(T) == 4) {
-            float4 q = *reinterpret_cast<const float4*>(p);
-            v[i][0] = q.x; v[i][1] = q.y; v[i][2] = q.z; v[i][3] = q.w;
-          } else {
-            double2 q0 = *reinterpret_cast<const double2*>(p);
-            double2 q1 = *reinterpret_cast<const double2*>(p + 2);
-            v[i][0] = q0.x; v[i][1] = q0.y; v[i][2] = q1.x; v[i][3] = q1.y;
-          }
+      const T* p = KCONTIG ? base + (long long)r * ld + k : base + (long long)k * ld + r;
+      const bool full = KCONTIG ? (r < rows_valid && k + 3 < kend) : (r + 3 < rows_valid && k < kend);
+      if (vec_ok && full) {
+        if constexpr (sizeof(T) == 4) {
+          const floatx4 q = *reinterpret_cast<const GAS floatx4*>(gload_ptr(p));
+          v[i][0] = q[0]; v[i][1] = q[1]; v[i][2] = q[2]; v[i][3] = q[3];
         } else {
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            v[i][j] = (r < rows_valid && k + j < kend) ? p[j] : T(0);
+          const doublex2 q0 = *reinterpret_cast<const GAS doublex2*>(gload_ptr(p));
+          const doublex2 q1 = *reinterpret_cast<const GAS doublex2*>(gload_ptr(p + 2));
+          v[i][0] = q0[0]; v[i][1] = q0[1]; v[i][2] = q1[0]; v[i][3] = q1[1];
         }
       } else {
-        const T* p = base + (long long)k * ld + r;
-        if (vec_ok && r + 3 < rows_valid && k < kend) {
-          if constexpr (sizeof(T) == 4) {
-            float4 q = *reinterpret_cast<const float4*>(p);
-            v[i][0] = q.x; v[i][1] = q.y; v[i][2] = q.z; v[i][3] = q.w;
-          } else {
-            double2 q0 = *reinterpret_cast<const double2*>(p);
-            double2 q1 = *reinterpret_cast<const double2*>(p + 2);
-            v[i][0] = q0.x; v[i][1] = q0.y; v[i][2] = q1.x; v[i][3] = q1.y;
-          }
-        } else {
+        const GAS T* g = gload_ptr(p);
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            v[i][j] = (r + j < rows_valid && k < kend) ? p[j] : T(0);
+        for (int j = 0; j < 4; ++j) {
+          const bool ok = KCONTIG ? (r < rows_valid && k + j < kend) : (r + j < rows_valid && k < kend);
+          v[i][j] = ok ? g[j] : T(0);
         }
       }
     }
@@ -358,7 +354,7 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
       for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          mine[(((wave * FM + i) * FN + j) * 4 + e) * 64 + lane] = acc[i][j][e];
+          gstore_ptr(mine)[(((wave * FM + i) * FN + j) * 4 + e) * 64 + lane] = acc[i][j][e];
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -376,14 +372,14 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
       for (int j = 0; j < FN; ++j) acc[i][j] = accv_t{0, 0, 0, 0};
 #pragma unroll 4
     for (int s = 0; s < d.splits; ++s) {
-      const acc_t* ps = part + (long long)s * (BM * BN) + lane;
+      const GAS acc_t* ps = gload_ptr(part + (long long)s * (BM * BN) + lane);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            acc[i][j][e] += __builtin_nontemporal_load(ps + (((wave * FM + i) * FN + j) * 4 + e) * 64);
+            acc[i][j][e] += ps[(((wave * FM + i) * FN + j) * 4 + e) * 64];
     }
     if (threadIdx.x == 0) d.counters[tile_id] = 0;
   }
@@ -402,7 +398,7 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
       for (int e = 0; e < 4; ++e) {
         const int row = m0 + wm + 16 * i + (MODE == Mode::F64 ? lgrp + 4 * e : 4 * lgrp + e);
         if (row < d.M && col < d.N) {
-          TC* p = Cb + (long long)row * d.ldc + col;
+          GAS TC* p = gstore_ptr(Cb + (long long)row * d.ldc + col);
           double v = alpha * (double)acc[i][j][e];
           if (d.beta) v += (double)*p;
           *p = (TC)v;

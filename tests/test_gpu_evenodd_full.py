@@ -109,11 +109,12 @@ def test_first_sweep_against_stored_oracle(pair, precision, tol):
     norm2 = mpo.left_orth_norm(C) ** 2
     inner = mpo.three_layer_inner(C, A, B)
     probes = [mpo.three_layer_inner(C, A, Bi) for Bi in mk.probes(B)]
-    # the probes are measured against their common scale (the largest of
-    # them): a probe nearly orthogonal to C has a small value whose relative
-    # error says nothing about C
-    pscale = max(abs(v) for v in ref["probes"])
+    # a probe is measured against its Cauchy-Schwarz scale ||C|| ||A B_i||
+    # (||A B_i||^2 from the device transfer pass): the probes are nearly
+    # orthogonal to C, so their own values are no scale for an error in C
+    from paper_2606_23274_amd.api import fit_error
+    pscale = [np.sqrt(ref["norm2"] * fit_error(A, Bi, C)[1]) for Bi in mk.probes(B)]
     rel = [abs(norm2 / ref["norm2"] - 1), abs(inner / ref["inner_ab"] - 1)] + \
-          [abs(p - v) / pscale for p, v in zip(probes, ref["probes"])]
+          [abs(p - v) / sc for p, v, sc in zip(probes, ref["probes"], pscale)]
     print(precision, "relative differences", rel)
     assert max(rel) <= tol
