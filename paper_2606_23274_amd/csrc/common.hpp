@@ -11,6 +11,15 @@
 namespace mpofit {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Global-memory views of generic pointers: accesses through them use the
+// global instructions, whose completion is tracked apart from LDS traffic
+// (generic "flat" accesses make every LDS wait also wait for memory).
+#define GAS __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const GAS T* gload_ptr(const T* p) { return (const GAS T*)p; }
+template <typename T>
+__device__ __forceinline__ GAS T* gstore_ptr(T* p) { return (GAS T*)p; }
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 

@@ -100,15 +100,7 @@ __device__ __forceinline__ unsigned short lo_part(T v, float inv_scale) {
   return f2bf(x - bf2f(f2bf(x)));
 }
 
-// Global-memory views of generic pointers: loads and stores then use the
-// global instructions, whose completion is tracked apart from LDS traffic
-// (generic "flat" accesses would make every LDS wait also wait for them).
-#define GAS __attribute__((address_space(1)))
 typedef double doublex2 __attribute__((ext_vector_type(2)));
-template <typename T>
-__device__ __forceinline__ const GAS T* gload_ptr(const T* p) { return (const GAS T*)p; }
-template <typename T>
-__device__ __forceinline__ GAS T* gstore_ptr(T* p) { return (GAS T*)p; }
 
 // Loads a (ROWS x BK) operand tile into registers in the stored type; the
 // conversion to the LDS type (and the BF16 scale) happens at the LDS store.

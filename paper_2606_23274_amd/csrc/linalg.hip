@@ -23,12 +23,17 @@ constexpr int kPackedMax = 176;      // packed lower triangle in LDS up to this 
 
 __device__ __forceinline__ long long pidx(int i, int j) { return (long long)i * (i + 1) / 2 + j; }
 
-struct Sym {
+// Symmetric matrix, lower triangle (i >= j): packed in LDS, or full
+// row-major in global memory.
+template <bool GLOBAL> struct SymT;
+template <> struct SymT<false> {
   double* p;
-  int ld;  // 0: packed lower
-  __device__ __forceinline__ double& at(int i, int j) const {  // i >= j
-    return ld ? p[(long long)i * ld + j] : p[pidx(i, j)];
-  }
+  __device__ __forceinline__ double& at(int i, int j) const { return p[pidx(i, j)]; }
+};
+template <> struct SymT<true> {
+  GAS double* p;
+  int ld;
+  __device__ __forceinline__ GAS double& at(int i, int j) const { return p[(long long)i * ld + j]; }
 };
 
 template <int NW>
@@ -45,15 +50,20 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------- Cholesky
+template <bool GLOBAL>
 __global__ void __launch_bounds__(kBig) chol_kernel(const CholDesc* __restrict__ descs) {
   extern __shared__ double lds[];
   __shared__ double s_piv;
   const CholDesc d = descs[blockIdx.x];
   const int k = d.k;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  Sym A{k <= kPackedMax ? lds : d.R, k <= kPackedMax ? 0 : d.ldr};
+  SymT<GLOBAL> A;
+  if constexpr (GLOBAL) A = SymT<true>{gstore_ptr(d.R), d.ldr};
+  else A = SymT<false>{lds};
+  const GAS double* G = gload_ptr(d.G);
+  GAS double* Rg = gstore_ptr(d.R);
   for (int i = wave; i < k; i += kBig / 64)
-    for (int j = lane; j <= i; j += 64) A.at(i, j) = d.G[(long long)i * d.ldg + j];
+    for (int j = lane; j <= i; j += 64) A.at(i, j) = G[(long long)i * d.ldg + j];
   if (d.shift > 0.0) {  // G + shift * trace(G) I
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -91,16 +101,16 @@ __global__ void __launch_bounds__(kBig) chol_kernel(const CholDesc* __restrict__
   __syncthreads();
   if (bad && d.flag) atomicOr(d.flag, FLAG_CHOL);
   // R = L^T, row-major upper triangle; zero below
-  if (k <= kPackedMax) {
+  if constexpr (!GLOBAL) {
     for (int i = wave; i < k; i += kBig / 64)
       for (int j = lane; j < k; j += 64)
-        d.R[(long long)i * d.ldr + j] = (j >= i) ? A.at(j, i) : 0.0;
+        Rg[(long long)i * d.ldr + j] = (j >= i) ? A.at(j, i) : 0.0;
   } else {
     for (int i = wave; i < k; i += kBig / 64)
       for (int j = lane; j < i; j += 64) {
-        double lo = d.R[(long long)i * d.ldr + j];  // L(i, j)
-        d.R[(long long)j * d.ldr + i] = lo;
-        d.R[(long long)i * d.ldr + j] = 0.0;
+        double lo = Rg[(long long)i * d.ldr + j];  // L(i, j)
+        Rg[(long long)j * d.ldr + i] = lo;
+        Rg[(long long)i * d.ldr + j] = 0.0;
       }
   }
 }
@@ -111,12 +121,13 @@ __global__ void __launch_bounds__(kBig) trsm_kernel(const TrsmDesc* __restrict__
   __shared__ double s_inv[64 * NS];
   const TrsmDesc d = descs[blockIdx.y];
   const int k = d.k;
-  for (int j = threadIdx.x; j < k; j += kBig) s_inv[j] = 1.0 / d.R[(long long)j * d.ldr + j];
+  const GAS double* Rg = gload_ptr(d.R);
+  for (int j = threadIdx.x; j < k; j += kBig) s_inv[j] = 1.0 / Rg[(long long)j * d.ldr + j];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (kBig / 64) + (threadIdx.x >> 6);
   if (row >= d.n) return;
-  double* x = d.X + (long long)row * d.ldx;
+  GAS double* x = gstore_ptr(d.X + (long long)row * d.ldx);
   double y[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
@@ -130,7 +141,7 @@ __global__ void __launch_bounds__(kBig) trsm_kernel(const TrsmDesc* __restrict__
       if (j >= k) break;
       const double xj = __shfl(y[s], jj) * s_inv[j];
       if (lane == jj) y[s] = xj;
-      const double* rj = d.R + (long long)j * d.ldr;
+      const GAS double* rj = Rg + (long long)j * d.ldr;
 #pragma unroll
       for (int s2 = s; s2 < NS; ++s2) {
         const int c = 64 * s2 + lane;
@@ -148,15 +159,17 @@ __global__ void __launch_bounds__(kBig) trsm_kernel(const TrsmDesc* __restrict__
 // ---------------------------------------------------------------- eigen
 // work layout (doubles): d[k] e[k] tau[k] V[k*k] X[k*r] Hfull[k*k]
 struct EigWork {
-  double *d, *e, *tau, *V, *X, *H;
+  GAS double *d, *e, *tau, *V, *X, *H;
   __device__ EigWork(double* w, int k, int r)
-      : d(w), e(w + k), tau(w + 2 * k), V(w + 3 * k), X(w + 3 * k + (long long)k * k),
-        H(w + 3 * k + (long long)k * k + (long long)k * r) {}
+      : d(gstore_ptr(w)), e(gstore_ptr(w + k)), tau(gstore_ptr(w + 2 * k)), V(gstore_ptr(w + 3 * k)),
+        X(gstore_ptr(w + 3 * k + (long long)k * k)),
+        H(gstore_ptr(w + 3 * k + (long long)k * k + (long long)k * r)) {}
 };
 
 // Householder reduction of the symmetric H to tridiagonal T = Q^T H Q with
 // Q = H_0 H_1 ... H_{k-3}, H_j = I - tau_j v_j v_j^T, v_j(j+1) = 1 (LAPACK's
 // dsytrd convention, lower triangle).
+template <bool GLOBAL>
 __global__ void __launch_bounds__(kBig) sytrd_kernel(const EigDesc* __restrict__ descs) {
   extern __shared__ double lds[];
   __shared__ double red[16];
@@ -165,12 +178,14 @@ __global__ void __launch_bounds__(kBig) sytrd_kernel(const EigDesc* __restrict__
   const int k = dd.k;
   EigWork W(dd.work, k, dd.r);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool packed = k <= kPackedMax;
   double* sv = lds;          // k
   double* sp = lds + k;      // k
-  Sym A{packed ? lds + 2 * k : W.H, packed ? 0 : k};
+  SymT<GLOBAL> A;
+  if constexpr (GLOBAL) A = SymT<true>{W.H, k};
+  else A = SymT<false>{lds + 2 * k};
+  const GAS double* Hin = gload_ptr(dd.H);
   for (int i = wave; i < k; i += 16)
-    for (int j = lane; j <= i; j += 64) A.at(i, j) = dd.H[(long long)i * dd.ldh + j];
+    for (int j = lane; j <= i; j += 64) A.at(i, j) = Hin[(long long)i * dd.ldh + j];
   for (int j = threadIdx.x; j < k * k; j += kBig) W.V[j] = 0.0;
   __syncthreads();
   for (int j = 0; j + 2 < k; ++j) {
@@ -503,7 +518,7 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int r = tr + 32 * i, c = tc + 32 * j;
-      a[i][j] = (r < k && c < k) ? d.G[(long long)r * d.ldg + c] : (r == c ? 1.0 : 0.0);
+      a[i][j] = (r < k && c < k) ? gload_ptr(d.G)[(long long)r * d.ldg + c] : (r == c ? 1.0 : 0.0);
     }
   bool bad = false;
   // Cholesky: a(r, c) -= a(r, jj) a(c, jj) / a(jj, jj) on the trailing block;
@@ -592,7 +607,7 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int r = tr + 32 * i, c = tc + 32 * j;
-      if (r < k && c < k) d.R[(long long)c * d.ldr + r] = (r >= c) ? a[i][j] : 0.0;
+      if (r < k && c < k) gstore_ptr(d.R)[(long long)c * d.ldr + r] = (r >= c) ? a[i][j] : 0.0;
     }
 }
 
@@ -607,7 +622,7 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
   const EigDesc dd = descs[blockIdx.x];
   const int k = dd.k;
   EigWork W(dd.work, k, dd.r);
-  double* vstore = W.H;
+  GAS double* vstore = W.H;
   const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double a[NB][NB];
@@ -617,7 +632,7 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
     for (int j = 0; j < NB; ++j) {
       const int r = tr + 32 * i, c = tc + 32 * j;
       const int hi = r > c ? r : c, lo = r > c ? c : r;
-      a[i][j] = (r < k && c < k) ? dd.H[(long long)hi * dd.ldh + lo] : 0.0;
+      a[i][j] = (r < k && c < k) ? gload_ptr(dd.H)[(long long)hi * dd.ldh + lo] : 0.0;
     }
   // Step jj works on the trailing block (rows and columns > jj), which lies
   // in register blocks >= JB = jj / 32; the JB loop is unrolled so register
@@ -889,10 +904,14 @@ void launch_chol(const CholDesc* d, int n, int max_k, int inverse, hipStream_t s
     hipLaunchKernelGGL(chol_inv_reg_kernel<kRegNB>, dim3(n), dim3(kBig), 0, s, d);
     return;
   }
-  // every problem with k <= kPackedMax works in LDS, whatever the batch's max
-  const int kp = std::min(max_k, kPackedMax);
-  size_t lds = (size_t)kp * (kp + 1) / 2 * sizeof(double);
-  hipLaunchKernelGGL(chol_kernel, dim3(n), dim3(kBig), lds, s, d);
+  // packed lower triangle in LDS when every problem fits, else the factor's
+  // own output array in global memory serves as working storage
+  if (max_k <= kPackedMax) {
+    const size_t lds = (size_t)max_k * (max_k + 1) / 2 * sizeof(double);
+    hipLaunchKernelGGL(chol_kernel<false>, dim3(n), dim3(kBig), lds, s, d);
+  } else {
+    hipLaunchKernelGGL(chol_kernel<true>, dim3(n), dim3(kBig), 0, s, d);
+  }
 }
 
 void launch_trsm(const TrsmDesc* d, int n, int max_rows, hipStream_t s) {
@@ -921,9 +940,12 @@ void launch_eig(const EigDesc* d, const EigDesc* h, int n, int reg, int stage, h
     if (reg) {
       hipLaunchKernelGGL(sytrd_reg_kernel<kRegNB>, dim3(n), dim3(kBig), 0, s, d);
     } else {
-      const int kp = std::min(max_k, kPackedMax);
-      const size_t lds1 = (2 * (size_t)max_k + (size_t)kp * (kp + 1) / 2) * sizeof(double);
-      hipLaunchKernelGGL(sytrd_kernel, dim3(n), dim3(kBig), lds1, s, d);
+      if (max_k <= kPackedMax) {
+        const size_t lds1 = (2 * (size_t)max_k + (size_t)max_k * (max_k + 1) / 2) * sizeof(double);
+        hipLaunchKernelGGL(sytrd_kernel<false>, dim3(n), dim3(kBig), lds1, s, d);
+      } else {
+        hipLaunchKernelGGL(sytrd_kernel<true>, dim3(n), dim3(kBig), 2 * (size_t)max_k * sizeof(double), s, d);
+      }
     }
   }
   if (all || stage == 1)
