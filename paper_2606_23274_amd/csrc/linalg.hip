@@ -481,6 +481,16 @@ __device__ __forceinline__ double row_reduce32(double v) {
   return v + __shfl_xor(v, 16);
 }
 
+// Sum over the 64 lanes of a wave, returned to all of them.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0x128>(v);
+  v += dpp_d<0x124>(v);
+  v += dpp_d<0x122>(v);
+  v += dpp_d<0x121>(v);
+  v += __shfl_xor(v, 16);
+  return v + __shfl_xor(v, 32);
+}
+
 // 1/x and 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton
 // steps (about 1 ulp), a shorter dependency chain than the IEEE division.
 __device__ __forceinline__ double rcp_nr(double x) {
@@ -497,14 +507,18 @@ __device__ __forceinline__ double rsq_nr(double x) {
   return y * fma(-h * y, y, 1.5);
 }
 
-// G = L L^T (Cholesky, L lower) then R^{-1} = (L^{-1})^T written row-major
-// (upper triangular, zeros below).  One barrier per step: the owners of
-// column jj (and, for the inverse, of row jj) publish it (double-buffered),
-// then every thread updates its trailing entries with masks folded into the
-// broadcast vectors; blocks outside the active region are skipped with
-// uniform branches.  The inverse X = L^{-1} overwrites L in place (row jj of
-// X only mixes columns <= jj, whose L entries are no longer needed), so one
-// register block holds the matrix.
+// G = L L^T (Cholesky, L lower) and R^{-1} = (L^{-1})^T written row-major
+// (upper triangular, zeros below), in one pass over the columns.  Step jj
+// (one barrier): the owners of column jj of the updated matrix and of row jj
+// of X = L^{-1} publish them (double-buffered); every thread then
+//   - finishes the Cholesky step: A(r, c) -= A(r, jj) A(c, jj) / A(jj, jj) on
+//     the trailing block r, c > jj, with L(r, jj) = A(r, jj) / sqrt(A(jj, jj));
+//   - does the row-oriented inverse step on columns c <= jj:
+//     X(jj, c) /= L(jj, jj), X(jj, jj) = 1 / L(jj, jj),
+//     X(r, c) -= L(r, jj) X(jj, c), X(r, jj) = -L(r, jj) X(jj, jj) (r > jj).
+// X overwrites L in place: row jj of X only mixes columns <= jj, whose L
+// entries no later Cholesky step reads.  Register indices are constants (the
+// column-block loop is unrolled); masks live in the broadcast vectors.
 template <int NB>
 __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __restrict__ descs) {
   __shared__ double colb[2][32 * NB];
@@ -521,51 +535,12 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
       a[i][j] = (r < k && c < k) ? gload_ptr(d.G)[(long long)r * d.ldg + c] : (r == c ? 1.0 : 0.0);
     }
   bool bad = false;
-  // Cholesky: a(r, c) -= a(r, jj) a(c, jj) / a(jj, jj) on the trailing block;
-  // column jj of L is a(:, jj) / sqrt(a(jj, jj)).  The loop over the column
-  // block JB is unrolled, so every register index below is a constant.
 #pragma unroll
   for (int JB = 0; JB < NB; ++JB) {
     const int jend = min(k, 32 * JB + 32);
     for (int jj = 32 * JB; jj < jend; ++jj) {
       const int jt = jj & 31, buf = jj & 1;
-      if (tc == jt) {
-#pragma unroll
-        for (int i = JB; i < NB; ++i) colb[buf][tr + 32 * i] = (tr + 32 * i >= jj) ? a[i][JB] : 0.0;
-      }
-      __syncthreads();
-      const double djj = colb[buf][jj];
-      const bool ok = djj > 0.0 && djj < INFINITY;
-      if (!ok) bad = true;
-      const double invd = ok ? rcp_nr(djj) : 0.0;
-      double cr[NB], cc[NB];
-#pragma unroll
-      for (int i = JB; i < NB; ++i) {
-        const int r = tr + 32 * i, c = tc + 32 * i;
-        cr[i] = (r > jj) ? colb[buf][r] * invd : 0.0;
-        cc[i] = (c > jj) ? colb[buf][c] : 0.0;
-      }
-      if (tc == jt) {  // finish column jj of L: scale by 1/sqrt(d)
-        const double invs = ok ? rsq_nr(djj) : 0.0;
-#pragma unroll
-        for (int i = JB; i < NB; ++i)
-          if (tr + 32 * i >= jj) a[i][JB] *= invs;
-      }
-#pragma unroll
-      for (int i = JB; i < NB; ++i)
-#pragma unroll
-        for (int j = JB; j < NB; ++j) a[i][j] -= cr[i] * cc[j];
-    }
-  }
-  // In-place X = L^{-1}, row by row: X(jj, c) = X(jj, c) / L(jj, jj) for
-  // c < jj, X(jj, jj) = 1 / L(jj, jj); then for r > jj
-  // X(r, c) -= L(r, jj) X(jj, c) (c < jj) and X(r, jj) = -L(r, jj) X(jj, jj).
-#pragma unroll
-  for (int JB = 0; JB < NB; ++JB) {
-    const int jend = min(k, 32 * JB + 32);
-    for (int jj = 32 * JB; jj < jend; ++jj) {
-      const int jt = jj & 31, buf = jj & 1;
-      if (tc == jt) {  // L(:, jj)
+      if (tc == jt) {  // column jj of the updated matrix (rows >= jj)
 #pragma unroll
         for (int i = JB; i < NB; ++i) colb[buf][tr + 32 * i] = (tr + 32 * i >= jj) ? a[i][JB] : 0.0;
       }
@@ -574,28 +549,41 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
         for (int j = 0; j <= JB; ++j) rowb[buf][tc + 32 * j] = (tc + 32 * j < jj) ? a[JB][j] : 0.0;
       }
       __syncthreads();
-      const double ljj = colb[buf][jj];
-      const double linv = ljj > 0.0 ? rcp_nr(ljj) : 0.0;
-      double l[NB], xr[NB];
+      const double djj = colb[buf][jj];
+      const bool ok = djj > 0.0 && djj < INFINITY;
+      if (!ok) bad = true;
+      const double invd = ok ? rcp_nr(djj) : 0.0;
+      const double invs = ok ? rsq_nr(djj) : 0.0;  // 1 / L(jj, jj)
+      double cr[NB], cc[NB], l[NB], xr[NB];
 #pragma unroll
-      for (int i = JB; i < NB; ++i) l[i] = (tr + 32 * i > jj) ? colb[buf][tr + 32 * i] : 0.0;
+      for (int i = JB; i < NB; ++i) {
+        const int r = tr + 32 * i, c = tc + 32 * i;
+        const double ar = (r > jj) ? colb[buf][r] : 0.0;
+        cr[i] = ar * invd;
+        l[i] = ar * invs;  // L(r, jj)
+        cc[i] = (c > jj) ? colb[buf][c] : 0.0;
+      }
 #pragma unroll
-      for (int j = 0; j <= JB; ++j) xr[j] = rowb[buf][tc + 32 * j] * linv;  // zero at columns >= jj
+      for (int j = 0; j <= JB; ++j) xr[j] = rowb[buf][tc + 32 * j] * invs;  // X(jj, c) / L(jj, jj)
+      // Cholesky trailing update (columns > jj) and inverse update (columns < jj)
 #pragma unroll
-      for (int i = JB; i < NB; ++i)
+      for (int i = JB; i < NB; ++i) {
+#pragma unroll
+        for (int j = JB; j < NB; ++j) a[i][j] -= cr[i] * cc[j];
 #pragma unroll
         for (int j = 0; j <= JB; ++j) a[i][j] -= l[i] * xr[j];
-      if (tr == jt) {  // row jj: scale the X part
+      }
+      if (tr == jt) {  // row jj of X: the scaled part
 #pragma unroll
         for (int j = 0; j <= JB; ++j)
-          if (tc + 32 * j < jj) a[JB][j] *= linv;
+          if (tc + 32 * j < jj) a[JB][j] *= invs;
       }
-      if (tc == jt) {  // column jj: X(jj, jj) and X(r, jj) for r > jj
+      if (tc == jt) {  // column jj of X: X(jj, jj) and X(r, jj) for r > jj
 #pragma unroll
         for (int i = JB; i < NB; ++i) {
           const int r = tr + 32 * i;
-          if (r == jj) a[i][JB] = linv;
-          else if (r > jj) a[i][JB] = -l[i] * linv;
+          if (r == jj) a[i][JB] = invs;
+          else if (r > jj) a[i][JB] = -l[i] * invs;
         }
       }
     }
@@ -658,37 +646,36 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
         for (int i = 0; i < JB; ++i) { v[tr + 32 * i] = 0.0; w[tr + 32 * i] = 0.0; }
       }
       __syncthreads();
-      if (wave == 0) {  // norm, beta, tau and the scaled reflector v (v(jj+1) = 1)
-        double part = 0.0;
-        for (int r = jj + 2 + lane; r < k; r += 64) part += v[r] * v[r];
-        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-        const double alpha = v[jj + 1];
-        double tau = 0.0, beta = alpha, scal = 0.0;
-        if (part > 0.0) {
-          beta = -copysign(sqrt(alpha * alpha + part), alpha);
-          tau = (beta - alpha) / beta;
-          scal = 1.0 / (alpha - beta);
-        }
-        for (int r = 32 * JB + lane; r < 32 * NB; r += 64) {
-          double vr = 0.0;
-          if (tau != 0.0) vr = (r == jj + 1) ? 1.0 : (r > jj + 1 && r < k ? v[r] * scal : 0.0);
-          v[r] = vr;
-          if (r < k) vstore[(long long)jj * k + r] = vr;
-        }
-        for (int r = lane; r < 32 * JB && r < k; r += 64) vstore[(long long)jj * k + r] = 0.0;
+      // every wave forms the reflector parameters from the column in LDS
+      // (identical arithmetic, so identical values), which saves a barrier
+      // and leaves no wave idle; v(r) is generated on the fly
+      double part = 0.0;
+      for (int r = jj + 2 + lane; r < k; r += 64) part += v[r] * v[r];
+      part = wave_sum(part);
+      const double alpha = v[jj + 1];
+      double tau = 0.0, beta = alpha, scal = 0.0;
+      if (part > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + part), alpha);
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      auto vref = [&](int r) {
+        return r == jj + 1 ? 1.0 : (r > jj + 1 && r < k ? v[r] * scal : 0.0);
+      };
+      if (wave == 0) {  // the reflector (v(jj+1) = 1) and tau for the back-accumulation
+        for (int r = lane; r < k; r += 64)
+          vstore[(long long)jj * k + r] = tau != 0.0 ? vref(r) : 0.0;
         if (lane == 0) {
           W.e[jj] = beta;
           W.tau[jj] = tau;
           s_taus[jj] = tau;
         }
       }
-      __syncthreads();
-      const double tau = s_taus[jj];
       if (tau == 0.0) continue;  // uniform
       // p = tau * A22 v on rows > jj (v vanishes on rows and columns <= jj)
       double vc[NB];
 #pragma unroll
-      for (int j = JB; j < NB; ++j) vc[j] = v[tc + 32 * j];
+      for (int j = JB; j < NB; ++j) vc[j] = vref(tc + 32 * j);
 #pragma unroll
       for (int i = JB; i < NB; ++i) {
         double pr = 0.0;
@@ -699,13 +686,9 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
       }
       __syncthreads();
       // w = p - (tau/2)(p.v) v: every thread forms p.v from the trailing rows
-      // (its wave's half-rows reduce the products; the halves meet in LDS)
       double pv = 0.0;
 #pragma unroll
-      for (int i = JB; i < NB; ++i) {
-        const int r = tc + 32 * i;
-        pv += w[r] * v[r];
-      }
+      for (int i = JB; i < NB; ++i) pv += w[tc + 32 * i] * vc[i];
       pv = row_reduce32<NB>(pv);
       const double K = -0.5 * tau * pv;
       // A22 -= v w^T + w v^T with w = p + K v (trailing block only)
@@ -715,7 +698,7 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
 #pragma unroll
       for (int i = JB; i < NB; ++i) {
         const int r = tr + 32 * i;
-        const double vi = v[r], wi = w[r] + K * vi;
+        const double vi = vref(r), wi = w[r] + K * vi;
 #pragma unroll
         for (int j = JB; j < NB; ++j) a[i][j] -= vi * wc[j] + wi * vc[j];
       }
@@ -799,15 +782,6 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
 
 
 // ---------------------------------------------------------------- one-sided Jacobi SVD
-// Sum over the 64 lanes of a wave, returned to all of them.
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_d<0x128>(v);
-  v += dpp_d<0x124>(v);
-  v += dpp_d<0x122>(v);
-  v += dpp_d<0x121>(v);
-  v += __shfl_xor(v, 16);
-  return v + __shfl_xor(v, 32);
-}
 
 // Round-robin pairing of qq (even) columns: player qq-1 stays, the others
 // rotate; round t pairs (qq-1, t) and (t+k, t-k) mod (qq-1), k = 1 .. qq/2-1.
