@@ -198,8 +198,8 @@ def accuracy(A, B, n_sweeps, Cs_oracle, tuning):
     if Cs_oracle:
         out["oracle_fp64"] = {"eps": [fit_error(A, B, C)[0] for C in Cs_oracle]}
     for prec, p in (("fp32", w["p"]), ("bf16x3", w["p"]), ("bf16", w["p"]), ("fp64", w["p"]),
-                    ("fp64", -1)):
-        key = prec + ("_plain" if p < 0 else "")
+                    ("fp64", -1), ("fp32", 48)):
+        key = prec + ("_plain" if p < 0 else "") + (f"_p{p}" if p not in (-1, w["p"]) else "")
         ctx = FitContext([(A, B)], w["chi_c"], precision=prec, sketch_p=p, seed=w["seed"],
                          tuning=tuning if prec == "fp32" else None)
         eps, delta = [], {}
@@ -208,7 +208,7 @@ def accuracy(A, B, n_sweeps, Cs_oracle, tuning):
             ctx.sweep(1)
             C = ctx.export_numpy(0)
             eps.append(fit_error(A, B, C)[0])
-            if p >= 0 and s <= last and s in (0, last):
+            if p == w["p"] and s <= last and s in (0, last):
                 delta[f"sweep{s + 1}"] = mpo.rel_diff(C, Cs_oracle[s])
         ctx.close()
         torch.cuda.synchronize()
@@ -379,7 +379,10 @@ def main():
         acc = accuracy(A, B, args.sweeps, Cs, table)
         # time to the plain FP64 path's final accuracy
         target = acc["fp64_plain"]["eps"][-1] * 1.01
-        for key, rate in (("fp32", value), ("fp64_plain", others["fp64_plain"]["sweeps_per_s"])):
+        wl48, _, _, _ = run_gpu(A, B, "fp32", 48, args.steps, args.warmup)
+        others["fp32_p48"] = {"sweeps_per_s": round(args.steps / wl48, 3)}
+        for key, rate in (("fp32", value), ("fp32_p48", args.steps / wl48),
+                          ("fp64_plain", others["fp64_plain"]["sweeps_per_s"])):
             e = acc[key]["eps"]
             n_need = next((i + 1 for i, v in enumerate(e) if v <= target), None)
             acc[key]["sweeps_to_1pct_of_fp64_plain_final_eps"] = n_need

@@ -55,20 +55,35 @@ __global__ void omega_kernel(const OmegaDesc* __restrict__ descs) {
   }
 }
 
-__global__ void signfix_kernel(const SignDesc* __restrict__ descs) {
-  __shared__ double s_max[4][64];
-  __shared__ int s_idx[4][64];
+// Sign rule on the columns of U: the entry of largest magnitude of each
+// column becomes positive (the first such row wins ties).  A workgroup takes
+// 64 columns; its 16 waves split the rows, four independent loads in flight
+// per lane.
+constexpr int kSignWaves = 16;
+__global__ void __launch_bounds__(64 * kSignWaves) signfix_kernel(const SignDesc* __restrict__ descs) {
+  __shared__ double s_max[kSignWaves][64];
+  __shared__ int s_idx[kSignWaves][64];
   __shared__ double s_sgn[64];
   const SignDesc d = descs[blockIdx.y];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = blockIdx.x * 64 + lane;
   if (blockIdx.x * 64 >= d.r) return;  // uniform
-  double best = -1.0, val = 0.0;
+  GAS double* U = gstore_ptr(d.U);
+  double best = -1.0;
   int bi = 0x7fffffff;
   if (col < d.r) {
-    for (int i = wave; i < d.n; i += 4) {
-      const double v = d.U[(long long)i * d.ld + col];
-      if (fabs(v) > best) { best = fabs(v); bi = i; val = v; }
+    int i = wave;
+    for (; i + 3 * kSignWaves < d.n; i += 4 * kSignWaves) {
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = U[(long long)(i + q * kSignWaves) * d.ld + col];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (fabs(v[q]) > best) { best = fabs(v[q]); bi = i + q * kSignWaves; }
+    }
+    for (; i < d.n; i += kSignWaves) {
+      const double v = U[(long long)i * d.ld + col];
+      if (fabs(v) > best) { best = fabs(v); bi = i; }
     }
   }
   s_max[wave][lane] = best;
@@ -77,25 +92,22 @@ __global__ void signfix_kernel(const SignDesc* __restrict__ descs) {
   if (wave == 0) {
     double b = s_max[0][lane];
     int ii = s_idx[0][lane];
-    int who = 0;
-    for (int w = 1; w < 4; ++w) {
+    for (int w = 1; w < kSignWaves; ++w) {
       const double bw = s_max[w][lane];
       const int iw = s_idx[w][lane];
-      if (bw > b || (bw == b && iw < ii)) { b = bw; ii = iw; who = w; }
+      if (bw > b || (bw == b && iw < ii)) { b = bw; ii = iw; }
     }
-    (void)who;
     double sg = 1.0;
-    if (col < d.r && ii != 0x7fffffff) sg = d.U[(long long)ii * d.ld + col] < 0.0 ? -1.0 : 1.0;
+    if (col < d.r && ii != 0x7fffffff) sg = U[(long long)ii * d.ld + col] < 0.0 ? -1.0 : 1.0;
     s_sgn[lane] = sg;
-    if (col < d.r) d.sign[col] = sg;
+    if (col < d.r) gstore_ptr(d.sign)[col] = sg;
   }
-  (void)val;
   __syncthreads();
   float amax = 0.f;
   if (col < d.r) {
     const double sg = s_sgn[lane];
-    for (int i = wave; i < d.n; i += 4) {
-      double* p = d.U + (long long)i * d.ld + col;
+    for (int i = wave; i < d.n; i += kSignWaves) {
+      GAS double* p = U + (long long)i * d.ld + col;
       const double v = *p * sg;
       *p = v;
       amax = fmaxf(amax, fabsf((float)v));
@@ -260,7 +272,7 @@ void launch_omega(const OmegaDesc* d, int n, int max_elems, hipStream_t s) {
 
 void launch_signfix(const SignDesc* d, int n, int max_r, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(signfix_kernel, dim3(ceil_div(max_r, 64), n), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(signfix_kernel, dim3(ceil_div(max_r, 64), n), dim3(64 * kSignWaves), 0, s, d);
 }
 
 void launch_scale(const ScaleDesc* d, int n, int max_elems, hipStream_t s) {
