@@ -34,7 +34,8 @@ WORKLOAD = dict(L=40, d=2, chi=64, chi_c=128, p=16, seed=0)
 # kernel classes timed by the library's profiling mode, and the kernel each
 # one launches (its name in a rocprofv3 kernel trace)
 MFMA_CLASSES = ("theta", "env_update", "env_ext1", "env_ext2", "sketch", "project")
-KERNEL_OF_CLASS = {"qr_chol_inv": "chol_inv_reg_kernel<5>", "eig_tridiag": "sytrd_reg_kernel<5>",
+# (k = chi_C + p = 144 runs the register kernels on their 16 x 16 grid)
+KERNEL_OF_CLASS = {"qr_chol_inv": "chol_inv_reg_kernel<9, 16>", "eig_tridiag": "sytrd_reg_kernel<9, 16>",
                    "eig_bisect": "bisect_kernel", "eig_vectors": "twisted_kernel",
                    "theta": "gemm_kernel<Mode::F32, float, float, float, true, true, 0|1>"}
 
@@ -348,6 +349,9 @@ def main():
                 "frac": round(ach / peak, 7), "traffic": None,
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches_per_sweep": nl_dom / 2,
                 "algorithmic_flops_per_launch": round(fl_dom / nl_dom)}
+        if not mfma:  # the serial factorization kernels run one workgroup (one CU of 256)
+            roof["workgroups_per_launch"] = 1
+            roof["frac_of_one_cu"] = round(ach / (peak / 256), 5)
         roof["traffic"] = measured_traffic(roof["kernel"])
 
     others, batched, grad, acc, cpu = {}, {}, {}, {}, None

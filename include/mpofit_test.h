@@ -29,6 +29,12 @@ mpo_status mpo_test_gemm(int mode, int ta, int tb, int tc, int a_kcontig, int b_
 mpo_status mpo_test_eig(const double* H, int k, int r, double* evals, double* Z, void* workspace,
                         size_t ws_bytes, void* stream);
 
+/* The same for n independent problems in one launch of each eigen kernel
+   (the batched schedules' configuration): H is n consecutive k x k
+   matrices, evals n x r, Z n consecutive k x r matrices. */
+mpo_status mpo_test_eig_batch(const double* H, int n, int k, int r, double* evals, double* Z,
+                              void* workspace, size_t ws_bytes, void* stream);
+
 /* Q = CholeskyQR2 of the n x k FP64 matrix X (row-major, in place). */
 mpo_status mpo_test_cholqr(double* X, int n, int k, void* workspace, size_t ws_bytes, void* stream);
 

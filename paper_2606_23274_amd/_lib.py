@@ -98,7 +98,8 @@ def check(status: int) -> None:
         raise MpoError(status, msg)
 
 
-TEST_EXPORTS = ["mpo_test_gemm", "mpo_test_eig", "mpo_test_cholqr", "mpo_test_omega"]
+TEST_EXPORTS = ["mpo_test_gemm", "mpo_test_eig", "mpo_test_eig_batch", "mpo_test_cholqr",
+                "mpo_test_omega"]
 
 
 def load_test_hooks() -> C.CDLL:
@@ -108,6 +109,7 @@ def load_test_hooks() -> C.CDLL:
     lib.mpo_test_gemm.argtypes = [i, i, i, i, i, i, i, i, i, i, vp, i, vp, i, vp, i, d, i, i, vp,
                                   C.c_size_t, vp]
     lib.mpo_test_eig.argtypes = [vp, i, i, vp, vp, vp, C.c_size_t, vp]
+    lib.mpo_test_eig_batch.argtypes = [vp, i, i, i, vp, vp, vp, C.c_size_t, vp]
     lib.mpo_test_cholqr.argtypes = [vp, i, i, vp, C.c_size_t, vp]
     lib.mpo_test_omega.argtypes = [vp, i, i, i, i, i, i, C.c_uint64, vp, C.c_size_t, vp]
     for n in TEST_EXPORTS:

@@ -11,6 +11,7 @@
 namespace mpofit {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex2 __attribute__((ext_vector_type(2)));
 
 // Global-memory views of generic pointers: accesses through them use the
 // global instructions, whose completion is tracked apart from LDS traffic

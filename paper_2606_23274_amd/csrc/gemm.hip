@@ -100,7 +100,6 @@ __device__ __forceinline__ unsigned short lo_part(T v, float inv_scale) {
   return f2bf(x - bf2f(f2bf(x)));
 }
 
-typedef double doublex2 __attribute__((ext_vector_type(2)));
 
 // Loads a (ROWS x BK) operand tile into registers in the stored type; the
 // conversion to the LDS type (and the BF16 scale) happens at the LDS store.

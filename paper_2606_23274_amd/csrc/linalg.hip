@@ -9,6 +9,7 @@
 //             (a workgroup evaluates 256 shifts per round), an eigenvector of
 //             the tridiagonal from its twisted factorization (one thread per
 //             eigenvalue), and the reflectors applied back in column blocks.
+#include <type_traits>
 #include <algorithm>
 #include <cfloat>
 
@@ -157,6 +158,79 @@ __global__ void __launch_bounds__(kBig) trsm_kernel(const TrsmDesc* __restrict__
 }
 
 // ---------------------------------------------------------------- eigen
+// One DPP move of a double (both 32-bit halves) with a row_ror control.  A
+// rotation inside a 16-lane row reads a valid lane everywhere, so no "old"
+// value is needed (and none has to be materialised).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the G lanes of a thread row, returned to all of them: rotations
+// by 8, 4, 2, 1 inside each 16-lane DPP row, then (G = 32) one exchange
+// between the two rows.
+template <int G>
+__device__ __forceinline__ double row_reduce(double v) {
+  v += dpp_d<0x128>(v);  // row_ror:8
+  v += dpp_d<0x124>(v);  // row_ror:4
+  v += dpp_d<0x122>(v);  // row_ror:2
+  v += dpp_d<0x121>(v);  // row_ror:1
+  if constexpr (G == 32) v += __shfl_xor(v, 16);
+  return v;
+}
+
+// Row sums for every row of a register block, level by level so that the
+// NB independent chains interleave.
+template <int G, int I0, int NB>
+__device__ __forceinline__ void row_reduce_all(double (&p)[NB]) {
+#pragma unroll
+  for (int i = I0; i < NB; ++i) p[i] += dpp_d<0x128>(p[i]);
+#pragma unroll
+  for (int i = I0; i < NB; ++i) p[i] += dpp_d<0x124>(p[i]);
+#pragma unroll
+  for (int i = I0; i < NB; ++i) p[i] += dpp_d<0x122>(p[i]);
+#pragma unroll
+  for (int i = I0; i < NB; ++i) p[i] += dpp_d<0x121>(p[i]);
+  if constexpr (G == 32) {
+#pragma unroll
+    for (int i = I0; i < NB; ++i) p[i] += __shfl_xor(p[i], 16);
+  }
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), returned to all of
+// them: row sums by DPP, then the four rows read out as (r0 + r1) + (r2 + r3).
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0x128>(v);
+  v += dpp_d<0x124>(v);
+  v += dpp_d<0x122>(v);
+  v += dpp_d<0x121>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// 1/x and 1/sqrt(x) for x != 0 (and finite): the hardware estimate refined by two Newton
+// steps (about 1 ulp), a shorter dependency chain than the IEEE division.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
 // work layout (doubles): d[k] e[k] tau[k] V[k*k] X[k*r] Hfull[k*k]
 struct EigWork {
   GAS double *d, *e, *tau, *V, *X, *H;
@@ -254,43 +328,271 @@ __global__ void __launch_bounds__(kBig) sytrd_kernel(const EigDesc* __restrict__
   }
 }
 
-// Number of eigenvalues of T strictly below x (Sturm count of the LDL^T of
-// T - x I, with LAPACK's pivmin guard).
-__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int k, double x,
-                                           double pivmin) {
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  int cnt = q < 0.0;
+// Sum over the workgroup (all threads active): wave sums through DPP, one
+// barrier.  `red` (16 doubles) must not be read by any thread since the
+// previous barrier; callers alternate buffers.
+__device__ __forceinline__ double block_sum1(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kBig / 64; ++w) s += red[w];
+  return s;
+}
+
+// Panel form of the same reduction (the delayed-update scheme of LAPACK's
+// dlatrd): the full symmetric matrix lives in W.H and is current at the
+// panel start j0; step jj = j0 + cur works with
+//   A_cur = A_j0 - V W^T - W V^T   (V, W: the panel's first cur vectors)
+// without forming it: column jj and the product A_cur v come from the
+// panel-start matrix plus the corrections, so each step reads the trailing
+// block once, row by row (coalesced; both triangles are kept).  The panel
+// vectors stay in LDS ([p][row]) and leave as P1 = [V W], P2 = [W V] (rows of
+// 2 NBP); a batched GEMM then applies A -= P1 P2^T to the trailing block
+// before the next panel.  Reflectors, tau, d and e as in sytrd_kernel.
+template <int NBP>
+__global__ void __launch_bounds__(kBig) sytrd_panel_kernel(const EigDesc* __restrict__ descs, int j0) {
+  // column chunks per row (k <= 64 QM for each panel width) and rows per group
+  constexpr int QM = NBP == 32 ? 3 : NBP == 16 ? 5 : 9;  // chunks of 128 columns
+  constexpr int RW = NBP == 32 ? 4 : 1;
+  extern __shared__ double lds[];
+  __shared__ double redA[16], redB[16];
+  __shared__ double s_y1[NBP], s_y2[NBP];
+  const EigDesc dd = descs[blockIdx.x];
+  const int k = dd.k;
+  EigWork W(dd.work, k, dd.r);
+  GAS double* A = W.H;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (j0 == 0) {  // the full symmetric copy (the lower triangle of H is read); zero reflectors
+    const GAS double* Hin = gload_ptr(dd.H);
+    for (int idx = threadIdx.x; idx < k * k; idx += kBig) {
+      const int i = idx / k, j = idx % k;
+      A[idx] = Hin[(long long)max(i, j) * dd.ldh + min(i, j)];
+      W.V[idx] = 0.0;
+    }
+    __syncthreads();
+    if (k <= 2) {
+      if (threadIdx.x == 0) {
+        W.d[0] = A[0];
+        W.e[0] = 0.0;
+        W.tau[0] = 0.0;
+        if (k == 2) { W.d[1] = A[3]; W.e[0] = A[2]; W.e[1] = 0.0; W.tau[1] = 0.0; }
+      }
+      return;
+    }
+  }
+  if (j0 >= k - 2) return;  // uniform: this problem's panels are done
+  const int pend = min(j0 + NBP, k - 2), nbp = pend - j0;
+  double* Vs = lds;                             // [NBP][k]
+  double* Ws = lds + (long long)NBP * k;        // [NBP][k]
+  double* sv = lds + 2 * (long long)NBP * k;    // k
+  double* sp = sv + k;                          // k
+  for (int cur = 0; cur < nbp; ++cur) {
+    const int jj = j0 + cur;
+    // column jj (rows >= jj) of A_cur: row jj of the panel-start matrix
+    // (symmetric storage) minus the corrections
+    double sq = 0.0;
+    for (int r = jj + threadIdx.x; r < k; r += kBig) {
+      // four independent partial sums so that the LDS reads overlap
+      double c0 = A[(long long)jj * k + r], c1 = 0.0, c2 = 0.0, c3 = 0.0;
+      int p = 0;
+      for (; p + 4 <= cur; p += 4) {
+        c0 -= Vs[p * k + r] * Ws[p * k + jj] + Ws[p * k + r] * Vs[p * k + jj];
+        c1 -= Vs[(p + 1) * k + r] * Ws[(p + 1) * k + jj] + Ws[(p + 1) * k + r] * Vs[(p + 1) * k + jj];
+        c2 -= Vs[(p + 2) * k + r] * Ws[(p + 2) * k + jj] + Ws[(p + 2) * k + r] * Vs[(p + 2) * k + jj];
+        c3 -= Vs[(p + 3) * k + r] * Ws[(p + 3) * k + jj] + Ws[(p + 3) * k + r] * Vs[(p + 3) * k + jj];
+      }
+      for (; p < cur; ++p) c0 -= Vs[p * k + r] * Ws[p * k + jj] + Ws[p * k + r] * Vs[p * k + jj];
+      const double c = (c0 + c1) + (c2 + c3);
+      if (r == jj) W.d[jj] = c;
+      else sv[r] = c;
+      sq += r >= jj + 2 ? c * c : 0.0;
+    }
+    const double xnorm2 = block_sum1(sq, redA);
+    const double alpha = sv[jj + 1];
+    double tau = 0.0, beta = alpha, scal = 0.0;
+    if (xnorm2 > 0.0) {
+      const double n2 = fma(alpha, alpha, xnorm2);
+      const double rs = rsq_nr(n2), nrm = n2 * rs;
+      const double sg = alpha < 0.0 ? -1.0 : 1.0;
+      beta = -sg * nrm;
+      tau = fma(fabs(alpha), rs, 1.0);
+      scal = sg * rcp_nr(fabs(alpha) + nrm);
+    }
+    if (threadIdx.x == 0) {
+      W.e[jj] = beta;
+      W.tau[jj] = tau;
+    }
+    double* v = Vs + (long long)cur * k;
+    for (int r = threadIdx.x; r < k; r += kBig) {
+      const double x = r == jj + 1 ? 1.0 : (r > jj + 1 ? sv[r] * scal : 0.0);
+      const double vr = tau != 0.0 ? x : 0.0;
+      v[r] = vr;
+      W.V[(long long)jj * k + r] = vr;
+    }
+    __syncthreads();
+    if (tau == 0.0) {  // uniform: H_jj = I, nothing to correct with
+      for (int r = threadIdx.x; r < k; r += kBig) Ws[(long long)cur * k + r] = 0.0;
+      __syncthreads();
+      continue;
+    }
+    // p = A_j0 v on rows > jj: a wave per row, RW rows at a time with every
+    // chunk's load issued before the first product, so a row group costs one
+    // L2 round trip.  A lane reads two adjacent columns (16 bytes; rows are
+    // 16-byte aligned when k is even, else 8-byte loads), chunks of 128
+    // columns from the even column c0 <= jj + 1 cover the row.
+    const int c0 = (jj + 1) & ~1;
+    double vq[QM][2];
+#pragma unroll
+    for (int q = 0; q < QM; ++q)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = c0 + 2 * lane + 128 * q + h;
+        const double x = v[min(c, k - 1)];  // in-bounds read, masked: no branch per load
+        vq[q][h] = (c > jj && c < k) ? x : 0.0;
+      }
+    const bool even = (k & 1) == 0;
+    for (int r0 = jj + 1 + wave; r0 < k; r0 += RW * (kBig / 64)) {
+      double x[RW][QM][2];
+#pragma unroll
+      for (int u = 0; u < RW; ++u) {
+        const int r = min(r0 + u * (kBig / 64), k - 1);
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {  // clamped columns meet vq = 0
+          const int c = c0 + 2 * lane + 128 * q;
+          const GAS double* row = A + (long long)r * k;
+          if (even) {  // c and k even: c < k implies c + 1 < k
+            const doublex2 t2 = *reinterpret_cast<const GAS doublex2*>(row + min(c, k - 2));
+            x[u][q][0] = t2[0];
+            x[u][q][1] = t2[1];
+          } else {
+            x[u][q][0] = row[min(c, k - 1)];
+            x[u][q][1] = row[min(c + 1, k - 1)];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RW; ++u) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < QM; ++q) acc = fma(x[u][q][1], vq[q][1], fma(x[u][q][0], vq[q][0], acc));
+        const int r = r0 + u * (kBig / 64);
+        const double sum = wave_sum(acc);
+        if (lane == 0 && r < k) sp[r] = sum;
+      }
+    }
+    // y1 = W^T v, y2 = V^T v over rows > jj (the correction's small factors)
+    for (int p = wave; p < cur; p += kBig / 64) {
+      double a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
+      for (int r = jj + 1 + lane; r < k; r += 64) {
+        const double vr = v[r];
+        a1 = fma(Ws[p * k + r], vr, a1);
+        a2 = fma(Vs[p * k + r], vr, a2);
+      }
+      a1 = wave_sum(a1);
+      a2 = wave_sum(a2);
+      if (lane == 0) { s_y1[p] = a1; s_y2[p] = a2; }
+    }
+    __syncthreads();
+    // p = tau (A_j0 v - V y1 - W y2); w = p - (tau/2)(p.v) v
+    double pvp = 0.0;
+    for (int r = jj + 1 + threadIdx.x; r < k; r += kBig) {
+      double p0 = sp[r], p1 = 0.0, p2 = 0.0, p3 = 0.0;
+      int p = 0;
+      for (; p + 4 <= cur; p += 4) {
+        p0 -= Vs[p * k + r] * s_y1[p] + Ws[p * k + r] * s_y2[p];
+        p1 -= Vs[(p + 1) * k + r] * s_y1[p + 1] + Ws[(p + 1) * k + r] * s_y2[p + 1];
+        p2 -= Vs[(p + 2) * k + r] * s_y1[p + 2] + Ws[(p + 2) * k + r] * s_y2[p + 2];
+        p3 -= Vs[(p + 3) * k + r] * s_y1[p + 3] + Ws[(p + 3) * k + r] * s_y2[p + 3];
+      }
+      for (; p < cur; ++p) p0 -= Vs[p * k + r] * s_y1[p] + Ws[p * k + r] * s_y2[p];
+      double pr = (p0 + p1) + (p2 + p3);
+      pr *= tau;
+      sp[r] = pr;
+      pvp = fma(pr, v[r], pvp);
+    }
+    const double K = -0.5 * tau * block_sum1(pvp, redB);
+    for (int r = threadIdx.x; r < k; r += kBig)
+      Ws[(long long)cur * k + r] = r > jj ? fma(K, v[r], sp[r]) : 0.0;
+    __syncthreads();
+  }
+  // the panel as GEMM operands (zero columns past nbp)
+  GAS double* P1 = gstore_ptr(eig_work_panel(dd.work, k, dd.r));
+  GAS double* P2 = P1 + 2 * (long long)kPanel * k;
+  for (int idx = threadIdx.x; idx < k * NBP; idx += kBig) {
+    const int r = idx / NBP, p = idx % NBP;
+    const double vv = p < nbp ? Vs[p * k + r] : 0.0, ww = p < nbp ? Ws[p * k + r] : 0.0;
+    P1[(long long)r * 2 * NBP + p] = vv;
+    P1[(long long)r * 2 * NBP + NBP + p] = ww;
+    P2[(long long)r * 2 * NBP + p] = ww;
+    P2[(long long)r * 2 * NBP + NBP + p] = vv;
+  }
+  if (pend == k - 2 && threadIdx.x == 0) {  // the trailing 2 x 2 block of the last panel
+    auto at = [&](int r, int c) {
+      double x = A[(long long)r * k + c];
+      for (int p = 0; p < nbp; ++p) x -= Vs[p * k + r] * Ws[p * k + c] + Ws[p * k + r] * Vs[p * k + c];
+      return x;
+    };
+    W.d[k - 2] = at(k - 2, k - 2);
+    W.d[k - 1] = at(k - 1, k - 1);
+    W.e[k - 2] = at(k - 1, k - 2);
+    W.e[k - 1] = 0.0;
+    W.tau[k - 2] = 0.0;
+    W.tau[k - 1] = 0.0;
+  }
+}
+
+// Number of eigenvalues of T strictly below x: the signs of the pivots q_i
+// of the LDL^T factorization of T - x I, with LAPACK's pivmin guard.
+// de[i] = (d_i, e_{i-1}^2) with e_{-1} = 0.  The guard keeps |q| >= pivmin =
+// DBL_MIN max(1, max e^2), so e^2 / q cannot overflow; the quotient uses the
+// refined reciprocal (a perturbation of e^2 by about an ulp, well inside the
+// backward error of the recurrence).
+__device__ __forceinline__ int sturm_count(const double2* de, int k, double x, double pivmin) {
+  double q = de[0].x - x;
+  q = fabs(q) < pivmin ? -pivmin : q;
+  int cnt = q < 0.0 ? 1 : 0;
   for (int i = 1; i < k; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
+    const double2 p = de[i];
+    q = fma(-p.y, rcp_nr(q), p.x - x);
+    q = fabs(q) < pivmin ? -pivmin : q;
+    cnt += q < 0.0 ? 1 : 0;
   }
   return cnt;
 }
 
 constexpr int kBisect = 256;
 
-// Eigenvalue jj (0 = largest) of T: each round the workgroup evaluates 256
-// shifts spread over the current bracket and keeps the sub-bracket holding it.
+// log2(WL + 1) bits per multisection round; the rounds give a bracket about
+// 2^-96 of the Gerschgorin interval unless the relative criterion stops first.
+constexpr int bisect_rounds(int WL) {
+  return WL == 8 ? 31 : WL == 16 ? 24 : WL == 32 ? 20 : WL == 64 ? 16 : 12;
+}
+
+// Eigenvalue jj (0 = largest) of T by multisection: a group of WL lanes
+// evaluates WL shifts spread over the current bracket and keeps the
+// sub-bracket holding it.  WL = 256 is the whole workgroup (counts through a
+// barrier), for few eigenvalues; WL <= 64 packs 256 / WL eigenvalues per
+// workgroup, each group counting through a wave ballot with no barrier.
+template <int WL>
 __global__ void __launch_bounds__(kBisect) bisect_kernel(const EigDesc* __restrict__ descs) {
-  extern __shared__ double lds[];
-  __shared__ double red[4];
+  extern __shared__ double2 lds_de[];  // 16-byte aligned pairs
+  __shared__ double s_lo[4], s_hi[4], s_em[4];
   __shared__ double s_a, s_b;
+  constexpr int PER = kBisect / WL;
   const EigDesc dd = descs[blockIdx.y];
   const int k = dd.k;
-  const int jj = blockIdx.x;
-  if (jj >= dd.r) return;
+  if (blockIdx.x * PER >= dd.r) return;  // uniform
   EigWork W(dd.work, k, dd.r);
-  double* sd = lds;
-  double* se2 = lds + k;
+  double2* de = lds_de;
   double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 0.0;
   for (int i = threadIdx.x; i < k; i += kBisect) {
     const double di = W.d[i];
     const double em = i > 0 ? fabs(W.e[i - 1]) : 0.0;
     const double ep = i + 1 < k ? fabs(W.e[i]) : 0.0;
-    sd[i] = di;
-    se2[i] = ep * ep;
+    de[i] = make_double2(di, em * em);
     lo = fmin(lo, di - em - ep);
     hi = fmax(hi, di + em + ep);
     emax2 = fmax(emax2, ep * ep);
@@ -301,7 +603,6 @@ __global__ void __launch_bounds__(kBisect) bisect_kernel(const EigDesc* __restri
     emax2 = fmax(emax2, __shfl_xor(emax2, off));
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __shared__ double s_lo[4], s_hi[4], s_em[4];
   if (lane == 0) { s_lo[wave] = lo; s_hi[wave] = hi; s_em[wave] = emax2; }
   __syncthreads();
   lo = fmin(fmin(s_lo[0], s_lo[1]), fmin(s_lo[2], s_lo[3]));
@@ -311,25 +612,47 @@ __global__ void __launch_bounds__(kBisect) bisect_kernel(const EigDesc* __restri
   const double span = fmax(hi - lo, DBL_MIN);
   double a = lo - 2.0 * DBL_EPSILON * span - pivmin;
   double b = hi + 2.0 * DBL_EPSILON * span + pivmin;
+  const int g = threadIdx.x / WL, t = threadIdx.x % WL;
+  const int jj = blockIdx.x * PER + g;
+  const bool active = jj < dd.r;
   const int m = k - 1 - jj;  // ascending index
-  for (int round = 0; round < 12; ++round) {
-    const double x = a + (b - a) * (double)(threadIdx.x + 1) / (double)(kBisect + 1);
-    const int c = sturm_count(sd, se2, k, x, pivmin);
-    const int below = __syncthreads_count(c <= m);
-    if (threadIdx.x == 0) {
-      double na = a, nb = b;
-      if (below > 0) na = a + (b - a) * (double)below / (double)(kBisect + 1);
-      if (below < kBisect) nb = a + (b - a) * (double)(below + 1) / (double)(kBisect + 1);
-      s_a = na;
-      s_b = nb;
+  if constexpr (WL == kBisect) {
+    for (int round = 0; round < bisect_rounds(WL); ++round) {
+      const double x = a + (b - a) * (double)(t + 1) / (double)(WL + 1);
+      const int c = sturm_count(de, k, x, pivmin);
+      const int below = __syncthreads_count(c <= m);
+      if (threadIdx.x == 0) {
+        double na = a, nb = b;
+        if (below > 0) na = a + (b - a) * (double)below / (double)(WL + 1);
+        if (below < WL) nb = a + (b - a) * (double)(below + 1) / (double)(WL + 1);
+        s_a = na;
+        s_b = nb;
+      }
+      __syncthreads();
+      a = s_a;
+      b = s_b;
+      if (b - a <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + pivmin) break;
     }
-    __syncthreads();
-    a = s_a;
-    b = s_b;
-    if (b - a <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + pivmin) break;
+  } else {
+    const int sh = (lane / WL) * WL;  // the group's first lane in the wave
+    const unsigned long long gmask = WL == 64 ? ~0ull : ((1ull << (WL & 63)) - 1ull);
+    for (int round = 0; round < bisect_rounds(WL); ++round) {
+      const bool done = !active || b - a <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + pivmin;
+      if (__ballot(!done) == 0ull) break;  // wave-uniform
+      const double x = a + (b - a) * (double)(t + 1) / (double)(WL + 1);
+      const int c = done ? 0 : sturm_count(de, k, x, pivmin);
+      const unsigned long long bal = __ballot(c <= m);
+      const int below = __popcll((bal >> sh) & gmask);
+      if (!done) {
+        double na = a, nb = b;
+        if (below > 0) na = a + (b - a) * (double)below / (double)(WL + 1);
+        if (below < WL) nb = a + (b - a) * (double)(below + 1) / (double)(WL + 1);
+        a = na;
+        b = nb;
+      }
+    }
   }
-  if (threadIdx.x == 0) dd.evals[jj] = 0.5 * (a + b);
-  (void)red;
+  if (active && t == 0) dd.evals[jj] = 0.5 * (a + b);
 }
 
 // Eigenvector of T for eigenvalue evals[j] from the twisted factorization
@@ -359,13 +682,15 @@ __global__ void twisted_kernel(const EigDesc* __restrict__ descs) {
   double emax2 = 0.0;
   for (int i = 0; i + 1 < k; ++i) emax2 = fmax(emax2, se[i] * se[i]);
   const double pivmin = DBL_MIN * fmax(1.0, emax2);
+  // |q| >= pivmin after the guard, so the quotients below cannot overflow;
+  // they use the refined reciprocal (about an ulp of e^2 / q)
   auto guard = [pivmin](double q) { return fabs(q) < pivmin ? (q < 0 ? -pivmin : pivmin) : q; };
   // bottom-up D-
   double q = guard(sd[k - 1] - lam);
   Dm[(long long)(k - 1) * T + tid] = q;
   for (int i = k - 2; i >= 0; --i) {
     const double ei = se[i];
-    q = guard((sd[i] - lam) - ei * ei / q);
+    q = guard(fma(-ei * ei, rcp_nr(q), sd[i] - lam));
     Dm[(long long)i * T + tid] = q;
   }
   // top-down D+ and the twist gamma_i = (d_i - lam) - e_{i-1}^2/D+_{i-1} - e_i^2/D-_{i+1}
@@ -375,8 +700,8 @@ __global__ void twisted_kernel(const EigDesc* __restrict__ descs) {
   for (int i = 0; i < k; ++i) {
     const double di = sd[i] - lam;
     const double em2 = i > 0 ? se[i - 1] * se[i - 1] : 0.0;
-    const double top = (i == 0) ? di : di - em2 / p;
-    const double gam = top - (i + 1 < k ? se[i] * se[i] / Dm[(long long)(i + 1) * T + tid] : 0.0);
+    const double top = (i == 0) ? di : fma(-em2, rcp_nr(p), di);
+    const double gam = i + 1 < k ? fma(-se[i] * se[i], rcp_nr(Dm[(long long)(i + 1) * T + tid]), top) : top;
     p = guard(top);
     Dp[(long long)i * T + tid] = p;
     if (fabs(gam) < best) { best = fabs(gam); g = i; }
@@ -385,17 +710,17 @@ __global__ void twisted_kernel(const EigDesc* __restrict__ descs) {
   double nrm2 = 1.0;
   double z = 1.0;
   for (int i = g - 1; i >= 0; --i) {
-    z = -(se[i] / Dp[(long long)i * T + tid]) * z;
+    z = -(se[i] * rcp_nr(Dp[(long long)i * T + tid])) * z;
     Dp[(long long)i * T + tid] = z;
     nrm2 += z * z;
   }
   z = 1.0;
   for (int i = g + 1; i < k; ++i) {
-    z = -(se[i - 1] / Dm[(long long)i * T + tid]) * z;
+    z = -(se[i - 1] * rcp_nr(Dm[(long long)i * T + tid])) * z;
     Dm[(long long)i * T + tid] = z;
     nrm2 += z * z;
   }
-  const double inv = 1.0 / sqrt(nrm2);
+  const double inv = rsq_nr(nrm2);
   for (int i = 0; i < k; ++i) {
     const double zi = (i < g) ? Dp[(long long)i * T + tid] : (i == g ? 1.0 : Dm[(long long)i * T + tid]);
     W.X[(long long)i * dd.r + j] = zi * inv;
@@ -455,56 +780,23 @@ __global__ void __launch_bounds__(kBig) backtransform_kernel(const EigDesc* __re
 
 
 // ---------------------------------------------------------------- register-resident variants
-// For k <= 32*NB the k x k matrix lives in registers: thread (tr, tc) of a
-// 32 x 32 grid (tid = 32 tr + tc, so one thread row is half a wave) holds
-// rows tr + 32a and columns tc + 32b, a, b < NB.  Reductions along a row stay
-// inside the wave (shuffles); column data is broadcast through LDS.
-constexpr int kRegNB = 5;  // k <= 160
+// For k <= G*NB the k x k matrix lives in registers: thread (tr, tc) of a
+// G x G grid (tid = G tr + tc) holds rows tr + G a and columns tc + G b,
+// a, b < NB.  A thread row is one 16-lane DPP row (G = 16) or half a wave
+// (G = 32), so reductions along a row stay inside the wave; column data is
+// broadcast through LDS.  The step cost is set by VALU issue: every wave
+// repeats the per-step vector work, so G = 16 (one wave per SIMD) is used
+// whenever k <= 144 and G = 32 (four waves per SIMD) only up to 160.
+constexpr int kRegNB = 5;  // k <= 160 on the 32 x 32 grid
 
-// One DPP move of a double (both 32-bit halves) with a row_ror control.
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-// Sum over the 32 lanes of a half-wave, returned to all of them: rotations
-// by 8, 4, 2, 1 inside each 16-lane DPP row, then one exchange between the
-// two rows (a single cross-lane permute instead of five).
-template <int NB>
-__device__ __forceinline__ double row_reduce32(double v) {
-  v += dpp_d<0x128>(v);  // row_ror:8
-  v += dpp_d<0x124>(v);  // row_ror:4
-  v += dpp_d<0x122>(v);  // row_ror:2
-  v += dpp_d<0x121>(v);  // row_ror:1
-  return v + __shfl_xor(v, 16);
-}
-
-// Sum over the 64 lanes of a wave, returned to all of them.
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_d<0x128>(v);
-  v += dpp_d<0x124>(v);
-  v += dpp_d<0x122>(v);
-  v += dpp_d<0x121>(v);
-  v += __shfl_xor(v, 16);
-  return v + __shfl_xor(v, 32);
-}
-
-// 1/x and 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton
-// steps (about 1 ulp), a shorter dependency chain than the IEEE division.
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  y = y * fma(-h * y, y, 1.5);
-  return y * fma(-h * y, y, 1.5);
+// f(integral_constant<int, I>) for I = B .. E-1: compile-time register-block
+// indices without relying on the unroller's size limits.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
 }
 
 // G = L L^T (Cholesky, L lower) and R^{-1} = (L^{-1})^T written row-major
@@ -519,34 +811,34 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // X overwrites L in place: row jj of X only mixes columns <= jj, whose L
 // entries no later Cholesky step reads.  Register indices are constants (the
 // column-block loop is unrolled); masks live in the broadcast vectors.
-template <int NB>
-__global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __restrict__ descs) {
-  __shared__ double colb[2][32 * NB];
-  __shared__ double rowb[2][32 * NB];
+template <int NB, int G>
+__global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __restrict__ descs) {
+  __shared__ double colb[2][G * NB];
+  __shared__ double rowb[2][G * NB];
   const CholDesc d = descs[blockIdx.x];
   const int k = d.k;
-  const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
+  const int tr = threadIdx.x / G, tc = threadIdx.x % G;
   double a[NB][NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int r = tr + 32 * i, c = tc + 32 * j;
+      const int r = tr + G * i, c = tc + G * j;
       a[i][j] = (r < k && c < k) ? gload_ptr(d.G)[(long long)r * d.ldg + c] : (r == c ? 1.0 : 0.0);
     }
   bool bad = false;
-#pragma unroll
-  for (int JB = 0; JB < NB; ++JB) {
-    const int jend = min(k, 32 * JB + 32);
-    for (int jj = 32 * JB; jj < jend; ++jj) {
-      const int jt = jj & 31, buf = jj & 1;
+  static_for<0, NB>([&](auto jb_) {
+    constexpr int JB = decltype(jb_)::value;
+    const int jend = min(k, G * JB + G);
+    for (int jj = G * JB; jj < jend; ++jj) {
+      const int jt = jj % G, buf = jj & 1;
       if (tc == jt) {  // column jj of the updated matrix (rows >= jj)
 #pragma unroll
-        for (int i = JB; i < NB; ++i) colb[buf][tr + 32 * i] = (tr + 32 * i >= jj) ? a[i][JB] : 0.0;
+        for (int i = JB; i < NB; ++i) colb[buf][tr + G * i] = (tr + G * i >= jj) ? a[i][JB] : 0.0;
       }
       if (tr == jt) {  // row jj of X (columns < jj; the rest masked)
 #pragma unroll
-        for (int j = 0; j <= JB; ++j) rowb[buf][tc + 32 * j] = (tc + 32 * j < jj) ? a[JB][j] : 0.0;
+        for (int j = 0; j <= JB; ++j) rowb[buf][tc + G * j] = (tc + G * j < jj) ? a[JB][j] : 0.0;
       }
       __syncthreads();
       const double djj = colb[buf][jj];
@@ -554,47 +846,46 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
       if (!ok) bad = true;
       const double invd = ok ? rcp_nr(djj) : 0.0;
       const double invs = ok ? rsq_nr(djj) : 0.0;  // 1 / L(jj, jj)
-      double cr[NB], cc[NB], l[NB], xr[NB];
+      // the broadcast vectors are read unconditionally (all indices lie in
+      // the buffers) and masked by selects, so the loads issue back to back
+      double cc[NB], xr[NB];
 #pragma unroll
-      for (int i = JB; i < NB; ++i) {
-        const int r = tr + 32 * i, c = tc + 32 * i;
-        const double ar = (r > jj) ? colb[buf][r] : 0.0;
-        cr[i] = ar * invd;
-        l[i] = ar * invs;  // L(r, jj)
-        cc[i] = (c > jj) ? colb[buf][c] : 0.0;
+      for (int j = JB; j < NB; ++j) {
+        const int c = tc + G * j;
+        const double x = colb[buf][c];
+        cc[j] = (c > jj) ? x : 0.0;
       }
 #pragma unroll
-      for (int j = 0; j <= JB; ++j) xr[j] = rowb[buf][tc + 32 * j] * invs;  // X(jj, c) / L(jj, jj)
+      for (int j = 0; j <= JB; ++j) xr[j] = rowb[buf][tc + G * j] * invs;  // X(jj, c) / L(jj, jj)
+      const bool col_owner = tc == jt, row_owner = tr == jt;
       // Cholesky trailing update (columns > jj) and inverse update (columns < jj)
 #pragma unroll
       for (int i = JB; i < NB; ++i) {
+        const int r = tr + G * i;
+        const double x = colb[buf][r];
+        const double ar = (r > jj) ? x : 0.0;
+        const double cr = ar * invd, l = ar * invs;  // l = L(r, jj)
 #pragma unroll
-        for (int j = JB; j < NB; ++j) a[i][j] -= cr[i] * cc[j];
+        for (int j = JB; j < NB; ++j) a[i][j] -= cr * cc[j];
 #pragma unroll
-        for (int j = 0; j <= JB; ++j) a[i][j] -= l[i] * xr[j];
+        for (int j = 0; j <= JB; ++j) a[i][j] -= l * xr[j];
+        // column jj of X: X(jj, jj) and X(r, jj) for r > jj
+        const double xc = (r == jj) ? invs : -l * invs;
+        a[i][JB] = (col_owner && r >= jj) ? xc : a[i][JB];
       }
-      if (tr == jt) {  // row jj of X: the scaled part
+      // row jj of X: the scaled part
 #pragma unroll
-        for (int j = 0; j <= JB; ++j)
-          if (tc + 32 * j < jj) a[JB][j] *= invs;
-      }
-      if (tc == jt) {  // column jj of X: X(jj, jj) and X(r, jj) for r > jj
-#pragma unroll
-        for (int i = JB; i < NB; ++i) {
-          const int r = tr + 32 * i;
-          if (r == jj) a[i][JB] = invs;
-          else if (r > jj) a[i][JB] = -l[i] * invs;
-        }
-      }
+      for (int j = 0; j <= JB; ++j)
+        a[JB][j] = (row_owner && tc + G * j < jj) ? a[JB][j] * invs : a[JB][j];
     }
-  }
+  });
   if (bad && d.flag) atomicOr(d.flag, FLAG_CHOL);
   // R^{-1}(c, r) = X(r, c) for r >= c; zeros below the diagonal of R^{-1}
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int r = tr + 32 * i, c = tc + 32 * j;
+      const int r = tr + G * i, c = tc + G * j;
       if (r < k && c < k) gstore_ptr(d.R)[(long long)c * d.ldr + r] = (r >= c) ? a[i][j] : 0.0;
     }
 }
@@ -603,114 +894,134 @@ __global__ void __launch_bounds__(kBig) chol_inv_reg_kernel(const CholDesc* __re
 // on the register-resident matrix; reflectors go to W.H (row j = v_j), then
 // Q^T = H_{k-3} ... H_0 is accumulated in the same registers and written to
 // W.V (row-major k x k); d, e to W.d, W.e.
-template <int NB>
-__global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restrict__ descs) {
-  __shared__ double vb[2][32 * NB], wb[2][32 * NB];
-  __shared__ double s_taus[32 * NB];
+template <int NB, int G>
+__global__ void __launch_bounds__(G * G) sytrd_reg_kernel(const EigDesc* __restrict__ descs) {
+  __shared__ double vb[2][G * NB], wb[2][G * NB];
+  __shared__ double s_taus[G * NB];
   const EigDesc dd = descs[blockIdx.x];
   const int k = dd.k;
   EigWork W(dd.work, k, dd.r);
   GAS double* vstore = W.H;
-  const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tr = threadIdx.x / G, tc = threadIdx.x % G;
   double a[NB][NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int r = tr + 32 * i, c = tc + 32 * j;
+      const int r = tr + G * i, c = tc + G * j;
       const int hi = r > c ? r : c, lo = r > c ? c : r;
       a[i][j] = (r < k && c < k) ? gload_ptr(dd.H)[(long long)hi * dd.ldh + lo] : 0.0;
     }
   // Step jj works on the trailing block (rows and columns > jj), which lies
-  // in register blocks >= JB = jj / 32; the JB loop is unrolled so register
+  // in register blocks >= JB = jj / G; the JB loop is unrolled so register
   // indices are constants.  vb / wb alternate between two buffers so that a
   // step's last reads and the next step's first writes need no barrier.
-#pragma unroll
-  for (int JB = 0; JB < NB; ++JB) {
-    const int jend = min(k - 2, 32 * JB + 32);
-    for (int jj = 32 * JB; jj < jend; ++jj) {
-      const int jt = jj & 31, buf = jj & 1;
+  static_for<0, NB>([&](auto jb_) {
+    constexpr int JB = decltype(jb_)::value;
+    const int jend = min(k - 2, G * JB + G);
+    for (int jj = G * JB; jj < jend; ++jj) {
+      const int jt = jj % G, buf = jj & 1;
       double* v = vb[buf];
       double* w = wb[buf];
       if (tc == jt) {  // x = A(jj+1:, jj) into v; the diagonal entry to d
 #pragma unroll
         for (int i = JB; i < NB; ++i) {
-          const int r = tr + 32 * i;
+          const int r = tr + G * i;
           v[r] = (r > jj && r < k) ? a[i][JB] : 0.0;
-          if (r == jj) W.d[jj] = a[i][JB];
         }
+        if (tr == jt) W.d[jj] = a[JB][JB];
       }
       if (tc == 0 && JB > 0) {  // rows of earlier blocks stay zero in v and w
 #pragma unroll
-        for (int i = 0; i < JB; ++i) { v[tr + 32 * i] = 0.0; w[tr + 32 * i] = 0.0; }
+        for (int i = 0; i < JB; ++i) { v[tr + G * i] = 0.0; w[tr + G * i] = 0.0; }
       }
       __syncthreads();
-      // every wave forms the reflector parameters from the column in LDS
-      // (identical arithmetic, so identical values), which saves a barrier
-      // and leaves no wave idle; v(r) is generated on the fly
+      // v now holds x on rows jj+1 .. k-1 and zeros elsewhere.  Every wave
+      // forms the reflector parameters from it (identical arithmetic, so
+      // identical values), which saves a barrier.  LDS reads are issued
+      // unconditionally (indices stay inside the buffer) and masked by selects.
+      constexpr int QN = (G * NB + 63) / 64;
+      const int lane = threadIdx.x & 63;
       double part = 0.0;
-      for (int r = jj + 2 + lane; r < k; r += 64) part += v[r] * v[r];
+#pragma unroll
+      for (int q = 0; q < QN; ++q) {
+        const int r = lane + 64 * q;
+        const double x = v[r < G * NB ? r : 0];
+        part += (r < G * NB && r != jj + 1) ? x * x : 0.0;
+      }
       part = wave_sum(part);
       const double alpha = v[jj + 1];
+      // beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta = 1 + |alpha| / ||x||,
+      // v = x / (alpha - beta) with v(jj+1) = 1
       double tau = 0.0, beta = alpha, scal = 0.0;
       if (part > 0.0) {
-        beta = -copysign(sqrt(alpha * alpha + part), alpha);
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
+        const double n2 = fma(alpha, alpha, part);
+        const double rs = rsq_nr(n2), nrm = n2 * rs;
+        const double sg = alpha < 0.0 ? -1.0 : 1.0;
+        beta = -sg * nrm;
+        tau = fma(fabs(alpha), rs, 1.0);
+        scal = sg * rcp_nr(fabs(alpha) + nrm);
       }
-      auto vref = [&](int r) {
-        return r == jj + 1 ? 1.0 : (r > jj + 1 && r < k ? v[r] * scal : 0.0);
-      };
-      if (wave == 0) {  // the reflector (v(jj+1) = 1) and tau for the back-accumulation
-        for (int r = lane; r < k; r += 64)
-          vstore[(long long)jj * k + r] = tau != 0.0 ? vref(r) : 0.0;
-        if (lane == 0) {
-          W.e[jj] = beta;
-          W.tau[jj] = tau;
-          s_taus[jj] = tau;
-        }
+      // the reflector (v(jj+1) = 1) and tau for the back-accumulation
+      if ((int)threadIdx.x < k) {
+        const int t = threadIdx.x;
+        const double x = v[t] * scal;
+        vstore[(long long)jj * k + t] = tau != 0.0 ? (t == jj + 1 ? 1.0 : x) : 0.0;
+      }
+      if (threadIdx.x == 0) {
+        W.e[jj] = beta;
+        W.tau[jj] = tau;
+        s_taus[jj] = tau;
       }
       if (tau == 0.0) continue;  // uniform
       // p = tau * A22 v on rows > jj (v vanishes on rows and columns <= jj)
-      double vc[NB];
+      double vc[NB], pr[NB];
 #pragma unroll
-      for (int j = JB; j < NB; ++j) vc[j] = vref(tc + 32 * j);
+      for (int j = JB; j < NB; ++j) {
+        const int c = tc + G * j;
+        const double x = v[c] * scal;
+        vc[j] = c == jj + 1 ? 1.0 : x;
+      }
 #pragma unroll
       for (int i = JB; i < NB; ++i) {
-        double pr = 0.0;
+        pr[i] = 0.0;
 #pragma unroll
-        for (int j = JB; j < NB; ++j) pr += a[i][j] * vc[j];
-        pr = row_reduce32<NB>(pr);
-        if (tc == 0) w[tr + 32 * i] = (tr + 32 * i > jj) ? tau * pr : 0.0;
+        for (int j = JB; j < NB; ++j) pr[i] = fma(a[i][j], vc[j], pr[i]);
+      }
+      row_reduce_all<G, JB>(pr);
+      if (tc == 0) {
+#pragma unroll
+        for (int i = JB; i < NB; ++i) w[tr + G * i] = (tr + G * i > jj) ? tau * pr[i] : 0.0;
       }
       __syncthreads();
       // w = p - (tau/2)(p.v) v: every thread forms p.v from the trailing rows
       double pv = 0.0;
 #pragma unroll
-      for (int i = JB; i < NB; ++i) pv += w[tc + 32 * i] * vc[i];
-      pv = row_reduce32<NB>(pv);
+      for (int i = JB; i < NB; ++i) pv = fma(w[tc + G * i], vc[i], pv);
+      pv = row_reduce<G>(pv);
       const double K = -0.5 * tau * pv;
       // A22 -= v w^T + w v^T with w = p + K v (trailing block only)
       double wc[NB];
 #pragma unroll
-      for (int j = JB; j < NB; ++j) wc[j] = w[tc + 32 * j] + K * vc[j];
+      for (int j = JB; j < NB; ++j) wc[j] = fma(K, vc[j], w[tc + G * j]);
 #pragma unroll
       for (int i = JB; i < NB; ++i) {
-        const int r = tr + 32 * i;
-        const double vi = vref(r), wi = w[r] + K * vi;
+        const int r = tr + G * i;
+        const double x = v[r] * scal;
+        const double vi = r == jj + 1 ? 1.0 : x;
+        const double wi = fma(K, vi, w[r]);
 #pragma unroll
         for (int j = JB; j < NB; ++j) a[i][j] -= vi * wc[j] + wi * vc[j];
       }
     }
-  }
+  });
   if (k >= 2) {
     const int r0 = k - 2, r1 = k - 1;
 #pragma unroll
     for (int i = 0; i < NB; ++i)
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        const int r = tr + 32 * i, c = tc + 32 * j;
+        const int r = tr + G * i, c = tc + G * j;
         if (r == r0 && c == r0) W.d[r0] = a[i][j];
         if (r == r1 && c == r1) W.d[r1] = a[i][j];
         if (r == r1 && c == r0) W.e[r0] = a[i][j];
@@ -722,60 +1033,63 @@ __global__ void __launch_bounds__(kBig) sytrd_reg_kernel(const EigDesc* __restri
   __threadfence_block();
   __syncthreads();
   // Q^T = H_{k-3} ... H_0: M <- M H_j = M - tau_j (M v_j) v_j^T for j = k-3 .. 0.
-  // v_j vanishes on columns <= j, i.e. below register block JB = (j + 1) / 32,
+  // v_j vanishes on columns <= j, i.e. below register block JB = (j + 1) / G,
   // and rows <= j of M = H_{k-3} ... H_{j+1} are rows of the identity, so
   // (M v_j) vanishes there too: only register blocks >= JB take part.
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) a[i][j] = (tr + 32 * i == tc + 32 * j) ? 1.0 : 0.0;
+    for (int j = 0; j < NB; ++j) a[i][j] = (tr + G * i == tc + G * j) ? 1.0 : 0.0;
   double vnext = 0.0;
-  if (k >= 3 && threadIdx.x < 32 * NB)
+  if (k >= 3 && threadIdx.x < G * NB)
     vnext = threadIdx.x < k ? vstore[(long long)(k - 3) * k + threadIdx.x] : 0.0;
-#pragma unroll
-  for (int JB = NB - 1; JB >= 0; --JB) {
-    const int jhi = min(k - 3, 32 * JB + 30), jlo = max(0, 32 * JB - 1);
+  static_for<0, NB>([&](auto t_) {
+    constexpr int JB = NB - 1 - decltype(t_)::value;
+    const int jhi = min(k - 3, G * JB + G - 2), jlo = max(0, G * JB - 1);
     for (int jj = jhi; jj >= jlo; --jj) {
       const int buf = jj & 1;
       const double tau = s_taus[jj];
       double* v = vb[buf];
       double* w = wb[buf];
-      if (threadIdx.x < 32 * NB) v[threadIdx.x] = vnext;
-      if (jj > 0 && threadIdx.x < 32 * NB)  // prefetch the next reflector
+      if (threadIdx.x < G * NB) v[threadIdx.x] = vnext;
+      if (jj > 0 && threadIdx.x < G * NB)  // prefetch the next reflector
         vnext = threadIdx.x < k ? vstore[(long long)(jj - 1) * k + threadIdx.x] : 0.0;
       __syncthreads();
       if (tau != 0.0) {  // uniform
-        double vc[NB];
+        double vc[NB], pr[NB];
 #pragma unroll
-        for (int j = JB; j < NB; ++j) vc[j] = v[tc + 32 * j];
+        for (int j = JB; j < NB; ++j) vc[j] = v[tc + G * j];
 #pragma unroll
         for (int i = JB; i < NB; ++i) {
-          double pr = 0.0;
+          pr[i] = 0.0;
 #pragma unroll
-          for (int j = JB; j < NB; ++j) pr += a[i][j] * vc[j];
-          pr = row_reduce32<NB>(pr);
-          if (tc == 0) w[tr + 32 * i] = tau * pr;
+          for (int j = JB; j < NB; ++j) pr[i] = fma(a[i][j], vc[j], pr[i]);
+        }
+        row_reduce_all<G, JB>(pr);
+        if (tc == 0) {
+#pragma unroll
+          for (int i = JB; i < NB; ++i) w[tr + G * i] = tau * pr[i];
         }
       }
       __syncthreads();
       if (tau != 0.0) {
         double vc[NB];
 #pragma unroll
-        for (int j = JB; j < NB; ++j) vc[j] = v[tc + 32 * j];
+        for (int j = JB; j < NB; ++j) vc[j] = v[tc + G * j];
 #pragma unroll
         for (int i = JB; i < NB; ++i) {
-          const double wi = w[tr + 32 * i];
+          const double wi = w[tr + G * i];
 #pragma unroll
           for (int j = JB; j < NB; ++j) a[i][j] -= wi * vc[j];
         }
       }
     }
-  }
+  });
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int r = tr + 32 * i, c = tc + 32 * j;
+      const int r = tr + G * i, c = tc + G * j;
       if (r < k && c < k) W.V[(long long)r * k + c] = a[i][j];
     }
 }
@@ -865,9 +1179,35 @@ __global__ void __launch_bounds__(kBig) jacobi_kernel(const JacobiDesc* __restri
 }
 }  // namespace
 
-size_t eig_work_doubles(int k, int r) {
-  return 3 * (size_t)k + 2 * (size_t)k * k + (size_t)k * r;
+// The register kernels by size: a 16 x 16 grid with the fewest register
+// blocks that hold k (k <= 144), else the 32 x 32 grid (k <= 160).
+struct RegChol {
+  template <int NB, int G>
+  static void go(const CholDesc* d, int n, hipStream_t s) {
+    hipLaunchKernelGGL((chol_inv_reg_kernel<NB, G>), dim3(n), dim3(G * G), 0, s, d);
+  }
+};
+struct RegSytrd {
+  template <int NB, int G>
+  static void go(const EigDesc* d, int n, hipStream_t s) {
+    hipLaunchKernelGGL((sytrd_reg_kernel<NB, G>), dim3(n), dim3(G * G), 0, s, d);
+  }
+};
+template <class K, class D>
+void launch_reg(const D* d, int n, int max_k, hipStream_t s) {
+  if (max_k <= 32) K::template go<2, 16>(d, n, s);
+  else if (max_k <= 64) K::template go<4, 16>(d, n, s);
+  else if (max_k <= 96) K::template go<6, 16>(d, n, s);
+  else if (max_k <= 128) K::template go<8, 16>(d, n, s);
+  else if (max_k <= 144) K::template go<9, 16>(d, n, s);
+  else K::template go<kRegNB, 32>(d, n, s);
 }
+
+size_t eig_work_doubles(int k, int r) {
+  return 3 * (size_t)k + 2 * (size_t)k * k + (size_t)k * r + 4 * (size_t)kPanel * k;
+}
+
+int eig_panel_width(int max_k) { return max_k <= 290 ? 32 : max_k <= 570 ? 16 : max_k <= 1100 ? 8 : 0; }
 
 double* eig_work_qt(double* w, int k, int r) { (void)r; return w + 3 * (size_t)k; }
 double* eig_work_x(double* w, int k, int r) { (void)r; return w + 3 * (size_t)k + (size_t)k * k; }
@@ -875,7 +1215,7 @@ double* eig_work_x(double* w, int k, int r) { (void)r; return w + 3 * (size_t)k 
 void launch_chol(const CholDesc* d, int n, int max_k, int inverse, hipStream_t s) {
   if (n <= 0) return;
   if (inverse) {
-    hipLaunchKernelGGL(chol_inv_reg_kernel<kRegNB>, dim3(n), dim3(kBig), 0, s, d);
+    launch_reg<RegChol>(d, n, max_k, s);
     return;
   }
   // packed lower triangle in LDS when every problem fits, else the factor's
@@ -909,10 +1249,18 @@ void launch_eig(const EigDesc* d, const EigDesc* h, int n, int reg, int stage, h
     max_k = std::max(max_k, h[i].k);
     max_r = std::max(max_r, h[i].r);
   }
+  if (stage >= kEigPanelStage) {  // one panel of the global-memory reduction
+    const int j0 = stage - kEigPanelStage, nb = eig_panel_width(max_k);
+    const size_t lds = (2 * (size_t)nb * max_k + 2 * (size_t)max_k) * sizeof(double);
+    if (nb == 32) hipLaunchKernelGGL(sytrd_panel_kernel<32>, dim3(n), dim3(kBig), lds, s, d, j0);
+    else if (nb == 16) hipLaunchKernelGGL(sytrd_panel_kernel<16>, dim3(n), dim3(kBig), lds, s, d, j0);
+    else hipLaunchKernelGGL(sytrd_panel_kernel<8>, dim3(n), dim3(kBig), lds, s, d, j0);
+    return;
+  }
   const bool all = stage < 0;
   if (all || stage == 0) {
     if (reg) {
-      hipLaunchKernelGGL(sytrd_reg_kernel<kRegNB>, dim3(n), dim3(kBig), 0, s, d);
+      launch_reg<RegSytrd>(d, n, max_k, s);
     } else {
       if (max_k <= kPackedMax) {
         const size_t lds1 = (2 * (size_t)max_k + (size_t)max_k * (max_k + 1) / 2) * sizeof(double);
@@ -922,10 +1270,20 @@ void launch_eig(const EigDesc* d, const EigDesc* h, int n, int reg, int stage, h
       }
     }
   }
-  if (all || stage == 1)
-    hipLaunchKernelGGL(bisect_kernel, dim3(max_r, n), dim3(kBisect), 2 * max_k * sizeof(double), s, d);
+  if (all || stage == 1) {
+    // few eigenvalues: a workgroup each (fewest rounds); many: eight lanes
+    // each, 32 per workgroup (fewest Sturm counts)
+    const size_t lds = 2 * (size_t)max_k * sizeof(double);
+    if ((long long)n * max_r >= 2048)
+      hipLaunchKernelGGL(bisect_kernel<8>, dim3(ceil_div(max_r, kBisect / 8), n), dim3(kBisect), lds, s, d);
+    else
+      hipLaunchKernelGGL(bisect_kernel<kBisect>, dim3(max_r, n), dim3(kBisect), lds, s, d);
+  }
   if (all || stage == 2) {
+    // one thread per eigenvalue; smaller groups when there are few, so that
+    // more compute units share the work
     int T = 64;
+    while (T > 16 && (long long)ceil_div(max_r, T) * n < 128) T /= 2;
     while (T > 1 && (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double) > 150 * 1024) T /= 2;
     hipLaunchKernelGGL(twisted_kernel, dim3(ceil_div(max_r, T), n), dim3(T),
                        (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double), s, d);

@@ -65,6 +65,20 @@ constexpr int kJacobiLds = 128;
 void launch_jacobi(const JacobiDesc* d, int n, int max_q, hipStream_t s);
 
 size_t eig_work_doubles(int k, int r);
+// Panel reduction of the global-memory path: widest panel, the panel width
+// for a launch (0: use the unblocked kernel), the stage code of the panel
+// starting at column j0 (kEigPanelStage + j0), and the work-array pieces the
+// trailing-update GEMM reads and writes: the full symmetric matrix (k x k)
+// and the panel operands P1 = [V W], P2 = P1 + 2 kPanel k (k rows of 2 nb).
+constexpr int kPanel = 32;
+constexpr int kEigPanelStage = 1 << 20;
+int eig_panel_width(int max_k);
+__host__ __device__ inline double* eig_work_h(double* w, int k, int r) {
+  return w + 3 * (size_t)k + (size_t)k * k + (size_t)k * r;
+}
+__host__ __device__ inline double* eig_work_panel(double* w, int k, int r) {
+  return w + 3 * (size_t)k + 2 * (size_t)k * k + (size_t)k * r;
+}
 // Offsets inside the eigen work area: Q^T (k x k, row-major) of the
 // register path, and the k x r eigenvectors of the tridiagonal matrix.
 double* eig_work_qt(double* w, int k, int r);

@@ -274,24 +274,62 @@ void add_simple(Program& P, LK kind, const std::vector<D>& ds, long long maxa, c
 // The eigen pipeline as one launch per stage (tridiagonalization, bisection,
 // eigenvectors, back-transformation) over one descriptor array, so that each
 // stage is timed on its own.  Tridiagonalization is credited (4/3) k^3 flops.
-void add_eig(Program& P, const std::vector<EigDesc>& ed, bool reg, const char* prefix) {
+Op op64(const void* p, bool kc, int ld) { return Op{p, DType::F64, kc, ld}; }
+Out out64(void* p, int ld) { return Out{p, DType::F64, ld}; }
+
+// Eigen stages of a batch of problems.  The register path (every k <=
+// kRegMax) has three kernels; otherwise the tridiagonal reduction runs panel
+// by panel (a panel kernel, then a batched FP64 GEMM for the trailing
+// update of the problems that have more panels), then bisection, twisted
+// vectors and the back-transformation.
+void add_eig(Program& P, const SplitBuf& sb, const std::vector<EigDesc>& ed, bool reg,
+             const char* prefix) {
   if (ed.empty()) return;
   const size_t off = P.push(ed);
   double ftri = 0;
-  for (auto& e : ed) ftri += (4.0 / 3.0) * e.k * (double)e.k * e.k;
+  int max_k = 0;
+  for (auto& e : ed) {
+    ftri += (4.0 / 3.0) * e.k * (double)e.k * e.k;
+    max_k = std::max(max_k, e.k);
+  }
   const bool init = std::string(prefix) == "init";
   const char* names[4] = {"eig_tridiag", "eig_bisect", "eig_vectors", "eig_backtransform"};
-  for (int st = 0; st < (reg ? 3 : 4); ++st) {
+  auto stage = [&](long long code, const char* cls, double flops) {
     Launch l;
     l.kind = LK::Eig;
     l.off = off;
     l.n = (int)ed.size();
     l.maxb = reg ? 1 : 0;
-    l.maxa = st;
-    l.cls = init ? "init" : names[st];
-    l.flops = st == 0 ? ftri : 0;
+    l.maxa = code;
+    l.cls = init ? "init" : cls;
+    l.flops = flops;
     P.launches.push_back(l);
+  };
+  const int nb = reg ? 0 : eig_panel_width(max_k);
+  if (nb > 0) {
+    int npan = 1;
+    for (auto& e : ed) npan = std::max(npan, ceil_div(std::max(e.k - 2, 1), nb));
+    for (int q = 0; q < npan; ++q) {
+      const int j0 = q * nb;
+      stage(kEigPanelStage + j0, names[0], q == 0 ? ftri : 0.0);
+      std::vector<GemmJob> upd;  // A(pend:, pend:) -= P1 P2^T for problems with panels left
+      for (auto& e : ed) {
+        const int pend = std::min(j0 + nb, e.k - 2), t = e.k - pend;
+        if (j0 >= e.k - 2 || pend >= e.k - 2) continue;
+        double* P1 = eig_work_panel(e.work, e.k, e.r);
+        double* P2 = P1 + 2 * (size_t)kPanel * e.k;
+        double* H = eig_work_h(e.work, e.k, e.r);
+        GemmJob g{t, t, 2 * nb, op64(P1 + (size_t)pend * 2 * nb, true, 2 * nb),
+                  op64(P2 + (size_t)pend * 2 * nb, true, 2 * nb),
+                  out64(H + (size_t)pend * e.k + pend, e.k)};
+        g.alpha = -1.0;
+        g.beta = 1;
+        upd.push_back(g);
+      }
+      add_gemm(P, sb, Mode::F64, upd, init ? "init" : names[0], 0.0);
+    }
   }
+  for (int st = nb > 0 ? 1 : 0; st < (reg ? 3 : 4); ++st) stage(st, names[st], st == 0 ? ftri : 0.0);
 }
 
 // ------------------------------------------------------------------ state
@@ -441,13 +479,11 @@ Op opW(const Ctx& X, const void* p, bool kc, int ld, const unsigned* amax = null
   o.amax = amax;
   return o;
 }
-Op op64(const void* p, bool kc, int ld) { return Op{p, DType::F64, kc, ld}; }
 Out outW(const Ctx& X, void* p, int ld, unsigned* amax = nullptr) {
   Out o{p, X.wt, ld};
   o.amax = amax;
   return o;
 }
-Out out64(void* p, int ld) { return Out{p, DType::F64, ld}; }
 
 PermDesc perm4(const void* in, int tin, void* out, int tout, std::array<int, 4> n,
                std::array<long long, 4> si, std::array<long long, 4> so, double scale = 1.0) {
@@ -982,7 +1018,7 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
   add_gemm(P, X.sb, Mode::F64, hw, "gram", 0);
   const bool reg = zq.size() == ed.size();
   if (!reg) zq.clear();
-  add_eig(P, ed, reg, "eig");
+  add_eig(P, X.sb, ed, reg, "eig");
   add_gemm(P, X.sb, Mode::F64, zq, "eig_backtransform", 0);
   add_simple(P, LK::Sval, sv, maxr, "svals");
 }
@@ -1128,7 +1164,7 @@ void rec_inverse_canonical(Ctx& X, Program& P, PairState& S) {
     add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(X.iRt, false, q), op64(X.iRt, false, q),
                                           out64(X.iH, q)}}, "init", 0);
     const bool reg = q <= kRegMax;
-    add_eig(P, {EigDesc{X.iH, q, q, q, X.iEv, X.iZ, q, X.iEw, X.flag}}, reg, "init");
+    add_eig(P, X.sb, {EigDesc{X.iH, q, q, q, X.iEv, X.iZ, q, X.iEw, X.flag}}, reg, "init");
     if (reg)
       add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(eig_work_qt(X.iEw, q, q), false, q),
                                             op64(eig_work_x(X.iEw, q, q), false, q), out64(X.iZ, q)}},
@@ -2465,11 +2501,37 @@ mpo_status mpo_test_eig(const double* H, int k, int r, double* evals, double* Z,
     if (T.cv.off > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "test workspace too small"};
     Program P;
     const bool reg = k <= kRegMax;
-    add_eig(P, {EigDesc{H, k, k, r, evals, Z, r, w, T.X.flag}}, reg, "eig");
+    add_eig(P, T.X.sb, {EigDesc{H, k, k, r, evals, Z, r, w, T.X.flag}}, reg, "eig");
     if (reg)
       add_gemm(P, T.X.sb, Mode::F64, {GemmJob{k, r, k, op64(eig_work_qt(w, k, r), false, k),
                                               op64(eig_work_x(w, k, r), false, r), out64(Z, r)}},
                "eig_backtransform", 0);
+    T.go(P);
+    check_flags(T.X);
+  });
+}
+
+mpo_status mpo_test_eig_batch(const double* H, int n, int k, int r, double* evals, double* Z,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    if (n < 1 || k < 1 || r < 1 || r > k) throw Error{MPO_ERR_INVALID_ARG, "bad eig batch shape"};
+    TestEnv T(workspace, ws_bytes, stream);
+    const bool reg = k <= kRegMax;
+    std::vector<EigDesc> ed;
+    std::vector<GemmJob> bt;
+    for (int i = 0; i < n; ++i) {
+      double* w = T.cv.take<double>(eig_work_doubles(k, r));
+      const double* Hi = H + (size_t)i * k * k;
+      double* Zi = Z + (size_t)i * k * r;
+      ed.push_back(EigDesc{Hi, k, k, r, evals + (size_t)i * r, Zi, r, w, T.X.flag});
+      if (reg)
+        bt.push_back(GemmJob{k, r, k, op64(eig_work_qt(w, k, r), false, k),
+                             op64(eig_work_x(w, k, r), false, r), out64(Zi, r)});
+    }
+    if (T.cv.off > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "test workspace too small"};
+    Program P;
+    add_eig(P, T.X.sb, ed, reg, "eig");
+    if (reg) add_gemm(P, T.X.sb, Mode::F64, bt, "eig_backtransform", 0);
     T.go(P);
     check_flags(T.X);
   });

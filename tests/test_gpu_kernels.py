@@ -57,7 +57,13 @@ def test_gemm_against_numpy(hooks, kind, akc, bkc, M, N, K, tile, splits):
     assert err < TOL[mode], err
 
 
-@pytest.mark.parametrize("k,r", [(1, 1), (2, 2), (5, 3), (64, 64), (144, 128), (200, 150), (272, 256)])
+# sizes on both sides of every register-grid boundary (k = 32, 64, 96, 128,
+# 144 on the 16 x 16 grid, 160 on the 32 x 32 grid) and of every panel width
+# of the global-memory reduction (32 up to k = 290, 16 up to 570, then 8)
+@pytest.mark.parametrize("k,r", [(1, 1), (2, 2), (5, 3), (17, 17), (32, 20), (33, 33), (64, 64),
+                                 (65, 40), (96, 96), (97, 90), (128, 128), (129, 100), (144, 128),
+                                 (145, 145), (160, 128), (199, 199), (200, 150), (201, 180),
+                                 (272, 256), (290, 256), (300, 200), (301, 250), (600, 100)])
 def test_eig_against_numpy(hooks, k, r):
     from tests.gpu_util import dev, ptr
     rng = np.random.default_rng(k)
@@ -79,7 +85,37 @@ def test_eig_against_numpy(hooks, k, r):
     assert np.abs(np.abs(np.sum(Z * V, axis=0)) - 1).max() < 1e-8
 
 
-@pytest.mark.parametrize("n,k", [(40, 12), (512, 144), (600, 161), (300, 300), (1024, 272), (900, 321)])
+# several problems per launch: the batched configuration of the eigen
+# kernels (eight-lane multisection once problems x eigenvalues >= 2048, the
+# register or the global-memory tridiagonalization by size), including a
+# partly filled last workgroup of eigenvalues
+@pytest.mark.parametrize("n,k,r", [(3, 100, 90), (24, 90, 90), (16, 144, 128), (32, 272, 256)])
+def test_eig_batch_against_numpy(hooks, n, k, r):
+    from tests.gpu_util import dev, ptr
+    Hs, refs = [], []
+    for i in range(n):
+        rng = np.random.default_rng(1000 * k + i)
+        X = rng.standard_normal((k, 3 * k)) * np.exp(-np.arange(3 * k) / (40.0 + 3 * i))
+        H = X @ X.T
+        w, V = np.linalg.eigh(H)
+        Hs.append(H)
+        refs.append((w[::-1][:r], V[:, ::-1][:, :r]))
+    Hd = dev(np.stack(Hs))
+    ev = torch.zeros((n, r), dtype=torch.float64, device="cuda:0")
+    Z = torch.zeros((n, k, r), dtype=torch.float64, device="cuda:0")
+    _lib.check(hooks.lib.mpo_test_eig_batch(ptr(Hd), n, k, r, ptr(ev), ptr(Z), *hooks.args()))
+    ev, Z = ev.cpu().numpy(), Z.cpu().numpy()
+    for i, (w, V) in enumerate(refs):
+        nrm = np.abs(w).max()
+        assert np.abs(ev[i] - w).max() <= 1e-13 * nrm, i
+        assert np.linalg.norm(Hs[i] @ Z[i] - Z[i] * ev[i]) / nrm < 1e-12, i
+        assert np.abs(Z[i].T @ Z[i] - np.eye(r)).max() < 1e-9, i
+        assert np.abs(np.abs(np.sum(Z[i] * V, axis=0)) - 1).max() < 1e-8, i
+
+
+@pytest.mark.parametrize("n,k", [(40, 12), (90, 32), (200, 33), (300, 64), (400, 96), (400, 97),
+                                 (500, 128), (512, 144), (520, 145), (600, 160), (600, 161),
+                                 (300, 300), (1024, 272), (900, 321)])
 def test_cholqr2_against_householder(hooks, n, k):
     from tests.gpu_util import dev, ptr
     rng = np.random.default_rng(n + k)
