@@ -37,6 +37,7 @@ template <> struct ModeT<Mode::F64> {
   using accv_t = doublex4;
   static constexpr int KSUB = 16;  // K per sub-slab (4 MFMA steps of 4)
   static constexpr int PAD = 2;
+  static constexpr int PADT = 2;   // row pad of the k-major staging
 };
 template <> struct ModeT<Mode::F32> {
   using acc_t = float;
@@ -44,6 +45,7 @@ template <> struct ModeT<Mode::F32> {
   using accv_t = floatx4;
   static constexpr int KSUB = 16;
   static constexpr int PAD = 4;
+  static constexpr int PADT = 4;
 };
 template <> struct ModeT<Mode::BF16> {
   using acc_t = float;
@@ -51,6 +53,7 @@ template <> struct ModeT<Mode::BF16> {
   using accv_t = floatx4;
   static constexpr int KSUB = 32;  // one MFMA step
   static constexpr int PAD = 8;
+  static constexpr int PADT = 0;  // (BF16 operands are always staged row-major)
 };
 template <> struct ModeT<Mode::BF16X3> : ModeT<Mode::BF16> {};
 
@@ -144,12 +147,31 @@ struct TileLoader {
     }
   }
 
-  template <Mode MODE, typename L>
+  // Row-major staging ([row][k], pitch ldl) or, with KMAJOR (an operand
+  // whose rows are contiguous in memory, FP32/FP64 only), k-major staging
+  // ([k][row], pitch ldl): the four rows a thread loaded go out as one
+  // 16-byte-aligned vector store, free of bank conflicts.
+  template <Mode MODE, bool KMAJOR = false, typename L>
   __device__ __forceinline__ void store(L* lds, L* lds_lo, int ldl, float inv_scale) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       int idx = threadIdx.x + kThreads * i;
-      if constexpr (KCONTIG) {
+      if constexpr (KMAJOR) {
+        static_assert(!KCONTIG, "k-major staging is for row-contiguous operands");
+        const int k = idx / (ROWS / 4);
+        const int r = 4 * (idx % (ROWS / 4));
+        L* q = lds + k * ldl + r;
+        if constexpr (sizeof(L) == 4) {
+          *reinterpret_cast<floatx4*>(q) =
+              floatx4{to_lds<MODE>(v[i][0], inv_scale), to_lds<MODE>(v[i][1], inv_scale),
+                      to_lds<MODE>(v[i][2], inv_scale), to_lds<MODE>(v[i][3], inv_scale)};
+        } else {
+          *reinterpret_cast<doublex2*>(q) =
+              doublex2{to_lds<MODE>(v[i][0], inv_scale), to_lds<MODE>(v[i][1], inv_scale)};
+          *reinterpret_cast<doublex2*>(q + 2) =
+              doublex2{to_lds<MODE>(v[i][2], inv_scale), to_lds<MODE>(v[i][3], inv_scale)};
+        }
+      } else if constexpr (KCONTIG) {
         int r = idx / (BK / 4);
         int k = 4 * (idx % (BK / 4));
         L* q = lds + r * ldl + k;
@@ -188,8 +210,13 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
   constexpr int FM = WM / 16, FN = WN / 16;     // MFMA blocks per wave
 
   constexpr int NLO = MODE == Mode::BF16X3 ? 2 : 1;  // hi (and lo) tiles
-  __shared__ __align__(16) lds_t sA[NLO][2][BM * LDL];
-  __shared__ __align__(16) lds_t sB[NLO][2][BN * LDL];
+  // row-contiguous FP32 / FP64 operands are staged k-major (pitch BM + PADT)
+  constexpr bool AT = !AK && (MODE == Mode::F32 || MODE == Mode::F64);
+  constexpr bool BT = !BKC && (MODE == Mode::F32 || MODE == Mode::F64);
+  constexpr int LDMA = BM + MT::PADT, LDMB = BN + MT::PADT;
+  constexpr int SZA = AT ? BK * LDMA : BM * LDL, SZB = BT ? BK * LDMB : BN * LDL;
+  __shared__ __align__(16) lds_t sA[NLO][2][SZA];
+  __shared__ __align__(16) lds_t sB[NLO][2][SZB];
   __shared__ int s_last;
 
   // locate this workgroup's problem
@@ -247,8 +274,8 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
   if (nslab > 0) {
     la.load(Ap, d.lda, rows_a, kbeg, kend, d.vec_a);
     lb.load(Bp, d.ldb, rows_b, kbeg, kend, d.vec_b);
-    la.template store<MODE>(sA[0][0], sA[NLO - 1][0], LDL, inv_sa);
-    lb.template store<MODE>(sB[0][0], sB[NLO - 1][0], LDL, inv_sb);
+    la.template store<MODE, AT>(sA[0][0], sA[NLO - 1][0], AT ? LDMA : LDL, inv_sa);
+    lb.template store<MODE, BT>(sB[0][0], sB[NLO - 1][0], BT ? LDMB : LDL, inv_sb);
   }
   __syncthreads();
 
@@ -302,15 +329,27 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
       lds_t af[FM][4], bfr[FN][4];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        const lds_t* p = As + (wm + 16 * i + lrow) * LDL + 4 * lgrp;
+        if constexpr (AT) {  // k-major: rows of one k are adjacent
+          const lds_t* p = sA[0][cur] + (ks * MT::KSUB + 4 * lgrp) * LDMA + wm + 16 * i + lrow;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) af[i][s] = p[s];
+          for (int s = 0; s < 4; ++s) af[i][s] = p[s * LDMA];
+        } else {
+          const lds_t* p = As + (wm + 16 * i + lrow) * LDL + 4 * lgrp;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) af[i][s] = p[s];
+        }
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const lds_t* p = Bs + (wn + 16 * j + lrow) * LDL + 4 * lgrp;
+        if constexpr (BT) {
+          const lds_t* p = sB[0][cur] + (ks * MT::KSUB + 4 * lgrp) * LDMB + wn + 16 * j + lrow;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) bfr[j][s] = p[s];
+          for (int s = 0; s < 4; ++s) bfr[j][s] = p[s * LDMB];
+        } else {
+          const lds_t* p = Bs + (wn + 16 * j + lrow) * LDL + 4 * lgrp;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) bfr[j][s] = p[s];
+        }
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s)
@@ -326,8 +365,8 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
     }
     }  // sub-slab
     if (more) {
-      la.template store<MODE>(sA[0][cur ^ 1], sA[NLO - 1][cur ^ 1], LDL, inv_sa);
-      lb.template store<MODE>(sB[0][cur ^ 1], sB[NLO - 1][cur ^ 1], LDL, inv_sb);
+      la.template store<MODE, AT>(sA[0][cur ^ 1], sA[NLO - 1][cur ^ 1], AT ? LDMA : LDL, inv_sa);
+      lb.template store<MODE, BT>(sB[0][cur ^ 1], sB[NLO - 1][cur ^ 1], BT ? LDMB : LDL, inv_sb);
     }
     __syncthreads();
   }
