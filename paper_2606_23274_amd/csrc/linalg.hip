@@ -784,10 +784,9 @@ __global__ void __launch_bounds__(kBig) backtransform_kernel(const EigDesc* __re
 // G x G grid (tid = G tr + tc) holds rows tr + G a and columns tc + G b,
 // a, b < NB.  A thread row is one 16-lane DPP row (G = 16) or half a wave
 // (G = 32), so reductions along a row stay inside the wave; column data is
-// broadcast through LDS.  The step cost is set by VALU issue: every wave
-// repeats the per-step vector work, so G = 16 (one wave per SIMD) is used
-// whenever k <= 144 and G = 32 (four waves per SIMD) only up to 160.
-constexpr int kRegNB = 5;  // k <= 160 on the 32 x 32 grid
+// broadcast through LDS.  Every wave repeats the per-step vector work, so
+// the launches use G = 16 (one wave per SIMD, up to 256 VGPRs a lane; the
+// largest instances park some values in AGPRs).
 
 // f(integral_constant<int, I>) for I = B .. E-1: compile-time register-block
 // indices without relying on the unroller's size limits.
@@ -1179,8 +1178,8 @@ __global__ void __launch_bounds__(kBig) jacobi_kernel(const JacobiDesc* __restri
 }
 }  // namespace
 
-// The register kernels by size: a 16 x 16 grid with the fewest register
-// blocks that hold k (k <= 144), else the 32 x 32 grid (k <= 160).
+// The register kernels by size: the 16 x 16 grid with the fewest register
+// blocks that hold k (k <= kRegMax).
 struct RegChol {
   template <int NB, int G>
   static void go(const CholDesc* d, int n, hipStream_t s) {
@@ -1200,7 +1199,8 @@ void launch_reg(const D* d, int n, int max_k, hipStream_t s) {
   else if (max_k <= 96) K::template go<6, 16>(d, n, s);
   else if (max_k <= 128) K::template go<8, 16>(d, n, s);
   else if (max_k <= 144) K::template go<9, 16>(d, n, s);
-  else K::template go<kRegNB, 32>(d, n, s);
+  else if (max_k <= 160) K::template go<10, 16>(d, n, s);
+  else K::template go<11, 16>(d, n, s);  // k <= kRegMax = 176
 }
 
 size_t eig_work_doubles(int k, int r) {

@@ -85,7 +85,7 @@ double* eig_work_qt(double* w, int k, int r);
 double* eig_work_x(double* w, int k, int r);
 
 // Largest k handled by the register-resident kernels.
-constexpr int kRegMax = 160;
+constexpr int kRegMax = 176;
 
 // Cholesky of G.  inverse = 0: R (upper, R^T R = G) into d.R.
 // inverse = 1 (needs every k <= kRegMax): R^{-1} (upper) into d.R instead.

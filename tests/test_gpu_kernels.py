@@ -57,12 +57,13 @@ def test_gemm_against_numpy(hooks, kind, akc, bkc, M, N, K, tile, splits):
     assert err < TOL[mode], err
 
 
-# sizes on both sides of every register-grid boundary (k = 32, 64, 96, 128,
-# 144 on the 16 x 16 grid, 160 on the 32 x 32 grid) and of every panel width
-# of the global-memory reduction (32 up to k = 290, 16 up to 570, then 8)
+# sizes on both sides of every register-kernel boundary (k = 32, 64, 96,
+# 128, 144, 160, 176) and of every panel width of the global-memory
+# reduction (32 up to k = 290, 16 up to 570, then 8)
 @pytest.mark.parametrize("k,r", [(1, 1), (2, 2), (5, 3), (17, 17), (32, 20), (33, 33), (64, 64),
                                  (65, 40), (96, 96), (97, 90), (128, 128), (129, 100), (144, 128),
-                                 (145, 145), (160, 128), (199, 199), (200, 150), (201, 180),
+                                 (145, 145), (160, 128), (161, 150), (176, 176), (177, 160),
+                                 (199, 199), (200, 150), (201, 180),
                                  (272, 256), (290, 256), (300, 200), (301, 250), (600, 100)])
 def test_eig_against_numpy(hooks, k, r):
     from tests.gpu_util import dev, ptr
@@ -115,7 +116,8 @@ def test_eig_batch_against_numpy(hooks, n, k, r):
 
 @pytest.mark.parametrize("n,k", [(40, 12), (90, 32), (200, 33), (300, 64), (400, 96), (400, 97),
                                  (500, 128), (512, 144), (520, 145), (600, 160), (600, 161),
-                                 (300, 300), (1024, 272), (900, 321)])
+                                 (600, 176), (600, 177), (300, 300), (1024, 272), (900, 321),
+                                 (900, 352), (800, 360)])
 def test_cholqr2_against_householder(hooks, n, k):
     from tests.gpu_util import dev, ptr
     rng = np.random.default_rng(n + k)
