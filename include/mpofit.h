@@ -107,7 +107,8 @@ typedef struct {
 /* One tuned class of grouped GEMM launches: the operand kind (mode as
    mpo_precision, operand types 0 = FP64 / 1 = FP32, K-contiguity of A and B),
    the largest problem of the launch (M, N, K) and its problem count; the
-   chosen output tile (0: 64x64, 1: 128x128) and split-K count, and the
+   chosen output tile (0: 64x64, 1: 128x128, 2: 64x64 with half-depth K
+   slabs; 1 and 2 are FP32/BF16 only) and split-K count, and the
    measured average launch time of that choice. */
 typedef struct mpo_gemm_tune {
   int32_t mode, ta, tb, tc, a_kcontig, b_kcontig;
@@ -218,7 +219,8 @@ mpo_status mpo_fit_profile(const mpo_fit_ctx* ctx, int32_t n, double* ms, const 
    pairs with these options in `workspace` (at least mpo_fit_workspace_bytes),
    runs one sweep so that the bond dimensions settle, then times every GEMM
    launch class of the next sweep's launch program under each candidate
-   (tile 64x64, and 128x128 for FP32/BF16 when every problem is large enough;
+   (tile 64x64; for FP32/BF16 also 64x64 with half-depth K slabs, and
+   128x128 when every problem is large enough;
    split-K 1, 2, 4, 8, 16 where K allows), `reps` launches per candidate with
    HIP events, and writes the fastest per class into out[0 .. *n_out - 1]
    (at most `cap`).  Pass the table back through mpo_fit_opts.tune.  The

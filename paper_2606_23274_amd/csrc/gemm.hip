@@ -29,6 +29,7 @@ constexpr int kThreads = 256;
 template <int TILE> struct TileShape;
 template <> struct TileShape<0> { static constexpr int BM = 64, BN = 64; };
 template <> struct TileShape<1> { static constexpr int BM = 128, BN = 128; };
+template <> struct TileShape<2> { static constexpr int BM = 64, BN = 64; };  // half-depth slabs
 
 template <Mode M> struct ModeT;
 template <> struct ModeT<Mode::F64> {
@@ -57,12 +58,15 @@ template <> struct ModeT<Mode::BF16> {
 };
 template <> struct ModeT<Mode::BF16X3> : ModeT<Mode::BF16> {};
 
-// Slab depth per (mode, tile); must agree with gemm_bk() below.
+// Slab depth per (mode, tile); must agree with gemm_bk() below.  Tile 2 is
+// the 64 x 64 tile with half-depth slabs: half the LDS, so twice the
+// workgroups per CU, which pays when K is short and every tile's first
+// loads are exposed.
 constexpr int slab_k(Mode m, int tile) {
   return m == Mode::F64 ? 32
-         : m == Mode::F32 ? (tile == 1 ? 32 : 64)
-         : m == Mode::BF16 ? (tile == 1 ? 64 : 128)
-                           : (tile == 1 ? 32 : 64);
+         : m == Mode::F32 ? (tile == 0 ? 64 : 32)
+         : m == Mode::BF16 ? (tile == 0 ? 128 : 64)
+                           : (tile == 0 ? 64 : 32);
 }
 
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
@@ -448,6 +452,7 @@ void launch_tile(int tile, const GemmDesc* d, int n, int wgs, hipStream_t s) {
     gemm_kernel<MODE, TA, TB, TC, AK, BKC, 0><<<wgs, kThreads, 0, s>>>(d, n);
   } else {
     if (tile == 1) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 1><<<wgs, kThreads, 0, s>>>(d, n);
+    else if (tile == 2) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 2><<<wgs, kThreads, 0, s>>>(d, n);
     else gemm_kernel<MODE, TA, TB, TC, AK, BKC, 0><<<wgs, kThreads, 0, s>>>(d, n);
   }
 }

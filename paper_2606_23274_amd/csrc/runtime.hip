@@ -168,10 +168,13 @@ void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<
   if (jobs.empty()) return;
   if (sb.record) sb.record->emplace_back(mode, jobs);
   GemmKind gk{mode, jobs[0].A.t, jobs[0].B.t, jobs[0].C.t, jobs[0].A.kc, jobs[0].B.kc, 0};
-  // tile 128x128 is possible for FP32/BF16 when every problem is large enough
+  // tile 128x128 is possible for FP32/BF16 when every problem is large
+  // enough; tile 2 (64x64, half-depth slabs) for FP32/BF16 always
   bool big = mode != Mode::F64;
   long long w128 = 0;
+  int kmax = 0;
   for (auto& j : jobs) {
+    kmax = std::max(kmax, j.K);
     if (j.M < 128 || j.N < 128) big = false;
     w128 += (long long)ceil_div(j.M, 128) * ceil_div(j.N, 128) * j.nb[0] * j.nb[1] * j.nb[2];
   }
@@ -181,16 +184,19 @@ void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<
     for (auto& t : *sb.tune)
       if (same_class(t, key)) { tuned = &t; break; }
   }
+  auto usable = [&](int t) { return mode == Mode::F64 ? 0 : t == 1 ? (big ? 1 : 0) : t == 2 ? 2 : 0; };
   int split_cap = 0;  // 0: built-in rule
   if (sb.force_tile >= 0) {
-    gk.tile = (sb.force_tile == 1 && big) ? 1 : 0;
+    gk.tile = usable(sb.force_tile);
     split_cap = std::max(1, sb.force_splits);
   } else if (tuned) {
-    gk.tile = (tuned->tile == 1 && big) ? 1 : 0;
+    gk.tile = usable(tuned->tile);
     split_cap = std::max(1, tuned->splits);
   } else if (big && w128 >= 256) {
     // built-in: the large tile when the launch still fills the chip
     gk.tile = 1;
+  } else if (kmax <= 512) {
+    gk.tile = usable(2);  // short K: more resident workgroups
   }
   const int BM = gemm_bm(gk.tile), BN = gemm_bn(gk.tile), BK = gemm_bk(mode, gk.tile);
   long long base_wgs = 0;
@@ -1419,7 +1425,7 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
     throw Error{MPO_ERR_INVALID_ARG, "bad tuning table"};
   X.tune.assign(o->tune, o->tune + o->n_tune);
   for (auto& t : X.tune)
-    if (t.tile < 0 || t.tile > 1 || t.splits < 1 || t.splits > 64)
+    if (t.tile < 0 || t.tile > 2 || t.splits < 1 || t.splits > 64)
       throw Error{MPO_ERR_INVALID_ARG, "bad tuning entry"};
   X.sb.tune = X.tune.empty() ? nullptr : &X.tune;
   X.pairs.resize(n_pairs);
@@ -2235,7 +2241,7 @@ mpo_status mpo_gemm_autotune(const mpo_pair* pairs, int32_t n_pairs, const mpo_f
         if (seen) continue;
         mpo_gemm_tune win = key;
         win.us = -1;
-        for (int tile = 0; tile < (r.first == Mode::F64 ? 1 : 2); ++tile) {
+        for (int tile = 0; tile < (r.first == Mode::F64 ? 1 : 3); ++tile) {
           for (int sp : {1, 2, 4, 8, 16}) {
             if (sp > 1 && key.K / sp < gemm_bk(r.first, tile)) continue;
             Program P;

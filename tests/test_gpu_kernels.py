@@ -25,7 +25,8 @@ TOL = {0: 1e-13, 1: 2e-5, 2: 2e-2}
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("akc,bkc", [(1, 1), (1, 0), (0, 1), (0, 0)])
 @pytest.mark.parametrize("M,N,K,tile,splits", [(64, 64, 64, 0, 1), (77, 45, 53, 0, 1),
-                                               (200, 136, 300, 1, 1), (130, 70, 1000, 0, 4)])
+                                               (200, 136, 300, 1, 1), (130, 70, 1000, 0, 4),
+                                               (77, 45, 53, 2, 1), (130, 70, 1000, 2, 4)])
 def test_gemm_against_numpy(hooks, kind, akc, bkc, M, N, K, tile, splits):
     from tests.gpu_util import dev, ptr
     mode, ta, tb, tc = kind
