@@ -223,6 +223,32 @@ def accuracy(A, B, n_sweeps, Cs_oracle, tuning):
     return out
 
 
+def hybrid_run(A, B, n_rand, n_plain, tuning):
+    """Randomized FP32 sweeps, then the plain FP64 fit started from their C
+    (the initial guess of Alg. 5): fit error after every sweep, and the time
+    of the switch (export of C and the plain context's initialization)."""
+    import torch
+    from paper_2606_23274_amd.api import FitContext, fit_error
+    w = WORKLOAD
+    ctx = FitContext([(A, B)], w["chi_c"], precision="fp32", sketch_p=w["p"], seed=w["seed"], tuning=tuning)
+    eps = []
+    for _ in range(n_rand):
+        ctx.sweep(1)
+        eps.append(fit_error(A, B, ctx.export_numpy(0))[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C = ctx.export_numpy(0)
+    ctx.close()
+    ctx2 = FitContext([(A, B)], w["chi_c"], precision="fp64", sketch_p=-1, c_init=[C])
+    torch.cuda.synchronize()
+    switch_s = time.perf_counter() - t0
+    for _ in range(n_plain):
+        ctx2.sweep(1)
+        eps.append(fit_error(A, B, ctx2.export_numpy(0))[0])
+    ctx2.close()
+    return eps, switch_s
+
+
 def batched_section(steps):
     import torch
     from paper_2606_23274_amd.api import FitContext, autotune
@@ -388,15 +414,27 @@ def main():
         rates = {"fp32": value, "fp32_p48": args.steps / wl48,
                  "bf16x3": others["bf16x3"]["sweeps_per_s"], "fp64": others["fp64"]["sweeps_per_s"],
                  "fp64_plain": others["fp64_plain"]["sweeps_per_s"]}
+        # randomized FP32 sweeps, then the plain FP64 fit from their result
+        n_rand = 2
+        h_eps, switch_s = hybrid_run(A, B, n_rand, max(1, args.sweeps - n_rand), table)
+        acc["hybrid_fp32_then_fp64_plain"] = {"eps": h_eps, "randomized_sweeps": n_rand,
+                                              "switch_seconds": round(switch_s, 4)}
         plain_final = acc["fp64_plain"]["eps"][-1]
         tta = {"fp64_plain_final_eps": plain_final}
+
+        def hybrid_seconds(n):
+            nr = min(n, n_rand)
+            return nr / value + (switch_s + (n - nr) / rates["fp64_plain"] if n > n_rand else 0.0)
         for thr in (1.01, 1.02, 1.10):
             row = {}
             for key, rate in rates.items():
                 n_need = next((i + 1 for i, v in enumerate(acc[key]["eps"]) if v <= plain_final * thr), None)
                 row[key] = {"sweeps": n_need, "seconds": round(n_need / rate, 4) if n_need else None}
+            n_need = next((i + 1 for i, v in enumerate(h_eps) if v <= plain_final * thr), None)
+            row["hybrid_fp32_then_fp64_plain"] = {"sweeps": n_need,
+                                                  "seconds": round(hybrid_seconds(n_need), 4) if n_need else None}
             base = row["fp64_plain"]["seconds"]
-            for key in rates:
+            for key in row:
                 sec = row[key]["seconds"]
                 row[key]["speedup_vs_fp64_plain"] = round(base / sec, 2) if base and sec else None
             tta[f"eps_within_{round((thr - 1) * 100)}pct"] = row

@@ -101,7 +101,14 @@ typedef struct {
                             mpo_gemm_autotune (copied at init); NULL = built-in
                             tile and split-K choice                          */
   int32_t n_tune;
-  int32_t reserved[3];
+  int32_t profile;    /* 1: time every launch with HIP events, eager, for
+                         mpo_fit_profile (no graph replay)                   */
+  const mpo_tt* c_init; /* optional initial guesses (Alg. 5 input "initial
+                           guess C"), n_pairs host entries, the same L and d
+                           as the pair, bond dims <= 512; NULL = A (Sec.
+                           2.3.5).  Used as given: right-orthogonalized, or
+                           brought to inverse canonical form; only read at
+                           init.                                            */
 } mpo_fit_opts;
 
 /* One tuned class of grouped GEMM launches: the operand kind (mode as
@@ -125,9 +132,10 @@ mpo_status mpo_fit_workspace_bytes(const mpo_pair* pairs, int32_t n_pairs,
                                    const mpo_fit_opts* opts, size_t* bytes);
 
 /* Prepares the fit of every pair (Alg. 5 preprocessing): copies the cores,
-   left-orthogonalizes A and B (norms split off), takes C = A right-
-   orthogonalized (serial) or in inverse canonical form (even/odd) as the
-   initial guess (Sec. 2.3.5), and precomputes the environments.  The inputs
+   left-orthogonalizes A and B (norms split off), takes C = A (or
+   opts->c_init) right-orthogonalized (serial) or in inverse canonical form
+   (even/odd) as the initial guess (Sec. 2.3.5), and precomputes the
+   environments.  The inputs
    may be released once the stream has passed this call.  `workspace` must be
    256-byte aligned and at least mpo_fit_workspace_bytes long.  On success
    *ctx receives a new context. */

@@ -204,19 +204,21 @@ def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
 
 
 def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
-                 on_half_step=None):
+                 on_half_step=None, C_init=None):
     """Single-device limit of the parallel fit in inverse canonical form
     (Sec. 4, Alg. 4 and Alg. 6 with every sub-TT two sites long): half-step q
     updates every bond l with l = 1 (mod 2) for q = 0 and l = 0 (mod 2) for
     q = 1, each independently from the environments as they stood at the
-    half-step's start.  An update sets Psi_l = U S, Psi_{l+1} = S V^T,
+    half-step's start.  The initial guess (A, or C_init) is right-
+    orthogonalized and brought to inverse canonical form.  An update sets
+    Psi_l = U S, Psi_{l+1} = S V^T,
     Y_l = S^{-1} (Alg. 4) and rebuilds L_l from Psi_l Y_l = U and R_{l+1}
     from Y_l Psi_{l+1} = V^T.  Omega of half-step q of sweep i at bond l is the
     Philox stream (pair, 2 i + q, l).  The result is merged as C_l = Psi_l Y_l,
     C_L = Psi_L (Sec. 4.7)."""
     L = len(A)
     A1, B1, nu, caps = _preprocess(A, B)
-    C0 = canon.right_orthogonalize(A1)
+    C0 = canon.right_orthogonalize(A1 if C_init is None else C_init)
     Psi, Y, n_guard = canon.inverse_canonical(C0)
     ones = np.ones((1, 1, 1))
     Lenv = [None] * (L + 1)

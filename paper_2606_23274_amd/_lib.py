@@ -32,7 +32,7 @@ class MpoFitOpts(C.Structure):
     _fields_ = [("chi_max", C.c_int32), ("tau", C.c_double), ("precision", C.c_int32),
                 ("schedule", C.c_int32), ("sketch_p", C.c_int32), ("seed", C.c_uint64),
                 ("capture_graph", C.c_int32), ("tune", C.POINTER(MpoGemmTune)),
-                ("n_tune", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("n_tune", C.c_int32), ("profile", C.c_int32), ("c_init", C.POINTER(MpoTT))]
 
 
 class MpoError(RuntimeError):

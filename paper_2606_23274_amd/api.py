@@ -42,7 +42,7 @@ class _Setup:
     """Device copies of the cores, the ctypes pair array and the options."""
 
     def __init__(self, pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
-                 profile, pair_chi_max, tuning):
+                 profile, pair_chi_max, tuning, c_init=None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.tts = []
@@ -61,11 +61,17 @@ class _Setup:
         opts.sketch_p = int(sketch_p)
         opts.seed = int(seed)
         opts.capture_graph = 1 if capture_graph else 0
-        opts.reserved[0] = 1 if profile else 0
+        opts.profile = 1 if profile else 0
         self.tune = tune_mod.to_ctypes(tune_mod.load(tuning)) if tuning is not None else None
         if self.tune is not None and len(self.tune):
             opts.tune = self.tune
             opts.n_tune = len(self.tune)
+        if c_init is not None:  # one initial guess (list of FP64 cores) per pair
+            if len(c_init) != len(pairs):
+                raise ValueError("c_init needs one MPO per pair")
+            self.c_tts = [_TT(_dev_cores(Cc, self.device)) for Cc in c_init]
+            self.c_arr = (_lib.MpoTT * len(pairs))(*[t.tt for t in self.c_tts])
+            opts.c_init = self.c_arr
         self.opts = opts
         nbytes = C.c_size_t()
         _lib.check(self.lib.mpo_fit_workspace_bytes(arr, len(pairs), C.byref(opts), C.byref(nbytes)))
@@ -82,13 +88,16 @@ class FitContext:
     'even_odd'; sketch_p < 0 runs the plain SVD, >= 0 the randomized SVD with
     chi_max + p sketch columns; pair_chi_max optionally sets each pair's cap;
     tuning: a GEMM tuning table (list of entries, or a JSON path) from
-    autotune().
+    autotune().  c_init: optional initial guess C per pair (lists of
+    (chi_l, d, d, chi_r) FP64 cores, e.g. export_numpy() of another fit);
+    default: A.
     """
 
     def __init__(self, pairs, chi_max, precision="fp32", schedule="serial", sketch_p=-1, seed=0,
-                 capture_graph=True, device="cuda:0", profile=False, pair_chi_max=None, tuning=None):
+                 capture_graph=True, device="cuda:0", profile=False, pair_chi_max=None, tuning=None,
+                 c_init=None):
         su = _Setup(pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
-                    profile, pair_chi_max, tuning)
+                    profile, pair_chi_max, tuning, c_init)
         self._setup = su
         self.lib = su.lib
         self.device = su.device

@@ -358,10 +358,16 @@ struct PairState {
   std::vector<double*> Yv;
   double* nu_dev = nullptr;       // [2]: nu_A, nu_B
   double nu = 1.0;
-  // host copies of the input shapes
-  std::vector<int> chiA_in, chiB_in;
-  std::vector<const double*> A_in, B_in;
+  // host copies of the input shapes; an optional initial guess C (else A)
+  std::vector<int> chiA_in, chiB_in, chiC_in;
+  std::vector<const double*> A_in, B_in, C_in;
 };
+
+// Bond b of the initial guess before its right-orthogonalization: the given
+// C, else the input A (whose preprocessed dims never exceed the input ones).
+int init_dim(const PairState& P, int b) {
+  return P.C_in.empty() ? P.chiA_in[b] : std::max(P.chiA_in[b], P.chiC_in[b]);
+}
 
 // Factorization scratch of one bond.
 struct BondScratch {
@@ -426,8 +432,8 @@ void plan_shapes(PairState& P, int chi_max, int schedule) {
   P.cB = leftorth(P.chiB_in);
   P.rcap.assign(L + 1, 1);
   for (int i = 1; i < L; ++i) P.rcap[i] = P.cA[i] * P.cB[i];
-  // initial C: A right-orthogonalized
-  std::vector<int> c(P.cA);
+  // initial C: the given guess (else A) right-orthogonalized
+  std::vector<int> c(P.C_in.empty() ? P.cA : P.chiC_in);
   for (int i = L - 1; i >= 1; --i) c[i] = std::min(c[i], dd * c[i + 1]);
   P.cC = c;
   P.capC = c;
@@ -702,8 +708,10 @@ void carve(Ctx& X, Carver& cv) {
     for (int i = 0; i < L; ++i) {
       P.A64[i] = cv.take<double>((size_t)P.chiA_in[i] * dd * P.chiA_in[i + 1]);
       P.B64[i] = cv.take<double>((size_t)P.chiB_in[i] * dd * P.chiB_in[i + 1]);
-      P.C64[i] = cv.take<double>((size_t)std::max(P.capC[i], P.chiA_in[i]) * dd *
-                                 std::max(P.capC[i + 1], P.chiA_in[i + 1]));
+      // C holds the initial guess unclipped (A or the given C) before its
+      // right-orthogonalization, and the fit's bonds afterwards
+      P.C64[i] = cv.take<double>((size_t)std::max(P.capC[i], init_dim(P, i)) * dd *
+                                 std::max(P.capC[i + 1], init_dim(P, i + 1)));
       const size_t na = (size_t)P.cA[i] * dd * P.cA[i + 1], nb = (size_t)P.cB[i] * dd * P.cB[i + 1];
       P.At[i] = cv.take<char>(na * wb); P.Amt[i] = cv.take<char>(na * wb);
       P.Bw[i] = cv.take<char>(nb * wb); P.Bmw[i] = cv.take<char>(nb * wb);
@@ -756,7 +764,7 @@ void carve(Ctx& X, Carver& cv) {
   long long core_max = 1, kq = 1;
   for (auto& P : X.pairs)
     for (int i = 0; i < P.L; ++i) {
-      const long long a = std::max(P.chiA_in[i], P.capC[i]), b = std::max(P.chiA_in[i + 1], P.capC[i + 1]);
+      const long long a = std::max(init_dim(P, i), P.capC[i]), b = std::max(init_dim(P, i + 1), P.capC[i + 1]);
       core_max = std::max({core_max, a * P.dd * b, (long long)P.chiB_in[i] * P.dd * P.chiB_in[i + 1]});
       kq = std::max({kq, a, b, (long long)P.chiB_in[i], (long long)P.chiB_in[i + 1]});
     }
@@ -852,10 +860,11 @@ void rec_left_orth(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores
   add_simple(P, LK::Norm, std::vector<NormDesc>{NormDesc{cores[L - 1], (long long)cur[L - 1] * dd, nu}}, 0, "init");
 }
 
-// C_init = A right-orthogonalized by an RQ sweep L..2 (Sec. 2.3.1).
+// The initial C (A, or the given guess) right-orthogonalized by an RQ sweep
+// L..2 (Sec. 2.3.1).
 void rec_right_orth(Ctx& X, Program& P, PairState& S) {
   const int L = S.L, dd = S.dd;
-  std::vector<int> cur(S.cA);
+  std::vector<int> cur(S.C_in.empty() ? S.cA : S.chiC_in);
   for (int j = L - 1; j >= 1; --j) {
     const int p = cur[j], q = dd * cur[j + 1];
     const int mp = cur[j - 1] * dd;  // rows of the previous core
@@ -1369,9 +1378,16 @@ void rec_init_pair(Ctx& X, Program& P, PairState& S, int pair) {
   rec_left_orth(X, P, S, S.A64, S.chiA_in, S.cA, S.nu_dev);
   rec_left_orth(X, P, S, S.B64, S.chiB_in, S.cB, S.nu_dev + 1);
   std::vector<PermDesc> cc;
-  for (int i = 0; i < L; ++i)
-    cc.push_back(perm4(S.A64[i], 0, S.C64[i], 0, {1, 1, S.cA[i], dd * S.cA[i + 1]},
-                       {0, 0, (long long)dd * S.cA[i + 1], 1}, {0, 0, (long long)dd * S.cA[i + 1], 1}));
+  for (int i = 0; i < L; ++i) {
+    if (S.C_in.empty()) {  // C = the preprocessed A
+      cc.push_back(perm4(S.A64[i], 0, S.C64[i], 0, {1, 1, S.cA[i], dd * S.cA[i + 1]},
+                         {0, 0, (long long)dd * S.cA[i + 1], 1}, {0, 0, (long long)dd * S.cA[i + 1], 1}));
+    } else {  // C = the given initial guess
+      const long long c0 = S.chiC_in[i], c1 = S.chiC_in[i + 1];
+      cc.push_back(perm4(S.C_in[i], 0, S.C64[i], 0, {1, 1, (int)c0, (int)(dd * c1)}, {0, 0, dd * c1, 1},
+                         {0, 0, dd * c1, 1}));
+    }
+  }
   add_perm(P, cc, "init");
   if (X.wmode == Mode::BF16 || X.wmode == Mode::BF16X3) {
     std::vector<unsigned*> sl;
@@ -1398,7 +1414,7 @@ void rec_init_pair(Ctx& X, Program& P, PairState& S, int pair) {
 int n_words(size_t bytes) { return (int)((bytes + 3) / 4); }
 
 void validate_tt(const mpo_tt& t, int L, int d) {
-  if (t.L != L || t.d != d) throw Error{MPO_ERR_SHAPE, "A and B must share L and d"};
+  if (t.L != L || t.d != d) throw Error{MPO_ERR_SHAPE, "A, B (and an initial guess) must share L and d"};
   if (!t.chi || !t.cores) throw Error{MPO_ERR_INVALID_ARG, "null bond dims or cores"};
   if (t.chi[0] != 1 || t.chi[L] != 1) throw Error{MPO_ERR_SHAPE, "boundary bond dims must be 1"};
   for (int i = 0; i <= L; ++i)
@@ -1420,7 +1436,7 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
             : o->precision == MPO_FP32 ? Mode::F32
             : o->precision == MPO_BF16 ? Mode::BF16 : Mode::BF16X3;
   X.wt = o->precision == MPO_FP64 ? DType::F64 : DType::F32;
-  X.profile = o->reserved[0] != 0;
+  X.profile = o->profile != 0;
   if (o->n_tune < 0 || (o->n_tune > 0 && !o->tune))
     throw Error{MPO_ERR_INVALID_ARG, "bad tuning table"};
   X.tune.assign(o->tune, o->tune + o->n_tune);
@@ -1441,6 +1457,14 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
     S.chiB_in.assign(pr.B.chi, pr.B.chi + L + 1);
     S.A_in.assign(pr.A.cores, pr.A.cores + L);
     S.B_in.assign(pr.B.cores, pr.B.cores + L);
+    if (o->c_init) {
+      const mpo_tt& c = o->c_init[p];
+      validate_tt(c, L, d);
+      S.chiC_in.assign(c.chi, c.chi + L + 1);
+      S.C_in.assign(c.cores, c.cores + L);
+      for (int b = 0; b <= L; ++b)
+        if (S.chiC_in[b] > 512) throw Error{MPO_ERR_UNSUPPORTED, "initial guess bond above 512"};
+    }
     for (int b = 0; b <= L; ++b)
       if (S.chiA_in[b] > 512 || S.chiB_in[b] > 512)
         throw Error{MPO_ERR_UNSUPPORTED, "bond dimensions above 512"};
@@ -2206,7 +2230,7 @@ mpo_status mpo_gemm_autotune(const mpo_pair* pairs, int32_t n_pairs, const mpo_f
     o.tune = nullptr;
     o.n_tune = 0;
     o.capture_graph = 0;
-    o.reserved[0] = 0;
+    o.profile = 0;
     mpo_fit_ctx* raw = nullptr;
     const mpo_status st = mpo_fit_init(&raw, pairs, n_pairs, &o, workspace, ws_bytes, stream);
     if (st != MPO_OK) throw Error{st, g_last_error};

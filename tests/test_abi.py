@@ -119,3 +119,24 @@ def test_null_pointers():
     p.pair.A.cores = C.cast(None, C.POINTER(C.c_void_p))
     assert _query([p], _opts())[0] == 1
     assert lib.mpo_fit_sweep(None, 1) == 1
+
+
+def test_initial_guess_validation():
+    """An initial guess must match the pair's L and d and have valid bonds."""
+    lib = _lib()
+    p = _Pair()
+    good = _Pair(chi_a=6)   # an MPO of the same L and d
+    opts = _opts()
+    arr = (lib_mod.MpoTT * 1)(good.pair.A)
+    opts.c_init = arr
+    assert _query([p], opts)[0] == 0
+    bad = _Pair(L=5)
+    opts.c_init = (lib_mod.MpoTT * 1)(bad.pair.A)
+    assert _query([p], opts)[0] == 2
+    nul = _Pair()
+    nul.pair.A.cores = C.cast(None, C.POINTER(C.c_void_p))
+    opts.c_init = (lib_mod.MpoTT * 1)(nul.pair.A)
+    assert _query([p], opts)[0] == 1
+    big = _Pair(chi_a=600)
+    opts.c_init = (lib_mod.MpoTT * 1)(big.pair.A)
+    assert _query([p], opts)[0] == 6

@@ -55,3 +55,14 @@ def test_multi_pair_ragged():
         ref = ofit.fit_even_odd(A, B, caps[i], 2, sketch_p=2, seed=9, pair=i)
         assert dims[i] == ref.bond_dims
         assert mpo.rel_diff(Cs[i], ref.C) < 1e-10
+
+
+def test_even_odd_initial_guess_fp64():
+    """The even/odd fit from a given initial guess against the oracle."""
+    A, B = make_pair(10, 2, 8, seed=31, decay=True)
+    rng = np.random.default_rng(32)
+    dims = [1, 4, 12, 12, 12, 12, 12, 12, 12, 4, 1]
+    C0 = [rng.standard_normal((dims[l], 2, 2, dims[l + 1])) / np.sqrt(dims[l + 1]) for l in range(10)]
+    C, _ = gpu_fit_pairs([(A, B)], 16, 2, precision="fp64", sketch_p=-1, c_init=[C0])
+    ref = ofit.fit_even_odd(A, B, 16, 2, C_init=C0)
+    assert mpo.rel_diff(C[0], ref.C) < 1e-10

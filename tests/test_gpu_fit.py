@@ -91,3 +91,23 @@ def test_ragged_dims_fp64():
     ref = ofit.fit_serial(A, B, 13, 3, sketch_p=2, seed=3)
     assert dims == ref.bond_dims
     assert mpo.rel_diff(C, ref.C) < 1e-10
+
+
+def _random_mpo(seed, L, d, dims):
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal((dims[l], d, d, dims[l + 1])) / np.sqrt(dims[l + 1]) for l in range(L)]
+
+
+@pytest.mark.parametrize("precision,sketch_p,tol", [("fp64", -1, 1e-10), ("fp64", 4, 1e-10),
+                                                    ("fp32", -1, 1e-5)])
+def test_initial_guess(precision, sketch_p, tol):
+    """Fit from a given initial guess (Alg. 5 input C), with unclipped bond
+    dims (12 next to the boundary, where d^2 = 4), against the oracle from the
+    same guess."""
+    A, B = make_pair(10, 2, 8, seed=21, decay=True)
+    C0 = _random_mpo(22, 10, 2, [1] + [12] * 9 + [1])
+    sweeps = 2 if precision == "fp64" else 1
+    C, dims = gpu_fit(A, B, 16, sweeps, precision=precision, sketch_p=sketch_p, seed=7, c_init=[C0])
+    ref = ofit.fit_serial(A, B, 16, sweeps, sketch_p=sketch_p, seed=7, C_init=C0)
+    assert dims == ref.bond_dims
+    assert mpo.rel_diff(C, ref.C) < tol

@@ -203,3 +203,46 @@ def test_even_odd_approaches_serial():
     e_s = mpo.fit_error_dense(A, B, fit.fit_serial(A, B, 12, 6).C)
     e_b = mpo.fit_error_dense(A, B, fit.fit_even_odd(A, B, 12, 8).C)
     assert e_b <= e_s * 1.05 + 1e-12
+
+
+def _random_mpo(rng, L, d, dims):
+    return [rng.standard_normal((dims[l], d, d, dims[l + 1])) / np.sqrt(dims[l + 1]) for l in range(L)]
+
+
+@pytest.mark.parametrize("schedule", ["serial", "even_odd"])
+def test_initial_guess_is_used_as_an_operator(schedule):
+    """Alg. 5 takes the initial guess C as an input.  The fit sees it only
+    through its right-orthogonal form, so a rescaled and gauge-transformed
+    copy of the same operator gives the same result, while a different
+    operator gives a different first sweep."""
+    L, d = 7, 2
+    A, B = make_pair(L, d, 5, seed=13, decay=True)
+    rng = np.random.default_rng(14)
+    dims = [1, 4, 9, 9, 9, 9, 4, 1]
+    C0 = _random_mpo(rng, L, d, dims)
+    Cg = [c.copy() for c in C0]
+    Cg[0] *= 3.7
+    for l in range(L - 1):
+        chi = Cg[l].shape[3]
+        G = rng.standard_normal((chi, chi)) + 3 * np.eye(chi)
+        Cg[l] = np.tensordot(Cg[l], G, axes=(3, 0))
+        Cg[l + 1] = np.tensordot(np.linalg.inv(G), Cg[l + 1], axes=(1, 0))
+    run = fit.fit_serial if schedule == "serial" else fit.fit_even_odd
+    r0 = run(A, B, 9, 1, C_init=C0)
+    r1 = run(A, B, 9, 1, C_init=Cg)
+    r2 = run(A, B, 9, 1)
+    assert mpo.rel_diff(r1.C, r0.C) < 1e-10
+    assert mpo.rel_diff(r2.C, r0.C) > 1e-6
+
+
+def test_initial_guess_fixed_point():
+    """Started from its own converged result, the plain fit stays there: the
+    fit error does not rise and the operator moves by no more than the last
+    sweeps did."""
+    A, B = make_pair(7, 2, 5, seed=11, decay=True)
+    r8 = fit.fit_serial(A, B, 8, 8)
+    r9 = fit.fit_serial(A, B, 8, 9)
+    r = fit.fit_serial(A, B, 8, 2, C_init=r8.C)
+    e8 = mpo.fit_error_dense(A, B, r8.C)
+    assert mpo.fit_error_dense(A, B, r.C) <= e8 + 1e-12
+    assert mpo.rel_diff(r.C, r8.C) <= 10 * mpo.rel_diff(r9.C, r8.C) + 1e-12
