@@ -890,13 +890,11 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
 }
 
 // Householder tridiagonalization (same reflector convention as sytrd_kernel)
-// on the register-resident matrix; reflectors go to W.H (row j = v_j), then
-// Q^T = H_{k-3} ... H_0 is accumulated in the same registers and written to
-// W.V (row-major k x k); d, e to W.d, W.e.
+// on the register-resident matrix; reflectors go to W.H (row j = v_j), tau
+// to W.tau, d and e to W.d, W.e; qt_rows_kernel then forms Q^T in W.V.
 template <int NB, int G>
 __global__ void __launch_bounds__(G * G) sytrd_reg_kernel(const EigDesc* __restrict__ descs) {
   __shared__ double vb[2][G * NB], wb[2][G * NB];
-  __shared__ double s_taus[G * NB];
   const EigDesc dd = descs[blockIdx.x];
   const int k = dd.k;
   EigWork W(dd.work, k, dd.r);
@@ -970,7 +968,6 @@ __global__ void __launch_bounds__(G * G) sytrd_reg_kernel(const EigDesc* __restr
       if (threadIdx.x == 0) {
         W.e[jj] = beta;
         W.tau[jj] = tau;
-        s_taus[jj] = tau;
       }
       if (tau == 0.0) continue;  // uniform
       // p = tau * A22 v on rows > jj (v vanishes on rows and columns <= jj)
@@ -1029,70 +1026,87 @@ __global__ void __launch_bounds__(G * G) sytrd_reg_kernel(const EigDesc* __restr
   } else {
     if (threadIdx.x == 0) { W.d[0] = a[0][0]; W.e[0] = 0.0; W.tau[0] = 0.0; }
   }
-  __threadfence_block();
-  __syncthreads();
-  // Q^T = H_{k-3} ... H_0: M <- M H_j = M - tau_j (M v_j) v_j^T for j = k-3 .. 0.
-  // v_j vanishes on columns <= j, i.e. below register block JB = (j + 1) / G,
-  // and rows <= j of M = H_{k-3} ... H_{j+1} are rows of the identity, so
-  // (M v_j) vanishes there too: only register blocks >= JB take part.
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) a[i][j] = (tr + G * i == tc + G * j) ? 1.0 : 0.0;
-  double vnext = 0.0;
-  if (k >= 3 && threadIdx.x < G * NB)
-    vnext = threadIdx.x < k ? vstore[(long long)(k - 3) * k + threadIdx.x] : 0.0;
-  static_for<0, NB>([&](auto t_) {
-    constexpr int JB = NB - 1 - decltype(t_)::value;
-    const int jhi = min(k - 3, G * JB + G - 2), jlo = max(0, G * JB - 1);
-    for (int jj = jhi; jj >= jlo; --jj) {
-      const int buf = jj & 1;
-      const double tau = s_taus[jj];
-      double* v = vb[buf];
-      double* w = wb[buf];
-      if (threadIdx.x < G * NB) v[threadIdx.x] = vnext;
-      if (jj > 0 && threadIdx.x < G * NB)  // prefetch the next reflector
-        vnext = threadIdx.x < k ? vstore[(long long)(jj - 1) * k + threadIdx.x] : 0.0;
-      __syncthreads();
-      if (tau != 0.0) {  // uniform
-        double vc[NB], pr[NB];
-#pragma unroll
-        for (int j = JB; j < NB; ++j) vc[j] = v[tc + G * j];
-#pragma unroll
-        for (int i = JB; i < NB; ++i) {
-          pr[i] = 0.0;
-#pragma unroll
-          for (int j = JB; j < NB; ++j) pr[i] = fma(a[i][j], vc[j], pr[i]);
-        }
-        row_reduce_all<G, JB>(pr);
-        if (tc == 0) {
-#pragma unroll
-          for (int i = JB; i < NB; ++i) w[tr + G * i] = tau * pr[i];
-        }
-      }
-      __syncthreads();
-      if (tau != 0.0) {
-        double vc[NB];
-#pragma unroll
-        for (int j = JB; j < NB; ++j) vc[j] = v[tc + G * j];
-#pragma unroll
-        for (int i = JB; i < NB; ++i) {
-          const double wi = w[tr + G * i];
-#pragma unroll
-          for (int j = JB; j < NB; ++j) a[i][j] -= wi * vc[j];
-        }
-      }
-    }
-  });
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int r = tr + G * i, c = tc + G * j;
-      if (r < k && c < k) W.V[(long long)r * k + c] = a[i][j];
-    }
 }
 
+// Q^T = H_{k-3} ... H_0 (register path), row by row: the rows of
+// M <- M H_j = M - tau_j (M v_j) v_j^T are independent, so a one-wave
+// workgroup takes 4 rows (lane (tr, tc) holds columns tc + 16 b, b < NB, of
+// row 4 blockIdx.x + tr) and applies every reflector without a barrier after
+// the taus are staged in LDS.  One wave per workgroup spreads the rows over
+// many CUs: the four rows of a wave read the same reflector entries, so the
+// vector-memory issue rate per CU, not the data volume, bounds the loads.
+// The reflectors (rows of W.H) are read from L2 four at a time into two
+// alternating register sets, the next four in flight while the current ones
+// are applied; the row products are DPP reductions over the 16 lanes of a row.  A column c >= k reads column 0
+// of the same reflector instead, which is zero (v_j vanishes on rows <= j),
+// so the loads need no mask.
+template <int NB>
+__global__ void __launch_bounds__(64) qt_rows_kernel(const EigDesc* __restrict__ descs) {
+  constexpr int D = 4;
+  const EigDesc dd = descs[blockIdx.y];
+  const int k = dd.k;
+  if (4 * (int)blockIdx.x >= k) return;  // uniform
+  EigWork W(dd.work, k, dd.r);
+  __shared__ double s_tau[16 * NB];
+  for (int t = threadIdx.x; t < k; t += 64) s_tau[t] = W.tau[t];
+  __syncthreads();
+  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+  const int r = 4 * blockIdx.x + tr;
+  double m[NB];
+  unsigned off[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int c = tc + 16 * b;
+    m[b] = c == r ? 1.0 : 0.0;
+    off[b] = c < k ? 8u * (unsigned)c : 0u;  // byte offsets
+  }
+  // reflectors j0, j0 - 1, ..., j0 - D + 1; one with j < 0 reads reflector
+  // 0 (written whenever the loop runs, k >= 3) and gets tau = 0, so that the
+  // loads stay unconditional and in flight together.  Buffer loads: the row
+  // offset is a scalar operand, the column offsets stay fixed per thread.
+  const __amdgpu_buffer_rsrc_t hres =
+      __builtin_amdgcn_make_buffer_rsrc((void*)W.H, (short)0, 8 * k * k, 0x00020000);
+  auto load = [&](int j0, double (&v)[D][NB], double (&t)[D]) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int j = max(j0 - u, 0);
+      const int so = __builtin_amdgcn_readfirstlane(8 * j * k);  // uniform
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        v[u][b] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(hres, off[b], so, 0));
+      const double tj = s_tau[j];
+      t[u] = j0 - u >= 0 ? tj : 0.0;
+    }
+  };
+  auto apply = [&](const double (&v)[D][NB], const double (&t)[D]) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      double p0 = 0.0, p1 = 0.0;  // two chains for latency
+#pragma unroll
+      for (int b = 0; b < NB; b += 2) p0 = fma(m[b], v[u][b], p0);
+#pragma unroll
+      for (int b = 1; b < NB; b += 2) p1 = fma(m[b], v[u][b], p1);
+      const double s = t[u] * row_reduce<16>(p0 + p1);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) m[b] = fma(-s, v[u][b], m[b]);
+    }
+  };
+  double va[D][NB], ta[D], vb[D][NB], tb[D];
+  if (k >= 3) load(k - 3, va, ta);
+  for (int j0 = k - 3; j0 >= 0; j0 -= 2 * D) {
+    load(j0 - D, vb, tb);
+    apply(va, ta);
+    load(j0 - 2 * D, va, ta);
+    apply(vb, tb);  // all taus zero once j0 - D < 0
+  }
+  if (r < k) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int c = tc + 16 * b;
+      if (c < k) W.V[(long long)r * k + c] = m[b];
+    }
+  }
+}
 
 // ---------------------------------------------------------------- one-sided Jacobi SVD
 
@@ -1189,7 +1203,9 @@ struct RegChol {
 struct RegSytrd {
   template <int NB, int G>
   static void go(const EigDesc* d, int n, hipStream_t s) {
+    static_assert(G == 16, "qt_rows_kernel takes 16 columns per row pass");
     hipLaunchKernelGGL((sytrd_reg_kernel<NB, G>), dim3(n), dim3(G * G), 0, s, d);
+    hipLaunchKernelGGL((qt_rows_kernel<NB>), dim3(4 * NB, n), dim3(64), 0, s, d);
   }
 };
 template <class K, class D>
