@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kBig = 1024;           // threads of the one-workgroup kernels
 constexpr int kPackedMax = 176;      // packed lower triangle in LDS up to this k
+constexpr int kTwistWaveMax = 1600;  // one wave per eigenvector up to this k (6 k doubles of LDS)
 
 __device__ __forceinline__ long long pidx(int i, int j) { return (long long)i * (i + 1) / 2 + j; }
 
@@ -727,6 +728,145 @@ __global__ void twisted_kernel(const EigDesc* __restrict__ descs) {
   }
 }
 
+// The same eigenvector as twisted_kernel, one wave per eigenvalue.  Lane 0
+// runs the bottom-up D- recurrence while lane 1 runs the top-down D+ one
+// (the same instructions on mirrored indices); all lanes then form the twist
+// values gamma_i and their first minimum.  Each side of the twist is a
+// product of ratios (z_i = prod_{l=i}^{g-1} f_l above g, prod_{l=g+1}^{i} f_l
+// below), taken as a prefix / suffix product scan over the wave: lane l owns
+// the rows [l C, l C + C), C = ceil(k / 64), and partial products are kept as
+// mantissa / exponent pairs so that no intermediate can overflow or underflow
+// before the final scaling.  LDS: 6 k doubles.
+struct MantExp {
+  double m;
+  int e;
+};
+__device__ __forceinline__ MantExp me_mul(MantExp a, MantExp b) {
+  int x;
+  const double m = frexp(a.m * b.m, &x);
+  return MantExp{m, a.e + b.e + x};
+}
+__device__ __forceinline__ MantExp me_of(double v) {
+  int x;
+  const double m = frexp(v, &x);
+  return MantExp{m, x};
+}
+
+__global__ void __launch_bounds__(64) twisted_wave_kernel(const EigDesc* __restrict__ descs) {
+  extern __shared__ double lds[];
+  const EigDesc dd = descs[blockIdx.y];
+  const int k = dd.k, j = blockIdx.x;
+  if (j >= dd.r) return;  // uniform
+  EigWork W(dd.work, k, dd.r);
+  double* sd = lds;          // d_i - lambda
+  double* se = lds + k;      // e_i, e_{k-1} = 0
+  double* Dm = lds + 2 * k;  // D-_i
+  double* Dp = lds + 3 * k;  // D+_i
+  double* tf = lds + 4 * k;  // D+_i before the guard, then the ratios f_i (2 k)
+  const int lane = threadIdx.x;
+  const double lam = dd.evals[j];
+  double emax2 = 0.0;
+  for (int i = lane; i < k; i += 64) {
+    sd[i] = W.d[i] - lam;
+    const double ei = i + 1 < k ? W.e[i] : 0.0;
+    se[i] = ei;
+    emax2 = fmax(emax2, ei * ei);
+  }
+  for (int off = 32; off > 0; off >>= 1) emax2 = fmax(emax2, __shfl_xor(emax2, off));
+  const double pivmin = DBL_MIN * fmax(1.0, emax2);
+  auto guard = [pivmin](double q) { return fabs(q) < pivmin ? (q < 0 ? -pivmin : pivmin) : q; };
+  __syncthreads();
+  if (lane < 2) {
+    // step t works on row i(t) = t (lane 1, D+) or k - 1 - t (lane 0, D-),
+    // with the off-diagonal entry e_{i-1} or e_i; both are read two steps
+    // ahead, before the stores of the steps in between
+    const bool down = lane == 1;
+    double* dst = down ? Dp : Dm;
+    double* tops = down ? tf : tf + k;  // lane 0 stores its tops past tf (unused)
+    auto row = [&](int t) { return down ? t : k - 1 - t; };
+    auto ecol = [&](int t) { return se[down ? max(t - 1, 0) : k - 1 - t]; };
+    double d0 = sd[row(0)], c0 = 0.0;
+    double d1 = k > 1 ? sd[row(1)] : 0.0, c1 = k > 1 ? ecol(1) : 0.0;
+    double q = 1.0;
+    for (int t = 0; t < k; ++t) {
+      const double di = d0, ci = c0;
+      d0 = d1;
+      c0 = c1;
+      if (t + 2 < k) {
+        d1 = sd[row(t + 2)];
+        c1 = ecol(t + 2);
+      }
+      const double top = t == 0 ? di : fma(-ci * ci, rcp_nr(q), di);
+      const double gq = top < 0.0 ? -pivmin : pivmin;
+      q = fabs(top) < pivmin ? gq : top;
+      const int i = row(t);
+      dst[i] = q;
+      tops[i] = top;
+    }
+  }
+  __syncthreads();
+  // twist: first i minimizing |gamma_i|, gamma_i = top_i - e_i^2 / D-_{i+1}
+  double best = DBL_MAX;
+  int g = 0;
+  for (int i = lane; i < k; i += 64) {
+    const double top = tf[i];
+    const double gam = i + 1 < k ? fma(-se[i] * se[i], rcp_nr(Dm[i + 1]), top) : top;
+    if (fabs(gam) < best) { best = fabs(gam); g = i; }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off);
+    const int og = __shfl_xor(g, off);
+    if (ob < best || (ob == best && og < g)) { best = ob; g = og; }
+  }
+  __syncthreads();  // every lane has read tf
+  // ratios: f_i = -e_i / D+_i above the twist, -e_{i-1} / D-_i below it
+  const int C = (k + 63) / 64;
+  const int i0 = min(lane * C, k), i1 = min(i0 + C, k);
+  MantExp pf{0.5, 1}, pu{0.5, 1};  // chunk products below / above the twist (1 = 0.5 * 2^1)
+  for (int i = i0; i < i1; ++i) {
+    double f = 1.0;
+    if (i < g) f = -(se[i] * rcp_nr(Dp[i]));
+    else if (i > g) f = -(se[i - 1] * rcp_nr(Dm[i]));
+    tf[i] = f;
+    if (i > g) pf = me_mul(pf, me_of(f));
+    if (i < g) pu = me_mul(pu, me_of(f));
+  }
+  // exclusive prefix product of pf over lower lanes, suffix product of pu over higher ones
+  MantExp xf = pf, xu = pu;
+  for (int off = 1; off < 64; off <<= 1) {
+    const double fm = __shfl_up(xf.m, off);
+    const int fe = __shfl_up(xf.e, off);
+    const double um = __shfl_down(xu.m, off);
+    const int ue = __shfl_down(xu.e, off);
+    if (lane >= off) xf = me_mul(xf, MantExp{fm, fe});
+    if (lane + off < 64) xu = me_mul(xu, MantExp{um, ue});
+  }
+  MantExp ef{__shfl_up(xf.m, 1), __shfl_up(xf.e, 1)};
+  MantExp eu{__shfl_down(xu.m, 1), __shfl_down(xu.e, 1)};
+  if (lane == 0) ef = MantExp{0.5, 1};
+  if (lane == 63) eu = MantExp{0.5, 1};
+  double nrm2 = 0.0;
+  for (int i = i0; i < i1; ++i) {  // below the twist and the twist itself, ascending
+    if (i > g) ef = me_mul(ef, me_of(tf[i]));
+    if (i >= g) {
+      const double z = i == g ? 1.0 : ldexp(ef.m, ef.e);
+      Dm[i] = z;
+      nrm2 = fma(z, z, nrm2);
+    }
+  }
+  for (int i = i1 - 1; i >= i0; --i) {  // above the twist, descending
+    if (i < g) {
+      eu = me_mul(eu, me_of(tf[i]));
+      const double z = ldexp(eu.m, eu.e);
+      Dm[i] = z;
+      nrm2 = fma(z, z, nrm2);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) nrm2 += __shfl_xor(nrm2, off);
+  const double inv = rsq_nr(nrm2);
+  for (int i = i0; i < i1; ++i) W.X[(long long)i * dd.r + j] = Dm[i] * inv;
+}
+
 // Z[:, cols] = H_0 H_1 ... H_{k-3} X[:, cols] for one block of columns.
 __global__ void __launch_bounds__(kBig) backtransform_kernel(const EigDesc* __restrict__ descs,
                                                              int rb) {
@@ -1296,13 +1436,18 @@ void launch_eig(const EigDesc* d, const EigDesc* h, int n, int reg, int stage, h
       hipLaunchKernelGGL(bisect_kernel<kBisect>, dim3(max_r, n), dim3(kBisect), lds, s, d);
   }
   if (all || stage == 2) {
-    // one thread per eigenvalue; smaller groups when there are few, so that
-    // more compute units share the work
-    int T = 64;
-    while (T > 16 && (long long)ceil_div(max_r, T) * n < 128) T /= 2;
-    while (T > 1 && (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double) > 150 * 1024) T /= 2;
-    hipLaunchKernelGGL(twisted_kernel, dim3(ceil_div(max_r, T), n), dim3(T),
-                       (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double), s, d);
+    // one wave per eigenvalue; beyond kTwistWaveMax one thread per
+    // eigenvalue, in smaller groups when there are few so that more compute
+    // units share the work
+    if (max_k <= kTwistWaveMax) {
+      hipLaunchKernelGGL(twisted_wave_kernel, dim3(max_r, n), dim3(64), 6 * (size_t)max_k * sizeof(double), s, d);
+    } else {
+      int T = 64;
+      while (T > 16 && (long long)ceil_div(max_r, T) * n < 128) T /= 2;
+      while (T > 1 && (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double) > 150 * 1024) T /= 2;
+      hipLaunchKernelGGL(twisted_kernel, dim3(ceil_div(max_r, T), n), dim3(T),
+                         (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double), s, d);
+    }
   }
   if (reg || !(all || stage == 3)) return;
   // column blocks so that the block plus vectors fit in LDS
