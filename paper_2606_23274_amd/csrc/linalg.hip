@@ -618,14 +618,27 @@ __global__ void __launch_bounds__(kBisect) bisect_kernel(const EigDesc* __restri
   const bool active = jj < dd.r;
   const int m = k - 1 - jj;  // ascending index
   if constexpr (WL == kBisect) {
+    // With a positive upper bound the first round uses the points
+    // hi 2^(t - WL + 1) (the lowest replaced by 0 when lo < 0): the bracket
+    // then holds the eigenvalue to a factor of 2 whatever its size, and the
+    // uniform rounds after it gain relative accuracy at the same rate for
+    // small eigenvalues as for large ones.
+    const bool geo = hi > 0.0;
+    auto gpt = [&](int u) { return (u == 0 && lo < 0.0) ? 0.0 : ldexp(hi, u - (WL - 1)); };
     for (int round = 0; round < bisect_rounds(WL); ++round) {
-      const double x = a + (b - a) * (double)(t + 1) / (double)(WL + 1);
+      const bool g0 = geo && round == 0;
+      const double x = g0 ? gpt(t) : a + (b - a) * (double)(t + 1) / (double)(WL + 1);
       const int c = sturm_count(de, k, x, pivmin);
       const int below = __syncthreads_count(c <= m);
       if (threadIdx.x == 0) {
         double na = a, nb = b;
-        if (below > 0) na = a + (b - a) * (double)below / (double)(WL + 1);
-        if (below < WL) nb = a + (b - a) * (double)(below + 1) / (double)(WL + 1);
+        if (g0) {
+          if (below > 0) na = fmax(a, gpt(below - 1));
+          if (below < WL) nb = fmin(b, gpt(below));
+        } else {
+          if (below > 0) na = a + (b - a) * (double)below / (double)(WL + 1);
+          if (below < WL) nb = a + (b - a) * (double)(below + 1) / (double)(WL + 1);
+        }
         s_a = na;
         s_b = nb;
       }
