@@ -962,11 +962,13 @@ __device__ __forceinline__ void static_for(F&& f) {
 //     X(r, c) -= L(r, jj) X(jj, c), X(r, jj) = -L(r, jj) X(jj, jj) (r > jj).
 // X overwrites L in place: row jj of X only mixes columns <= jj, whose L
 // entries no later Cholesky step reads.  Register indices are constants (the
-// column-block loop is unrolled); masks live in the broadcast vectors.
+// column-block loop is unrolled); masks live in the broadcast vectors, which
+// are zero outside the rows and columns a step updates.
 template <int NB, int G>
 __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __restrict__ descs) {
   __shared__ double colb[2][G * NB];
   __shared__ double rowb[2][G * NB];
+  __shared__ double dgb[2];
   const CholDesc d = descs[blockIdx.x];
   const int k = d.k;
   const int tr = threadIdx.x / G, tc = threadIdx.x % G;
@@ -984,29 +986,26 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
     const int jend = min(k, G * JB + G);
     for (int jj = G * JB; jj < jend; ++jj) {
       const int jt = jj % G, buf = jj & 1;
-      if (tc == jt) {  // column jj of the updated matrix (rows >= jj)
+      if (tc == jt) {  // column jj of the updated matrix below the diagonal; the diagonal apart
 #pragma unroll
-        for (int i = JB; i < NB; ++i) colb[buf][tr + G * i] = (tr + G * i >= jj) ? a[i][JB] : 0.0;
+        for (int i = JB; i < NB; ++i) colb[buf][tr + G * i] = (tr + G * i > jj) ? a[i][JB] : 0.0;
+        if (tr == jt) dgb[buf] = a[JB][JB];
       }
       if (tr == jt) {  // row jj of X (columns < jj; the rest masked)
 #pragma unroll
         for (int j = 0; j <= JB; ++j) rowb[buf][tc + G * j] = (tc + G * j < jj) ? a[JB][j] : 0.0;
       }
       __syncthreads();
-      const double djj = colb[buf][jj];
+      const double djj = dgb[buf];
       const bool ok = djj > 0.0 && djj < INFINITY;
       if (!ok) bad = true;
       const double invd = ok ? rcp_nr(djj) : 0.0;
       const double invs = ok ? rsq_nr(djj) : 0.0;  // 1 / L(jj, jj)
-      // the broadcast vectors are read unconditionally (all indices lie in
-      // the buffers) and masked by selects, so the loads issue back to back
+      // the broadcast vectors hold zeros outside rows > jj (column) and
+      // columns < jj (row), so they are used unmasked
       double cc[NB], xr[NB];
 #pragma unroll
-      for (int j = JB; j < NB; ++j) {
-        const int c = tc + G * j;
-        const double x = colb[buf][c];
-        cc[j] = (c > jj) ? x : 0.0;
-      }
+      for (int j = JB; j < NB; ++j) cc[j] = colb[buf][tc + G * j];
 #pragma unroll
       for (int j = 0; j <= JB; ++j) xr[j] = rowb[buf][tc + G * j] * invs;  // X(jj, c) / L(jj, jj)
       const bool col_owner = tc == jt, row_owner = tr == jt;
@@ -1014,8 +1013,7 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
 #pragma unroll
       for (int i = JB; i < NB; ++i) {
         const int r = tr + G * i;
-        const double x = colb[buf][r];
-        const double ar = (r > jj) ? x : 0.0;
+        const double ar = colb[buf][r];
         const double cr = ar * invd, l = ar * invs;  // l = L(r, jj)
 #pragma unroll
         for (int j = JB; j < NB; ++j) a[i][j] -= cr * cc[j];
@@ -1356,8 +1354,13 @@ struct RegChol {
 struct RegSytrd {
   template <int NB, int G>
   static void go(const EigDesc* d, int n, hipStream_t s) {
-    static_assert(G == 16, "qt_rows_kernel takes 16 columns per row pass");
     hipLaunchKernelGGL((sytrd_reg_kernel<NB, G>), dim3(n), dim3(G * G), 0, s, d);
+  }
+};
+struct RegQt {
+  template <int NB, int G>
+  static void go(const EigDesc* d, int n, hipStream_t s) {
+    static_assert(G == 16, "qt_rows_kernel takes 16 columns per row pass");
     hipLaunchKernelGGL((qt_rows_kernel<NB>), dim3(4 * NB, n), dim3(64), 0, s, d);
   }
 };
@@ -1462,7 +1465,11 @@ void launch_eig(const EigDesc* d, const EigDesc* h, int n, int reg, int stage, h
                          (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double), s, d);
     }
   }
-  if (reg || !(all || stage == 3)) return;
+  if (!(all || stage == 3)) return;
+  if (reg) {  // Q^T from the reflectors; the caller forms Z = Q X
+    launch_reg<RegQt>(d, n, max_k, s);
+    return;
+  }
   // column blocks so that the block plus vectors fit in LDS
   int rb = std::max(1, std::min(max_r, (int)(120 * 1024 / sizeof(double) / max_k)));
   rb = std::min(rb, kBig);

@@ -92,10 +92,11 @@ constexpr int kRegMax = 176;
 void launch_chol(const CholDesc* d, int n, int max_k, int inverse, hipStream_t s);
 void launch_trsm(const TrsmDesc* d, int n, int max_rows, hipStream_t s);
 // Runs the eigen pipeline: tridiagonalization (stage 0), bisection (1),
-// twisted-factorization eigenvectors (2), back-transformation (3, not with
-// `reg`); stage < 0 runs all of them.  With `reg` (every k <= kRegMax) the
-// reduction keeps the matrix in registers and leaves Q^T in the work area;
-// the caller then forms Z = Q X with a GEMM.  `h_descs` is the host copy of `d`.
+// twisted-factorization eigenvectors (2), back-transformation (3); stage < 0
+// runs all of them.  With `reg` (every k <= kRegMax) the reduction keeps the
+// matrix in registers and stage 3 forms Q^T in the work area from the
+// reflectors; the caller then forms Z = Q X with a GEMM.  `h_descs` is the
+// host copy of `d`.
 void launch_eig(const EigDesc* d, const EigDesc* h_descs, int n, int reg, int stage, hipStream_t s);
 
 }  // namespace mpofit

@@ -335,7 +335,8 @@ void add_eig(Program& P, const SplitBuf& sb, const std::vector<EigDesc>& ed, boo
       add_gemm(P, sb, Mode::F64, upd, init ? "init" : names[0], 0.0);
     }
   }
-  for (int st = nb > 0 ? 1 : 0; st < (reg ? 3 : 4); ++st) stage(st, names[st], st == 0 ? ftri : 0.0);
+  // with `reg`, stage 3 forms Q^T from the reflectors ((4/3) k^3 flops)
+  for (int st = nb > 0 ? 1 : 0; st < 4; ++st) stage(st, names[st], st == 0 || (st == 3 && reg) ? ftri : 0.0);
 }
 
 // ------------------------------------------------------------------ state
