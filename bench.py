@@ -36,7 +36,8 @@ WORKLOAD = dict(L=40, d=2, chi=64, chi_c=128, p=16, seed=0)
 MFMA_CLASSES = ("theta", "env_update", "env_ext1", "env_ext2", "sketch", "project")
 # (k = chi_C + p = 144 runs the register kernels on their 16 x 16 grid)
 KERNEL_OF_CLASS = {"qr_chol_inv": "chol_inv_reg_kernel<9, 16>", "eig_tridiag": "sytrd_reg_kernel<9, 16>",
-                   "eig_bisect": "bisect_kernel", "eig_vectors": "twisted_kernel",
+                   "gauge_chol_inv": "chol_inv_reg_kernel<8, 16>",
+                   "eig_bisect": "bisect_kernel<256>", "eig_vectors": "twisted_wave_kernel",
                    "theta": "gemm_kernel<Mode::F32, float, float, float, true, true, 0|1>"}
 
 

@@ -554,7 +554,18 @@ double chol_shift(int n, int k) { return 11.0 * ((double)n * k + (double)k * (k 
 // so R^{-1} = [[R11^{-1}, X12], [., R22^{-1}]] (the lower-left block is never
 // read), and X R^{-1} = [X1 R11^{-1}, X [X12; R22^{-1}]].  Temporaries live in
 // the second k x k block of the job's R scratch.
-void add_chol_inv_blocked(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int pass) {
+// Profile classes of a Cholesky-QR: the range finder's ("qr_*") or the
+// re-orthonormalization of a gauge factor ("gauge_*").
+struct QrClasses {
+  const char *gram, *chol_inv, *chol, *apply;
+};
+inline QrClasses qr_classes(bool gauge) {
+  return gauge ? QrClasses{"gauge_gram", "gauge_chol_inv", "gauge_chol", "gauge_apply"}
+               : QrClasses{"qr_gram", "qr_chol_inv", "qr_chol", "qr_apply"};
+}
+
+void add_chol_inv_blocked(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int pass, bool gauge) {
+  const QrClasses qc = qr_classes(gauge);
   std::vector<GemmJob> gj, l21, s22, t2, x12, ap;
   std::vector<CholDesc> c1, c2;
   std::vector<PermDesc> cp;
@@ -593,11 +604,11 @@ void add_chol_inv_blocked(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs
     l.n = (int)cd.size();
     l.maxa = kRegMax;
     l.maxb = 1;
-    l.cls = "qr_chol_inv";
+    l.cls = qc.chol_inv;
     for (auto& c : cd) l.flops += 2.0 / 3.0 * c.k * (double)c.k * c.k;
     P.launches.push_back(l);
   };
-  add_gemm(P, X.sb, Mode::F64, gj, "qr_gram", 0);
+  add_gemm(P, X.sb, Mode::F64, gj, qc.gram, 0);
   chol(c1);
   add_gemm(P, X.sb, Mode::F64, l21, "qr_block", 0);
   add_perm(P, cp, "qr_block");
@@ -605,18 +616,19 @@ void add_chol_inv_blocked(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs
   chol(c2);
   add_gemm(P, X.sb, Mode::F64, t2, "qr_block", 0);
   add_gemm(P, X.sb, Mode::F64, x12, "qr_block", 0);
-  add_gemm(P, X.sb, Mode::F64, ap, "qr_apply", 0);
+  add_gemm(P, X.sb, Mode::F64, ap, qc.apply, 0);
 }
 
-void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int passes) {
+void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int passes, bool gauge = false) {
   if (jobs.empty()) return;
+  const QrClasses qc = qr_classes(gauge);
   bool fast = true, blocked = true;
   for (auto& j : jobs) {
     fast = fast && j.k <= kRegMax && !j.Rout && j.T;
     blocked = blocked && j.k <= 2 * kRegMax && !j.Rout && j.T;
   }
   if (!fast && blocked) {
-    for (int pass = 0; pass < passes; ++pass) add_chol_inv_blocked(X, P, jobs, pass);
+    for (int pass = 0; pass < passes; ++pass) add_chol_inv_blocked(X, P, jobs, pass, gauge);
     if (passes % 2 == 1) {
       std::vector<PermDesc> cp;
       for (auto& j : jobs)
@@ -647,17 +659,17 @@ void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int pass
       maxk = std::max(maxk, j.k);
       maxn = std::max(maxn, j.n);
     }
-    add_gemm(P, X.sb, Mode::F64, gj, "qr_gram", 0);
+    add_gemm(P, X.sb, Mode::F64, gj, qc.gram, 0);
     Launch l;
     l.kind = LK::Chol;
     l.off = P.push(cd);
     l.n = (int)cd.size();
     l.maxa = maxk;
     l.maxb = fast ? 1 : 0;
-    l.cls = fast ? "qr_chol_inv" : "qr_chol";
+    l.cls = fast ? qc.chol_inv : qc.chol;
     for (auto& j : jobs) l.flops += (fast ? 2.0 : 1.0) / 3.0 * j.k * (double)j.k * j.k;
     P.launches.push_back(l);
-    if (fast) add_gemm(P, X.sb, Mode::F64, tj, "qr_apply", 0);
+    if (fast) add_gemm(P, X.sb, Mode::F64, tj, qc.apply, 0);
     else add_simple(P, LK::Trsm, td, maxn, "qr_trsm");
     // Rout <- R_pass Rout (the second R block is the product's temp)
     std::vector<GemmJob> rj;
@@ -1111,7 +1123,7 @@ void rec_assign_site(Ctx& X, Program& P, std::vector<BondJob>& bj) {
   add_perm(P, cp, "copy");
   if (fwd) {
     add_simple(P, LK::Scale, sc0, maxsc, "scale");
-    add_cholqr(X, P, orth, 1);
+    add_cholqr(X, P, orth, 1, true);
     add_simple(P, LK::Sign, sg, maxr, "sign");
     add_gemm(P, X.sb, Mode::F64, svt, "assemble", 0);
     add_perm(P, perm, "copy");
@@ -1119,7 +1131,7 @@ void rec_assign_site(Ctx& X, Program& P, std::vector<BondJob>& bj) {
     add_gemm(P, X.sb, Mode::F64, vj, "assemble", 0);
     add_perm(P, cpv, "copy");
     add_simple(P, LK::Scale, sc1, maxsc, "scale");
-    add_cholqr(X, P, orth, 1);
+    add_cholqr(X, P, orth, 1, true);
     add_simple(P, LK::Scale, sc2, maxsc, "scale");
     add_simple(P, LK::Sign, sg, maxr, "sign");
     add_simple(P, LK::Scale, sc3, maxsc, "scale");
@@ -1296,8 +1308,8 @@ void rec_assign_inverse(Ctx& X, Program& P, std::vector<BondJob>& bj) {
   add_gemm(P, X.sb, Mode::F64, vj, "assemble", 0);
   add_perm(P, cp, "copy");
   add_simple(P, LK::Scale, sv1, maxsc, "scale");
-  add_cholqr(X, P, orthU, 1);
-  add_cholqr(X, P, orthV, 1);
+  add_cholqr(X, P, orthU, 1, true);
+  add_cholqr(X, P, orthV, 1, true);
   add_simple(P, LK::Sign, sg, maxr, "sign");
   add_simple(P, LK::Scale, sv2, maxsc, "scale");
   add_simple(P, LK::Scale, mk, maxsc, "scale");
