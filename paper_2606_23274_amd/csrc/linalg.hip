@@ -952,23 +952,29 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // G = L L^T (Cholesky, L lower) and R^{-1} = (L^{-1})^T written row-major
-// (upper triangular, zeros below), in one pass over the columns.  Step jj
-// (one barrier): the owners of column jj of the updated matrix and of row jj
-// of X = L^{-1} publish them (double-buffered); every thread then
-//   - finishes the Cholesky step: A(r, c) -= A(r, jj) A(c, jj) / A(jj, jj) on
-//     the trailing block r, c > jj, with L(r, jj) = A(r, jj) / sqrt(A(jj, jj));
-//   - does the row-oriented inverse step on columns c <= jj:
-//     X(jj, c) /= L(jj, jj), X(jj, jj) = 1 / L(jj, jj),
-//     X(r, c) -= L(r, jj) X(jj, c), X(r, jj) = -L(r, jj) X(jj, jj) (r > jj).
-// X overwrites L in place: row jj of X only mixes columns <= jj, whose L
-// entries no later Cholesky step reads.  Register indices are constants (the
-// column-block loop is unrolled); masks live in the broadcast vectors, which
-// are zero outside the rows and columns a step updates.
+// (upper triangular, zeros below), in one pass over the columns, as a
+// right-looking blocked Cholesky with block size G on the register layout
+// (thread (tr, tc) holds A(tr + G i, tc + G j)).  X = L^{-1} overwrites L in
+// place: row jj of X only mixes columns <= jj, whose L entries no later step
+// reads.  Step jj of block JB publishes column jj (below the diagonal, the
+// pivot apart) and row jj of X through one barrier, then updates only block
+// column JB (the panel: A(r, c) -= L(r, jj) L(c, jj), c in the block) and
+// the X entries of block row JB (X(r, c) -= L(r, jj) X(jj, c), X(jj, c) =
+// partial / L(jj, jj), X(r, jj) = -L(r, jj) / L(jj, jj)); the col owner
+// records L(r, jj) for the rows of later blocks in LDS (PT).  At the end of the block, with the block row JB
+// of X (XB) published, every thread applies the rank-G updates of the block:
+//   A(r, c) -= sum_m L(r, m) L(c, m)            r, c in later blocks (r >= c)
+//   X(r, c) -= sum_m L(r, m) X(m, c)            r in later blocks, c < G JB
+//   X(r, c)  = -sum_m L(r, m) X(m, c)           r in later blocks, c in block JB
+// (m over the block's columns, X(m, c) = 0 for m < c), so a step carries
+// about NB multiply-adds per thread instead of NB^2.
 template <int NB, int G>
 __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __restrict__ descs) {
   __shared__ double colb[2][G * NB];
   __shared__ double rowb[2][G * NB];
   __shared__ double dgb[2];
+  __shared__ double PT[G][G * NB];  // PT[m][r] = L(r, G JB + m), rows of later blocks
+  __shared__ double XB[G][G * NB];  // XB[m][c] = X(G JB + m, c), c < G (JB + 1)
   const CholDesc d = descs[blockIdx.x];
   const int k = d.k;
   const int tr = threadIdx.x / G, tc = threadIdx.x % G;
@@ -986,47 +992,79 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
     const int jend = min(k, G * JB + G);
     for (int jj = G * JB; jj < jend; ++jj) {
       const int jt = jj % G, buf = jj & 1;
-      if (tc == jt) {  // column jj of the updated matrix below the diagonal; the diagonal apart
+      if (tc == jt) {  // column jj below the diagonal; the diagonal apart
 #pragma unroll
         for (int i = JB; i < NB; ++i) colb[buf][tr + G * i] = (tr + G * i > jj) ? a[i][JB] : 0.0;
         if (tr == jt) dgb[buf] = a[JB][JB];
       }
-      if (tr == jt) {  // row jj of X (columns < jj; the rest masked)
+      if (tr == jt) {  // row jj of X (columns < jj)
 #pragma unroll
         for (int j = 0; j <= JB; ++j) rowb[buf][tc + G * j] = (tc + G * j < jj) ? a[JB][j] : 0.0;
       }
       __syncthreads();
+      // every broadcast value is read before the pivot is used
       const double djj = dgb[buf];
+      const double cc = colb[buf][tc + G * JB];  // zero unless tc + G JB > jj
+      double xr[JB + 1], av[NB];
+#pragma unroll
+      for (int j = 0; j <= JB; ++j) xr[j] = rowb[buf][tc + G * j];
+#pragma unroll
+      for (int i = JB; i < NB; ++i) av[i] = colb[buf][tr + G * i];
       const bool ok = djj > 0.0 && djj < INFINITY;
       if (!ok) bad = true;
-      const double invd = ok ? rcp_nr(djj) : 0.0;
-      const double invs = ok ? rsq_nr(djj) : 0.0;  // 1 / L(jj, jj)
-      // the broadcast vectors hold zeros outside rows > jj (column) and
-      // columns < jj (row), so they are used unmasked
-      double cc[NB], xr[NB];
-#pragma unroll
-      for (int j = JB; j < NB; ++j) cc[j] = colb[buf][tc + G * j];
-#pragma unroll
-      for (int j = 0; j <= JB; ++j) xr[j] = rowb[buf][tc + G * j] * invs;  // X(jj, c) / L(jj, jj)
+      const double rs = rsq_nr(djj);
+      const double invs = ok ? rs : 0.0;  // 1 / L(jj, jj)
+      const double lc = cc * invs;        // L(c, jj)
       const bool col_owner = tc == jt, row_owner = tr == jt;
-      // Cholesky trailing update (columns > jj) and inverse update (columns < jj)
+      {  // rows of block JB: the panel, the X row update and X's column jj
+        const int r = tr + G * JB;
+        const double l = av[JB] * invs;  // L(r, jj)
+        a[JB][JB] -= l * lc;
 #pragma unroll
-      for (int i = JB; i < NB; ++i) {
-        const int r = tr + G * i;
-        const double ar = colb[buf][r];
-        const double cr = ar * invd, l = ar * invs;  // l = L(r, jj)
-#pragma unroll
-        for (int j = JB; j < NB; ++j) a[i][j] -= cr * cc[j];
-#pragma unroll
-        for (int j = 0; j <= JB; ++j) a[i][j] -= l * xr[j];
-        // column jj of X: X(jj, jj) and X(r, jj) for r > jj
+        for (int j = 0; j <= JB; ++j) a[JB][j] -= l * (xr[j] * invs);  // X(jj, c) = xr / L(jj, jj)
         const double xc = (r == jj) ? invs : -l * invs;
-        a[i][JB] = (col_owner && r >= jj) ? xc : a[i][JB];
+        a[JB][JB] = (col_owner && r >= jj) ? xc : a[JB][JB];
       }
-      // row jj of X: the scaled part
+      double lv[NB];
+#pragma unroll
+      for (int i = JB + 1; i < NB; ++i) {  // rows of later blocks: the panel
+        lv[i] = av[i] * invs;
+        a[i][JB] -= lv[i] * lc;
+      }
+      if (col_owner) {  // L(r, jj) of the later rows to PT (stores only, after all reads)
+#pragma unroll
+        for (int i = JB + 1; i < NB; ++i) PT[jt][tr + G * i] = lv[i];
+      }
 #pragma unroll
       for (int j = 0; j <= JB; ++j)
         a[JB][j] = (row_owner && tc + G * j < jj) ? a[JB][j] * invs : a[JB][j];
+    }
+    if (G * JB + G < k) {  // uniform: a later block holds rows of the matrix
+#pragma unroll
+      for (int j = 0; j <= JB; ++j) XB[tr][tc + G * j] = (tc + G * j <= G * JB + tr) ? a[JB][j] : 0.0;
+      __syncthreads();
+      double acc[NB];
+#pragma unroll
+      for (int i = JB + 1; i < NB; ++i) acc[i] = 0.0;
+      for (int m = 0; m < G; ++m) {
+        double p[NB], q[NB], x[JB + 1];
+#pragma unroll
+        for (int i = JB + 1; i < NB; ++i) p[i] = PT[m][tr + G * i];
+#pragma unroll
+        for (int j = JB + 1; j < NB; ++j) q[j] = PT[m][tc + G * j];
+#pragma unroll
+        for (int j = 0; j <= JB; ++j) x[j] = XB[m][tc + G * j];
+#pragma unroll
+        for (int i = JB + 1; i < NB; ++i) {
+#pragma unroll
+          for (int j = JB + 1; j <= i; ++j) a[i][j] = fma(-p[i], q[j], a[i][j]);
+#pragma unroll
+          for (int j = 0; j < JB; ++j) a[i][j] = fma(-p[i], x[j], a[i][j]);
+          acc[i] = fma(p[i], x[JB], acc[i]);
+        }
+      }
+#pragma unroll
+      for (int i = JB + 1; i < NB; ++i) a[i][JB] = -acc[i];
     }
   });
   if (bad && d.flag) atomicOr(d.flag, FLAG_CHOL);
