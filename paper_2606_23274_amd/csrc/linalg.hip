@@ -961,8 +961,9 @@ __device__ __forceinline__ void static_for(F&& f) {
 // column JB (the panel: A(r, c) -= L(r, jj) L(c, jj), c in the block) and
 // the X entries of block row JB (X(r, c) -= L(r, jj) X(jj, c), X(jj, c) =
 // partial / L(jj, jj), X(r, jj) = -L(r, jj) / L(jj, jj)); the col owner
-// records L(r, jj) for the rows of later blocks in LDS (PT).  At the end of the block, with the block row JB
-// of X (XB) published, every thread applies the rank-G updates of the block:
+// records L(r, jj) for the rows of later blocks in LDS (PT).  At the end of
+// the block, with block row JB of X (XB) published, every thread applies the
+// rank-G updates of the block:
 //   A(r, c) -= sum_m L(r, m) L(c, m)            r, c in later blocks (r >= c)
 //   X(r, c) -= sum_m L(r, m) X(m, c)            r in later blocks, c < G JB
 //   X(r, c)  = -sum_m L(r, m) X(m, c)           r in later blocks, c in block JB
