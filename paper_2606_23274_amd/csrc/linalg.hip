@@ -961,7 +961,8 @@ __device__ __forceinline__ void static_for(F&& f) {
 // column JB (the panel: A(r, c) -= L(r, jj) L(c, jj), c in the block) and
 // the X entries of block row JB (X(r, c) -= L(r, jj) X(jj, c), X(jj, c) =
 // partial / L(jj, jj), X(r, jj) = -L(r, jj) / L(jj, jj)); the col owner
-// records L(r, jj) for the rows of later blocks in LDS (PT).  At the end of
+// keeps 1 / L(jj, jj), and L(r, jj) for the rows of later blocks goes to LDS
+// (PT) at the end of the block, all columns at once.  At the end of
 // the block, with block row JB of X (XB) published, every thread applies the
 // rank-G updates of the block:
 //   A(r, c) -= sum_m L(r, m) L(c, m)            r, c in later blocks (r >= c)
@@ -988,6 +989,7 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
       a[i][j] = (r < k && c < k) ? gload_ptr(d.G)[(long long)r * d.ldg + c] : (r == c ? 1.0 : 0.0);
     }
   bool bad = false;
+  double own_invs = 0.0;  // 1 / L(c, c) of this lane's column c = tc + G JB
   static_for<0, NB>([&](auto jb_) {
     constexpr int JB = decltype(jb_)::value;
     const int jend = min(k, G * JB + G);
@@ -1026,21 +1028,18 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
         const double xc = (r == jj) ? invs : -l * invs;
         a[JB][JB] = (col_owner && r >= jj) ? xc : a[JB][JB];
       }
-      double lv[NB];
 #pragma unroll
-      for (int i = JB + 1; i < NB; ++i) {  // rows of later blocks: the panel
-        lv[i] = av[i] * invs;
-        a[i][JB] -= lv[i] * lc;
-      }
-      if (col_owner) {  // L(r, jj) of the later rows to PT (stores only, after all reads)
-#pragma unroll
-        for (int i = JB + 1; i < NB; ++i) PT[jt][tr + G * i] = lv[i];
-      }
+      for (int i = JB + 1; i < NB; ++i) a[i][JB] -= (av[i] * invs) * lc;  // rows of later blocks: the panel
+      // column jj of the later rows stays as it is from here on: the owner
+      // keeps 1 / L(jj, jj) and forms L(r, jj) for PT at the end of the block
+      own_invs = col_owner ? invs : own_invs;
 #pragma unroll
       for (int j = 0; j <= JB; ++j)
         a[JB][j] = (row_owner && tc + G * j < jj) ? a[JB][j] * invs : a[JB][j];
     }
     if (G * JB + G < k) {  // uniform: a later block holds rows of the matrix
+#pragma unroll
+      for (int i = JB + 1; i < NB; ++i) PT[tc][tr + G * i] = a[i][JB] * own_invs;
 #pragma unroll
       for (int j = 0; j <= JB; ++j) XB[tr][tc + G * j] = (tc + G * j <= G * JB + tr) ? a[JB][j] : 0.0;
       __syncthreads();
