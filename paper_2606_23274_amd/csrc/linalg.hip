@@ -1189,15 +1189,20 @@ __global__ void __launch_bounds__(G * G) sytrd_reg_kernel(const EigDesc* __restr
       double wc[NB];
 #pragma unroll
       for (int j = JB; j < NB; ++j) wc[j] = fma(K, vc[j], w[tc + G * j]);
-#pragma unroll
-      for (int i = JB; i < NB; ++i) {
+      // v and w on this thread's rows: lane tc of a 16-lane row reads row
+      // tr + G (JB + tc) once and the row shares it by DPP broadcast, instead
+      // of every lane reading every row from LDS
+      const int rd = tr + G * (JB + min(tc, NB - 1 - JB));
+      const double vd = v[rd], wd = w[rd];
+      static_for<JB, NB>([&](auto i_) {
+        constexpr int i = decltype(i_)::value;
         const int r = tr + G * i;
-        const double x = v[r] * scal;
+        const double x = dpp_d<0x150 + (i - JB)>(vd) * scal;  // row_newbcast
         const double vi = r == jj + 1 ? 1.0 : x;
-        const double wi = fma(K, vi, w[r]);
+        const double wi = fma(K, vi, dpp_d<0x150 + (i - JB)>(wd));
 #pragma unroll
         for (int j = JB; j < NB; ++j) a[i][j] -= vi * wc[j] + wi * vc[j];
-      }
+      });
     }
   });
   if (k >= 2) {
