@@ -59,13 +59,15 @@ def test_gemm_against_numpy(hooks, kind, akc, bkc, M, N, K, tile, splits):
 
 
 # sizes on both sides of every register-kernel boundary (k = 32, 64, 96,
-# 128, 144, 160, 176) and of every panel width of the global-memory
-# reduction (32 up to k = 290, 16 up to 570, then 8)
+# 128, 144, 160, 176), of every panel width of the global-memory reduction
+# (32 up to k = 290, 16 up to 570, then 8, unblocked beyond 1100) and of the
+# one-wave twisted-vector kernel (k <= 1600; one thread per vector beyond)
 @pytest.mark.parametrize("k,r", [(1, 1), (2, 2), (5, 3), (17, 17), (32, 20), (33, 33), (64, 64),
                                  (65, 40), (96, 96), (97, 90), (128, 128), (129, 100), (144, 128),
                                  (145, 145), (160, 128), (161, 150), (176, 176), (177, 160),
                                  (199, 199), (200, 150), (201, 180),
-                                 (272, 256), (290, 256), (300, 200), (301, 250), (600, 100)])
+                                 (272, 256), (290, 256), (300, 200), (301, 250), (600, 100),
+                                 (1200, 64), (1700, 48)])
 def test_eig_against_numpy(hooks, k, r):
     from tests.gpu_util import dev, ptr
     rng = np.random.default_rng(k)
