@@ -1,14 +1,19 @@
 // FP64 small dense linear algebra of the two-site update (see linalg.hpp).
 //
-// Cholesky:   one workgroup per matrix, right-looking, the working copy packed
-//             (lower triangle) in LDS when it fits, else in the output buffer.
+// Cholesky:   one workgroup per matrix; up to k = 176 the matrix and its
+//             inverse stay in registers (blocked, right-looking), beyond that
+//             the working copy is packed (lower triangle) in LDS when it fits,
+//             else kept in the output buffer.
 // TRSM:       one wave per row of X; the row lives in registers and the
 //             right-looking substitution needs one broadcast per column.
-// Eigenpairs: Householder tridiagonalization in one workgroup (packed in LDS
-//             when it fits), then per eigenvalue: bisection on Sturm counts
-//             (a workgroup evaluates 256 shifts per round), an eigenvector of
-//             the tridiagonal from its twisted factorization (one thread per
-//             eigenvalue), and the reflectors applied back in column blocks.
+// Eigenpairs: Householder tridiagonalization in one workgroup (in registers
+//             up to k = 176, with Q^T then formed row by row; in panels with
+//             GPU-wide GEMM updates beyond), then per eigenvalue: bisection on
+//             Sturm counts (a workgroup evaluates 256 shifts per round, or
+//             eight lanes 8 when there are many eigenvalues), an eigenvector
+//             of the tridiagonal from its twisted factorization (one wave per
+//             eigenvalue), and the reflectors applied back in column blocks
+//             (the register path forms Z = Q X with a GEMM instead).
 #include <type_traits>
 #include <algorithm>
 #include <cfloat>
@@ -1148,7 +1153,7 @@ __global__ void __launch_bounds__(G * G) sytrd_reg_kernel(const EigDesc* __restr
         tau = fma(fabs(alpha), rs, 1.0);
         scal = sg * rcp_nr(fabs(alpha) + nrm);
       }
-      // the reflector (v(jj+1) = 1) and tau for the back-accumulation
+      // the reflector (v(jj+1) = 1) and tau for the formation of Q^T
       if ((int)threadIdx.x < k) {
         const int t = threadIdx.x;
         const double x = v[t] * scal;
