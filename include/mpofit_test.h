@@ -17,8 +17,9 @@ extern "C" {
 /* C[M x N] = alpha * op(A) op(B) (+ C if beta), through the grouped MFMA GEMM.
    mode: 0 FP64, 1 FP32, 2 BF16; ta/tb/tc: 0 FP64, 1 FP32 element types;
    a_kcontig: A(m,k) at m*lda+k (1) or k*lda+m (0); b_kcontig: B(k,n) at
-   n*ldb+k (1) or k*ldb+n (0); C(m,n) at m*ldc+n; tile 0 (64x64) or 1
-   (128x128, FP32/BF16); splits >= 1 forces that many K chunks. */
+   n*ldb+k (1) or k*ldb+n (0); C(m,n) at m*ldc+n; tile 0 (64x64), 1
+   (128x128, FP32/BF16) or 2 (64x64 with half-depth K slabs); splits >= 1
+   forces that many K chunks. */
 mpo_status mpo_test_gemm(int mode, int ta, int tb, int tc, int a_kcontig, int b_kcontig, int tile,
                          int M, int N, int K, const void* A, int lda, const void* B, int ldb,
                          void* Cm, int ldc, double alpha, int beta, int splits, void* workspace,
