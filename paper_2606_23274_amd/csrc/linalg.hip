@@ -957,31 +957,33 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // G = L L^T (Cholesky, L lower) and R^{-1} = (L^{-1})^T written row-major
-// (upper triangular, zeros below), in one pass over the columns, as a
-// right-looking blocked Cholesky with block size G on the register layout
-// (thread (tr, tc) holds A(tr + G i, tc + G j)).  X = L^{-1} overwrites L in
-// place: row jj of X only mixes columns <= jj, whose L entries no later step
-// reads.  Step jj of block JB publishes column jj (below the diagonal, the
-// pivot apart) and row jj of X through one barrier, then updates only block
-// column JB (the panel: A(r, c) -= L(r, jj) L(c, jj), c in the block) and
-// the X entries of block row JB (X(r, c) -= L(r, jj) X(jj, c), X(jj, c) =
-// partial / L(jj, jj), X(r, jj) = -L(r, jj) / L(jj, jj)); the col owner
-// keeps 1 / L(jj, jj), and L(r, jj) for the rows of later blocks goes to LDS
-// (PT) at the end of the block, all columns at once.  At the end of
-// the block, with block row JB of X (XB) published, every thread applies the
-// rank-G updates of the block:
-//   A(r, c) -= sum_m L(r, m) L(c, m)            r, c in later blocks (r >= c)
-//   X(r, c) -= sum_m L(r, m) X(m, c)            r in later blocks, c < G JB
-//   X(r, c)  = -sum_m L(r, m) X(m, c)           r in later blocks, c in block JB
-// (m over the block's columns, X(m, c) = 0 for m < c), so a step carries
-// about NB multiply-adds per thread instead of NB^2.
+// (upper triangular, zeros below), as a right-looking blocked Cholesky with
+// block size G on the register layout (thread (tr, tc) holds A(tr + G i,
+// tc + G j)), X = L^{-1} overwriting L in place.  Step jj of block JB
+// publishes column jj (below the diagonal, the pivot apart) through one
+// barrier and updates only block column JB (the panel: A(r, c) -= L(r, jj)
+// L(c, jj), c in the block); the owner of column jj keeps 1 / L(jj, jj).
+// At the end of the block:
+//   - L of the diagonal block and its inverse Linv (forward substitution of
+//     each unit column),
+//   - block row JB of X: X_J,<J = Linv S_J with S_J the partial sums left by
+//     the earlier blocks, and X_JJ = Linv,
+//   - with L(r, c) of the later rows (PT) and that block row (XB) in LDS, the
+//     rank-G updates of the later rows:
+//       A(r, c) -= sum_m L(r, m) L(c, m)        r, c in later blocks (r >= c)
+//       X(r, c) -= sum_m L(r, m) X(m, c)        c < G JB
+//       X(r, c)  = -sum_m L(r, m) X(m, c)       c in block JB
+//     (m over the block's columns, X(m, c) = 0 for m < c),
+// so a step carries about NB multiply-adds and NB + 2 LDS reads per thread.
 template <int NB, int G>
 __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __restrict__ descs) {
   __shared__ double colb[2][G * NB];
-  __shared__ double rowb[2][G * NB];
   __shared__ double dgb[2];
   __shared__ double PT[G][G * NB];  // PT[m][r] = L(r, G JB + m), rows of later blocks
-  __shared__ double XB[G][G * NB];  // XB[m][c] = X(G JB + m, c), c < G (JB + 1)
+  __shared__ double XB[G][G * NB];  // partial block row S_J, then X(G JB + m, c), c < G (JB + 1)
+  __shared__ double LJ[G][G + 1];   // L of the diagonal block
+  __shared__ double LI[G][G];       // its inverse
+  __shared__ double invsJ[G];       // 1 / L(m, m) of the block
   const CholDesc d = descs[blockIdx.x];
   const int k = d.k;
   const int tr = threadIdx.x / G, tc = threadIdx.x % G;
@@ -998,6 +1000,7 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
   static_for<0, NB>([&](auto jb_) {
     constexpr int JB = decltype(jb_)::value;
     const int jend = min(k, G * JB + G);
+    if (G * JB >= k) return;  // uniform
     for (int jj = G * JB; jj < jend; ++jj) {
       const int jt = jj % G, buf = jj & 1;
       if (tc == jt) {  // column jj below the diagonal; the diagonal apart
@@ -1005,17 +1008,11 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
         for (int i = JB; i < NB; ++i) colb[buf][tr + G * i] = (tr + G * i > jj) ? a[i][JB] : 0.0;
         if (tr == jt) dgb[buf] = a[JB][JB];
       }
-      if (tr == jt) {  // row jj of X (columns < jj)
-#pragma unroll
-        for (int j = 0; j <= JB; ++j) rowb[buf][tc + G * j] = (tc + G * j < jj) ? a[JB][j] : 0.0;
-      }
       __syncthreads();
       // every broadcast value is read before the pivot is used
       const double djj = dgb[buf];
       const double cc = colb[buf][tc + G * JB];  // zero unless tc + G JB > jj
-      double xr[JB + 1], av[NB];
-#pragma unroll
-      for (int j = 0; j <= JB; ++j) xr[j] = rowb[buf][tc + G * j];
+      double av[NB];
 #pragma unroll
       for (int i = JB; i < NB; ++i) av[i] = colb[buf][tr + G * i];
       const bool ok = djj > 0.0 && djj < INFINITY;
@@ -1023,25 +1020,52 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
       const double rs = rsq_nr(djj);
       const double invs = ok ? rs : 0.0;  // 1 / L(jj, jj)
       const double lc = cc * invs;        // L(c, jj)
-      const bool col_owner = tc == jt, row_owner = tr == jt;
-      {  // rows of block JB: the panel, the X row update and X's column jj
-        const int r = tr + G * JB;
-        const double l = av[JB] * invs;  // L(r, jj)
-        a[JB][JB] -= l * lc;
 #pragma unroll
-        for (int j = 0; j <= JB; ++j) a[JB][j] -= l * (xr[j] * invs);  // X(jj, c) = xr / L(jj, jj)
-        const double xc = (r == jj) ? invs : -l * invs;
-        a[JB][JB] = (col_owner && r >= jj) ? xc : a[JB][JB];
+      for (int i = JB; i < NB; ++i) a[i][JB] -= (av[i] * invs) * lc;  // the panel
+      // column jj stays as it is from here on: its owner keeps 1 / L(jj, jj)
+      // and forms L(r, jj) at the end of the block
+      own_invs = tc == jt ? invs : own_invs;
+    }
+    // the diagonal block's L and, by forward substitution of each unit
+    // column (lanes of row group 0), its inverse
+    const int mv = jend - G * JB;
+    LJ[tr][tc] = (tr >= tc) ? a[JB][JB] * own_invs : 0.0;
+    if (tr == 0) invsJ[tc] = own_invs;
+    __syncthreads();
+    if (tr == 0) {
+      double rhs[G];
+#pragma unroll
+      for (int m = 0; m < G; ++m) rhs[m] = (m == tc) ? 1.0 : 0.0;
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        const double x = (t < mv) ? rhs[t] * invsJ[t] : 0.0;
+        LI[t][tc] = x;
+#pragma unroll
+        for (int m = t + 1; m < G; ++m) rhs[m] = fma(-LJ[m][t], x, rhs[m]);
+      }
+    }
+    if constexpr (JB > 0) {
+#pragma unroll
+      for (int j = 0; j < JB; ++j) XB[tr][tc + G * j] = a[JB][j];  // S_J
+    }
+    __syncthreads();
+    // block row JB of X: X_J,<J = Linv S_J, X_JJ = Linv
+    if constexpr (JB > 0) {
+      double sx[JB];
+#pragma unroll
+      for (int j = 0; j < JB; ++j) sx[j] = 0.0;
+#pragma unroll 2
+      for (int m = 0; m < G; ++m) {
+        const double lim = LI[tr][m];
+#pragma unroll
+        for (int j = 0; j < JB; ++j) sx[j] = fma(lim, XB[m][tc + G * j], sx[j]);
       }
 #pragma unroll
-      for (int i = JB + 1; i < NB; ++i) a[i][JB] -= (av[i] * invs) * lc;  // rows of later blocks: the panel
-      // column jj of the later rows stays as it is from here on: the owner
-      // keeps 1 / L(jj, jj) and forms L(r, jj) for PT at the end of the block
-      own_invs = col_owner ? invs : own_invs;
-#pragma unroll
-      for (int j = 0; j <= JB; ++j)
-        a[JB][j] = (row_owner && tc + G * j < jj) ? a[JB][j] * invs : a[JB][j];
+      for (int j = 0; j < JB; ++j) a[JB][j] = sx[j];
     }
+    const double li = LI[tr][tc];
+    if (G * JB + G < k) __syncthreads();  // uniform: S_J read before XB is rewritten
+    a[JB][JB] = (tr >= tc) ? li : 0.0;
     if (G * JB + G < k) {  // uniform: a later block holds rows of the matrix
 #pragma unroll
       for (int i = JB + 1; i < NB; ++i) PT[tc][tr + G * i] = a[i][JB] * own_invs;
