@@ -89,6 +89,33 @@ def test_eig_against_numpy(hooks, k, r):
     assert np.abs(np.abs(np.sum(Z * V, axis=0)) - 1).max() < 1e-8
 
 
+# spectra of either sign: the multisection's first round is geometric below a
+# positive upper bound (with a point at 0 when the lower bound is negative)
+# and uniform when the upper bound is not positive
+@pytest.mark.parametrize("k,kind", [(40, "mixed"), (144, "mixed"), (40, "negative"), (144, "negative"),
+                                    (300, "mixed")])
+def test_eig_indefinite(hooks, k, kind):
+    from tests.gpu_util import dev, ptr
+    rng = np.random.default_rng(7 + k)
+    Q, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    lam = np.linspace(-1.0, 1.0, k) if kind == "mixed" else -np.linspace(1.0, 10.0, k)
+    H = (Q * lam) @ Q.T
+    H = 0.5 * (H + H.T)
+    r = k // 2
+    w, V = np.linalg.eigh(H)
+    w, V = w[::-1][:r], V[:, ::-1][:, :r]
+    Hd = dev(H)
+    ev = torch.zeros(r, dtype=torch.float64, device="cuda:0")
+    Z = torch.zeros((k, r), dtype=torch.float64, device="cuda:0")
+    _lib.check(hooks.lib.mpo_test_eig(ptr(Hd), k, r, ptr(ev), ptr(Z), *hooks.args()))
+    ev, Z = ev.cpu().numpy(), Z.cpu().numpy()
+    nrm = np.abs(lam).max()
+    assert np.abs(ev - w).max() <= 1e-13 * nrm
+    assert np.linalg.norm(H @ Z - Z * ev) / nrm < 1e-12
+    assert np.abs(Z.T @ Z - np.eye(r)).max() < 1e-10
+    assert np.abs(np.abs(np.sum(Z * V, axis=0)) - 1).max() < 1e-8
+
+
 # several problems per launch: the batched configuration of the eigen
 # kernels (eight-lane multisection once problems x eigenvalues >= 2048, the
 # register or the global-memory tridiagonalization by size), including a
