@@ -1,0 +1,46 @@
+"""The serial randomized fit at the headline configuration's full size:
+L=40, d=2, chi_A=chi_B=64 with exp(-k/6) bond weights, chi_C=128, sketch
+p=16 (Philox seed 0), the size and launch configuration the benchmark times.
+
+The FP64 oracle's first sweep (about 6 s on 16 host cores) is the reference:
+the device's first sweep is compared element by element through the exported
+train, in FP64 to 1e-10 and in FP32 contractions to 1e-5 (relative Frobenius
+distance of the MPO C, all cores at once), with the same bond dimensions."""
+import numpy as np
+import pytest
+
+from oracle import fit as ofit
+from oracle import mpo
+from synth import make_pair
+
+pytestmark = pytest.mark.gpu
+
+L, D, CHI, CHI_C, P, SEED = 40, 2, 64, 128, 16, 0
+
+
+@pytest.fixture(scope="module")
+def case():
+    A, B = make_pair(L, D, CHI, seed=SEED, decay=True)
+    ref = ofit.fit_serial(A, B, CHI_C, 1, sketch_p=P, seed=SEED)
+    return A, B, ref
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_first_sweep_full_size(case, precision, tol):
+    from paper_2606_23274_amd.api import FitContext, autotune
+    A, B, ref = case
+    # the benchmark's configuration: GEMM tiles and split counts from the autotuner
+    table = autotune([(A, B)], CHI_C, precision=precision, sketch_p=P, seed=SEED, reps=3)
+    ctx = FitContext([(A, B)], CHI_C, precision=precision, schedule="serial", sketch_p=P, seed=SEED,
+                     tuning=table)
+    try:
+        ctx.sweep(1)
+        C = ctx.export_numpy(0)
+        dims = ctx.bond_dims(0)
+    finally:
+        ctx.close()
+    assert dims == ref.bond_dims
+    assert all(np.isfinite(c).all() for c in C)
+    err = mpo.rel_diff(C, ref.C)
+    print(precision, "relative distance to the oracle", err)
+    assert err <= tol
