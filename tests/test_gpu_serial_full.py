@@ -4,8 +4,9 @@ p=16 (Philox seed 0), the size and launch configuration the benchmark times.
 
 The FP64 oracle's first sweep (about 6 s on 16 host cores) is the reference:
 the device's first sweep is compared element by element through the exported
-train, in FP64 to 1e-10 and in FP32 contractions to 1e-5 (relative Frobenius
-distance of the MPO C, all cores at once), with the same bond dimensions."""
+train, in FP64 to 1e-10, with FP32 contractions to 1e-5 and with split BF16 to
+3e-3 (relative Frobenius distance of the MPO C, all cores at once), with the
+same bond dimensions."""
 import numpy as np
 import pytest
 
@@ -25,7 +26,10 @@ def case():
     return A, B, ref
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+# split BF16 meets 3e-3; pure BF16 (about 3e-2 here, from the 2^-9 operand
+# rounding chained through the environments) is held to a regression bound
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 3e-3),
+                                           ("bf16", 5e-2)])
 def test_first_sweep_full_size(case, precision, tol):
     from paper_2606_23274_amd.api import FitContext, autotune
     A, B, ref = case
