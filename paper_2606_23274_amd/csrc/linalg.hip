@@ -7,13 +7,14 @@
 // TRSM:       one wave per row of X; the row lives in registers and the
 //             right-looking substitution needs one broadcast per column.
 // Eigenpairs: Householder tridiagonalization in one workgroup (in registers
-//             up to k = 176, with Q^T then formed row by row; in panels with
+//             up to k = 176; in panels with
 //             GPU-wide GEMM updates beyond), then per eigenvalue: bisection on
 //             Sturm counts (a workgroup evaluates 256 shifts per round, or
 //             eight lanes 8 when there are many eigenvalues), an eigenvector
 //             of the tridiagonal from its twisted factorization (one wave per
 //             eigenvalue), and the reflectors applied back in column blocks
-//             (the register path forms Z = Q X with a GEMM instead).
+//             (on the register path row by row, one wave per four
+//             eigenvectors).
 #include <type_traits>
 #include <algorithm>
 #include <cfloat>
@@ -1109,7 +1110,8 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
 
 // Householder tridiagonalization (same reflector convention as sytrd_kernel)
 // on the register-resident matrix; reflectors go to W.H (row j = v_j), tau
-// to W.tau, d and e to W.d, W.e; qt_rows_kernel then forms Q^T in W.V.
+// to W.tau, d and e to W.d, W.e; z_rows_kernel applies them to the
+// eigenvectors of the tridiagonal matrix.
 template <int NB, int G>
 __global__ void __launch_bounds__(G * G) sytrd_reg_kernel(const EigDesc* __restrict__ descs) {
   __shared__ double vb[2][G * NB], wb[2][G * NB];
@@ -1251,36 +1253,39 @@ __global__ void __launch_bounds__(G * G) sytrd_reg_kernel(const EigDesc* __restr
   }
 }
 
-// Q^T = H_{k-3} ... H_0 (register path), row by row: the rows of
-// M <- M H_j = M - tau_j (M v_j) v_j^T are independent, so a one-wave
-// workgroup takes 4 rows (lane (tr, tc) holds columns tc + 16 b, b < NB, of
-// row 4 blockIdx.x + tr) and applies every reflector without a barrier after
-// the taus are staged in LDS.  One wave per workgroup spreads the rows over
-// many CUs: the four rows of a wave read the same reflector entries, so the
-// vector-memory issue rate per CU, not the data volume, bounds the loads.
-// The reflectors (rows of W.H) are read from L2 four at a time into two
-// alternating register sets, the next four in flight while the current ones
-// are applied; the row products are DPP reductions over the 16 lanes of a row.  A column c >= k reads column 0
-// of the same reflector instead, which is zero (v_j vanishes on rows <= j),
-// so the loads need no mask.
+// Z = Q X (register path) as Z^T = X^T Q^T = X^T H_{k-3} ... H_0, row by
+// row: the rows of M <- M H_j = M - tau_j (M v_j) v_j^T are independent, so a
+// one-wave workgroup takes 4 rows of X^T (eigenvectors 4 blockIdx.x + tr of
+// the tridiagonal matrix; lane (tr, tc) holds entries tc + 16 b, b < NB) and
+// applies every reflector without a barrier after the taus are staged in
+// LDS, then writes its rows as columns of Z.  One wave per workgroup spreads
+// the rows over many CUs: the four rows of a wave read the same reflector
+// entries, so the vector-memory issue rate per CU, not the data volume,
+// bounds the loads.  The reflectors (rows of W.H) are read from L2 four at a
+// time into two alternating register sets, the next four in flight while the
+// current ones are applied; the row products are DPP reductions over the 16
+// lanes of a row.  A column c >= k reads column 0 of the same reflector
+// instead, which is zero (v_j vanishes on rows <= j), so the loads need no
+// mask.
 template <int NB>
-__global__ void __launch_bounds__(64) qt_rows_kernel(const EigDesc* __restrict__ descs) {
+__global__ void __launch_bounds__(64) z_rows_kernel(const EigDesc* __restrict__ descs) {
   constexpr int D = 4;
   const EigDesc dd = descs[blockIdx.y];
   const int k = dd.k;
-  if (4 * (int)blockIdx.x >= k) return;  // uniform
+  if (4 * (int)blockIdx.x >= dd.r) return;  // uniform
   EigWork W(dd.work, k, dd.r);
   __shared__ double s_tau[16 * NB];
   for (int t = threadIdx.x; t < k; t += 64) s_tau[t] = W.tau[t];
   __syncthreads();
   const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
-  const int r = 4 * blockIdx.x + tr;
+  const int r = 4 * blockIdx.x + tr;  // eigenvector (row of X^T)
+  const bool live = r < dd.r;
   double m[NB];
   unsigned off[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int c = tc + 16 * b;
-    m[b] = c == r ? 1.0 : 0.0;
+    m[b] = (live && c < k) ? W.X[(long long)c * dd.r + r] : 0.0;
     off[b] = c < k ? 8u * (unsigned)c : 0u;  // byte offsets
   }
   // reflectors j0, j0 - 1, ..., j0 - D + 1; one with j < 0 reads reflector
@@ -1322,11 +1327,11 @@ __global__ void __launch_bounds__(64) qt_rows_kernel(const EigDesc* __restrict__
     load(j0 - 2 * D, va, ta);
     apply(vb, tb);  // all taus zero once j0 - D < 0
   }
-  if (r < k) {
+  if (live) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int c = tc + 16 * b;
-      if (c < k) W.V[(long long)r * k + c] = m[b];
+      if (c < k) gstore_ptr(dd.Z)[(long long)c * dd.ldz + r] = m[b];
     }
   }
 }
@@ -1429,11 +1434,11 @@ struct RegSytrd {
     hipLaunchKernelGGL((sytrd_reg_kernel<NB, G>), dim3(n), dim3(G * G), 0, s, d);
   }
 };
-struct RegQt {
+struct RegZ {
   template <int NB, int G>
   static void go(const EigDesc* d, int n, hipStream_t s) {
-    static_assert(G == 16, "qt_rows_kernel takes 16 columns per row pass");
-    hipLaunchKernelGGL((qt_rows_kernel<NB>), dim3(4 * NB, n), dim3(64), 0, s, d);
+    static_assert(G == 16, "z_rows_kernel takes 16 columns per row pass");
+    hipLaunchKernelGGL((z_rows_kernel<NB>), dim3(4 * NB, n), dim3(64), 0, s, d);  // r <= k <= 16 NB
   }
 };
 template <class K, class D>
@@ -1453,8 +1458,6 @@ size_t eig_work_doubles(int k, int r) {
 
 int eig_panel_width(int max_k) { return max_k <= 290 ? 32 : max_k <= 570 ? 16 : max_k <= 1100 ? 8 : 0; }
 
-double* eig_work_qt(double* w, int k, int r) { (void)r; return w + 3 * (size_t)k; }
-double* eig_work_x(double* w, int k, int r) { (void)r; return w + 3 * (size_t)k + (size_t)k * k; }
 
 void launch_chol(const CholDesc* d, int n, int max_k, int inverse, hipStream_t s) {
   if (n <= 0) return;
@@ -1538,8 +1541,8 @@ void launch_eig(const EigDesc* d, const EigDesc* h, int n, int reg, int stage, h
     }
   }
   if (!(all || stage == 3)) return;
-  if (reg) {  // Q^T from the reflectors; the caller forms Z = Q X
-    launch_reg<RegQt>(d, n, max_k, s);
+  if (reg) {  // Z = Q X row by row from the reflectors
+    launch_reg<RegZ>(d, n, max_k, s);
     return;
   }
   // column blocks so that the block plus vectors fit in LDS

@@ -79,10 +79,6 @@ __host__ __device__ inline double* eig_work_h(double* w, int k, int r) {
 __host__ __device__ inline double* eig_work_panel(double* w, int k, int r) {
   return w + 3 * (size_t)k + 2 * (size_t)k * k + (size_t)k * r;
 }
-// Offsets inside the eigen work area: Q^T (k x k, row-major) of the
-// register path, and the k x r eigenvectors of the tridiagonal matrix.
-double* eig_work_qt(double* w, int k, int r);
-double* eig_work_x(double* w, int k, int r);
 
 // Largest k handled by the register-resident kernels.
 constexpr int kRegMax = 176;
@@ -94,9 +90,8 @@ void launch_trsm(const TrsmDesc* d, int n, int max_rows, hipStream_t s);
 // Runs the eigen pipeline: tridiagonalization (stage 0), bisection (1),
 // twisted-factorization eigenvectors (2), back-transformation (3); stage < 0
 // runs all of them.  With `reg` (every k <= kRegMax) the reduction keeps the
-// matrix in registers and stage 3 forms Q^T in the work area from the
-// reflectors; the caller then forms Z = Q X with a GEMM.  `h_descs` is the
-// host copy of `d`.
+// matrix in registers and stage 3 applies the reflectors to the rows of X^T
+// (Z^T = X^T Q^T).  `h_descs` is the host copy of `d`.
 void launch_eig(const EigDesc* d, const EigDesc* h_descs, int n, int reg, int stage, hipStream_t s);
 
 }  // namespace mpofit

@@ -292,10 +292,11 @@ void add_eig(Program& P, const SplitBuf& sb, const std::vector<EigDesc>& ed, boo
              const char* prefix) {
   if (ed.empty()) return;
   const size_t off = P.push(ed);
-  double ftri = 0;
+  double ftri = 0, fback = 0;
   int max_k = 0;
   for (auto& e : ed) {
     ftri += (4.0 / 3.0) * e.k * (double)e.k * e.k;
+    fback += 4.0 * e.k * (double)e.k * e.r;
     max_k = std::max(max_k, e.k);
   }
   const bool init = std::string(prefix) == "init";
@@ -335,8 +336,8 @@ void add_eig(Program& P, const SplitBuf& sb, const std::vector<EigDesc>& ed, boo
       add_gemm(P, sb, Mode::F64, upd, init ? "init" : names[0], 0.0);
     }
   }
-  // with `reg`, stage 3 forms Q^T from the reflectors ((4/3) k^3 flops)
-  for (int st = nb > 0 ? 1 : 0; st < 4; ++st) stage(st, names[st], st == 0 || (st == 3 && reg) ? ftri : 0.0);
+  // stage 3 applies the reflectors to the r eigenvectors (4 k^2 r flops)
+  for (int st = nb > 0 ? 1 : 0; st < 4; ++st) stage(st, names[st], st == 0 ? ftri : st == 3 ? fback : 0.0);
 }
 
 // ------------------------------------------------------------------ state
@@ -995,7 +996,7 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
   std::vector<CholQRJob> qr;
   std::vector<EigDesc> ed;
   std::vector<SvalDesc> sv;
-  std::vector<GemmJob> zq;
+  bool reg = true;  // every eigenproblem on the register path
   double fth = 0, fsk = 0;
   long long maxom = 1;
   int maxr = 1;
@@ -1028,9 +1029,7 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
                            out64(B.H, b.n)});
     }
     ed.push_back(EigDesc{B.H, b.k, b.k, b.r, B.evals, B.Z, b.r, B.eigw, X.flag});
-    if (b.k <= kRegMax)  // register path: Z = Q X afterwards
-      zq.push_back(GemmJob{b.k, b.r, b.k, op64(eig_work_qt(B.eigw, b.k, b.r), false, b.k),
-                           op64(eig_work_x(B.eigw, b.k, b.r), false, b.r), out64(B.Z, b.r)});
+    reg = reg && b.k <= kRegMax;
     sv.push_back(SvalDesc{B.evals, B.S, b.r, halfstep ? 1 : 0, X.flag, B.keep, X.flag + 2});
     maxr = std::max(maxr, b.r);
   }
@@ -1044,10 +1043,7 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
   for (auto& h : hj) (h.A.t == DType::F64 ? h64 : hw).push_back(h);
   add_gemm(P, X.sb, Mode::F64, h64, "gram", 0);
   add_gemm(P, X.sb, Mode::F64, hw, "gram", 0);
-  const bool reg = zq.size() == ed.size();
-  if (!reg) zq.clear();
   add_eig(P, X.sb, ed, reg, "eig");
-  add_gemm(P, X.sb, Mode::F64, zq, "eig_backtransform", 0);
   add_simple(P, LK::Sval, sv, maxr, "svals");
 }
 
@@ -1193,10 +1189,6 @@ void rec_inverse_canonical(Ctx& X, Program& P, PairState& S) {
                                           out64(X.iH, q)}}, "init", 0);
     const bool reg = q <= kRegMax;
     add_eig(P, X.sb, {EigDesc{X.iH, q, q, q, X.iEv, X.iZ, q, X.iEw, X.flag}}, reg, "init");
-    if (reg)
-      add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(eig_work_qt(X.iEw, q, q), false, q),
-                                            op64(eig_work_x(X.iEw, q, q), false, q), out64(X.iZ, q)}},
-               "init", 0);
     add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(X.iRt, true, q), op64(X.iZ, false, q),
                                           out64(X.iG, q)}}, "init", 0);
     {
@@ -2545,10 +2537,6 @@ mpo_status mpo_test_eig(const double* H, int k, int r, double* evals, double* Z,
     Program P;
     const bool reg = k <= kRegMax;
     add_eig(P, T.X.sb, {EigDesc{H, k, k, r, evals, Z, r, w, T.X.flag}}, reg, "eig");
-    if (reg)
-      add_gemm(P, T.X.sb, Mode::F64, {GemmJob{k, r, k, op64(eig_work_qt(w, k, r), false, k),
-                                              op64(eig_work_x(w, k, r), false, r), out64(Z, r)}},
-               "eig_backtransform", 0);
     T.go(P);
     check_flags(T.X);
   });
@@ -2561,20 +2549,15 @@ mpo_status mpo_test_eig_batch(const double* H, int n, int k, int r, double* eval
     TestEnv T(workspace, ws_bytes, stream);
     const bool reg = k <= kRegMax;
     std::vector<EigDesc> ed;
-    std::vector<GemmJob> bt;
     for (int i = 0; i < n; ++i) {
       double* w = T.cv.take<double>(eig_work_doubles(k, r));
       const double* Hi = H + (size_t)i * k * k;
       double* Zi = Z + (size_t)i * k * r;
       ed.push_back(EigDesc{Hi, k, k, r, evals + (size_t)i * r, Zi, r, w, T.X.flag});
-      if (reg)
-        bt.push_back(GemmJob{k, r, k, op64(eig_work_qt(w, k, r), false, k),
-                             op64(eig_work_x(w, k, r), false, r), out64(Zi, r)});
     }
     if (T.cv.off > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "test workspace too small"};
     Program P;
     add_eig(P, T.X.sb, ed, reg, "eig");
-    if (reg) add_gemm(P, T.X.sb, Mode::F64, bt, "eig_backtransform", 0);
     T.go(P);
     check_flags(T.X);
   });
