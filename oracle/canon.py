@@ -77,7 +77,12 @@ def right_orthogonalize(cores):
     return cores
 
 
-INV_TRUNC = 1e-12
+# Relative cut of singular values (truncation before inversion, Sec. 2.3.1,
+# and the drop rule of the two-site update): values at or below
+# INV_TRUNC * sigma_1 are set to zero.  At this level an FP64 singular
+# value decomposition still fixes the vectors of the smallest kept values to
+# about 1e-10, and 1/sigma amplifies rounding by at most 1e6.
+INV_TRUNC = 1e-6
 
 
 def truncate_inverse(U, S, Vt, thresh: float = INV_TRUNC):

@@ -15,6 +15,13 @@ Conventions (shared with the GPU path as definitions, not as code):
     plain SVD;
   * singular vectors are sign-fixed (largest-magnitude entry of each U column
     positive, Vt rows flipped along), Q of the sketch has R_jj >= 0;
+  * of the r kept singular values, those at or below DROP * sigma_1 are
+    dropped: the value and its singular vectors become zero and the bond keeps
+    its size (zero padding).  Sec. 2.3.4 truncates by a bond cap and a
+    tolerance; a relative cut at this level is the reading taken for values the
+    GPU's FP64 factorization cannot resolve (its Gram eigenproblem resolves
+    sigma down to about 1e-8 sigma_1), and in the inverse gauge it is the
+    truncation before inversion that Sec. 2.3.1 allows;
   * tau > 0 truncation keeps the smallest r with
     (sum_{j>r} sigma_j^2)^(1/2) <= (tau / L) ||sigma||_2 (Sec. 2.3.4).
 
@@ -35,7 +42,7 @@ import numpy as np
 from . import canon
 from .philox import gaussian_matrix
 
-GUARD = 1e-14
+DROP = canon.INV_TRUNC
 
 
 def ext_left(Lprev, A, B):
@@ -120,8 +127,12 @@ def factorize(M, chi_max, sketch_p, rank_cap, omega, tau=0.0, L=1):
     U, Sr, Vt = U[:, :r], S[:r], Vt[:r]
     s = canon.sign_fix_columns(U)
     U, Vt = U * s[None, :], Vt * s[:, None]
-    n_guard = int(np.sum(Sr <= GUARD * Sr[0]))
-    return Factor(U, Sr, Vt, k, gap, n_guard, S)
+    keep = Sr > DROP * Sr[0]
+    U = np.where(keep[None, :], U, 0.0)
+    Vt = np.where(keep[:, None], Vt, 0.0)
+    Sr = np.where(keep, Sr, 0.0)
+    n_drop = int(np.sum(~keep))
+    return Factor(U, Sr, Vt, k, gap, n_drop, S)
 
 
 @dataclass
@@ -145,7 +156,7 @@ def _preprocess(A, B):
 
 
 def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
-               on_update=None, C_init=None):
+               on_update=None, C_init=None, first_sweep=0):
     """Alg. 5 with the site-canonical update of Alg. 3.
 
     Preprocessing left-orthogonalizes A and B and splits off their norms; the
@@ -154,20 +165,35 @@ def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
     pass of L-1 updates (the first backward update repeats the last forward
     bond with a fresh Omega).  Omega of sweep i at bond l (1-based) is the
     Philox stream (pair, i, l).  ``on_update(sweep, l, C_scaled)`` is called
-    after each update."""
+    after each update.
+
+    ``first_sweep`` = s resumes a fit as if s sweeps had been run: the sweep
+    indices (direction and Philox stream) are s, s+1, ...; the initial guess
+    is right-orthogonalized with all right environments precomputed when
+    sweep s runs forward (s even), and left-orthogonalized with all left
+    environments precomputed when it runs backward (s odd).  From the result
+    of the first s sweeps, which is already in that form up to rounding, this
+    continues the same fit."""
     L = len(A)
     A1, B1, nu, caps = _preprocess(A, B)
-    C = canon.right_orthogonalize(A1 if C_init is None else C_init)
+    guess = A1 if C_init is None else C_init
     ones = np.ones((1, 1, 1))
     Lenv = [None] * (L + 1)
     Renv = [None] * (L + 2)
     Lenv[0] = ones
     Renv[L + 1] = ones
     # environments use 1-based site labels: site l is index l-1 in the lists
-    for l in range(L, 2, -1):
-        Renv[l] = env_right(Renv[l + 1], C[l - 1], A1[l - 1], B1[l - 1])
+    if first_sweep % 2 == 0:
+        C = canon.right_orthogonalize(guess)
+        for l in range(L, 2, -1):
+            Renv[l] = env_right(Renv[l + 1], C[l - 1], A1[l - 1], B1[l - 1])
+    else:
+        C, cnorm = canon.left_orthogonalize(guess)
+        C[-1] = C[-1] * cnorm
+        for l in range(1, L - 1):
+            Lenv[l] = env_left(Lenv[l - 1], C[l - 1], A1[l - 1], B1[l - 1])
     min_gap, n_guard, ks = 1.0, 0, []
-    for sweep in range(n_sweeps):
+    for sweep in range(first_sweep, first_sweep + n_sweeps):
         fwd = sweep % 2 == 0
         bonds = range(1, L) if fwd else range(L - 1, 0, -1)
         for l in bonds:
@@ -199,12 +225,13 @@ def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
     out = [c.copy() for c in C]
     out[0] = out[0] * nu
     dims = [1] + [c.shape[3] for c in C]
-    centre = L - 1 if n_sweeps % 2 == 1 else 0
+    last = first_sweep + n_sweeps - 1
+    centre = (L - 1 if last % 2 == 0 else 0) if n_sweeps > 0 else (0 if first_sweep % 2 == 0 else L - 1)
     return FitResult(out, nu, dims, min_gap, n_guard, ks, C_norm=[c.copy() for c in C], centre=centre)
 
 
 def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
-                 on_half_step=None, C_init=None):
+                 on_half_step=None, C_init=None, first_sweep=0, on_bond=None):
     """Single-device limit of the parallel fit in inverse canonical form
     (Sec. 4, Alg. 4 and Alg. 6 with every sub-TT two sites long): half-step q
     updates every bond l with l = 1 (mod 2) for q = 0 and l = 0 (mod 2) for
@@ -214,8 +241,12 @@ def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
     Psi_l = U S, Psi_{l+1} = S V^T,
     Y_l = S^{-1} (Alg. 4) and rebuilds L_l from Psi_l Y_l = U and R_{l+1}
     from Y_l Psi_{l+1} = V^T.  Omega of half-step q of sweep i at bond l is the
-    Philox stream (pair, 2 i + q, l).  The result is merged as C_l = Psi_l Y_l,
-    C_L = Psi_L (Sec. 4.7)."""
+    Philox stream (pair, 2 i + q, l); ``first_sweep`` offsets i.  The result
+    is merged as C_l = Psi_l Y_l, C_L = Psi_L (Sec. 4.7).
+
+    ``on_bond(sweep, q, l, M, factor, Psi0, Y0)`` sees every update: the
+    two-site matrix, its factorization and the train (Psi, Y) as it stood at
+    the half-step's start."""
     L = len(A)
     A1, B1, nu, caps = _preprocess(A, B)
     C0 = canon.right_orthogonalize(A1 if C_init is None else C_init)
@@ -232,9 +263,12 @@ def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
         Cl = Y[l - 2][:, None, None, None] * Psi[l - 1]
         Renv[l] = env_right(Renv[l + 1], Cl, A1[l - 1], B1[l - 1])
     min_gap, ks = 1.0, []
-    for sweep in range(n_sweeps):
+    for sweep in range(first_sweep, first_sweep + n_sweeps):
         for q in (0, 1):
             bonds = [l for l in range(1, L) if (l % 2 == 1) == (q == 0)]
+            if on_bond is not None:
+                Psi0 = [p.copy() for p in Psi]
+                Y0 = [y.copy() for y in Y]
             facs = {}
             for l in bonds:
                 M = two_site_matrix(Lenv[l - 1], A1[l - 1], B1[l - 1], A1[l], B1[l], Renv[l + 2])
@@ -242,6 +276,8 @@ def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
                     M, chi_max, sketch_p, caps[l - 1],
                     lambda m, k, l=l, st=2 * sweep + q: gaussian_matrix(m, k, seed, pair, st, l),
                     tau, L)
+                if on_bond is not None:
+                    on_bond(sweep, q, l, M, facs[l], Psi0, Y0)
             for l in bonds:
                 f = facs[l]
                 cl = Psi[l - 1].shape[0]

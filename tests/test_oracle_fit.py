@@ -246,3 +246,189 @@ def test_initial_guess_fixed_point():
     e8 = mpo.fit_error_dense(A, B, r8.C)
     assert mpo.fit_error_dense(A, B, r.C) <= e8 + 1e-12
     assert mpo.rel_diff(r.C, r8.C) <= 10 * mpo.rel_diff(r9.C, r8.C) + 1e-12
+
+
+# ---------------------------------------------------------------- resume
+@pytest.mark.parametrize("sketch_p", [-1, 3])
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_resume_continues_the_fit(s, sketch_p):
+    """first_sweep = s started from the result of s sweeps reproduces sweep
+    s + 1 of the uninterrupted fit (Alg. 5): after a forward sweep C is left
+    canonical and after a backward one right canonical, so the QR / RQ
+    sweep of the resumed start leaves every core in place (R = I), and the
+    Philox stream of sweep s is drawn again."""
+    A, B = make_pair(9, 2, 4, seed=21, decay=True)
+    rs = fit.fit_serial(A, B, 6, s, sketch_p=sketch_p, seed=5)
+    r_cont = fit.fit_serial(A, B, 6, s + 1, sketch_p=sketch_p, seed=5)
+    r_res = fit.fit_serial(A, B, 6, 1, sketch_p=sketch_p, seed=5, C_init=rs.C, first_sweep=s)
+    assert r_res.bond_dims == r_cont.bond_dims
+    assert mpo.rel_diff(r_res.C, r_cont.C) < 1e-12
+    assert r_res.centre == r_cont.centre
+
+
+def test_resume_stream_matters():
+    """The resumed sweep draws the Philox stream of its own index: the same
+    start with another first_sweep of the same direction differs."""
+    A, B = make_pair(9, 2, 4, seed=21, decay=True)
+    rs = fit.fit_serial(A, B, 6, 2, sketch_p=3, seed=5)
+    r2 = fit.fit_serial(A, B, 6, 1, sketch_p=3, seed=5, C_init=rs.C, first_sweep=2)
+    r4 = fit.fit_serial(A, B, 6, 1, sketch_p=3, seed=5, C_init=rs.C, first_sweep=4)
+    assert mpo.rel_diff(r2.C, r4.C) > 1e-8
+
+
+# ---------------------------------------------------------------- even/odd pins
+def _left_isometry(cores, l, d):
+    """T[x_<l, y_<l, c] of the first l-1 cores (1-based bond l)."""
+    T = np.ones((1, 1, 1))
+    for j in range(l - 1):
+        c = cores[j]
+        T = np.einsum("xyc,csuC->xsyuC", T, c).reshape(T.shape[0] * d, T.shape[1] * d, c.shape[3])
+    return T
+
+
+def _right_isometry(cores, l, d):
+    """V[c'', x_>l+1, y_>l+1] of the cores after site l+1 (1-based bond l)."""
+    L = len(cores)
+    V = np.ones((1, 1, 1))
+    for j in range(L - 1, l, -1):  # 0-based sites l+1 .. L-1 = 1-based l+2 .. L
+        c = cores[j]
+        V = np.einsum("csuC,Cxy->csxuy", c, V).reshape(c.shape[0], d * V.shape[1], d * V.shape[2])
+    return V
+
+
+def _even_odd_dense_check(A, B, chi_max, n_sweeps, sketch_p=-1):
+    """Every update of fit_even_odd against brute force.
+
+    Half-step h = 2 sweep + q updates the bonds of one parity from the
+    environments as they stood at its start, and each update rebuilds L_l
+    from U and R_{l+1} from V^T (Alg. 4, Sec. 4 with two-site sub-TTs).  So
+    the left environment of bond l at half-step h is made of a light cone of
+    isometries: site j < l contributes the U of bond j's update at half-step
+    h - (l - j), or the initial train's Psi_j Y_j if that index is negative;
+    the right environment mirrors this with the V^T of bond j - 1 for sites
+    j > l + 1 (or Y_{j-1} Psi_j of the initial train).  Checked: Theta_l is
+    the dense product A B (preprocessed) projected onto those isometries;
+    without the sketch S_l is the leading part of that matrix's singular
+    values (Eckart-Young, Alg. 3); U and V^T have orthonormal columns / rows
+    (Psi_l Y_l left and Y_l Psi_{l+1} right orthogonal, Sec. 2.3.1)."""
+    L, d = len(A), A[0].shape[1]
+    A1, B1, _, _ = fit._preprocess(A, B)
+    P = mpo.dense(A1) @ mpo.dense(B1)
+    hist = {}  # (h, l) -> (U4, V4)
+    init = {}
+    seen = []
+
+    def left_core(j, h):  # 1-based site j, as seen by a bond right of it at half-step h
+        if h < 0:
+            return init["Psi"][j - 1] * init["Y"][j - 1][None, None, None, :]
+        return hist[(h, j)][0]
+
+    def right_core(j, h):  # 1-based site j, seen by a bond left of it
+        if h < 0:
+            return init["Y"][j - 2][:, None, None, None] * init["Psi"][j - 1]
+        return hist[(h, j - 1)][1]
+
+    def on_bond(sweep, q, l, M, f, Psi0, Y0):
+        h = 2 * sweep + q
+        if not init:
+            init["Psi"] = [p.copy() for p in Psi0]
+            init["Y"] = [y.copy() for y in Y0]
+            # the initial train: inverse canonical form of the right-
+            # orthogonalized A (Sec. 2.3.1) with the same operator
+            for j in range(L - 1):
+                X = (Psi0[j] * Y0[j][None, None, None, :]).reshape(-1, Y0[j].size)
+                W = (Y0[j][:, None, None, None] * Psi0[j + 1]).reshape(Y0[j].size, -1)
+                kj = Y0[j] != 0
+                assert np.abs(X[:, kj].T @ X[:, kj] - np.eye(kj.sum())).max() < 1e-12
+                assert np.abs(W[kj] @ W[kj].T - np.eye(kj.sum())).max() < 1e-12
+            Cm = canon.merge_inverse_canonical(Psi0, Y0)
+            D0 = mpo.dense(A1)
+            assert np.abs(mpo.dense(Cm) - D0).max() <= 1e-12 * np.abs(D0).max()
+        Cl = [left_core(j, h - (l - j)) for j in range(1, l)]
+        Cr = [None] * L
+        for j in range(l + 2, L + 1):
+            Cr[j - 1] = right_core(j, h - (j - 1 - l))
+        T = _left_isometry(Cl, l, d)
+        V = _right_isometry(Cr, l, d)
+        nl, nr = d ** (l - 1), d ** (L - l - 1)
+        P8 = P.reshape(nl, d, d, nr, nl, d, d, nr)  # x<, s1, s2, x>, y<, u1, u2, y>
+        Th = np.einsum("xyc,xabXyefY,FXY->caebfF", T, P8, V).reshape(M.shape)
+        scale = np.abs(Th).max()
+        assert np.abs(M - Th).max() <= 1e-12 * scale, (sweep, q, l)
+        if sketch_p < 0:
+            sv = np.linalg.svd(Th, compute_uv=False)
+            r = len(f.S)
+            kept = f.S > 0
+            assert np.allclose(f.S[kept], sv[:r][kept], rtol=1e-12, atol=1e-13 * sv[0]), (sweep, q, l)
+        kept = f.S > 0
+        Uk = f.U[:, kept]
+        Vk = f.Vt[kept]
+        assert np.abs(Uk.T @ Uk - np.eye(Uk.shape[1])).max() < 1e-12
+        assert np.abs(Vk @ Vk.T - np.eye(Vk.shape[0])).max() < 1e-12
+        cl = Cl[-1].shape[3] if Cl else 1
+        cr = Cr[l + 1].shape[0] if l + 1 < L else 1
+        r = len(f.S)
+        # the environments of later half-steps use these isometries (the
+        # dropped triplets are already zero)
+        hist[(h, l)] = (f.U.reshape(cl, d, d, r), f.Vt.reshape(r, d, d, cr))
+        seen.append((sweep, q, l))
+
+    res = fit.fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=sketch_p, on_bond=on_bond)
+    assert len(seen) == n_sweeps * (L - 1)
+    return res
+
+
+@pytest.mark.parametrize("sketch_p", [-1, 2])
+@pytest.mark.parametrize("L,chi,chi_max", [(6, 3, 4), (7, 3, 5), (7, 2, 3)])
+def test_even_odd_half_steps_against_dense_projection(L, chi, chi_max, sketch_p):
+    """Truncating regime (chi_C below the structural rank chi^2): every bond of
+    both half-steps of three sweeps checked against the dense product."""
+    A, B = make_pair(L, 2, chi, seed=31 + L + chi, decay=True)
+    res = _even_odd_dense_check(A, B, chi_max, 3, sketch_p)
+    P = mpo.dense(A) @ mpo.dense(B)
+    assert mpo.fit_error_dense(A, B, res.C) > 1e-6  # truncation really happens
+
+
+def test_even_odd_dense_pin_catches_planted_mistakes(monkeypatch):
+    """The dense half-step pin fails for the two plausible slips in the
+    inverse-gauge bookkeeping: environments built from Psi = U S instead of
+    U, and the bond matrix Y = S instead of S^-1."""
+    A, B = make_pair(6, 2, 3, seed=40, decay=True)
+    orig = fit.canon.truncate_inverse
+
+    def env_from_psi(U, S, Vt, thresh=canon.INV_TRUNC):
+        U2, S2, V2, Y, n = orig(U, S, Vt, thresh)
+        return U2 * S2[None, :], S2, V2, Y, n
+
+    def y_not_inverted(U, S, Vt, thresh=canon.INV_TRUNC):
+        U2, S2, V2, Y, n = orig(U, S, Vt, thresh)
+        return U2, S2, V2, S2.copy(), n
+
+    for plant in (env_from_psi, y_not_inverted):
+        monkeypatch.setattr(fit.canon, "truncate_inverse", plant)
+        with pytest.raises(AssertionError):
+            _even_odd_dense_check(A, B, 4, 2)
+        monkeypatch.setattr(fit.canon, "truncate_inverse", orig)
+    _even_odd_dense_check(A, B, 4, 2)
+
+
+def test_drop_rule_on_rank_deficient_product():
+    """A B with bond rank below chi_C at interior bonds (B the identity MPO
+    on a doubled bond, so A B = A but chi^A chi^B = 2 chi^A): the singular
+    values beyond A's rank are dropped (zero padding), the fit reproduces A
+    exactly in both schedules, and the count of dropped values is reported."""
+    L, d, chi = 6, 2, 3
+    rng = np.random.default_rng(50)
+    A = gaussian_mpo(rng, L, d, chi)
+    Bid = []
+    for l in range(L):
+        cl = 1 if l == 0 else 2
+        cr = 1 if l == L - 1 else 2
+        core = np.zeros((cl, d, d, cr))
+        for i in range(d):
+            core[0, i, i, 0] = 1.0
+        Bid.append(core)
+    for run in (fit.fit_serial, fit.fit_even_odd):
+        res = run(A, Bid, 6, 3)
+        assert mpo.fit_error_dense(A, Bid, res.C) < 1e-12
+        assert res.n_guard > 0
