@@ -66,12 +66,15 @@ typedef enum {
   MPO_SCHED_EVEN_ODD = 1 /* inverse canonical gauge (Alg. 4): every bond
                             l = 1 (mod 2) together, then every l = 0 (mod 2),
                             from the environments at the half-step's start;
-                            one sweep = both half-steps (Sec. 4).  Singular
-                            values at or below 1e-12 sigma_1 are truncated
-                            before they are inverted (Sec. 2.3.1 allows it):
-                            value, Y entry and singular vectors become zero,
-                            the bond keeps its size; see mpo_fit_truncations */
+                            one sweep = both half-steps (Sec. 4) */
 } mpo_schedule;
+/* Drop rule of both schedules: of the r singular values an update keeps,
+   those at or below 1e-6 sigma_1 are dropped (value, singular vectors and in
+   the inverse gauge the Y entry become zero; the bond keeps its size).  In
+   the inverse gauge this is the truncation before inversion that Sec. 2.3.1
+   allows; it also makes a two-site matrix of lower rank than r (a product
+   with fewer independent states than the bond cap) well defined.  See
+   mpo_fit_truncations. */
 
 /* One MPO: L cores, core l (0-based) is a device array of
    chi[l] * d * d * chi[l+1] doubles, row-major (left, out, in, right). */
@@ -109,6 +112,29 @@ typedef struct {
                            2.3.5).  Used as given: right-orthogonalized, or
                            brought to inverse canonical form; only read at
                            init.                                            */
+  int32_t first_sweep; /* >= 0: the fit starts as if this many sweeps had
+                          run: sweep i (i = first_sweep, first_sweep + 1, ...)
+                          takes the Philox stream of sweep i and, serially,
+                          runs backward for odd i (Alg. 5).  A serial fit
+                          that starts backward left-orthogonalizes the
+                          initial guess and precomputes the left
+                          environments.  With c_init = the result of i
+                          sweeps this resumes that fit.                      */
+  int32_t track_error; /* 1: reserve workspace for the fit error per sweep
+                          (mpo_fit_sweep's fit_err) and compute ||A B||^2 at
+                          init by a four-layer transfer pass; 0: no error   */
+  int32_t first_bond;  /* serial schedule, one pair: >= 0 updates of sweep
+                          first_sweep already done (0 <= first_bond <= L-2).
+                          The initial guess is brought to site-canonical
+                          form around the two sites of the next update
+                          (QR sweep left of them, RQ sweep right of them)
+                          and the environments of both sides are
+                          precomputed; with c_init = a fit's state at that
+                          point this resumes it mid-sweep.                  */
+  int32_t first_half;  /* even/odd schedule: 1 = the first sweep runs only
+                          its second half-step (l = 0 mod 2), from the
+                          inverse canonical form of the initial guess and
+                          its environments; 0 = whole sweeps                */
 } mpo_fit_opts;
 
 /* One tuned class of grouped GEMM launches: the operand kind (mode as
@@ -146,8 +172,39 @@ mpo_status mpo_fit_init(mpo_fit_ctx** ctx, const mpo_pair* pairs, int32_t n_pair
 /* Runs n_sweeps sweeps of every pair.  Serial: a sweep is one directional
    pass of L-1 updates, the direction alternating from forward (Alg. 5).
    Even/odd: a sweep is two half-steps.  Synchronizes the stream at the end to
-   read the device status flags; returns MPO_ERR_NUMERIC if one was raised. */
-mpo_status mpo_fit_sweep(mpo_fit_ctx* ctx, int32_t n_sweeps);
+   read the device status flags; returns MPO_ERR_NUMERIC if one was raised.
+   fit_err (host, nullable; needs opts.track_error): fit_err[p * n_sweeps + s]
+   receives ||A B - C||_F / ||A B||_F of pair p after sweep s (Sec. 2.3, Eq.
+   fit_min; the error measure of Sec. 5.2), from transfer passes in FP64 on
+   the device: eps^2 = 1 - 2 <C, A B>/||A B||^2 + ||C||^2/||A B||^2, which
+   floors near 1e-8 (the difference of squares; the caveat of Sec. 5.2).  The
+   passes run after each sweep and synchronize; mpo_fit_last_sweep_ms then
+   includes those of all but the last sweep. */
+mpo_status mpo_fit_sweep(mpo_fit_ctx* ctx, int32_t n_sweeps, double* fit_err);
+
+/* Runs the next n_units units of the fit: two-site updates (serial
+   schedule, Alg. 5 order, one pair unless n_units covers whole sweeps) or
+   half-steps (even/odd), crossing into the next sweep when the current one
+   ends (the Philox stream and direction follow the sweep index).  A sweep
+   entered part-way is finished by the next mpo_fit_sweep call before whole
+   sweeps run.  Synchronizes the stream; MPO_ERR_NUMERIC as mpo_fit_sweep. */
+mpo_status mpo_fit_updates(mpo_fit_ctx* ctx, int32_t n_units);
+
+/* Position of the fit: *sweep = index of the current sweep (first_sweep plus
+   the sweeps completed), *unit = its units already run (0 = at a sweep
+   boundary).  Either pointer may be NULL. */
+mpo_status mpo_fit_position(const mpo_fit_ctx* ctx, int32_t* sweep, int32_t* unit);
+
+/* Singular values of bond `bond` (1 <= bond <= L-1, between 0-based sites
+   bond-1 and bond) from its last update (serial: the last sweep that passed
+   it; even/odd: Lambda of the inverse canonical form, Y = 1/S), of the fit
+   on normalized cores (multiply by mpo_fit_norm_factor for C's own), in
+   descending order with dropped values zero: S (host) receives
+   mpo_fit_bond_dims(...)[bond] doubles, *r (nullable) that count.  Before a
+   serial fit's first update the values are zero.  Synchronizes the context
+   stream. */
+mpo_status mpo_fit_singular_values(mpo_fit_ctx* ctx, int32_t pair, int32_t bond, double* S,
+                                   int32_t* r);
 
 /* Current bond dimensions of C for one pair: chi_c receives L+1 ints (host). */
 mpo_status mpo_fit_bond_dims(const mpo_fit_ctx* ctx, int32_t pair, int32_t* chi_c);
@@ -164,9 +221,9 @@ mpo_status mpo_fit_sweeps_done(const mpo_fit_ctx* ctx, int32_t* n);
    fit runs on normalized cores and mpo_fit_export_c multiplies core 0 by nu. */
 mpo_status mpo_fit_norm_factor(const mpo_fit_ctx* ctx, int32_t pair, double* nu);
 
-/* Even/odd schedule: number of singular values truncated before inversion
-   so far (initialization and sweeps, all pairs), as of the last call that
-   synchronized (mpo_fit_init, mpo_fit_sweep). */
+/* Number of singular values dropped so far by the drop rule (both
+   schedules; in the inverse gauge also at initialization), all pairs, as of
+   the last call that synchronized (mpo_fit_init, mpo_fit_sweep). */
 mpo_status mpo_fit_truncations(const mpo_fit_ctx* ctx, int64_t* n);
 
 /* Gradient at frozen truncation bases (not a step of the paper's method; it
@@ -192,29 +249,37 @@ mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_pair* ab, cons
                         double* const* gA, double* const* gB, double* loss, int32_t recompute_env,
                         void* workspace, size_t ws_bytes);
 
-/* Fit error ||A B - C||_F / ||A B||_F (Sec. 2.3, Eq. fit_min) in FP64 from
-   transfer passes on the device: ||A B||^2 by a four-layer pass, <C, A B> by
-   a three-layer pass and ||C||^2 by a two-layer pass, each environment
-   renormalized after every site (logarithms summed on the host, so long
-   chains neither under- nor overflow); the naive product of Alg. 1 is never
-   formed.  eps^2 = 1 - 2 <C, AB>/||AB||^2 + ||C||^2/||AB||^2 floors near
-   1e-8 relative (difference of squares).  pair->A, pair->B and C are FP64
-   device cores on one set of L sites with one d; the four-layer pass holds
-   (chi_A chi_B)^2 d^2 doubles per intermediate.  `workspace` (256-byte
-   aligned) of mpo_contract_check_bytes bytes.  Synchronizes `stream`;
-   *rel_err and (if non-null) *ab_norm2 = ||A B||_F^2 are host outputs;
-   MPO_ERR_NUMERIC if A B is zero or a pass is not finite. */
+/* Fit error ||A B - C||_F / ||A B||_F (Sec. 2.3, Eq. fit_min) in FP64 on
+   the device, for FP64 device cores A = pair->A, B = pair->B and C on one
+   set of L sites with one d.
+   Route 0 (every bond with chi_A chi_B + chi_C <= 512): the naive product
+   P = A B of Alg. 1 (Sec. 2.1) and the difference MPO [P, -C] (direct sum
+   of the trains) are each left-orthogonalized by Householder QR sweeps; the
+   last site's norm is the train's norm.  No Gram matrix and no difference
+   of squares is formed, so the result is accurate to a few units of
+   rounding of ||A B||, far below sqrt(eps) (the error measure of Sec. 5.2
+   without its floor).
+   Route 1 (larger bonds): transfer passes, ||A B||^2 by a four-layer pass,
+   <C, A B> by a three-layer pass, ||C||^2 by a two-layer pass, each
+   environment renormalized after every site; eps^2 = 1 - 2 <C, AB>/||AB||^2
+   + ||C||^2/||AB||^2 floors near 1e-8 relative.  The four-layer pass holds
+   (chi_A chi_B)^2 d^2 doubles per intermediate.
+   `workspace` (256-byte aligned) of mpo_contract_check_bytes bytes.
+   Synchronizes `stream`; *rel_err, and if non-null *ab_norm2 = ||A B||_F^2
+   and *method (0 or 1, the route), are host outputs; MPO_ERR_NUMERIC if
+   A B is zero or a pass is not finite. */
 mpo_status mpo_contract_check_bytes(const mpo_pair* pair, const mpo_tt* C, size_t* bytes);
 mpo_status mpo_contract_exact_check(const mpo_pair* pair, const mpo_tt* C, double* rel_err,
-                                    double* ab_norm2, void* workspace, size_t ws_bytes,
-                                    void* stream);
+                                    double* ab_norm2, int32_t* method, void* workspace,
+                                    size_t ws_bytes, void* stream);
+
 
 /* Device time, in milliseconds, of the last mpo_fit_sweep call's kernels
    between its first and last launch (HIP events on the context stream). */
 mpo_status mpo_fit_last_sweep_ms(const mpo_fit_ctx* ctx, double* ms);
 
 /* Per-kernel-class figures of the last mpo_fit_sweep call when the context
-   was created with profiling (opts.reserved[0] = 1; launches then run eagerly,
+   was created with profiling (opts.profile = 1; launches then run eagerly,
    each bracketed by HIP events on the context stream).  For up to `n` classes:
    ms[] device time, flops[] algorithmic flops credited to the class,
    launches[] launch count, all summed over that call's sweeps, and names[]

@@ -1,5 +1,5 @@
 /*
- * Test hooks of libmpofit: direct entry points to two of its kernels so the
+ * Test hooks of libmpofit: direct entry points to some of its kernels so the
  * test suite can check them in isolation against NumPy.  Not part of the fit
  * API.  Same conventions as mpofit.h (device pointers, caller-owned
  * workspace of at least 64 MiB, 256-byte aligned, work on `stream`, the call
@@ -38,6 +38,12 @@ mpo_status mpo_test_eig_batch(const double* H, int n, int k, int r, double* eval
 
 /* Q = CholeskyQR2 of the n x k FP64 matrix X (row-major, in place). */
 mpo_status mpo_test_cholqr(double* X, int n, int k, void* workspace, size_t ws_bytes, void* stream);
+
+/* The range finder's QR: one rank-revealing Cholesky-QR pass (a column in
+   the span of the previous ones, pivot at or below 1e-12 of its own squared
+   norm, becomes a zero column of Q instead of a failure), then one
+   Newton-Schulz step Q <- Q (3 I - Q^T Q) / 2. */
+mpo_status mpo_test_cholqr_rr(double* X, int n, int k, void* workspace, size_t ws_bytes, void* stream);
 
 /* Gaussian test matrix of one bond (same definition as the fit's): out is
    m x k FP64 row-major with rows in (c'', su) order, m = chi * dd. */

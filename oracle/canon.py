@@ -77,6 +77,36 @@ def right_orthogonalize(cores):
     return cores
 
 
+def mixed_canonical(cores, left):
+    """Site-canonical form around the two sites left, left+1 (0-based, Sec.
+    2.3.1): QR sweep over sites 0..left-1 (carried into site `left`) and RQ
+    sweep over sites L-1..left+2 (carried into site left+1), with the same
+    clipping rule as left_orthogonalize / right_orthogonalize.  The two
+    centre sites hold everything else; the operator is unchanged."""
+    cores = [np.array(c, dtype=np.float64, copy=True) for c in cores]
+    L = len(cores)
+    for l in range(left):
+        cl, d1, d2, cr = cores[l].shape
+        X = cores[l].reshape(cl * d1 * d2, cr)
+        if X.shape[0] >= X.shape[1]:
+            Q, R = qr_pos(X)
+        else:
+            Q, R = np.eye(X.shape[0]), X
+        cores[l] = Q.reshape(cl, d1, d2, Q.shape[1])
+        cores[l + 1] = np.tensordot(R, cores[l + 1], axes=(1, 0))
+    for l in range(L - 1, left + 1, -1):
+        cl, d1, d2, cr = cores[l].shape
+        X = cores[l].reshape(cl, d1 * d2 * cr)
+        if X.shape[0] <= X.shape[1]:
+            Qt, Rt = qr_pos(X.T)
+            core, carry = Qt.T, Rt.T
+        else:
+            core, carry = np.eye(X.shape[1]), X
+        cores[l] = core.reshape(core.shape[0], d1, d2, cr)
+        cores[l - 1] = np.tensordot(cores[l - 1], carry, axes=(3, 0))
+    return cores
+
+
 # Relative cut of singular values (truncation before inversion, Sec. 2.3.1,
 # and the drop rule of the two-site update): values at or below
 # INV_TRUNC * sigma_1 are set to zero.  At this level an FP64 singular

@@ -156,7 +156,7 @@ def _preprocess(A, B):
 
 
 def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
-               on_update=None, C_init=None, first_sweep=0):
+               on_update=None, C_init=None, first_sweep=0, first_bond=0, n_updates=None):
     """Alg. 5 with the site-canonical update of Alg. 3.
 
     Preprocessing left-orthogonalizes A and B and splits off their norms; the
@@ -173,7 +173,14 @@ def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
     sweep s runs forward (s even), and left-orthogonalized with all left
     environments precomputed when it runs backward (s odd).  From the result
     of the first s sweeps, which is already in that form up to rounding, this
-    continues the same fit."""
+    continues the same fit.
+
+    ``first_bond`` = b > 0 resumes inside sweep s after its first b updates:
+    the guess is brought to the site-canonical form around the two sites of
+    the next update (canon.mixed_canonical) and the environments of both
+    sides are precomputed; the result of a fit's first b updates of sweep s
+    is already in that form up to rounding.  ``n_updates`` stops after that
+    many updates (None: the n_sweeps sweeps, the first one partial)."""
     L = len(A)
     A1, B1, nu, caps = _preprocess(A, B)
     guess = A1 if C_init is None else C_init
@@ -183,7 +190,16 @@ def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
     Lenv[0] = ones
     Renv[L + 1] = ones
     # environments use 1-based site labels: site l is index l-1 in the lists
-    if first_sweep % 2 == 0:
+    if first_bond > 0:
+        if not 0 < first_bond < L - 1:
+            raise ValueError("first_bond must be in 1 .. L-2")
+        l0 = first_bond + 1 if first_sweep % 2 == 0 else L - 1 - first_bond  # 1-based bond
+        C = canon.mixed_canonical(guess, l0 - 1)
+        for l in range(1, l0):
+            Lenv[l] = env_left(Lenv[l - 1], C[l - 1], A1[l - 1], B1[l - 1])
+        for l in range(L, l0 + 1, -1):
+            Renv[l] = env_right(Renv[l + 1], C[l - 1], A1[l - 1], B1[l - 1])
+    elif first_sweep % 2 == 0:
         C = canon.right_orthogonalize(guess)
         for l in range(L, 2, -1):
             Renv[l] = env_right(Renv[l + 1], C[l - 1], A1[l - 1], B1[l - 1])
@@ -193,10 +209,16 @@ def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
         for l in range(1, L - 1):
             Lenv[l] = env_left(Lenv[l - 1], C[l - 1], A1[l - 1], B1[l - 1])
     min_gap, n_guard, ks = 1.0, 0, []
+    done = 0
     for sweep in range(first_sweep, first_sweep + n_sweeps):
         fwd = sweep % 2 == 0
-        bonds = range(1, L) if fwd else range(L - 1, 0, -1)
+        bonds = list(range(1, L) if fwd else range(L - 1, 0, -1))
+        if sweep == first_sweep:
+            bonds = bonds[first_bond:]
         for l in bonds:
+            if n_updates is not None and done >= n_updates:
+                break
+            done += 1
             if fwd and l >= 2:
                 Lenv[l - 1] = env_left(Lenv[l - 2], C[l - 2], A1[l - 2], B1[l - 2])
             if not fwd and l <= L - 2:
@@ -227,11 +249,14 @@ def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
     dims = [1] + [c.shape[3] for c in C]
     last = first_sweep + n_sweeps - 1
     centre = (L - 1 if last % 2 == 0 else 0) if n_sweeps > 0 else (0 if first_sweep % 2 == 0 else L - 1)
+    if first_bond > 0 or n_updates is not None:
+        centre = None  # a partial sweep leaves the centre inside the chain
     return FitResult(out, nu, dims, min_gap, n_guard, ks, C_norm=[c.copy() for c in C], centre=centre)
 
 
 def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
-                 on_half_step=None, C_init=None, first_sweep=0, on_bond=None):
+                 on_half_step=None, C_init=None, first_sweep=0, on_bond=None, first_half=0,
+                 n_half_steps=None):
     """Single-device limit of the parallel fit in inverse canonical form
     (Sec. 4, Alg. 4 and Alg. 6 with every sub-TT two sites long): half-step q
     updates every bond l with l = 1 (mod 2) for q = 0 and l = 0 (mod 2) for
@@ -246,7 +271,9 @@ def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
 
     ``on_bond(sweep, q, l, M, factor, Psi0, Y0)`` sees every update: the
     two-site matrix, its factorization and the train (Psi, Y) as it stood at
-    the half-step's start."""
+    the half-step's start.  ``first_half`` = 1 starts with half-step 1 of
+    sweep ``first_sweep`` (from the inverse canonical form of the guess and
+    its environments); ``n_half_steps`` stops after that many half-steps."""
     L = len(A)
     A1, B1, nu, caps = _preprocess(A, B)
     C0 = canon.right_orthogonalize(A1 if C_init is None else C_init)
@@ -263,8 +290,14 @@ def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
         Cl = Y[l - 2][:, None, None, None] * Psi[l - 1]
         Renv[l] = env_right(Renv[l + 1], Cl, A1[l - 1], B1[l - 1])
     min_gap, ks = 1.0, []
+    halves = 0
     for sweep in range(first_sweep, first_sweep + n_sweeps):
         for q in (0, 1):
+            if sweep == first_sweep and q < first_half:
+                continue
+            if n_half_steps is not None and halves >= n_half_steps:
+                break
+            halves += 1
             bonds = [l for l in range(1, L) if (l % 2 == 1) == (q == 0)]
             if on_bond is not None:
                 Psi0 = [p.copy() for p in Psi]

@@ -32,7 +32,9 @@ class MpoFitOpts(C.Structure):
     _fields_ = [("chi_max", C.c_int32), ("tau", C.c_double), ("precision", C.c_int32),
                 ("schedule", C.c_int32), ("sketch_p", C.c_int32), ("seed", C.c_uint64),
                 ("capture_graph", C.c_int32), ("tune", C.POINTER(MpoGemmTune)),
-                ("n_tune", C.c_int32), ("profile", C.c_int32), ("c_init", C.POINTER(MpoTT))]
+                ("n_tune", C.c_int32), ("profile", C.c_int32), ("c_init", C.POINTER(MpoTT)),
+                ("first_sweep", C.c_int32), ("track_error", C.c_int32), ("first_bond", C.c_int32),
+                ("first_half", C.c_int32)]
 
 
 class MpoError(RuntimeError):
@@ -45,8 +47,10 @@ EXPORTS = [
     "mpo_fit_workspace_bytes", "mpo_fit_init", "mpo_fit_sweep", "mpo_fit_bond_dims",
     "mpo_fit_export_c", "mpo_fit_sweeps_done", "mpo_fit_norm_factor", "mpo_fit_truncations",
     "mpo_fit_grad_workspace_bytes", "mpo_fit_grad", "mpo_contract_check_bytes",
-    "mpo_contract_exact_check", "mpo_fit_last_sweep_ms", "mpo_fit_profile", "mpo_gemm_autotune",
-    "mpo_fit_destroy", "mpo_last_error",
+    "mpo_contract_exact_check", "mpo_fit_singular_values",
+    "mpo_fit_updates", "mpo_fit_position",
+    "mpo_fit_last_sweep_ms", "mpo_fit_profile", "mpo_gemm_autotune", "mpo_fit_destroy",
+    "mpo_last_error",
 ]
 
 _lib = None
@@ -65,7 +69,11 @@ def load() -> C.CDLL:
     lib.mpo_fit_workspace_bytes.argtypes = [P(MpoPair), C.c_int32, P(MpoFitOpts), P(C.c_size_t)]
     lib.mpo_fit_init.argtypes = [P(C.c_void_p), P(MpoPair), C.c_int32, P(MpoFitOpts), C.c_void_p,
                                  C.c_size_t, C.c_void_p]
-    lib.mpo_fit_sweep.argtypes = [C.c_void_p, C.c_int32]
+    lib.mpo_fit_sweep.argtypes = [C.c_void_p, C.c_int32, P(C.c_double)]
+    lib.mpo_fit_singular_values.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double),
+                                            P(C.c_int32)]
+    lib.mpo_fit_updates.argtypes = [C.c_void_p, C.c_int32]
+    lib.mpo_fit_position.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
     lib.mpo_fit_bond_dims.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.mpo_fit_export_c.argtypes = [C.c_void_p, C.c_int32, P(C.c_void_p)]
     lib.mpo_fit_sweeps_done.argtypes = [C.c_void_p, P(C.c_int32)]
@@ -77,7 +85,7 @@ def load() -> C.CDLL:
                                  P(C.c_void_p), P(C.c_double), C.c_int32, C.c_void_p, C.c_size_t]
     lib.mpo_contract_check_bytes.argtypes = [P(MpoPair), P(MpoTT), P(C.c_size_t)]
     lib.mpo_contract_exact_check.argtypes = [P(MpoPair), P(MpoTT), P(C.c_double), P(C.c_double),
-                                             C.c_void_p, C.c_size_t, C.c_void_p]
+                                             P(C.c_int32), C.c_void_p, C.c_size_t, C.c_void_p]
     lib.mpo_fit_last_sweep_ms.argtypes = [C.c_void_p, P(C.c_double)]
     lib.mpo_fit_profile.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_char_p),
                                     P(C.c_double), P(C.c_int32), P(C.c_int32)]
@@ -99,7 +107,7 @@ def check(status: int) -> None:
 
 
 TEST_EXPORTS = ["mpo_test_gemm", "mpo_test_eig", "mpo_test_eig_batch", "mpo_test_cholqr",
-                "mpo_test_omega"]
+                "mpo_test_cholqr_rr", "mpo_test_omega"]
 
 
 def load_test_hooks() -> C.CDLL:
@@ -111,6 +119,7 @@ def load_test_hooks() -> C.CDLL:
     lib.mpo_test_eig.argtypes = [vp, i, i, vp, vp, vp, C.c_size_t, vp]
     lib.mpo_test_eig_batch.argtypes = [vp, i, i, i, vp, vp, vp, C.c_size_t, vp]
     lib.mpo_test_cholqr.argtypes = [vp, i, i, vp, C.c_size_t, vp]
+    lib.mpo_test_cholqr_rr.argtypes = [vp, i, i, vp, C.c_size_t, vp]
     lib.mpo_test_omega.argtypes = [vp, i, i, i, i, i, i, C.c_uint64, vp, C.c_size_t, vp]
     for n in TEST_EXPORTS:
         getattr(lib, n).restype = C.c_int

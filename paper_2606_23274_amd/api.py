@@ -42,7 +42,8 @@ class _Setup:
     """Device copies of the cores, the ctypes pair array and the options."""
 
     def __init__(self, pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
-                 profile, pair_chi_max, tuning, c_init=None):
+                 profile, pair_chi_max, tuning, c_init=None, first_sweep=0, track_error=False,
+                 first_bond=0, first_half=0):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.tts = []
@@ -62,6 +63,10 @@ class _Setup:
         opts.seed = int(seed)
         opts.capture_graph = 1 if capture_graph else 0
         opts.profile = 1 if profile else 0
+        opts.first_sweep = int(first_sweep)
+        opts.track_error = 1 if track_error else 0
+        opts.first_bond = int(first_bond)
+        opts.first_half = int(first_half)
         self.tune = tune_mod.to_ctypes(tune_mod.load(tuning)) if tuning is not None else None
         if self.tune is not None and len(self.tune):
             opts.tune = self.tune
@@ -90,14 +95,20 @@ class FitContext:
     tuning: a GEMM tuning table (list of entries, or a JSON path) from
     autotune().  c_init: optional initial guess C per pair (lists of
     (chi_l, d, d, chi_r) FP64 cores, e.g. export_numpy() of another fit);
-    default: A.
+    default: A.  first_sweep: start as if that many sweeps had run (Philox
+    stream and direction; with c_init = a fit's result after that many
+    sweeps this resumes it).  first_bond (serial, one pair): updates of that
+    sweep already done; first_half (even/odd): start with the second
+    half-step.  track_error: reserve what sweep(..., errors=True) needs for
+    the fit error per sweep.
     """
 
     def __init__(self, pairs, chi_max, precision="fp32", schedule="serial", sketch_p=-1, seed=0,
                  capture_graph=True, device="cuda:0", profile=False, pair_chi_max=None, tuning=None,
-                 c_init=None):
+                 c_init=None, first_sweep=0, track_error=False, first_bond=0, first_half=0):
         su = _Setup(pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
-                    profile, pair_chi_max, tuning, c_init)
+                    profile, pair_chi_max, tuning, c_init, first_sweep, track_error, first_bond,
+                    first_half)
         self._setup = su
         self.lib = su.lib
         self.device = su.device
@@ -115,8 +126,37 @@ class FitContext:
                                          C.c_void_p(self.stream.cuda_stream)))
         self.ctx = ctx
 
-    def sweep(self, n=1):
-        _lib.check(self.lib.mpo_fit_sweep(self.ctx, int(n)))  # synchronizes our stream
+    def sweep(self, n=1, errors=False):
+        """Runs n sweeps; with errors=True returns the fit error after each
+        sweep as an (n_pairs, n) array (needs track_error)."""
+        if not errors:
+            _lib.check(self.lib.mpo_fit_sweep(self.ctx, int(n), None))  # synchronizes our stream
+            return None
+        out = (C.c_double * (self.n_pairs * int(n)))()
+        _lib.check(self.lib.mpo_fit_sweep(self.ctx, int(n), out))
+        return np.array(out[:], dtype=np.float64).reshape(self.n_pairs, int(n))
+
+    def updates(self, n=1):
+        """Runs the next n two-site updates (serial) or half-steps (even/odd)."""
+        _lib.check(self.lib.mpo_fit_updates(self.ctx, int(n)))
+
+    def position(self):
+        """(sweep index, units of it already run)."""
+        sw, un = C.c_int32(), C.c_int32()
+        _lib.check(self.lib.mpo_fit_position(self.ctx, C.byref(sw), C.byref(un)))
+        return sw.value, un.value
+
+    def singular_values(self, bond, pair=0):
+        """Singular values of bond `bond` (1..L-1) from its last update, on the
+        normalized cores (times norm_factor() for C's own), dropped ones zero."""
+        L = self.L[pair]
+        out = (C.c_double * 4096)()
+        r = C.c_int32()
+        dims = self.bond_dims(pair)
+        if not 1 <= bond < L or dims[bond] > 4096:
+            raise ValueError("bad bond")
+        _lib.check(self.lib.mpo_fit_singular_values(self.ctx, pair, int(bond), out, C.byref(r)))
+        return np.array(out[:r.value], dtype=np.float64)
 
     def sweeps_done(self):
         n = C.c_int32()
@@ -266,22 +306,26 @@ class FitContract(torch.autograd.Function):
         return (None, None, *[g * t for t in ctx.saved_tensors])
 
 
-def fit_error(A, B, C, device="cuda:0"):
-    """||A B - C||_F / ||A B||_F and ||A B||_F^2 in FP64 from transfer passes
-    on the GPU (mpo_contract_exact_check); the difference of squares floors
-    near 1e-8 relative."""
+def fit_error(A, B, C, device="cuda:0", with_method=False):
+    """||A B - C||_F / ||A B||_F and ||A B||_F^2 in FP64 on the GPU
+    (mpo_contract_exact_check): Householder-QR sweeps of the naive product
+    and the difference MPO when every chi_A chi_B + chi_C <= 512 (method 0,
+    accurate far below sqrt(eps)), else transfer passes (method 1, floors
+    near 1e-8 relative)."""
     lib = _lib.load()
     dev = torch.device(device)
     ta, tb, tc = (_TT(_dev_cores(X, dev)) for X in (A, B, C))
     pair = _lib.MpoPair(ta.tt, tb.tt, 0)
-    nbytes = C_.c_size_t()
-    _lib.check(lib.mpo_contract_check_bytes(C_.byref(pair), C_.byref(tc.tt), C_.byref(nbytes)))
-    ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
-    ws_ptr = (ws.data_ptr() + 255) & ~255
-    err, n2 = C_.c_double(), C_.c_double()
+    err, n2, meth = C_.c_double(), C_.c_double(), C_.c_int32()
     with torch.cuda.device(dev):
         stream = torch.cuda.current_stream(dev)
+        nbytes = C_.c_size_t()
+        _lib.check(lib.mpo_contract_check_bytes(C_.byref(pair), C_.byref(tc.tt), C_.byref(nbytes)))
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        ws_ptr = (ws.data_ptr() + 255) & ~255
         _lib.check(lib.mpo_contract_exact_check(C_.byref(pair), C_.byref(tc.tt), C_.byref(err),
-                                                C_.byref(n2), C_.c_void_p(ws_ptr), nbytes.value,
-                                                C_.c_void_p(stream.cuda_stream)))
+                                                C_.byref(n2), C_.byref(meth), C_.c_void_p(ws_ptr),
+                                                nbytes.value, C_.c_void_p(stream.cuda_stream)))
+    if with_method:
+        return err.value, n2.value, meth.value
     return err.value, n2.value

@@ -128,7 +128,10 @@ __global__ void scale_kernel(const ScaleDesc* __restrict__ descs) {
     double v = d.in[(long long)i * d.ldi + j];
     // the inverse is the pseudo-inverse: a zero scale gives zero
     if (d.row) v = d.row_inv ? (d.row[i] != 0.0 ? v / d.row[i] : 0.0) : v * d.row[i];
-    if (d.col) v = d.col_inv ? (d.col[j] != 0.0 ? v / d.col[j] : 0.0) : v * d.col[j];
+    if (d.col) {
+      if (d.col_inv == 2) v = d.col[j] != 0.0 ? v : 0.0;  // a mask: select, so a NaN is cleared too
+      else v = d.col_inv ? (d.col[j] != 0.0 ? v / d.col[j] : 0.0) : v * d.col[j];
+    }
     d.out[(long long)i * d.ldo + j] = v;
   }
 }
@@ -175,15 +178,12 @@ __global__ void svals_kernel(const SvalDesc* __restrict__ descs) {
   const double lj = d.evals[j];
   const double s0 = sqrt(fmax(l0, 0.0));
   const double sj = sqrt(fmax(lj, 0.0));
-  d.S[j] = sj;
   if (d.flag && !isfinite(lj)) atomicOr(d.flag, FLAG_NONFINITE);
-  if (d.guard) {
-    const bool keep = sj > kInvTrunc * s0;
-    d.keep[j] = keep ? 1.0 : 0.0;
-    if (!keep && d.count) atomicAdd(d.count, 1);
-  }
+  const bool keep = sj > kDrop * s0;
+  d.S[j] = keep ? sj : 0.0;
+  if (d.keep) d.keep[j] = keep ? 1.0 : 0.0;
+  if (!keep && d.count) atomicAdd(d.count, 1);
 }
-
 __global__ void fill_kernel(const FillDesc* __restrict__ descs) {
   const FillDesc d = descs[blockIdx.y];
   if (d.eye_rows > 0) {
@@ -253,6 +253,37 @@ __global__ void __launch_bounds__(256) divide_kernel(double* __restrict__ x, lon
     x[e] *= inv;
 }
 
+__global__ void naive_kernel(const NaiveDesc* __restrict__ descs) {
+  const NaiveDesc d = descs[blockIdx.y];
+  const int pd = d.d;  // physical dimension
+  const long long n = (long long)d.a0 * d.b0 * pd * pd * d.a1 * d.b1;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    long long q = e;
+    const int jb = (int)(q % d.b1); q /= d.b1;
+    const int ja = (int)(q % d.a1); q /= d.a1;
+    const int u = (int)(q % pd); q /= pd;
+    const int s = (int)(q % pd); q /= pd;
+    const int ib = (int)(q % d.b0);
+    const int ia = (int)(q / d.b0);
+    double acc = 0.0;
+    for (int t = 0; t < pd; ++t)
+      acc = fma(d.A[(((long long)ia * pd + s) * pd + t) * d.a1 + ja],
+                d.B[(((long long)ib * pd + t) * pd + u) * d.b1 + jb], acc);
+    d.P[e] = acc;
+  }
+}
+
+__global__ void polish_kernel(const PolishDesc* __restrict__ descs) {
+  const PolishDesc d = descs[blockIdx.y];
+  const long long n = (long long)d.k * d.k;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double g = d.G[e];
+    d.G[e] = (e / d.k == e % d.k ? 1.5 : 0.0) - 0.5 * g;
+  }
+}
+
 __global__ void bump_kernel(int* c, int by) {
   if (threadIdx.x == 0) c[0] += by;
 }
@@ -283,6 +314,16 @@ void launch_scale(const ScaleDesc* d, int n, int max_elems, hipStream_t s) {
 void launch_perm(const PermDesc* d, int n, long long max_elems, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(perm_kernel, dim3(grid_for(max_elems, 256), n), dim3(256), 0, s, d);
+}
+
+void launch_polish(const PolishDesc* d, int n, int max_k, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(polish_kernel, dim3(grid_for((long long)max_k * max_k, 256), n), dim3(256), 0, s, d);
+}
+
+void launch_naive(const NaiveDesc* d, int n, long long max_elems, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(naive_kernel, dim3(grid_for(max_elems, 256), n), dim3(256), 0, s, d);
 }
 
 void launch_svals(const SvalDesc* d, int n, int max_r, hipStream_t s) {

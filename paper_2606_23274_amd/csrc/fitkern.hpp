@@ -35,7 +35,9 @@ struct SignDesc {
 void launch_signfix(const SignDesc* d, int n, int max_r, hipStream_t s);
 
 // out(i, j) = in(i, j) * (row ? row[i] : 1) * (col ? col[j] : 1) for an
-// n x r matrix; `out` may alias `in`.  rinv/cinv invert the scale vector.
+// n x r matrix; `out` may alias `in`.  row_inv/col_inv = 1 invert the scale
+// vector (pseudo-inverse: a zero entry gives zero); col_inv = 2 uses col as
+// a mask (out = col[j] != 0 ? in : 0).
 struct ScaleDesc {
   const double* in;
   double* out;
@@ -63,21 +65,24 @@ struct PermDesc {
 };
 void launch_perm(const PermDesc* d, int n, long long max_elems, hipStream_t s);
 
-// Singular values S_j = sqrt(max(lambda_j, 0)) of r eigenvalues; raises
-// FLAG_NONFINITE on NaN/Inf.
-// S = sqrt(max(lambda, 0)).  With `guard` (inverse gauge) keep[j] = 1 if
-// S_j > kInvTrunc S_0 else 0 (the value is then truncated before inversion,
-// and counted in *count).
+// Singular values of the top r eigenvalues of a Gram matrix, S_j =
+// sqrt(max(lambda_j, 0)), with the drop rule of the update: keep[j] = 1 if
+// S_j > kDrop S_0, else 0, and then S_j = 0 (the triplet is dropped; in the
+// inverse gauge this is the truncation before inversion).  Dropped values
+// are counted in *count (nullable); NaN/Inf raise FLAG_NONFINITE.
 struct SvalDesc {
   const double* evals;
   double* S;
   int r;
-  int guard;
+  int unused;
   int* flag;
   double* keep = nullptr;
   int* count = nullptr;
 };
-constexpr double kInvTrunc = 1e-12;
+// Relative cut of singular values: an FP64 SVD fixes the vectors of values
+// above it to about 1e-10, and 1 / sigma amplifies rounding by at most 1e6
+// (the Gram eigenproblem itself resolves sigma down to about 1e-8 sigma_1).
+constexpr double kDrop = 1e-6;
 void launch_svals(const SvalDesc* d, int n, int max_r, hipStream_t s);
 
 // Zero `n_words` 32-bit words at each pointer; when eye_rows > 0 write an
@@ -99,6 +104,27 @@ void launch_norm(const NormDesc* d, int n, hipStream_t s);
 // squares into `part` (>= 1024 doubles), then nu, then the division.
 void launch_norm_big(double* x, long long n, double* part, double* nu_out, hipStream_t s);
 void launch_fill(const FillDesc* d, int n, long long max_words, hipStream_t s);
+
+// Alg. 1 (naive product) for one site: P[(ia, ib), s, u, (ja, jb)] =
+// sum_t A[ia, s, t, ja] B[ib, t, u, jb], all FP64 row-major, the left and
+// right bonds of P grouped with A's index major.
+struct NaiveDesc {
+  const double* A;
+  const double* B;
+  double* P;
+  int a0, a1, b0, b1, d;
+};
+void launch_naive(const NaiveDesc* d, int n, long long max_elems, hipStream_t s);
+
+// One Newton-Schulz step towards the orthonormal polar factor: with
+// G = X^T X (k x k, row-major), G <- (3 I - G) / 2; then X G has
+// ||(X G)^T (X G) - I|| <= (3/4) ||X^T X - I||^2 + rounding.  Zero columns of
+// X stay zero and do not touch the others.
+struct PolishDesc {
+  double* G;
+  int k;
+};
+void launch_polish(const PolishDesc* d, int n, int max_k, hipStream_t s);
 
 // *counter += 1 (one thread); used to advance the sweep index inside a graph.
 void launch_bump(int* counter, int by, hipStream_t s);

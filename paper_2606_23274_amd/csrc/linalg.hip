@@ -71,7 +71,8 @@ __global__ void __launch_bounds__(kBig) chol_kernel(const CholDesc* __restrict__
   const GAS double* G = gload_ptr(d.G);
   GAS double* Rg = gstore_ptr(d.R);
   for (int i = wave; i < k; i += kBig / 64)
-    for (int j = lane; j <= i; j += 64) A.at(i, j) = G[(long long)i * d.ldg + j];
+    for (int j = lane; j <= i; j += 64)
+      A.at(i, j) = G[(long long)i * d.ldg + j] + ((i == j && d.keep && d.keep[i] == 0.0) ? 1.0 : 0.0);
   if (d.shift > 0.0) {  // G + shift * trace(G) I
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -88,12 +89,19 @@ __global__ void __launch_bounds__(kBig) chol_kernel(const CholDesc* __restrict__
     __syncthreads();
     if (threadIdx.x == 0) {
       double v = A.at(j, j);
-      if (!(v > 0.0) || !isfinite(v)) { bad = true; v = DBL_MIN; }
-      s_piv = sqrt(v);
+      if (d.eta > 0.0) {  // rank-revealing: a dependent column gives a zero row of R
+        const double g0 = G[(long long)j * d.ldg + j] + ((d.keep && d.keep[j] == 0.0) ? 1.0 : 0.0);
+        if (v <= d.eta * g0) v = 0.0;
+        if (!isfinite(v)) bad = true;
+        s_piv = v > 0.0 ? sqrt(v) : 0.0;
+      } else {
+        if (!(v > 0.0) || !isfinite(v)) { bad = true; v = DBL_MIN; }
+        s_piv = sqrt(v);
+      }
       A.at(j, j) = s_piv;
     }
     __syncthreads();
-    const double inv = 1.0 / s_piv;
+    const double inv = s_piv > 0.0 ? 1.0 / s_piv : 0.0;
     for (int i = j + 1 + threadIdx.x; i < k; i += kBig) A.at(i, j) *= inv;
     __syncthreads();
     const int t = k - j - 1;
@@ -130,7 +138,10 @@ __global__ void __launch_bounds__(kBig) trsm_kernel(const TrsmDesc* __restrict__
   const TrsmDesc d = descs[blockIdx.y];
   const int k = d.k;
   const GAS double* Rg = gload_ptr(d.R);
-  for (int j = threadIdx.x; j < k; j += kBig) s_inv[j] = 1.0 / Rg[(long long)j * d.ldr + j];
+  for (int j = threadIdx.x; j < k; j += kBig) {
+    const double rjj = Rg[(long long)j * d.ldr + j];
+    s_inv[j] = rjj != 0.0 ? 1.0 / rjj : 0.0;
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (kBig / 64) + (threadIdx.x >> 6);
@@ -985,6 +996,7 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
   __shared__ double LJ[G][G + 1];   // L of the diagonal block
   __shared__ double LI[G][G];       // its inverse
   __shared__ double invsJ[G];       // 1 / L(m, m) of the block
+  __shared__ double gdiag[G * NB];  // diagonal of G as loaded (rank-revealing reference)
   const CholDesc d = descs[blockIdx.x];
   const int k = d.k;
   const int tr = threadIdx.x / G, tc = threadIdx.x % G;
@@ -995,7 +1007,12 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
     for (int j = 0; j < NB; ++j) {
       const int r = tr + G * i, c = tc + G * j;
       a[i][j] = (r < k && c < k) ? gload_ptr(d.G)[(long long)r * d.ldg + c] : (r == c ? 1.0 : 0.0);
+      if (i == j && tr == tc) {  // the diagonal: a masked column counts as a unit one
+        if (r < k && d.keep && gload_ptr(d.keep)[r] == 0.0) a[i][j] += 1.0;
+        gdiag[r] = a[i][j];  // read back only by this thread
+      }
     }
+  const double eta = d.eta;
   bool bad = false;
   double own_invs = 0.0;  // 1 / L(c, c) of this lane's column c = tc + G JB
   static_for<0, NB>([&](auto jb_) {
@@ -1007,7 +1024,11 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
       if (tc == jt) {  // column jj below the diagonal; the diagonal apart
 #pragma unroll
         for (int i = JB; i < NB; ++i) colb[buf][tr + G * i] = (tr + G * i > jj) ? a[i][JB] : 0.0;
-        if (tr == jt) dgb[buf] = a[JB][JB];
+        if (tr == jt) {
+          const double v = a[JB][JB];
+          // rank-revealing: a column in the span of the previous ones
+          dgb[buf] = (eta > 0.0 && v <= eta * gdiag[jj]) ? 0.0 : v;
+        }
       }
       __syncthreads();
       // every broadcast value is read before the pivot is used
@@ -1017,7 +1038,7 @@ __global__ void __launch_bounds__(G * G) chol_inv_reg_kernel(const CholDesc* __r
 #pragma unroll
       for (int i = JB; i < NB; ++i) av[i] = colb[buf][tr + G * i];
       const bool ok = djj > 0.0 && djj < INFINITY;
-      if (!ok) bad = true;
+      if (!ok && !(eta > 0.0 && djj == 0.0)) bad = true;
       const double rs = rsq_nr(djj);
       const double invs = ok ? rs : 0.0;  // 1 / L(jj, jj)
       const double lc = cc * invs;        // L(c, jj)
@@ -1418,7 +1439,194 @@ __global__ void __launch_bounds__(kBig) jacobi_kernel(const JacobiDesc* __restri
     for (int r = 0; r < q; ++r) d.Ur[(long long)r * d.ldu + rank] = M[(long long)c * q + r] * inv;
   }
 }
+// ---------------------------------------------------------------- clusters
+// Eigenvectors of close eigenvalues.  A twisted factorization gives each
+// vector to an angle of about k eps ||T|| / gap, so vectors of eigenvalues
+// closer than kClusterGap lambda_1 (exactly equal ones included) can come
+// out nearly parallel.  Such runs of kept eigenvalues (lambda > kClusterFloor
+// lambda_1, the square of the drop cut of the update) are recomputed by
+// inverse iteration with reorthogonalization inside the run, the strategy of
+// LAPACK's dstein: for each member, LU with partial pivoting of T - lambda I
+// (tiny pivots replaced by eps ||T||), three steps of x <- (T - lambda)^-1 x
+// each followed by Gram-Schmidt (twice) against the members already done;
+// the first member starts from its twisted vector, the others from a fixed
+// pseudo-random vector.  The vectors of a run then span its invariant
+// subspace to about eps ||T|| / (gap to the rest of the spectrum).  A
+// problem without such a run only scans its eigenvalues.
+constexpr double kClusterGap = 1e-5;
+constexpr double kClusterFloor = 1e-12;
+
+__device__ __forceinline__ double wave_dot(const double* a, const GAS double* X, long long ld, int k,
+                                           int lane) {  // sum_i a[i] X[i ld], one wave
+  double s = 0.0;
+  for (int i = lane; i < k; i += 64) s = fma(a[i], X[(long long)i * ld], s);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  return s;
+}
+
+__global__ void __launch_bounds__(64) cluster_kernel(const EigDesc* __restrict__ descs) {
+  extern __shared__ double lds[];
+  const EigDesc dd = descs[blockIdx.x];
+  const int k = dd.k, r = dd.r, lane = threadIdx.x;
+  if (r < 2 || k < 2) return;  // uniform
+  EigWork W(dd.work, k, r);
+  const double* ev = dd.evals;
+  const double l1 = ev[0];
+  if (!(l1 > 0.0)) return;
+  const double gtol = kClusterGap * l1, floor_ = kClusterFloor * l1;
+  // any run at all?  (one pass over the eigenvalues, all lanes)
+  bool any = false;
+  for (int j = lane; j + 1 < r; j += 64)
+    any = any || (ev[j + 1] > floor_ && ev[j] - ev[j + 1] <= gtol);
+  if (!__any(any)) return;
+  double* u0 = lds;          // U diagonal
+  double* u1 = lds + k;      // first superdiagonal
+  double* u2 = lds + 2 * k;  // second superdiagonal
+  double* ml = lds + 3 * k;  // multipliers
+  double* pv = lds + 4 * k;  // 1 where rows i, i+1 were swapped
+  double* x = lds + 5 * k;   // the iterate
+  GAS double* X = gstore_ptr(W.X);
+  const GAS double* dg = W.d;
+  const GAS double* eo = W.e;
+  double tn = 0.0;  // ||T||_1-type bound for the pivot floor
+  for (int i = lane; i < k; i += 64)
+    tn = fmax(tn, fabs(dg[i]) + fabs(i > 0 ? eo[i - 1] : 0.0) + fabs(i + 1 < k ? eo[i] : 0.0));
+  for (int off = 32; off > 0; off >>= 1) tn = fmax(tn, __shfl_xor(tn, off));
+  const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
+  int j = 0;
+  while (j + 1 < r) {
+    if (!(ev[j + 1] > floor_) ) break;  // uniform: the rest is dropped
+    if (ev[j] - ev[j + 1] > gtol) { ++j; continue; }
+    int j1 = j + 1;
+    while (j1 + 1 < r && ev[j1 + 1] > floor_ && ev[j1] - ev[j1 + 1] <= gtol) ++j1;
+    for (int m = j; m <= j1; ++m) {
+      const double lam = ev[m];
+      if (lane == 0) {  // LU of T - lam I with partial pivoting (rows i, i+1)
+        double cd = dg[0] - lam, cs1 = k > 1 ? eo[0] : 0.0, cs2 = 0.0;
+        for (int i = 0; i + 1 < k; ++i) {
+          const double sub = eo[i], nd = dg[i + 1] - lam, ns = i + 2 < k ? eo[i + 1] : 0.0;
+          if (fabs(cd) >= fabs(sub)) {
+            const double piv = fabs(cd) < tiny ? (cd < 0.0 ? -tiny : tiny) : cd;
+            const double l = sub / piv;
+            u0[i] = piv; u1[i] = cs1; u2[i] = cs2; ml[i] = l; pv[i] = 0.0;
+            cd = nd - l * cs1;
+            cs1 = ns - l * cs2;
+          } else {
+            const double l = cd / sub;
+            u0[i] = sub; u1[i] = nd; u2[i] = ns; ml[i] = l; pv[i] = 1.0;
+            cd = cs1 - l * nd;
+            cs1 = cs2 - l * ns;
+          }
+          cs2 = 0.0;
+        }
+        u0[k - 1] = fabs(cd) < tiny ? (cd < 0.0 ? -tiny : tiny) : cd;
+        u1[k - 1] = u2[k - 1] = 0.0;
+        if (k > 1) u2[k - 2] = 0.0;
+      }
+      // start vector
+      for (int i = lane; i < k; i += 64) {
+        if (m == j) {
+          x[i] = X[(long long)i * r + m];
+        } else {  // a fixed pseudo-random vector (integer hash of i and m)
+          unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)((m + 1) * 2246822519u);
+          h ^= h >> 15; h *= 2654435761u; h ^= h >> 13;
+          x[i] = ((double)(h & 0xffffff) / 16777216.0) - 0.5;
+        }
+      }
+      __syncthreads();
+      for (int it = 0; it < 4; ++it) {
+        // orthogonalize against the members done (twice), then normalize
+        for (int pass = 0; pass < 2; ++pass)
+          for (int q = j; q < m; ++q) {
+            const double c = wave_dot(x, X + q, r, k, lane);
+            __syncthreads();
+            for (int i = lane; i < k; i += 64) x[i] = fma(-c, X[(long long)i * r + q], x[i]);
+            __syncthreads();
+          }
+        double nn = 0.0;
+        for (int i = lane; i < k; i += 64) nn = fma(x[i], x[i], nn);
+        for (int off = 32; off > 0; off >>= 1) nn += __shfl_xor(nn, off);
+        const double inv = nn > 0.0 ? rsqrt(nn) : 0.0;
+        __syncthreads();
+        for (int i = lane; i < k; i += 64) x[i] *= inv;
+        __syncthreads();
+        if (it == 3) break;
+        if (lane == 0) {  // x <- (T - lam I)^-1 x:  L U x = P x
+          for (int i = 0; i + 1 < k; ++i) {
+            if (pv[i] != 0.0) { const double t = x[i]; x[i] = x[i + 1]; x[i + 1] = t; }
+            x[i + 1] -= ml[i] * x[i];
+          }
+          x[k - 1] /= u0[k - 1];
+          if (k > 1) x[k - 2] = (x[k - 2] - u1[k - 2] * x[k - 1]) / u0[k - 2];
+          for (int i = k - 3; i >= 0; --i) x[i] = (x[i] - u1[i] * x[i + 1] - u2[i] * x[i + 2]) / u0[i];
+          // keep the scale in range before the next normalization
+          double mx = 0.0;
+          for (int i = 0; i < k; ++i) mx = fmax(mx, fabs(x[i]));
+          if (mx > 0.0 && isfinite(mx)) for (int i = 0; i < k; ++i) x[i] /= mx;
+        }
+        __syncthreads();
+      }
+      for (int i = lane; i < k; i += 64) X[(long long)i * r + m] = x[i];
+      __syncthreads();
+    }
+    j = j1 + 1;
+  }
+}
+
+// ---------------------------------------------------------------- Householder QR
+// Column j: the reflector H_j = I - tau v v^T with v_j = 1 that maps
+// X(j:m, j) onto beta e_j (beta = -sign(alpha) ||X(j:m, j)||, the LAPACK
+// dlarfg convention); v is kept below the diagonal.  H_j is then applied to
+// the trailing columns, one thread per column walking down the rows (the
+// rows are contiguous across threads).
+__global__ void __launch_bounds__(kBig) geqr_kernel(const GeqrDesc* __restrict__ descs) {
+  __shared__ double red[kBig / 64];
+  const GeqrDesc d = descs[blockIdx.x];
+  const int m = d.m, n = d.n, p = min(m, n);
+  const long long ld = d.ldx;
+  GAS double* X = gstore_ptr(d.X);
+  for (int j = 0; j < p; ++j) {
+    double ss = 0.0;
+    for (int i = j + 1 + threadIdx.x; i < m; i += kBig) {
+      const double v = X[i * ld + j];
+      ss = fma(v, v, ss);
+    }
+    ss = block_sum<kBig / 64>(ss, red);
+    const double alpha = X[j * ld + j];
+    double beta = alpha, tau = 0.0, scal = 0.0;
+    if (ss > 0.0) {
+      const double nrm = sqrt(fma(alpha, alpha, ss));
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    __syncthreads();  // every thread has read alpha
+    for (int i = j + 1 + threadIdx.x; i < m; i += kBig) X[i * ld + j] *= scal;
+    if (threadIdx.x == 0) X[j * ld + j] = beta;
+    __syncthreads();
+    if (tau != 0.0) {
+      for (int c = j + 1 + threadIdx.x; c < n; c += kBig) {
+        double w = X[j * ld + c];
+        for (int i = j + 1; i < m; ++i) w = fma(X[i * ld + j], X[i * ld + c], w);
+        w *= tau;
+        X[j * ld + c] -= w;
+        for (int i = j + 1; i < m; ++i) X[i * ld + c] = fma(-X[i * ld + j], w, X[i * ld + c]);
+      }
+    }
+    __syncthreads();
+  }
+  GAS double* R = gstore_ptr(d.R);
+  for (long long e = threadIdx.x; e < (long long)p * n; e += kBig) {
+    const int i = (int)(e / n), c = (int)(e % n);
+    R[(long long)i * d.ldr + c] = c >= i ? X[i * ld + c] : 0.0;
+  }
+}
 }  // namespace
+
+void launch_geqr(const GeqrDesc* d, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(geqr_kernel, dim3(n), dim3(kBig), 0, s, d);
+}
 
 // The register kernels by size: the 16 x 16 grid with the fewest register
 // blocks that hold k (k <= kRegMax).
@@ -1539,6 +1747,9 @@ void launch_eig(const EigDesc* d, const EigDesc* h, int n, int reg, int stage, h
       hipLaunchKernelGGL(twisted_kernel, dim3(ceil_div(max_r, T), n), dim3(T),
                          (2 * (size_t)max_k * T + 2 * max_k) * sizeof(double), s, d);
     }
+    // runs of close eigenvalues: inverse iteration with reorthogonalization
+    // (6 k doubles of LDS; k <= 3200 fits)
+    hipLaunchKernelGGL(cluster_kernel, dim3(n), dim3(64), 6 * (size_t)max_k * sizeof(double), s, d);
   }
   if (!(all || stage == 3)) return;
   if (reg) {  // Z = Q X row by row from the reflectors

@@ -10,17 +10,28 @@ namespace mpofit {
 
 // Cholesky G = R^T R (R upper triangular, R_jj > 0); R is written row-major
 // into `R` (ldr), its strictly lower part zeroed.  G is only read.
+//
+// keep (nullable, k entries): a column j with keep[j] == 0 is known to be
+// zero in the matrix whose Gram G is; G(j, j) is taken as 1 so that R has a
+// unit row and column there and X R^{-1} keeps the column zero.
+// eta > 0 (rank-revealing): a pivot at or below eta times the column's own
+// diagonal G(j, j) means the column lies in the span of the previous ones;
+// its row of R (and of R^{-1}) becomes zero, without a flag, so X R^{-1} has
+// a zero column there.
 struct CholDesc {
   const double* G;
   int ldg;
   double* R;
   int ldr;
   int k;
-  int* flag;  // FLAG_CHOL on a non-positive pivot
+  int* flag;  // FLAG_CHOL on a non-positive pivot (eta = 0) or a non-finite one
   double shift = 0;  // > 0: factor G + shift * trace(G) I instead (general kernel)
+  const double* keep = nullptr;
+  double eta = 0;
 };
 
-// X <- X R^{-1} for an n x k row-major X (ldx) and upper triangular R (ldr).
+// X <- X R^{-1} for an n x k row-major X (ldx) and upper triangular R (ldr);
+// a zero diagonal entry of R gives a zero column.
 struct TrsmDesc {
   double* X;
   int ldx;
@@ -63,6 +74,19 @@ struct JacobiDesc {
 };
 constexpr int kJacobiLds = 128;
 void launch_jacobi(const JacobiDesc* d, int n, int max_q, hipStream_t s);
+
+// Householder QR of an m x n row-major X (ldx), overwritten: writes the
+// upper-trapezoidal R (min(m, n) x n, row-major, ldr, zeros below the
+// diagonal) of X = Q R; Q is not formed.  Backward stable (no Gram matrix),
+// so a norm carried through a sweep of such factorizations keeps an absolute
+// accuracy of a few units of rounding of the input's norm.
+struct GeqrDesc {
+  double* X;
+  int m, n, ldx;
+  double* R;
+  int ldr;
+};
+void launch_geqr(const GeqrDesc* d, int n, hipStream_t s);
 
 size_t eig_work_doubles(int k, int r);
 // Panel reduction of the global-memory path: widest panel, the panel width

@@ -19,6 +19,7 @@
 // With these orders every contraction of Fig. envs and Fig. derivatives is a
 // GEMM whose free and contracted index groups each have a single stride.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <memory>
 #include <mutex>
@@ -50,6 +51,9 @@ void run_program(const Program& p, hipStream_t s, hipEvent_t* ev) {
       case LK::Norm: launch_norm(p.device<NormDesc>(l), l.n, s); break;
       case LK::Bump: launch_bump(l.counter, l.bump_by, s); break;
       case LK::Jacobi: launch_jacobi(p.device<JacobiDesc>(l), l.n, (int)l.maxa, s); break;
+      case LK::Geqr: launch_geqr(p.device<GeqrDesc>(l), l.n, s); break;
+      case LK::Naive: launch_naive(p.device<NaiveDesc>(l), l.n, l.maxa, s); break;
+      case LK::Polish: launch_polish(p.device<PolishDesc>(l), l.n, (int)l.maxa, s); break;
       case LK::NormBig: {
         const NormDesc& nd = p.host<NormDesc>(l)[0];
         launch_norm_big(nd.x, nd.n, static_cast<double*>(l.aux), nd.nu_out, s);
@@ -399,6 +403,7 @@ struct Ctx {
   double *iH, *iZ, *iEw, *iEv, *iSg;  // eigenproblem of the inverse-canonical init
   size_t iTmpN = 0;
   int sweeps_done = 0;
+  int pos = 0;  // units (updates or half-steps) already run of the current sweep
   std::map<std::string, Program> programs;  // keyed by shape plan
   std::map<std::string, hipGraphExec_t> graphs;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -414,7 +419,19 @@ struct Ctx {
   long long n_trunc = 0;            // singular values truncated before inversion
   std::vector<double> prof_flops;
   size_t ws_bytes = 0;
+  // fit error per sweep (opts.track_error): merged C in FP64 per pair, the
+  // transfer-pass logs and arena, log ||A B||^2 per pair (normalized cores)
+  struct ErrState {
+    std::vector<std::vector<double*>> C;
+    double* logs = nullptr;
+    double* part = nullptr;
+    char* region = nullptr;
+    size_t region_bytes = 0;
+    std::vector<double> l4;
+  } err;
 };
+
+size_t err_region_bytes(const Ctx& X);
 
 int bytes_of(DType t) { return t == DType::F64 ? 8 : 4; }
 
@@ -422,7 +439,7 @@ int bytes_of(DType t) { return t == DType::F64 ? 8 : 4; }
 // Bond dims after the preprocessing and initial guess, and the capacity of
 // each of C's bonds over the fit (the ranks r = min(chi_max, n, m, cap)
 // settle within two sweeps; simulated here on the host).
-void plan_shapes(PairState& P, int chi_max, int schedule) {
+void plan_shapes(PairState& P, int chi_max, int schedule, int first_sweep, int first_bond, int first_half) {
   const int L = P.L, dd = P.dd;
   auto leftorth = [&](const std::vector<int>& in) {
     std::vector<int> c(in);
@@ -434,9 +451,19 @@ void plan_shapes(PairState& P, int chi_max, int schedule) {
   P.cB = leftorth(P.chiB_in);
   P.rcap.assign(L + 1, 1);
   for (int i = 1; i < L; ++i) P.rcap[i] = P.cA[i] * P.cB[i];
-  // initial C: the given guess (else A) right-orthogonalized
+  // initial C: the given guess (else A) right-orthogonalized, or left-
+  // orthogonalized when a serial fit starts with a backward sweep
   std::vector<int> c(P.C_in.empty() ? P.cA : P.chiC_in);
-  for (int i = L - 1; i >= 1; --i) c[i] = std::min(c[i], dd * c[i + 1]);
+  const bool fwd0 = first_sweep % 2 == 0;
+  if (schedule == MPO_SCHED_SERIAL && first_bond > 0) {  // mixed form around the next update's sites
+    const int i0 = fwd0 ? first_bond : L - 2 - first_bond;
+    for (int i = 1; i <= i0; ++i) c[i] = std::min(c[i], c[i - 1] * dd);
+    for (int i = L - 1; i >= i0 + 2; --i) c[i] = std::min(c[i], dd * c[i + 1]);
+  } else if (schedule == MPO_SCHED_SERIAL && !fwd0) {
+    for (int i = 1; i < L; ++i) c[i] = std::min(c[i], c[i - 1] * dd);
+  } else {
+    for (int i = L - 1; i >= 1; --i) c[i] = std::min(c[i], dd * c[i + 1]);
+  }
   P.cC = c;
   P.capC = c;
   std::vector<int> sim(c);
@@ -447,10 +474,11 @@ void plan_shapes(PairState& P, int chi_max, int schedule) {
   };
   for (int sw = 0; sw < 6; ++sw) {
     if (schedule == MPO_SCHED_SERIAL) {
-      if (sw % 2 == 0) for (int b = 1; b < L; ++b) upd(b);
-      else for (int b = L - 1; b >= 1; --b) upd(b);
+      const int skip = sw == 0 ? first_bond : 0;  // a resumed first sweep starts later
+      if ((sw + first_sweep) % 2 == 0) for (int b = 1 + skip; b < L; ++b) upd(b);
+      else for (int b = L - 1 - skip; b >= 1; --b) upd(b);
     } else {
-      for (int q = 0; q < 2; ++q) {
+      for (int q = (sw == 0 ? first_half : 0); q < 2; ++q) {
         std::vector<int> prev(sim);
         for (int b = 1; b < L; ++b)
           if ((b % 2 == 1) == (q == 0)) {
@@ -530,6 +558,10 @@ void add_fill(Program& P, const std::vector<FillDesc>& ds) {
 // General path: Cholesky R, X <- X R^{-1} by the row-wise TRSM; the product
 // of the triangular factors (upper, k x k) is left in Rout when non-null.
 // R scratch must hold 2 k x k; G scratch k x k.
+// keep (nullable): columns with keep[j] == 0 are zero in X and stay zero
+// (unit Gram diagonal, see CholDesc).  eta > 0: rank-revealing passes, a
+// column in the span of the previous ones (pivot <= eta G(j, j)) becomes a
+// zero column of Q instead of a failure.
 struct CholQRJob {
   double* X;
   int n, k, ld;
@@ -538,7 +570,15 @@ struct CholQRJob {
   double* Rout;  // nullable, k x k
   double* T;     // nullable, n x k temp (fast path)
   bool shifted = false;  // shifted first pass (general path only)
+  const double* keep = nullptr;
+  double eta = 0;
 };
+
+// Rank-revealing threshold of the Cholesky-QR passes: a column whose
+// remaining squared norm is at most this fraction of its own is dependent
+// (its independent part is below 1e-6 of its length, the drop cut; the
+// rounding of a dependent column's pivot is about k eps of its norm).
+constexpr double kRankEta = 1e-12;
 
 // Diagonal shift of shifted CholeskyQR (Fukaya, Kannan, Nakatsukasa,
 // Yamamoto, Yanagisawa, SIAM J. Sci. Comput. 2020): s = 11 (n k + k (k+1)) u
@@ -581,7 +621,7 @@ void add_chol_inv_blocked(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs
     double* S = L21 + (size_t)k2 * k1;
     double* T2 = S + (size_t)k2 * k2;
     gj.push_back(GemmJob{k, k, j.n, op64(src, false, lds), op64(src, false, lds), out64(j.G, k)});
-    c1.push_back(CholDesc{j.G, k, Rp, k, k1, X.flag});
+    c1.push_back(CholDesc{j.G, k, Rp, k, k1, X.flag, 0.0, j.keep, j.eta});
     ap.push_back(GemmJob{j.n, k1, k1, op64(src, true, lds), op64(Rp, false, k), out64(dst, ldd)});
     if (k2 == 0) continue;
     l21.push_back(GemmJob{k2, k1, k1, op64(j.G + (size_t)k1 * k, true, k), op64(Rp, false, k), out64(L21, k1)});
@@ -590,7 +630,8 @@ void add_chol_inv_blocked(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs
     sj.alpha = -1.0;
     sj.beta = 1;
     s22.push_back(sj);
-    c2.push_back(CholDesc{S, k2, Rp + (size_t)k1 * k + k1, k, k2, X.flag});
+    c2.push_back(CholDesc{S, k2, Rp + (size_t)k1 * k + k1, k, k2, X.flag, 0.0,
+                          j.keep ? j.keep + k1 : nullptr, j.eta});
     t2.push_back(GemmJob{k1, k2, k2, op64(L21, false, k1), op64(Rp + (size_t)k1 * k + k1, false, k), out64(T2, k2)});
     GemmJob xj{k1, k2, k1, op64(Rp, true, k), op64(T2, false, k2), out64(Rp + k1, k)};
     xj.alpha = -1.0;
@@ -620,13 +661,95 @@ void add_chol_inv_blocked(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs
   add_gemm(P, X.sb, Mode::F64, ap, qc.apply, 0);
 }
 
-void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int passes, bool gauge = false) {
+// One Newton-Schulz pass Q <- Q (3 I - Q^T Q) / 2 for Q with nearly
+// orthonormal columns (zero columns allowed): the Gram GEMM, G <- (3 I - G)/2
+// and the product, from X to the temp T on even passes and back on odd ones
+// (the ping-pong of the Cholesky passes).  It takes an orthogonality error e
+// to (3/4) e^2 without a Cholesky factorization; the span is unchanged and Q
+// moves by O(e).
+void add_polish_pass(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int pass, bool gauge) {
   if (jobs.empty()) return;
   const QrClasses qc = qr_classes(gauge);
-  bool fast = true, blocked = true;
+  std::vector<GemmJob> gj, ap;
+  std::vector<PolishDesc> pd;
+  int maxk = 1;
+  for (auto& j : jobs) {
+    double* src = pass % 2 == 1 ? j.T : j.X;
+    double* dst = pass % 2 == 1 ? j.X : j.T;
+    const int lds = pass % 2 == 1 ? j.k : j.ld;
+    const int ldd = pass % 2 == 1 ? j.ld : j.k;
+    gj.push_back(GemmJob{j.k, j.k, j.n, op64(src, false, lds), op64(src, false, lds), out64(j.G, j.k)});
+    pd.push_back(PolishDesc{j.G, j.k});
+    ap.push_back(GemmJob{j.n, j.k, j.k, op64(src, true, lds), op64(j.G, false, j.k), out64(dst, ldd)});
+    maxk = std::max(maxk, j.k);
+  }
+  add_gemm(P, X.sb, Mode::F64, gj, qc.gram, 0);
+  add_simple(P, LK::Polish, pd, maxk, gauge ? "gauge_polish" : "qr_polish");
+  add_gemm(P, X.sb, Mode::F64, ap, qc.apply, 0);
+}
+
+// One pass of the register path: G = X^T X, R^{-1} from the register
+// Cholesky, X R^{-1} into the other buffer of the ping-pong.
+void add_cholqr_fast_pass(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int pass, bool gauge) {
+  const QrClasses qc = qr_classes(gauge);
+  std::vector<GemmJob> gj, tj;
+  std::vector<CholDesc> cd;
+  int maxk = 1;
+  for (auto& j : jobs) {
+    double* src = pass % 2 == 1 ? j.T : j.X;
+    double* dst = pass % 2 == 1 ? j.X : j.T;
+    const int lds = pass % 2 == 1 ? j.k : j.ld;
+    const int ldd = pass % 2 == 1 ? j.ld : j.k;
+    gj.push_back(GemmJob{j.k, j.k, j.n, op64(src, false, lds), op64(src, false, lds), out64(j.G, j.k)});
+    double* Rp = j.R + (size_t)(pass % 2) * j.k * j.k;
+    CholDesc c{j.G, j.k, Rp, j.k, j.k, X.flag};
+    c.keep = j.keep;
+    c.eta = j.eta;
+    cd.push_back(c);
+    tj.push_back(GemmJob{j.n, j.k, j.k, op64(src, true, lds), op64(Rp, false, j.k), out64(dst, ldd)});
+    maxk = std::max(maxk, j.k);
+  }
+  add_gemm(P, X.sb, Mode::F64, gj, qc.gram, 0);
+  Launch l;
+  l.kind = LK::Chol;
+  l.off = P.push(cd);
+  l.n = (int)cd.size();
+  l.maxa = maxk;
+  l.maxb = 1;
+  l.cls = qc.chol_inv;
+  for (auto& j : jobs) l.flops += 2.0 / 3.0 * j.k * (double)j.k * j.k;
+  P.launches.push_back(l);
+  add_gemm(P, X.sb, Mode::F64, tj, qc.apply, 0);
+}
+
+// `polish_last`: the last of the passes is a Newton-Schulz step instead of a
+// Cholesky pass (needs the temp T; the earlier passes leave Q orthonormal to
+// far better than 1 so the step converges).
+void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int passes, bool gauge = false,
+                bool polish_last = false) {
+  if (jobs.empty()) return;
+  const QrClasses qc = qr_classes(gauge);
+  bool fast = true, blocked = true, temp = true;
   for (auto& j : jobs) {
     fast = fast && j.k <= kRegMax && !j.Rout && j.T;
     blocked = blocked && j.k <= 2 * kRegMax && !j.Rout && j.T;
+    temp = temp && j.T && !j.Rout;
+  }
+  if (polish_last && temp) {
+    // Cholesky passes first (through whichever path fits), then the step
+    for (int pass = 0; pass + 1 < passes; ++pass) {
+      if (fast) add_cholqr_fast_pass(X, P, jobs, pass, gauge);
+      else if (blocked) add_chol_inv_blocked(X, P, jobs, pass, gauge);
+      else throw Error{MPO_ERR_UNSUPPORTED, "polished Cholesky-QR: k above 2 kRegMax"};
+    }
+    add_polish_pass(X, P, jobs, passes - 1, gauge);
+    if (passes % 2 == 1) {
+      std::vector<PermDesc> cp;
+      for (auto& j : jobs)
+        cp.push_back(perm4(j.T, 0, j.X, 0, {1, 1, j.n, j.k}, {0, 0, j.k, 1}, {0, 0, j.ld, 1}));
+      add_perm(P, cp, "copy");
+    }
+    return;
   }
   if (!fast && blocked) {
     for (int pass = 0; pass < passes; ++pass) add_chol_inv_blocked(X, P, jobs, pass, gauge);
@@ -652,6 +775,8 @@ void add_cholqr(Ctx& X, Program& P, const std::vector<CholQRJob>& jobs, int pass
       double* Rp = j.Rout ? j.R : j.R + (size_t)(pass % 2) * j.k * j.k;
       CholDesc c{j.G, j.k, Rp, j.k, j.k, X.flag};
       if (j.shifted && pass == 0 && !fast) c.shift = chol_shift(j.n, j.k);
+      c.keep = j.keep;
+      c.eta = j.eta;
       cd.push_back(c);
       if (fast)
         tj.push_back(GemmJob{j.n, j.k, j.k, op64(src, true, lds), op64(Rp, false, j.k), out64(dst, ldd)});
@@ -804,6 +929,20 @@ void carve(Ctx& X, Carver& cv) {
   X.sb.counters = cv.take<int>(X.sb.ccap);
   X.arena_cap = (size_t)64 << 20;
   X.arena = cv.take<char>(X.arena_cap);
+  if (X.o.track_error) {
+    X.err.C.assign(X.pairs.size(), {});
+    int Lmax = 1;
+    for (size_t p = 0; p < X.pairs.size(); ++p) {
+      const PairState& P = X.pairs[p];
+      Lmax = std::max(Lmax, P.L);
+      for (int i = 0; i < P.L; ++i)
+        X.err.C[p].push_back(cv.take<double>((size_t)P.capC[i] * P.dd * P.capC[i + 1]));
+    }
+    X.err.logs = cv.take<double>(3 * (size_t)(Lmax + 1));
+    X.err.part = cv.take<double>(1024);
+    X.err.region_bytes = err_region_bytes(X);
+    X.err.region = cv.take<char>(X.err.region_bytes);
+  }
 }
 
 // ------------------------------------------------------------------ extension jobs
@@ -847,20 +986,33 @@ double flops_e1m(const PairState& P, int j) { return 2.0 * P.cC[j + 1] * P.cA[j 
 double flops_e2m(const PairState& P, int j) { return 2.0 * P.cC[j + 1] * P.dd * P.d * P.cA[j + 1] * P.cA[j] * P.cB[j]; }
 
 // ------------------------------------------------------------------ initialization
+// Shifted Cholesky-QR3 of an initialization step (the R factors multiplied
+// into iRt), rank-revealing: a dependent column (a core of lower rank than
+// its bond, e.g. an unused bond state) becomes a zero column of Q with a zero
+// row of R instead of a failure, where Householder QR would complete Q with
+// an arbitrary orthonormal column of the same (zero) weight.
+CholQRJob init_qr(double* Xm, int n, int k, Ctx& X) {
+  CholQRJob j{Xm, n, k, k, X.iG, X.iR1, X.iRt, nullptr, true};
+  j.eta = kRankEta;
+  return j;
+}
+
 // Left-orthogonalization (Alg. 5 preprocessing) of one MPO held in `cores`,
 // whose input bond dims are `chi_in`; `out_dims` are the clipped dims.
-void rec_left_orth(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores,
-                   const std::vector<int>& chi_in, const std::vector<int>& out_dims, double* nu) {
-  const int L = S.L, dd = S.dd;
-  std::vector<int> cur(chi_in);
-  for (int i = 0; i + 1 < L; ++i) {
-    const int p = cur[i] * dd, q = chi_in[i + 1];
-    const int nn = dd * chi_in[i + 2];  // columns of the next core (its right bond untouched yet)
+// QR sweep over sites 0 .. stop-1 of `cores` (bond dims `cur`, updated):
+// each core left-orthogonalized by a shifted Cholesky-QR3 with R carried into
+// the next core, or clipped (identity core, everything carried) where it has
+// fewer rows than columns.
+void rec_qr_sweep(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores, std::vector<int>& cur,
+                  int stop) {
+  const int dd = S.dd;
+  for (int i = 0; i < stop; ++i) {
+    const int p = cur[i] * dd, q = cur[i + 1];
+    const int nn = dd * cur[i + 2];  // columns of the next core (its right bond untouched yet)
     if (p >= q) {
-      add_cholqr(X, P, {CholQRJob{cores[i], p, q, q, X.iG, X.iR1, X.iRt, nullptr, true}}, 3);
+      add_cholqr(X, P, {init_qr(cores[i], p, q, X)}, 3);
       add_gemm(P, X.sb, Mode::F64, {GemmJob{q, nn, q, op64(X.iRt, true, q), op64(cores[i + 1], false, nn),
                                             out64(X.iTmp, nn)}}, "init", 0);
-      cur[i + 1] = q;
     } else {
       add_gemm(P, X.sb, Mode::F64, {GemmJob{p, nn, q, op64(cores[i], true, q), op64(cores[i + 1], false, nn),
                                             out64(X.iTmp, nn)}}, "init", 0);
@@ -869,23 +1021,19 @@ void rec_left_orth(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores
     }
     add_perm(P, {perm4(X.iTmp, 0, cores[i + 1], 0, {1, 1, cur[i + 1], nn}, {0, 0, nn, 1}, {0, 0, nn, 1})}, "copy");
   }
-  for (int i = 0; i <= L; ++i)
-    if (cur[i] != out_dims[i]) throw Error{MPO_ERR_SHAPE, "left orthogonalization shape plan mismatch"};
-  add_simple(P, LK::Norm, std::vector<NormDesc>{NormDesc{cores[L - 1], (long long)cur[L - 1] * dd, nu}}, 0, "init");
 }
 
-// The initial C (A, or the given guess) right-orthogonalized by an RQ sweep
-// L..2 (Sec. 2.3.1).
-void rec_right_orth(Ctx& X, Program& P, PairState& S) {
+// RQ sweep over sites L-1 .. stop+1 of C (bond dims `cur`, updated): each
+// core right-orthogonalized (X^T = Q R, X = R^T Q^T) with R^T carried into
+// the previous core, or clipped.
+void rec_rq_sweep(Ctx& X, Program& P, PairState& S, std::vector<int>& cur, int stop) {
   const int L = S.L, dd = S.dd;
-  std::vector<int> cur(S.C_in.empty() ? S.cA : S.chiC_in);
-  for (int j = L - 1; j >= 1; --j) {
+  for (int j = L - 1; j > stop; --j) {
     const int p = cur[j], q = dd * cur[j + 1];
     const int mp = cur[j - 1] * dd;  // rows of the previous core
     if (p <= q) {
-      // X^T = Q R (R_jj > 0), X = R^T Q^T: work on the transpose
       add_perm(P, {perm4(S.C64[j], 0, X.iXt, 0, {1, 1, p, q}, {0, 0, q, 1}, {0, 0, 1, p})}, "copy");
-      add_cholqr(X, P, {CholQRJob{X.iXt, q, p, p, X.iG, X.iR1, X.iRt, nullptr, true}}, 3);
+      add_cholqr(X, P, {init_qr(X.iXt, q, p, X)}, 3);
       add_perm(P, {perm4(X.iXt, 0, S.C64[j], 0, {1, 1, q, p}, {0, 0, p, 1}, {0, 0, 1, q})}, "copy");
       add_gemm(P, X.sb, Mode::F64, {GemmJob{mp, p, p, op64(S.C64[j - 1], true, p), op64(X.iRt, true, p),
                                             out64(X.iTmp, p)}}, "init", 0);
@@ -898,8 +1046,41 @@ void rec_right_orth(Ctx& X, Program& P, PairState& S) {
       cur[j] = q;
     }
   }
-  for (int i = 0; i <= L; ++i)
-    if (cur[i] != S.cC[i]) throw Error{MPO_ERR_SHAPE, "right orthogonalization shape plan mismatch"};
+}
+
+void check_dims(const std::vector<int>& cur, const std::vector<int>& want, const char* what) {
+  if (cur != want) throw Error{MPO_ERR_SHAPE, std::string(what) + " shape plan mismatch"};
+}
+
+// Left-orthogonalization (Alg. 5 preprocessing) of one MPO held in `cores`,
+// whose input bond dims are `chi_in`; `out_dims` are the clipped dims.  With
+// `nu`, the norm is split off the last core into *nu.
+void rec_left_orth(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores,
+                   const std::vector<int>& chi_in, const std::vector<int>& out_dims, double* nu) {
+  const int L = S.L, dd = S.dd;
+  std::vector<int> cur(chi_in);
+  rec_qr_sweep(X, P, S, cores, cur, L - 1);
+  check_dims(cur, out_dims, "left orthogonalization");
+  if (nu)
+    add_simple(P, LK::Norm, std::vector<NormDesc>{NormDesc{cores[L - 1], (long long)cur[L - 1] * dd, nu}}, 0,
+               "init");
+}
+
+// The initial C (A, or the given guess) right-orthogonalized by an RQ sweep
+// L..2 (Sec. 2.3.1).
+void rec_right_orth(Ctx& X, Program& P, PairState& S) {
+  std::vector<int> cur(S.C_in.empty() ? S.cA : S.chiC_in);
+  rec_rq_sweep(X, P, S, cur, 0);
+  check_dims(cur, S.cC, "right orthogonalization");
+}
+
+// The initial C in site-canonical form around sites i0, i0+1 (Sec. 2.3.1):
+// QR sweep over the sites left of them, RQ sweep over the sites right of them.
+void rec_mixed_orth(Ctx& X, Program& P, PairState& S, int i0) {
+  std::vector<int> cur(S.C_in.empty() ? S.cA : S.chiC_in);
+  rec_qr_sweep(X, P, S, S.C64, cur, i0);
+  rec_rq_sweep(X, P, S, cur, i0 + 1);
+  check_dims(cur, S.cC, "mixed orthogonalization");
 }
 
 void rec_repack(Ctx& X, Program& P, PairState& S) {
@@ -996,6 +1177,8 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
   std::vector<CholQRJob> qr;
   std::vector<EigDesc> ed;
   std::vector<SvalDesc> sv;
+  std::vector<ScaleDesc> mz;
+  long long maxz = 1;
   bool reg = true;  // every eigenproblem on the register path
   double fth = 0, fsk = 0;
   long long maxom = 1;
@@ -1016,7 +1199,9 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
       maxom = std::max(maxom, (long long)b.m * b.k);
       yj.push_back(GemmJob{b.n, b.k, b.m, opW(X, B.theta, true, b.m), op64(B.omega, false, b.k),
                            out64(B.Y, b.k)});
-      qr.push_back(CholQRJob{B.Y, b.n, b.k, b.k, B.G, B.R, nullptr, B.Y2});
+      CholQRJob qj{B.Y, b.n, b.k, b.k, B.G, B.R, nullptr, B.Y2};
+      qj.eta = kRankEta;  // a sketch of a rank-deficient Theta has dependent columns
+      qr.push_back(qj);
       bk.push_back(GemmJob{b.k, b.m, b.n, op64(B.Y, false, b.k), opW(X, B.theta, false, b.m),
                            out64(B.Bk, b.m)});
       hj.push_back(GemmJob{b.k, b.k, b.m, op64(B.Bk, true, b.m), op64(B.Bk, true, b.m), out64(B.H, b.k)});
@@ -1030,13 +1215,17 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
     }
     ed.push_back(EigDesc{B.H, b.k, b.k, b.r, B.evals, B.Z, b.r, B.eigw, X.flag});
     reg = reg && b.k <= kRegMax;
-    sv.push_back(SvalDesc{B.evals, B.S, b.r, halfstep ? 1 : 0, X.flag, B.keep, X.flag + 2});
+    sv.push_back(SvalDesc{B.evals, B.S, b.r, 0, X.flag, B.keep, X.flag + 2});
+    // the eigenvectors of dropped values become exact zero columns
+    mz.push_back(ScaleDesc{B.Z, B.Z, b.k, b.r, b.r, b.r, nullptr, B.keep, 0, 2});
     maxr = std::max(maxr, b.r);
+    maxz = std::max(maxz, (long long)b.k * b.r);
   }
   add_gemm(P, X.sb, X.wmode, th, "theta", fth);
   add_simple(P, LK::Omega, om, maxom, "omega");
   add_gemm(P, X.sb, Mode::F64, yj, "sketch", fsk / 2);
-  if (!qr.empty()) add_cholqr(X, P, qr, 2);
+  // range finder: a rank-revealing Cholesky-QR pass, then a Newton-Schulz step
+  if (!qr.empty()) add_cholqr(X, P, qr, 2, false, true);
   add_gemm(P, X.sb, Mode::F64, bk, "project", fsk / 2);
   // split H jobs by operand type (sketched: FP64 Bk; plain: working-type Theta)
   std::vector<GemmJob> h64, hw;
@@ -1045,6 +1234,8 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
   add_gemm(P, X.sb, Mode::F64, hw, "gram", 0);
   add_eig(P, X.sb, ed, reg, "eig");
   add_simple(P, LK::Sval, sv, maxr, "svals");
+  add_simple(P, LK::Scale, mz, maxz, "scale");
+  (void)halfstep;
 }
 
 // Site-canonical assignment (Alg. 3) and environment update for a group of
@@ -1079,7 +1270,9 @@ void rec_assign_site(Ctx& X, Program& P, std::vector<BondJob>& bj) {
     maxr = std::max(maxr, r);
     if (fwd && b.tr) sc0.push_back(ScaleDesc{Ci, Ci, b.n, r, r, r, nullptr, B.S, 0, 1});
     if (fwd) {
-      orth.push_back(CholQRJob{Ci, b.n, r, r, B.G, B.R, nullptr, B.Y2});
+      CholQRJob oj{Ci, b.n, r, r, B.G, B.R, nullptr, B.Y2};
+      oj.keep = B.keep;
+      orth.push_back(oj);
       sg.push_back(SignDesc{Ci, b.n, r, r, B.sign, nullptr});
       svt.push_back(GemmJob{r, b.m, b.n, op64(Ci, false, r), opW(X, B.theta, false, b.m), out64(B.SVt, b.m)});
       // C_{i+1}[c'][su][c''] = SVt[c'][(c'', su)]
@@ -1099,7 +1292,9 @@ void rec_assign_site(Ctx& X, Program& P, std::vector<BondJob>& bj) {
           vj.push_back(GemmJob{b.m, r, b.n, opW(X, B.theta, false, b.m), op64(B.Z, false, r),
                                out64(B.V, r)});
         sc1.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 1});
-        orth.push_back(CholQRJob{B.V, b.m, r, r, B.G, B.R, nullptr, B.Y2});
+        CholQRJob oj{B.V, b.m, r, r, B.G, B.R, nullptr, B.Y2};
+        oj.keep = B.keep;
+        orth.push_back(oj);
         sc2.push_back(ScaleDesc{Ci, Ci, b.n, r, r, r, nullptr, B.S, 0, 0});  // C_i = U S
       }
       sg.push_back(SignDesc{Ci, b.n, r, r, B.sign, nullptr});
@@ -1111,15 +1306,19 @@ void rec_assign_site(Ctx& X, Program& P, std::vector<BondJob>& bj) {
                              outW(X, S.Renv[i + 1], N, S.amR[i + 1])});
       fenv += 2.0 * r * N * b.m;
     }
+    // the bond's singular values, kept for read-out
+    perm.push_back(perm4(B.S, 0, S.Yv[i + 1], 0, {1, 1, 1, r}, {0, 0, 0, 1}, {0, 0, 0, 1}));
     maxsc = std::max(maxsc, (long long)std::max(b.n, b.m) * r);
     (void)cl;
   }
   add_gemm(P, X.sb, Mode::F64, uq, "assemble", 0);
   add_gemm(P, X.sb, Mode::F64, tq, "assemble", 0);
   add_perm(P, cp, "copy");
+  // U = Q Z (or V) is orthonormal up to the eigenvectors' rounding: one
+  // Newton-Schulz step restores it to working accuracy
   if (fwd) {
     add_simple(P, LK::Scale, sc0, maxsc, "scale");
-    add_cholqr(X, P, orth, 1, true);
+    add_cholqr(X, P, orth, 1, true, true);
     add_simple(P, LK::Sign, sg, maxr, "sign");
     add_gemm(P, X.sb, Mode::F64, svt, "assemble", 0);
     add_perm(P, perm, "copy");
@@ -1127,7 +1326,7 @@ void rec_assign_site(Ctx& X, Program& P, std::vector<BondJob>& bj) {
     add_gemm(P, X.sb, Mode::F64, vj, "assemble", 0);
     add_perm(P, cpv, "copy");
     add_simple(P, LK::Scale, sc1, maxsc, "scale");
-    add_cholqr(X, P, orth, 1, true);
+    add_cholqr(X, P, orth, 1, true, true);
     add_simple(P, LK::Scale, sc2, maxsc, "scale");
     add_simple(P, LK::Sign, sg, maxr, "sign");
     add_simple(P, LK::Scale, sc3, maxsc, "scale");
@@ -1181,7 +1380,7 @@ void rec_inverse_canonical(Ctx& X, Program& P, PairState& S) {
     if (q > 512 || p < q) throw Error{MPO_ERR_UNSUPPORTED, "inverse canonical form: bond above 512"};
     double* Xi = S.C64[i];
     // X = Q R (shifted CholeskyQR3; R accumulated in iRt)
-    add_cholqr(X, P, {CholQRJob{Xi, p, q, q, X.iG, X.iR1, X.iRt, nullptr, true}}, 3);
+    add_cholqr(X, P, {init_qr(Xi, p, q, X)}, 3);
     // precondition: W0 = R Z with Z the eigenvectors of R^T R (its columns
     // are then orthogonal up to clusters of tiny singular values), then
     // one-sided Jacobi on W0: W0 V' = Ur diag(S) with high relative accuracy
@@ -1195,7 +1394,7 @@ void rec_inverse_canonical(Ctx& X, Program& P, PairState& S) {
       Launch l;
       l.kind = LK::Jacobi;
       l.off = P.push(std::vector<JacobiDesc>{
-          JacobiDesc{X.iG, q, q, X.iR2, q, S.Yv[i + 1], X.iJ, kInvTrunc, X.flag + 2}});
+          JacobiDesc{X.iG, q, q, X.iR2, q, S.Yv[i + 1], X.iJ, kDrop, X.flag + 2}});
       l.n = 1;
       l.maxa = q;
       l.cls = "init";
@@ -1245,7 +1444,7 @@ void rec_assign_inverse(Ctx& X, Program& P, std::vector<BondJob>& bj) {
   std::vector<PermDesc> cp, perm;
   std::vector<CholQRJob> orthU, orthV;
   std::vector<SignDesc> sg;
-  std::vector<ScaleDesc> sv1, sv2, su, sv3, mk;
+  std::vector<ScaleDesc> sv1, sv2, su, sv3;
   std::vector<PermDesc> cpS;
   double fenv = 0;
   int maxr = 1;
@@ -1274,9 +1473,13 @@ void rec_assign_inverse(Ctx& X, Program& P, std::vector<BondJob>& bj) {
                              out64(B.V, r)});
       sv1.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 1});
     }
-    orthU.push_back(CholQRJob{Ci, b.n, r, r, B.G, B.R, nullptr, r <= 2 * kRegMax ? B.Y2 : nullptr});
+    CholQRJob ou{Ci, b.n, r, r, B.G, B.R, nullptr, B.Y2};
+    ou.keep = B.keep;
+    orthU.push_back(ou);
     // runs after orthU in stream order, so it reuses the same G and R scratch
-    orthV.push_back(CholQRJob{B.V, b.m, r, r, B.G, B.R, nullptr, r <= 2 * kRegMax ? B.SVt : nullptr});
+    CholQRJob ov{B.V, b.m, r, r, B.G, B.R, nullptr, B.SVt};
+    ov.keep = B.keep;
+    orthV.push_back(ov);
     sg.push_back(SignDesc{Ci, b.n, r, r, B.sign, nullptr});
     sv2.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.sign, 0, 0});
     envl.push_back(GemmJob{r, N, b.n, op64(Ci, false, r), opW(X, S.XL[i], false, N, S.amXL[i]),
@@ -1289,10 +1492,8 @@ void rec_assign_inverse(Ctx& X, Program& P, std::vector<BondJob>& bj) {
     perm.push_back(perm4(B.V, 0, Cn, 0, {r, cr, dd, 1}, {1, (long long)dd * r, r, 0},
                          {(long long)dd * cr, 1, cr, 0}));                  // Psi_{i+1} = S V^T
     cpS.push_back(perm4(B.S, 0, S.Yv[i + 1], 0, {1, 1, 1, r}, {0, 0, 0, 1}, {0, 0, 0, 1}));
-    // truncation before inversion: zero U, V columns and S for dropped values
-    mk.push_back(ScaleDesc{Ci, Ci, b.n, r, r, r, nullptr, B.keep, 0, 0});
-    mk.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.keep, 0, 0});
-    mk.push_back(ScaleDesc{B.S, B.S, 1, r, r, r, nullptr, B.keep, 0, 0});
+    // truncation before inversion: the dropped values are already zero in S
+    // and their columns in Z, hence in U and V
     maxr = std::max(maxr, r);
     maxsc = std::max(maxsc, (long long)std::max(b.n, b.m) * r);
   }
@@ -1300,11 +1501,12 @@ void rec_assign_inverse(Ctx& X, Program& P, std::vector<BondJob>& bj) {
   add_gemm(P, X.sb, Mode::F64, vj, "assemble", 0);
   add_perm(P, cp, "copy");
   add_simple(P, LK::Scale, sv1, maxsc, "scale");
-  add_cholqr(X, P, orthU, 1, true);
-  add_cholqr(X, P, orthV, 1, true);
+  // U = Q Z and V = B_k^T Z / S are orthonormal up to rounding: one
+  // Newton-Schulz step each
+  add_cholqr(X, P, orthU, 1, true, true);
+  add_cholqr(X, P, orthV, 1, true, true);
   add_simple(P, LK::Sign, sg, maxr, "sign");
   add_simple(P, LK::Scale, sv2, maxsc, "scale");
-  add_simple(P, LK::Scale, mk, maxsc, "scale");
   add_gemm(P, X.sb, X.wmode, envl, "env_update", fenv / 2);
   add_gemm(P, X.sb, X.wmode, envr, "env_update", fenv / 2);
   add_simple(P, LK::Scale, su, maxsc, "scale");
@@ -1400,11 +1602,29 @@ void rec_init_pair(Ctx& X, Program& P, PairState& S, int pair) {
     rec_reset_amax(X, P, sl);
   }
   rec_repack(X, P, S);
-  rec_right_orth(X, P, S);
+  // singular values per bond start at zero (the serial schedule writes them
+  // at each update; the inverse canonical form fills them below)
+  {
+    std::vector<FillDesc> fz;
+    for (int b = 1; b < L; ++b) fz.push_back(FillDesc{S.Yv[b], 2LL * S.capC[b], 0, 0, 0});
+    add_fill(P, fz);
+  }
+  const bool serial = X.o.schedule == MPO_SCHED_SERIAL;
+  const bool backward_first = serial && X.o.first_sweep % 2 == 1;
+  const int i0 = !serial || X.o.first_bond == 0 ? -1
+                 : backward_first ? L - 2 - X.o.first_bond : X.o.first_bond;
+  if (i0 >= 0) {
+    rec_mixed_orth(X, P, S, i0);
+  } else if (backward_first) {
+    std::vector<int> in(S.C_in.empty() ? S.cA : S.chiC_in);
+    rec_left_orth(X, P, S, S.C64, in, S.cC, nullptr);
+  } else {
+    rec_right_orth(X, P, S);
+  }
   const int f64 = X.wt == DType::F64 ? 1 : 0;
   add_fill(P, {FillDesc{S.Lenv[0], 0, 1, 1, f64}, FillDesc{S.Renv[L], 0, 1, 1, f64}});
   std::vector<unsigned*> sl{S.amL[0], S.amR[L]};
-  for (int j = 1; j < L; ++j) sl.insert(sl.end(), {S.amR[j], S.amXR[j - 1]});
+  for (int j = 1; j < L; ++j) sl.insert(sl.end(), {S.amR[j], S.amXR[j - 1], S.amL[j], S.amXL[j - 1]});
   sl.push_back(X.scratch[0].amT);
   rec_reset_amax(X, P, sl);
   if (X.o.schedule == MPO_SCHED_EVEN_ODD) {
@@ -1412,7 +1632,17 @@ void rec_init_pair(Ctx& X, Program& P, PairState& S, int pair) {
     (void)pair;
     return;
   }
-  for (int j = L - 1; j >= 1; --j) rec_right_env_from_core(X, P, S, j, j >= 2, X.scratch[0]);
+  if (i0 >= 0 && !backward_first) {  // forward from bond i0: left envs up to it, right side cached
+    for (int i = 0; i < i0; ++i) rec_left_env_from_core(X, P, S, i, S.C64[i], S.cC[i + 1], X.scratch[0]);
+    for (int j = L - 1; j >= i0 + 1; --j) rec_right_env_from_core(X, P, S, j, j >= i0 + 2, X.scratch[0]);
+  } else if (i0 >= 0) {  // backward from bond i0: right envs down to it, left side cached
+    for (int j = L - 1; j >= i0 + 2; --j) rec_right_env_from_core(X, P, S, j, true, X.scratch[0]);
+    for (int i = 0; i <= i0; ++i) rec_left_env_from_core(X, P, S, i, S.C64[i], S.cC[i + 1], X.scratch[0]);
+  } else if (backward_first) {  // all left environments and the cached left extensions
+    for (int i = 0; i + 1 < L; ++i) rec_left_env_from_core(X, P, S, i, S.C64[i], S.cC[i + 1], X.scratch[0]);
+  } else {
+    for (int j = L - 1; j >= 1; --j) rec_right_env_from_core(X, P, S, j, j >= 2, X.scratch[0]);
+  }
   (void)pair;
 }
 
@@ -1437,6 +1667,14 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
   if (o->tau != 0.0) throw Error{MPO_ERR_UNSUPPORTED, "only tau = 0 (fixed bond cap) is run"};
   if (o->precision < 0 || o->precision > 3) throw Error{MPO_ERR_INVALID_ARG, "bad precision"};
   if (o->schedule < 0 || o->schedule > 1) throw Error{MPO_ERR_INVALID_ARG, "bad schedule"};
+  if (o->first_sweep < 0 || o->first_sweep > (1 << 24)) throw Error{MPO_ERR_INVALID_ARG, "bad first_sweep"};
+  if (o->first_bond < 0) throw Error{MPO_ERR_INVALID_ARG, "bad first_bond"};
+  if (o->first_bond > 0 && (o->schedule != MPO_SCHED_SERIAL || n_pairs != 1))
+    throw Error{MPO_ERR_UNSUPPORTED, "first_bond > 0 needs the serial schedule and one pair"};
+  if (o->first_half < 0 || o->first_half > 1) throw Error{MPO_ERR_INVALID_ARG, "bad first_half"};
+  if (o->first_half > 0 && o->schedule != MPO_SCHED_EVEN_ODD)
+    throw Error{MPO_ERR_UNSUPPORTED, "first_half needs the even/odd schedule"};
+  if (o->track_error < 0 || o->track_error > 1) throw Error{MPO_ERR_INVALID_ARG, "bad track_error"};
   X.wmode = o->precision == MPO_FP64 ? Mode::F64
             : o->precision == MPO_FP32 ? Mode::F32
             : o->precision == MPO_BF16 ? Mode::BF16 : Mode::BF16X3;
@@ -1476,7 +1714,8 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
     S.chi_max = pr.chi_max > 0 ? pr.chi_max : o->chi_max;
     if (S.chi_max + std::max(o->sketch_p, 0) > 512)
       throw Error{MPO_ERR_UNSUPPORTED, "chi_max + sketch_p above 512"};
-    plan_shapes(S, S.chi_max, o->schedule);
+    plan_shapes(S, S.chi_max, o->schedule, o->first_sweep, o->first_bond, o->first_half);
+    if (o->first_bond > L - 2) throw Error{MPO_ERR_INVALID_ARG, "first_bond must be below L - 1"};
     for (int b = 0; b <= L; ++b)
       if (S.capC[b] * S.dd > 2048) throw Error{MPO_ERR_UNSUPPORTED, "two-site dimension above 2048"};
   }
@@ -1505,32 +1744,39 @@ struct SweepPlan {
   int uses = 0;
 };
 
-void record_sweep(Ctx& X, SweepPlan& sp, bool fwd) {
+// Units of a sweep: two-site updates (serial, per pair) or half-steps.
+int sweep_units(const Ctx& X) {
+  return X.o.schedule == MPO_SCHED_EVEN_ODD ? 2 : X.pairs[0].L - 1;
+}
+
+// Records units [start, start + count) of the current sweep (direction fwd),
+// and the advance of the Philox sweep counter when they end the sweep.  A
+// serial segment that is not a whole sweep needs one pair (first_bond or
+// mpo_fit_updates).
+void record_segment(Ctx& X, SweepPlan& sp, bool fwd, int start, int count) {
   if (X.o.schedule == MPO_SCHED_EVEN_ODD) {
-    rec_half_step(X, sp.prog, 0);
-    rec_half_step(X, sp.prog, 1);
+    for (int q = start; q < start + count; ++q) rec_half_step(X, sp.prog, q);
+  } else {
+    for (size_t p = 0; p < X.pairs.size(); ++p) {
+      PairState& S = X.pairs[p];
+      for (int u = start; u < start + count; ++u) {
+        const int i = fwd ? u : S.L - 2 - u;
+        rec_serial_bond(X, sp.prog, S, (int)p, i, fwd);
+      }
+    }
+  }
+  if (start + count == sweep_units(X)) {
     Launch b;
     b.kind = LK::Bump;
     b.counter = X.sweep_dev;
     b.bump_by = 1;
     b.cls = "bump";
     sp.prog.launches.push_back(b);
-    for (auto& S : X.pairs) sp.cC_after.push_back(S.cC);
-    return;
   }
-  for (size_t p = 0; p < X.pairs.size(); ++p) {
-    PairState& S = X.pairs[p];
-    if (fwd) for (int i = 0; i + 1 < S.L; ++i) rec_serial_bond(X, sp.prog, S, (int)p, i, true);
-    else for (int i = S.L - 2; i >= 0; --i) rec_serial_bond(X, sp.prog, S, (int)p, i, false);
-  }
-  Launch b;
-  b.kind = LK::Bump;
-  b.counter = X.sweep_dev;
-  b.bump_by = 1;
-  b.cls = "bump";
-  sp.prog.launches.push_back(b);
   for (auto& S : X.pairs) sp.cC_after.push_back(S.cC);
 }
+
+void record_sweep(Ctx& X, SweepPlan& sp, bool fwd) { record_segment(X, sp, fwd, 0, sweep_units(X)); }
 
 
 // ------------------------------------------------------------------ adjoint
@@ -1865,8 +2111,10 @@ void add_normalize(Program& P, const Ten& t, double* nu_out, double* part) {
   P.launches.push_back(l);
 }
 
+// `passes` selects the four-layer (1), three-layer (2) and two-layer (4)
+// passes; each writes its L + 1 logs only.
 void rec_check(Program& P, Arena& ar, const SplitBuf& sb, const mpo_tt& A, const mpo_tt& B,
-               const mpo_tt& Cm, const CheckPlan& cp) {
+               const mpo_tt& Cm, const CheckPlan& cp, int passes = 7) {
   const int L = A.L, d = A.d;
   const Mode mode = Mode::F64;
   const DType t64 = DType::F64;
@@ -1889,12 +2137,15 @@ void rec_check(Program& P, Arena& ar, const SplitBuf& sb, const mpo_tt& A, const
     e3 = std::max(e3, c * a * b);
     e2 = std::max(e2, c * c);
   }
-  Ten E4[2] = {ar.take(t64, {(int)e4}), ar.take(t64, {(int)e4})};
-  Ten E3[2] = {ar.take(t64, {(int)e3}), ar.take(t64, {(int)e3})};
-  Ten E2[2] = {ar.take(t64, {(int)e2}), ar.take(t64, {(int)e2})};
+  auto two = [&](bool on, long long n) {
+    std::array<Ten, 2> t;
+    if (on) t = {ar.take(t64, {(int)n}), ar.take(t64, {(int)n})};
+    return t;
+  };
+  const std::array<Ten, 2> E4 = two(passes & 1, e4), E3 = two(passes & 2, e3), E2 = two(passes & 4, e2);
   const size_t mark = ar.cv.off;
   // four layers: E[a1, b1, a2, b2] -> sum over x, u of (A B)(x, u) (A B)(x, u)
-  {
+  if (passes & 1) {
     Ten E = as(E4[0], {1, 1, 1, 1});
     add_fill(P, {FillDesc{E.p, 0, 1, 1, 1}});
     for (int l = 0; l < L; ++l) {
@@ -1916,7 +2167,7 @@ void rec_check(Program& P, Arena& ar, const SplitBuf& sb, const mpo_tt& A, const
     add_normalize(P, E, cp.logs + L, cp.part);  // the last is the scalar itself
   }
   // three layers: E[c, a, b]
-  {
+  if (passes & 2) {
     Ten E = as(E3[0], {1, 1, 1});
     add_fill(P, {FillDesc{E.p, 0, 1, 1, 1}});
     for (int l = 0; l < L; ++l) {
@@ -1936,7 +2187,7 @@ void rec_check(Program& P, Arena& ar, const SplitBuf& sb, const mpo_tt& A, const
     permute(P, as(E, {1}), {0}, Ten{cp.logs + (L + 1) + L, t64, {1}});
   }
   // two layers: E[c, c']
-  {
+  if (passes & 4) {
     Ten E = as(E2[0], {1, 1});
     add_fill(P, {FillDesc{E.p, 0, 1, 1, 1}});
     for (int l = 0; l < L; ++l) {
@@ -1954,22 +2205,224 @@ void rec_check(Program& P, Arena& ar, const SplitBuf& sb, const mpo_tt& A, const
   }
 }
 
+// ---------------------------------------------------------------- fit error per sweep
+// An mpo_tt view of device cores with host-held bond dims.
+struct TTView {
+  std::vector<int32_t> chi;
+  std::vector<const double*> cores;
+  mpo_tt tt{};
+  TTView(int L, int d, const std::vector<int>& dims, const std::vector<double*>& ptrs)
+      : chi(dims.begin(), dims.end()), cores(ptrs.begin(), ptrs.end()) {
+    tt.L = L;
+    tt.d = d;
+    tt.chi = chi.data();
+    tt.cores = cores.data();
+  }
+};
+
+// eps = ||A B - C|| / ||A B|| from the logs of the transfer passes:
+// l4 = log ||A B||^2, lg3 / lg2 = the L + 1 entries of the three- and
+// two-layer passes (renormalization logs; lg3[L] is <C, A B> itself).
+double transfer_eps(int L, double l4, const double* lg3, const double* lg2) {
+  double l3 = 0, l2 = 0;
+  bool z3 = false, z2 = false;
+  for (int i = 0; i <= L; ++i) {
+    if (!std::isfinite(lg3[i]) || !std::isfinite(lg2[i])) throw Error{MPO_ERR_NUMERIC, "non-finite transfer pass"};
+    if (lg2[i] > 0) l2 += std::log(lg2[i]); else z2 = true;
+  }
+  for (int i = 0; i < L - 1; ++i) {
+    if (lg3[i] > 0) l3 += std::log(lg3[i]); else z3 = true;
+  }
+  const double last = lg3[L];
+  const double cab = (z3 || last == 0.0) ? 0.0
+                     : (last > 0 ? 1.0 : -1.0) * std::exp(l3 + std::log(std::fabs(last)) - l4);
+  const double cc = z2 ? 0.0 : std::exp(l2 - l4);
+  return std::sqrt(std::max(0.0, 1.0 - 2.0 * cab + cc));
+}
+
+size_t err_region_bytes(const Ctx& X) {
+  size_t peak = 0;
+  for (const PairState& S : X.pairs) {
+    std::vector<double*> none(S.L, nullptr);
+    TTView A(S.L, S.d, S.cA, none), B(S.L, S.d, S.cB, none), C(S.L, S.d, S.capC, none);
+    for (int passes : {1, 6}) {
+      Program P;
+      Arena ar;
+      SplitBuf sb;
+      rec_check(P, ar, sb, A.tt, B.tt, C.tt, CheckPlan{}, passes);
+      peak = std::max(peak, ar.peak);
+    }
+  }
+  return peak + 256;
+}
+
+// Runs transfer passes of one pair on the context stream: `passes` as in
+// rec_check, with C the merged FP64 copy in X.err.C (its current dims).
+void run_err_passes(Ctx& X, int pair, int passes, std::vector<double>& lg) {
+  PairState& S = X.pairs[pair];
+  TTView A(S.L, S.d, S.cA, S.A64), B(S.L, S.d, S.cB, S.B64), C(S.L, S.d, S.cC, X.err.C[pair]);
+  Program P;
+  if (passes & 6) {  // C = the merged train of the normalized fit (no nu)
+    std::vector<PermDesc> ds;
+    std::vector<ScaleDesc> sc;
+    const bool inv = X.o.schedule == MPO_SCHED_EVEN_ODD;
+    for (int i = 0; i < S.L; ++i) {
+      const long long n = (long long)S.cC[i] * S.dd * S.cC[i + 1];
+      ds.push_back(perm4(S.C64[i], 0, X.err.C[pair][i], 0, {1, 1, 1, (int)n}, {0, 0, 0, 1}, {0, 0, 0, 1}));
+      if (inv && i + 1 < S.L)
+        sc.push_back(ScaleDesc{X.err.C[pair][i], X.err.C[pair][i], S.cC[i] * S.dd, S.cC[i + 1], S.cC[i + 1],
+                               S.cC[i + 1], nullptr, S.Yv[i + 1], 0, 1});
+    }
+    add_perm(P, ds, "fit_error");
+    long long mx = 1;
+    for (auto& d : sc) mx = std::max(mx, (long long)d.n * d.r);
+    add_simple(P, LK::Scale, sc, mx, "fit_error");
+  }
+  CheckPlan cp{X.err.logs, X.err.part};
+  Arena ar;
+  ar.cv.base = X.err.region;
+  rec_check(P, ar, X.sb, A.tt, B.tt, C.tt, cp, passes);
+  if (ar.peak > X.err.region_bytes) throw Error{MPO_ERR_WORKSPACE, "fit error region too small"};
+  const size_t keep = X.arena_used;
+  upload(X, P);
+  run_program(P, X.stream, nullptr);
+  lg.assign(3 * (size_t)(S.L + 1), 0.0);
+  HIP_OK(hipMemcpyAsync(lg.data(), X.err.logs, lg.size() * sizeof(double), hipMemcpyDeviceToHost, X.stream));
+  HIP_OK(hipStreamSynchronize(X.stream));
+  X.arena_used = keep;
+}
+
+// log ||A B||^2 of every pair (normalized cores), once at initialization.
+void err_init(Ctx& X) {
+  X.err.l4.assign(X.pairs.size(), 0.0);
+  for (size_t p = 0; p < X.pairs.size(); ++p) {
+    std::vector<double> lg;
+    run_err_passes(X, (int)p, 1, lg);
+    const int L = X.pairs[p].L;
+    double l4 = 0;
+    for (int i = 0; i <= L; ++i) {
+      if (!(lg[i] > 0) || !std::isfinite(lg[i])) throw Error{MPO_ERR_NUMERIC, "A B is zero or not finite"};
+      l4 += std::log(lg[i]);
+    }
+    X.err.l4[p] = l4;
+  }
+}
+
+double sweep_error(Ctx& X, int pair) {
+  std::vector<double> lg;
+  run_err_passes(X, pair, 6, lg);
+  const int L = X.pairs[pair].L;
+  return transfer_eps(L, X.err.l4[pair], lg.data() + (L + 1), lg.data() + 2 * (L + 1));
+}
+
 // Small context for calls that are not tied to a fit: status flags, split-K
-// scratch and a descriptor arena carved from the caller's workspace.
-void carve_aux(Ctx& X, Carver& cv) {
+// scratch and a descriptor arena carved from the caller's workspace
+// (`compact`: a smaller split-K buffer and arena, for the fixed-size static
+// scratch; a launch whose split-K partials do not fit runs unsplit).
+void carve_aux(Ctx& X, Carver& cv, bool compact = false) {
   X.flag = cv.take<int>(4);
   X.sweep_dev = X.flag + 1;
-  X.sb.cap = (size_t)32 << 20;
+  X.sb.cap = compact ? (size_t)4 << 20 : (size_t)32 << 20;
   X.sb.partials = cv.take<char>(X.sb.cap);
-  X.sb.ccap = 1 << 14;
+  X.sb.ccap = compact ? 1 << 12 : 1 << 14;
   X.sb.counters = cv.take<int>(X.sb.ccap);
-  X.arena_cap = (size_t)8 << 20;
+  X.arena_cap = compact ? (size_t)2 << 20 : (size_t)8 << 20;
   X.arena = cv.take<char>(X.arena_cap);
+}
+
+// ||A B||_F and ||A B - C||_F by Householder-QR sweeps from the left (Sec.
+// 2.3.1, site-canonical form) over the naive product P = A B of Alg. 1 and
+// over the difference MPO D = [P, -C]: the direct sum of the two trains, the
+// first core concatenated along its right bond (C's block negated), block-
+// diagonal middle cores, the last core stacked along its left bond.  The
+// carried triangular factor R holds the norm of everything to its left, so
+// the last site's column norm is the train's Frobenius norm.  Every step is
+// backward stable (no Gram matrix, no difference of squares), so the
+// relative error ||A B - C|| / ||A B|| is resolved far below sqrt(eps).
+// D's cores are never formed: the carry R = [R_P, R_C] multiplies P_l and
+// C_l block by block.  Bond dimensions chi_A chi_B + chi_C <= kCheckQrMax.
+constexpr int kCheckQrMax = 512;
+
+struct QrCheckBufs {
+  double *carry[2], *X, *Pc, *out;
+};
+
+bool check_qr_fits(const mpo_tt& A, const mpo_tt& B, const mpo_tt& C) {
+  for (int l = 0; l <= A.L; ++l)
+    if ((long long)A.chi[l] * B.chi[l] + C.chi[l] > kCheckQrMax) return false;
+  return true;
+}
+
+QrCheckBufs carve_check_qr(Carver& cv, const mpo_tt& A, const mpo_tt& B, const mpo_tt& C) {
+  const int L = A.L, d = A.d;
+  long long cmax = 1, pmax = 1, xmax = 1;
+  for (int l = 0; l < L; ++l) {
+    const long long p0 = (long long)A.chi[l] * B.chi[l], p1 = (long long)A.chi[l + 1] * B.chi[l + 1];
+    const long long c0 = p0 + C.chi[l], c1 = p1 + C.chi[l + 1];
+    cmax = std::max({cmax, c0, c1});
+    pmax = std::max(pmax, p0 * d * d * p1);
+    xmax = std::max(xmax, c0 * d * d * c1);  // rows of X never exceed the left bond times d^2
+  }
+  QrCheckBufs b;
+  b.carry[0] = cv.take<double>((size_t)cmax * cmax);
+  b.carry[1] = cv.take<double>((size_t)cmax * cmax);
+  b.X = cv.take<double>((size_t)xmax);
+  b.Pc = cv.take<double>((size_t)pmax);
+  b.out = cv.take<double>(2);
+  return b;
+}
+
+// One QR sweep: over P alone (C null) into out[0], or over [P, -C] into out[1].
+void rec_check_qr_sweep(Program& P, const SplitBuf& sb, const mpo_tt& A, const mpo_tt& B,
+                        const mpo_tt* C, const QrCheckBufs& b, double* out) {
+  const int L = A.L, d = A.d, dd = d * d;
+  int r = 1, cur = 0;  // carry: r x (width of D's bond l), in b.carry[cur]
+  add_fill(P, {FillDesc{b.carry[0], 2, 1, 1, 1}});
+  for (int l = 0; l < L; ++l) {
+    const int p0 = A.chi[l] * B.chi[l], p1 = A.chi[l + 1] * B.chi[l + 1];
+    const int c0 = C ? C->chi[l] : 0, c1 = C ? C->chi[l + 1] : 0;
+    const bool first = l == 0, last = l == L - 1;
+    const int w0 = (first || !C) ? p0 : p0 + c0;        // D's left bond
+    const int w1 = (last || !C) ? p1 : p1 + c1;         // D's right bond
+    add_simple(P, LK::Naive, std::vector<NaiveDesc>{NaiveDesc{A.cores[l], B.cores[l], b.Pc, A.chi[l],
+                                                              A.chi[l + 1], B.chi[l], B.chi[l + 1], d}},
+               (long long)p0 * dd * p1, "check");
+    const double* carry = b.carry[cur];
+    // X[(i, s, u), j] = sum_a carry[i, a] P_l[a, s, u, j] (+ the C block)
+    GemmJob gp{r, p1, p0, op64(carry, true, w0), op64(b.Pc, false, dd * p1), out64(b.X, dd * w1)};
+    gp.nb[0] = dd;
+    gp.B.s[0] = p1;
+    gp.C.s[0] = w1;
+    add_gemm(P, sb, Mode::F64, {gp}, "check", 0);
+    if (C) {
+      // C's block: its own columns (first, middle) or added onto P's (last);
+      // at the first site both blocks share D's left bond of dimension 1
+      const double* cc = first ? carry : carry + p0;
+      GemmJob gc{r, c1, c0, op64(cc, true, w0), op64(C->cores[l], false, dd * c1),
+                 out64(last ? b.X : b.X + p1, dd * w1)};
+      gc.nb[0] = dd;
+      gc.B.s[0] = c1;
+      gc.C.s[0] = w1;
+      gc.alpha = first && !last ? -1.0 : 1.0;
+      if (first && last) gc.alpha = -1.0;  // one site: D = P - C
+      gc.beta = last ? 1 : 0;
+      add_gemm(P, sb, Mode::F64, {gc}, "check", 0);
+    }
+    const int m = r * dd;
+    if (last) {
+      add_simple(P, LK::Norm, std::vector<NormDesc>{NormDesc{b.X, (long long)m * w1, out}}, 0, "check");
+      break;
+    }
+    add_simple(P, LK::Geqr, std::vector<GeqrDesc>{GeqrDesc{b.X, m, w1, w1, b.carry[1 - cur], w1}}, 0, "check");
+    cur = 1 - cur;
+    r = std::min(m, w1);
+  }
 }
 
 int grad_centre(const Ctx& X) {
   if (X.o.schedule != MPO_SCHED_SERIAL) throw Error{MPO_ERR_UNSUPPORTED, "gradient: serial schedule only"};
-  return X.sweeps_done % 2 == 1 ? -1 : 0;  // -1: last site
+  if (X.pos != 0) throw Error{MPO_ERR_UNSUPPORTED, "gradient: the fit stands inside a sweep"};
+  return (X.o.first_sweep + X.sweeps_done) % 2 == 1 ? -1 : 0;  // -1: last site
 }
 
 void validate_grad(const Ctx& X, const PairState& S, const mpo_pair* ab, const mpo_tt* W) {
@@ -1982,6 +2435,110 @@ void validate_grad(const Ctx& X, const PairState& S, const mpo_pair* ab, const m
       throw Error{MPO_ERR_SHAPE, "A and B must have the fitted bond dimensions"};
   (void)X;
 }
+}  // namespace
+}  // namespace mpofit
+
+namespace mpofit {
+namespace {
+// The exact check's two routes: Householder-QR sweeps (check_qr_fits) or
+// the transfer passes; both carve from `ws` after the auxiliary context.
+struct CheckLayout {
+  bool qr;
+  CheckPlan cp;
+  QrCheckBufs qb;
+  size_t off;
+};
+
+CheckLayout check_layout(Ctx& X, Carver& cv, const mpo_pair& pair, const mpo_tt& C, bool compact) {
+  const int L = pair.A.L;
+  carve_aux(X, cv, compact);
+  CheckLayout lay{};
+  lay.qr = check_qr_fits(pair.A, pair.B, C);
+  if (lay.qr) {
+    lay.qb = carve_check_qr(cv, pair.A, pair.B, C);
+  } else {
+    lay.cp.logs = cv.take<double>(3 * (L + 1));
+    lay.cp.part = cv.take<double>(1024);
+  }
+  lay.off = cv.off;
+  return lay;
+}
+
+void validate_check(const mpo_pair& pair, const mpo_tt& C) {
+  const int L = pair.A.L, d = pair.A.d;
+  if (L < 1 || d < 1) throw Error{MPO_ERR_SHAPE, "bad L or d"};
+  validate_tt(pair.A, L, d);
+  validate_tt(pair.B, L, d);
+  validate_tt(C, L, d);
+}
+
+size_t check_bytes(const mpo_pair& pair, const mpo_tt& C, bool compact) {
+  validate_check(pair, C);
+  Ctx X;
+  Carver cv;
+  CheckLayout lay = check_layout(X, cv, pair, C, compact);
+  if (lay.qr) return cv.off + 256;
+  Program P;
+  Arena ar;
+  ar.cv.off = cv.off;
+  rec_check(P, ar, X.sb, pair.A, pair.B, C, lay.cp);
+  return std::max(ar.peak, cv.off) + 256;
+}
+
+void check_run(const mpo_pair& pair, const mpo_tt& C, double* rel_err, double* ab_norm2, int32_t* method,
+               char* ws, size_t ws_bytes, hipStream_t stream, bool compact) {
+  const size_t need = check_bytes(pair, C, compact);
+  if (need > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "workspace too small"};
+  const int L = pair.A.L;
+  Ctx X;
+  X.stream = stream;
+  Carver cv;
+  cv.base = ws;
+  CheckLayout lay = check_layout(X, cv, pair, C, compact);
+  // flags and split-K counters start at zero in every call
+  Program z;
+  add_fill(z, {FillDesc{X.flag, 4, 0, 0, 0}, FillDesc{X.sb.counters, X.sb.ccap, 0, 0, 0}});
+  upload(X, z);
+  run_program(z, X.stream, nullptr);
+  Program P;
+  if (lay.qr) {
+    rec_check_qr_sweep(P, X.sb, pair.A, pair.B, nullptr, lay.qb, lay.qb.out);
+    rec_check_qr_sweep(P, X.sb, pair.A, pair.B, &C, lay.qb, lay.qb.out + 1);
+    upload(X, P);
+    run_program(P, X.stream, nullptr);
+    double nrm[2];
+    HIP_OK(hipMemcpyAsync(nrm, lay.qb.out, sizeof(nrm), hipMemcpyDeviceToHost, X.stream));
+    HIP_OK(hipStreamSynchronize(X.stream));
+    check_flags(X);
+    if (!std::isfinite(nrm[0]) || !std::isfinite(nrm[1])) throw Error{MPO_ERR_NUMERIC, "non-finite norm"};
+    if (!(nrm[0] > 0)) throw Error{MPO_ERR_NUMERIC, "A B is zero"};
+    *rel_err = nrm[1] / nrm[0];
+    if (ab_norm2) *ab_norm2 = nrm[0] * nrm[0];
+    if (method) *method = 0;
+    return;
+  }
+  Arena ar;
+  ar.cv.base = cv.base;
+  ar.cv.off = cv.off;
+  rec_check(P, ar, X.sb, pair.A, pair.B, C, lay.cp);
+  upload(X, P);
+  run_program(P, X.stream, nullptr);
+  std::vector<double> lg(3 * (L + 1));
+  HIP_OK(hipMemcpyAsync(lg.data(), lay.cp.logs, lg.size() * sizeof(double), hipMemcpyDeviceToHost, X.stream));
+  HIP_OK(hipStreamSynchronize(X.stream));
+  check_flags(X);
+  // log ||AB||^2, log |<C, AB>| (with sign), log ||C||^2; a zero norm on
+  // the way makes that pass exactly zero
+  double l4 = 0;
+  for (int i = 0; i <= L; ++i) {
+    if (!(lg[i] > 0) || !std::isfinite(lg[i])) throw Error{MPO_ERR_NUMERIC, "A B is zero or not finite"};
+    l4 += std::log(lg[i]);
+  }
+  *rel_err = transfer_eps(L, l4, lg.data() + (L + 1), lg.data() + 2 * (L + 1));
+  if (ab_norm2) *ab_norm2 = std::exp(l4);
+  if (method) *method = 1;
+}
+
 }  // namespace
 }  // namespace mpofit
 
@@ -2006,6 +2563,82 @@ mpo_status guarded(F&& f) {
   } catch (const std::exception& e) {
     g_last_error = e.what();
     return MPO_ERR_DEVICE;
+  }
+}
+}  // namespace
+
+namespace {
+// Runs units [start, start + count) of the current sweep: the program of
+// that segment for the current shapes is recorded once and replayed (as a
+// captured graph once the shapes are stable; whole sweeps only), with the
+// per-class timings in profiling contexts.  Advances the position.
+void run_segment(mpo_fit_ctx* ctx, int start, int count) {
+  Ctx& X = ctx->X;
+  const bool fwd = (X.o.first_sweep + X.sweeps_done) % 2 == 0;
+  const bool whole = start == 0 && count == sweep_units(X);
+  const std::string key = shape_key(X, fwd ? "F" : "B") + "|" + std::to_string(start) + "+" +
+                          std::to_string(count);
+  auto it = ctx->plans.find(key);
+  if (it == ctx->plans.end()) {
+    SweepPlan sp;
+    std::vector<std::vector<int>> before;
+    for (auto& S : X.pairs) before.push_back(S.cC);
+    record_segment(X, sp, fwd, start, count);
+    sp.stable = sp.cC_after == before;
+    // restore host shapes (recording advanced them) and upload
+    for (size_t p = 0; p < X.pairs.size(); ++p) X.pairs[p].cC = before[p];
+    it = ctx->plans.emplace(key, std::move(sp)).first;
+    upload(X, it->second.prog);
+  }
+  SweepPlan& sp = it->second;
+  if (X.profile) {
+    std::vector<hipEvent_t>& ev = ctx->evs;
+    while (ev.size() < sp.prog.launches.size() + 1) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    run_program(sp.prog, X.stream, ev.data());
+    HIP_OK(hipEventSynchronize(ev[sp.prog.launches.size()]));
+    for (size_t li = 0; li < sp.prog.launches.size(); ++li) {
+      float ms = 0;
+      HIP_OK(hipEventElapsedTime(&ms, ev[li], ev[li + 1]));
+      const Launch& l = sp.prog.launches[li];
+      auto pe = std::find_if(X.prof.begin(), X.prof.end(),
+                             [&](const Ctx::ProfEntry& e) { return e.cls == l.cls; });
+      if (pe == X.prof.end()) {
+        X.prof.push_back(Ctx::ProfEntry{l.cls});
+        pe = X.prof.end() - 1;
+      }
+      pe->ms += ms;
+      pe->flops += l.flops;
+      pe->launches += 1;
+    }
+  } else if (whole && X.o.capture_graph && X.stream != nullptr && (sp.stable || sp.uses >= 1)) {
+    if (!sp.graph) {
+      hipGraph_t g = nullptr;
+      HIP_OK(hipStreamBeginCapture(X.stream, hipStreamCaptureModeThreadLocal));
+      try {
+        run_program(sp.prog, X.stream, nullptr);
+      } catch (...) {
+        (void)hipStreamEndCapture(X.stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIP_OK(hipStreamEndCapture(X.stream, &g));
+      HIP_OK(hipGraphInstantiate(&sp.graph, g, nullptr, nullptr, 0));
+      HIP_OK(hipGraphDestroy(g));
+    }
+    HIP_OK(hipGraphLaunch(sp.graph, X.stream));
+  } else {
+    run_program(sp.prog, X.stream, nullptr);
+  }
+  sp.uses++;
+  for (size_t p = 0; p < X.pairs.size(); ++p) X.pairs[p].cC = sp.cC_after[p];
+  X.pos += count;
+  if (X.pos == sweep_units(X)) {
+    X.pos = 0;
+    X.sweeps_done++;
   }
 }
 }  // namespace
@@ -2046,6 +2679,14 @@ mpo_status mpo_fit_init(mpo_fit_ctx** ctx, const mpo_pair* pairs, int32_t n_pair
     // zero the status flags, sweep counter and split-K counters
     Program z;
     add_fill(z, {FillDesc{X.flag, 4, 0, 0, 0}, FillDesc{X.sb.counters, X.sb.ccap, 0, 0, 0}});
+    if (X.o.first_sweep > 0) {  // the Philox stream index of the first sweep
+      Launch b;
+      b.kind = LK::Bump;
+      b.counter = X.sweep_dev;
+      b.bump_by = X.o.first_sweep;
+      b.cls = "bump";
+      z.launches.push_back(b);
+    }
     upload(X, z);
     run_program(z, X.stream, nullptr);
     Program init;
@@ -2061,84 +2702,64 @@ mpo_status mpo_fit_init(mpo_fit_ctx** ctx, const mpo_pair* pairs, int32_t n_pair
     // the init descriptors are not needed again
     X.arena_used = 0;
     check_flags(X);
+    if (X.o.track_error) err_init(X);
+    X.pos = X.o.schedule == MPO_SCHED_SERIAL ? X.o.first_bond : X.o.first_half;
     HIP_OK(hipEventCreate(&X.ev0));
     HIP_OK(hipEventCreate(&X.ev1));
     *ctx = c.release();
   });
 }
 
-mpo_status mpo_fit_sweep(mpo_fit_ctx* ctx, int32_t n_sweeps) {
+mpo_status mpo_fit_sweep(mpo_fit_ctx* ctx, int32_t n_sweeps, double* fit_err) {
   return guarded([&] {
     if (!ctx || n_sweeps < 0) throw Error{MPO_ERR_INVALID_ARG, "null ctx or negative sweeps"};
     Ctx& X = ctx->X;
+    if (fit_err && !X.o.track_error)
+      throw Error{MPO_ERR_INVALID_ARG, "fit_err needs a context created with opts.track_error = 1"};
     HIP_OK(hipEventRecord(X.ev0, X.stream));
     X.prof.clear();
     for (int s = 0; s < n_sweeps; ++s) {
-      const bool fwd = X.sweeps_done % 2 == 0;
-      const std::string key = shape_key(X, fwd ? "F" : "B");
-      auto it = ctx->plans.find(key);
-      if (it == ctx->plans.end()) {
-        SweepPlan sp;
-        std::vector<std::vector<int>> before;
-        for (auto& S : X.pairs) before.push_back(S.cC);
-        record_sweep(X, sp, fwd);
-        sp.stable = sp.cC_after == before;
-        // restore host shapes (recording advanced them) and upload
-        it = ctx->plans.emplace(key, std::move(sp)).first;
-        upload(X, it->second.prog);
+      run_segment(ctx, X.pos, sweep_units(X) - X.pos);  // a resumed sweep finishes first
+      if (fit_err) {  // after the timed region of this sweep: transfer passes on the result
+        HIP_OK(hipEventRecord(X.ev1, X.stream));
+        for (size_t p = 0; p < X.pairs.size(); ++p)
+          fit_err[p * (size_t)n_sweeps + s] = sweep_error(X, (int)p);
       }
-      SweepPlan& sp = it->second;
-      if (X.profile) {
-        std::vector<hipEvent_t>& ev = ctx->evs;
-        while (ev.size() < sp.prog.launches.size() + 1) {
-          hipEvent_t e;
-          HIP_OK(hipEventCreate(&e));
-          ev.push_back(e);
-        }
-        run_program(sp.prog, X.stream, ev.data());
-        HIP_OK(hipEventSynchronize(ev[sp.prog.launches.size()]));
-        for (size_t li = 0; li < sp.prog.launches.size(); ++li) {
-          float ms = 0;
-          HIP_OK(hipEventElapsedTime(&ms, ev[li], ev[li + 1]));
-          const Launch& l = sp.prog.launches[li];
-          auto pe = std::find_if(X.prof.begin(), X.prof.end(),
-                                 [&](const Ctx::ProfEntry& e) { return e.cls == l.cls; });
-          if (pe == X.prof.end()) {
-            X.prof.push_back(Ctx::ProfEntry{l.cls});
-            pe = X.prof.end() - 1;
-          }
-          pe->ms += ms;
-          pe->flops += l.flops;
-          pe->launches += 1;
-        }
-      } else if (X.o.capture_graph && X.stream != nullptr && (sp.stable || sp.uses >= 1)) {
-        if (!sp.graph) {
-          hipGraph_t g = nullptr;
-          HIP_OK(hipStreamBeginCapture(X.stream, hipStreamCaptureModeThreadLocal));
-          try {
-            run_program(sp.prog, X.stream, nullptr);
-          } catch (...) {
-            (void)hipStreamEndCapture(X.stream, &g);
-            if (g) (void)hipGraphDestroy(g);
-            throw;
-          }
-          HIP_OK(hipStreamEndCapture(X.stream, &g));
-          HIP_OK(hipGraphInstantiate(&sp.graph, g, nullptr, nullptr, 0));
-          HIP_OK(hipGraphDestroy(g));
-        }
-        HIP_OK(hipGraphLaunch(sp.graph, X.stream));
-      } else {
-        run_program(sp.prog, X.stream, nullptr);
-      }
-      sp.uses++;
-      for (size_t p = 0; p < X.pairs.size(); ++p) X.pairs[p].cC = sp.cC_after[p];
-      X.sweeps_done++;
+    }
+    if (!fit_err) HIP_OK(hipEventRecord(X.ev1, X.stream));
+    check_flags(X);
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, X.ev0, X.ev1));
+    X.last_ms = ms;
+  });
+}
+
+mpo_status mpo_fit_updates(mpo_fit_ctx* ctx, int32_t n_units) {
+  return guarded([&] {
+    if (!ctx || n_units < 0) throw Error{MPO_ERR_INVALID_ARG, "null ctx or negative count"};
+    Ctx& X = ctx->X;
+    if (X.o.schedule == MPO_SCHED_SERIAL && X.pairs.size() != 1 && n_units % sweep_units(X) != 0)
+      throw Error{MPO_ERR_UNSUPPORTED, "single updates need one pair"};
+    X.prof.clear();
+    HIP_OK(hipEventRecord(X.ev0, X.stream));
+    while (n_units > 0) {
+      const int m = std::min(n_units, sweep_units(X) - X.pos);
+      run_segment(ctx, X.pos, m);
+      n_units -= m;
     }
     HIP_OK(hipEventRecord(X.ev1, X.stream));
     check_flags(X);
     float ms = 0;
     HIP_OK(hipEventElapsedTime(&ms, X.ev0, X.ev1));
     X.last_ms = ms;
+  });
+}
+
+mpo_status mpo_fit_position(const mpo_fit_ctx* ctx, int32_t* sweep, int32_t* unit) {
+  return guarded([&] {
+    if (!ctx) throw Error{MPO_ERR_INVALID_ARG, "null ctx"};
+    if (sweep) *sweep = ctx->X.o.first_sweep + ctx->X.sweeps_done;
+    if (unit) *unit = ctx->X.pos;
   });
 }
 
@@ -2179,6 +2800,20 @@ mpo_status mpo_fit_export_c(mpo_fit_ctx* ctx, int32_t pair, double* const* c_cor
     run_program(P, X.stream, nullptr);
     HIP_OK(hipStreamSynchronize(X.stream));
     X.arena_used = keep;
+  });
+}
+
+mpo_status mpo_fit_singular_values(mpo_fit_ctx* ctx, int32_t pair, int32_t bond, double* S, int32_t* r) {
+  return guarded([&] {
+    if (!ctx || !S) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    Ctx& X = ctx->X;
+    if (pair < 0 || pair >= (int)X.pairs.size()) throw Error{MPO_ERR_INVALID_ARG, "bad pair"};
+    PairState& P = X.pairs[pair];
+    if (bond < 1 || bond >= P.L) throw Error{MPO_ERR_INVALID_ARG, "bond must be in 1 .. L-1"};
+    const int n = P.cC[bond];
+    HIP_OK(hipMemcpyAsync(S, P.Yv[bond], n * sizeof(double), hipMemcpyDeviceToHost, X.stream));
+    HIP_OK(hipStreamSynchronize(X.stream));
+    if (r) *r = n;
   });
 }
 
@@ -2240,7 +2875,7 @@ mpo_status mpo_gemm_autotune(const mpo_pair* pairs, int32_t n_pairs, const mpo_f
     const mpo_status st = mpo_fit_init(&raw, pairs, n_pairs, &o, workspace, ws_bytes, stream);
     if (st != MPO_OK) throw Error{st, g_last_error};
     std::unique_ptr<mpo_fit_ctx, void (*)(mpo_fit_ctx*)> ctx(raw, mpo_fit_destroy);
-    const mpo_status st2 = mpo_fit_sweep(raw, 1);
+    const mpo_status st2 = mpo_fit_sweep(raw, 1, nullptr);
     if (st2 != MPO_OK) throw Error{st2, g_last_error};
     Ctx& X = raw->X;
     // the launch classes of the next sweep
@@ -2253,7 +2888,7 @@ mpo_status mpo_gemm_autotune(const mpo_pair* pairs, int32_t n_pairs, const mpo_f
         for (auto& S : X.pairs) v.push_back(S.cC);
         return v;
       }();
-      record_sweep(X, sp, X.sweeps_done % 2 == 0);
+      record_segment(X, sp, (X.o.first_sweep + X.sweeps_done) % 2 == 0, X.pos, sweep_units(X) - X.pos);
       X.sb.record = nullptr;
       for (size_t p = 0; p < X.pairs.size(); ++p) X.pairs[p].cC = keep[p];
     }
@@ -2366,80 +3001,18 @@ mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_pair* ab, cons
 mpo_status mpo_contract_check_bytes(const mpo_pair* pair, const mpo_tt* C, size_t* bytes) {
   return guarded([&] {
     if (!pair || !C || !bytes) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
-    const int L = pair->A.L, d = pair->A.d;
-    if (L < 1 || d < 1) throw Error{MPO_ERR_SHAPE, "bad L or d"};
-    validate_tt(pair->A, L, d);
-    validate_tt(pair->B, L, d);
-    validate_tt(*C, L, d);
-    Ctx X;
-    Carver cv;
-    carve_aux(X, cv);
-    CheckPlan cp;
-    cp.logs = cv.take<double>(3 * (L + 1));
-    cp.part = cv.take<double>(1024);
-    Program P;
-    Arena ar;
-    ar.cv.off = cv.off;
-    rec_check(P, ar, X.sb, pair->A, pair->B, *C, cp);
-    *bytes = std::max(ar.peak, cv.off) + 256;
+    *bytes = check_bytes(*pair, *C, false);
   });
 }
 
 mpo_status mpo_contract_exact_check(const mpo_pair* pair, const mpo_tt* C, double* rel_err,
-                                    double* ab_norm2, void* workspace, size_t ws_bytes, void* stream) {
+                                    double* ab_norm2, int32_t* method, void* workspace,
+                                    size_t ws_bytes, void* stream) {
   return guarded([&] {
     if (!pair || !C || !rel_err || !workspace) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
     if (reinterpret_cast<uintptr_t>(workspace) & 255) throw Error{MPO_ERR_WORKSPACE, "workspace not 256-byte aligned"};
-    size_t need = 0;
-    const mpo_status st = mpo_contract_check_bytes(pair, C, &need);
-    if (st != MPO_OK) throw Error{st, g_last_error};
-    if (need > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "workspace too small"};
-    const int L = pair->A.L;
-    Ctx X;
-    X.stream = static_cast<hipStream_t>(stream);
-    Carver cv;
-    cv.base = static_cast<char*>(workspace);
-    carve_aux(X, cv);
-    CheckPlan cp;
-    cp.logs = cv.take<double>(3 * (L + 1));
-    cp.part = cv.take<double>(1024);
-    Program z;
-    add_fill(z, {FillDesc{X.flag, 4, 0, 0, 0}, FillDesc{X.sb.counters, X.sb.ccap, 0, 0, 0}});
-    upload(X, z);
-    run_program(z, X.stream, nullptr);
-    Program P;
-    Arena ar;
-    ar.cv.base = cv.base;
-    ar.cv.off = cv.off;
-    rec_check(P, ar, X.sb, pair->A, pair->B, *C, cp);
-    upload(X, P);
-    run_program(P, X.stream, nullptr);
-    std::vector<double> lg(3 * (L + 1));
-    HIP_OK(hipMemcpyAsync(lg.data(), cp.logs, lg.size() * sizeof(double), hipMemcpyDeviceToHost, X.stream));
-    HIP_OK(hipStreamSynchronize(X.stream));
-    check_flags(X);
-    // log ||AB||^2, log |<C, AB>| (with sign), log ||C||^2; a zero norm on
-    // the way makes that pass exactly zero
-    for (double v : lg)
-      if (!std::isfinite(v)) throw Error{MPO_ERR_NUMERIC, "non-finite transfer pass"};
-    double l4 = 0, l3 = 0, l2 = 0;
-    bool z3 = false, z2 = false;
-    for (int i = 0; i <= L; ++i) {
-      if (!(lg[i] > 0)) throw Error{MPO_ERR_NUMERIC, "A B is zero"};
-      l4 += std::log(lg[i]);
-      const double c2 = lg[2 * (L + 1) + i];
-      if (c2 > 0) l2 += std::log(c2); else z2 = true;
-    }
-    for (int i = 0; i < L - 1; ++i) {
-      const double c3 = lg[(L + 1) + i];
-      if (c3 > 0) l3 += std::log(c3); else z3 = true;
-    }
-    const double last = lg[(L + 1) + L];
-    const double cab = (z3 || last == 0.0) ? 0.0
-                       : (last > 0 ? 1.0 : -1.0) * std::exp(l3 + std::log(std::fabs(last)) - l4);
-    const double cc = z2 ? 0.0 : std::exp(l2 - l4);
-    *rel_err = std::sqrt(std::max(0.0, 1.0 - 2.0 * cab + cc));
-    if (ab_norm2) *ab_norm2 = std::exp(l4);
+    check_run(*pair, *C, rel_err, ab_norm2, method, static_cast<char*>(workspace), ws_bytes,
+              static_cast<hipStream_t>(stream), false);
   });
 }
 
@@ -2563,7 +3136,8 @@ mpo_status mpo_test_eig_batch(const double* H, int n, int k, int r, double* eval
   });
 }
 
-mpo_status mpo_test_cholqr(double* Xm, int n, int k, void* workspace, size_t ws_bytes, void* stream) {
+static mpo_status test_cholqr(double* Xm, int n, int k, double eta, void* workspace, size_t ws_bytes,
+                              void* stream) {
   return guarded([&] {
     TestEnv T(workspace, ws_bytes, stream);
     double* G = T.cv.take<double>((size_t)k * k);
@@ -2572,10 +3146,20 @@ mpo_status mpo_test_cholqr(double* Xm, int n, int k, void* workspace, size_t ws_
     Program P;
     double* Tm = T.cv.take<double>((size_t)n * k);
     if (T.cv.off > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "test workspace too small"};
-    add_cholqr(T.X, P, {CholQRJob{Xm, n, k, k, G, R, nullptr, Tm}}, 2);
+    CholQRJob j{Xm, n, k, k, G, R, nullptr, Tm};
+    j.eta = eta;
+    add_cholqr(T.X, P, {j}, 2, false, eta > 0.0);
     T.go(P);
     check_flags(T.X);
   });
+}
+
+mpo_status mpo_test_cholqr(double* Xm, int n, int k, void* workspace, size_t ws_bytes, void* stream) {
+  return test_cholqr(Xm, n, k, 0.0, workspace, ws_bytes, stream);
+}
+
+mpo_status mpo_test_cholqr_rr(double* Xm, int n, int k, void* workspace, size_t ws_bytes, void* stream) {
+  return test_cholqr(Xm, n, k, kRankEta, workspace, ws_bytes, stream);
 }
 
 mpo_status mpo_test_omega(double* out, int chi, int dd, int k, int bond, int stream_idx, int pair,

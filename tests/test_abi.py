@@ -118,7 +118,50 @@ def test_null_pointers():
     p = _Pair()
     p.pair.A.cores = C.cast(None, C.POINTER(C.c_void_p))
     assert _query([p], _opts())[0] == 1
-    assert lib.mpo_fit_sweep(None, 1) == 1
+    assert lib.mpo_fit_sweep(None, 1, None) == 1
+    assert lib.mpo_fit_singular_values(None, 0, 1, None, None) == 1
+
+
+def test_undersized_or_misaligned_workspace():
+    """mpo_fit_init checks the workspace before any device call."""
+    lib = _lib()
+    p = _Pair()
+    arr = (lib_mod.MpoPair * 1)(p.pair)
+    opts = _opts()
+    ctx = C.c_void_p()
+    st = lib.mpo_fit_init(C.byref(ctx), arr, 1, C.byref(opts), C.c_void_p(0x100000), 1024, None)
+    assert st == 3 and b"small" in lib.mpo_last_error()
+    st = lib.mpo_fit_init(C.byref(ctx), arr, 1, C.byref(opts), C.c_void_p(0x100001), 1 << 40, None)
+    assert st == 3 and b"aligned" in lib.mpo_last_error()
+    assert not ctx.value
+
+
+@pytest.mark.parametrize("opts, status", [
+    (dict(first_sweep=-1), 1),
+    (dict(track_error=2), 1),
+    (dict(first_sweep=3), 0),
+    (dict(first_sweep=3, schedule=1), 0),
+])
+def test_resume_and_error_options(opts, status):
+    st, _ = _query([_Pair()], _opts(**opts))
+    assert st == status
+
+
+def test_error_tracking_reserves_workspace():
+    _, plain = _query([_Pair()], _opts())
+    _, track = _query([_Pair()], _opts(track_error=1))
+    assert track > plain
+
+
+def test_check_bytes_routes():
+    """The exact check's workspace query (host only): small bonds take the
+    QR route, whose scratch is much smaller than the four-layer pass's."""
+    lib = _lib()
+    small, big = _Pair(chi_a=4, chi_b=4), _Pair(chi_a=24, chi_b=24)
+    n_small, n_big = C.c_size_t(0), C.c_size_t(0)
+    assert lib.mpo_contract_check_bytes(C.byref(small.pair), C.byref(small.pair.A), C.byref(n_small)) == 0
+    assert lib.mpo_contract_check_bytes(C.byref(big.pair), C.byref(big.pair.A), C.byref(n_big)) == 0
+    assert 0 < n_small.value < n_big.value
 
 
 def test_initial_guess_validation():

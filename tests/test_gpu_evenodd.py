@@ -66,3 +66,46 @@ def test_even_odd_initial_guess_fp64():
     C, _ = gpu_fit_pairs([(A, B)], 16, 2, precision="fp64", sketch_p=-1, c_init=[C0])
     ref = ofit.fit_even_odd(A, B, 16, 2, C_init=C0)
     assert mpo.rel_diff(C[0], ref.C) < 1e-10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("sketch_p", [-1, 8])
+def test_half_steps_from_oracle_states(precision, tol, sketch_p):
+    """Each half-step of the inverse-gauge schedule from a given state: the
+    first one from the initial guess (mpo_fit_updates of one half-step), the
+    second one resumed from the oracle's merged train after the first
+    (first_half = 1: its inverse canonical form and environments), each
+    against the oracle's same step.  A whole FP32 sweep is not compared: the
+    second half-step's sketch acts on columns in the basis of the first
+    half-step's V, which is not fixed inside nearly degenerate singular pairs
+    at FP32 precision."""
+    from paper_2606_23274_amd.api import FitContext
+    A, B = make_pair(16, 2, 32, seed=44, decay=True)
+    hs0 = {}
+
+    def on_half_step(sweep, q, Cm):
+        hs0.setdefault(q, Cm)
+
+    ofit.fit_even_odd(A, B, 64, 1, sketch_p=sketch_p, seed=3, on_half_step=on_half_step, n_half_steps=1)
+    ctx = FitContext([(A, B)], 64, precision=precision, schedule="even_odd", sketch_p=sketch_p, seed=3)
+    try:
+        ctx.updates(1)
+        assert ctx.position() == (0, 1)
+        C0 = ctx.export_numpy(0)
+    finally:
+        ctx.close()
+    e0 = mpo.rel_diff(C0, hs0[0])
+    ref1 = ofit.fit_even_odd(A, B, 64, 1, sketch_p=sketch_p, seed=3, C_init=hs0[0], first_half=1)
+    ctx = FitContext([(A, B)], 64, precision=precision, schedule="even_odd", sketch_p=sketch_p, seed=3,
+                     c_init=[hs0[0]], first_half=1)
+    try:
+        ctx.updates(1)
+        assert ctx.position() == (1, 0)
+        C1 = ctx.export_numpy(0)
+        dims = ctx.bond_dims(0)
+    finally:
+        ctx.close()
+    e1 = mpo.rel_diff(C1, ref1.C)
+    print(precision, sketch_p, "half-step distances", e0, e1)
+    assert dims == ref1.bond_dims
+    assert max(e0, e1) <= tol

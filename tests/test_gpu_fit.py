@@ -70,15 +70,15 @@ def test_sketch_bf16x3_first_sweep():
     assert mpo.rel_diff(C, ref.C) < 3e-3
 
 
+@pytest.mark.xfail(reason="pure BF16 operands: each product carries ~2^-9 relative rounding and "
+                          "the environments chain it over every site (measured 2.35e-2 here)",
+                   strict=True)
 def test_sketch_bf16_pure_first_sweep():
-    """Pure BF16 operands: each product carries ~2^-9 relative rounding and the
-    environments chain it over every site, so the first-sweep distance to the
-    FP64 oracle is ~2e-2 here (measured 2.35e-2), above the 3e-3 bar that the
-    split-BF16 mode meets; this bound guards against regressions only."""
+    """Pure BF16 against the BF16 bar of 3e-3 (the split-BF16 mode meets it)."""
     A, B = make_pair(12, 2, 8, seed=5, decay=True)
     C, _ = gpu_fit(A, B, 16, 1, precision="bf16", sketch_p=4, seed=1)
     ref = ofit.fit_serial(A, B, 16, 1, sketch_p=4, seed=1)
-    assert mpo.rel_diff(C, ref.C) < 5e-2
+    assert mpo.rel_diff(C, ref.C) < 3e-3
 
 
 def test_ragged_dims_fp64():
@@ -111,3 +111,56 @@ def test_initial_guess(precision, sketch_p, tol):
     ref = ofit.fit_serial(A, B, 16, sweeps, sketch_p=sketch_p, seed=7, C_init=C0)
     assert dims == ref.bond_dims
     assert mpo.rel_diff(C, ref.C) < tol
+
+
+@pytest.mark.parametrize("sketch_p", [-1, 10])
+def test_cfg2_L20_six_sweeps(sketch_p):
+    """The plain-and-sketched FP64 configuration: L=20, d=2, chi_A=chi_B=32
+    with exp(-k/6) bond weights, chi_C=64, plain and p=10 (k=74), 6 sweeps.
+    The first sweep is checked at 1e-10 directly; sweeps 2..6 by single
+    updates at five positions each (both directions), resumed from the
+    oracle's state just before them (first_sweep, first_bond, c_init); the
+    fit error per sweep (fit_err, transfer passes) of the uninterrupted device
+    fit matches the oracle's."""
+    from paper_2606_23274_amd.api import FitContext
+    A, B = make_pair(20, 2, 32, seed=0, decay=True)
+    traj, cases, state, count = {}, [], {}, {}
+
+    def on_update(sweep, l, Cs):
+        if (sweep % 2 == 0 and l == 19) or (sweep % 2 == 1 and l == 1):
+            traj[sweep + 1] = Cs
+        if sweep > 0:
+            pos = count.get(sweep, 0)
+            count[sweep] = pos + 1
+            if pos in (0, 5, 9, 13, 18):
+                cases.append((sweep, pos, state["C"], l - 1, Cs))
+        state["C"] = Cs
+
+    ofit.fit_serial(A, B, 64, 6, sketch_p=sketch_p, seed=0, on_update=on_update)
+    n2 = mpo.product_norm2(A, B)
+    ctx = FitContext([(A, B)], 64, precision="fp64", sketch_p=sketch_p, seed=0, track_error=True)
+    try:
+        eps = ctx.sweep(6, errors=True)[0]
+        C6 = ctx.export_numpy(0)
+    finally:
+        ctx.close()
+    for s in range(6):
+        ref = mpo.fit_error_transfer(A, B, traj[s + 1], n2)
+        assert abs(eps[s] - ref) <= 1e-7, (s, eps[s], ref)
+    C1, dims = gpu_fit(A, B, 64, 1, precision="fp64", sketch_p=sketch_p, seed=0)
+    assert dims == mpo.bond_dims(traj[1])
+    assert mpo.rel_diff(C1, traj[1]) < 1e-10
+    errs = []
+    for sweep, pos, before, i, after in cases:
+        ctx = FitContext([(A, B)], 64, precision="fp64", sketch_p=sketch_p, seed=0, c_init=[before],
+                         first_sweep=sweep, first_bond=pos)
+        try:
+            ctx.updates(1)
+            C = ctx.export_numpy(0)
+            assert ctx.bond_dims(0) == mpo.bond_dims(after)
+        finally:
+            ctx.close()
+        errs.append(mpo.rel_diff(C, after))
+    print("sketch_p", sketch_p, "single-update distances", ["%.1e" % e for e in errs],
+          "uninterrupted after 6:", mpo.rel_diff(C6, traj[6]))
+    assert len(errs) == 25 and max(errs) < 1e-10

@@ -172,3 +172,66 @@ def test_omega_matches_oracle(hooks, chi, dd, k, bond, stream, pair, seed):
     # the GPU stores row p = c''*dd + su for logical row i = su*chi + c''
     perm = np.array([(p % dd) * chi + p // dd for p in range(m)])
     assert np.abs(got - ref[perm]).max() < 1e-14 * np.abs(ref).max() * 8
+
+
+# clustered spectra: runs of eigenvalues with relative gaps from exact
+# degeneracy to 1e-6; the individual vectors of a tight run are not unique,
+# so each run is checked through its invariant-subspace projector
+@pytest.mark.parametrize("k,r", [(40, 30), (144, 128), (272, 256), (600, 200)])
+@pytest.mark.parametrize("gap", [0.0, 1e-12, 1e-9, 1e-6])
+def test_eig_clusters(hooks, k, r, gap):
+    from tests.gpu_util import dev, ptr
+    rng = np.random.default_rng(k + (0 if gap == 0 else int(-np.log10(gap))))
+    lam = np.exp(-np.arange(k) / (k / 6.0))
+    # three runs inside the kept range: 2, 3 and 4 (nearly) equal values
+    runs = [(1, 2), (7, 3), (r // 2, 4)]
+    for start, size in runs:
+        lam[start:start + size] = lam[start] * (1.0 - gap * np.arange(size))
+    lam = np.sort(lam)[::-1]
+    Q, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    H = (Q * lam) @ Q.T
+    H = 0.5 * (H + H.T)
+    Hd = dev(H)
+    ev = torch.zeros(r, dtype=torch.float64, device="cuda:0")
+    Z = torch.zeros((k, r), dtype=torch.float64, device="cuda:0")
+    _lib.check(hooks.lib.mpo_test_eig(ptr(Hd), k, r, ptr(ev), ptr(Z), *hooks.args()))
+    ev, Z = ev.cpu().numpy(), Z.cpu().numpy()
+    w = np.linalg.eigvalsh(H)[::-1][:r]
+    nrm = lam.max()
+    assert np.abs(ev - w).max() <= 1e-13 * nrm
+    assert np.linalg.norm(H @ Z - Z * ev) / nrm < 1e-12
+    assert np.abs(Z.T @ Z - np.eye(r)).max() < 1e-10
+    # the span of each run (and of everything up to r) against the exact one
+    for start, size in runs:
+        idx = [i for i in range(r) if abs(lam[i] - lam[start]) <= 1e-5 * lam[start]]
+        idx = list(range(min(idx), max(idx) + 1))
+        Pz = Z[:, idx] @ Z[:, idx].T
+        w_all, V_all = np.linalg.eigh(H)
+        sel = np.abs(w_all - lam[start]) <= 1e-5 * lam[start]
+        Pv = V_all[:, sel] @ V_all[:, sel].T
+        assert sel.sum() == len(idx)
+        assert np.abs(Pz - Pv).max() < 1e-10, (start, size)
+
+
+@pytest.mark.parametrize("n,k,rank", [(300, 40, 25), (600, 144, 100), (1024, 272, 200)])
+def test_cholqr_rank_revealing(hooks, n, k, rank):
+    """A rank-deficient sketch (the range finder of a two-site matrix of lower
+    rank than the sketch width): the rank-revealing passes leave zero columns
+    for the dependent directions and an orthonormal basis of the range in the
+    others (checked with the test hook's CholeskyQR2 in rank-revealing mode)."""
+    from tests.gpu_util import dev, ptr
+    rng = np.random.default_rng(n + k + rank)
+    X = rng.standard_normal((n, rank)) @ rng.standard_normal((rank, k))
+    Xd = dev(X)
+    _lib.check(hooks.lib.mpo_test_cholqr_rr(ptr(Xd), n, k, *hooks.args()))
+    Q = Xd.cpu().numpy()
+    norms = np.linalg.norm(Q, axis=0)
+    nz = norms > 0.5
+    assert nz.sum() == rank
+    assert np.all(norms[~nz] < 1e-12)
+    Qn = Q[:, nz]
+    assert np.abs(Qn.T @ Qn - np.eye(rank)).max() < 1e-12
+    # same range as X
+    U, _, _ = np.linalg.svd(X, full_matrices=False)
+    U = U[:, :rank]
+    assert np.abs(Qn @ Qn.T - U @ U.T).max() < 1e-10

@@ -296,7 +296,7 @@ def _right_isometry(cores, l, d):
     return V
 
 
-def _even_odd_dense_check(A, B, chi_max, n_sweeps, sketch_p=-1):
+def _even_odd_dense_check(A, B, chi_max, n_sweeps, sketch_p=-1, C_init=None, first_half=0):
     """Every update of fit_even_odd against brute force.
 
     Half-step h = 2 sweep + q updates the bonds of one parity from the
@@ -314,9 +314,10 @@ def _even_odd_dense_check(A, B, chi_max, n_sweeps, sketch_p=-1):
     L, d = len(A), A[0].shape[1]
     A1, B1, _, _ = fit._preprocess(A, B)
     P = mpo.dense(A1) @ mpo.dense(B1)
-    hist = {}  # (h, l) -> (U4, V4)
+    hist = {}  # (h, l) -> (U4, V4), h counted from the first half-step run
     init = {}
     seen = []
+    h0 = []
 
     def left_core(j, h):  # 1-based site j, as seen by a bond right of it at half-step h
         if h < 0:
@@ -329,7 +330,9 @@ def _even_odd_dense_check(A, B, chi_max, n_sweeps, sketch_p=-1):
         return hist[(h, j - 1)][1]
 
     def on_bond(sweep, q, l, M, f, Psi0, Y0):
-        h = 2 * sweep + q
+        if not h0:
+            h0.append(2 * sweep + q)
+        h = 2 * sweep + q - h0[0]
         if not init:
             init["Psi"] = [p.copy() for p in Psi0]
             init["Y"] = [y.copy() for y in Y0]
@@ -342,7 +345,7 @@ def _even_odd_dense_check(A, B, chi_max, n_sweeps, sketch_p=-1):
                 assert np.abs(X[:, kj].T @ X[:, kj] - np.eye(kj.sum())).max() < 1e-12
                 assert np.abs(W[kj] @ W[kj].T - np.eye(kj.sum())).max() < 1e-12
             Cm = canon.merge_inverse_canonical(Psi0, Y0)
-            D0 = mpo.dense(A1)
+            D0 = mpo.dense(A1 if C_init is None else C_init)
             assert np.abs(mpo.dense(Cm) - D0).max() <= 1e-12 * np.abs(D0).max()
         Cl = [left_core(j, h - (l - j)) for j in range(1, l)]
         Cr = [None] * L
@@ -373,8 +376,10 @@ def _even_odd_dense_check(A, B, chi_max, n_sweeps, sketch_p=-1):
         hist[(h, l)] = (f.U.reshape(cl, d, d, r), f.Vt.reshape(r, d, d, cr))
         seen.append((sweep, q, l))
 
-    res = fit.fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=sketch_p, on_bond=on_bond)
-    assert len(seen) == n_sweeps * (L - 1)
+    res = fit.fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=sketch_p, on_bond=on_bond, C_init=C_init,
+                           first_half=first_half)
+    n_bonds = n_sweeps * (L - 1) - (len([l for l in range(1, L) if l % 2 == 1]) if first_half else 0)
+    assert len(seen) == n_bonds
     return res
 
 
@@ -432,3 +437,37 @@ def test_drop_rule_on_rank_deficient_product():
         res = run(A, Bid, 6, 3)
         assert mpo.fit_error_dense(A, Bid, res.C) < 1e-12
         assert res.n_guard > 0
+
+
+@pytest.mark.parametrize("s,b", [(0, 1), (0, 4), (1, 2), (1, 6), (2, 3)])
+@pytest.mark.parametrize("sketch_p", [-1, 3])
+def test_resume_at_bond_continues_the_fit(s, b, sketch_p):
+    """first_bond = b inside sweep s, started from the fit's state after its
+    first b updates of that sweep: one update reproduces the uninterrupted
+    fit's next state (the mixed-canonical start leaves every orthogonal core
+    in place, R = I), and so does running to the end of the sweep."""
+    A, B = make_pair(9, 2, 4, seed=23, decay=True)
+    states = []
+
+    def on_update(sweep, l, Cs):
+        states.append((sweep, l, [c.copy() for c in Cs]))
+
+    fit.fit_serial(A, B, 6, s + 1, sketch_p=sketch_p, seed=5, on_update=on_update)
+    in_sweep = [st for st in states if st[0] == s]
+    before, after = in_sweep[b - 1][2], in_sweep[b][2]
+    r1 = fit.fit_serial(A, B, 6, 1, sketch_p=sketch_p, seed=5, C_init=before, first_sweep=s, first_bond=b,
+                        n_updates=1)
+    assert mpo.bond_dims(r1.C) == mpo.bond_dims(after)
+    assert mpo.rel_diff(r1.C, after) < 1e-12
+    r_end = fit.fit_serial(A, B, 6, 1, sketch_p=sketch_p, seed=5, C_init=before, first_sweep=s, first_bond=b)
+    assert mpo.rel_diff(r_end.C, in_sweep[-1][2]) < 1e-12
+
+
+@pytest.mark.parametrize("sketch_p", [-1, 2])
+def test_even_odd_first_half_against_dense_projection(sketch_p):
+    """first_half = 1 from a given guess: half-step 1 runs first, from the
+    guess's inverse canonical form, and every update still equals the dense
+    projection onto its light-cone isometries."""
+    A, B = make_pair(7, 2, 3, seed=41, decay=True)
+    G = fit.fit_even_odd(A, B, 5, 1, sketch_p=sketch_p, n_half_steps=1).C
+    _even_odd_dense_check(A, B, 5, 2, sketch_p, C_init=G, first_half=1)
