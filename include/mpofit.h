@@ -214,6 +214,15 @@ mpo_status mpo_fit_bond_dims(const mpo_fit_ctx* ctx, int32_t pair, int32_t* chi_
    split off A and B, so that C ~ A B.  Enqueued on the context's stream. */
 mpo_status mpo_fit_export_c(mpo_fit_ctx* ctx, int32_t pair, double* const* c_cores);
 
+/* Even/odd schedule: the site tensors Psi_l of the inverse canonical form
+   (Sec. 2.3.1) of one pair, of the fit on normalized cores (no norm factor),
+   into caller-owned FP64 device arrays shaped like C's cores; with Y_l =
+   1 / S_l (mpo_fit_singular_values, zero where dropped) the merged train is
+   C_l = Psi_l Y_l.  After a half-step, Psi_l Y_l Psi_{l+1} of an updated
+   bond l is its two-site block U S V^T (Alg. 4).  Synchronizes the context
+   stream. */
+mpo_status mpo_fit_export_psi(mpo_fit_ctx* ctx, int32_t pair, double* const* psi_cores);
+
 /* Number of sweeps run so far. */
 mpo_status mpo_fit_sweeps_done(const mpo_fit_ctx* ctx, int32_t* n);
 

@@ -277,6 +277,9 @@ def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
     L = len(A)
     A1, B1, nu, caps = _preprocess(A, B)
     C0 = canon.right_orthogonalize(A1 if C_init is None else C_init)
+    # the guess acts only as an operator: its scale (it enters Lambda, hence
+    # Y, of the bonds a half-step leaves alone) is set to one
+    C0[0] = C0[0] / np.linalg.norm(C0[0])
     Psi, Y, n_guard = canon.inverse_canonical(C0)
     ones = np.ones((1, 1, 1))
     Lenv = [None] * (L + 1)

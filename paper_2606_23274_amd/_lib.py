@@ -48,7 +48,7 @@ EXPORTS = [
     "mpo_fit_export_c", "mpo_fit_sweeps_done", "mpo_fit_norm_factor", "mpo_fit_truncations",
     "mpo_fit_grad_workspace_bytes", "mpo_fit_grad", "mpo_contract_check_bytes",
     "mpo_contract_exact_check", "mpo_fit_singular_values",
-    "mpo_fit_updates", "mpo_fit_position",
+    "mpo_fit_updates", "mpo_fit_position", "mpo_fit_export_psi",
     "mpo_fit_last_sweep_ms", "mpo_fit_profile", "mpo_gemm_autotune", "mpo_fit_destroy",
     "mpo_last_error",
 ]
@@ -73,6 +73,7 @@ def load() -> C.CDLL:
     lib.mpo_fit_singular_values.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double),
                                             P(C.c_int32)]
     lib.mpo_fit_updates.argtypes = [C.c_void_p, C.c_int32]
+    lib.mpo_fit_export_psi.argtypes = [C.c_void_p, C.c_int32, P(C.c_void_p)]
     lib.mpo_fit_position.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
     lib.mpo_fit_bond_dims.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.mpo_fit_export_c.argtypes = [C.c_void_p, C.c_int32, P(C.c_void_p)]

@@ -228,6 +228,19 @@ class FitContext:
         _lib.check(self.lib.mpo_fit_export_c(self.ctx, pair, ptrs))  # synchronizes our stream
         return cores
 
+    def export_psi(self, pair=0):
+        """Even/odd: the Psi_l of the inverse canonical form (normalized cores,
+        no norm factor) as numpy arrays."""
+        dims = self.bond_dims(pair)
+        L = self.L[pair]
+        d = self._setup.tts[2 * pair].d
+        cores = [torch.empty((dims[i], d, d, dims[i + 1]), dtype=torch.float64, device=self.device)
+                 for i in range(L)]
+        ptrs = (C.c_void_p * L)(*[c.data_ptr() for c in cores])
+        torch.cuda.current_stream(self.device).synchronize()
+        _lib.check(self.lib.mpo_fit_export_psi(self.ctx, pair, ptrs))
+        return [c.cpu().numpy() for c in cores]
+
     def export_numpy(self, pair=0):
         return [c.cpu().numpy() for c in self.export(pair)]
 

@@ -1628,6 +1628,10 @@ void rec_init_pair(Ctx& X, Program& P, PairState& S, int pair) {
   sl.push_back(X.scratch[0].amT);
   rec_reset_amax(X, P, sl);
   if (X.o.schedule == MPO_SCHED_EVEN_ODD) {
+    // the guess acts only as an operator: unit norm (its scale would enter
+    // Lambda, hence Y, of the bonds a half-step leaves alone)
+    add_simple(P, LK::Norm, std::vector<NormDesc>{NormDesc{S.C64[0], (long long)S.cC[0] * S.dd * S.cC[1],
+                                                           X.iEv}}, 0, "init");
     rec_inverse_canonical(X, P, S);
     (void)pair;
     return;
@@ -2814,6 +2818,29 @@ mpo_status mpo_fit_singular_values(mpo_fit_ctx* ctx, int32_t pair, int32_t bond,
     HIP_OK(hipMemcpyAsync(S, P.Yv[bond], n * sizeof(double), hipMemcpyDeviceToHost, X.stream));
     HIP_OK(hipStreamSynchronize(X.stream));
     if (r) *r = n;
+  });
+}
+
+mpo_status mpo_fit_export_psi(mpo_fit_ctx* ctx, int32_t pair, double* const* psi_cores) {
+  return guarded([&] {
+    if (!ctx || !psi_cores) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    Ctx& X = ctx->X;
+    if (X.o.schedule != MPO_SCHED_EVEN_ODD) throw Error{MPO_ERR_UNSUPPORTED, "Psi: even/odd schedule only"};
+    if (pair < 0 || pair >= (int)X.pairs.size()) throw Error{MPO_ERR_INVALID_ARG, "bad pair"};
+    PairState& S = X.pairs[pair];
+    Program P;
+    std::vector<PermDesc> ds;
+    for (int i = 0; i < S.L; ++i) {
+      if (!psi_cores[i]) throw Error{MPO_ERR_INVALID_ARG, "null output core"};
+      const long long n = (long long)S.cC[i] * S.dd * S.cC[i + 1];
+      ds.push_back(perm4(S.C64[i], 0, psi_cores[i], 0, {1, 1, 1, (int)n}, {0, 0, 0, 1}, {0, 0, 0, 1}));
+    }
+    add_perm(P, ds, "export");
+    const size_t keep = X.arena_used;
+    upload(X, P);
+    run_program(P, X.stream, nullptr);
+    HIP_OK(hipStreamSynchronize(X.stream));
+    X.arena_used = keep;
   });
 }
 

@@ -26,3 +26,27 @@ def dev(x, dtype=torch.float64):
 
 def ptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+def device_blocks(ctx, pair, bonds):
+    """Two-site blocks Psi_{l} Y_l Psi_{l+1} (= U S V^T of bond l's last
+    update) of an even/odd fit, as (chi_{l-1} d^2) x (d^2 chi_{l+1}) matrices
+    with rows (c, s1, u1) and columns (s2, u2, c''); 1-based bonds."""
+    psi = ctx.export_psi(pair)
+    out = {}
+    for l in bonds:
+        S = ctx.singular_values(l, pair)
+        Y = np.where(S > 0, 1.0 / np.where(S > 0, S, 1.0), 0.0)
+        a, b = psi[l - 1], psi[l]
+        r = a.shape[3]
+        out[l] = (a.reshape(-1, r) * Y[None, :]) @ b.reshape(r, -1)
+    return out
+
+
+def oracle_block(f):
+    """U S V^T of an oracle factorization (fit.Factor)."""
+    return (f.U * f.S[None, :]) @ f.Vt
+
+
+def block_dist(Bd, Bo):
+    return float(np.linalg.norm(Bd - Bo) / np.linalg.norm(Bo))

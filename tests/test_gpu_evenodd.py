@@ -86,16 +86,21 @@ def test_half_steps_from_oracle_states(precision, tol, sketch_p):
     def on_half_step(sweep, q, Cm):
         hs0.setdefault(q, Cm)
 
-    ofit.fit_even_odd(A, B, 64, 1, sketch_p=sketch_p, seed=3, on_half_step=on_half_step, n_half_steps=1)
+    from tests.gpu_util import block_dist, device_blocks, oracle_block
+    blk0, blk1 = {}, {}
+    ofit.fit_even_odd(A, B, 64, 1, sketch_p=sketch_p, seed=3, on_half_step=on_half_step, n_half_steps=1,
+                      on_bond=lambda s, q, l, M, f, P0, Y0: blk0.__setitem__(l, oracle_block(f)))
     ctx = FitContext([(A, B)], 64, precision=precision, schedule="even_odd", sketch_p=sketch_p, seed=3)
     try:
         ctx.updates(1)
         assert ctx.position() == (0, 1)
         C0 = ctx.export_numpy(0)
+        b0 = device_blocks(ctx, 0, sorted(blk0))
     finally:
         ctx.close()
     e0 = mpo.rel_diff(C0, hs0[0])
-    ref1 = ofit.fit_even_odd(A, B, 64, 1, sketch_p=sketch_p, seed=3, C_init=hs0[0], first_half=1)
+    ref1 = ofit.fit_even_odd(A, B, 64, 1, sketch_p=sketch_p, seed=3, C_init=hs0[0], first_half=1,
+                             on_bond=lambda s, q, l, M, f, P0, Y0: blk1.__setitem__(l, oracle_block(f)))
     ctx = FitContext([(A, B)], 64, precision=precision, schedule="even_odd", sketch_p=sketch_p, seed=3,
                      c_init=[hs0[0]], first_half=1)
     try:
@@ -103,9 +108,11 @@ def test_half_steps_from_oracle_states(precision, tol, sketch_p):
         assert ctx.position() == (1, 0)
         C1 = ctx.export_numpy(0)
         dims = ctx.bond_dims(0)
+        b1 = device_blocks(ctx, 0, sorted(blk1))
     finally:
         ctx.close()
     e1 = mpo.rel_diff(C1, ref1.C)
-    print(precision, sketch_p, "half-step distances", e0, e1)
+    be = max([block_dist(b0[l], blk0[l]) for l in blk0] + [block_dist(b1[l], blk1[l]) for l in blk1])
+    print(precision, sketch_p, "half-step distances", e0, e1, "blocks", be)
     assert dims == ref1.bond_dims
-    assert max(e0, e1) <= tol
+    assert max(e0, e1, be) <= tol

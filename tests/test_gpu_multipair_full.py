@@ -4,16 +4,20 @@ seeded choice) and exp(-k/6) bond weights (seed 1000 + i), chi_C = 2 chi_i,
 sketch p=16, FP32 contractions, all pairs in one context (every stage one
 grouped launch over the bonds of all pairs).
 
-Per pair, through the whole exported train (relative Frobenius distance, the
-FP32 bar 1e-5, same bond dimensions): the first half-step from the initial
-guess against the oracle's; for the pairs of chi <= 64 also the second
-half-step resumed from the oracle's state after the first (first_half = 1),
-in a second grouped context over those pairs.  The distance after the whole
-first sweep is reported: the second half-step's sketch acts on columns in
-the basis of the first half-step's V, which FP32 does not fix inside nearly
-degenerate singular pairs, so it differs from the FP64 oracle's by the
-sketch's own error.  The oracle runs per pair (its first half-step takes
-about half a minute for chi = 128)."""
+Per pair: the first half-step from the initial guess against the oracle's;
+for the pairs of chi <= 64 also the second half-step resumed from the
+oracle's state after the first (first_half = 1), in a second grouped context
+over those pairs.  Each updated bond's two-site block U S V^T (unique, well
+conditioned) is compared at the FP32 bar, 1e-5 relative Frobenius.  The
+merged train C_l = Psi_l Y_l multiplies by Y = 1/S of the bonds the
+half-step leaves alone (up to 1e6 at the drop cut): the oracle's own first
+half-step moves by 5.8e-6 .. 8.4e-6 when its inputs are perturbed by 1e-7
+relative (one FP32 rounding; pairs of chi 64 and 128), so the merged train
+is held to 5e-5, five times that response.  The whole first
+sweep is checked for validity only: the second half-step's sketch acts on
+columns in the basis of the first half-step's V, which FP32 does not fix
+inside nearly degenerate singular pairs.  The oracle runs per pair (its
+first half-step takes about half a minute for chi = 128)."""
 import numpy as np
 import pytest
 
@@ -24,6 +28,7 @@ from synth import make_multi_pair
 pytestmark = pytest.mark.gpu
 
 N_PAIRS, L, P, SEED = 16, 24, 16, 0
+BLOCK_TOL, MERGED_TOL = 1e-5, 5e-5
 
 
 @pytest.fixture(scope="module")
@@ -36,72 +41,87 @@ def device_run():
     ctx = FitContext(pairs, 256, precision="fp32", schedule="even_odd", sketch_p=P, seed=SEED,
                      pair_chi_max=[2 * c for c in chis])
     try:
+        from tests.gpu_util import device_blocks
         ctx.updates(1)
         C0 = [ctx.export_numpy(i) for i in range(N_PAIRS)]
+        blocks0 = [device_blocks(ctx, i, range(1, L, 2)) for i in range(N_PAIRS)]
         ctx.updates(1)
         C1 = [ctx.export_numpy(i) for i in range(N_PAIRS)]
         dims = [ctx.bond_dims(i) for i in range(N_PAIRS)]
     finally:
         ctx.close()
-    return mp, C0, C1, dims
+    return mp, C0, C1, dims, blocks0
 
 
 @pytest.fixture(scope="module")
 def oracle_states(device_run):
+    """The oracle's merged train after its first half-step, and the blocks
+    of the bonds it updated."""
     mp = device_run[0]
     cache = {}
 
     def get(i):
         if i not in cache:
+            from tests.gpu_util import oracle_block
             A, B, chi = mp[i]
-            got = {}
+            got, blk = {}, {}
             ofit.fit_even_odd(A, B, 2 * chi, 1, sketch_p=P, seed=SEED, pair=i,
-                              on_half_step=lambda s, q, Cm: got.setdefault(q, Cm), n_half_steps=1)
-            cache[i] = got[0]
+                              on_half_step=lambda s, q, Cm: got.setdefault(q, Cm), n_half_steps=1,
+                              on_bond=lambda s, q, l, M, f, P0, Y0: blk.__setitem__(l, oracle_block(f)))
+            cache[i] = (got[0], blk)
         return cache[i]
     return get
 
 
 @pytest.mark.parametrize("i", range(N_PAIRS))
 def test_first_half_step(device_run, oracle_states, i):
-    mp, C0, _, _ = device_run
-    ref = oracle_states(i)
+    from tests.gpu_util import block_dist
+    mp, C0, _, _, blocks0 = device_run
+    ref, blk = oracle_states(i)
     err = mpo.rel_diff(C0[i], ref)
-    print(f"pair {i} chi={mp[i][2]}: half-step 0 distance {err:.3e}")
+    berr = max(block_dist(blocks0[i][l], blk[l]) for l in blk)
+    print(f"pair {i} chi={mp[i][2]}: half-step 0 blocks {berr:.3e}, merged train {err:.3e}")
     assert mpo.bond_dims(C0[i]) == mpo.bond_dims(ref)
     assert all(np.isfinite(c).all() for c in C0[i])
-    assert err <= 1e-5
+    assert berr <= BLOCK_TOL
+    assert err <= MERGED_TOL
 
 
 def test_second_half_step_resumed(device_run, oracle_states):
     from paper_2606_23274_amd.api import FitContext
-    mp, _, C1, dims = device_run
+    from tests.gpu_util import block_dist, device_blocks, oracle_block
+    mp = device_run[0]
     small = [i for i in range(N_PAIRS) if mp[i][2] <= 64]
-    starts = [oracle_states(i) for i in small]
+    starts = [oracle_states(i)[0] for i in small]
     ctx = FitContext([(mp[i][0], mp[i][1]) for i in small], 256, precision="fp32", schedule="even_odd",
                      sketch_p=P, seed=SEED, pair_chi_max=[2 * mp[i][2] for i in small], c_init=starts,
                      first_half=1)
     try:
         ctx.updates(1)
         got = [ctx.export_numpy(j) for j in range(len(small))]
+        blocks = [device_blocks(ctx, j, range(2, L, 2)) for j in range(len(small))]
     finally:
         ctx.close()
-    errs = []
+    errs, berrs = [], []
     for j, i in enumerate(small):
         A, B, chi = mp[i]
         # pair index j in the resumed context: its Philox stream is that of pair j
+        blk = {}
         ref = ofit.fit_even_odd(A, B, 2 * chi, 1, sketch_p=P, seed=SEED, pair=j, C_init=starts[j],
-                                first_half=1)
+                                first_half=1,
+                                on_bond=lambda s, q, l, M, f, P0, Y0: blk.__setitem__(l, oracle_block(f)))
         assert mpo.bond_dims(got[j]) == ref.bond_dims
         errs.append(mpo.rel_diff(got[j], ref.C))
-    print("resumed second half-steps:", ["%.1e" % e for e in errs])
-    assert max(errs) <= 1e-5
+        berrs.append(max(block_dist(blocks[j][l], blk[l]) for l in blk))
+    print("resumed second half-steps: blocks", ["%.1e" % e for e in berrs], "merged", ["%.1e" % e for e in errs])
+    assert max(berrs) <= BLOCK_TOL
+    assert max(errs) <= MERGED_TOL
 
 
 def test_whole_sweep_valid(device_run):
     """The first whole sweep: a finite train whose bond dimensions never
     exceed the pair's cap."""
-    mp, _, C1, dims = device_run
+    mp, _, C1, dims, _ = device_run
     for i in range(N_PAIRS):
         assert all(np.isfinite(c).all() for c in C1[i])
         assert max(dims[i]) <= 2 * mp[i][2]

@@ -346,6 +346,7 @@ def _even_odd_dense_check(A, B, chi_max, n_sweeps, sketch_p=-1, C_init=None, fir
                 assert np.abs(W[kj] @ W[kj].T - np.eye(kj.sum())).max() < 1e-12
             Cm = canon.merge_inverse_canonical(Psi0, Y0)
             D0 = mpo.dense(A1 if C_init is None else C_init)
+            D0 = D0 / np.linalg.norm(D0)  # the guess is taken at unit norm
             assert np.abs(mpo.dense(Cm) - D0).max() <= 1e-12 * np.abs(D0).max()
         Cl = [left_core(j, h - (l - j)) for j in range(1, l)]
         Cr = [None] * L
