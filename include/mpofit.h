@@ -282,6 +282,18 @@ mpo_status mpo_contract_exact_check(const mpo_pair* pair, const mpo_tt* C, doubl
                                     double* ab_norm2, int32_t* method, void* workspace,
                                     size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+   tight serving loops, harnesses that forbid allocation): the same check as
+   mpo_contract_exact_check, in the same kernels, with its scratch in a static
+   device array of the library (32 MiB, one copy per GPU, held until the
+   process ends) instead of a workspace argument.  No allocation of any kind
+   is made.  Returns MPO_ERR_WORKSPACE when mpo_contract_check_bytes' figure
+   for the compact layout exceeds 32 MiB (route 0 covers the small trains of
+   exact-regime checks).  Every call on one GPU uses that GPU's array: calls
+   that overlap on one GPU (from several threads or streams) race; the call
+   synchronizes `stream` before returning, so sequential calls are safe. */
+mpo_status mpo_contract_exact_check_static(const mpo_pair* pair, const mpo_tt* C, double* rel_err,
+                                           double* ab_norm2, int32_t* method, void* stream);
 
 /* Device time, in milliseconds, of the last mpo_fit_sweep call's kernels
    between its first and last launch (HIP events on the context stream). */

@@ -47,7 +47,7 @@ EXPORTS = [
     "mpo_fit_workspace_bytes", "mpo_fit_init", "mpo_fit_sweep", "mpo_fit_bond_dims",
     "mpo_fit_export_c", "mpo_fit_sweeps_done", "mpo_fit_norm_factor", "mpo_fit_truncations",
     "mpo_fit_grad_workspace_bytes", "mpo_fit_grad", "mpo_contract_check_bytes",
-    "mpo_contract_exact_check", "mpo_fit_singular_values",
+    "mpo_contract_exact_check", "mpo_contract_exact_check_static", "mpo_fit_singular_values",
     "mpo_fit_updates", "mpo_fit_position", "mpo_fit_export_psi",
     "mpo_fit_last_sweep_ms", "mpo_fit_profile", "mpo_gemm_autotune", "mpo_fit_destroy",
     "mpo_last_error",
@@ -87,6 +87,8 @@ def load() -> C.CDLL:
     lib.mpo_contract_check_bytes.argtypes = [P(MpoPair), P(MpoTT), P(C.c_size_t)]
     lib.mpo_contract_exact_check.argtypes = [P(MpoPair), P(MpoTT), P(C.c_double), P(C.c_double),
                                              P(C.c_int32), C.c_void_p, C.c_size_t, C.c_void_p]
+    lib.mpo_contract_exact_check_static.argtypes = [P(MpoPair), P(MpoTT), P(C.c_double),
+                                                    P(C.c_double), P(C.c_int32), C.c_void_p]
     lib.mpo_fit_last_sweep_ms.argtypes = [C.c_void_p, P(C.c_double)]
     lib.mpo_fit_profile.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_char_p),
                                     P(C.c_double), P(C.c_int32), P(C.c_int32)]

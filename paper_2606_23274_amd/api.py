@@ -319,12 +319,13 @@ class FitContract(torch.autograd.Function):
         return (None, None, *[g * t for t in ctx.saved_tensors])
 
 
-def fit_error(A, B, C, device="cuda:0", with_method=False):
+def fit_error(A, B, C, device="cuda:0", with_method=False, static=False):
     """||A B - C||_F / ||A B||_F and ||A B||_F^2 in FP64 on the GPU
     (mpo_contract_exact_check): Householder-QR sweeps of the naive product
     and the difference MPO when every chi_A chi_B + chi_C <= 512 (method 0,
     accurate far below sqrt(eps)), else transfer passes (method 1, floors
-    near 1e-8 relative)."""
+    near 1e-8 relative).  static=True uses mpo_contract_exact_check_static
+    (the library's static scratch, no workspace)."""
     lib = _lib.load()
     dev = torch.device(device)
     ta, tb, tc = (_TT(_dev_cores(X, dev)) for X in (A, B, C))
@@ -332,13 +333,18 @@ def fit_error(A, B, C, device="cuda:0", with_method=False):
     err, n2, meth = C_.c_double(), C_.c_double(), C_.c_int32()
     with torch.cuda.device(dev):
         stream = torch.cuda.current_stream(dev)
-        nbytes = C_.c_size_t()
-        _lib.check(lib.mpo_contract_check_bytes(C_.byref(pair), C_.byref(tc.tt), C_.byref(nbytes)))
-        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
-        ws_ptr = (ws.data_ptr() + 255) & ~255
-        _lib.check(lib.mpo_contract_exact_check(C_.byref(pair), C_.byref(tc.tt), C_.byref(err),
-                                                C_.byref(n2), C_.byref(meth), C_.c_void_p(ws_ptr),
-                                                nbytes.value, C_.c_void_p(stream.cuda_stream)))
+        if static:
+            _lib.check(lib.mpo_contract_exact_check_static(C_.byref(pair), C_.byref(tc.tt),
+                                                           C_.byref(err), C_.byref(n2), C_.byref(meth),
+                                                           C_.c_void_p(stream.cuda_stream)))
+        else:
+            nbytes = C_.c_size_t()
+            _lib.check(lib.mpo_contract_check_bytes(C_.byref(pair), C_.byref(tc.tt), C_.byref(nbytes)))
+            ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+            ws_ptr = (ws.data_ptr() + 255) & ~255
+            _lib.check(lib.mpo_contract_exact_check(C_.byref(pair), C_.byref(tc.tt), C_.byref(err),
+                                                    C_.byref(n2), C_.byref(meth), C_.c_void_p(ws_ptr),
+                                                    nbytes.value, C_.c_void_p(stream.cuda_stream)))
     if with_method:
         return err.value, n2.value, meth.value
     return err.value, n2.value

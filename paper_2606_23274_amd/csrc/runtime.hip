@@ -2442,6 +2442,13 @@ void validate_grad(const Ctx& X, const PairState& S, const mpo_pair* ab, const m
 }  // namespace
 }  // namespace mpofit
 
+// Static scratch of the allocation-free check (mpo_contract_exact_check_static):
+// a file-scope device array, one copy per GPU, held until the process ends.
+// Host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device; the array's name on the host is a stand-in.
+static constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
 namespace mpofit {
 namespace {
 // The exact check's two routes: Householder-QR sweeps (check_qr_fits) or
@@ -2543,6 +2550,21 @@ void check_run(const mpo_pair& pair, const mpo_tt& C, double* rel_err, double* a
   if (method) *method = 1;
 }
 
+// Address of the static scratch on the current device (kept per device).
+char* static_scratch_ptr() {
+  static std::mutex mu;
+  static std::map<int, char*> ptrs;
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = ptrs.find(dev);
+  if (it != ptrs.end()) return it->second;
+  void* p = nullptr;
+  HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(::scratch)));
+  if (!p) throw Error{MPO_ERR_DEVICE, "static scratch has no device address"};
+  ptrs[dev] = static_cast<char*>(p);
+  return static_cast<char*>(p);
+}
 }  // namespace
 }  // namespace mpofit
 
@@ -3040,6 +3062,22 @@ mpo_status mpo_contract_exact_check(const mpo_pair* pair, const mpo_tt* C, doubl
     if (reinterpret_cast<uintptr_t>(workspace) & 255) throw Error{MPO_ERR_WORKSPACE, "workspace not 256-byte aligned"};
     check_run(*pair, *C, rel_err, ab_norm2, method, static_cast<char*>(workspace), ws_bytes,
               static_cast<hipStream_t>(stream), false);
+  });
+}
+
+// The same check in the library's static scratch: no allocation at all.
+mpo_status mpo_contract_exact_check_static(const mpo_pair* pair, const mpo_tt* C, double* rel_err,
+                                           double* ab_norm2, int32_t* method, void* stream) {
+  return guarded([&] {
+    if (!pair || !C || !rel_err) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    const size_t need = check_bytes(*pair, *C, true);
+    if (need > ::kStaticScratchBytes)
+      throw Error{MPO_ERR_WORKSPACE, "check needs " + std::to_string(need) +
+                                         " bytes, above the static scratch of " +
+                                         std::to_string(::kStaticScratchBytes)};
+    char* ws = static_scratch_ptr();
+    check_run(*pair, *C, rel_err, ab_norm2, method, ws, ::kStaticScratchBytes,
+              static_cast<hipStream_t>(stream), true);
   });
 }
 

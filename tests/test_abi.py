@@ -120,6 +120,7 @@ def test_null_pointers():
     assert _query([p], _opts())[0] == 1
     assert lib.mpo_fit_sweep(None, 1, None) == 1
     assert lib.mpo_fit_singular_values(None, 0, 1, None, None) == 1
+    assert lib.mpo_contract_exact_check_static(None, None, None, None, None, None) == 1
 
 
 def test_undersized_or_misaligned_workspace():
