@@ -110,7 +110,7 @@ def check(status: int) -> None:
 
 
 TEST_EXPORTS = ["mpo_test_gemm", "mpo_test_eig", "mpo_test_eig_batch", "mpo_test_cholqr",
-                "mpo_test_cholqr_rr", "mpo_test_omega"]
+                "mpo_test_cholqr_rr", "mpo_test_jacobi", "mpo_test_omega"]
 
 
 def load_test_hooks() -> C.CDLL:
@@ -123,6 +123,7 @@ def load_test_hooks() -> C.CDLL:
     lib.mpo_test_eig_batch.argtypes = [vp, i, i, i, vp, vp, vp, C.c_size_t, vp]
     lib.mpo_test_cholqr.argtypes = [vp, i, i, vp, C.c_size_t, vp]
     lib.mpo_test_cholqr_rr.argtypes = [vp, i, i, vp, C.c_size_t, vp]
+    lib.mpo_test_jacobi.argtypes = [vp, i, vp, vp, vp, C.c_size_t, vp]
     lib.mpo_test_omega.argtypes = [vp, i, i, i, i, i, i, C.c_uint64, vp, C.c_size_t, vp]
     for n in TEST_EXPORTS:
         getattr(lib, n).restype = C.c_int

@@ -30,6 +30,17 @@ template <int TILE> struct TileShape;
 template <> struct TileShape<0> { static constexpr int BM = 64, BN = 64; };
 template <> struct TileShape<1> { static constexpr int BM = 128, BN = 128; };
 template <> struct TileShape<2> { static constexpr int BM = 64, BN = 64; };  // half-depth slabs
+// FP64 only, for the small factorization products (k x k Gram matrices,
+// n x k applications), where 64 x 64 tiles leave most of the chip idle and
+// split-K pays a device-scope fence per tile:
+//   3: 32 x 32, one 16 x 16 MFMA block per wave, 32-deep slabs;
+//   4: the same with 128-deep slabs (fewer global-load round trips);
+//   5: 16 x 16, the four waves take interleaved quarters of each 128-deep
+//      slab and sum their blocks through LDS at the end (a quarter of the
+//      MFMA chain per wave, no global split-K).
+template <> struct TileShape<3> { static constexpr int BM = 32, BN = 32; };
+template <> struct TileShape<4> { static constexpr int BM = 32, BN = 32; };
+template <> struct TileShape<5> { static constexpr int BM = 16, BN = 16; };
 
 template <Mode M> struct ModeT;
 template <> struct ModeT<Mode::F64> {
@@ -63,7 +74,7 @@ template <> struct ModeT<Mode::BF16X3> : ModeT<Mode::BF16> {};
 // workgroups per CU, which pays when K is short and every tile's first
 // loads are exposed.
 constexpr int slab_k(Mode m, int tile) {
-  return m == Mode::F64 ? 32
+  return m == Mode::F64 ? (tile >= 4 ? 128 : 32)
          : m == Mode::F32 ? (tile == 0 ? 64 : 32)
          : m == Mode::BF16 ? (tile == 0 ? 128 : 64)
                            : (tile == 0 ? 64 : 32);
@@ -210,7 +221,8 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
   constexpr int BM = TileShape<TILE>::BM, BN = TileShape<TILE>::BN;
   constexpr int BK = slab_k(MODE, TILE), LDL = BK + MT::PAD;
   constexpr int NSUB = BK / MT::KSUB;
-  constexpr int WM = BM / 2, WN = BN / 2;       // wave tile
+  constexpr bool KW = TILE == 5;                // waves split K (one output block)
+  constexpr int WM = KW ? BM : BM / 2, WN = KW ? BN : BN / 2;  // wave tile
   constexpr int FM = WM / 16, FN = WN / 16;     // MFMA blocks per wave
 
   constexpr int NLO = MODE == Mode::BF16X3 ? 2 : 1;  // hi (and lo) tiles
@@ -262,7 +274,7 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int wm = KW ? 0 : (wave >> 1) * WM, wn = KW ? 0 : (wave & 1) * WN;
   const int lrow = lane & 15, lgrp = lane >> 4;
 
   accv_t acc[FM][FN];
@@ -292,6 +304,7 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
     }
 #pragma unroll
     for (int ks = 0; ks < NSUB; ++ks) {
+    if (KW && (ks & 3) != wave) continue;  // wave-uniform
     const lds_t* As = sA[0][cur] + ks * MT::KSUB;
     const lds_t* Bs = sB[0][cur] + ks * MT::KSUB;
     if constexpr (MODE == Mode::BF16X3) {
@@ -375,9 +388,22 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
     __syncthreads();
   }
 
+  if constexpr (KW) {  // the four partial blocks, summed in wave order
+    __shared__ acc_t red[3][4][64];
+    if (wave > 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[wave - 1][e][lane] = acc[0][0][e];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[0][0][e] += red[w][e][lane];
+  }
   // split-K: every split stores its partial tile; the last to arrive sums
   // them in split order (deterministic) and runs the epilogue.
-  if (d.splits > 1) {
+  if (!KW && d.splits > 1) {
     const long long tile_id = ((long long)bidx * d.tiles_m + tm) * d.tiles_n + tn;
     acc_t* part = reinterpret_cast<acc_t*>(d.partials) +
                   (tile_id * d.splits) * (long long)(BM * BN);
@@ -449,7 +475,10 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
 template <Mode MODE, typename TA, typename TB, typename TC, bool AK, bool BKC>
 void launch_tile(int tile, const GemmDesc* d, int n, int wgs, hipStream_t s) {
   if constexpr (MODE == Mode::F64) {
-    gemm_kernel<MODE, TA, TB, TC, AK, BKC, 0><<<wgs, kThreads, 0, s>>>(d, n);
+    if (tile == 3) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 3><<<wgs, kThreads, 0, s>>>(d, n);
+    else if (tile == 4) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 4><<<wgs, kThreads, 0, s>>>(d, n);
+    else if (tile == 5) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 5><<<wgs, kThreads, 0, s>>>(d, n);
+    else gemm_kernel<MODE, TA, TB, TC, AK, BKC, 0><<<wgs, kThreads, 0, s>>>(d, n);
   } else {
     if (tile == 1) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 1><<<wgs, kThreads, 0, s>>>(d, n);
     else if (tile == 2) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 2><<<wgs, kThreads, 0, s>>>(d, n);
@@ -485,9 +514,9 @@ void launch_types(const GemmKind& k, const GemmDesc* d, int n, int wgs, hipStrea
 
 }  // namespace
 
-int gemm_bm(int tile) { return tile == 1 ? 128 : 64; }
-int gemm_bn(int tile) { return tile == 1 ? 128 : 64; }
-int gemm_bk(Mode mode, int tile) { return slab_k(mode, mode == Mode::F64 ? 0 : tile); }
+int gemm_bm(int tile) { return tile == 1 ? 128 : tile == 5 ? 16 : tile >= 3 ? 32 : 64; }
+int gemm_bn(int tile) { return gemm_bm(tile); }
+int gemm_bk(Mode mode, int tile) { return slab_k(mode, mode == Mode::F64 ? (tile >= 3 ? tile : 0) : tile); }
 size_t gemm_acc_bytes(Mode mode) { return mode == Mode::F64 ? 8 : 4; }
 
 void launch_gemm(const GemmKind& kind, const GemmDesc* d_descs, int n_desc, int total_wgs,

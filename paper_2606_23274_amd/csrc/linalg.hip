@@ -1606,7 +1606,10 @@ __global__ void __launch_bounds__(kBig) geqr_kernel(const GeqrDesc* __restrict__
     }
     __syncthreads();  // every thread has read alpha
     for (int i = j + 1 + threadIdx.x; i < m; i += kBig) X[i * ld + j] *= scal;
-    if (threadIdx.x == 0) X[j * ld + j] = beta;
+    if (threadIdx.x == 0) {
+      X[j * ld + j] = beta;
+      if (d.tau) gstore_ptr(d.tau)[j] = tau;
+    }
     __syncthreads();
     if (tau != 0.0) {
       for (int c = j + 1 + threadIdx.x; c < n; c += kBig) {
@@ -1626,6 +1629,41 @@ __global__ void __launch_bounds__(kBig) geqr_kernel(const GeqrDesc* __restrict__
   }
 }
 }  // namespace
+
+// Q = H_0 H_1 ... H_{n-1} [I; 0], one thread per column: column c starts as
+// e_c and takes H_{n-1} .. H_c (H_j leaves columns c < j alone: they vanish
+// on rows >= j), so the columns never interact.  The reflector entries are
+// the same address across the threads (a broadcast).
+__global__ void __launch_bounds__(kBig) orgqr_kernel(const OrgqrDesc* __restrict__ descs) {
+  const OrgqrDesc d = descs[blockIdx.x];
+  const int m = d.m, n = d.n;
+  const long long ldx = d.ldx, ldq = d.ldq;
+  const GAS double* X = gload_ptr(d.X);
+  const GAS double* tau = gload_ptr(d.tau);
+  GAS double* Q = gstore_ptr(d.Q);
+  for (int c = threadIdx.x; c < n; c += kBig) {
+    for (int i = 0; i < m; ++i) Q[i * ldq + c] = i == c ? 1.0 : 0.0;
+    for (int j = c; j >= 0; --j) {
+      const double t = tau[j];
+      if (t == 0.0) continue;
+      double w = Q[j * ldq + c];
+      for (int i = j + 1; i < m; ++i) w = fma(X[i * ldx + j], Q[i * ldq + c], w);
+      w *= t;
+      Q[j * ldq + c] -= w;
+      for (int i = j + 1; i < m; ++i) Q[i * ldq + c] = fma(-X[i * ldx + j], w, Q[i * ldq + c]);
+    }
+    GAS double* R = gstore_ptr(d.R);
+    if (R[(long long)c * d.ldr + c] < 0.0) {
+      for (int i = 0; i < m; ++i) Q[i * ldq + c] = -Q[i * ldq + c];
+      for (int e = c; e < n; ++e) R[(long long)c * d.ldr + e] = -R[(long long)c * d.ldr + e];
+    }
+  }
+}
+
+void launch_orgqr(const OrgqrDesc* d, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(orgqr_kernel, dim3(n), dim3(kBig), 0, s, d);
+}
 
 void launch_geqr(const GeqrDesc* d, int n, hipStream_t s) {
   if (n <= 0) return;

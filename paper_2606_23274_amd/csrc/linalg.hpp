@@ -85,8 +85,22 @@ struct GeqrDesc {
   int m, n, ldx;
   double* R;
   int ldr;
+  double* tau;  // nullable: the reflector coefficients, for orgqr_kernel
+};
+// Q (m x n, m >= n) from the reflectors geqr_kernel left in X and tau, with
+// the signs normalized so that diag(R) >= 0 (column c of Q and row c of R
+// negated where R(c, c) < 0).
+struct OrgqrDesc {
+  const double* X;
+  int m, n, ldx;
+  const double* tau;
+  double* Q;
+  int ldq;
+  double* R;
+  int ldr;
 };
 void launch_geqr(const GeqrDesc* d, int n, hipStream_t s);
+void launch_orgqr(const OrgqrDesc* d, int n, hipStream_t s);
 
 size_t eig_work_doubles(int k, int r);
 // Panel reduction of the global-memory path: widest panel, the panel width

@@ -52,6 +52,7 @@ void run_program(const Program& p, hipStream_t s, hipEvent_t* ev) {
       case LK::Bump: launch_bump(l.counter, l.bump_by, s); break;
       case LK::Jacobi: launch_jacobi(p.device<JacobiDesc>(l), l.n, (int)l.maxa, s); break;
       case LK::Geqr: launch_geqr(p.device<GeqrDesc>(l), l.n, s); break;
+      case LK::Orgqr: launch_orgqr(p.device<OrgqrDesc>(l), l.n, s); break;
       case LK::Naive: launch_naive(p.device<NaiveDesc>(l), l.n, l.maxa, s); break;
       case LK::Polish: launch_polish(p.device<PolishDesc>(l), l.n, (int)l.maxa, s); break;
       case LK::NormBig: {
@@ -173,7 +174,8 @@ void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<
   if (sb.record) sb.record->emplace_back(mode, jobs);
   GemmKind gk{mode, jobs[0].A.t, jobs[0].B.t, jobs[0].C.t, jobs[0].A.kc, jobs[0].B.kc, 0};
   // tile 128x128 is possible for FP32/BF16 when every problem is large
-  // enough; tile 2 (64x64, half-depth slabs) for FP32/BF16 always
+  // enough; tile 2 (64x64, half-depth slabs) for FP32/BF16 always; tiles 3-5
+  // (32x32, 32x32 with deep slabs, 16x16 with the waves splitting K) for FP64
   bool big = mode != Mode::F64;
   long long w128 = 0;
   int kmax = 0;
@@ -188,7 +190,12 @@ void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<
     for (auto& t : *sb.tune)
       if (same_class(t, key)) { tuned = &t; break; }
   }
-  auto usable = [&](int t) { return mode == Mode::F64 ? 0 : t == 1 ? (big ? 1 : 0) : t == 2 ? 2 : 0; };
+  auto usable = [&](int t) {
+    if (mode == Mode::F64) return t >= 3 && t <= 5 ? t : 0;
+    return t == 1 ? (big ? 1 : 0) : t == 2 ? 2 : 0;
+  };
+  long long w64 = 0;
+  for (auto& j : jobs) w64 += (long long)ceil_div(j.M, 64) * ceil_div(j.N, 64) * j.nb[0] * j.nb[1] * j.nb[2];
   int split_cap = 0;  // 0: built-in rule
   if (sb.force_tile >= 0) {
     gk.tile = usable(sb.force_tile);
@@ -199,6 +206,9 @@ void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<
   } else if (big && w128 >= 256) {
     // built-in: the large tile when the launch still fills the chip
     gk.tile = 1;
+  } else if (mode == Mode::F64 && w64 < 128) {
+    // small FP64 products: 16x16 tiles, K split over the waves
+    gk.tile = 5;
   } else if (kmax <= 512) {
     gk.tile = usable(2);  // short K: more resident workgroups
   }
@@ -209,7 +219,8 @@ void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<
   // built-in split-K rule: only launches of fewer than 128 tiles are split,
   // up to filling 256 CUs once, with at least four K slabs per split (the
   // deterministic reduction costs a device-scope fence per tile)
-  const int want = split_cap > 0 ? split_cap
+  const int want = gk.tile == 5 ? 1  // (the waves split K; no global split)
+                   : split_cap > 0 ? split_cap
                    : base_wgs >= 128 ? 1
                                      : (int)std::min<long long>(8, (256 + base_wgs - 1) / base_wgs);
   const int min_slabs = split_cap > 0 ? 1 : 4;
@@ -399,7 +410,7 @@ struct Ctx {
   size_t arena_cap = 0;
   size_t arena_used = 0;
   // init scratch (FP64)
-  double *iG, *iR1, *iR2, *iRt, *iTmp, *iXt, *iJ;
+  double *iG, *iR1, *iR2, *iRt, *iTmp, *iXt, *iJ, *iTau;
   double *iH, *iZ, *iEw, *iEv, *iSg;  // eigenproblem of the inverse-canonical init
   size_t iTmpN = 0;
   int sweeps_done = 0;
@@ -914,6 +925,7 @@ void carve(Ctx& X, Carver& cv) {
   X.iTmp = cv.take<double>((size_t)core_max);
   X.iXt = cv.take<double>((size_t)core_max);
   X.iJ = cv.take<double>((size_t)kq * kq);
+  X.iTau = cv.take<double>((size_t)kq);
   if (X.o.schedule == MPO_SCHED_EVEN_ODD) {
     X.iH = cv.take<double>((size_t)kq * kq);
     X.iZ = cv.take<double>((size_t)kq * kq);
@@ -991,10 +1003,18 @@ double flops_e2m(const PairState& P, int j) { return 2.0 * P.cC[j + 1] * P.dd * 
 // its bond, e.g. an unused bond state) becomes a zero column of Q with a zero
 // row of R instead of a failure, where Householder QR would complete Q with
 // an arbitrary orthonormal column of the same (zero) weight.
-CholQRJob init_qr(double* Xm, int n, int k, Ctx& X) {
-  CholQRJob j{Xm, n, k, k, X.iG, X.iR1, X.iRt, nullptr, true};
-  j.eta = kRankEta;
-  return j;
+// Householder QR of the n x k matrix Xm (row-major, n >= k) for the
+// canonical forms of the initialization: the reflectors overwrite Xm, R
+// (diag >= 0, row-major) goes to X.iRt and Q (n x k, row-major, leading
+// dimension k) to Qout.  Unlike Cholesky-QR, whose backward error carries
+// the squared condition number of the first pass, Householder QR keeps
+// the small singular directions of the graded factors that the sweeps
+// carry from core to core, which the inverse gauge then divides by.
+void add_hhqr(Ctx& X, Program& P, double* Xm, int n, int k, double* Qout) {
+  if (n < k) throw Error{MPO_ERR_SHAPE, "Householder QR needs rows >= columns"};
+  add_simple(P, LK::Geqr, std::vector<GeqrDesc>{GeqrDesc{Xm, n, k, k, X.iRt, k, X.iTau}}, 0, "init");
+  add_simple(P, LK::Orgqr, std::vector<OrgqrDesc>{OrgqrDesc{Xm, n, k, k, X.iTau, Qout, k, X.iRt, k}}, 0,
+             "init");
 }
 
 // Left-orthogonalization (Alg. 5 preprocessing) of one MPO held in `cores`,
@@ -1010,7 +1030,8 @@ void rec_qr_sweep(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores,
     const int p = cur[i] * dd, q = cur[i + 1];
     const int nn = dd * cur[i + 2];  // columns of the next core (its right bond untouched yet)
     if (p >= q) {
-      add_cholqr(X, P, {init_qr(cores[i], p, q, X)}, 3);
+      add_hhqr(X, P, cores[i], p, q, X.iTmp);
+      add_perm(P, {perm4(X.iTmp, 0, cores[i], 0, {1, 1, p, q}, {0, 0, q, 1}, {0, 0, q, 1})}, "copy");
       add_gemm(P, X.sb, Mode::F64, {GemmJob{q, nn, q, op64(X.iRt, true, q), op64(cores[i + 1], false, nn),
                                             out64(X.iTmp, nn)}}, "init", 0);
     } else {
@@ -1033,8 +1054,8 @@ void rec_rq_sweep(Ctx& X, Program& P, PairState& S, std::vector<int>& cur, int s
     const int mp = cur[j - 1] * dd;  // rows of the previous core
     if (p <= q) {
       add_perm(P, {perm4(S.C64[j], 0, X.iXt, 0, {1, 1, p, q}, {0, 0, q, 1}, {0, 0, 1, p})}, "copy");
-      add_cholqr(X, P, {init_qr(X.iXt, q, p, X)}, 3);
-      add_perm(P, {perm4(X.iXt, 0, S.C64[j], 0, {1, 1, q, p}, {0, 0, p, 1}, {0, 0, 1, q})}, "copy");
+      add_hhqr(X, P, X.iXt, q, p, X.iTmp);
+      add_perm(P, {perm4(X.iTmp, 0, S.C64[j], 0, {1, 1, q, p}, {0, 0, p, 1}, {0, 0, 1, q})}, "copy");
       add_gemm(P, X.sb, Mode::F64, {GemmJob{mp, p, p, op64(S.C64[j - 1], true, p), op64(X.iRt, true, p),
                                             out64(X.iTmp, p)}}, "init", 0);
       add_perm(P, {perm4(X.iTmp, 0, S.C64[j - 1], 0, {1, 1, mp, p}, {0, 0, p, 1}, {0, 0, p, 1})}, "copy");
@@ -1379,8 +1400,8 @@ void rec_inverse_canonical(Ctx& X, Program& P, PairState& S) {
     const int p = S.cC[i] * dd, q = S.cC[i + 1], nn = dd * S.cC[i + 2];
     if (q > 512 || p < q) throw Error{MPO_ERR_UNSUPPORTED, "inverse canonical form: bond above 512"};
     double* Xi = S.C64[i];
-    // X = Q R (shifted CholeskyQR3; R accumulated in iRt)
-    add_cholqr(X, P, {init_qr(Xi, p, q, X)}, 3);
+    // X = Q R (Householder; Q into iXt, R into iRt)
+    add_hhqr(X, P, Xi, p, q, X.iXt);
     // precondition: W0 = R Z with Z the eigenvectors of R^T R (its columns
     // are then orthogonal up to clusters of tiny singular values), then
     // one-sided Jacobi on W0: W0 V' = Ur diag(S) with high relative accuracy
@@ -1388,6 +1409,14 @@ void rec_inverse_canonical(Ctx& X, Program& P, PairState& S) {
                                           out64(X.iH, q)}}, "init", 0);
     const bool reg = q <= kRegMax;
     add_eig(P, X.sb, {EigDesc{X.iH, q, q, q, X.iEv, X.iZ, q, X.iEw, X.flag}}, reg, "init");
+    // Z orthonormal to working precision (two Newton-Schulz steps, iZ -> iJ
+    // -> iZ): Jacobi returns the left singular vectors of R Z, which are
+    // those of R only for an orthogonal Z, and eigenvectors of tiny, close
+    // eigenvalues of R^T R come out orthogonal only to about
+    // eps ||R||^2 / gap
+    const std::vector<CholQRJob> zj{CholQRJob{X.iZ, q, q, q, X.iG, X.iR1, nullptr, X.iJ}};
+    add_polish_pass(X, P, zj, 0, false);
+    add_polish_pass(X, P, zj, 1, false);
     add_gemm(P, X.sb, Mode::F64, {GemmJob{q, q, q, op64(X.iRt, true, q), op64(X.iZ, false, q),
                                           out64(X.iG, q)}}, "init", 0);
     {
@@ -1401,7 +1430,7 @@ void rec_inverse_canonical(Ctx& X, Program& P, PairState& S) {
       P.launches.push_back(l);
     }
     // U = Q Ur (into iTmp), sign rule on U, the same flips on Ur
-    add_gemm(P, X.sb, Mode::F64, {GemmJob{p, q, q, op64(Xi, true, q), op64(X.iR2, false, q),
+    add_gemm(P, X.sb, Mode::F64, {GemmJob{p, q, q, op64(X.iXt, true, q), op64(X.iR2, false, q),
                                           out64(X.iTmp, q)}}, "init", 0);
     add_simple(P, LK::Sign, std::vector<SignDesc>{SignDesc{X.iTmp, p, q, q, X.iSg, nullptr}}, q, "init");
     add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{X.iR2, X.iR2, q, q, q, q, nullptr, X.iSg, 0, 0}},
@@ -1688,7 +1717,7 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
     throw Error{MPO_ERR_INVALID_ARG, "bad tuning table"};
   X.tune.assign(o->tune, o->tune + o->n_tune);
   for (auto& t : X.tune)
-    if (t.tile < 0 || t.tile > 2 || t.splits < 1 || t.splits > 64)
+    if (t.tile < 0 || t.tile > 5 || t.splits < 1 || t.splits > 64)
       throw Error{MPO_ERR_INVALID_ARG, "bad tuning entry"};
   X.sb.tune = X.tune.empty() ? nullptr : &X.tune;
   X.pairs.resize(n_pairs);
@@ -2954,9 +2983,11 @@ mpo_status mpo_gemm_autotune(const mpo_pair* pairs, int32_t n_pairs, const mpo_f
         if (seen) continue;
         mpo_gemm_tune win = key;
         win.us = -1;
-        for (int tile = 0; tile < (r.first == Mode::F64 ? 1 : 3); ++tile) {
+        const std::vector<int> tiles = r.first == Mode::F64 ? std::vector<int>{0, 3, 4, 5}
+                                                            : std::vector<int>{0, 1, 2};
+        for (int tile : tiles) {
           for (int sp : {1, 2, 4, 8, 16}) {
-            if (sp > 1 && key.K / sp < gemm_bk(r.first, tile)) continue;
+            if (sp > 1 && (tile == 5 || key.K / sp < gemm_bk(r.first, tile))) continue;
             Program P;
             X.sb.force_tile = tile;
             X.sb.force_splits = sp;
@@ -3145,6 +3176,9 @@ mpo_status mpo_test_gemm(int mode, int ta, int tb, int tc, int a_kcontig, int b_
     d.alpha = alpha; d.beta = beta;
     auto vec = [](const void* p, int ld) { return (ld % 4 == 0 && aligned16(p)) ? 1 : 0; };
     d.vec_a = vec(A, lda); d.vec_b = vec(B, ldb);
+    const bool f64_tile = tile == 0 || tile >= 3;  // FP64: 0, 3, 4, 5; otherwise 0, 1, 2
+    if (tile < 0 || tile > 5 || (tile != 0 && (md == Mode::F64) != f64_tile) || (tile == 5 && splits > 1))
+      throw Error{MPO_ERR_INVALID_ARG, "GEMM tile"};
     int s = std::max(1, splits);
     int kchunk = ceil_div(ceil_div(K, s), BK) * BK;
     s = std::max(1, ceil_div(K, kchunk));
@@ -3221,6 +3255,25 @@ static mpo_status test_cholqr(double* Xm, int n, int k, double eta, void* worksp
 
 mpo_status mpo_test_cholqr(double* Xm, int n, int k, void* workspace, size_t ws_bytes, void* stream) {
   return test_cholqr(Xm, n, k, 0.0, workspace, ws_bytes, stream);
+}
+
+mpo_status mpo_test_jacobi(const double* W, int q, double* Ur, double* S, void* workspace, size_t ws_bytes,
+                           void* stream) {
+  return guarded([&] {
+    if (!W || !Ur || !S || q < 1 || q > 512) throw Error{MPO_ERR_INVALID_ARG, "jacobi: q in 1..512"};
+    TestEnv T(workspace, ws_bytes, stream);
+    double* work = T.cv.take<double>((size_t)q * q);
+    if (T.cv.off > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "test workspace too small"};
+    Program P;
+    Launch l;
+    l.kind = LK::Jacobi;
+    l.off = P.push(std::vector<JacobiDesc>{JacobiDesc{W, q, q, Ur, q, S, work, 0.0, nullptr}});
+    l.n = 1;
+    l.maxa = q;
+    l.cls = "jacobi";
+    P.launches.push_back(l);
+    T.go(P);
+  });
 }
 
 mpo_status mpo_test_cholqr_rr(double* Xm, int n, int k, void* workspace, size_t ws_bytes, void* stream) {

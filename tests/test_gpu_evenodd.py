@@ -68,9 +68,11 @@ def test_even_odd_initial_guess_fp64():
     assert mpo.rel_diff(C[0], ref.C) < 1e-10
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+# (tolerance of the first half-step and of the per-bond blocks, of the
+# resumed second half-step)
+@pytest.mark.parametrize("precision,tol,tol_resumed", [("fp64", 1e-10, 5e-10), ("fp32", 1e-5, 1e-5)])
 @pytest.mark.parametrize("sketch_p", [-1, 8])
-def test_half_steps_from_oracle_states(precision, tol, sketch_p):
+def test_half_steps_from_oracle_states(precision, tol, tol_resumed, sketch_p):
     """Each half-step of the inverse-gauge schedule from a given state: the
     first one from the initial guess (mpo_fit_updates of one half-step), the
     second one resumed from the oracle's merged train after the first
@@ -78,7 +80,11 @@ def test_half_steps_from_oracle_states(precision, tol, sketch_p):
     against the oracle's same step.  A whole FP32 sweep is not compared: the
     second half-step's sketch acts on columns in the basis of the first
     half-step's V, which is not fixed inside nearly degenerate singular pairs
-    at FP32 precision."""
+    at FP32 precision.  The resumed FP64 half-step is held to 5e-10: it
+    starts from the inverse canonical form of a merged train whose singular
+    values reach 1.2e-6 of the largest, and the environments divide the rows
+    of each Psi by them, so a canonical form accurate to eps in norm per
+    bond leaves errors of eps / 1.2e-6 (about 1e-10) in those rows."""
     from paper_2606_23274_amd.api import FitContext
     A, B = make_pair(16, 2, 32, seed=44, decay=True)
     hs0 = {}
@@ -115,4 +121,5 @@ def test_half_steps_from_oracle_states(precision, tol, sketch_p):
     be = max([block_dist(b0[l], blk0[l]) for l in blk0] + [block_dist(b1[l], blk1[l]) for l in blk1])
     print(precision, sketch_p, "half-step distances", e0, e1, "blocks", be)
     assert dims == ref1.bond_dims
-    assert max(e0, e1, be) <= tol
+    assert max(e0, be) <= tol
+    assert e1 <= tol_resumed

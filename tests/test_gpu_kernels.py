@@ -26,12 +26,18 @@ TOL = {0: 1e-13, 1: 2e-5, 2: 2e-2}
 @pytest.mark.parametrize("akc,bkc", [(1, 1), (1, 0), (0, 1), (0, 0)])
 @pytest.mark.parametrize("M,N,K,tile,splits", [(64, 64, 64, 0, 1), (77, 45, 53, 0, 1),
                                                (200, 136, 300, 1, 1), (130, 70, 1000, 0, 4),
-                                               (77, 45, 53, 2, 1), (130, 70, 1000, 2, 4)])
+                                               (77, 45, 53, 2, 1), (130, 70, 1000, 2, 4),
+                                               (77, 45, 53, 3, 1), (130, 70, 1000, 3, 4),
+                                               (77, 45, 53, 4, 1), (144, 144, 300, 4, 2),
+                                               (77, 45, 53, 5, 1), (144, 144, 512, 5, 1),
+                                               (513, 145, 143, 5, 1)])
 def test_gemm_against_numpy(hooks, kind, akc, bkc, M, N, K, tile, splits):
     from tests.gpu_util import dev, ptr
     mode, ta, tb, tc = kind
-    if mode == 0 and tile == 1:
-        tile = 0
+    if mode == 0 and tile in (1, 2):
+        tile = 0  # (FP32/BF16 tiles)
+    if mode != 0 and tile >= 3:
+        pytest.skip("FP64 tile")
     rng = np.random.default_rng(M * 7 + N * 3 + K)
     A = rng.standard_normal((M, K))
     B = rng.standard_normal((K, N))
@@ -235,3 +241,30 @@ def test_cholqr_rank_revealing(hooks, n, k, rank):
     U, _, _ = np.linalg.svd(X, full_matrices=False)
     U = U[:, :rank]
     assert np.abs(Qn @ Qn.T - U @ U.T).max() < 1e-10
+
+
+@pytest.mark.parametrize("q", [1, 7, 64, 130])
+def test_jacobi_against_lapack(hooks, q):
+    """One-sided Jacobi SVD of a row-graded matrix (rows scaled over ten
+    decades, the shape of the canonical forms' R factors) against LAPACK's
+    preconditioned Jacobi SVD (dgejsv, relatively accurate for such
+    matrices): singular values to 1e-12 relative, left singular vectors to
+    1e-12 over the relative gap to the neighbouring values."""
+    import scipy.linalg.lapack as lapack
+    from tests.gpu_util import dev, ptr
+    rng = np.random.default_rng(q)
+    W = np.logspace(0, -10, q)[:, None] * rng.standard_normal((q, q))
+    sva, U, _, work, _, info = lapack.dgejsv(W, joba=2, jobu=0, jobv=0, jobr=1, jobt=0, jobp=0)
+    assert info == 0
+    S = sva * (work[0] / work[1])
+    Wd = dev(W)
+    Ud = torch.zeros((q, q), dtype=torch.float64, device="cuda:0")
+    Sd = torch.zeros(q, dtype=torch.float64, device="cuda:0")
+    _lib.check(hooks.lib.mpo_test_jacobi(ptr(Wd), q, ptr(Ud), ptr(Sd), *hooks.args()))
+    Ug, Sg = Ud.cpu().numpy(), Sd.cpu().numpy()
+    assert np.max(np.abs(Sg - S) / S) < 1e-12
+    rel = np.abs(np.diff(S)) / S[1:] if q > 1 else np.zeros(0)
+    gap = np.minimum(np.r_[rel, np.inf], np.r_[np.inf, rel]) if q > 1 else np.ones(1)
+    sg = np.sign(np.sum(Ug * U[:, :q], axis=0))
+    dist = np.linalg.norm(Ug * sg[None, :] - U[:, :q], axis=0)
+    assert np.all(dist <= 1e-12 / np.minimum(gap, 1.0)), (dist.max(), gap.min())

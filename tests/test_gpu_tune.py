@@ -19,9 +19,12 @@ def test_autotune_table_and_fit(tmp_path, precision, schedule):
                      reps=2)
     assert table
     for e in table:
-        assert e["tile"] in (0, 1, 2) and e["splits"] >= 1 and e["us"] > 0
-        if e["mode"] == 0:
-            assert e["tile"] == 0
+        assert e["splits"] >= 1 and e["us"] > 0
+        if e["mode"] == 0:  # FP64 tiles: 64x64, 32x32, 32x32 deep slabs, 16x16 with K over the waves
+            assert e["tile"] in (0, 3, 4, 5)
+            assert e["tile"] != 5 or e["splits"] == 1
+        else:
+            assert e["tile"] in (0, 1, 2)
     path = str(tmp_path / "tune.json")
     tune.save(table, path)
     ctx = FitContext([(A, B)], 16, precision=precision, schedule=schedule, sketch_p=4, seed=1,

@@ -53,7 +53,7 @@ def test_library_validates_table():
     good = tune.to_ctypes([ENTRY])
     o.tune, o.n_tune = good, 1
     assert _query(o) == 0
-    bad = tune.to_ctypes([dict(ENTRY, tile=3)])
+    bad = tune.to_ctypes([dict(ENTRY, tile=6)])
     o.tune = bad
     assert _query(o) == 1
     o2 = _opts()
