@@ -261,6 +261,33 @@ mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_pair* ab, cons
                         double* const* gA, double* const* gB, double* loss, int32_t recompute_env,
                         void* workspace, size_t ws_bytes);
 
+/* Randomized bond projection of one MPO (Sec. 3.2, Fig. random_update and
+   random_env, Table 1): every inner bond l (1 .. L-1) with k < chi_l is cut
+   to k by the projector Q_l Q_l^T, Q_l (chi_l x k) an orthonormal basis of
+   X^T Omega (the Gaussian range finder of Sec. 3.1 on the row space of core
+   l-1, X = that core unfolded as (chi_{l-1} d^2) x chi_l; Householder QR
+   with diag(R) >= 0); Omega is the Philox4x64-10 stream of the update's
+   sketch (seed, element counter, bond = l, stream, pair), elements in
+   row-major (chi_{l-1} d^2) x k order.  `out` receives the projected cores
+   Q_{l-1}^T A_l Q_l, so with every bond projected the fit of the projected
+   pair carries out the randomized contractions of Sec. 3.2 (environments
+   O(chi^3 k d^3), two-site contraction O(chi^3 k d^4)).  Bonds with
+   k >= chi_l are kept.  The projection pays only when the cores' spectra
+   across their bonds decay (the caveat of Sec. 3.2): pass the cores as
+   given, not orthogonalized.
+   in: FP64 device cores; out: caller-allocated FP64 device cores with
+   out->chi[l] = min(k, in->chi[l]) (chi[0] = chi[L] = 1), not overlapping
+   `in`; stream: any value >= 0 not used by the fit's sweeps
+   (MPO_PROJ_STREAM_A / _B below are the conventional ones for A and B);
+   workspace 256-byte aligned, of mpo_bond_project_bytes bytes.
+   Synchronizes `hip_stream`.  Errors: INVALID_ARG (null pointers, k < 1,
+   negative stream or pair), SHAPE (L < 2, bond dims, output dims),
+   UNSUPPORTED (a bond above 4096), WORKSPACE. */
+enum { MPO_PROJ_STREAM_A = 1 << 30, MPO_PROJ_STREAM_B = (1 << 30) + 1 };
+mpo_status mpo_bond_project_bytes(const mpo_tt* in, int32_t k, size_t* bytes);
+mpo_status mpo_bond_project(const mpo_tt* in, int32_t k, uint64_t seed, int32_t pair, int32_t stream,
+                            const mpo_tt* out, void* workspace, size_t ws_bytes, void* hip_stream);
+
 /* Fit error ||A B - C||_F / ||A B||_F (Sec. 2.3, Eq. fit_min) in FP64 on
    the device, for FP64 device cores A = pair->A, B = pair->B and C on one
    set of L sites with one d.

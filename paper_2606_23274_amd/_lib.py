@@ -12,6 +12,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "SHAPE", 3: "WORKSPACE", 4: "DEVICE", 5:
           6: "UNSUPPORTED"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 SCHEDULE = {"serial": 0, "even_odd": 1}
+PROJ_STREAM = {"A": 1 << 30, "B": (1 << 30) + 1}
 
 
 class MpoTT(C.Structure):
@@ -48,7 +49,8 @@ EXPORTS = [
     "mpo_fit_export_c", "mpo_fit_sweeps_done", "mpo_fit_norm_factor", "mpo_fit_truncations",
     "mpo_fit_grad_workspace_bytes", "mpo_fit_grad", "mpo_contract_check_bytes",
     "mpo_contract_exact_check", "mpo_contract_exact_check_static", "mpo_fit_singular_values",
-    "mpo_fit_updates", "mpo_fit_position", "mpo_fit_export_psi",
+    "mpo_fit_updates", "mpo_fit_position", "mpo_fit_export_psi", "mpo_bond_project_bytes",
+    "mpo_bond_project",
     "mpo_fit_last_sweep_ms", "mpo_fit_profile", "mpo_gemm_autotune", "mpo_fit_destroy",
     "mpo_last_error",
 ]
@@ -89,6 +91,9 @@ def load() -> C.CDLL:
                                              P(C.c_int32), C.c_void_p, C.c_size_t, C.c_void_p]
     lib.mpo_contract_exact_check_static.argtypes = [P(MpoPair), P(MpoTT), P(C.c_double),
                                                     P(C.c_double), P(C.c_int32), C.c_void_p]
+    lib.mpo_bond_project_bytes.argtypes = [P(MpoTT), C.c_int32, P(C.c_size_t)]
+    lib.mpo_bond_project.argtypes = [P(MpoTT), C.c_int32, C.c_uint64, C.c_int32, C.c_int32, P(MpoTT),
+                                     C.c_void_p, C.c_size_t, C.c_void_p]
     lib.mpo_fit_last_sweep_ms.argtypes = [C.c_void_p, P(C.c_double)]
     lib.mpo_fit_profile.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_char_p),
                                     P(C.c_double), P(C.c_int32), P(C.c_int32)]

@@ -319,6 +319,32 @@ class FitContract(torch.autograd.Function):
         return (None, None, *[g * t for t in ctx.saved_tensors])
 
 
+def project_bonds(cores, k, seed=0, pair=0, which="A", device="cuda:0", numpy=True):
+    """Randomized bond projection of one MPO on the GPU (mpo_bond_project,
+    Sec. 3.2): every inner bond l with k < chi_l becomes min(k, chi_l) by
+    Q_{l-1}^T A_l Q_l, Q_l from the Gaussian range finder on core l-1's
+    right bond.  `which` picks the conventional Philox stream of A or B.
+    Returns numpy arrays (or device tensors with numpy=False)."""
+    lib = _lib.load()
+    dev = torch.device(device)
+    tin = _TT(_dev_cores(cores, dev))
+    L = len(cores)
+    dims = [1] + [min(int(k), int(tin.chi[l])) for l in range(1, L)] + [1]
+    d = tin.d
+    outs = [torch.empty((dims[i], d, d, dims[i + 1]), dtype=torch.float64, device=dev) for i in range(L)]
+    tout = _TT(outs)
+    nbytes = C.c_size_t()
+    _lib.check(lib.mpo_bond_project_bytes(C.byref(tin.tt), int(k), C.byref(nbytes)))
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev)
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        ws_ptr = (ws.data_ptr() + 255) & ~255
+        _lib.check(lib.mpo_bond_project(C.byref(tin.tt), int(k), int(seed), int(pair),
+                                        int(_lib.PROJ_STREAM[which]), C.byref(tout.tt), C.c_void_p(ws_ptr),
+                                        nbytes.value, C.c_void_p(stream.cuda_stream)))
+    return [o.cpu().numpy() for o in outs] if numpy else outs
+
+
 def fit_error(A, B, C, device="cuda:0", with_method=False, static=False):
     """||A B - C||_F / ||A B||_F and ||A B||_F^2 in FP64 on the GPU
     (mpo_contract_exact_check): Householder-QR sweeps of the naive product

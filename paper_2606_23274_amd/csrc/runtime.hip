@@ -2698,6 +2698,125 @@ void run_segment(mpo_fit_ctx* ctx, int start, int count) {
 }
 }  // namespace
 
+namespace {
+// ------------------------------------------------------------------ bond projection
+// Randomized projection of every inner bond of one MPO (Sec. 3.2): Q_l from
+// the Gaussian range finder on the row space of core l-1's right unfolding
+// X (Y = X^T Omega, Householder QR with diag(R) >= 0), projected cores
+// Q_{l-1}^T A_l Q_l.  A bond with k >= chi_l is kept (Q_l = I, no launch).
+struct ProjLayout {
+  std::vector<int> k;                       // projected bond dims (k_0 = k_L = 1)
+  std::vector<double*> om, y, q, R, tau, t; // per bond l (om..tau) and per site (t)
+};
+
+void validate_proj(const mpo_tt& in, int32_t k) {
+  if (in.L < 2 || in.d < 1) throw Error{MPO_ERR_SHAPE, "bond projection: L >= 2 and d >= 1"};
+  validate_tt(in, in.L, in.d);
+  if (k < 1) throw Error{MPO_ERR_INVALID_ARG, "bond projection: k >= 1"};
+  for (int l = 1; l < in.L; ++l)
+    if (in.chi[l] > 4096) throw Error{MPO_ERR_UNSUPPORTED, "bond projection: bond above 4096"};
+}
+
+ProjLayout carve_proj(Carver& cv, const mpo_tt& in, int k) {
+  const int L = in.L, dd = in.d * in.d;
+  ProjLayout P;
+  P.k.assign(L + 1, 1);
+  P.om.assign(L + 1, nullptr); P.y = P.om; P.q = P.om; P.R = P.om; P.tau = P.om;
+  P.t.assign(L, nullptr);
+  for (int l = 1; l < L; ++l) P.k[l] = std::min(k, in.chi[l]);
+  for (int l = 1; l < L; ++l) {
+    const int chi = in.chi[l], kl = P.k[l];
+    if (kl >= chi) continue;
+    const long long m = (long long)in.chi[l - 1] * dd;
+    P.om[l] = cv.take<double>((size_t)m * kl);
+    P.y[l] = cv.take<double>((size_t)chi * kl);
+    P.q[l] = cv.take<double>((size_t)chi * kl);
+    P.R[l] = cv.take<double>((size_t)kl * kl);
+    P.tau[l] = cv.take<double>((size_t)kl);
+  }
+  for (int i = 0; i < L; ++i)
+    if (i > 0 && P.k[i] < in.chi[i]) P.t[i] = cv.take<double>((size_t)P.k[i] * dd * in.chi[i + 1]);
+  return P;
+}
+
+size_t proj_bytes(const mpo_tt& in, int k) {
+  Ctx X;
+  Carver cv;
+  carve_aux(X, cv, true);
+  carve_proj(cv, in, k);
+  return cv.off + 256;
+}
+
+void proj_run(const mpo_tt& in, int32_t k, uint64_t seed, int32_t pair, int32_t stream, const mpo_tt& out,
+              char* ws, size_t ws_bytes, hipStream_t hs) {
+  const int L = in.L, dd = in.d * in.d;
+  if (proj_bytes(in, k) > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "workspace too small"};
+  Ctx X;
+  X.stream = hs;
+  Carver cv;
+  cv.base = ws;
+  carve_aux(X, cv, true);
+  ProjLayout Pl = carve_proj(cv, in, k);
+  if (out.L != L || out.d != in.d || !out.chi || !out.cores) throw Error{MPO_ERR_SHAPE, "output train: L, d"};
+  for (int l = 0; l <= L; ++l)
+    if (out.chi[l] != Pl.k[l]) throw Error{MPO_ERR_SHAPE, "output bond dims must be min(k, chi_l)"};
+  for (int i = 0; i < L; ++i)
+    if (!out.cores[i]) throw Error{MPO_ERR_INVALID_ARG, "null output core"};
+  Program z;
+  add_fill(z, {FillDesc{X.flag, 4, 0, 0, 0}, FillDesc{X.sb.counters, X.sb.ccap, 0, 0, 0}});
+  upload(X, z);
+  run_program(z, X.stream, nullptr);
+  Program P;
+  std::vector<OmegaDesc> om;
+  std::vector<GemmJob> yj, lj, rj;
+  std::vector<GeqrDesc> gq;
+  std::vector<OrgqrDesc> oq;
+  std::vector<PermDesc> cp;
+  long long maxom = 1;
+  for (int l = 1; l < L; ++l) {
+    const int chi = in.chi[l], kl = Pl.k[l];
+    if (kl >= chi) continue;
+    const int m = in.chi[l - 1] * dd;
+    OmegaDesc o{};
+    o.out = Pl.om[l]; o.m = m; o.k = kl; o.chi = m; o.dd = 1; o.bond = l; o.pair = pair;
+    o.stream_mul = 0; o.stream_add = stream; o.stream_base = X.sweep_dev; o.seed = seed;
+    om.push_back(o);
+    maxom = std::max(maxom, (long long)m * kl);
+    // Y = X^T Omega, X = core l-1 as (chi_{l-1} d^2) x chi_l
+    yj.push_back(GemmJob{chi, kl, m, op64(in.cores[l - 1], false, chi), op64(Pl.om[l], false, kl),
+                         out64(Pl.y[l], kl)});
+    gq.push_back(GeqrDesc{Pl.y[l], chi, kl, kl, Pl.R[l], kl, Pl.tau[l]});
+    oq.push_back(OrgqrDesc{Pl.y[l], chi, kl, kl, Pl.tau[l], Pl.q[l], kl, Pl.R[l], kl});
+  }
+  for (int i = 0; i < L; ++i) {
+    const int cl = in.chi[i], cr = in.chi[i + 1], kl = Pl.k[i], kr = Pl.k[i + 1];
+    const bool left = i > 0 && kl < cl, right = i + 1 < L && kr < cr;
+    const double* src = in.cores[i];
+    if (left) {  // Q_i^T core_i: (k_i) x (d^2 chi_{i+1})
+      lj.push_back(GemmJob{kl, dd * cr, cl, op64(Pl.q[i], false, kl), op64(src, false, dd * cr),
+                           out64(Pl.t[i], dd * cr)});
+      src = Pl.t[i];
+    }
+    double* dst = const_cast<double*>(out.cores[i]);
+    if (right)  // (.) Q_{i+1}: (k_i d^2) x k_{i+1}
+      rj.push_back(GemmJob{kl * dd, kr, cr, op64(src, true, cr), op64(Pl.q[i + 1], false, kr), out64(dst, kr)});
+    else
+      cp.push_back(perm4(src, 0, dst, 0, {1, 1, kl * dd, cr}, {0, 0, cr, 1}, {0, 0, cr, 1}));
+  }
+  add_simple(P, LK::Omega, om, maxom, "project");
+  add_gemm(P, X.sb, Mode::F64, yj, "project", 0);
+  add_simple(P, LK::Geqr, gq, 0, "project");
+  add_simple(P, LK::Orgqr, oq, 0, "project");
+  add_gemm(P, X.sb, Mode::F64, lj, "project", 0);
+  add_gemm(P, X.sb, Mode::F64, rj, "project", 0);
+  add_perm(P, cp, "copy");
+  upload(X, P);
+  run_program(P, X.stream, nullptr);
+  HIP_OK(hipStreamSynchronize(X.stream));
+  check_flags(X);
+}
+}  // namespace
+
 extern "C" {
 
 const char* mpo_last_error(void) { return g_last_error.c_str(); }
@@ -3075,6 +3194,26 @@ mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_pair* ab, cons
     HIP_OK(hipStreamSynchronize(X.stream));
     X.arena_used = arena_mark;
     check_flags(X);
+  });
+}
+
+mpo_status mpo_bond_project_bytes(const mpo_tt* in, int32_t k, size_t* bytes) {
+  return guarded([&] {
+    if (!in || !bytes) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    validate_proj(*in, k);
+    *bytes = proj_bytes(*in, k);
+  });
+}
+
+mpo_status mpo_bond_project(const mpo_tt* in, int32_t k, uint64_t seed, int32_t pair, int32_t stream,
+                            const mpo_tt* out, void* workspace, size_t ws_bytes, void* hip_stream) {
+  return guarded([&] {
+    if (!in || !out || !workspace) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) throw Error{MPO_ERR_WORKSPACE, "workspace not 256-byte aligned"};
+    if (stream < 0 || pair < 0) throw Error{MPO_ERR_INVALID_ARG, "stream and pair must be >= 0"};
+    validate_proj(*in, k);
+    proj_run(*in, k, seed, pair, stream, *out, static_cast<char*>(workspace), ws_bytes,
+             static_cast<hipStream_t>(hip_stream));
   });
 }
 

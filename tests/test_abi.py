@@ -184,3 +184,28 @@ def test_initial_guess_validation():
     big = _Pair(chi_a=600)
     opts.c_init = (lib_mod.MpoTT * 1)(big.pair.A)
     assert _query([p], opts)[0] == 6
+
+
+def test_bond_project_queries_and_errors():
+    """mpo_bond_project's host-side validation (no device access): the
+    workspace grows with the bonds that are cut, k < 1, L < 2, null
+    pointers and an output of the wrong bond dims are rejected before any
+    launch."""
+    lib = _lib()
+    p = _Pair(L=6, chi_a=16)
+    n4, n8, n64 = C.c_size_t(0), C.c_size_t(0), C.c_size_t(0)
+    assert lib.mpo_bond_project_bytes(C.byref(p.pair.A), 4, C.byref(n4)) == 0
+    assert lib.mpo_bond_project_bytes(C.byref(p.pair.A), 8, C.byref(n8)) == 0
+    assert lib.mpo_bond_project_bytes(C.byref(p.pair.A), 64, C.byref(n64)) == 0
+    assert n64.value < n4.value < n8.value
+    assert lib.mpo_bond_project_bytes(C.byref(p.pair.A), 0, C.byref(n4)) == 1
+    assert lib.mpo_bond_project_bytes(None, 4, C.byref(n4)) == 1
+    one = _Pair(L=1)
+    assert lib.mpo_bond_project_bytes(C.byref(one.pair.A), 4, C.byref(n4)) == 2
+    ws = C.c_void_p(0x100000)
+    assert lib.mpo_bond_project(C.byref(p.pair.A), 4, 0, 0, 1 << 30, None, ws, n4.value, None) == 1
+    wrong = _Pair(L=6, chi_a=16)  # output dims must be min(k, chi) = 4
+    assert lib.mpo_bond_project(C.byref(p.pair.A), 4, 0, 0, 1 << 30, C.byref(wrong.pair.A), ws,
+                                1 << 40, None) == 2
+    assert lib.mpo_bond_project(C.byref(p.pair.A), 4, 0, 0, -1, C.byref(wrong.pair.A), ws,
+                                1 << 40, None) == 1
