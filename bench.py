@@ -11,7 +11,9 @@ Beside it (unless --quick): the split-BF16, pure-BF16 and FP64 sweeps and the
 plain (unsketched) FP64 sweep; the fit error per sweep of every precision and
 of the FP64 oracle, and the distance to the oracle; the batched even/odd
 schedule at L=64, chi=128, chi_C=256 and over 16 pairs of uneven chi; the
-gradient at frozen bases at L=30, chi=64; the oracle timed on the host.
+gradient at frozen bases at L=30, chi=64; the randomized bond projection of
+Sec. 3.2 (every A and B bond cut to k = O(chi^{1/2}), speed and fit error
+against the exact product); the oracle timed on the host.
 
 Prints one JSON line.
 """
@@ -288,6 +290,52 @@ def batched_section(steps):
     return res
 
 
+def randomized_section(steps):
+    """Sec. 3.2: every A and B bond cut to k = O(chi^{1/2}) by a randomized
+    projector (mpo_bond_project), then the fit of the projected pair; the
+    fit error of its C against the exact product A B, beside the
+    unprojected fit's, and the paper's "randomized sweeps first, then exact
+    sweeps" (the projected fit's C seeds the fit of A B)."""
+    import torch
+    from paper_2606_23274_amd.api import FitContext, fit_error, project_bonds
+    from synth import make_pair
+    w = WORKLOAD
+    res = {}
+    for name, (L, chi, chi_c, k, sched) in {
+            "serial_L40_chi64": (40, 64, 128, 16, "serial"),
+            "even_odd_L64_chi128": (64, 128, 256, 24, "even_odd")}.items():
+        A, B = make_pair(L, 2, chi, seed=0, decay=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        At = project_bonds(A, k, seed=0, which="A", numpy=False)
+        Bt = project_bonds(B, k, seed=0, which="B", numpy=False)
+        torch.cuda.synchronize()
+        proj_s = time.perf_counter() - t0
+        At = [t.cpu().numpy() for t in At]
+        Bt = [t.cpu().numpy() for t in Bt]
+        rec = {"k": k, "schedule": sched, "projection_seconds": round(proj_s, 4)}
+        for tag, (X, Y) in (("projected", (At, Bt)), ("exact", (A, B))):
+            wl, _, _, _ = run_gpu(X, Y, "fp32", w["p"], steps, 2, schedule=sched, chi_c=chi_c)
+            rec[f"{tag}_sweeps_per_s"] = round(steps / wl, 3)
+        rec["speedup"] = round(rec["projected_sweeps_per_s"] / rec["exact_sweeps_per_s"], 3)
+        if sched == "serial":
+            eps = {}
+            for tag, (X, Y) in (("projected", (At, Bt)), ("exact", (A, B))):
+                ctx = FitContext([(X, Y)], chi_c, precision="fp32", sketch_p=w["p"], seed=0)
+                ctx.sweep(2)
+                C = ctx.export_numpy(0)
+                ctx.close()
+                eps[tag] = fit_error(A, B, C)[0]
+                if tag == "projected":
+                    ctx = FitContext([(A, B)], chi_c, precision="fp32", sketch_p=w["p"], seed=0, c_init=[C])
+                    ctx.sweep(1)
+                    eps["projected_2_then_exact_1"] = fit_error(A, B, ctx.export_numpy(0))[0]
+                    ctx.close()
+            rec["fit_error_vs_AB_after_2_sweeps"] = eps
+        res[name] = rec
+    return res
+
+
 def gradient_section():
     import torch
     from paper_2606_23274_amd.api import FitContext
@@ -319,7 +367,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=6, help="sweeps of the accuracy comparison")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline, profile and roofline only")
-    ap.add_argument("--section", choices=["batched", "gradient"],
+    ap.add_argument("--section", choices=["batched", "gradient", "randomized"],
                     help="run only that section (for profiling) and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 256 MiB (4 times): the reference for "
@@ -335,7 +383,9 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": src.numel() * 4, "copies": 4}), flush=True)
         return
     if args.section:
-        out = batched_section(max(2, args.steps // 2)) if args.section == "batched" else gradient_section()
+        out = (batched_section(max(2, args.steps // 2)) if args.section == "batched" else
+               randomized_section(max(2, args.steps // 2)) if args.section == "randomized" else
+               gradient_section())
         print(json.dumps(out), flush=True)
         return
     if args.gpus != 1:
@@ -381,7 +431,7 @@ def main():
             roof["frac_of_one_cu"] = round(ach / (peak / 256), 5)
         roof["traffic"] = measured_traffic(roof["kernel"])
 
-    others, batched, grad, acc, cpu = {}, {}, {}, {}, None
+    others, batched, grad, acc, cpu, randomized = {}, {}, {}, {}, None, {}
     if not args.quick:
         wall_b, _, _, _ = run_gpu(A, B, "fp32", w["p"], args.steps, args.warmup)
         others["fp32_built_in_gemm_choice"] = {"sweeps_per_s": round(args.steps / wall_b, 3)}
@@ -398,6 +448,8 @@ def main():
         print("batched done", file=sys.stderr, flush=True)
         grad = gradient_section()
         print("gradient done", file=sys.stderr, flush=True)
+        randomized = randomized_section(max(2, args.steps // 2))
+        print("randomized done", file=sys.stderr, flush=True)
         Cs = []
         if not args.no_cpu:
             Cs, t_end, cores = oracle_run(A, B, args.sweeps, budget_s=30.0)
@@ -461,7 +513,7 @@ def main():
     }
     if not args.quick:
         line.update({"other_precisions": others, "accuracy": acc, "batched_schedule": batched,
-                     "gradient": grad})
+                     "gradient": grad, "randomized_bonds": randomized})
         if cpu is not None:
             line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
