@@ -261,6 +261,31 @@ mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_pair* ab, cons
                         double* const* gA, double* const* gB, double* loss, int32_t recompute_env,
                         void* workspace, size_t ws_bytes);
 
+/* Zip-up contraction C ~ A B (Alg. 2, Sec. 2.2), the fit's initial guess
+   (pass C as mpo_fit_opts.c_init): copies of A and B are brought to
+   right-canonical form (Householder RQ sweeps), then one left-to-right
+   pass contracts the residual R_{l-1} with A_l and B_l into R''_l, whose
+   matrix M_l ((r_{l-1} d^2) x (chi_A,l chi_B,l), bond dims of the
+   right-canonical A and B) is factorized by the truncated SVD of the
+   two-site update (rank min(chi_max, rows, chi_A chi_B); the randomized
+   range finder of Sec. 3.1 with k = chi_max + sketch_p when that is
+   narrower than M_l, else the Gram eigenproblem of its smaller side;
+   singular values <= 1e-6 sigma_1 dropped, sign rule on U): C_l = U,
+   R_l = U^T M_l; the last core is M_L.  The sketch draws Omega from the
+   Philox stream (seed, element counter, bond = l, stream 2^30 + 2, pair 0).
+   mpo_zipup_bytes: workspace bytes and, when `dims` is non-null, C's
+   bond dims (L+1 entries) into it; host only.
+   pair: FP64 device cores of A and B (pair->chi_max ignored); C: caller-
+   allocated FP64 device cores with C->chi = those dims; workspace 256-byte
+   aligned.  Synchronizes `stream`.  Errors: INVALID_ARG (null pointers,
+   chi_max < 1), SHAPE (L < 2, A and B not matching, C's dims),
+   UNSUPPORTED (chi_max + sketch_p > 512, a factorization beyond the eigen
+   kernels' sizes), WORKSPACE, NUMERIC (device flags). */
+mpo_status mpo_zipup_bytes(const mpo_pair* pair, int32_t chi_max, int32_t sketch_p, int32_t* dims,
+                           size_t* bytes);
+mpo_status mpo_zipup(const mpo_pair* pair, int32_t chi_max, int32_t sketch_p, uint64_t seed, const mpo_tt* C,
+                     void* workspace, size_t ws_bytes, void* stream);
+
 /* Randomized bond projection of one MPO (Sec. 3.2, Fig. random_update and
    random_env, Table 1): every inner bond l (1 .. L-1) with k < chi_l is cut
    to k by the projector Q_l Q_l^T, Q_l (chi_l x k) an orthonormal basis of

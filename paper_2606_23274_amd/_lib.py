@@ -50,7 +50,7 @@ EXPORTS = [
     "mpo_fit_grad_workspace_bytes", "mpo_fit_grad", "mpo_contract_check_bytes",
     "mpo_contract_exact_check", "mpo_contract_exact_check_static", "mpo_fit_singular_values",
     "mpo_fit_updates", "mpo_fit_position", "mpo_fit_export_psi", "mpo_bond_project_bytes",
-    "mpo_bond_project",
+    "mpo_bond_project", "mpo_zipup_bytes", "mpo_zipup",
     "mpo_fit_last_sweep_ms", "mpo_fit_profile", "mpo_gemm_autotune", "mpo_fit_destroy",
     "mpo_last_error",
 ]
@@ -94,6 +94,9 @@ def load() -> C.CDLL:
     lib.mpo_bond_project_bytes.argtypes = [P(MpoTT), C.c_int32, P(C.c_size_t)]
     lib.mpo_bond_project.argtypes = [P(MpoTT), C.c_int32, C.c_uint64, C.c_int32, C.c_int32, P(MpoTT),
                                      C.c_void_p, C.c_size_t, C.c_void_p]
+    lib.mpo_zipup_bytes.argtypes = [P(MpoPair), C.c_int32, C.c_int32, P(C.c_int32), P(C.c_size_t)]
+    lib.mpo_zipup.argtypes = [P(MpoPair), C.c_int32, C.c_int32, C.c_uint64, P(MpoTT), C.c_void_p, C.c_size_t,
+                              C.c_void_p]
     lib.mpo_fit_last_sweep_ms.argtypes = [C.c_void_p, P(C.c_double)]
     lib.mpo_fit_profile.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_char_p),
                                     P(C.c_double), P(C.c_int32), P(C.c_int32)]

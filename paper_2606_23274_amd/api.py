@@ -319,6 +319,30 @@ class FitContract(torch.autograd.Function):
         return (None, None, *[g * t for t in ctx.saved_tensors])
 
 
+def zipup(A, B, chi_max, sketch_p=-1, seed=0, device="cuda:0", numpy=True):
+    """Zip-up contraction C ~ A B on the GPU (mpo_zipup, Alg. 2): the fit's
+    initial guess (FitContext(..., c_init=[zipup(A, B, chi)])).  Returns
+    numpy arrays (or device tensors with numpy=False)."""
+    lib = _lib.load()
+    dev = torch.device(device)
+    ta, tb = _TT(_dev_cores(A, dev)), _TT(_dev_cores(B, dev))
+    pair = _lib.MpoPair(ta.tt, tb.tt, 0)
+    L = len(A)
+    dims = (C.c_int32 * (L + 1))()
+    nbytes = C.c_size_t()
+    _lib.check(lib.mpo_zipup_bytes(C.byref(pair), int(chi_max), int(sketch_p), dims, C.byref(nbytes)))
+    d = ta.d
+    outs = [torch.empty((dims[i], d, d, dims[i + 1]), dtype=torch.float64, device=dev) for i in range(L)]
+    tc = _TT(outs)
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev)
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        ws_ptr = (ws.data_ptr() + 255) & ~255
+        _lib.check(lib.mpo_zipup(C.byref(pair), int(chi_max), int(sketch_p), int(seed), C.byref(tc.tt),
+                                 C.c_void_p(ws_ptr), nbytes.value, C.c_void_p(stream.cuda_stream)))
+    return [o.cpu().numpy() for o in outs] if numpy else outs
+
+
 def project_bonds(cores, k, seed=0, pair=0, which="A", device="cuda:0", numpy=True):
     """Randomized bond projection of one MPO on the GPU (mpo_bond_project,
     Sec. 3.2): every inner bond l with k < chi_l becomes min(k, chi_l) by

@@ -2699,6 +2699,223 @@ void run_segment(mpo_fit_ctx* ctx, int start, int count) {
 }  // namespace
 
 namespace {
+// ------------------------------------------------------------------ zip-up
+// Zip-up contraction (Alg. 2, Sec. 2.2) in FP64: copies of A and B brought
+// to right-canonical form (RQ sweeps by Householder QR, as the fit's
+// initialization), then one left-to-right pass: R''_l = R_{l-1} A_l B_l by
+// two batched GEMMs (over the A bond, then over the B bond and the shared
+// physical leg), M_l = R''_l as (r_{l-1} d^2) x (chi_A chi_B) factorized by
+// the update's truncated SVD (the randomized range finder when the sketch
+// is narrower than M_l, the Gram eigenproblem, drop and sign rules),
+// C_l = U, R_l = U^T M_l; the last core is M_L.  One launch program, run
+// eagerly.
+constexpr int kZipStream = (1 << 30) + 2;
+
+struct ZipShape {
+  int L, d, dd;
+  std::vector<int> ca, cb;  // right-canonical bond dims of A and B
+  std::vector<int> r;       // C's bond dims
+  long long nmax = 1, kmax = 1, Kmax = 1, rmax = 1, core_a = 1, core_b = 1, t1 = 1, hmax = 1;
+};
+
+ZipShape zip_shape(const mpo_pair& pair, int chi_max, int sketch_p) {
+  ZipShape z;
+  z.L = pair.A.L; z.d = pair.A.d; z.dd = z.d * z.d;
+  const int L = z.L, dd = z.dd;
+  z.ca.assign(L + 1, 1); z.cb.assign(L + 1, 1); z.r.assign(L + 1, 1);
+  for (int j = L - 1; j >= 1; --j) {  // RQ sweeps: chi'_j = min(chi_j, d^2 chi'_{j+1})
+    z.ca[j] = std::min(pair.A.chi[j], dd * z.ca[j + 1]);
+    z.cb[j] = std::min(pair.B.chi[j], dd * z.cb[j + 1]);
+  }
+  for (int l = 0; l < L; ++l) {
+    z.core_a = std::max(z.core_a, (long long)pair.A.chi[l] * dd * pair.A.chi[l + 1]);
+    z.core_b = std::max(z.core_b, (long long)pair.B.chi[l] * dd * pair.B.chi[l + 1]);
+  }
+  for (int l = 0; l < L; ++l) {
+    const long long n = (long long)z.r[l] * dd, K = (long long)z.ca[l + 1] * z.cb[l + 1];
+    if (l + 1 < L) z.r[l + 1] = (int)std::min<long long>({(long long)chi_max, n, K});
+    const long long k = sketch_p >= 0 ? std::min<long long>({(long long)chi_max + sketch_p, n, K}) : std::min(n, K);
+    z.nmax = std::max(z.nmax, n);
+    z.Kmax = std::max(z.Kmax, K);
+    z.kmax = std::max(z.kmax, k);
+    z.rmax = std::max(z.rmax, (long long)z.r[l + 1]);
+    z.hmax = std::max(z.hmax, std::min(n, K));
+    z.t1 = std::max(z.t1, (long long)z.r[l] * z.cb[l] * dd * z.ca[l + 1]);
+  }
+  if (z.nmax > 4096 || z.hmax > 1700 || z.kmax > 512)
+    throw Error{MPO_ERR_UNSUPPORTED, "zip-up: a factorization beyond the eigen kernels' sizes"};
+  return z;
+}
+
+struct ZipBufs {
+  std::vector<double*> A, B;
+  double *Rres, *T1, *M, *omega, *Y, *Y2, *G, *R, *Bk, *H, *eigw, *evals, *Z, *S, *keep, *sign, *U2;
+};
+
+ZipBufs carve_zip(Ctx& X, Carver& cv, const ZipShape& z) {
+  ZipBufs b;
+  b.A.resize(z.L); b.B.resize(z.L);
+  for (int l = 0; l < z.L; ++l) {
+    b.A[l] = cv.take<double>((size_t)z.core_a);
+    b.B[l] = cv.take<double>((size_t)z.core_b);
+  }
+  const long long coremax = std::max(z.core_a, z.core_b);
+  const long long kq = std::max<long long>(
+      {*std::max_element(z.ca.begin(), z.ca.end()), *std::max_element(z.cb.begin(), z.cb.end()), 1});
+  X.iRt = cv.take<double>((size_t)kq * kq);
+  X.iTau = cv.take<double>((size_t)kq);
+  X.iTmp = cv.take<double>((size_t)coremax);
+  X.iXt = cv.take<double>((size_t)coremax);
+  b.Rres = cv.take<double>((size_t)z.rmax * z.Kmax);
+  b.T1 = cv.take<double>((size_t)z.t1);
+  b.M = cv.take<double>((size_t)z.nmax * z.Kmax);
+  b.omega = cv.take<double>((size_t)z.Kmax * z.kmax);
+  b.Y = cv.take<double>((size_t)z.nmax * std::max(z.kmax, z.hmax));
+  b.Y2 = cv.take<double>((size_t)z.nmax * std::max(z.kmax, z.hmax));
+  b.G = cv.take<double>((size_t)z.hmax * z.hmax);
+  b.R = cv.take<double>(2 * (size_t)z.hmax * z.hmax);
+  b.Bk = cv.take<double>((size_t)z.kmax * z.Kmax);
+  b.H = cv.take<double>((size_t)z.hmax * z.hmax);
+  b.eigw = cv.take<double>(eig_work_doubles((int)z.hmax, (int)z.rmax));
+  b.evals = cv.take<double>((size_t)z.hmax);
+  b.Z = cv.take<double>((size_t)z.hmax * z.rmax);
+  b.S = cv.take<double>((size_t)z.rmax);
+  b.keep = cv.take<double>((size_t)z.rmax);
+  b.sign = cv.take<double>((size_t)z.rmax);
+  b.U2 = cv.take<double>((size_t)z.nmax * z.rmax);
+  return b;
+}
+
+// RQ sweep of one train (cores in `c`, dims `dims` updated to the
+// right-canonical ones), as the fit's initialization does it.
+void rec_rq_train(Ctx& X, Program& P, std::vector<double*>& c, std::vector<int>& dims, int dd) {
+  const int L = (int)c.size();
+  for (int j = L - 1; j >= 1; --j) {
+    const int p = dims[j], q = dd * dims[j + 1], mp = dims[j - 1] * dd;
+    if (p <= q) {
+      add_perm(P, {perm4(c[j], 0, X.iXt, 0, {1, 1, p, q}, {0, 0, q, 1}, {0, 0, 1, p})}, "copy");
+      add_hhqr(X, P, X.iXt, q, p, X.iTmp);
+      add_perm(P, {perm4(X.iTmp, 0, c[j], 0, {1, 1, q, p}, {0, 0, p, 1}, {0, 0, 1, q})}, "copy");
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{mp, p, p, op64(c[j - 1], true, p), op64(X.iRt, true, p),
+                                            out64(X.iTmp, p)}}, "init", 0);
+      add_perm(P, {perm4(X.iTmp, 0, c[j - 1], 0, {1, 1, mp, p}, {0, 0, p, 1}, {0, 0, p, 1})}, "copy");
+    } else {
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{mp, q, p, op64(c[j - 1], true, p), op64(c[j], false, q),
+                                            out64(X.iTmp, q)}}, "init", 0);
+      add_perm(P, {perm4(X.iTmp, 0, c[j - 1], 0, {1, 1, mp, q}, {0, 0, q, 1}, {0, 0, q, 1})}, "copy");
+      add_fill(P, {FillDesc{c[j], 0, q, q, 1}});
+      dims[j] = q;
+    }
+  }
+}
+
+void zip_run(const mpo_pair& pair, int chi_max, int sketch_p, uint64_t seed, const mpo_tt& out, char* ws,
+             size_t ws_bytes, hipStream_t hs, size_t* bytes_only) {
+  const ZipShape z = zip_shape(pair, chi_max, sketch_p);
+  const int L = z.L, dd = z.dd, d = z.d;
+  Ctx X;
+  X.stream = hs;
+  Carver cv;
+  cv.base = ws;
+  carve_aux(X, cv, false);
+  ZipBufs b = carve_zip(X, cv, z);
+  if (bytes_only) {
+    *bytes_only = cv.off + 256;
+    return;
+  }
+  if (cv.off + 256 > ws_bytes) throw Error{MPO_ERR_WORKSPACE, "workspace too small"};
+  if (out.L != L || out.d != d || !out.chi || !out.cores) throw Error{MPO_ERR_SHAPE, "output train: L, d"};
+  for (int l = 0; l <= L; ++l)
+    if (out.chi[l] != z.r[l]) throw Error{MPO_ERR_SHAPE, "output bond dims: see mpo_zipup_bytes"};
+  for (int l = 0; l < L; ++l)
+    if (!out.cores[l]) throw Error{MPO_ERR_INVALID_ARG, "null output core"};
+  Program zp;
+  add_fill(zp, {FillDesc{X.flag, 4, 0, 0, 0}, FillDesc{X.sb.counters, X.sb.ccap, 0, 0, 0}});
+  upload(X, zp);
+  run_program(zp, X.stream, nullptr);
+  Program P;
+  std::vector<int> da(pair.A.chi, pair.A.chi + L + 1), db(pair.B.chi, pair.B.chi + L + 1);
+  for (int l = 0; l < L; ++l) {
+    add_perm(P, {perm4(pair.A.cores[l], 0, b.A[l], 0, {1, 1, da[l], dd * da[l + 1]},
+                       {0, 0, (long long)dd * da[l + 1], 1}, {0, 0, (long long)dd * da[l + 1], 1})}, "copy");
+    add_perm(P, {perm4(pair.B.cores[l], 0, b.B[l], 0, {1, 1, db[l], dd * db[l + 1]},
+                       {0, 0, (long long)dd * db[l + 1], 1}, {0, 0, (long long)dd * db[l + 1], 1})}, "copy");
+  }
+  rec_rq_train(X, P, b.A, da, dd);
+  rec_rq_train(X, P, b.B, db, dd);
+  add_fill(P, {FillDesc{b.Rres, 0, 1, 1, 1}});  // R_0 = [[[1]]]
+  for (int l = 0; l < L; ++l) {
+    const int c0 = z.r[l], a0 = da[l], a1 = da[l + 1], b0 = db[l], b1 = db[l + 1];
+    const int n = c0 * dd, K = a1 * b1;
+    // T1[c][s][b][t][a'] = sum_a R[c][a][b] A[a][s][t][a'] (batches c, s)
+    GemmJob t1{b0, d * a1, a0, op64(b.Rres, false, b0), op64(b.A[l], false, dd * a1), out64(b.T1, d * a1)};
+    t1.nb[0] = c0; t1.nb[1] = d;
+    t1.A.s[0] = (long long)a0 * b0; t1.A.s[1] = 0;
+    t1.B.s[0] = 0; t1.B.s[1] = (long long)d * a1;
+    t1.C.s[0] = (long long)d * b0 * d * a1; t1.C.s[1] = (long long)b0 * d * a1;
+    add_gemm(P, X.sb, Mode::F64, {t1}, "zip_ext", 0);
+    // M[c][s][u][a'][b'] = sum_{b,t} T1[c][s][(b t)][a'] B[(b t)][u][b'] (batches c, s, u)
+    double* M = (l == L - 1) ? const_cast<double*>(out.cores[l]) : b.M;
+    GemmJob t2{a1, b1, b0 * d, op64(b.T1, false, a1), op64(b.B[l], false, d * b1), out64(M, b1)};
+    t2.nb[0] = c0; t2.nb[1] = d; t2.nb[2] = d;
+    t2.A.s[0] = (long long)d * b0 * d * a1; t2.A.s[1] = (long long)b0 * d * a1; t2.A.s[2] = 0;
+    t2.B.s[0] = 0; t2.B.s[1] = 0; t2.B.s[2] = b1;
+    t2.C.s[0] = (long long)dd * a1 * b1; t2.C.s[1] = (long long)d * a1 * b1; t2.C.s[2] = (long long)a1 * b1;
+    add_gemm(P, X.sb, Mode::F64, {t2}, "zip_ext", 0);
+    if (l == L - 1) break;  // C_L = M_L
+    const int r = z.r[l + 1];
+    const bool sketch = sketch_p >= 0 && chi_max + sketch_p < std::min(n, K);
+    const int k = sketch ? chi_max + sketch_p : std::min(n, K);
+    double* U = const_cast<double*>(out.cores[l]);  // n x r
+    if (sketch) {
+      OmegaDesc o{};
+      o.out = b.omega; o.m = K; o.k = k; o.chi = K; o.dd = 1; o.bond = l + 1; o.pair = 0;
+      o.stream_mul = 0; o.stream_add = kZipStream; o.stream_base = X.sweep_dev; o.seed = seed;
+      add_simple(P, LK::Omega, std::vector<OmegaDesc>{o}, (long long)K * k, "omega");
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{n, k, K, op64(M, true, K), op64(b.omega, false, k), out64(b.Y, k)}},
+               "sketch", 0);
+      CholQRJob qj{b.Y, n, k, k, b.G, b.R, nullptr, b.Y2};
+      qj.eta = kRankEta;
+      add_cholqr(X, P, {qj}, 2, false, true);
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{k, K, n, op64(b.Y, false, k), op64(M, false, K), out64(b.Bk, K)}},
+               "project", 0);
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{k, k, K, op64(b.Bk, true, K), op64(b.Bk, true, K), out64(b.H, k)}},
+               "gram", 0);
+    } else if (n <= K) {
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{n, n, K, op64(M, true, K), op64(M, true, K), out64(b.H, n)}}, "gram", 0);
+    } else {  // M^T M (K x K): right vectors first
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{K, K, n, op64(M, false, K), op64(M, false, K), out64(b.H, K)}}, "gram", 0);
+    }
+    add_eig(P, X.sb, {EigDesc{b.H, k, k, r, b.evals, b.Z, r, b.eigw, X.flag}}, k <= kRegMax, "eig");
+    add_simple(P, LK::Sval, std::vector<SvalDesc>{SvalDesc{b.evals, b.S, r, 0, X.flag, b.keep, X.flag + 2}}, r,
+               "svals");
+    add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{b.Z, b.Z, k, r, r, r, nullptr, b.keep, 0, 2}},
+               (long long)k * r, "scale");
+    if (sketch) {  // U = Q Z
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{n, r, k, op64(b.Y, true, k), op64(b.Z, false, r), out64(U, r)}},
+               "assemble", 0);
+    } else if (n <= K) {
+      add_perm(P, {perm4(b.Z, 0, U, 0, {1, 1, n, r}, {0, 0, r, 1}, {0, 0, r, 1})}, "copy");
+    } else {  // U = M V / S
+      add_gemm(P, X.sb, Mode::F64, {GemmJob{n, r, K, op64(M, true, K), op64(b.Z, false, r), out64(U, r)}},
+               "assemble", 0);
+      add_simple(P, LK::Scale, std::vector<ScaleDesc>{ScaleDesc{U, U, n, r, r, r, nullptr, b.S, 0, 1}},
+                 (long long)n * r, "scale");
+    }
+    CholQRJob ou{U, n, r, r, b.G, b.R, nullptr, b.U2};
+    ou.keep = b.keep;
+    add_cholqr(X, P, {ou}, 1, true, true);
+    add_simple(P, LK::Sign, std::vector<SignDesc>{SignDesc{U, n, r, r, b.sign, nullptr}}, r, "sign");
+    // R_l = U^T M (r x K)
+    add_gemm(P, X.sb, Mode::F64, {GemmJob{r, K, n, op64(U, false, r), op64(M, false, K), out64(b.Rres, K)}},
+             "env_update", 0);
+  }
+  upload(X, P);
+  run_program(P, X.stream, nullptr);
+  HIP_OK(hipStreamSynchronize(X.stream));
+  check_flags(X);
+}
+
 // ------------------------------------------------------------------ bond projection
 // Randomized projection of every inner bond of one MPO (Sec. 3.2): Q_l from
 // the Gaussian range finder on the row space of core l-1's right unfolding
@@ -3194,6 +3411,35 @@ mpo_status mpo_fit_grad(mpo_fit_ctx* ctx, int32_t pair, const mpo_pair* ab, cons
     HIP_OK(hipStreamSynchronize(X.stream));
     X.arena_used = arena_mark;
     check_flags(X);
+  });
+}
+
+mpo_status mpo_zipup_bytes(const mpo_pair* pair, int32_t chi_max, int32_t sketch_p, int32_t* dims,
+                           size_t* bytes) {
+  return guarded([&] {
+    if (!pair || !bytes) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    if (chi_max < 1) throw Error{MPO_ERR_INVALID_ARG, "chi_max >= 1"};
+    if (chi_max + std::max(sketch_p, 0) > 512) throw Error{MPO_ERR_UNSUPPORTED, "chi_max + sketch_p above 512"};
+    validate_check(*pair, pair->A);
+    if (pair->A.L < 2) throw Error{MPO_ERR_SHAPE, "zip-up: L >= 2"};
+    const ZipShape z = zip_shape(*pair, chi_max, sketch_p);
+    if (dims)
+      for (int l = 0; l <= z.L; ++l) dims[l] = z.r[l];
+    zip_run(*pair, chi_max, sketch_p, 0, pair->A, nullptr, 0, nullptr, bytes);
+  });
+}
+
+mpo_status mpo_zipup(const mpo_pair* pair, int32_t chi_max, int32_t sketch_p, uint64_t seed, const mpo_tt* C,
+                     void* workspace, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    if (!pair || !C || !workspace) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) throw Error{MPO_ERR_WORKSPACE, "workspace not 256-byte aligned"};
+    if (chi_max < 1) throw Error{MPO_ERR_INVALID_ARG, "chi_max >= 1"};
+    if (chi_max + std::max(sketch_p, 0) > 512) throw Error{MPO_ERR_UNSUPPORTED, "chi_max + sketch_p above 512"};
+    validate_check(*pair, pair->A);
+    if (pair->A.L < 2) throw Error{MPO_ERR_SHAPE, "zip-up: L >= 2"};
+    zip_run(*pair, chi_max, sketch_p, seed, *C, static_cast<char*>(workspace), ws_bytes,
+            static_cast<hipStream_t>(stream), nullptr);
   });
 }
 

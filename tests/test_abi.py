@@ -209,3 +209,25 @@ def test_bond_project_queries_and_errors():
                                 1 << 40, None) == 2
     assert lib.mpo_bond_project(C.byref(p.pair.A), 4, 0, 0, -1, C.byref(wrong.pair.A), ws,
                                 1 << 40, None) == 1
+
+
+def test_zipup_dims_and_errors():
+    """mpo_zipup_bytes (host only): C's bond dims r_l = min(chi_max, r_{l-1}
+    d^2, chi_A chi_B of the right-canonical inputs) and the error codes."""
+    lib = _lib()
+    p = _Pair(L=6, chi_a=4, chi_b=3)
+    dims = (C.c_int32 * 7)()
+    n = C.c_size_t(0)
+    assert lib.mpo_zipup_bytes(C.byref(p.pair), 10, 4, dims, C.byref(n)) == 0
+    # right-canonical dims of A: [1, 4, 4, 4, 4, 4, 1] (4 <= d^2 * 4), of B: [1, 3, ..., 3, 1]
+    assert list(dims) == [1, 4, 10, 10, 10, 10, 1]
+    assert n.value > 0
+    assert lib.mpo_zipup_bytes(C.byref(p.pair), 0, 4, dims, C.byref(n)) == 1
+    assert lib.mpo_zipup_bytes(C.byref(p.pair), 600, 4, dims, C.byref(n)) == 6
+    assert lib.mpo_zipup_bytes(None, 10, 4, dims, C.byref(n)) == 1
+    bad = _Pair(L=6)
+    bad.pair.B.L = 5
+    assert lib.mpo_zipup_bytes(C.byref(bad.pair), 10, 4, dims, C.byref(n)) == 2
+    wrong = _Pair(L=6, chi_a=4)  # C's dims must be the zip-up's
+    assert lib.mpo_zipup(C.byref(p.pair), 10, 4, 0, C.byref(wrong.pair.A), C.c_void_p(0x100000), 1 << 40,
+                         None) == 2
