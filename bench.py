@@ -13,7 +13,8 @@ of the FP64 oracle, and the distance to the oracle; the batched even/odd
 schedule at L=64, chi=128, chi_C=256 and over 16 pairs of uneven chi; the
 gradient at frozen bases at L=30, chi=64; the randomized bond projection of
 Sec. 3.2 (every A and B bond cut to k = O(chi^{1/2}), speed and fit error
-against the exact product); the oracle timed on the host.
+against the exact product); the zip-up (Alg. 2) as the initial guess; the
+oracle timed on the host.
 
 Prints one JSON line.
 """
@@ -336,6 +337,33 @@ def randomized_section(steps):
     return res
 
 
+def zipup_section():
+    """Alg. 2 as Alg. 5's initial guess at the headline workload: the zip-up's
+    device time (randomized, k = chi_C + p), its fit error, and the fit error
+    after one and two FP32 sweeps from it and from the guess A."""
+    import torch
+    from paper_2606_23274_amd.api import FitContext, fit_error, zipup
+    from synth import make_pair
+    w = WORKLOAD
+    A, B = make_pair(w["L"], w["d"], w["chi"], seed=w["seed"], decay=True)
+    zipup(A, B, w["chi_c"], sketch_p=w["p"], seed=0)  # warm-up (module load, first launches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C0 = zipup(A, B, w["chi_c"], sketch_p=w["p"], seed=0)
+    torch.cuda.synchronize()
+    zip_s = time.perf_counter() - t0
+    res = {"zipup_seconds": round(zip_s, 4), "zipup_fit_error": fit_error(A, B, C0)[0]}
+    for tag, kw in (("from_zipup", {"c_init": [C0]}), ("from_A", {})):
+        ctx = FitContext([(A, B)], w["chi_c"], precision="fp32", sketch_p=w["p"], seed=w["seed"], **kw)
+        errs = []
+        for _ in range(2):
+            ctx.sweep(1)
+            errs.append(fit_error(A, B, ctx.export_numpy(0))[0])
+        ctx.close()
+        res[f"fit_error_{tag}_after_1_2_sweeps"] = errs
+    return res
+
+
 def gradient_section():
     import torch
     from paper_2606_23274_amd.api import FitContext
@@ -367,7 +395,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=6, help="sweeps of the accuracy comparison")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline, profile and roofline only")
-    ap.add_argument("--section", choices=["batched", "gradient", "randomized"],
+    ap.add_argument("--section", choices=["batched", "gradient", "randomized", "zipup"],
                     help="run only that section (for profiling) and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 256 MiB (4 times): the reference for "
@@ -385,7 +413,7 @@ def main():
     if args.section:
         out = (batched_section(max(2, args.steps // 2)) if args.section == "batched" else
                randomized_section(max(2, args.steps // 2)) if args.section == "randomized" else
-               gradient_section())
+               zipup_section() if args.section == "zipup" else gradient_section())
         print(json.dumps(out), flush=True)
         return
     if args.gpus != 1:
@@ -449,7 +477,8 @@ def main():
         grad = gradient_section()
         print("gradient done", file=sys.stderr, flush=True)
         randomized = randomized_section(max(2, args.steps // 2))
-        print("randomized done", file=sys.stderr, flush=True)
+        randomized["zipup_initial_guess"] = zipup_section()
+        print("randomized and zip-up done", file=sys.stderr, flush=True)
         Cs = []
         if not args.no_cpu:
             Cs, t_end, cores = oracle_run(A, B, args.sweeps, budget_s=30.0)
