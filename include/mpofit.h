@@ -307,7 +307,7 @@ mpo_status mpo_zipup(const mpo_pair* pair, int32_t chi_max, int32_t sketch_p, ui
    workspace 256-byte aligned, of mpo_bond_project_bytes bytes.
    Synchronizes `hip_stream`.  Errors: INVALID_ARG (null pointers, k < 1,
    negative stream or pair), SHAPE (L < 2, bond dims, output dims),
-   UNSUPPORTED (a bond above 4096), WORKSPACE. */
+   UNSUPPORTED (a bond above 4096, k above 1024), WORKSPACE. */
 enum { MPO_PROJ_STREAM_A = 1 << 30, MPO_PROJ_STREAM_B = (1 << 30) + 1 };
 mpo_status mpo_bond_project_bytes(const mpo_tt* in, int32_t k, size_t* bytes);
 mpo_status mpo_bond_project(const mpo_tt* in, int32_t k, uint64_t seed, int32_t pair, int32_t stream,

@@ -1580,11 +1580,47 @@ __global__ void __launch_bounds__(64) cluster_kernel(const EigDesc* __restrict__
 // ---------------------------------------------------------------- Householder QR
 // Column j: the reflector H_j = I - tau v v^T with v_j = 1 that maps
 // X(j:m, j) onto beta e_j (beta = -sign(alpha) ||X(j:m, j)||, the LAPACK
-// dlarfg convention); v is kept below the diagonal.  H_j is then applied to
-// the trailing columns, one thread per column walking down the rows (the
-// rows are contiguous across threads).
+// dlarfg convention); v is kept below the diagonal.  H_j is applied to the
+// trailing columns by the whole workgroup: w = v^T X(j:, j+1:) with
+// kBig / nc threads per column (nc trailing columns, each thread a
+// contiguous block of rows, the blocks summed in row order in LDS: the
+// order of a sequential dot product, which measured more accurate on the
+// graded factors of the canonical forms than strided slices), then the
+// rank-1 update over (row,
+// column) pairs, columns fastest so that the accesses are coalesced.  The
+// matrix stays in global memory (L2); n <= kBig.
+__device__ __forceinline__ void hh_apply(GAS double* Y, long long ldy, const GAS double* V, long long ldv,
+                                         int j, int m, int c0, int nc, double tau, double* wpart,
+                                         double* wv) {
+  const int tid = threadIdx.x;
+  const int per = kBig / nc;
+  if (tid < nc * per) {  // thread r0 of a column sums a contiguous block of rows, in row order
+    const int c = c0 + tid % nc, r0 = tid / nc;
+    const int rows = m - j - 1, blk = (rows + per - 1) / per;
+    const int i0 = j + 1 + r0 * blk, i1 = min(m, i0 + blk);
+    double s = r0 == 0 ? Y[(long long)j * ldy + c] : 0.0;
+    for (int i = i0; i < i1; ++i) s = fma(V[(long long)i * ldv + j], Y[(long long)i * ldy + c], s);
+    wpart[tid] = s;
+  }
+  __syncthreads();
+  if (tid < nc) {
+    double w = 0.0;
+    for (int q = 0; q < per; ++q) w += wpart[q * nc + tid];
+    wv[tid] = tau * w;
+  }
+  __syncthreads();
+  const long long tot = (long long)(m - j) * nc;
+  for (long long e = tid; e < tot; e += kBig) {
+    const int i = j + (int)(e / nc), cc = (int)(e % nc);
+    const double vi = i == j ? 1.0 : V[(long long)i * ldv + j];
+    Y[(long long)i * ldy + c0 + cc] = fma(-vi, wv[cc], Y[(long long)i * ldy + c0 + cc]);
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(kBig) geqr_kernel(const GeqrDesc* __restrict__ descs) {
   __shared__ double red[kBig / 64];
+  __shared__ double wpart[kBig], wv[kBig];
   const GeqrDesc d = descs[blockIdx.x];
   const int m = d.m, n = d.n, p = min(m, n);
   const long long ld = d.ldx;
@@ -1611,16 +1647,7 @@ __global__ void __launch_bounds__(kBig) geqr_kernel(const GeqrDesc* __restrict__
       if (d.tau) gstore_ptr(d.tau)[j] = tau;
     }
     __syncthreads();
-    if (tau != 0.0) {
-      for (int c = j + 1 + threadIdx.x; c < n; c += kBig) {
-        double w = X[j * ld + c];
-        for (int i = j + 1; i < m; ++i) w = fma(X[i * ld + j], X[i * ld + c], w);
-        w *= tau;
-        X[j * ld + c] -= w;
-        for (int i = j + 1; i < m; ++i) X[i * ld + c] = fma(-X[i * ld + j], w, X[i * ld + c]);
-      }
-    }
-    __syncthreads();
+    if (tau != 0.0 && j + 1 < n) hh_apply(X, ld, X, ld, j, m, j + 1, n - j - 1, tau, wpart, wv);
   }
   GAS double* R = gstore_ptr(d.R);
   for (long long e = threadIdx.x; e < (long long)p * n; e += kBig) {
@@ -1628,37 +1655,41 @@ __global__ void __launch_bounds__(kBig) geqr_kernel(const GeqrDesc* __restrict__
     R[(long long)i * d.ldr + c] = c >= i ? X[i * ld + c] : 0.0;
   }
 }
-}  // namespace
 
-// Q = H_0 H_1 ... H_{n-1} [I; 0], one thread per column: column c starts as
-// e_c and takes H_{n-1} .. H_c (H_j leaves columns c < j alone: they vanish
-// on rows >= j), so the columns never interact.  The reflector entries are
-// the same address across the threads (a broadcast).
+// Q = H_0 H_1 ... H_{n-1} [I; 0], the reflectors applied last to first to
+// the trailing block Q(j:, j:) (columns left of j are still e_c there), each
+// by the whole workgroup as in geqr_kernel; then the signs: column c of Q
+// and row c of R negated where R(c, c) < 0, so that diag(R) >= 0.
 __global__ void __launch_bounds__(kBig) orgqr_kernel(const OrgqrDesc* __restrict__ descs) {
+  __shared__ double wpart[kBig], wv[kBig], sgn[kBig];
   const OrgqrDesc d = descs[blockIdx.x];
   const int m = d.m, n = d.n;
   const long long ldx = d.ldx, ldq = d.ldq;
   const GAS double* X = gload_ptr(d.X);
-  const GAS double* tau = gload_ptr(d.tau);
   GAS double* Q = gstore_ptr(d.Q);
-  for (int c = threadIdx.x; c < n; c += kBig) {
-    for (int i = 0; i < m; ++i) Q[i * ldq + c] = i == c ? 1.0 : 0.0;
-    for (int j = c; j >= 0; --j) {
-      const double t = tau[j];
-      if (t == 0.0) continue;
-      double w = Q[j * ldq + c];
-      for (int i = j + 1; i < m; ++i) w = fma(X[i * ldx + j], Q[i * ldq + c], w);
-      w *= t;
-      Q[j * ldq + c] -= w;
-      for (int i = j + 1; i < m; ++i) Q[i * ldq + c] = fma(-X[i * ldx + j], w, Q[i * ldq + c]);
-    }
-    GAS double* R = gstore_ptr(d.R);
-    if (R[(long long)c * d.ldr + c] < 0.0) {
-      for (int i = 0; i < m; ++i) Q[i * ldq + c] = -Q[i * ldq + c];
-      for (int e = c; e < n; ++e) R[(long long)c * d.ldr + e] = -R[(long long)c * d.ldr + e];
-    }
+  for (long long e = threadIdx.x; e < (long long)m * n; e += kBig) {
+    const int i = (int)(e / n), c = (int)(e % n);
+    Q[i * ldq + c] = i == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = n - 1; j >= 0; --j) {
+    const double t = gload_ptr(d.tau)[j];
+    if (t == 0.0) continue;  // uniform
+    hh_apply(Q, ldq, X, ldx, j, m, j, n - j, t, wpart, wv);
+  }
+  GAS double* R = gstore_ptr(d.R);
+  for (int c = threadIdx.x; c < n; c += kBig) sgn[c] = R[(long long)c * d.ldr + c] < 0.0 ? -1.0 : 1.0;
+  __syncthreads();
+  for (long long e = threadIdx.x; e < (long long)m * n; e += kBig) {
+    const int i = (int)(e / n), c = (int)(e % n);
+    if (sgn[c] < 0.0) Q[i * ldq + c] = -Q[i * ldq + c];
+  }
+  for (long long e = threadIdx.x; e < (long long)n * n; e += kBig) {
+    const int c = (int)(e / n), c2 = (int)(e % n);
+    if (sgn[c] < 0.0 && c2 >= c) R[(long long)c * d.ldr + c2] = -R[(long long)c * d.ldr + c2];
   }
 }
+}  // namespace
 
 void launch_orgqr(const OrgqrDesc* d, int n, hipStream_t s) {
   if (n <= 0) return;

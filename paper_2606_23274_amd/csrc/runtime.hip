@@ -2930,6 +2930,7 @@ void validate_proj(const mpo_tt& in, int32_t k) {
   if (in.L < 2 || in.d < 1) throw Error{MPO_ERR_SHAPE, "bond projection: L >= 2 and d >= 1"};
   validate_tt(in, in.L, in.d);
   if (k < 1) throw Error{MPO_ERR_INVALID_ARG, "bond projection: k >= 1"};
+  if (k > 1024) throw Error{MPO_ERR_UNSUPPORTED, "bond projection: k above 1024"};
   for (int l = 1; l < in.L; ++l)
     if (in.chi[l] > 4096) throw Error{MPO_ERR_UNSUPPORTED, "bond projection: bond above 4096"};
 }
