@@ -92,7 +92,18 @@ typedef struct {
 
 typedef struct {
   int32_t chi_max;    /* bond cap chi_C of C (Alg. 3 "maxbonddim"), >= 1      */
-  double tau;         /* truncation tolerance of Sec. 2.3.4; only 0 is run    */
+  double tau;         /* truncation tolerance of Sec. 2.3.4, finite, >= 0.
+                         0: every bond keeps r = min(chi_max, n, m,
+                         chi^A_l chi^B_l) values.  > 0: an update keeps the
+                         smallest r' <= r with (sum_{j >= r'} sigma_j^2)^(1/2)
+                         <= (tau / L) (sum_j sigma_j^2)^(1/2) over the
+                         sigma_j it computed (all of the plain SVD, the k of
+                         the sketch); r' >= 1.  The bond dims then change
+                         on the device during a sweep: the buffers keep the
+                         tau = 0 plan's sizes with zero rows and columns
+                         beyond r', Omega takes the bond's actual shape, and
+                         mpo_fit_bond_dims / mpo_fit_export_c report and
+                         copy out the actual dims.  The gradient needs 0.  */
   int32_t precision;  /* mpo_precision                                         */
   int32_t schedule;   /* mpo_schedule                                          */
   int32_t sketch_p;   /* < 0: plain SVD of the two-site matrix; >= 0: RSVD with
@@ -209,7 +220,9 @@ mpo_status mpo_fit_position(const mpo_fit_ctx* ctx, int32_t* sweep, int32_t* uni
 mpo_status mpo_fit_singular_values(mpo_fit_ctx* ctx, int32_t pair, int32_t bond, double* S,
                                    int32_t* r);
 
-/* Current bond dimensions of C for one pair: chi_c receives L+1 ints (host). */
+/* Current bond dimensions of C for one pair: chi_c receives L+1 ints (host).
+   With opts.tau > 0 they are read from the device after the context's
+   stream (synchronizes it). */
 mpo_status mpo_fit_bond_dims(const mpo_fit_ctx* ctx, int32_t pair, int32_t* chi_c);
 
 /* Copies C of one pair into caller-owned device arrays (FP64, same layout as

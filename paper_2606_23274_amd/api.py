@@ -43,7 +43,7 @@ class _Setup:
 
     def __init__(self, pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
                  profile, pair_chi_max, tuning, c_init=None, first_sweep=0, track_error=False,
-                 first_bond=0, first_half=0):
+                 first_bond=0, first_half=0, tau=0.0):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.tts = []
@@ -56,7 +56,7 @@ class _Setup:
         self.pairs = arr
         opts = _lib.MpoFitOpts()
         opts.chi_max = int(chi_max)
-        opts.tau = 0.0
+        opts.tau = float(tau)
         opts.precision = _lib.PRECISION[precision]
         opts.schedule = _lib.SCHEDULE[schedule]
         opts.sketch_p = int(sketch_p)
@@ -100,15 +100,17 @@ class FitContext:
     sweeps this resumes it).  first_bond (serial, one pair): updates of that
     sweep already done; first_half (even/odd): start with the second
     half-step.  track_error: reserve what sweep(..., errors=True) needs for
-    the fit error per sweep.
+    the fit error per sweep.  tau > 0: the truncation tolerance of Sec.
+    2.3.4 (bond dims then follow the singular values; bond_dims() reads
+    them from the device).
     """
 
     def __init__(self, pairs, chi_max, precision="fp32", schedule="serial", sketch_p=-1, seed=0,
                  capture_graph=True, device="cuda:0", profile=False, pair_chi_max=None, tuning=None,
-                 c_init=None, first_sweep=0, track_error=False, first_bond=0, first_half=0):
+                 c_init=None, first_sweep=0, track_error=False, first_bond=0, first_half=0, tau=0.0):
         su = _Setup(pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
                     profile, pair_chi_max, tuning, c_init, first_sweep, track_error, first_bond,
-                    first_half)
+                    first_half, tau)
         self._setup = su
         self.lib = su.lib
         self.device = su.device

@@ -30,7 +30,13 @@ __device__ __forceinline__ double u53(unsigned long long w) {
 
 __global__ void omega_kernel(const OmegaDesc* __restrict__ descs) {
   const OmegaDesc d = descs[blockIdx.y];
-  const long long n = (long long)d.m * d.k;
+  int chi = d.chi, k = d.k;
+  if (d.rk) {  // the bond's current shape (tolerance truncation)
+    chi = d.rk[d.bond + 1];
+    const int nt = d.rk[d.bond - 1] * d.dd, mt = d.dd * chi;
+    k = min(min(d.kk, d.cap), min(nt, mt));
+  }
+  const long long n = (long long)d.dd * chi * k;
   const long long blk = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (4 * blk >= n) return;
   const int stream = (*d.stream_base) * d.stream_mul + d.stream_add;
@@ -46,8 +52,8 @@ __global__ void omega_kernel(const OmegaDesc* __restrict__ descs) {
     for (int h = 0; h < 2; ++h) {
       const long long e = 4 * blk + 2 * q + h;
       if (e < n) {
-        const int i = (int)(e / d.k), j = (int)(e % d.k);
-        const int cc = i % d.chi, su = i / d.chi;
+        const int i = (int)(e / k), j = (int)(e % k);
+        const int cc = i % chi, su = i / chi;
         const int p = cc * d.dd + su;
         d.out[(long long)p * d.k + j] = h ? rad * sn : rad * cs;
       }
@@ -184,6 +190,44 @@ __global__ void svals_kernel(const SvalDesc* __restrict__ descs) {
   if (d.keep) d.keep[j] = keep ? 1.0 : 0.0;
   if (!keep && d.count) atomicAdd(d.count, 1);
 }
+__global__ void __launch_bounds__(256) trunc_kernel(const TruncDesc* __restrict__ descs) {
+  __shared__ double red[4];
+  __shared__ int s_keep;
+  const TruncDesc d = descs[blockIdx.x];
+  double t = 0.0;
+  for (int e = threadIdx.x; e < d.kd; e += 256) t += d.diag[e];
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double tot = (red[0] + red[1]) + (red[2] + red[3]);
+    const double lim = d.thr * tot;
+    int cmax = min(min(d.chi_max, d.cap), d.r);
+    cmax = min(cmax, min(d.rk[d.bond - 1] * d.dd, d.dd * d.rk[d.bond + 1]));
+    cmax = max(cmax, 1);
+    int c = cmax;
+    double head = 0.0;
+    for (int j = 0; j < cmax; ++j) {
+      head += fmax(d.evals[j], 0.0);
+      if (tot - head <= lim) { c = j + 1; break; }
+    }
+    s_keep = c;
+    d.rk[d.bond] = c;
+  }
+  __syncthreads();
+  const int c = s_keep;
+  int drops = 0;
+  for (int j = threadIdx.x; j < d.r; j += 256) {
+    if (j >= c) {
+      d.S[j] = 0.0;
+      d.keep[j] = 0.0;
+    } else if (d.keep[j] == 0.0) {
+      ++drops;
+    }
+  }
+  if (d.count && drops) atomicAdd(d.count, drops);
+}
+
 __global__ void fill_kernel(const FillDesc* __restrict__ descs) {
   const FillDesc d = descs[blockIdx.y];
   if (d.eye_rows > 0) {
@@ -329,6 +373,11 @@ void launch_naive(const NaiveDesc* d, int n, long long max_elems, hipStream_t s)
 void launch_svals(const SvalDesc* d, int n, int max_r, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(svals_kernel, dim3(ceil_div(max_r, 256), n), dim3(256), 0, s, d);
+}
+
+void launch_trunc(const TruncDesc* d, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(trunc_kernel, dim3(n), dim3(256), 0, s, d);
 }
 
 void launch_fill(const FillDesc* d, int n, long long max_words, hipStream_t s) {

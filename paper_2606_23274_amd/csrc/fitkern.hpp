@@ -20,6 +20,14 @@ struct OmegaDesc {
   int stream_mul, stream_add;
   const int* stream_base;
   unsigned long long seed;
+  // with rk (the current bond dims of the train, indexed by bond: the
+  // tolerance rule of Sec. 2.3.4 changes them during a sweep) the matrix
+  // has the bond's actual shape, chi = rk[bond + 1] and
+  // k = min(kk, cap, rk[bond - 1] * dd, dd * chi), drawn as above into rows
+  // with c'' < chi and columns j < k of the buffer (ld k), which the caller
+  // zeroes first
+  const int* rk = nullptr;
+  int kk = 0, cap = 0;  // chi_max + p and the rank cap chi^A chi^B of the bond
 };
 void launch_omega(const OmegaDesc* d, int n, int max_elems, hipStream_t s);
 
@@ -84,6 +92,28 @@ struct SvalDesc {
 // (the Gram eigenproblem itself resolves sigma down to about 1e-8 sigma_1).
 constexpr double kDrop = 1e-6;
 void launch_svals(const SvalDesc* d, int n, int max_r, hipStream_t s);
+
+// Tolerance truncation of Sec. 2.3.4 for one bond, after launch_svals: with
+// lambda_j (descending, j < r) the computed top eigenvalues of a Gram matrix
+// whose diagonal (kd entries) is `diag`, so that the sum of all sigma^2 is
+// its trace T, the kept count is the smallest c >= 1 with
+// T - sum_{j<c} max(lambda_j, 0) <= thr T (thr = (tau / L)^2), capped at
+// min(chi_max, cap, rk[bond - 1] dd, dd rk[bond + 1], r).  S_j and keep_j
+// are zeroed for j >= c, rk[bond] = c, and the drop rule's zeros among the
+// kept values are counted into *count (nullable).  One workgroup per bond.
+struct TruncDesc {
+  const double* diag;
+  int kd;
+  int r;
+  const double* evals;
+  double* S;
+  double* keep;
+  int* rk;
+  int bond, dd, chi_max, cap;
+  double thr;
+  int* count;
+};
+void launch_trunc(const TruncDesc* d, int n, hipStream_t s);
 
 // Zero `n_words` 32-bit words at each pointer; when eye_rows > 0 write an
 // eye_rows x eye_cols identity (row-major, FP64 if eye_f64 else FP32) instead.

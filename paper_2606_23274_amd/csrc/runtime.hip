@@ -53,6 +53,7 @@ void run_program(const Program& p, hipStream_t s, hipEvent_t* ev) {
       case LK::Jacobi: launch_jacobi(p.device<JacobiDesc>(l), l.n, (int)l.maxa, s); break;
       case LK::Geqr: launch_geqr(p.device<GeqrDesc>(l), l.n, s); break;
       case LK::Orgqr: launch_orgqr(p.device<OrgqrDesc>(l), l.n, s); break;
+      case LK::Trunc: launch_trunc(p.device<TruncDesc>(l), l.n, s); break;
       case LK::Naive: launch_naive(p.device<NaiveDesc>(l), l.n, l.maxa, s); break;
       case LK::Polish: launch_polish(p.device<PolishDesc>(l), l.n, (int)l.maxa, s); break;
       case LK::NormBig: {
@@ -375,6 +376,9 @@ struct PairState {
   std::vector<double*> Yv;
   double* nu_dev = nullptr;       // [2]: nu_A, nu_B
   double nu = 1.0;
+  // tolerance truncation (tau > 0): the current bond dims on the device
+  // (L+1, indexed by bond); the host dims above are then capacities
+  int* rk = nullptr;
   // host copies of the input shapes; an optional initial guess C (else A)
   std::vector<int> chiA_in, chiB_in, chiC_in;
   std::vector<const double*> A_in, B_in, C_in;
@@ -393,6 +397,7 @@ struct BondScratch {
   unsigned* amT;
   double *omega, *Y, *Y2, *G, *R, *Bk, *H, *eigw, *evals, *Z, *S, *V, *sign, *SVt;
   double* keep;  // inverse gauge: 1 for kept singular values, 0 for truncated
+  double* diag;  // tolerance truncation: the Gram matrix's diagonal
 };
 
 struct Ctx {
@@ -886,6 +891,7 @@ void carve(Ctx& X, Carver& cv) {
     P.Yv.assign(L + 1, nullptr);
     for (int b = 1; b < L; ++b) P.Yv[b] = cv.take<double>(P.capC[b]);
     P.nu_dev = cv.take<double>(2);
+    P.rk = X.o.tau > 0.0 ? cv.take<int>((size_t)L + 1) : nullptr;
   }
   const size_t nscr = X.o.schedule == MPO_SCHED_SERIAL ? 1 : max_bonds * X.pairs.size();
   X.scratch.resize(nscr);
@@ -909,6 +915,7 @@ void carve(Ctx& X, Carver& cv) {
     B.sign = cv.take<double>((size_t)rx);
     B.keep = cv.take<double>((size_t)rx);
     B.SVt = cv.take<double>((size_t)rx * nm);
+    B.diag = X.o.tau > 0.0 ? cv.take<double>((size_t)kx) : nullptr;
   }
   // initialization scratch (FP64): Gram / triangular factors and a core-sized temp
   long long core_max = 1, kq = 1;
@@ -1199,6 +1206,10 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
   std::vector<EigDesc> ed;
   std::vector<SvalDesc> sv;
   std::vector<ScaleDesc> mz;
+  std::vector<FillDesc> omz;
+  std::vector<PermDesc> dg;
+  std::vector<TruncDesc> tr;
+  const bool tol = X.o.tau > 0.0;
   long long maxz = 1;
   bool reg = true;  // every eigenproblem on the register path
   double fth = 0, fsk = 0;
@@ -1216,6 +1227,10 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
       o.out = B.omega; o.m = b.m; o.k = b.k; o.chi = S.cC[b.i + 2]; o.dd = S.dd;
       o.bond = b.i + 1; o.pair = b.pair; o.stream_mul = stream_mul; o.stream_add = stream_add_base;
       o.stream_base = X.sweep_dev; o.seed = X.o.seed;
+      if (tol) {  // the bond's current shape lies inside the buffer's
+        o.rk = S.rk; o.kk = S.chi_max + X.o.sketch_p; o.cap = S.rcap[b.i + 1];
+        omz.push_back(FillDesc{B.omega, 2LL * b.m * b.k, 0, 0, 0});
+      }
       om.push_back(o);
       maxom = std::max(maxom, (long long)b.m * b.k);
       yj.push_back(GemmJob{b.n, b.k, b.m, opW(X, B.theta, true, b.m), op64(B.omega, false, b.k),
@@ -1236,13 +1251,20 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
     }
     ed.push_back(EigDesc{B.H, b.k, b.k, b.r, B.evals, B.Z, b.r, B.eigw, X.flag});
     reg = reg && b.k <= kRegMax;
-    sv.push_back(SvalDesc{B.evals, B.S, b.r, 0, X.flag, B.keep, X.flag + 2});
+    sv.push_back(SvalDesc{B.evals, B.S, b.r, 0, X.flag, B.keep, tol ? nullptr : X.flag + 2});
+    if (tol) {  // the Gram matrix's trace is the sum of all sigma^2
+      dg.push_back(perm4(B.H, 0, B.diag, 0, {1, 1, 1, b.k}, {0, 0, 0, (long long)b.k + 1}, {0, 0, 0, 1}));
+      const double t = X.o.tau / S.L;
+      tr.push_back(TruncDesc{B.diag, b.k, b.r, B.evals, B.S, B.keep, S.rk, b.i + 1, S.dd, S.chi_max,
+                             S.rcap[b.i + 1], t * t, X.flag + 2});
+    }
     // the eigenvectors of dropped values become exact zero columns
     mz.push_back(ScaleDesc{B.Z, B.Z, b.k, b.r, b.r, b.r, nullptr, B.keep, 0, 2});
     maxr = std::max(maxr, b.r);
     maxz = std::max(maxz, (long long)b.k * b.r);
   }
   add_gemm(P, X.sb, X.wmode, th, "theta", fth);
+  add_fill(P, omz);
   add_simple(P, LK::Omega, om, maxom, "omega");
   add_gemm(P, X.sb, Mode::F64, yj, "sketch", fsk / 2);
   // range finder: a rank-revealing Cholesky-QR pass, then a Newton-Schulz step
@@ -1253,8 +1275,10 @@ void rec_factor(Ctx& X, Program& P, std::vector<BondJob>& bj, int stream_mul, in
   for (auto& h : hj) (h.A.t == DType::F64 ? h64 : hw).push_back(h);
   add_gemm(P, X.sb, Mode::F64, h64, "gram", 0);
   add_gemm(P, X.sb, Mode::F64, hw, "gram", 0);
+  add_perm(P, dg, "svals");
   add_eig(P, X.sb, ed, reg, "eig");
   add_simple(P, LK::Sval, sv, maxr, "svals");
+  add_simple(P, LK::Trunc, tr, 0, "svals");
   add_simple(P, LK::Scale, mz, maxz, "scale");
   (void)halfstep;
 }
@@ -1697,7 +1721,7 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
   if (o->chi_max < 1) throw Error{MPO_ERR_INVALID_ARG, "chi_max must be >= 1"};
   if (o->chi_max + std::max(o->sketch_p, 0) > 512)
     throw Error{MPO_ERR_UNSUPPORTED, "chi_max + sketch_p above 512"};
-  if (o->tau != 0.0) throw Error{MPO_ERR_UNSUPPORTED, "only tau = 0 (fixed bond cap) is run"};
+  if (!(o->tau >= 0.0 && o->tau < INFINITY)) throw Error{MPO_ERR_INVALID_ARG, "tau must be finite and >= 0"};
   if (o->precision < 0 || o->precision > 3) throw Error{MPO_ERR_INVALID_ARG, "bad precision"};
   if (o->schedule < 0 || o->schedule > 1) throw Error{MPO_ERR_INVALID_ARG, "bad schedule"};
   if (o->first_sweep < 0 || o->first_sweep > (1 << 24)) throw Error{MPO_ERR_INVALID_ARG, "bad first_sweep"};
@@ -2454,6 +2478,7 @@ void rec_check_qr_sweep(Program& P, const SplitBuf& sb, const mpo_tt& A, const m
 
 int grad_centre(const Ctx& X) {
   if (X.o.schedule != MPO_SCHED_SERIAL) throw Error{MPO_ERR_UNSUPPORTED, "gradient: serial schedule only"};
+  if (X.o.tau > 0.0) throw Error{MPO_ERR_UNSUPPORTED, "gradient: fixed bond cap (tau = 0) only"};
   if (X.pos != 0) throw Error{MPO_ERR_UNSUPPORTED, "gradient: the fit stands inside a sweep"};
   return (X.o.first_sweep + X.sweeps_done) % 2 == 1 ? -1 : 0;  // -1: last site
 }
@@ -2619,6 +2644,24 @@ mpo_status guarded(F&& f) {
     g_last_error = e.what();
     return MPO_ERR_DEVICE;
   }
+}
+
+// The bond dims of a pair's train as they stand: the planned ones, or with a
+// truncation tolerance the device's (read after the context's stream).
+std::vector<int> current_dims(const Ctx& X, const PairState& S) {
+  if (!S.rk) return S.cC;
+  std::vector<int> c(S.cC.size());
+  HIP_OK(hipStreamSynchronize(X.stream));
+  HIP_OK(hipMemcpy(c.data(), S.rk, c.size() * sizeof(int), hipMemcpyDeviceToHost));
+  return c;
+}
+
+// Core i stored with the planned dims (cC) copied out with dims c (<= cC:
+// the leading block, which holds every kept value), times scale.
+PermDesc export_core(const PairState& S, int i, const std::vector<int>& c, double* out, double scale) {
+  const long long cr = S.cC[i + 1];
+  return perm4(S.C64[i], 0, out, 0, {1, c[i], S.dd, c[i + 1]}, {0, S.dd * cr, cr, 1},
+               {0, (long long)S.dd * c[i + 1], c[i + 1], 1}, scale);
 }
 }  // namespace
 
@@ -3086,6 +3129,8 @@ mpo_status mpo_fit_init(mpo_fit_ctx** ctx, const mpo_pair* pairs, int32_t n_pair
     upload(X, init);
     run_program(init, X.stream, nullptr);
     for (auto& S : X.pairs) {
+      if (S.rk)  // the initial guess's dims; the tolerance rule updates them on the device
+        HIP_OK(hipMemcpyAsync(S.rk, S.cC.data(), S.cC.size() * sizeof(int), hipMemcpyHostToDevice, X.stream));
       double nu[2];
       HIP_OK(hipMemcpyAsync(nu, S.nu_dev, sizeof(nu), hipMemcpyDeviceToHost, X.stream));
       HIP_OK(hipStreamSynchronize(X.stream));
@@ -3159,7 +3204,7 @@ mpo_status mpo_fit_bond_dims(const mpo_fit_ctx* ctx, int32_t pair, int32_t* chi_
   return guarded([&] {
     if (!ctx || !chi_c) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
     if (pair < 0 || pair >= (int)ctx->X.pairs.size()) throw Error{MPO_ERR_INVALID_ARG, "bad pair"};
-    const auto& c = ctx->X.pairs[pair].cC;
+    const auto c = current_dims(ctx->X, ctx->X.pairs[pair]);
     for (size_t i = 0; i < c.size(); ++i) chi_c[i] = c[i];
   });
 }
@@ -3174,14 +3219,13 @@ mpo_status mpo_fit_export_c(mpo_fit_ctx* ctx, int32_t pair, double* const* c_cor
     std::vector<PermDesc> ds;
     std::vector<ScaleDesc> sc;
     const bool inv = X.o.schedule == MPO_SCHED_EVEN_ODD;
+    const std::vector<int> c = current_dims(X, S);
     for (int i = 0; i < S.L; ++i) {
       if (!c_cores[i]) throw Error{MPO_ERR_INVALID_ARG, "null output core"};
-      const long long n = (long long)S.cC[i] * S.dd * S.cC[i + 1];
-      ds.push_back(perm4(S.C64[i], 0, c_cores[i], 0, {1, 1, 1, (int)n}, {0, 0, 0, 1}, {0, 0, 0, 1},
-                         i == 0 ? S.nu : 1.0));
+      ds.push_back(export_core(S, i, c, c_cores[i], i == 0 ? S.nu : 1.0));
       if (inv && i + 1 < S.L)  // merged form C_l = Psi_l Y_l
-        sc.push_back(ScaleDesc{c_cores[i], c_cores[i], S.cC[i] * S.dd, S.cC[i + 1], S.cC[i + 1],
-                               S.cC[i + 1], nullptr, S.Yv[i + 1], 0, 1});
+        sc.push_back(ScaleDesc{c_cores[i], c_cores[i], c[i] * S.dd, c[i + 1], c[i + 1], c[i + 1], nullptr,
+                               S.Yv[i + 1], 0, 1});
     }
     add_perm(P, ds, "export");
     long long mx = 1;
@@ -3202,7 +3246,7 @@ mpo_status mpo_fit_singular_values(mpo_fit_ctx* ctx, int32_t pair, int32_t bond,
     if (pair < 0 || pair >= (int)X.pairs.size()) throw Error{MPO_ERR_INVALID_ARG, "bad pair"};
     PairState& P = X.pairs[pair];
     if (bond < 1 || bond >= P.L) throw Error{MPO_ERR_INVALID_ARG, "bond must be in 1 .. L-1"};
-    const int n = P.cC[bond];
+    const int n = current_dims(X, P)[bond];
     HIP_OK(hipMemcpyAsync(S, P.Yv[bond], n * sizeof(double), hipMemcpyDeviceToHost, X.stream));
     HIP_OK(hipStreamSynchronize(X.stream));
     if (r) *r = n;
@@ -3218,10 +3262,10 @@ mpo_status mpo_fit_export_psi(mpo_fit_ctx* ctx, int32_t pair, double* const* psi
     PairState& S = X.pairs[pair];
     Program P;
     std::vector<PermDesc> ds;
+    const std::vector<int> c = current_dims(X, S);
     for (int i = 0; i < S.L; ++i) {
       if (!psi_cores[i]) throw Error{MPO_ERR_INVALID_ARG, "null output core"};
-      const long long n = (long long)S.cC[i] * S.dd * S.cC[i + 1];
-      ds.push_back(perm4(S.C64[i], 0, psi_cores[i], 0, {1, 1, 1, (int)n}, {0, 0, 0, 1}, {0, 0, 0, 1}));
+      ds.push_back(export_core(S, i, c, psi_cores[i], 1.0));
     }
     add_perm(P, ds, "export");
     const size_t keep = X.arena_used;

@@ -79,6 +79,15 @@ def test_workspace_query_ok(schedule, precision):
     assert st == 0 and n > 0 and n % 256 == 0
 
 
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_tau_workspace_adds_the_rank_slots(schedule):
+    """A tolerance keeps the fixed-cap plan's buffers and adds the device
+    bond dims and a diagonal per factorization."""
+    st0, n0 = _query([_Pair()], _opts(schedule=schedule))
+    st1, n1 = _query([_Pair()], _opts(schedule=schedule, tau=0.5))
+    assert st0 == 0 and st1 == 0 and n0 < n1 <= n0 + 64 * 1024
+
+
 def test_workspace_grows_with_pairs_and_bond():
     _, one = _query([_Pair()], _opts())
     _, two = _query([_Pair(), _Pair()], _opts())
@@ -87,7 +96,9 @@ def test_workspace_grows_with_pairs_and_bond():
 
 
 @pytest.mark.parametrize("opts, status", [
-    (dict(tau=1e-3), 6),            # tau > 0 is not run
+    (dict(tau=-1e-3), 1),           # tau must be >= 0
+    (dict(tau=float("inf")), 1),    # and finite
+    (dict(tau=float("nan")), 1),
     (dict(precision=9), 1),
     (dict(schedule=5), 1),
     (dict(chi_max=0), 1),

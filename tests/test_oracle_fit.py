@@ -188,6 +188,91 @@ def test_tau_truncation_rule():
     assert fit.truncation_rank(S, 2, 10, tau=0.0, L=3) == 2
 
 
+def _brute_rank(S, tau, L):
+    """Smallest count c >= 1 whose discarded tail meets the Sec. 2.3.4 rule,
+    by trying every c in order (pure Python sums)."""
+    tot = sum(float(x) * float(x) for x in S)
+    for c in range(1, len(S) + 1):
+        tail = sum(float(x) * float(x) for x in S[c:])
+        if tail ** 0.5 <= (tau / L) * tot ** 0.5:
+            return c
+    return len(S)
+
+
+def test_tau_rule_against_brute_force():
+    rng = np.random.default_rng(21)
+    for _ in range(200):
+        n = int(rng.integers(1, 30))
+        S = np.sort(np.exp(rng.uniform(-12, 0, n)))[::-1]
+        tau, L = float(10 ** rng.uniform(-6, 0.5)), int(rng.integers(2, 50))
+        assert fit.truncation_rank(S, 10 ** 6, 10 ** 6, tau, L) == _brute_rank(S, tau, L)
+        assert fit.truncation_rank(S, 3, 10 ** 6, tau, L) == min(3, _brute_rank(S, tau, L))
+
+
+@pytest.mark.parametrize("schedule", ["serial", "even_odd"])
+def test_tau_L2_is_tolerance_truncated_svd(schedule):
+    """L = 2: the tau fit is the SVD of the d^2 x d^2 unfolding cut at the
+    smallest rank whose tail is at most (tau / 2) ||A B||_F (Eckart-Young
+    with the rank of the rule, from LAPACK's singular values)."""
+    rng = np.random.default_rng(5)
+    A = gaussian_mpo(rng, 2, 3, 3, decay=True)
+    B = gaussian_mpo(rng, 2, 3, 3, decay=True)
+    P = mpo.dense(A) @ mpo.dense(B)
+    sv = np.linalg.svd(_dense_unfold(P, 2, 3, 1), compute_uv=False)
+    nP = np.linalg.norm(P)
+    for c_want in (1, 2, 4):
+        # a tolerance halfway (in log) between the tails of c_want and c_want - 1
+        hi = np.sqrt(np.sum(sv[c_want - 1:] ** 2)) if c_want > 1 else nP
+        lo = np.sqrt(np.sum(sv[c_want:] ** 2))
+        tau = 2.0 * np.sqrt(lo * hi) / nP
+        run = fit.fit_serial if schedule == "serial" else fit.fit_even_odd
+        res = run(A, B, 9, 2, tau=tau)
+        assert res.bond_dims == [1, c_want, 1]
+        err = np.linalg.norm(P - mpo.dense(res.C))
+        assert abs(err - lo) < 1e-12 * nP
+
+
+@pytest.mark.parametrize("schedule", ["serial", "even_odd"])
+def test_tau_below_every_tail_is_the_fixed_cap_fit(schedule):
+    A, B = make_pair(6, 2, 4, seed=7, decay=True)
+    run = fit.fit_serial if schedule == "serial" else fit.fit_even_odd
+    r0 = run(A, B, 6, 2)
+    r1 = run(A, B, 6, 2, tau=1e-300)
+    assert r1.bond_dims == r0.bond_dims
+    for a, b in zip(r0.C, r1.C):
+        assert np.array_equal(a, b)
+
+
+def test_tau_first_update_rank_and_error():
+    """The first update (bond 1 from the same environments for every tau)
+    keeps the rule's count of the two-site matrix's singular values, and
+    what it discards is at most (tau / L) of that matrix's norm."""
+    A, B = make_pair(8, 2, 6, seed=3, decay=True)
+    A1, B1, _, caps = fit._preprocess(A, B)
+    C = canon.right_orthogonalize(A1)
+    R = [None] * 10
+    R[9] = np.ones((1, 1, 1))
+    for l in range(8, 2, -1):
+        R[l] = fit.env_right(R[l + 1], C[l - 1], A1[l - 1], B1[l - 1])
+    M = fit.two_site_matrix(np.ones((1, 1, 1)), A1[0], B1[0], A1[1], B1[1], R[3])
+    sv = np.linalg.svd(M, compute_uv=False)
+    prev = None
+    ranks = []
+    for tau in (0.0, 1.0, 2.0, 4.0):
+        seen = {}
+        fit.fit_serial(A, B, 12, 1, tau=tau, n_updates=1,
+                       on_update=lambda sw, l, Cs: seen.setdefault("r", Cs[0].shape[3]))
+        r = seen["r"]
+        assert r == min(fit.truncation_rank(sv, 12, caps[0], tau, 8), len(sv))
+        if tau > 0:
+            assert np.sqrt(np.sum(sv[r:] ** 2)) <= tau / 8 * np.linalg.norm(sv) * (1 + 1e-12)
+        if prev is not None:
+            assert r <= prev
+        prev = r
+        ranks.append(r)
+    assert ranks[0] > ranks[-1]  # the rule cuts below the cap here
+
+
 def test_even_odd_gauge_relations_and_fixed_point():
     """Exact-rank regime: after convergence a further even/odd sweep leaves C
     unchanged, and the inverse gauge relations hold."""
