@@ -11,12 +11,16 @@ choices below are taken, by the GPU path too):
     possible, the first ones one site longer; each at least two sites.
     Sub-TT n is "odd" in the paper's 1-based count when n (0-based) is even:
     it sweeps forward first ("F"); the others sweep backward first ("B").
-  * Initialization: the guess (preprocessed A, or C_init) right-
-    orthogonalized as for the serial fit (Alg. 5); every B sub-TT moves its
-    orthogonality centre to its right-most site by a QR sweep inside itself
-    (the operator is unchanged).  All environments are those of this guess;
-    the ones at a sub-TT's boundary stand in for the paper's identities or
-    random isometries, which only save the cost of building them.
+  * Initialization: every sub-TT starts from the guess (preprocessed A, or
+    C_init) in the mixed canonical form centred on it, so that its
+    environments are isometric, as the paper's identities or random
+    isometries at the boundaries are: the guess right-orthogonalized, then
+    left-orthogonalized (QR sweep, carried to the last site), which gives
+    every left environment, then right-orthogonalized again (RQ sweep),
+    which gives every right environment.  The local problems are then those
+    of the serial fit at the same positions; environments built on the
+    guess's own (non-isometric) cores instead would weight each local
+    problem by the guess's Schmidt values.
   * One set of local full sweeps (``n_sets`` of them), phases 0..3:
       0: F sub-TTs sweep forward over their inner bonds, B sub-TTs backward
          (each update the serial site-canonical update of Alg. 3);
@@ -173,13 +177,12 @@ def fit_parallel_site(A, B, chi_max, n_sets, n_parts, sketch_p=-1, seed=0, pair=
     A1, B1, nu, caps = _preprocess(A, B)
     C = canon.right_orthogonalize(A1 if C_init is None else C_init)
     st = _State(A1, B1, C, chi_max, sketch_p, seed, pair, caps, tau)
-    for n, (s, e) in enumerate(parts):
-        if n % 2 == 1:
-            st.qr_sweep(s, e)
-    for b in range(L - 1, 0, -1):
-        st.right_env(b)
+    st.qr_sweep(0, L - 1)
     for b in range(0, L - 1):
         st.left_env(b)
+    st.rq_sweep(L - 1, 0)
+    for b in range(L - 1, 0, -1):
+        st.right_env(b)
     for t in range(n_sets):
         _half_sweeps(st, parts, True, 4 * t)
         for n in range(0, n_parts, 2):
