@@ -364,6 +364,55 @@ def zipup_section():
     return res
 
 
+def parallel_section(steps):
+    """Site-canonical parallel fit (Sec. 4, variant II) at the headline
+    workload, FP32: sets per second for 4 and 8 sub-TTs (one set = the two
+    local half-sweeps of every sub-TT and both groups of connections,
+    2 (L - n_parts) + n_parts - 1 two-site updates), the merge's time, and
+    the fit error after 1 and 2 sets + merge next to the serial fit's after
+    2 and 4 sweeps (the same number of passes over the chain)."""
+    import torch
+    from paper_2606_23274_amd.api import FitContext, fit_error
+    from synth import make_pair
+    w = WORKLOAD
+    A, B = make_pair(w["L"], w["d"], w["chi"], seed=w["seed"], decay=True)
+    res = {}
+    for n_parts in (4, 8):
+        ctx = FitContext([(A, B)], w["chi_c"], precision="fp32", schedule="parallel", sketch_p=w["p"],
+                         seed=w["seed"], n_parts=n_parts)
+        ctx.sweep(2)  # shapes settle, graphs captured
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.sweep(steps)
+        wall = time.perf_counter() - t0
+        ctx.merge()
+        merge_ms = ctx.last_sweep_ms()
+        ctx.close()
+        upd = 2 * (w["L"] - n_parts) + n_parts - 1
+        errs = []
+        for sets in (1, 2):
+            c2 = FitContext([(A, B)], w["chi_c"], precision="fp32", schedule="parallel", sketch_p=w["p"],
+                            seed=w["seed"], n_parts=n_parts)
+            c2.sweep(sets)
+            c2.merge()
+            errs.append(fit_error(A, B, c2.export_numpy(0))[0])
+            c2.close()
+        res[f"n_parts_{n_parts}"] = {"sets_per_s": round(steps / wall, 3),
+                                     "updates_per_set": upd,
+                                     "updates_per_s": round(upd * steps / wall, 1),
+                                     "merge_ms": round(merge_ms, 3),
+                                     "fit_error_after_1_2_sets_merged": errs}
+    ctx = FitContext([(A, B)], w["chi_c"], precision="fp32", sketch_p=w["p"], seed=w["seed"])
+    serr = []
+    for k in range(4):
+        ctx.sweep(1)
+        if k in (1, 3):
+            serr.append(fit_error(A, B, ctx.export_numpy(0))[0])
+    ctx.close()
+    res["serial_fit_error_after_2_4_sweeps"] = serr
+    return res
+
+
 def gradient_section():
     import torch
     from paper_2606_23274_amd.api import FitContext
@@ -395,7 +444,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=6, help="sweeps of the accuracy comparison")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline, profile and roofline only")
-    ap.add_argument("--section", choices=["batched", "gradient", "randomized", "zipup"],
+    ap.add_argument("--section", choices=["batched", "gradient", "randomized", "zipup", "parallel"],
                     help="run only that section (for profiling) and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 256 MiB (4 times): the reference for "
@@ -413,7 +462,8 @@ def main():
     if args.section:
         out = (batched_section(max(2, args.steps // 2)) if args.section == "batched" else
                randomized_section(max(2, args.steps // 2)) if args.section == "randomized" else
-               zipup_section() if args.section == "zipup" else gradient_section())
+               zipup_section() if args.section == "zipup" else
+               parallel_section(max(2, args.steps // 2)) if args.section == "parallel" else gradient_section())
         print(json.dumps(out), flush=True)
         return
     if args.gpus != 1:
@@ -459,7 +509,7 @@ def main():
             roof["frac_of_one_cu"] = round(ach / (peak / 256), 5)
         roof["traffic"] = measured_traffic(roof["kernel"])
 
-    others, batched, grad, acc, cpu, randomized = {}, {}, {}, {}, None, {}
+    others, batched, grad, acc, cpu, randomized, par = {}, {}, {}, {}, None, {}, {}
     if not args.quick:
         wall_b, _, _, _ = run_gpu(A, B, "fp32", w["p"], args.steps, args.warmup)
         others["fp32_built_in_gemm_choice"] = {"sweeps_per_s": round(args.steps / wall_b, 3)}
@@ -478,6 +528,7 @@ def main():
         print("gradient done", file=sys.stderr, flush=True)
         randomized = randomized_section(max(2, args.steps // 2))
         randomized["zipup_initial_guess"] = zipup_section()
+        par = parallel_section(max(2, args.steps // 2))
         print("randomized and zip-up done", file=sys.stderr, flush=True)
         Cs = []
         if not args.no_cpu:
@@ -542,7 +593,7 @@ def main():
     }
     if not args.quick:
         line.update({"other_precisions": others, "accuracy": acc, "batched_schedule": batched,
-                     "gradient": grad, "randomized_bonds": randomized})
+                     "gradient": grad, "randomized_bonds": randomized, "parallel_site_canonical": par})
         if cpu is not None:
             line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

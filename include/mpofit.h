@@ -63,10 +63,24 @@ typedef enum {
 typedef enum {
   MPO_SCHED_SERIAL = 0,  /* Alg. 5: alternating forward/backward sweeps of the
                             site-canonical update of Alg. 3                   */
-  MPO_SCHED_EVEN_ODD = 1 /* inverse canonical gauge (Alg. 4): every bond
+  MPO_SCHED_EVEN_ODD = 1, /* inverse canonical gauge (Alg. 4): every bond
                             l = 1 (mod 2) together, then every l = 0 (mod 2),
                             from the environments at the half-step's start;
                             one sweep = both half-steps (Sec. 4) */
+  MPO_SCHED_PARALLEL = 2  /* site-canonical parallel fit (Sec. 4, variant II),
+                            one pair: opts.n_parts sub-TTs (a power of two,
+                            each >= 2 sites, the first ones one site longer)
+                            swept in lockstep, sub-TT n forward first for
+                            even n; one "sweep" = one set of four phases:
+                            local half-sweeps, the connections from even to
+                            odd sub-TTs, the reversed half-sweeps, the
+                            connections from odd to even sub-TTs.  A
+                            connection leaves U S on its left site and S V^T
+                            on its right one (each sub-TT keeps its own
+                            gauge) and rebuilds both environments; Omega of
+                            phase q of set t is stream 4 t + q.  The cores
+                            form one train only after mpo_fit_merge.  Needs
+                            tau = 0, first_sweep = 0, track_error = 0.       */
 } mpo_schedule;
 /* Drop rule of both schedules: of the r singular values an update keeps,
    those at or below 1e-6 sigma_1 are dropped (value, singular vectors and in
@@ -146,6 +160,7 @@ typedef struct {
                           its second half-step (l = 0 mod 2), from the
                           inverse canonical form of the initial guess and
                           its environments; 0 = whole sweeps                */
+  int32_t n_parts;     /* parallel schedule: number of sub-TTs; else unused  */
 } mpo_fit_opts;
 
 /* One tuned class of grouped GEMM launches: the operand kind (mode as
@@ -203,6 +218,21 @@ mpo_status mpo_fit_sweep(mpo_fit_ctx* ctx, int32_t n_sweeps, double* fit_err);
    entered part-way is finished by the next mpo_fit_sweep call before whole
    sweeps run.  Synchronizes the stream; MPO_ERR_NUMERIC as mpo_fit_sweep. */
 mpo_status mpo_fit_updates(mpo_fit_ctx* ctx, int32_t n_units);
+
+/* Parallel schedule (Sec. 4, variant II): the binary merge after the sets
+   run so far.  Local half-sweeps once more (Omega stream 4 t, t = sets
+   run), a forward update at every connection from an even to an odd
+   sub-TT with fresh environments on both sides (stream 4 t + 1; each pair
+   of sub-TTs becomes one site-canonical train), then for level v = 2, 3,
+   ... the adjacent groups of 2^(v-1) sub-TTs are joined: the left group's
+   centre moved to its last site by Householder QR sweeps and its left
+   environments rebuilt, the right group's centre moved to its first site
+   by RQ sweeps and its right environments rebuilt, one forward update at
+   the boundary (stream 4 t + v).  Afterwards C is one site-canonical train
+   (mpo_fit_export_c), and sweeps are refused.  Synchronizes the stream;
+   mpo_fit_last_sweep_ms gives the merge's time.  UNSUPPORTED for other
+   schedules, a second call, or a position inside a set. */
+mpo_status mpo_fit_merge(mpo_fit_ctx* ctx);
 
 /* Position of the fit: *sweep = index of the current sweep (first_sweep plus
    the sweeps completed), *unit = its units already run (0 = at a sweep

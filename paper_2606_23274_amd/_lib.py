@@ -11,7 +11,7 @@ MPO_OK = 0
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "SHAPE", 3: "WORKSPACE", 4: "DEVICE", 5: "NUMERIC",
           6: "UNSUPPORTED"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
-SCHEDULE = {"serial": 0, "even_odd": 1}
+SCHEDULE = {"serial": 0, "even_odd": 1, "parallel": 2}
 PROJ_STREAM = {"A": 1 << 30, "B": (1 << 30) + 1}
 
 
@@ -35,7 +35,7 @@ class MpoFitOpts(C.Structure):
                 ("capture_graph", C.c_int32), ("tune", C.POINTER(MpoGemmTune)),
                 ("n_tune", C.c_int32), ("profile", C.c_int32), ("c_init", C.POINTER(MpoTT)),
                 ("first_sweep", C.c_int32), ("track_error", C.c_int32), ("first_bond", C.c_int32),
-                ("first_half", C.c_int32)]
+                ("first_half", C.c_int32), ("n_parts", C.c_int32)]
 
 
 class MpoError(RuntimeError):
@@ -49,7 +49,7 @@ EXPORTS = [
     "mpo_fit_export_c", "mpo_fit_sweeps_done", "mpo_fit_norm_factor", "mpo_fit_truncations",
     "mpo_fit_grad_workspace_bytes", "mpo_fit_grad", "mpo_contract_check_bytes",
     "mpo_contract_exact_check", "mpo_contract_exact_check_static", "mpo_fit_singular_values",
-    "mpo_fit_updates", "mpo_fit_position", "mpo_fit_export_psi", "mpo_bond_project_bytes",
+    "mpo_fit_updates", "mpo_fit_merge", "mpo_fit_position", "mpo_fit_export_psi", "mpo_bond_project_bytes",
     "mpo_bond_project", "mpo_zipup_bytes", "mpo_zipup",
     "mpo_fit_last_sweep_ms", "mpo_fit_profile", "mpo_gemm_autotune", "mpo_fit_destroy",
     "mpo_last_error",
@@ -75,6 +75,7 @@ def load() -> C.CDLL:
     lib.mpo_fit_singular_values.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double),
                                             P(C.c_int32)]
     lib.mpo_fit_updates.argtypes = [C.c_void_p, C.c_int32]
+    lib.mpo_fit_merge.argtypes = [C.c_void_p]
     lib.mpo_fit_export_psi.argtypes = [C.c_void_p, C.c_int32, P(C.c_void_p)]
     lib.mpo_fit_position.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
     lib.mpo_fit_bond_dims.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]

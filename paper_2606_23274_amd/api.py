@@ -43,7 +43,7 @@ class _Setup:
 
     def __init__(self, pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
                  profile, pair_chi_max, tuning, c_init=None, first_sweep=0, track_error=False,
-                 first_bond=0, first_half=0, tau=0.0):
+                 first_bond=0, first_half=0, tau=0.0, n_parts=0):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.tts = []
@@ -67,6 +67,7 @@ class _Setup:
         opts.track_error = 1 if track_error else 0
         opts.first_bond = int(first_bond)
         opts.first_half = int(first_half)
+        opts.n_parts = int(n_parts)
         self.tune = tune_mod.to_ctypes(tune_mod.load(tuning)) if tuning is not None else None
         if self.tune is not None and len(self.tune):
             opts.tune = self.tune
@@ -102,15 +103,18 @@ class FitContext:
     half-step.  track_error: reserve what sweep(..., errors=True) needs for
     the fit error per sweep.  tau > 0: the truncation tolerance of Sec.
     2.3.4 (bond dims then follow the singular values; bond_dims() reads
-    them from the device).
+    them from the device).  schedule='parallel' with n_parts sub-TTs: the
+    site-canonical parallel fit of Sec. 4; sweep(n) runs n sets, merge()
+    joins the sub-TTs into one train before export.
     """
 
     def __init__(self, pairs, chi_max, precision="fp32", schedule="serial", sketch_p=-1, seed=0,
                  capture_graph=True, device="cuda:0", profile=False, pair_chi_max=None, tuning=None,
-                 c_init=None, first_sweep=0, track_error=False, first_bond=0, first_half=0, tau=0.0):
+                 c_init=None, first_sweep=0, track_error=False, first_bond=0, first_half=0, tau=0.0,
+                 n_parts=0):
         su = _Setup(pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
                     profile, pair_chi_max, tuning, c_init, first_sweep, track_error, first_bond,
-                    first_half, tau)
+                    first_half, tau, n_parts)
         self._setup = su
         self.lib = su.lib
         self.device = su.device
@@ -137,6 +141,10 @@ class FitContext:
         out = (C.c_double * (self.n_pairs * int(n)))()
         _lib.check(self.lib.mpo_fit_sweep(self.ctx, int(n), out))
         return np.array(out[:], dtype=np.float64).reshape(self.n_pairs, int(n))
+
+    def merge(self):
+        """Parallel schedule: the binary merge of the sub-TTs (mpo_fit_merge)."""
+        _lib.check(self.lib.mpo_fit_merge(self.ctx))
 
     def updates(self, n=1):
         """Runs the next n two-site updates (serial) or half-steps (even/odd)."""

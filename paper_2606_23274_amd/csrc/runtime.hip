@@ -404,6 +404,8 @@ struct Ctx {
   mpo_fit_opts o{};
   hipStream_t stream = nullptr;
   int device = 0;
+  std::vector<std::pair<int, int>> parts;  // parallel schedule: sub-TT site ranges
+  bool merged = false;                     // parallel schedule: mpo_fit_merge has run
   Mode wmode = Mode::F32;  // arithmetic of the contractions
   DType wt = DType::F32;   // storage type of environments and extensions
   std::vector<PairState> pairs;
@@ -452,10 +454,26 @@ size_t err_region_bytes(const Ctx& X);
 int bytes_of(DType t) { return t == DType::F64 ? 8 : 4; }
 
 // ------------------------------------------------------------------ shapes
+// Sub-TTs of the parallel schedule (Sec. 4): n_parts contiguous site ranges
+// as equal as possible, the first ones one site longer.  Block n sweeps
+// forward first when n is even ("F"), backward first otherwise ("B").
+std::vector<std::pair<int, int>> partition_sites(int L, int n_parts) {
+  std::vector<std::pair<int, int>> out;
+  const int base = L / n_parts, extra = L % n_parts;
+  int s = 0;
+  for (int n = 0; n < n_parts; ++n) {
+    const int ln = base + (n < extra ? 1 : 0);
+    out.push_back({s, s + ln - 1});
+    s += ln;
+  }
+  return out;
+}
+
 // Bond dims after the preprocessing and initial guess, and the capacity of
 // each of C's bonds over the fit (the ranks r = min(chi_max, n, m, cap)
 // settle within two sweeps; simulated here on the host).
-void plan_shapes(PairState& P, int chi_max, int schedule, int first_sweep, int first_bond, int first_half) {
+void plan_shapes(PairState& P, int chi_max, int schedule, int first_sweep, int first_bond, int first_half,
+                 int n_parts = 0) {
   const int L = P.L, dd = P.dd;
   auto leftorth = [&](const std::vector<int>& in) {
     std::vector<int> c(in);
@@ -488,6 +506,33 @@ void plan_shapes(PairState& P, int chi_max, int schedule, int first_sweep, int f
     sim[b] = std::min(std::min(chi_max, P.rcap[b]), std::min(n, m));
     P.capC[b] = std::max(P.capC[b], sim[b]);
   };
+  if (schedule == MPO_SCHED_PARALLEL) {
+    // the QR sweep after the RQ sweep (clipping as rec_qr_sweep), then the
+    // phases of six sets and the merge's updates
+    const auto parts = partition_sites(L, n_parts);
+    for (int i = 0; i + 1 < L; ++i)
+      if (c[i] * dd < c[i + 1]) c[i + 1] = c[i] * dd;
+    P.cC = c;
+    P.capC = c;
+    sim = c;
+    auto sweeps = [&](bool fwd_first) {
+      for (size_t n = 0; n < parts.size(); ++n) {
+        const bool fwd = (n % 2 == 0) == fwd_first;
+        const int s = parts[n].first, e = parts[n].second;
+        if (fwd) for (int i = s; i < e; ++i) upd(i + 1);
+        else for (int i = e - 1; i >= s; --i) upd(i + 1);
+      }
+    };
+    for (int set = 0; set < 7; ++set) {
+      sweeps(true);
+      for (size_t n = 0; n + 1 < parts.size(); n += 2) upd(parts[n].second + 1);
+      if (set == 6) break;  // the merge: local sweeps and updates at every boundary
+      sweeps(false);
+      for (size_t n = 1; n + 1 < parts.size(); n += 2) upd(parts[n].second + 1);
+    }
+    for (size_t n = 1; n + 1 < parts.size(); n += 2) upd(parts[n].second + 1);
+    return;
+  }
   for (int sw = 0; sw < 6; ++sw) {
     if (schedule == MPO_SCHED_SERIAL) {
       const int skip = sw == 0 ? first_bond : 0;  // a resumed first sweep starts later
@@ -893,7 +938,9 @@ void carve(Ctx& X, Carver& cv) {
     P.nu_dev = cv.take<double>(2);
     P.rk = X.o.tau > 0.0 ? cv.take<int>((size_t)L + 1) : nullptr;
   }
-  const size_t nscr = X.o.schedule == MPO_SCHED_SERIAL ? 1 : max_bonds * X.pairs.size();
+  const size_t nscr = X.o.schedule == MPO_SCHED_SERIAL     ? 1
+                      : X.o.schedule == MPO_SCHED_PARALLEL ? X.parts.size()
+                                                           : max_bonds * X.pairs.size();
   X.scratch.resize(nscr);
   const long long nm = all.nm_max, kx = all.kmax, rx = all.rmax;
   for (auto& B : X.scratch) {
@@ -1026,14 +1073,14 @@ void add_hhqr(Ctx& X, Program& P, double* Xm, int n, int k, double* Qout) {
 
 // Left-orthogonalization (Alg. 5 preprocessing) of one MPO held in `cores`,
 // whose input bond dims are `chi_in`; `out_dims` are the clipped dims.
-// QR sweep over sites 0 .. stop-1 of `cores` (bond dims `cur`, updated):
-// each core left-orthogonalized by a shifted Cholesky-QR3 with R carried into
-// the next core, or clipped (identity core, everything carried) where it has
+// QR sweep over sites start .. stop-1 of `cores` (bond dims `cur`, updated):
+// each core left-orthogonalized by Householder QR with R carried into the
+// next core, or clipped (identity core, everything carried) where it has
 // fewer rows than columns.
 void rec_qr_sweep(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores, std::vector<int>& cur,
-                  int stop) {
+                  int stop, int start = 0) {
   const int dd = S.dd;
-  for (int i = 0; i < stop; ++i) {
+  for (int i = start; i < stop; ++i) {
     const int p = cur[i] * dd, q = cur[i + 1];
     const int nn = dd * cur[i + 2];  // columns of the next core (its right bond untouched yet)
     if (p >= q) {
@@ -1051,12 +1098,12 @@ void rec_qr_sweep(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores,
   }
 }
 
-// RQ sweep over sites L-1 .. stop+1 of C (bond dims `cur`, updated): each
-// core right-orthogonalized (X^T = Q R, X = R^T Q^T) with R^T carried into
-// the previous core, or clipped.
-void rec_rq_sweep(Ctx& X, Program& P, PairState& S, std::vector<int>& cur, int stop) {
+// RQ sweep over sites start .. stop+1 of C (start < 0: from L-1; bond dims
+// `cur`, updated): each core right-orthogonalized (X^T = Q R, X = R^T Q^T)
+// with R^T carried into the previous core, or clipped.
+void rec_rq_sweep(Ctx& X, Program& P, PairState& S, std::vector<int>& cur, int stop, int start = -1) {
   const int L = S.L, dd = S.dd;
-  for (int j = L - 1; j > stop; --j) {
+  for (int j = start < 0 ? L - 1 : start; j > stop; --j) {
     const int p = cur[j], q = dd * cur[j + 1];
     const int mp = cur[j - 1] * dd;  // rows of the previous core
     if (p <= q) {
@@ -1604,6 +1651,169 @@ void rec_half_step(Ctx& X, Program& P, int q) {
   for (auto& b : bj) b.P->cC[b.i + 1] = b.r;
 }
 
+// ------------------------------------------------------------------ parallel schedule
+// Site-canonical parallel fit (Sec. 4, variant II) on one device: every
+// sub-TT is one member of a grouped update.  A bond of a group is updated
+// in one of four modes: forward (Alg. 3: C_i = U, C_{i+1} = S V^T, L_{i+1}),
+// backward (C_i = U S, C_{i+1} = V^T, R_{i+1}), a connection between two
+// sub-TTs' centres (C_i = U S for the left one, C_{i+1} = S V^T for the
+// right one, both L_{i+1} and R_{i+1} rebuilt: each sub-TT keeps its own
+// gauge), or forward with a fresh right extension (the merge's first level).
+struct ParBond {
+  int i;     // 0-based bond: sites i, i+1
+  int mode;  // 0 forward, 1 backward, 2 connection, 3 forward with a fresh XR
+};
+
+// Second half of a connection (after the forward assignment left C_i = U,
+// S V^T in SVt, C_{i+1} = S V^T and L_{i+1}): V = (S V^T)^T S^-1 (zero for
+// dropped values), re-orthonormalized as in the backward assignment,
+// R_{i+1} = V^T XR, then C_i = U S.
+void rec_assign_conn(Ctx& X, Program& P, std::vector<BondJob>& bj) {
+  std::vector<PermDesc> tp;
+  std::vector<ScaleDesc> sv, us;
+  std::vector<CholQRJob> orth;
+  std::vector<GemmJob> envg;
+  double fenv = 0;
+  long long maxsc = 1;
+  for (auto& b : bj) {
+    PairState& S = *b.P;
+    BondScratch& B = *b.B;
+    const int i = b.i, r = b.r, N = S.cA[i + 1] * S.cB[i + 1];
+    tp.push_back(perm4(B.SVt, 0, B.V, 0, {1, 1, r, b.m}, {0, 0, b.m, 1}, {0, 0, 1, r}));
+    sv.push_back(ScaleDesc{B.V, B.V, b.m, r, r, r, nullptr, B.S, 0, 1});
+    CholQRJob oj{B.V, b.m, r, r, B.G, B.R, nullptr, B.Y2};
+    oj.keep = B.keep;
+    orth.push_back(oj);
+    envg.push_back(GemmJob{r, N, b.m, op64(B.V, false, r), opW(X, S.XR[i], false, N, S.amXR[i]),
+                           outW(X, S.Renv[i + 1], N, S.amR[i + 1])});
+    fenv += 2.0 * r * N * b.m;
+    us.push_back(ScaleDesc{S.C64[i], S.C64[i], b.n, r, r, r, nullptr, B.S, 0, 0});
+    maxsc = std::max(maxsc, (long long)std::max(b.n, b.m) * r);
+  }
+  add_perm(P, tp, "copy");
+  add_simple(P, LK::Scale, sv, maxsc, "scale");
+  add_cholqr(X, P, orth, 1, true, true);
+  add_gemm(P, X.sb, X.wmode, envg, "env_update", fenv);
+  add_simple(P, LK::Scale, us, maxsc, "scale");
+}
+
+// One group of bond updates of the parallel schedule (at most one per
+// sub-TT, so no two share an environment): the fresh extensions (XL for
+// modes 0, 2, 3; XR for 1, 2, 3: the ones a mode needs on both sides go in
+// a second pair of launches, as each bond has one first-step scratch), the
+// factorizations with Omega of stream 4 * set + stream_add, the
+// assignments.
+void rec_par_group(Ctx& X, Program& P, PairState& S, const std::vector<ParBond>& bonds, int stream_add) {
+  if (bonds.empty()) return;
+  std::vector<GemmJob> e1, e2, e1m, e2m;
+  std::vector<unsigned*> slots, slots2;
+  double f1 = 0, f2 = 0, f1m = 0, f2m = 0;
+  std::vector<BondJob> bj;
+  for (size_t q = 0; q < bonds.size(); ++q) {
+    BondScratch& B = X.scratch.at(q);
+    const int i = bonds[q].i, mode = bonds[q].mode;
+    if (mode != 1) {  // XL in the first pair
+      e1.push_back(job_e1(X, S, i, B.T, B.amT));
+      e2.push_back(job_e2(X, S, i, B.T, B.amT));
+      f1 += flops_e1(S, i);
+      f2 += flops_e2(S, i);
+      slots.insert(slots.end(), {B.amT, S.amXL[i], S.amL[i + 1]});
+    }
+    if (mode != 0) {  // XR: alone in the first pair, after XL in the second
+      auto& a = mode == 1 ? e1 : e1m;
+      auto& c = mode == 1 ? e2 : e2m;
+      a.push_back(job_e1m(X, S, i + 1, B.T, B.amT));
+      c.push_back(job_e2m(X, S, i + 1, B.T, B.amT));
+      (mode == 1 ? f1 : f1m) += flops_e1m(S, i + 1);
+      (mode == 1 ? f2 : f2m) += flops_e2m(S, i + 1);
+      auto& sl = mode == 1 ? slots : slots2;
+      sl.insert(sl.end(), {B.amT, S.amXR[i], S.amR[i + 1]});
+    }
+    bj.push_back(make_bond(X, S, 0, i, mode != 1, B));
+  }
+  rec_reset_amax(X, P, slots);
+  add_gemm(P, X.sb, X.wmode, e1, "env_ext1", f1);
+  add_gemm(P, X.sb, X.wmode, e2, "env_ext2", f2);
+  if (!e1m.empty()) {
+    rec_reset_amax(X, P, slots2);
+    add_gemm(P, X.sb, X.wmode, e1m, "env_ext1", f1m);
+    add_gemm(P, X.sb, X.wmode, e2m, "env_ext2", f2m);
+  }
+  rec_factor(X, P, bj, 4, stream_add, false);
+  std::vector<BondJob> fw, bw, cn;
+  for (size_t q = 0; q < bonds.size(); ++q) {
+    (bonds[q].mode == 1 ? bw : fw).push_back(bj[q]);
+    if (bonds[q].mode == 2) cn.push_back(bj[q]);
+  }
+  if (!fw.empty()) rec_assign_site(X, P, fw);
+  if (!bw.empty()) rec_assign_site(X, P, bw);
+  if (!cn.empty()) rec_assign_conn(X, P, cn);
+  for (auto& b : bj) S.cC[b.i + 1] = b.r;
+}
+
+// Phase q of a set: 0 every F sub-TT sweeps forward over its inner bonds and
+// every B one backward (in lockstep, one group per step), 1 the F|B
+// connections, 2 F backward and B forward, 3 the B|F connections.
+void rec_par_phase(Ctx& X, Program& P, PairState& S, int q, int stream_add) {
+  const auto& parts = X.parts;
+  const int np = (int)parts.size();
+  if (q == 0 || q == 2) {
+    int steps = 0;
+    for (auto& p : parts) steps = std::max(steps, p.second - p.first);
+    for (int k = 0; k < steps; ++k) {
+      std::vector<ParBond> bonds;
+      for (int n = 0; n < np; ++n) {
+        const int s = parts[n].first, e = parts[n].second;
+        if (k >= e - s) continue;
+        const bool fwd = (n % 2 == 0) == (q == 0);
+        bonds.push_back(ParBond{fwd ? s + k : e - 1 - k, fwd ? 0 : 1});
+      }
+      rec_par_group(X, P, S, bonds, stream_add);
+    }
+  } else {
+    std::vector<ParBond> bonds;
+    for (int n = q == 1 ? 0 : 1; n + 1 < np; n += 2) bonds.push_back(ParBond{parts[n].second, 2});
+    rec_par_group(X, P, S, bonds, stream_add);
+  }
+}
+
+// The binary merge: phase 0 once more (stream 4 n_sets), forward updates
+// at every F|B boundary with a fresh XR (level 1: each pair of sub-TTs
+// becomes one site-canonical train, centre right of the boundary), then
+// level t >= 2 joins adjacent groups of 2^(t-1) sub-TTs: QR sweep of the
+// left group from its centre to the boundary and its left environments,
+// RQ sweep of the right group from its centre back to the boundary and its
+// right environments, one forward update at the boundary (stream
+// 4 n_sets + t).
+void rec_par_merge(Ctx& X, Program& P, PairState& S) {
+  const auto& parts = X.parts;
+  const int np = (int)parts.size();
+  rec_par_phase(X, P, S, 0, 0);
+  std::vector<ParBond> first;
+  for (int n = 0; n + 1 < np; n += 2) first.push_back(ParBond{parts[n].second, 3});
+  rec_par_group(X, P, S, first, 1);
+  int level = 2;
+  for (int size = 2; size < np; size *= 2, ++level) {
+    for (int g = 0; g < np; g += 2 * size) {
+      const int m = parts[g + size - 1].second;
+      const int ol = parts[g + size / 2 - 1].second + 1;
+      const int orr = parts[g + size + size / 2 - 1].second + 1;
+      BondScratch& B = X.scratch[0];
+      rec_qr_sweep(X, P, S, S.C64, S.cC, m, ol);
+      for (int i = ol; i < m; ++i) {
+        rec_reset_amax(X, P, {B.amT, S.amXL[i], S.amL[i + 1]});
+        rec_left_env_from_core(X, P, S, i, S.C64[i], S.cC[i + 1], B);
+      }
+      rec_rq_sweep(X, P, S, S.cC, m + 1, orr);
+      for (int j = orr; j >= m + 1; --j) {
+        rec_reset_amax(X, P, {B.amT, S.amXR[j - 1], S.amR[j]});
+        rec_right_env_from_core(X, P, S, j, j >= m + 2, B);
+      }
+      rec_par_group(X, P, S, {ParBond{m, 0}}, level);
+    }
+  }
+}
+
 std::string shape_key(const Ctx& X, const char* tag) {
   std::string k(tag);
   for (auto& P : X.pairs)
@@ -1666,7 +1876,16 @@ void rec_init_pair(Ctx& X, Program& P, PairState& S, int pair) {
   const bool backward_first = serial && X.o.first_sweep % 2 == 1;
   const int i0 = !serial || X.o.first_bond == 0 ? -1
                  : backward_first ? L - 2 - X.o.first_bond : X.o.first_bond;
-  if (i0 >= 0) {
+  if (X.o.schedule == MPO_SCHED_PARALLEL) {
+    // every sub-TT starts from the guess in the mixed canonical form centred
+    // on it: right-orthogonalized, then left-orthogonalized (the left
+    // environments are built from this form below), then right-
+    // orthogonalized again (the right ones)
+    std::vector<int> cur(S.C_in.empty() ? S.cA : S.chiC_in);
+    rec_rq_sweep(X, P, S, cur, 0);
+    rec_qr_sweep(X, P, S, S.C64, cur, L - 1);
+    check_dims(cur, S.cC, "parallel initialization");
+  } else if (i0 >= 0) {
     rec_mixed_orth(X, P, S, i0);
   } else if (backward_first) {
     std::vector<int> in(S.C_in.empty() ? S.cA : S.chiC_in);
@@ -1689,7 +1908,13 @@ void rec_init_pair(Ctx& X, Program& P, PairState& S, int pair) {
     (void)pair;
     return;
   }
-  if (i0 >= 0 && !backward_first) {  // forward from bond i0: left envs up to it, right side cached
+  if (X.o.schedule == MPO_SCHED_PARALLEL) {  // isometric environments on both sides
+    for (int i = 0; i + 1 < L; ++i) rec_left_env_from_core(X, P, S, i, S.C64[i], S.cC[i + 1], X.scratch[0]);
+    std::vector<int> cur(S.cC);
+    rec_rq_sweep(X, P, S, cur, 0);
+    check_dims(cur, S.cC, "parallel initialization");
+    for (int j = L - 1; j >= 1; --j) rec_right_env_from_core(X, P, S, j, j >= 2, X.scratch[0]);
+  } else if (i0 >= 0 && !backward_first) {  // forward from bond i0: left envs up to it, right side cached
     for (int i = 0; i < i0; ++i) rec_left_env_from_core(X, P, S, i, S.C64[i], S.cC[i + 1], X.scratch[0]);
     for (int j = L - 1; j >= i0 + 1; --j) rec_right_env_from_core(X, P, S, j, j >= i0 + 2, X.scratch[0]);
   } else if (i0 >= 0) {  // backward from bond i0: right envs down to it, left side cached
@@ -1723,7 +1948,14 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
     throw Error{MPO_ERR_UNSUPPORTED, "chi_max + sketch_p above 512"};
   if (!(o->tau >= 0.0 && o->tau < INFINITY)) throw Error{MPO_ERR_INVALID_ARG, "tau must be finite and >= 0"};
   if (o->precision < 0 || o->precision > 3) throw Error{MPO_ERR_INVALID_ARG, "bad precision"};
-  if (o->schedule < 0 || o->schedule > 1) throw Error{MPO_ERR_INVALID_ARG, "bad schedule"};
+  if (o->schedule < 0 || o->schedule > 2) throw Error{MPO_ERR_INVALID_ARG, "bad schedule"};
+  if (o->schedule == MPO_SCHED_PARALLEL) {
+    if (o->n_parts < 2 || (o->n_parts & (o->n_parts - 1)))
+      throw Error{MPO_ERR_INVALID_ARG, "parallel schedule: n_parts must be a power of two >= 2"};
+    if (n_pairs != 1) throw Error{MPO_ERR_UNSUPPORTED, "parallel schedule: one pair"};
+    if (o->tau != 0.0 || o->first_sweep != 0 || o->track_error != 0)
+      throw Error{MPO_ERR_UNSUPPORTED, "parallel schedule: tau, first_sweep and track_error must be 0"};
+  }
   if (o->first_sweep < 0 || o->first_sweep > (1 << 24)) throw Error{MPO_ERR_INVALID_ARG, "bad first_sweep"};
   if (o->first_bond < 0) throw Error{MPO_ERR_INVALID_ARG, "bad first_bond"};
   if (o->first_bond > 0 && (o->schedule != MPO_SCHED_SERIAL || n_pairs != 1))
@@ -1771,7 +2003,11 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
     S.chi_max = pr.chi_max > 0 ? pr.chi_max : o->chi_max;
     if (S.chi_max + std::max(o->sketch_p, 0) > 512)
       throw Error{MPO_ERR_UNSUPPORTED, "chi_max + sketch_p above 512"};
-    plan_shapes(S, S.chi_max, o->schedule, o->first_sweep, o->first_bond, o->first_half);
+    if (o->schedule == MPO_SCHED_PARALLEL) {
+      if (L < 2 * o->n_parts) throw Error{MPO_ERR_SHAPE, "parallel schedule: every sub-TT needs two sites"};
+      X.parts = partition_sites(L, o->n_parts);
+    }
+    plan_shapes(S, S.chi_max, o->schedule, o->first_sweep, o->first_bond, o->first_half, o->n_parts);
     if (o->first_bond > L - 2) throw Error{MPO_ERR_INVALID_ARG, "first_bond must be below L - 1"};
     for (int b = 0; b <= L; ++b)
       if (S.capC[b] * S.dd > 2048) throw Error{MPO_ERR_UNSUPPORTED, "two-site dimension above 2048"};
@@ -1803,7 +2039,7 @@ struct SweepPlan {
 
 // Units of a sweep: two-site updates (serial, per pair) or half-steps.
 int sweep_units(const Ctx& X) {
-  return X.o.schedule == MPO_SCHED_EVEN_ODD ? 2 : X.pairs[0].L - 1;
+  return X.o.schedule == MPO_SCHED_EVEN_ODD ? 2 : X.o.schedule == MPO_SCHED_PARALLEL ? 4 : X.pairs[0].L - 1;
 }
 
 // Records units [start, start + count) of the current sweep (direction fwd),
@@ -1813,6 +2049,8 @@ int sweep_units(const Ctx& X) {
 void record_segment(Ctx& X, SweepPlan& sp, bool fwd, int start, int count) {
   if (X.o.schedule == MPO_SCHED_EVEN_ODD) {
     for (int q = start; q < start + count; ++q) rec_half_step(X, sp.prog, q);
+  } else if (X.o.schedule == MPO_SCHED_PARALLEL) {
+    for (int q = start; q < start + count; ++q) rec_par_phase(X, sp.prog, X.pairs[0], q, q);
   } else {
     for (size_t p = 0; p < X.pairs.size(); ++p) {
       PairState& S = X.pairs[p];
@@ -3153,6 +3391,7 @@ mpo_status mpo_fit_sweep(mpo_fit_ctx* ctx, int32_t n_sweeps, double* fit_err) {
     Ctx& X = ctx->X;
     if (fit_err && !X.o.track_error)
       throw Error{MPO_ERR_INVALID_ARG, "fit_err needs a context created with opts.track_error = 1"};
+    if (X.merged) throw Error{MPO_ERR_UNSUPPORTED, "the parallel fit has been merged"};
     HIP_OK(hipEventRecord(X.ev0, X.stream));
     X.prof.clear();
     for (int s = 0; s < n_sweeps; ++s) {
@@ -3177,6 +3416,7 @@ mpo_status mpo_fit_updates(mpo_fit_ctx* ctx, int32_t n_units) {
     Ctx& X = ctx->X;
     if (X.o.schedule == MPO_SCHED_SERIAL && X.pairs.size() != 1 && n_units % sweep_units(X) != 0)
       throw Error{MPO_ERR_UNSUPPORTED, "single updates need one pair"};
+    if (X.merged) throw Error{MPO_ERR_UNSUPPORTED, "the parallel fit has been merged"};
     X.prof.clear();
     HIP_OK(hipEventRecord(X.ev0, X.stream));
     while (n_units > 0) {
@@ -3209,11 +3449,37 @@ mpo_status mpo_fit_bond_dims(const mpo_fit_ctx* ctx, int32_t pair, int32_t* chi_
   });
 }
 
+mpo_status mpo_fit_merge(mpo_fit_ctx* ctx) {
+  return guarded([&] {
+    if (!ctx) throw Error{MPO_ERR_INVALID_ARG, "null ctx"};
+    Ctx& X = ctx->X;
+    if (X.o.schedule != MPO_SCHED_PARALLEL) throw Error{MPO_ERR_UNSUPPORTED, "merge: parallel schedule only"};
+    if (X.merged) throw Error{MPO_ERR_UNSUPPORTED, "the parallel fit has been merged"};
+    if (X.pos != 0) throw Error{MPO_ERR_UNSUPPORTED, "merge: the fit stands inside a set"};
+    Program P;
+    rec_par_merge(X, P, X.pairs[0]);
+    const size_t keep = X.arena_used;
+    upload(X, P);
+    HIP_OK(hipEventRecord(X.ev0, X.stream));
+    run_program(P, X.stream, nullptr);
+    HIP_OK(hipEventRecord(X.ev1, X.stream));
+    HIP_OK(hipStreamSynchronize(X.stream));
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, X.ev0, X.ev1));
+    X.last_ms = ms;
+    X.arena_used = keep;
+    X.merged = true;
+    check_flags(X);
+  });
+}
+
 mpo_status mpo_fit_export_c(mpo_fit_ctx* ctx, int32_t pair, double* const* c_cores) {
   return guarded([&] {
     if (!ctx || !c_cores) throw Error{MPO_ERR_INVALID_ARG, "null argument"};
     Ctx& X = ctx->X;
     if (pair < 0 || pair >= (int)X.pairs.size()) throw Error{MPO_ERR_INVALID_ARG, "bad pair"};
+    if (X.o.schedule == MPO_SCHED_PARALLEL && !X.merged)
+      throw Error{MPO_ERR_UNSUPPORTED, "the parallel fit's sub-TTs disagree in gauge until mpo_fit_merge"};
     PairState& S = X.pairs[pair];
     Program P;
     std::vector<PermDesc> ds;

@@ -88,6 +88,27 @@ def test_tau_workspace_adds_the_rank_slots(schedule):
     assert st0 == 0 and st1 == 0 and n0 < n1 <= n0 + 64 * 1024
 
 
+@pytest.mark.parametrize("n_parts", [2, 4])
+def test_parallel_workspace_query_ok(n_parts):
+    st, n = _query([_Pair(L=8)], _opts(schedule=2, n_parts=n_parts))
+    assert st == 0 and n > 0 and n % 256 == 0
+
+
+@pytest.mark.parametrize("kw, pairs, status", [
+    (dict(n_parts=0), 1, 1),          # n_parts must be a power of two >= 2
+    (dict(n_parts=3), 1, 1),
+    (dict(n_parts=4), 2, 6),          # one pair
+    (dict(n_parts=2, tau=0.5), 1, 6),
+    (dict(n_parts=2, track_error=1), 1, 6),
+    (dict(n_parts=2, first_sweep=1), 1, 6),
+    (dict(n_parts=4), 1, 2),          # L = 6 < 2 * 4 sites
+])
+def test_parallel_bad_options(kw, pairs, status):
+    st, _ = _query([_Pair() for _ in range(pairs)], _opts(schedule=2, **kw))
+    assert st == status
+    assert _lib().mpo_last_error()
+
+
 def test_workspace_grows_with_pairs_and_bond():
     _, one = _query([_Pair()], _opts())
     _, two = _query([_Pair(), _Pair()], _opts())
@@ -101,6 +122,7 @@ def test_workspace_grows_with_pairs_and_bond():
     (dict(tau=float("nan")), 1),
     (dict(precision=9), 1),
     (dict(schedule=5), 1),
+    (dict(schedule=3), 1),
     (dict(chi_max=0), 1),
     (dict(chi_max=500, sketch_p=16), 6),
 ])
