@@ -86,12 +86,13 @@ template <DType T> struct DT;
 template <> struct DT<DType::F64> { using type = double; };
 template <> struct DT<DType::F32> { using type = float; };
 
-// FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
-__device__ __forceinline__ unsigned short f2bf(float x) {
-  unsigned u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (unsigned short)((u >> 16) | 0x40);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+// FP32 -> BF16 bits, round to nearest even: the hardware conversion
+// (v_cvt_pk_bf16_f32 on gfx950), two values per instruction.
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned short f2bf(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
+__device__ __forceinline__ unsigned f2bf2(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2v{a, b}, bf16x2v));
 }
 
 // Exponent e with 2^e <= amax < 2^(e+1); 0 for amax == 0.
@@ -111,17 +112,13 @@ __device__ __forceinline__ typename ModeT<MODE>::lds_t to_lds(T v, float inv_sca
   else return f2bf((float)v * inv_scale);
 }
 
-// low part of the BF16 split of a scaled value: bf16(x - hi)
-template <typename T>
-__device__ __forceinline__ unsigned short lo_part(T v, float inv_scale) {
-  const float x = (float)v * inv_scale;
-  return f2bf(x - bf2f(f2bf(x)));
-}
-
-
 // Loads a (ROWS x BK) operand tile into registers in the stored type; the
 // conversion to the LDS type (and the BF16 scale) happens at the LDS store.
-template <typename T, bool KCONTIG, int ROWS, int BK>
+// RT (BF16 modes, operand rows contiguous in memory): each thread loads four
+// consecutive k of one row (lanes take consecutive rows, so every load is
+// coalesced across the wave) and stores them as one packed 8-byte LDS write
+// into the row-major [row][k] tile the BF16 MFMA reads.
+template <typename T, bool KCONTIG, int ROWS, int BK, bool RT = false>
 struct TileLoader {
   static constexpr int NV = ROWS * BK / 4 / kThreads;  // 4-wide loads per thread
   static_assert(NV >= 1, "tile too small");
@@ -133,7 +130,15 @@ struct TileLoader {
     for (int i = 0; i < NV; ++i) {
       int idx = threadIdx.x + kThreads * i;
       int r, k;
-      if constexpr (KCONTIG) {
+      if constexpr (RT) {
+        r = idx % ROWS;
+        k = k0 + 4 * (idx / ROWS);
+        const GAS T* g = gload_ptr(base + (long long)k * ld + r);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          v[i][j] = (r < rows_valid && k + j < kend) ? g[(long long)j * ld] : T(0);
+        continue;
+      } else if constexpr (KCONTIG) {
         r = idx / (BK / 4);
         k = k0 + 4 * (idx % (BK / 4));
       } else {
@@ -186,26 +191,28 @@ struct TileLoader {
           *reinterpret_cast<doublex2*>(q + 2) =
               doublex2{to_lds<MODE>(v[i][2], inv_scale), to_lds<MODE>(v[i][3], inv_scale)};
         }
+      } else if constexpr (MODE == Mode::BF16 || MODE == Mode::BF16X3) {
+        static_assert(KCONTIG || RT, "BF16 operands are staged row-major");
+        const int r = RT ? idx % ROWS : idx / (BK / 4);
+        const int k = RT ? 4 * (idx / ROWS) : 4 * (idx % (BK / 4));
+        float x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = (float)v[i][j] * inv_scale;
+        const unsigned h0 = f2bf2(x[0], x[1]), h1 = f2bf2(x[2], x[3]);
+        *reinterpret_cast<uint2*>(lds + r * ldl + k) = uint2{h0, h1};
+        if constexpr (MODE == Mode::BF16X3) {  // lo = bf16(x - hi)
+          const float l0 = x[0] - __uint_as_float(h0 << 16), l1 = x[1] - __uint_as_float(h0 & 0xffff0000u);
+          const float l2 = x[2] - __uint_as_float(h1 << 16), l3 = x[3] - __uint_as_float(h1 & 0xffff0000u);
+          *reinterpret_cast<uint2*>(lds_lo + r * ldl + k) = uint2{f2bf2(l0, l1), f2bf2(l2, l3)};
+        }
       } else if constexpr (KCONTIG) {
         int r = idx / (BK / 4);
         int k = 4 * (idx % (BK / 4));
         L* q = lds + r * ldl + k;
 #pragma unroll
         for (int j = 0; j < 4; ++j) q[j] = to_lds<MODE>(v[i][j], inv_scale);
-        if constexpr (MODE == Mode::BF16X3) {
-          L* ql = lds_lo + r * ldl + k;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) ql[j] = lo_part(v[i][j], inv_scale);
-        }
       } else {
-        int k = idx / (ROWS / 4);
-        int r = 4 * (idx % (ROWS / 4));
-#pragma unroll
-        for (int j = 0; j < 4; ++j) lds[(r + j) * ldl + k] = to_lds<MODE>(v[i][j], inv_scale);
-        if constexpr (MODE == Mode::BF16X3) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) lds_lo[(r + j) * ldl + k] = lo_part(v[i][j], inv_scale);
-        }
+        static_assert(KCONTIG, "row-contiguous FP32 / FP64 operands are staged k-major");
       }
     }
   }
@@ -283,8 +290,9 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = accv_t{0, 0, 0, 0};
 
-  TileLoader<TA, AK, BM, BK> la;
-  TileLoader<TB, BKC, BN, BK> lb;
+  constexpr bool BF = MODE == Mode::BF16 || MODE == Mode::BF16X3;
+  TileLoader<TA, AK, BM, BK, BF && !AK> la;
+  TileLoader<TB, BKC, BN, BK, BF && !BKC> lb;
   const int nslab = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
 
   if (nslab > 0) {
