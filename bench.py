@@ -260,10 +260,10 @@ def batched_section(steps):
     res = {}
     # one pair, L=64 chi=128 chi_C=256, all bonds of one parity per launch
     A4, B4 = make_pair(64, 2, 128, seed=0, decay=True)
-    table = autotune([(A4, B4)], 256, precision="fp32", schedule="even_odd", sketch_p=16, reps=2)
-    for prec in ("fp32", "bf16x3"):
+    for prec in ("fp32", "bf16", "bf16x3"):
+        table = autotune([(A4, B4)], 256, precision=prec, schedule="even_odd", sketch_p=16, reps=2)
         wl, _, _, bd = run_gpu(A4, B4, prec, 16, steps, 2, schedule="even_odd", chi_c=256,
-                               tuning=table if prec == "fp32" else None)
+                               tuning=table)
         fb = batched_sweep_flops(64, 2, 128, bd)
         res[f"even_odd_L64_chi128_{prec}"] = {
             "sweeps_per_s": round(steps / wl, 3), "ms_per_sweep": round(wl / steps * 1e3, 3),
