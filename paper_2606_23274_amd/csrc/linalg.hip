@@ -1689,7 +1689,125 @@ __global__ void __launch_bounds__(kBig) orgqr_kernel(const OrgqrDesc* __restrict
     if (sgn[c] < 0.0 && c2 >= c) R[(long long)c * d.ldr + c2] = -R[(long long)c * d.ldr + c2];
   }
 }
+
+// Householder QR with the explicit Q in one kernel, X (m x n, m >= n)
+// resident in LDS (row pitch n + 1, which spreads a column over the banks):
+// the reflectors as in geqr_kernel; R (upper n x n) and tau out; then Q =
+// H_0 ... H_{n-1} [I; 0] formed in place of the reflectors, last reflector
+// first (LAPACK's backward accumulation: apply H_j to the columns right of
+// j, then column j becomes -tau_j v_j with 1 - tau_j on the diagonal and
+// zeros above); the signs as in orgqr_kernel.  Each reflector's products
+// with the columns it acts on are sums over contiguous row blocks in row
+// order, then over the blocks in order.
+__device__ __forceinline__ void hh_apply_lds(double* A, int lda, int j, int m, int c0, int nc, double tau,
+                                             double* wpart, double* wv) {
+  const int tid = threadIdx.x;
+  const int per = min(kBig / nc, 16);  // row blocks per column: a short in-order sum of the partials
+  if (tid < nc * per) {
+    const int c = c0 + tid % nc, r0 = tid / nc;
+    const int rows = m - j - 1, blk = (rows + per - 1) / per;
+    const int i0 = j + 1 + r0 * blk, i1 = min(m, i0 + blk);
+    double s = r0 == 0 ? A[j * lda + c] : 0.0;
+    for (int i = i0; i < i1; ++i) s = fma(A[i * lda + j], A[i * lda + c], s);
+    wpart[tid] = s;
+  }
+  __syncthreads();
+  if (tid < nc) {
+    double w = 0.0;
+    for (int q = 0; q < per; ++q) w += wpart[q * nc + tid];
+    wv[tid] = tau * w;
+  }
+  __syncthreads();
+  const int tot = (m - j) * nc;
+  for (int e = tid; e < tot; e += kBig) {
+    const int i = j + e / nc, cc = e % nc;
+    const double vi = i == j ? 1.0 : A[i * lda + j];
+    A[i * lda + c0 + cc] = fma(-vi, wv[cc], A[i * lda + c0 + cc]);
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kBig) hhqr_lds_kernel(const HhqrDesc* __restrict__ descs) {
+  extern __shared__ double A[];
+  __shared__ double red[kBig / 64];
+  __shared__ double wpart[kBig], wv[kBig], taus[kBig];
+  __shared__ signed char sgn[kBig];
+  const HhqrDesc d = descs[blockIdx.x];
+  const int m = d.m, n = d.n, lda = n + 1;
+  const GAS double* X = gload_ptr(d.X);
+  for (int e = threadIdx.x; e < m * n; e += kBig) A[(e / n) * lda + e % n] = X[(long long)(e / n) * d.ldx + e % n];
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double ss = 0.0;
+    for (int i = j + 1 + threadIdx.x; i < m; i += kBig) ss = fma(A[i * lda + j], A[i * lda + j], ss);
+    ss = block_sum<kBig / 64>(ss, red);
+    const double alpha = A[j * lda + j];
+    double beta = alpha, tau = 0.0, scal = 0.0;
+    if (ss > 0.0) {
+      const double nrm = sqrt(fma(alpha, alpha, ss));
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    __syncthreads();  // every thread has read alpha
+    for (int i = j + 1 + threadIdx.x; i < m; i += kBig) A[i * lda + j] *= scal;
+    if (threadIdx.x == 0) {
+      A[j * lda + j] = beta;
+      taus[j] = tau;
+    }
+    __syncthreads();
+    if (tau != 0.0 && j + 1 < n) hh_apply_lds(A, lda, j, m, j + 1, n - j - 1, tau, wpart, wv);
+  }
+  // R (signs normalized so that diag(R) >= 0) and tau out
+  for (int c = threadIdx.x; c < n; c += kBig) {
+    sgn[c] = A[c * lda + c] < 0.0 ? -1 : 1;
+    if (d.tau) gstore_ptr(d.tau)[c] = taus[c];
+  }
+  __syncthreads();
+  GAS double* R = gstore_ptr(d.R);
+  for (int e = threadIdx.x; e < n * n; e += kBig) {
+    const int i = e / n, c = e % n;
+    R[(long long)i * d.ldr + c] = c >= i ? (double)sgn[i] * A[i * lda + c] : 0.0;
+  }
+  __syncthreads();
+  // Q in place of the reflectors
+  for (int j = n - 1; j >= 0; --j) {
+    const double t = taus[j];
+    if (j + 1 < n && t != 0.0) hh_apply_lds(A, lda, j, m, j + 1, n - j - 1, t, wpart, wv);
+    for (int i = threadIdx.x; i < m; i += kBig) {
+      double& a = A[i * lda + j];
+      a = i < j ? 0.0 : i == j ? 1.0 - t : -t * a;
+    }
+    __syncthreads();
+  }
+  GAS double* Q = gstore_ptr(d.Q);
+  for (int e = threadIdx.x; e < m * n; e += kBig) {
+    const int i = e / n, c = e % n;
+    Q[(long long)i * d.ldq + c] = (double)sgn[c] * A[i * lda + c];
+  }
+}
 }  // namespace
+
+size_t hhqr_lds_bytes(int m, int n) { return (size_t)m * (n + 1) * sizeof(double); }
+
+bool hhqr_fits_lds(int m, int n) {
+  static int limit = -1;
+  if (limit < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 0;
+    limit = v;
+  }
+  // static LDS of the kernel: the reduction slots, three kBig vectors, the signs
+  const size_t fixed = (kBig / 64 + 3 * kBig) * sizeof(double) + kBig;
+  return n <= kBig && m >= n && hhqr_lds_bytes(m, n) + fixed <= (size_t)limit;
+}
+
+void launch_hhqr(const HhqrDesc* d, int n, int max_m, int max_n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(hhqr_lds_kernel, dim3(n), dim3(kBig), hhqr_lds_bytes(max_m, max_n), s, d);
+}
 
 void launch_orgqr(const OrgqrDesc* d, int n, hipStream_t s) {
   if (n <= 0) return;

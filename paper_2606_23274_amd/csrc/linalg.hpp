@@ -101,6 +101,20 @@ struct OrgqrDesc {
 };
 void launch_geqr(const GeqrDesc* d, int n, hipStream_t s);
 void launch_orgqr(const OrgqrDesc* d, int n, hipStream_t s);
+// Both in one kernel with X resident in LDS (when hhqr_fits_lds(m, n) for
+// every problem of the launch; max_m, max_n size the LDS): R (diag >= 0),
+// tau (nullable) and Q out, X left unchanged.
+struct HhqrDesc {
+  const double* X;
+  int m, n, ldx;
+  double* tau;
+  double* Q;
+  int ldq;
+  double* R;
+  int ldr;
+};
+bool hhqr_fits_lds(int m, int n);
+void launch_hhqr(const HhqrDesc* d, int n, int max_m, int max_n, hipStream_t s);
 
 size_t eig_work_doubles(int k, int r);
 // Panel reduction of the global-memory path: widest panel, the panel width

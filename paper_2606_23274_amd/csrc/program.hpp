@@ -14,7 +14,7 @@
 
 namespace mpofit {
 
-enum class LK { Gemm, Chol, Trsm, Eig, Omega, Sign, Scale, Perm, Sval, Fill, Norm, Bump, Jacobi, NormBig, Geqr, Naive, Polish, Orgqr, Trunc };
+enum class LK { Gemm, Chol, Trsm, Eig, Omega, Sign, Scale, Perm, Sval, Fill, Norm, Bump, Jacobi, NormBig, Geqr, Naive, Polish, Orgqr, Trunc, Hhqr };
 
 struct Launch {
   LK kind;

@@ -54,6 +54,7 @@ void run_program(const Program& p, hipStream_t s, hipEvent_t* ev) {
       case LK::Geqr: launch_geqr(p.device<GeqrDesc>(l), l.n, s); break;
       case LK::Orgqr: launch_orgqr(p.device<OrgqrDesc>(l), l.n, s); break;
       case LK::Trunc: launch_trunc(p.device<TruncDesc>(l), l.n, s); break;
+      case LK::Hhqr: launch_hhqr(p.device<HhqrDesc>(l), l.n, (int)l.maxa, l.maxb, s); break;
       case LK::Naive: launch_naive(p.device<NaiveDesc>(l), l.n, l.maxa, s); break;
       case LK::Polish: launch_polish(p.device<PolishDesc>(l), l.n, (int)l.maxa, s); break;
       case LK::NormBig: {
@@ -1064,8 +1065,24 @@ double flops_e2m(const PairState& P, int j) { return 2.0 * P.cC[j + 1] * P.dd * 
 // the squared condition number of the first pass, Householder QR keeps
 // the small singular directions of the graded factors that the sweeps
 // carry from core to core, which the inverse gauge then divides by.
+void add_hhqr_group(Program& P, const std::vector<HhqrDesc>& ds, const char* cls) {
+  if (ds.empty()) return;
+  int mm = 1, nn = 1;
+  for (auto& d : ds) { mm = std::max(mm, d.m); nn = std::max(nn, d.n); }
+  add_simple(P, LK::Hhqr, ds, mm, cls);
+  P.launches.back().maxb = nn;
+}
+
+// The one-kernel LDS form when the panel fits, except in the even/odd
+// schedule's initialization: its inverse canonical form amplifies the QR's
+// rounding to about 1e-10 of the resumed half-step (reading 24), which was
+// measured with the two-kernel form (Q applied forward to [I; 0]).
 void add_hhqr(Ctx& X, Program& P, double* Xm, int n, int k, double* Qout) {
   if (n < k) throw Error{MPO_ERR_SHAPE, "Householder QR needs rows >= columns"};
+  if (X.o.schedule != MPO_SCHED_EVEN_ODD && hhqr_fits_lds(n, k)) {  // one kernel, the panel in LDS
+    add_hhqr_group(P, {HhqrDesc{Xm, n, k, k, X.iTau, Qout, k, X.iRt, k}}, "init");
+    return;
+  }
   add_simple(P, LK::Geqr, std::vector<GeqrDesc>{GeqrDesc{Xm, n, k, k, X.iRt, k, X.iTau}}, 0, "init");
   add_simple(P, LK::Orgqr, std::vector<OrgqrDesc>{OrgqrDesc{Xm, n, k, k, X.iTau, Qout, k, X.iRt, k}}, 0,
              "init");
@@ -3270,6 +3287,8 @@ void proj_run(const mpo_tt& in, int32_t k, uint64_t seed, int32_t pair, int32_t 
   std::vector<GemmJob> yj, lj, rj;
   std::vector<GeqrDesc> gq;
   std::vector<OrgqrDesc> oq;
+  std::vector<HhqrDesc> hq;
+  bool fused = true;
   std::vector<PermDesc> cp;
   long long maxom = 1;
   for (int l = 1; l < L; ++l) {
@@ -3286,6 +3305,8 @@ void proj_run(const mpo_tt& in, int32_t k, uint64_t seed, int32_t pair, int32_t 
                          out64(Pl.y[l], kl)});
     gq.push_back(GeqrDesc{Pl.y[l], chi, kl, kl, Pl.R[l], kl, Pl.tau[l]});
     oq.push_back(OrgqrDesc{Pl.y[l], chi, kl, kl, Pl.tau[l], Pl.q[l], kl, Pl.R[l], kl});
+    hq.push_back(HhqrDesc{Pl.y[l], chi, kl, kl, Pl.tau[l], Pl.q[l], kl, Pl.R[l], kl});
+    fused = fused && hhqr_fits_lds(chi, kl);
   }
   for (int i = 0; i < L; ++i) {
     const int cl = in.chi[i], cr = in.chi[i + 1], kl = Pl.k[i], kr = Pl.k[i + 1];
@@ -3304,8 +3325,12 @@ void proj_run(const mpo_tt& in, int32_t k, uint64_t seed, int32_t pair, int32_t 
   }
   add_simple(P, LK::Omega, om, maxom, "project");
   add_gemm(P, X.sb, Mode::F64, yj, "project", 0);
-  add_simple(P, LK::Geqr, gq, 0, "project");
-  add_simple(P, LK::Orgqr, oq, 0, "project");
+  if (fused) {
+    add_hhqr_group(P, hq, "project");
+  } else {
+    add_simple(P, LK::Geqr, gq, 0, "project");
+    add_simple(P, LK::Orgqr, oq, 0, "project");
+  }
   add_gemm(P, X.sb, Mode::F64, lj, "project", 0);
   add_gemm(P, X.sb, Mode::F64, rj, "project", 0);
   add_perm(P, cp, "copy");
