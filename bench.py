@@ -122,20 +122,35 @@ def grad_flops(L, d, chiA, chiB, chiP):
     return t
 
 
+def kernel_source_sha1(source_file, kernel):
+    """SHA-1 of a kernel's definition in its source file: from the line that
+    declares `kernel` (its template line included) to the closing brace at
+    column 0.  None if the definition is not found."""
+    import hashlib
+    import re
+    name = kernel.split("<")[0]
+    with open(os.path.join(ROOT, source_file)) as f:
+        text = f.read()
+    m = re.search(r"(template <[^\n]*>\n)?__global__ void [^\n]*\b" + re.escape(name) + r"\(", text)
+    if not m:
+        return None
+    end = text.find("\n}\n", m.start())
+    return hashlib.sha1(text[m.start():end + 3].encode()).hexdigest() if end >= 0 else None
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     runs (profiles/traffic_*.json), scaled by the copy-probe calibration;
-    None when no such record exists or the kernel's source has changed."""
+    None when no such record exists or the kernel's definition has changed
+    since the counters were taken."""
     import glob
-    import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
         with open(path) as f:
             rec = json.load(f)
         if rec.get("kernel") != kernel:
             continue
-        with open(os.path.join(ROOT, rec["source_file"]), "rb") as f:
-            if hashlib.sha1(f.read()).hexdigest() != rec["source_sha1"]:
-                return None
+        if kernel_source_sha1(rec["source_file"], kernel) != rec.get("kernel_sha1"):
+            return None
         return rec["traffic_bytes_per_dispatch"]
     return None
 
