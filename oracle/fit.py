@@ -148,6 +148,19 @@ class FitResult:
     centre: int = 0  # 0-based site of the orthogonality centre (serial schedule)
 
 
+def default_guess(A1, B1):
+    """The initial guess when none is given (Sec. 2.3.5: one of the two
+    inputs): A, whose legs (A's out, A's in) are C's (A's out, B's in) when
+    A's and B's input legs agree, as for MPO-MPO products; otherwise B,
+    whose legs are then C's: the MPO-MPS variant of Sec. 1, with B an MPS
+    (an MPO with a unit input leg)."""
+    if A1[0].shape[2] == B1[0].shape[2]:
+        return A1
+    if B1[0].shape[1] == A1[0].shape[1]:
+        return B1
+    raise ValueError("neither input has the product's physical legs: pass C_init")
+
+
 def _preprocess(A, B):
     A1, nuA = canon.left_orthogonalize(A)
     B1, nuB = canon.left_orthogonalize(B)
@@ -183,7 +196,7 @@ def fit_serial(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
     many updates (None: the n_sweeps sweeps, the first one partial)."""
     L = len(A)
     A1, B1, nu, caps = _preprocess(A, B)
-    guess = A1 if C_init is None else C_init
+    guess = default_guess(A1, B1) if C_init is None else C_init
     ones = np.ones((1, 1, 1))
     Lenv = [None] * (L + 1)
     Renv = [None] * (L + 2)
@@ -276,7 +289,7 @@ def fit_even_odd(A, B, chi_max, n_sweeps, sketch_p=-1, seed=0, pair=0, tau=0.0,
     its environments); ``n_half_steps`` stops after that many half-steps."""
     L = len(A)
     A1, B1, nu, caps = _preprocess(A, B)
-    C0 = canon.right_orthogonalize(A1 if C_init is None else C_init)
+    C0 = canon.right_orthogonalize(default_guess(A1, B1) if C_init is None else C_init)
     # the guess acts only as an operator: its scale (it enters Lambda, hence
     # Y, of the bonds a half-step leaves alone) is set to one
     C0[0] = C0[0] / np.linalg.norm(C0[0])

@@ -37,8 +37,8 @@ def naive_product(A, B):
     C = []
     for a, b in zip(A, B):
         c = np.einsum("astc,btud->absucd", a, b)
-        ca, d1, d2, cc = a.shape
-        cb, _, _, cd = b.shape
+        ca, d1, _, cc = a.shape
+        cb, _, d2, cd = b.shape  # C's input leg is B's (1 for an MPS)
         C.append(np.ascontiguousarray(c.reshape(ca * cb, d1, d2, cc * cd)))
     return C
 
