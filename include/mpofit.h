@@ -161,6 +161,14 @@ typedef struct {
                           inverse canonical form of the initial guess and
                           its environments; 0 = whole sweeps                */
   int32_t n_parts;     /* parallel schedule: number of sub-TTs; else unused  */
+  int32_t mps;         /* 1: the MPO-MPS product of Sec. 1.  B is an MPS,
+                          stored as an MPO whose input leg has size 1: its
+                          cores are (chi_l, d, 1, chi_r) with B.d = d, and so
+                          are C's (the initial guess's, and the exported
+                          cores); A keeps (chi_l, d, d, chi_r).  The default
+                          initial guess is then B.  Serial and even/odd
+                          schedules, no track_error, no gradient
+                          (MPO_ERR_UNSUPPORTED).  0: MPO-MPO             */
 } mpo_fit_opts;
 
 /* One tuned class of grouped GEMM launches: the operand kind (mode as

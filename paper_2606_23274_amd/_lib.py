@@ -35,7 +35,8 @@ class MpoFitOpts(C.Structure):
                 ("capture_graph", C.c_int32), ("tune", C.POINTER(MpoGemmTune)),
                 ("n_tune", C.c_int32), ("profile", C.c_int32), ("c_init", C.POINTER(MpoTT)),
                 ("first_sweep", C.c_int32), ("track_error", C.c_int32), ("first_bond", C.c_int32),
-                ("first_half", C.c_int32), ("n_parts", C.c_int32)]
+                ("first_half", C.c_int32), ("n_parts", C.c_int32),
+                ("mps", C.c_int32)]
 
 
 class MpoError(RuntimeError):

@@ -43,12 +43,17 @@ class _Setup:
 
     def __init__(self, pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
                  profile, pair_chi_max, tuning, c_init=None, first_sweep=0, track_error=False,
-                 first_bond=0, first_half=0, tau=0.0, n_parts=0):
+                 first_bond=0, first_half=0, tau=0.0, n_parts=0, mps=None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.tts = []
+        if mps is None:  # B an MPS: its cores have a unit input leg while A's do not
+            mps = int(pairs[0][1][0].shape[2]) == 1 and int(pairs[0][0][0].shape[2]) != 1
+        self.mps = bool(mps)
         arr = (_lib.MpoPair * len(pairs))()
         for i, (A, B) in enumerate(pairs):
+            if self.mps and any(int(b.shape[2]) != 1 for b in B):
+                raise ValueError("an MPO-MPS fit needs B's cores as (chi, d, 1, chi)")
             ta, tb = _TT(_dev_cores(A, self.device)), _TT(_dev_cores(B, self.device))
             self.tts += [ta, tb]
             cm = 0 if pair_chi_max is None else int(pair_chi_max[i])
@@ -68,6 +73,7 @@ class _Setup:
         opts.first_bond = int(first_bond)
         opts.first_half = int(first_half)
         opts.n_parts = int(n_parts)
+        opts.mps = 1 if self.mps else 0
         self.tune = tune_mod.to_ctypes(tune_mod.load(tuning)) if tuning is not None else None
         if self.tune is not None and len(self.tune):
             opts.tune = self.tune
@@ -105,16 +111,18 @@ class FitContext:
     2.3.4 (bond dims then follow the singular values; bond_dims() reads
     them from the device).  schedule='parallel' with n_parts sub-TTs: the
     site-canonical parallel fit of Sec. 4; sweep(n) runs n sets, merge()
-    joins the sub-TTs into one train before export.
+    joins the sub-TTs into one train before export.  mps: the MPO-MPS
+    product of Sec. 1, B (and C) with (chi, d, 1, chi) cores; None detects
+    it from B's cores.
     """
 
     def __init__(self, pairs, chi_max, precision="fp32", schedule="serial", sketch_p=-1, seed=0,
                  capture_graph=True, device="cuda:0", profile=False, pair_chi_max=None, tuning=None,
                  c_init=None, first_sweep=0, track_error=False, first_bond=0, first_half=0, tau=0.0,
-                 n_parts=0):
+                 n_parts=0, mps=None):
         su = _Setup(pairs, chi_max, precision, schedule, sketch_p, seed, capture_graph, device,
                     profile, pair_chi_max, tuning, c_init, first_sweep, track_error, first_bond,
-                    first_half, tau, n_parts)
+                    first_half, tau, n_parts, mps)
         self._setup = su
         self.lib = su.lib
         self.device = su.device
@@ -231,7 +239,8 @@ class FitContext:
         dims = self.bond_dims(pair)
         L = self.L[pair]
         d = self._setup.tts[2 * pair].d
-        cores = [torch.empty((dims[i], d, d, dims[i + 1]), dtype=torch.float64, device=self.device)
+        du = 1 if self._setup.mps else d
+        cores = [torch.empty((dims[i], d, du, dims[i + 1]), dtype=torch.float64, device=self.device)
                  for i in range(L)]
         ptrs = (C.c_void_p * L)(*[c.data_ptr() for c in cores])
         torch.cuda.current_stream(self.device).synchronize()  # allocations visible to our stream
@@ -244,7 +253,8 @@ class FitContext:
         dims = self.bond_dims(pair)
         L = self.L[pair]
         d = self._setup.tts[2 * pair].d
-        cores = [torch.empty((dims[i], d, d, dims[i + 1]), dtype=torch.float64, device=self.device)
+        du = 1 if self._setup.mps else d
+        cores = [torch.empty((dims[i], d, du, dims[i + 1]), dtype=torch.float64, device=self.device)
                  for i in range(L)]
         ptrs = (C.c_void_p * L)(*[c.data_ptr() for c in cores])
         torch.cuda.current_stream(self.device).synchronize()

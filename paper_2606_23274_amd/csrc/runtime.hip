@@ -2,8 +2,9 @@
 // even/odd sweep programs, export, and the C ABI (include/mpofit.h).
 //
 // Device layouts (all row-major; c, a, b = bonds of C, A, B; s = A's output
-// leg, t = the contracted leg, u = B's input leg; dd = d*d; i = 0-based site):
-//   A, B cores (FP64 master)          [a][s][t][a']
+// leg, t = the contracted leg, u = B's input leg, of size du = d, or 1 when B
+// is an MPS (Sec. 1); dd = d*du, C's two legs; i = 0-based site):
+//   A, B cores (FP64 master)          [a][s][t][a'], [b][t][u][b']
 //   C cores (FP64)                    [c][s][u][c']
 //   working copies (FP32 or FP64):
 //     Bw  = B            [b][t][u][b']   right operand of the first left step
@@ -359,7 +360,10 @@ void add_eig(Program& P, const SplitBuf& sb, const std::vector<EigDesc>& ed, boo
 
 // ------------------------------------------------------------------ state
 struct PairState {
-  int L = 0, d = 0, dd = 0;
+  int L = 0, d = 0, dd = 0;  // d: A's legs and C's output leg; dd = C's two legs (d du)
+  int du = 0;                // C's and B's input leg: d, or 1 for an MPS (MPO-MPS variant)
+  int dA = 0, dB = 0;        // physical size of an A core (d d) and of a B core (d du)
+  bool mps = false;
   int chi_max = 1;
   std::vector<int> cA, cB, cC;  // bond dims (L+1): preprocessed A, B; current C
   std::vector<int> capC;        // capacity of C's bonds over the whole fit
@@ -388,7 +392,8 @@ struct PairState {
 // Bond b of the initial guess before its right-orthogonalization: the given
 // C, else the input A (whose preprocessed dims never exceed the input ones).
 int init_dim(const PairState& P, int b) {
-  return P.C_in.empty() ? P.chiA_in[b] : std::max(P.chiA_in[b], P.chiC_in[b]);
+  const int g = P.mps ? P.chiB_in[b] : P.chiA_in[b];
+  return P.C_in.empty() ? g : std::max(g, P.chiC_in[b]);
 }
 
 // Factorization scratch of one bond.
@@ -476,19 +481,19 @@ std::vector<std::pair<int, int>> partition_sites(int L, int n_parts) {
 void plan_shapes(PairState& P, int chi_max, int schedule, int first_sweep, int first_bond, int first_half,
                  int n_parts = 0) {
   const int L = P.L, dd = P.dd;
-  auto leftorth = [&](const std::vector<int>& in) {
+  auto leftorth = [&](const std::vector<int>& in, int pd) {
     std::vector<int> c(in);
-    for (int i = 1; i < L; ++i) c[i] = std::min(in[i], c[i - 1] * dd);
+    for (int i = 1; i < L; ++i) c[i] = std::min(in[i], c[i - 1] * pd);
     // the left sweep only clips from the left; entries to the right keep in[]
     return c;
   };
-  P.cA = leftorth(P.chiA_in);
-  P.cB = leftorth(P.chiB_in);
+  P.cA = leftorth(P.chiA_in, P.dA);
+  P.cB = leftorth(P.chiB_in, P.dB);
   P.rcap.assign(L + 1, 1);
   for (int i = 1; i < L; ++i) P.rcap[i] = P.cA[i] * P.cB[i];
   // initial C: the given guess (else A) right-orthogonalized, or left-
   // orthogonalized when a serial fit starts with a backward sweep
-  std::vector<int> c(P.C_in.empty() ? P.cA : P.chiC_in);
+  std::vector<int> c(P.C_in.empty() ? (P.mps ? P.cB : P.cA) : P.chiC_in);
   const bool fwd0 = first_sweep % 2 == 0;
   if (schedule == MPO_SCHED_SERIAL && first_bond > 0) {  // mixed form around the next update's sites
     const int i0 = fwd0 ? first_bond : L - 2 - first_bond;
@@ -569,8 +574,8 @@ Caps pair_caps(const PairState& P, const mpo_fit_opts& o) {
   }
   for (int i = 0; i < P.L; ++i) {
     // first extension step: rows (c, a) x cols (t, u, b') and its mirror
-    c.T = std::max(c.T, (long long)P.capC[i] * P.cA[i] * P.dd * P.cB[i + 1]);
-    c.T = std::max(c.T, (long long)P.capC[i + 1] * P.cA[i + 1] * P.dd * P.cB[i]);
+    c.T = std::max(c.T, (long long)P.capC[i] * P.cA[i] * P.dB * P.cB[i + 1]);
+    c.T = std::max(c.T, (long long)P.capC[i + 1] * P.cA[i + 1] * P.dB * P.cB[i]);
     c.ext = std::max(c.ext, (long long)P.capC[i] * P.dd * P.cA[i + 1] * P.cB[i + 1]);
     c.ext = std::max(c.ext, (long long)P.capC[i + 1] * P.dd * P.cA[i] * P.cB[i]);
   }
@@ -907,13 +912,13 @@ void carve(Ctx& X, Carver& cv) {
     P.Bw.resize(L); P.Bmw.resize(L); P.At.resize(L); P.Amt.resize(L);
     P.amBw.resize(L); P.amBmw.resize(L); P.amAt.resize(L); P.amAmt.resize(L);
     for (int i = 0; i < L; ++i) {
-      P.A64[i] = cv.take<double>((size_t)P.chiA_in[i] * dd * P.chiA_in[i + 1]);
-      P.B64[i] = cv.take<double>((size_t)P.chiB_in[i] * dd * P.chiB_in[i + 1]);
+      P.A64[i] = cv.take<double>((size_t)P.chiA_in[i] * P.dA * P.chiA_in[i + 1]);
+      P.B64[i] = cv.take<double>((size_t)P.chiB_in[i] * P.dB * P.chiB_in[i + 1]);
       // C holds the initial guess unclipped (A or the given C) before its
       // right-orthogonalization, and the fit's bonds afterwards
       P.C64[i] = cv.take<double>((size_t)std::max(P.capC[i], init_dim(P, i)) * dd *
                                  std::max(P.capC[i + 1], init_dim(P, i + 1)));
-      const size_t na = (size_t)P.cA[i] * dd * P.cA[i + 1], nb = (size_t)P.cB[i] * dd * P.cB[i + 1];
+      const size_t na = (size_t)P.cA[i] * P.dA * P.cA[i + 1], nb = (size_t)P.cB[i] * P.dB * P.cB[i + 1];
       P.At[i] = cv.take<char>(na * wb); P.Amt[i] = cv.take<char>(na * wb);
       P.Bw[i] = cv.take<char>(nb * wb); P.Bmw[i] = cv.take<char>(nb * wb);
       P.amAt[i] = amax(); P.amAmt[i] = amax(); P.amBw[i] = amax(); P.amBmw[i] = amax();
@@ -970,8 +975,10 @@ void carve(Ctx& X, Carver& cv) {
   for (auto& P : X.pairs)
     for (int i = 0; i < P.L; ++i) {
       const long long a = std::max(init_dim(P, i), P.capC[i]), b = std::max(init_dim(P, i + 1), P.capC[i + 1]);
-      core_max = std::max({core_max, a * P.dd * b, (long long)P.chiB_in[i] * P.dd * P.chiB_in[i + 1]});
-      kq = std::max({kq, a, b, (long long)P.chiB_in[i], (long long)P.chiB_in[i + 1]});
+      core_max = std::max({core_max, a * P.dd * b, (long long)P.chiB_in[i] * P.dB * P.chiB_in[i + 1],
+                           (long long)P.chiA_in[i] * P.dA * P.chiA_in[i + 1]});
+      kq = std::max({kq, a, b, (long long)P.chiB_in[i], (long long)P.chiB_in[i + 1], (long long)P.chiA_in[i],
+                     (long long)P.chiA_in[i + 1]});
     }
   X.iG = cv.take<double>((size_t)kq * kq);
   X.iR1 = cv.take<double>(2 * (size_t)kq * kq);
@@ -1015,41 +1022,42 @@ void carve(Ctx& X, Carver& cv) {
 // ------------------------------------------------------------------ extension jobs
 // left step 1 at site i: T[(c,a), (t,u,b')] = Lenv[i][(c,a), b] Bw[i][b, (t,u,b')]
 GemmJob job_e1(const Ctx& X, const PairState& P, int i, void* T, unsigned* amT) {
-  const int M = P.cC[i] * P.cA[i], K = P.cB[i], N = P.dd * P.cB[i + 1];
+  const int M = P.cC[i] * P.cA[i], K = P.cB[i], N = P.dB * P.cB[i + 1];
   return GemmJob{M, N, K, opW(X, P.Lenv[i], true, K, P.amL[i]), opW(X, P.Bw[i], false, N, P.amBw[i]),
                  outW(X, T, N, amT)};
 }
 // left step 2 at site i: XL[i][c][s][u][a'][b'] = sum_(a,t) At[i][(a,t)][s][a'] T[c][(a,t)][u][b']
+// (s over d, t over d, u over du)
 GemmJob job_e2(const Ctx& X, const PairState& P, int i, const void* T, const unsigned* amT) {
-  const int d = P.d, a0 = P.cA[i], a1 = P.cA[i + 1], b1 = P.cB[i + 1];
+  const int d = P.d, du = P.du, a0 = P.cA[i], a1 = P.cA[i + 1], b1 = P.cB[i + 1];
   GemmJob g{a1, b1, d * a0, opW(X, P.At[i], false, d * a1, P.amAt[i]),
-            opW(X, T, false, d * b1, amT), outW(X, P.XL[i], b1, P.amXL[i])};
-  g.nb[0] = P.cC[i]; g.nb[1] = d; g.nb[2] = d;
+            opW(X, T, false, du * b1, amT), outW(X, P.XL[i], b1, P.amXL[i])};
+  g.nb[0] = P.cC[i]; g.nb[1] = d; g.nb[2] = du;
   g.A.s[0] = 0; g.A.s[1] = a1; g.A.s[2] = 0;
-  g.B.s[0] = (long long)a0 * P.dd * b1; g.B.s[1] = 0; g.B.s[2] = b1;
-  g.C.s[0] = (long long)P.dd * a1 * b1; g.C.s[1] = (long long)d * a1 * b1; g.C.s[2] = (long long)a1 * b1;
+  g.B.s[0] = (long long)a0 * P.dB * b1; g.B.s[1] = 0; g.B.s[2] = b1;
+  g.C.s[0] = (long long)P.dd * a1 * b1; g.C.s[1] = (long long)du * a1 * b1; g.C.s[2] = (long long)a1 * b1;
   return g;
 }
 // right step 1 at site j: T[(c'',a''), (t,u,b)] = Renv[j+1][(c'',a''), b''] Bmw[j][b'', (t,u,b)]
 GemmJob job_e1m(const Ctx& X, const PairState& P, int j, void* T, unsigned* amT) {
-  const int M = P.cC[j + 1] * P.cA[j + 1], K = P.cB[j + 1], N = P.dd * P.cB[j];
+  const int M = P.cC[j + 1] * P.cA[j + 1], K = P.cB[j + 1], N = P.dB * P.cB[j];
   return GemmJob{M, N, K, opW(X, P.Renv[j + 1], true, K, P.amR[j + 1]),
                  opW(X, P.Bmw[j], false, N, P.amBmw[j]), outW(X, T, N, amT)};
 }
 // right step 2 at site j: XR[j-1][c''][s][u][a][b] = sum_(a'',t) Amt[j][(a'',t)][s][a] T[c''][(a'',t)][u][b]
 GemmJob job_e2m(const Ctx& X, const PairState& P, int j, const void* T, const unsigned* amT) {
-  const int d = P.d, a0 = P.cA[j], a1 = P.cA[j + 1], b0 = P.cB[j];
+  const int d = P.d, du = P.du, a0 = P.cA[j], a1 = P.cA[j + 1], b0 = P.cB[j];
   GemmJob g{a0, b0, d * a1, opW(X, P.Amt[j], false, d * a0, P.amAmt[j]),
-            opW(X, T, false, d * b0, amT), outW(X, P.XR[j - 1], b0, P.amXR[j - 1])};
-  g.nb[0] = P.cC[j + 1]; g.nb[1] = d; g.nb[2] = d;
+            opW(X, T, false, du * b0, amT), outW(X, P.XR[j - 1], b0, P.amXR[j - 1])};
+  g.nb[0] = P.cC[j + 1]; g.nb[1] = d; g.nb[2] = du;
   g.A.s[0] = 0; g.A.s[1] = a0; g.A.s[2] = 0;
-  g.B.s[0] = (long long)a1 * P.dd * b0; g.B.s[1] = 0; g.B.s[2] = b0;
-  g.C.s[0] = (long long)P.dd * a0 * b0; g.C.s[1] = (long long)d * a0 * b0; g.C.s[2] = (long long)a0 * b0;
+  g.B.s[0] = (long long)a1 * P.dB * b0; g.B.s[1] = 0; g.B.s[2] = b0;
+  g.C.s[0] = (long long)P.dd * a0 * b0; g.C.s[1] = (long long)du * a0 * b0; g.C.s[2] = (long long)a0 * b0;
   return g;
 }
-double flops_e1(const PairState& P, int i) { return 2.0 * P.cC[i] * P.cA[i] * P.cB[i] * P.dd * P.cB[i + 1]; }
+double flops_e1(const PairState& P, int i) { return 2.0 * P.cC[i] * P.cA[i] * P.cB[i] * P.dB * P.cB[i + 1]; }
 double flops_e2(const PairState& P, int i) { return 2.0 * P.cC[i] * P.dd * P.d * P.cA[i] * P.cA[i + 1] * P.cB[i + 1]; }
-double flops_e1m(const PairState& P, int j) { return 2.0 * P.cC[j + 1] * P.cA[j + 1] * P.cB[j + 1] * P.dd * P.cB[j]; }
+double flops_e1m(const PairState& P, int j) { return 2.0 * P.cC[j + 1] * P.cA[j + 1] * P.cB[j + 1] * P.dB * P.cB[j]; }
 double flops_e2m(const PairState& P, int j) { return 2.0 * P.cC[j + 1] * P.dd * P.d * P.cA[j + 1] * P.cA[j] * P.cB[j]; }
 
 // ------------------------------------------------------------------ initialization
@@ -1095,8 +1103,8 @@ void add_hhqr(Ctx& X, Program& P, double* Xm, int n, int k, double* Qout) {
 // next core, or clipped (identity core, everything carried) where it has
 // fewer rows than columns.
 void rec_qr_sweep(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores, std::vector<int>& cur,
-                  int stop, int start = 0) {
-  const int dd = S.dd;
+                  int stop, int start = 0, int pd = 0) {
+  const int dd = pd > 0 ? pd : S.dd;  // physical size of a core of this train
   for (int i = start; i < stop; ++i) {
     const int p = cur[i] * dd, q = cur[i + 1];
     const int nn = dd * cur[i + 2];  // columns of the next core (its right bond untouched yet)
@@ -1148,10 +1156,10 @@ void check_dims(const std::vector<int>& cur, const std::vector<int>& want, const
 // whose input bond dims are `chi_in`; `out_dims` are the clipped dims.  With
 // `nu`, the norm is split off the last core into *nu.
 void rec_left_orth(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores,
-                   const std::vector<int>& chi_in, const std::vector<int>& out_dims, double* nu) {
-  const int L = S.L, dd = S.dd;
+                   const std::vector<int>& chi_in, const std::vector<int>& out_dims, double* nu, int pd = 0) {
+  const int L = S.L, dd = pd > 0 ? pd : S.dd;
   std::vector<int> cur(chi_in);
-  rec_qr_sweep(X, P, S, cores, cur, L - 1);
+  rec_qr_sweep(X, P, S, cores, cur, L - 1, 0, dd);
   check_dims(cur, out_dims, "left orthogonalization");
   if (nu)
     add_simple(P, LK::Norm, std::vector<NormDesc>{NormDesc{cores[L - 1], (long long)cur[L - 1] * dd, nu}}, 0,
@@ -1160,8 +1168,12 @@ void rec_left_orth(Ctx& X, Program& P, PairState& S, std::vector<double*>& cores
 
 // The initial C (A, or the given guess) right-orthogonalized by an RQ sweep
 // L..2 (Sec. 2.3.1).
+const std::vector<int>& guess_dims(const PairState& S) {
+  return S.C_in.empty() ? (S.mps ? S.cB : S.cA) : S.chiC_in;
+}
+
 void rec_right_orth(Ctx& X, Program& P, PairState& S) {
-  std::vector<int> cur(S.C_in.empty() ? S.cA : S.chiC_in);
+  std::vector<int> cur(guess_dims(S));
   rec_rq_sweep(X, P, S, cur, 0);
   check_dims(cur, S.cC, "right orthogonalization");
 }
@@ -1169,31 +1181,31 @@ void rec_right_orth(Ctx& X, Program& P, PairState& S) {
 // The initial C in site-canonical form around sites i0, i0+1 (Sec. 2.3.1):
 // QR sweep over the sites left of them, RQ sweep over the sites right of them.
 void rec_mixed_orth(Ctx& X, Program& P, PairState& S, int i0) {
-  std::vector<int> cur(S.C_in.empty() ? S.cA : S.chiC_in);
+  std::vector<int> cur(guess_dims(S));
   rec_qr_sweep(X, P, S, S.C64, cur, i0);
   rec_rq_sweep(X, P, S, cur, i0 + 1);
   check_dims(cur, S.cC, "mixed orthogonalization");
 }
 
 void rec_repack(Ctx& X, Program& P, PairState& S) {
-  const int L = S.L, d = S.d, dd = S.dd;
+  const int L = S.L, d = S.d, du = S.du, dA = S.dA, dB = S.dB;
   const int tw = X.wt == DType::F64 ? 0 : 1;
   std::vector<PermDesc> ds;
   for (int i = 0; i < L; ++i) {
     const long long a0 = S.cA[i], a1 = S.cA[i + 1], b0 = S.cB[i], b1 = S.cB[i + 1];
-    // B [b][t][u][b'] -> Bw same, Bmw [b'][t][u][b]
-    PermDesc p1 = perm4(S.B64[i], 0, S.Bw[i], tw, {(int)b0, d, d, (int)b1}, {dd * b1, d * b1, b1, 1},
-                        {dd * b1, d * b1, b1, 1});
+    // B [b][t][u][b'] -> Bw same, Bmw [b'][t][u][b]  (t over d, u over du)
+    PermDesc p1 = perm4(S.B64[i], 0, S.Bw[i], tw, {(int)b0, d, du, (int)b1}, {dB * b1, du * b1, b1, 1},
+                        {dB * b1, du * b1, b1, 1});
     p1.amax = S.amBw[i];
-    PermDesc p2 = perm4(S.B64[i], 0, S.Bmw[i], tw, {(int)b0, d, d, (int)b1}, {dd * b1, d * b1, b1, 1},
-                        {1, d * b0, b0, dd * b0});
+    PermDesc p2 = perm4(S.B64[i], 0, S.Bmw[i], tw, {(int)b0, d, du, (int)b1}, {dB * b1, du * b1, b1, 1},
+                        {1, du * b0, b0, dB * b0});
     p2.amax = S.amBmw[i];
     // A [a][s][t][a'] -> At [a][t][s][a'], Amt [a'][t][s][a]
-    PermDesc p3 = perm4(S.A64[i], 0, S.At[i], tw, {(int)a0, d, d, (int)a1}, {dd * a1, d * a1, a1, 1},
-                        {dd * a1, a1, d * a1, 1});
+    PermDesc p3 = perm4(S.A64[i], 0, S.At[i], tw, {(int)a0, d, d, (int)a1}, {dA * a1, d * a1, a1, 1},
+                        {dA * a1, a1, d * a1, 1});
     p3.amax = S.amAt[i];
-    PermDesc p4 = perm4(S.A64[i], 0, S.Amt[i], tw, {(int)a0, d, d, (int)a1}, {dd * a1, d * a1, a1, 1},
-                        {1, a0, d * a0, dd * a0});
+    PermDesc p4 = perm4(S.A64[i], 0, S.Amt[i], tw, {(int)a0, d, d, (int)a1}, {dA * a1, d * a1, a1, 1},
+                        {1, a0, d * a0, dA * a0});
     p4.amax = S.amAmt[i];
     ds.insert(ds.end(), {p1, p2, p3, p4});
   }
@@ -1856,19 +1868,22 @@ void rec_init_pair(Ctx& X, Program& P, PairState& S, int pair) {
   std::vector<PermDesc> cps;
   for (int i = 0; i < L; ++i) {
     const int a0 = S.chiA_in[i], a1 = S.chiA_in[i + 1], b0 = S.chiB_in[i], b1 = S.chiB_in[i + 1];
-    cps.push_back(perm4(S.A_in[i], 0, S.A64[i], 0, {1, 1, a0, dd * a1}, {0, 0, (long long)dd * a1, 1},
-                        {0, 0, (long long)dd * a1, 1}));
-    cps.push_back(perm4(S.B_in[i], 0, S.B64[i], 0, {1, 1, b0, dd * b1}, {0, 0, (long long)dd * b1, 1},
-                        {0, 0, (long long)dd * b1, 1}));
+    const int dA = S.dA, dB = S.dB;
+    cps.push_back(perm4(S.A_in[i], 0, S.A64[i], 0, {1, 1, a0, dA * a1}, {0, 0, (long long)dA * a1, 1},
+                        {0, 0, (long long)dA * a1, 1}));
+    cps.push_back(perm4(S.B_in[i], 0, S.B64[i], 0, {1, 1, b0, dB * b1}, {0, 0, (long long)dB * b1, 1},
+                        {0, 0, (long long)dB * b1, 1}));
   }
   add_perm(P, cps, "init");
-  rec_left_orth(X, P, S, S.A64, S.chiA_in, S.cA, S.nu_dev);
-  rec_left_orth(X, P, S, S.B64, S.chiB_in, S.cB, S.nu_dev + 1);
+  rec_left_orth(X, P, S, S.A64, S.chiA_in, S.cA, S.nu_dev, S.dA);
+  rec_left_orth(X, P, S, S.B64, S.chiB_in, S.cB, S.nu_dev + 1, S.dB);
   std::vector<PermDesc> cc;
   for (int i = 0; i < L; ++i) {
-    if (S.C_in.empty()) {  // C = the preprocessed A
-      cc.push_back(perm4(S.A64[i], 0, S.C64[i], 0, {1, 1, S.cA[i], dd * S.cA[i + 1]},
-                         {0, 0, (long long)dd * S.cA[i + 1], 1}, {0, 0, (long long)dd * S.cA[i + 1], 1}));
+    if (S.C_in.empty()) {  // C = the preprocessed A (B for an MPS, whose legs are C's)
+      const auto& g = S.mps ? S.B64 : S.A64;
+      const auto& gc = S.mps ? S.cB : S.cA;
+      cc.push_back(perm4(g[i], 0, S.C64[i], 0, {1, 1, gc[i], dd * gc[i + 1]},
+                         {0, 0, (long long)dd * gc[i + 1], 1}, {0, 0, (long long)dd * gc[i + 1], 1}));
     } else {  // C = the given initial guess
       const long long c0 = S.chiC_in[i], c1 = S.chiC_in[i + 1];
       cc.push_back(perm4(S.C_in[i], 0, S.C64[i], 0, {1, 1, (int)c0, (int)(dd * c1)}, {0, 0, dd * c1, 1},
@@ -1898,14 +1913,14 @@ void rec_init_pair(Ctx& X, Program& P, PairState& S, int pair) {
     // on it: right-orthogonalized, then left-orthogonalized (the left
     // environments are built from this form below), then right-
     // orthogonalized again (the right ones)
-    std::vector<int> cur(S.C_in.empty() ? S.cA : S.chiC_in);
+    std::vector<int> cur(guess_dims(S));
     rec_rq_sweep(X, P, S, cur, 0);
     rec_qr_sweep(X, P, S, S.C64, cur, L - 1);
     check_dims(cur, S.cC, "parallel initialization");
   } else if (i0 >= 0) {
     rec_mixed_orth(X, P, S, i0);
   } else if (backward_first) {
-    std::vector<int> in(S.C_in.empty() ? S.cA : S.chiC_in);
+    std::vector<int> in(guess_dims(S));
     rec_left_orth(X, P, S, S.C64, in, S.cC, nullptr);
   } else {
     rec_right_orth(X, P, S);
@@ -1981,6 +1996,9 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
   if (o->first_half > 0 && o->schedule != MPO_SCHED_EVEN_ODD)
     throw Error{MPO_ERR_UNSUPPORTED, "first_half needs the even/odd schedule"};
   if (o->track_error < 0 || o->track_error > 1) throw Error{MPO_ERR_INVALID_ARG, "bad track_error"};
+  if (o->mps < 0 || o->mps > 1) throw Error{MPO_ERR_INVALID_ARG, "bad mps"};
+  if (o->mps && (o->track_error || o->schedule == MPO_SCHED_PARALLEL))
+    throw Error{MPO_ERR_UNSUPPORTED, "MPO-MPS: serial or even/odd schedule, no fit-error tracking"};
   X.wmode = o->precision == MPO_FP64 ? Mode::F64
             : o->precision == MPO_FP32 ? Mode::F32
             : o->precision == MPO_BF16 ? Mode::BF16 : Mode::BF16X3;
@@ -2001,7 +2019,8 @@ void setup(Ctx& X, const mpo_pair* pairs, int n_pairs, const mpo_fit_opts* o) {
     validate_tt(pr.A, L, d);
     validate_tt(pr.B, L, d);
     PairState& S = X.pairs[p];
-    S.L = L; S.d = d; S.dd = d * d;
+    S.L = L; S.d = d; S.mps = o->mps != 0;
+    S.du = S.mps ? 1 : d; S.dd = d * S.du; S.dA = d * d; S.dB = d * S.du;
     S.chiA_in.assign(pr.A.chi, pr.A.chi + L + 1);
     S.chiB_in.assign(pr.B.chi, pr.B.chi + L + 1);
     S.A_in.assign(pr.A.cores, pr.A.cores + L);
@@ -2734,6 +2753,7 @@ void rec_check_qr_sweep(Program& P, const SplitBuf& sb, const mpo_tt& A, const m
 int grad_centre(const Ctx& X) {
   if (X.o.schedule != MPO_SCHED_SERIAL) throw Error{MPO_ERR_UNSUPPORTED, "gradient: serial schedule only"};
   if (X.o.tau > 0.0) throw Error{MPO_ERR_UNSUPPORTED, "gradient: fixed bond cap (tau = 0) only"};
+  if (X.o.mps) throw Error{MPO_ERR_UNSUPPORTED, "gradient: MPO-MPO fits only"};
   if (X.pos != 0) throw Error{MPO_ERR_UNSUPPORTED, "gradient: the fit stands inside a sweep"};
   return (X.o.first_sweep + X.sweeps_done) % 2 == 1 ? -1 : 0;  // -1: last site
 }

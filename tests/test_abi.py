@@ -109,6 +109,26 @@ def test_parallel_bad_options(kw, pairs, status):
     assert _lib().mpo_last_error()
 
 
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_mps_workspace_is_smaller(schedule):
+    """B an MPS (unit input leg): its cores, C's and the extensions shrink."""
+    st0, n0 = _query([_Pair()], _opts(schedule=schedule))
+    st1, n1 = _query([_Pair()], _opts(schedule=schedule, mps=1))
+    assert st0 == 0 and st1 == 0 and 0 < n1 < n0
+
+
+@pytest.mark.parametrize("kw, status", [
+    (dict(mps=2), 1),
+    (dict(mps=-1), 1),
+    (dict(mps=1, track_error=1), 6),
+    (dict(mps=1, schedule=2, n_parts=2), 6),
+])
+def test_mps_bad_options(kw, status):
+    st, _ = _query([_Pair(L=8)], _opts(**kw))
+    assert st == status
+    assert _lib().mpo_last_error()
+
+
 def test_workspace_grows_with_pairs_and_bond():
     _, one = _query([_Pair()], _opts())
     _, two = _query([_Pair(), _Pair()], _opts())
