@@ -428,6 +428,30 @@ def parallel_section(steps):
     return res
 
 
+def mps_section(steps):
+    """MPO-MPS products (Sec. 1): A an MPO (L = 40, d = 2, chi = 64), B an
+    MPS (chi = 128, unit input leg), C an MPS with chi_C = 128, p = 16:
+    sweeps per second of the serial fit (FP32 with autotuned GEMMs, FP64)
+    and of the even/odd schedule (FP32), and the MFMA classes' algorithmic
+    TFLOP/s from the library's per-launch flop counts (profiled pass)."""
+    from paper_2606_23274_amd.api import autotune
+    from synth import gaussian_mpo
+    w = WORKLOAD
+    A = gaussian_mpo(np.random.default_rng(11), w["L"], w["d"], w["chi"], decay=True)
+    B = [b[:, :, :1, :].copy() for b in gaussian_mpo(np.random.default_rng(12), w["L"], w["d"], 128, decay=True)]
+    res = {}
+    for tag, prec, sched in (("serial_fp32", "fp32", "serial"), ("serial_fp64", "fp64", "serial"),
+                             ("even_odd_fp32", "fp32", "even_odd")):
+        table = autotune([(A, B)], w["chi_c"], precision=prec, schedule=sched, sketch_p=w["p"],
+                         reps=2) if prec == "fp32" else None
+        wl, _, _, dims = run_gpu(A, B, prec, w["p"], steps, 2, schedule=sched, tuning=table)
+        _, _, prof, _ = run_gpu(A, B, prec, w["p"], 2, 2, schedule=sched, profile=True, tuning=table)
+        mf = sum(v[1] for c, v in prof.items() if c in MFMA_CLASSES) / 2
+        res[tag] = {"sweeps_per_s": round(steps / wl, 3), "ms_per_sweep": round(wl / steps * 1e3, 3),
+                    "mfma_tflops": round(mf / (wl / steps) / 1e12, 3), "max_bond": max(dims)}
+    return {"mpo_mps_L40_chiA64_chiB128_chiC128": res}
+
+
 def gradient_section():
     import torch
     from paper_2606_23274_amd.api import FitContext
@@ -459,7 +483,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=6, help="sweeps of the accuracy comparison")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline, profile and roofline only")
-    ap.add_argument("--section", choices=["batched", "gradient", "randomized", "zipup", "parallel"],
+    ap.add_argument("--section", choices=["batched", "gradient", "randomized", "zipup", "parallel", "mps"],
                     help="run only that section (for profiling) and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 256 MiB (4 times): the reference for "
@@ -478,7 +502,8 @@ def main():
         out = (batched_section(max(2, args.steps // 2)) if args.section == "batched" else
                randomized_section(max(2, args.steps // 2)) if args.section == "randomized" else
                zipup_section() if args.section == "zipup" else
-               parallel_section(max(2, args.steps // 2)) if args.section == "parallel" else gradient_section())
+               parallel_section(max(2, args.steps // 2)) if args.section == "parallel" else
+               mps_section(max(2, args.steps // 2)) if args.section == "mps" else gradient_section())
         print(json.dumps(out), flush=True)
         return
     if args.gpus != 1:
@@ -524,7 +549,7 @@ def main():
             roof["frac_of_one_cu"] = round(ach / (peak / 256), 5)
         roof["traffic"] = measured_traffic(roof["kernel"])
 
-    others, batched, grad, acc, cpu, randomized, par = {}, {}, {}, {}, None, {}, {}
+    others, batched, grad, acc, cpu, randomized, par, mps = {}, {}, {}, {}, None, {}, {}, {}
     if not args.quick:
         wall_b, _, _, _ = run_gpu(A, B, "fp32", w["p"], args.steps, args.warmup)
         others["fp32_built_in_gemm_choice"] = {"sweeps_per_s": round(args.steps / wall_b, 3)}
@@ -544,6 +569,7 @@ def main():
         randomized = randomized_section(max(2, args.steps // 2))
         randomized["zipup_initial_guess"] = zipup_section()
         par = parallel_section(max(2, args.steps // 2))
+        mps = mps_section(max(2, args.steps // 2))
         print("randomized and zip-up done", file=sys.stderr, flush=True)
         Cs = []
         if not args.no_cpu:
@@ -608,7 +634,8 @@ def main():
     }
     if not args.quick:
         line.update({"other_precisions": others, "accuracy": acc, "batched_schedule": batched,
-                     "gradient": grad, "randomized_bonds": randomized, "parallel_site_canonical": par})
+                     "gradient": grad, "randomized_bonds": randomized, "parallel_site_canonical": par,
+                     "mpo_mps": mps})
         if cpu is not None:
             line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
