@@ -11,5 +11,7 @@ from .mpo_inputs import (  # noqa: F401
     make_problem,
     multi_pair_chis,
     make_multi_pair,
+    string_sum_mpo,
+    reflector_product_mpo,
     CONFIGS,
 )

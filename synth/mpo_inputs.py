@@ -52,6 +52,39 @@ def uniform_alpha_mpo(rng: np.random.Generator, L: int, d: int, chi: int,
     return cores
 
 
+def string_sum_mpo(L: int, d: int, weights) -> list[np.ndarray]:
+    """sum_k w_k E_k x E_k x ... x E_k over L sites, E_k the k-th d x d
+    matrix unit (entry (k // d, k % d) = 1), as an MPO of bond dimension
+    len(weights) <= d^2 with diagonal bonds and the weights on site 0.  The
+    strings are orthonormal on every set of sites, so every bond's
+    spectrum is |w| (sorted): degenerate or steep spectra on demand."""
+    n = len(weights)
+    if n > d * d:
+        raise ValueError("at most d^2 strings")
+    units = np.zeros((n, d, d))
+    for k in range(n):
+        units[k, k // d, k % d] = 1.0
+    cores = []
+    for l in range(L):
+        cl = 1 if l == 0 else n
+        cr = 1 if l == L - 1 else n
+        core = np.zeros((cl, d, d, cr))
+        for k in range(n):
+            core[0 if l == 0 else k, :, :, 0 if l == L - 1 else k] = units[k] * (weights[k] if l == 0 else 1.0)
+        cores.append(core)
+    return cores
+
+
+def reflector_product_mpo(rng: np.random.Generator, L: int, d: int) -> list[np.ndarray]:
+    """A product of L orthogonal d x d matrices (bond dimension 1), each the
+    Householder reflector I - 2 v v^T / (v^T v) of a Gaussian v."""
+    cores = []
+    for _ in range(L):
+        v = rng.standard_normal(d)
+        cores.append((np.eye(d) - 2.0 * np.outer(v, v) / (v @ v)).reshape(1, d, d, 1))
+    return cores
+
+
 def make_problem(L: int, d: int, chi_a: int, chi_b: int | None = None, seed: int = 0,
                  decay: bool = False, chi_w: int | None = None):
     """A, B (and W if ``chi_w``) drawn from one stream in the order A, B, W."""
