@@ -63,9 +63,12 @@ __global__ void omega_kernel(const OmegaDesc* __restrict__ descs) {
 
 // Sign rule on the columns of U: the entry of largest magnitude of each
 // column becomes positive (the first such row wins ties).  A workgroup takes
-// 64 columns; its 16 waves split the rows, four independent loads in flight
-// per lane.
+// 64 columns; its 16 waves split the rows (row i to wave i % 16).  Up to
+// kSignCache rows per lane (n <= 512) the column slice is read once, with
+// every load in flight, and scaled from registers; taller matrices read it
+// twice, four loads in flight per lane.
 constexpr int kSignWaves = 16;
+constexpr int kSignCache = 32;
 __global__ void __launch_bounds__(64 * kSignWaves) signfix_kernel(const SignDesc* __restrict__ descs) {
   __shared__ double s_max[kSignWaves][64];
   __shared__ int s_idx[kSignWaves][64];
@@ -75,21 +78,36 @@ __global__ void __launch_bounds__(64 * kSignWaves) signfix_kernel(const SignDesc
   const int col = blockIdx.x * 64 + lane;
   if (blockIdx.x * 64 >= d.r) return;  // uniform
   GAS double* U = gstore_ptr(d.U);
+  const bool cached = d.n <= kSignWaves * kSignCache;  // uniform
+  double v[kSignCache];
   double best = -1.0;
   int bi = 0x7fffffff;
   if (col < d.r) {
-    int i = wave;
-    for (; i + 3 * kSignWaves < d.n; i += 4 * kSignWaves) {
-      double v[4];
+    if (cached) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = U[(long long)(i + q * kSignWaves) * d.ld + col];
+      for (int q = 0; q < kSignCache; ++q) {
+        const int i = wave + kSignWaves * q;
+        v[q] = i < d.n ? U[(long long)i * d.ld + col] : 0.0;
+      }
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (fabs(v[q]) > best) { best = fabs(v[q]); bi = i + q * kSignWaves; }
-    }
-    for (; i < d.n; i += kSignWaves) {
-      const double v = U[(long long)i * d.ld + col];
-      if (fabs(v) > best) { best = fabs(v); bi = i; }
+      for (int q = 0; q < kSignCache; ++q) {
+        const int i = wave + kSignWaves * q;
+        if (i < d.n && fabs(v[q]) > best) { best = fabs(v[q]); bi = i; }
+      }
+    } else {
+      int i = wave;
+      for (; i + 3 * kSignWaves < d.n; i += 4 * kSignWaves) {
+        double x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = U[(long long)(i + q * kSignWaves) * d.ld + col];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (fabs(x[q]) > best) { best = fabs(x[q]); bi = i + q * kSignWaves; }
+      }
+      for (; i < d.n; i += kSignWaves) {
+        const double x = U[(long long)i * d.ld + col];
+        if (fabs(x) > best) { best = fabs(x); bi = i; }
+      }
     }
   }
   s_max[wave][lane] = best;
@@ -103,6 +121,7 @@ __global__ void __launch_bounds__(64 * kSignWaves) signfix_kernel(const SignDesc
       const int iw = s_idx[w][lane];
       if (bw > b || (bw == b && iw < ii)) { b = bw; ii = iw; }
     }
+    // the winning entry sits in another wave's registers: read it again
     double sg = 1.0;
     if (col < d.r && ii != 0x7fffffff) sg = U[(long long)ii * d.ld + col] < 0.0 ? -1.0 : 1.0;
     s_sgn[lane] = sg;
@@ -112,11 +131,23 @@ __global__ void __launch_bounds__(64 * kSignWaves) signfix_kernel(const SignDesc
   float amax = 0.f;
   if (col < d.r) {
     const double sg = s_sgn[lane];
-    for (int i = wave; i < d.n; i += kSignWaves) {
-      GAS double* p = U + (long long)i * d.ld + col;
-      const double v = *p * sg;
-      *p = v;
-      amax = fmaxf(amax, fabsf((float)v));
+    if (cached) {
+#pragma unroll
+      for (int q = 0; q < kSignCache; ++q) {
+        const int i = wave + kSignWaves * q;
+        if (i < d.n) {
+          const double x = v[q] * sg;
+          U[(long long)i * d.ld + col] = x;
+          amax = fmaxf(amax, fabsf((float)x));
+        }
+      }
+    } else {
+      for (int i = wave; i < d.n; i += kSignWaves) {
+        GAS double* p = U + (long long)i * d.ld + col;
+        const double x = *p * sg;
+        *p = x;
+        amax = fmaxf(amax, fabsf((float)x));
+      }
     }
   }
   if (d.amax) {
