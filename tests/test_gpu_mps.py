@@ -125,3 +125,37 @@ def test_mps_refusals():
         assert e.value.status == 6
     finally:
         ctx.close()
+
+
+def test_mps_split_bf16_first_sweep():
+    """Split BF16 contractions (FP64 factorizations) at the BF16 bar of 3e-3."""
+    A, B = _pair(12, 2, 8, 8, seed=9)
+    (C,), (dims,) = _gpu([(A, B)], 12, 1, precision="bf16x3", sketch_p=4, seed=2)
+    ref = ofit.fit_serial(A, B, 12, 1, sketch_p=4, seed=2)
+    assert dims == ref.bond_dims
+    d = mpo.rel_diff(C, ref.C)
+    print("mps bf16x3", d)
+    assert d < 3e-3
+
+
+def test_mps_even_odd_second_half_resume():
+    """first_half = 1 from an MPS guess: the second half-step alone, as the
+    oracle's resumed even/odd fit."""
+    A, B = _pair(9, 2, 5, 4, seed=10)
+    g = ofit.fit_serial(A, B, 6, 1, sketch_p=2, seed=5).C
+    ref = ofit.fit_even_odd(A, B, 6, 1, sketch_p=2, seed=5, C_init=g, first_half=1)
+    (C,), (dims,) = _gpu([(A, B)], 6, 1, precision="fp64", schedule="even_odd", sketch_p=2, seed=5,
+                         c_init=[g], first_half=1)
+    assert dims == ref.bond_dims
+    assert mpo.rel_diff(C, ref.C) < 1e-10
+
+
+def test_mps_graph_replay_matches_eager():
+    """A captured sweep replays the eager one bit for bit."""
+    A, B = _pair(10, 2, 6, 5, seed=11)
+    outs = []
+    for graph in (False, True):
+        (C,), _ = _gpu([(A, B)], 8, 4, precision="fp32", sketch_p=3, seed=1, capture_graph=graph)
+        outs.append(C)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
