@@ -91,7 +91,11 @@ typedef enum {
    mpo_fit_truncations. */
 
 /* One MPO: L cores, core l (0-based) is a device array of
-   chi[l] * d * d * chi[l+1] doubles, row-major (left, out, in, right). */
+   chi[l] * d * d * chi[l+1] doubles, row-major (left, out, in, right).  The
+   library reads the cores by these sizes: an array of another shape is read
+   past its end.  Only the fit (mpo_fit_opts.mps) takes MPS cores
+   (chi[l] * d * 1 * chi[l+1]); the zip-up, the bond projection, the check
+   and the gradient take MPO cores. */
 typedef struct {
   int32_t L;                 /* number of sites, >= 2                         */
   int32_t d;                 /* physical dimension (d_out = d_in = d), >= 1   */

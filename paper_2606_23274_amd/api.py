@@ -17,6 +17,29 @@ from . import _lib
 from . import tune as tune_mod
 
 
+def check_train(cores, what, unit_in=False):
+    """Shapes of a tensor train handed to the library, checked on the host:
+    4-D cores (chi_l, d, d_in, chi_r) whose bonds chain up, boundary bonds
+    1, one d, and d_in = d (an MPO) or d_in = 1 (unit_in: an MPS stored as
+    an MPO).  The C ABI reads cores by these sizes, so a mismatch would read
+    past the tensors."""
+    if len(cores) < 1:
+        raise ValueError(f"{what}: no cores")
+    d = int(cores[0].shape[1])
+    prev = 1
+    for l, c in enumerate(cores):
+        sh = tuple(int(x) for x in c.shape)
+        if len(sh) != 4:
+            raise ValueError(f"{what}: core {l} is not 4-D")
+        want_in = 1 if unit_in else d
+        if sh[0] != prev or sh[1] != d or sh[2] != want_in:
+            raise ValueError(f"{what}: core {l} has shape {sh}, expected ({prev}, {d}, {want_in}, chi)")
+        prev = sh[3]
+    if prev != 1:
+        raise ValueError(f"{what}: the last bond must be 1")
+    return d
+
+
 def _dev_cores(cores, device):
     out = []
     for c in cores:
@@ -52,8 +75,9 @@ class _Setup:
         self.mps = bool(mps)
         arr = (_lib.MpoPair * len(pairs))()
         for i, (A, B) in enumerate(pairs):
-            if self.mps and any(int(b.shape[2]) != 1 for b in B):
-                raise ValueError("an MPO-MPS fit needs B's cores as (chi, d, 1, chi)")
+            d = check_train(A, f"pair {i} A")
+            if check_train(B, f"pair {i} B", unit_in=self.mps) != d or len(B) != len(A):
+                raise ValueError(f"pair {i}: A and B must share L and d")
             ta, tb = _TT(_dev_cores(A, self.device)), _TT(_dev_cores(B, self.device))
             self.tts += [ta, tb]
             cm = 0 if pair_chi_max is None else int(pair_chi_max[i])
@@ -81,6 +105,8 @@ class _Setup:
         if c_init is not None:  # one initial guess (list of FP64 cores) per pair
             if len(c_init) != len(pairs):
                 raise ValueError("c_init needs one MPO per pair")
+            for i, Cc in enumerate(c_init):
+                check_train(Cc, f"c_init {i}", unit_in=self.mps)
             self.c_tts = [_TT(_dev_cores(Cc, self.device)) for Cc in c_init]
             self.c_arr = (_lib.MpoTT * len(pairs))(*[t.tt for t in self.c_tts])
             opts.c_init = self.c_arr
@@ -343,6 +369,8 @@ def zipup(A, B, chi_max, sketch_p=-1, seed=0, device="cuda:0", numpy=True):
     """Zip-up contraction C ~ A B on the GPU (mpo_zipup, Alg. 2): the fit's
     initial guess (FitContext(..., c_init=[zipup(A, B, chi)])).  Returns
     numpy arrays (or device tensors with numpy=False)."""
+    check_train(A, "A")
+    check_train(B, "B")
     lib = _lib.load()
     dev = torch.device(device)
     ta, tb = _TT(_dev_cores(A, dev)), _TT(_dev_cores(B, dev))
@@ -369,6 +397,7 @@ def project_bonds(cores, k, seed=0, pair=0, which="A", device="cuda:0", numpy=Tr
     Q_{l-1}^T A_l Q_l, Q_l from the Gaussian range finder on core l-1's
     right bond.  `which` picks the conventional Philox stream of A or B.
     Returns numpy arrays (or device tensors with numpy=False)."""
+    check_train(cores, "cores")
     lib = _lib.load()
     dev = torch.device(device)
     tin = _TT(_dev_cores(cores, dev))
@@ -396,6 +425,8 @@ def fit_error(A, B, C, device="cuda:0", with_method=False, static=False):
     accurate far below sqrt(eps)), else transfer passes (method 1, floors
     near 1e-8 relative).  static=True uses mpo_contract_exact_check_static
     (the library's static scratch, no workspace)."""
+    for X, what in ((A, "A"), (B, "B"), (C, "C")):
+        check_train(X, what)
     lib = _lib.load()
     dev = torch.device(device)
     ta, tb, tc = (_TT(_dev_cores(X, dev)) for X in (A, B, C))

@@ -284,3 +284,27 @@ def test_zipup_dims_and_errors():
     wrong = _Pair(L=6, chi_a=4)  # C's dims must be the zip-up's
     assert lib.mpo_zipup(C.byref(p.pair), 10, 4, 0, C.byref(wrong.pair.A), C.c_void_p(0x100000), 1 << 40,
                          None) == 2
+
+
+def test_python_front_end_checks_train_shapes():
+    """The front end refuses trains the library would read past: broken bond
+    chains, wrong boundary bonds, MPS cores where MPO cores are read."""
+    import numpy as np
+    from paper_2606_23274_amd.api import check_train
+    ok = [np.zeros((1, 2, 2, 3)), np.zeros((3, 2, 2, 1))]
+    assert check_train(ok, "A") == 2
+    mps = [np.zeros((1, 2, 1, 3)), np.zeros((3, 2, 1, 1))]
+    assert check_train(mps, "B", unit_in=True) == 2
+    bad = [
+        [np.zeros((1, 2, 2, 3)), np.zeros((4, 2, 2, 1))],   # bonds do not chain
+        [np.zeros((2, 2, 2, 3)), np.zeros((3, 2, 2, 1))],   # left boundary
+        [np.zeros((1, 2, 2, 3)), np.zeros((3, 2, 2, 2))],   # right boundary
+        [np.zeros((1, 2, 2, 3)), np.zeros((3, 3, 3, 1))],   # d changes
+        mps,                                                  # MPS where an MPO is read
+        [np.zeros((1, 2, 2))],                                # not 4-D, one core
+    ]
+    for t in bad:
+        with pytest.raises(ValueError):
+            check_train(t, "A")
+    with pytest.raises(ValueError):
+        check_train(ok, "B", unit_in=True)
