@@ -159,3 +159,29 @@ def test_mps_graph_replay_matches_eager():
         outs.append(C)
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("s,b", [(0, 3), (1, 5)])
+def test_mps_resume_mid_sweep(s, b):
+    """first_bond = b inside sweep s from the oracle's state after b updates:
+    the next update, and the rest of the sweep, as the uninterrupted fit."""
+    A, B = _pair(9, 2, 5, 4, seed=12)
+    states = []
+    ofit.fit_serial(A, B, 6, s + 1, sketch_p=2, seed=5,
+                    on_update=lambda sweep, l, Cs: states.append((sweep, l, [c.copy() for c in Cs])))
+    in_sweep = [st for st in states if st[0] == s]
+    before, after, end = in_sweep[b - 1][2], in_sweep[b][2], in_sweep[-1][2]
+    from paper_2606_23274_amd.api import FitContext
+    for n, want in ((1, after), (None, end)):
+        ctx = FitContext([(A, B)], 6, precision="fp64", sketch_p=2, seed=5, c_init=[before], first_sweep=s,
+                         first_bond=b)
+        try:
+            if n is None:
+                ctx.sweep(1)
+            else:
+                ctx.updates(n)
+            C = ctx.export_numpy(0)
+        finally:
+            ctx.close()
+        assert [c.shape for c in C] == [c.shape for c in want]
+        assert mpo.rel_diff(C, want) < 1e-10
