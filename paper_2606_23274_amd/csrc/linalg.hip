@@ -1380,6 +1380,21 @@ __global__ void __launch_bounds__(kBig) jacobi_kernel(const JacobiDesc* __restri
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int kWaves = kBig / 64;
+  // ||W||_F^2, which the rotations keep.  A column whose squared norm is
+  // below 1e-40 of it carries singular values under 1e-20 ||W||, far below
+  // the truncation, and is not rotated: its products underflow, and against
+  // a large column the rotation angle's z^2 overflows, so the relative test
+  // below would never settle on it; a rotation with a large column would
+  // change that column by less than 1e-20 of its norm
+  double fro = 0.0;
+  for (int idx = threadIdx.x; idx < q * q; idx += kBig) fro = fma(M[idx], M[idx], fro);
+  fro = wave_sum(fro);
+  if (lane == 0) s_n[wave] = fro;
+  __syncthreads();
+  fro = 0.0;
+  for (int w = 0; w < kWaves; ++w) fro += s_n[w];
+  const double floor2 = 1e-40 * fro;
+  __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (threadIdx.x == 0) s_rot = 0;
     __syncthreads();
@@ -1400,7 +1415,7 @@ __global__ void __launch_bounds__(kBig) jacobi_kernel(const JacobiDesc* __restri
         a = wave_sum(a);
         b = wave_sum(b);
         c = wave_sum(c);
-        if (c != 0.0 && fabs(c) > 1e-15 * sqrt(a * b)) {
+        if (c != 0.0 && fmin(a, b) >= floor2 && fabs(c) > 1e-15 * sqrt(a) * sqrt(b)) {
           const double z = (b - a) / (2.0 * c);
           const double tt = copysign(1.0, z) / (fabs(z) + sqrt(fma(z, z, 1.0)));
           const double cs = 1.0 / sqrt(fma(tt, tt, 1.0)), sn = cs * tt;
