@@ -292,6 +292,18 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = accv_t{0, 0, 0, 0};
+  // FP32 32 x 32 tiles run unsplit over long K (4096 in the serial two-site
+  // product): sub-slab ks accumulates into partial sum ks % NACC, which
+  // shortens each FP32 accumulation chain NACC times; the partial sums are
+  // added in a fixed order after the last slab
+  constexpr int NACC = (MODE == Mode::F32 && (TILE == 3 || TILE == 4)) ? 4 : 1;
+  accv_t accp[NACC > 1 ? NACC - 1 : 1][FM][FN];
+#pragma unroll
+  for (int q = 0; q < (NACC > 1 ? NACC - 1 : 1); ++q)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) accp[q][i][j] = accv_t{0, 0, 0, 0};
 
   constexpr bool BF = MODE == Mode::BF16 || MODE == Mode::BF16X3;
   TileLoader<TA, AK, BM, BK, BF && !AK> la;
@@ -387,6 +399,9 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
           for (int j = 0; j < FN; ++j) {
             if constexpr (MODE == Mode::F64)
               acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bfr[j][s], acc[i][j], 0, 0, 0);
+            else if (NACC > 1 && ks % NACC != 0)
+              accp[ks % NACC - 1][i][j] =
+                  __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s], bfr[j][s], accp[ks % NACC - 1][i][j], 0, 0, 0);
             else
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s], bfr[j][s], acc[i][j], 0, 0, 0);
           }
@@ -397,6 +412,16 @@ gemm_kernel(const GemmDesc* __restrict__ descs, int n_desc) {
       lb.template store<MODE, BT>(sB[0][cur ^ 1], sB[NLO - 1][cur ^ 1], BT ? LDMB : LDL, inv_sb);
     }
     __syncthreads();
+  }
+  if constexpr (NACC > 1) {
+#pragma unroll
+    for (int q = 0; q < NACC - 1; ++q)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[i][j][e] += accp[q][i][j][e];
   }
 
   if constexpr (KW) {  // the four partial blocks, summed in wave order
