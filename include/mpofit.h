@@ -179,8 +179,9 @@ typedef struct {
    mpo_precision, operand types 0 = FP64 / 1 = FP32, K-contiguity of A and B),
    the largest problem of the launch (M, N, K) and its problem count; the
    chosen output tile (0: 64x64, 1: 128x128, 2: 64x64 with half-depth K
-   slabs, the last two FP32/BF16 only; 3: 32x32, 4: 32x32 with 128-deep K
-   slabs, these two FP64 and FP32; 5: 16x16 with the K range split over the
+   slabs, the last two FP32/BF16 only; 3: 32x32, 4: 32x32 with deep K
+   slabs (128; 64 in split BF16), these two every mode; 5: 16x16 with the K
+   range split over the
    workgroup's waves and no split-K, FP64 only; a tile that does not apply
    to the mode falls back to 0) and split-K count, and the measured average launch time
    of that choice. */
@@ -424,8 +425,8 @@ mpo_status mpo_fit_profile(const mpo_fit_ctx* ctx, int32_t n, double* ms, const 
    runs one sweep so that the bond dimensions settle, then times every GEMM
    launch class of the next sweep's launch program under each candidate
    (tile 64x64; for FP32/BF16 also 64x64 with half-depth K slabs, and
-   128x128 when every problem is large enough; for FP32 also the 32x32
-   tiles; for FP64 also the 32x32 and 16x16 tiles; split-K 1, 2, 4, 8, 16 where K and the tile allow), `reps`
+   128x128 when every problem is large enough; the 32x32 tiles; for FP64
+   also the 16x16 tile; split-K 1, 2, 4, 8, 16 where K and the tile allow), `reps`
    launches per candidate with
    HIP events, and writes the fastest per class into out[0 .. *n_out - 1]
    (at most `cap`).  Pass the table back through mpo_fit_opts.tune.  The

@@ -19,7 +19,7 @@ extern "C" {
    a_kcontig: A(m,k) at m*lda+k (1) or k*lda+m (0); b_kcontig: B(k,n) at
    n*ldb+k (1) or k*ldb+n (0); C(m,n) at m*ldc+n; tile 0 (64x64), 1
    (128x128, FP32/BF16), 2 (64x64 with half-depth K slabs, FP32/BF16), 3
-   (32x32, FP64/FP32), 4 (32x32 with 128-deep K slabs, FP64/FP32) or 5 (16x16 with the
+   (32x32), 4 (32x32 with deep K slabs) or 5 (16x16 with the
    K range split over the workgroup's waves, FP64, splits = 1); splits >= 1
    forces that many K chunks.  Another tile returns MPO_ERR_INVALID_ARG. */
 mpo_status mpo_test_gemm(int mode, int ta, int tb, int tc, int a_kcontig, int b_kcontig, int tile,

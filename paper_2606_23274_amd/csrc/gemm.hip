@@ -33,10 +33,12 @@ template <> struct TileShape<2> { static constexpr int BM = 64, BN = 64; };  // 
 // For products with few 64 x 64 tiles, where those leave most of the chip
 // idle and split-K pays a device-scope fence per tile (FP64: the small
 // factorization products, k x k Gram matrices and n x k applications; FP32:
-// the serial sweep's two-site product, 64 tiles of 64 x 64):
-//   3: 32 x 32, one 16 x 16 MFMA block per wave, 32-deep slabs (FP64, FP32);
-//   4: the same with 128-deep slabs (fewer global-load round trips; FP64,
-//      FP32);
+// the serial sweep's two-site product, 64 tiles of 64 x 64; BF16 modes
+// likewise):
+//   3: 32 x 32, one 16 x 16 MFMA block per wave, 32-deep slabs (BF16: 64,
+//      split BF16: 32);
+//   4: the same with 128-deep slabs (fewer global-load round trips; split
+//      BF16: 64);
 // FP64 only:
 //   5: 16 x 16, the four waves take interleaved quarters of each 128-deep
 //      slab and sum their blocks through LDS at the end (a quarter of the
@@ -79,8 +81,8 @@ template <> struct ModeT<Mode::BF16X3> : ModeT<Mode::BF16> {};
 constexpr int slab_k(Mode m, int tile) {
   return m == Mode::F64 ? (tile >= 4 ? 128 : 32)
          : m == Mode::F32 ? (tile == 0 ? 64 : tile == 4 ? 128 : 32)
-         : m == Mode::BF16 ? (tile == 0 ? 128 : 64)
-                           : (tile == 0 ? 64 : 32);
+         : m == Mode::BF16 ? (tile == 0 || tile == 4 ? 128 : 64)
+                           : (tile == 0 || tile == 4 ? 64 : 32);
 }
 
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
@@ -518,13 +520,10 @@ void launch_tile(int tile, const GemmDesc* d, int n, int wgs, hipStream_t s) {
   } else {
     if (tile == 1) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 1><<<wgs, kThreads, 0, s>>>(d, n);
     else if (tile == 2) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 2><<<wgs, kThreads, 0, s>>>(d, n);
-    else if constexpr (MODE == Mode::F32) {  // the 32 x 32 tiles, for products with few 64 x 64 tiles
-      if (tile == 3) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 3><<<wgs, kThreads, 0, s>>>(d, n);
-      else if (tile == 4) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 4><<<wgs, kThreads, 0, s>>>(d, n);
-      else gemm_kernel<MODE, TA, TB, TC, AK, BKC, 0><<<wgs, kThreads, 0, s>>>(d, n);
-    } else {
-      gemm_kernel<MODE, TA, TB, TC, AK, BKC, 0><<<wgs, kThreads, 0, s>>>(d, n);
-    }
+    // the 32 x 32 tiles, for products with few 64 x 64 tiles
+    else if (tile == 3) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 3><<<wgs, kThreads, 0, s>>>(d, n);
+    else if (tile == 4) gemm_kernel<MODE, TA, TB, TC, AK, BKC, 4><<<wgs, kThreads, 0, s>>>(d, n);
+    else gemm_kernel<MODE, TA, TB, TC, AK, BKC, 0><<<wgs, kThreads, 0, s>>>(d, n);
   }
 }
 

@@ -195,7 +195,7 @@ void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<
   }
   auto usable = [&](int t) {
     if (mode == Mode::F64) return t >= 3 && t <= 5 ? t : 0;
-    if (mode == Mode::F32 && (t == 3 || t == 4)) return t;
+    if (t == 3 || t == 4) return t;  // the 32 x 32 tiles serve every mode
     return t == 1 ? (big ? 1 : 0) : t == 2 ? 2 : 0;
   };
   long long w64 = 0;
@@ -3676,9 +3676,8 @@ mpo_status mpo_gemm_autotune(const mpo_pair* pairs, int32_t n_pairs, const mpo_f
         if (seen) continue;
         mpo_gemm_tune win = key;
         win.us = -1;
-        const std::vector<int> tiles = r.first == Mode::F64   ? std::vector<int>{0, 3, 4, 5}
-                                       : r.first == Mode::F32 ? std::vector<int>{0, 1, 2, 3, 4}
-                                                              : std::vector<int>{0, 1, 2};
+        const std::vector<int> tiles = r.first == Mode::F64 ? std::vector<int>{0, 3, 4, 5}
+                                                            : std::vector<int>{0, 1, 2, 3, 4};
         for (int tile : tiles) {
           for (int sp : {1, 2, 4, 8, 16}) {
             if (sp > 1 && (tile == 5 || key.K / sp < gemm_bk(r.first, tile))) continue;
@@ -3920,7 +3919,7 @@ mpo_status mpo_test_gemm(int mode, int ta, int tb, int tc, int a_kcontig, int b_
     auto vec = [](const void* p, int ld) { return (ld % 4 == 0 && aligned16(p)) ? 1 : 0; };
     d.vec_a = vec(A, lda); d.vec_b = vec(B, ldb);
     const bool f64_tile = tile == 0 || tile >= 3;  // FP64: 0, 3, 4, 5; otherwise 0, 1, 2
-    const bool ok_tile = md == Mode::F64 ? f64_tile : (tile <= 2 || (md == Mode::F32 && tile <= 4));
+    const bool ok_tile = md == Mode::F64 ? f64_tile : tile <= 4;
     if (tile < 0 || tile > 5 || !ok_tile || (tile == 5 && splits > 1))
       throw Error{MPO_ERR_INVALID_ARG, "GEMM tile"};
     int s = std::max(1, splits);
