@@ -555,12 +555,16 @@ def main():
         others["fp32_built_in_gemm_choice"] = {"sweeps_per_s": round(args.steps / wall_b, 3)}
         for prec, p, st in (("bf16x3", w["p"], args.steps), ("bf16", w["p"], args.steps),
                             ("fp64", w["p"], args.steps), ("fp64", -1, 2)):
-            wl, _, _, _ = run_gpu(A, B, prec, p, st, args.warmup if p >= 0 else 2)
+            # each sketched precision with its own tuning table, as the headline
+            tab = autotune([(A, B)], w["chi_c"], precision=prec, sketch_p=p, seed=w["seed"],
+                           reps=3) if p >= 0 else None
+            wl, _, _, _ = run_gpu(A, B, prec, p, st, args.warmup if p >= 0 else 2, tuning=tab)
             key = prec + ("_plain" if p < 0 else "")
             mfp, _ = sweep_flops(w["L"], w["d"], w["chi"], w["chi_c"], w["p"], dims, p >= 0)
             others[key] = {"sweeps_per_s": round(st / wl, 3), "ms_per_sweep": round(wl / st * 1e3, 3),
                            "tflops": round(mfp / (wl / st) / 1e12, 3),
-                           "mfma_frac": round(mfp / (wl / st) / PEAK[prec], 5)}
+                           "mfma_frac": round(mfp / (wl / st) / PEAK[prec], 5),
+                           "autotuned": tab is not None}
         print("precisions done", file=sys.stderr, flush=True)
         batched = batched_section(max(2, args.steps // 2))
         print("batched done", file=sys.stderr, flush=True)
