@@ -41,7 +41,7 @@ MFMA_CLASSES = ("theta", "env_update", "env_ext1", "env_ext2", "sketch", "projec
 KERNEL_OF_CLASS = {"qr_chol_inv": "chol_inv_reg_kernel<9, 16>", "eig_tridiag": "sytrd_reg_kernel<9, 16>",
                    "gauge_chol_inv": "chol_inv_reg_kernel<8, 16>",
                    "eig_bisect": "bisect_kernel<256>", "eig_vectors": "twisted_wave_kernel",
-                   "theta": "gemm_kernel<Mode::F32, float, float, float, true, true, 0|1>"}
+                   "theta": "gemm_kernel<Mode::F32, float, float, float, true, true, autotuned tile>"}
 
 
 def bonds_of(L, d, chi):
@@ -55,9 +55,13 @@ def bonds_of(L, d, chi):
 
 
 def sweep_flops(L, d, chi, chi_c, p, dims_c, sketch=True):
-    """Algorithmic flops of one serial sweep: one fresh extension per bond
-    (the other is cached), the dense two-site matrix, sketch and projection
-    when sketched, one environment update; the FP64 factorization apart."""
+    """Algorithmic flops of one serial sweep, averaged over the two
+    directions: one fresh extension per bond (of site i going forward, of
+    site i+1 going backward; the other side is cached), the dense two-site
+    matrix, one environment update (from U going forward, from V^T going
+    backward); the FP64 sketch, projection and factorization apart.  A's
+    and B's bonds are clipped from the left only, as the library's
+    preprocessing leaves them."""
     dd = d * d
     mfma, f64 = 0.0, 0.0
     chiA = [1] + [chi] * (L - 1) + [1]
@@ -66,11 +70,12 @@ def sweep_flops(L, d, chi, chi_c, p, dims_c, sketch=True):
     for i in range(L - 1):  # bond i joins sites i, i+1
         cl, cr = dims_c[i], dims_c[i + 2]
         n, m = cl * dd, dd * cr
-        a0, a1 = chiA[i], chiA[i + 1]
+        a0, a1, a2 = chiA[i], chiA[i + 1], chiA[i + 2]
         K = a1 * a1
         r = dims_c[i + 1]
-        ext = 2.0 * cl * a0 * a0 * dd * a1 + 2.0 * cl * dd * d * a0 * a1 * a1
-        mfma += ext + 2.0 * n * m * K + 2.0 * r * K * n
+        ext_fwd = 2.0 * cl * a0 * a0 * dd * a1 + 2.0 * cl * dd * d * a0 * a1 * a1
+        ext_bwd = 2.0 * cr * a2 * a2 * dd * a1 + 2.0 * cr * dd * d * a2 * a1 * a1
+        mfma += 0.5 * (ext_fwd + ext_bwd) + 2.0 * n * m * K + 2.0 * r * K * 0.5 * (n + m)
         k = min(chi_c + p, n, m, K) if sketch else min(n, m)
         if sketch and k < min(n, m):
             f64 += 4.0 * n * m * k + 4.0 * n * k * k + 4.0 * m * k * k + 10.0 * k ** 3
