@@ -213,6 +213,11 @@ void add_gemm_kind(Program& P, const SplitBuf& sb, Mode mode, const std::vector<
   } else if (mode == Mode::F64 && w64 < 128) {
     // small FP64 products: 16x16 tiles, K split over the waves
     gk.tile = 5;
+  } else if (mode == Mode::F32 && w64 < 128 && kmax >= 2048) {
+    // few long-K FP32 tiles (the serial two-site product): 32x32 tiles with
+    // deep slabs and no split-K give every CU several workgroups
+    gk.tile = 4;
+    split_cap = 1;
   } else if (kmax <= 512) {
     gk.tile = usable(2);  // short K: more resident workgroups
   }
