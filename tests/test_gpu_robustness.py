@@ -48,3 +48,33 @@ def test_graph_replay_matches_eager_bitwise(schedule, precision):
     for s, (g, e) in enumerate(zip(runs[True], runs[False])):
         for cg, ce in zip(g, e):
             assert np.array_equal(cg, ce), f"sweep {s + 1} differs"
+
+
+@pytest.mark.parametrize("kw", [dict(schedule="serial", tau=1.0), dict(schedule="even_odd", tau=2.0),
+                                dict(schedule="parallel", n_parts=4)],
+                         ids=["serial-tau", "even_odd-tau", "parallel"])
+def test_graph_replay_matches_eager_bitwise_tau_and_parallel(kw):
+    """The same for the tolerance rule (bond dims on the device, Omega of the
+    actual shape drawn into a zero-filled buffer) and for the site-canonical
+    parallel schedule (sets replayed, then the merge)."""
+    from paper_2606_23274_amd.api import FitContext
+    A, B = make_pair(16, 2, 8, seed=7, decay=True)
+    runs = {}
+    for graph in (True, False):
+        ctx = FitContext([(A, B)], 12, precision="fp32", sketch_p=3, seed=4, capture_graph=graph, **kw)
+        try:
+            out = []
+            for _ in range(4):
+                ctx.sweep(1)
+                if kw["schedule"] != "parallel":
+                    out.append((ctx.bond_dims(0), ctx.export_numpy(0)))
+            if kw["schedule"] == "parallel":
+                ctx.merge()
+                out.append((ctx.bond_dims(0), ctx.export_numpy(0)))
+            runs[graph] = out
+        finally:
+            ctx.close()
+    for s, ((dg, g), (de, e)) in enumerate(zip(runs[True], runs[False])):
+        assert dg == de, f"step {s + 1}: bond dims differ"
+        for cg, ce in zip(g, e):
+            assert np.array_equal(cg, ce), f"step {s + 1} differs"
